@@ -1,0 +1,131 @@
+"""Pins of the oracle's L, B, H operators (Sec. 2.1-2.2, Eq. 7)."""
+import numpy as np
+import pytest
+
+from oracle import lens, mock
+from oracle import operators as ops
+
+
+def _table(seed=0, n=200, ns=9, R=1.0):
+    rng = np.random.default_rng(seed)
+    bx = rng.uniform(-1.3, 1.3, (n, 4))
+    by = rng.uniform(-1.3, 1.3, (n, 4))
+    return bx, by, ops.bilinear_table(bx, by, ns, R)
+
+
+def test_bilinear_reproduces_bilinear_functions():
+    ns, R = 9, 1.0
+    bx, by, tab = _table(ns=ns, R=R)
+    h = 2 * R / (ns - 1)
+    nodes = -R + np.arange(ns) * h
+    NX, NY = np.meshgrid(nodes, nodes)
+    f = lambda x, y: 0.3 + 1.7 * x - 0.9 * y + 2.2 * x * y
+    s = f(NX, NY).reshape(-1)
+    idx, w, inside = tab
+    vals = (w * s[idx]).sum(axis=2)
+    np.testing.assert_allclose(vals[inside], f(bx, by)[inside], atol=1e-13)
+    # weights sum to one per inside subpixel, zero outside
+    np.testing.assert_allclose(w.sum(axis=2)[inside], 1.0, atol=1e-15)
+    assert np.all(w.sum(axis=2)[~inside] == 0)
+
+
+def test_L_of_ones_counts_inside_subpixels():
+    bx, by, tab = _table()
+    img = ops.apply_L(tab, np.ones(81), 2)
+    np.testing.assert_allclose(img, tab[2].sum(axis=1) / 4.0, atol=1e-15)
+
+
+def test_grid_edges_inclusive():
+    # a subpixel exactly on the last node row/column is inside and uses the last cell
+    ns, R = 5, 1.0
+    tab = ops.bilinear_table(np.array([[1.0, -1.0, 1.0 + 1e-12, 0.0]]),
+                             np.array([[1.0, -1.0, 0.0, -1.0 - 1e-12]]), ns, R)
+    idx, w, inside = tab
+    assert list(inside[0]) == [True, True, False, False]
+    assert idx[0, 0, 3] == ns * ns - 1 and w[0, 0, 3] == pytest.approx(1.0)
+    assert idx[0, 1, 0] == 0 and w[0, 1, 0] == pytest.approx(1.0)
+
+
+def test_adjoint_L():
+    bx, by, tab = _table(seed=5)
+    rng = np.random.default_rng(6)
+    x = rng.standard_normal(81)
+    y = rng.standard_normal(200)
+    lhs = ops.apply_L(tab, x, 2) @ y
+    rhs = x @ ops.apply_LT(tab, y, 81, 2)
+    assert abs(lhs - rhs) <= 1e-12 * (abs(lhs) + 1)
+    Lm = ops.dense_L(tab, 81, 2)
+    np.testing.assert_allclose(Lm @ x, ops.apply_L(tab, x, 2), atol=1e-14)
+
+
+@pytest.mark.parametrize("K", [3, 5, 7])
+def test_adjoint_and_fft_B(K):
+    rng = np.random.default_rng(K)
+    P = rng.uniform(0, 1, (K, K))
+    P /= P.sum()
+    x = rng.standard_normal((11, 13))
+    y = rng.standard_normal((11, 13))
+    bx = ops.apply_B(P, x)
+    assert abs((bx * y).sum() - (x * ops.apply_BT(P, y)).sum()) < 1e-12
+    # zero-padded linear convolution via FFT padded to >= N + K - 1 (independent)
+    ny, nx = x.shape
+    sy, sx = ny + K - 1, nx + K - 1
+    full = np.real(np.fft.ifft2(np.fft.fft2(x, (sy, sx)) * np.fft.fft2(P, (sy, sx))))
+    ck = (K - 1) // 2
+    np.testing.assert_allclose(bx, full[ck:ck + ny, ck:ck + nx], atol=1e-12)
+
+
+def test_B_delta_and_flux():
+    P = mock.gaussian_psf(5, 1.5)
+    assert abs(P.sum() - 1) < 1e-15
+    e = np.zeros((9, 9))
+    e[4, 4] = 1.0
+    np.testing.assert_allclose(ops.apply_B(P, e)[2:7, 2:7], P, atol=1e-16)
+    rng = np.random.default_rng(0)
+    x = np.zeros((20, 20))
+    x[5:15, 5:15] = rng.uniform(size=(10, 10))
+    assert abs(ops.apply_B(P, x).sum() - x.sum()) < 1e-12
+
+
+def test_gaussian_psf_fwhm():
+    # the sampled profile along a row through the centre is exp(-a^2/(2 sig^2)),
+    # with half maximum at a = FWHM/2
+    P = mock.gaussian_psf(15, 3.0)
+    row = P[7] / P[7, 7]
+    sig = 3.0 / (2 * np.sqrt(2 * np.log(2)))
+    np.testing.assert_allclose(row, np.exp(-(np.arange(15) - 7.0) ** 2 / (2 * sig * sig)), rtol=1e-14)
+    assert abs(np.exp(-(1.5 ** 2) / (2 * sig * sig)) - 0.5) < 1e-15
+
+
+def test_dense_B_matches_operator():
+    P = mock.gaussian_psf(3, 1.0)
+    Bm = ops.dense_B(P, 5, 4)
+    x = np.random.default_rng(1).standard_normal((4, 5))
+    np.testing.assert_allclose(Bm @ x.reshape(-1), ops.apply_B(P, x).reshape(-1), atol=1e-15)
+    np.testing.assert_allclose(Bm.T @ x.reshape(-1), ops.apply_BT(P, x).reshape(-1), atol=1e-15)
+
+
+def test_curvature_H_rows():
+    ns = 6
+    Hm = ops.dense_H(ns, "curvature")
+    HtH = Hm.T @ Hm
+    # along one axis the 1-D Dirichlet D^2 has rows [5,-4,1], [-4,6,-4,1], [1,-4,6,-4,1]
+    D = np.diag(-2.0 * np.ones(ns)) + np.diag(np.ones(ns - 1), 1) + np.diag(np.ones(ns - 1), -1)
+    D2 = D @ D
+    assert list(D2[0, :3]) == [5, -4, 1] and list(D2[1, :4]) == [-4, 6, -4, 1]
+    assert list(D2[2, :5]) == [1, -4, 6, -4, 1]
+    Id = np.eye(ns)
+    np.testing.assert_allclose(HtH, np.kron(Id, D2) + np.kron(D2, Id), atol=0)
+    # SPD
+    assert np.linalg.eigvalsh(HtH).min() > 0
+    rng = np.random.default_rng(2)
+    x = rng.standard_normal(ns * ns)
+    y = rng.standard_normal(ns * ns)
+    hx = ops.apply_H(x, ns, "curvature")
+    np.testing.assert_allclose(hx, Hm @ x, atol=1e-14)
+    assert abs(hx @ ops.apply_H(y, ns, "curvature") - x @ ops.apply_HtH(y, ns, "curvature")) < 1e-11
+
+
+def test_identity_H():
+    x = np.arange(9.0)
+    np.testing.assert_array_equal(ops.apply_HtH(x, 3, "identity"), x)
