@@ -1,0 +1,239 @@
+/*
+ * semilin.h -- C ABI of the MI355X (gfx950) matrix-free semilinear lens solver.
+ *
+ * The library scores lens parameter sets the way Rogers & Fiege (2011) do:
+ * image pixels, split into n x n subpixels, are traced to the source plane
+ * through an analytic lens (thin-lens mapping, Sec. 2 Eq. 1; SIE deflection,
+ * Sec. 2.3 Eqs. 10-11; SIS, Sec. 4; plus uniform external shear, which the
+ * paper does not use); a pixelated source s is interpolated bilinearly at the
+ * traced positions and averaged over subpixels (L, Sec. 2.1-2.2), blurred by
+ * the PSF (B, Sec. 2.2); the regularised normal equations
+ *     (L^T B^T B L + lambda H^T H) s = L^T B^T d          (Eq. 7, Eq. 13-14, x0 = 0)
+ * are solved by conjugate gradients from a blank source (Sec. 2.2) for every
+ * lambda of a grid; chi^2 (Eq. 4) and ||H s||^2 form the L-curve whose point
+ * of maximum curvature (Sec. 2.6, Eq. 20) gives the lens's fitness.
+ *
+ * Conventions shared by every call:
+ *  - lengths in arcsec, angles in radians, arrays row-major;
+ *  - image pixel (r, c), index j = r*nx + c, has centre
+ *    ((c-(nx-1)/2) pix, (r-(ny-1)/2) pix); its subpixel k = sr*nsub + sc sits
+ *    at offset (((sc+1/2)/nsub - 1/2) pix, ((sr+1/2)/nsub - 1/2) pix);
+ *  - a member's source grid has ns x ns nodes at (-R + c h, -R + r h),
+ *    h = 2R/(ns-1), node i = r*ns + c; packed source vectors of several
+ *    members are concatenated in member order (member m starts at
+ *    sum_{m'<m} ns_{m'}^2);
+ *  - a subpixel traced to grid coordinates (u, v) is inside iff
+ *    0 <= u, v <= ns-1; it then spreads bilinear weights, each divided by
+ *    nsub^2, over the 4 nodes of cell (min(floor v, ns-2), min(floor u, ns-2));
+ *    outside subpixels contribute nothing;
+ *  - B is the zero-padded "same"-size convolution with a K x K PSF (K odd)
+ *    centred at (K-1)/2; B^T is the matching correlation;
+ *  - H is the identity or the stacked Dirichlet second differences along x
+ *    and along y (one row per node per axis);
+ *  - lens genome = 7 doubles (theta_E, q, pa, gamma, gamma_pa, x0, y0):
+ *    Einstein radius, axis ratio in (0,1], mass major-axis angle from +x,
+ *    external shear strength and angle, lens centre.
+ *
+ * Ownership: every array is allocated by the caller.  "device" arrays live
+ * in GPU memory of the current HIP device; "host" arrays in host memory and
+ * are only read during the call.  The library allocates no memory the caller
+ * sees; the solver's scratch comes from a caller workspace sized by
+ * sl_solve_workspace_size().  Calls are asynchronous on `stream` (a
+ * hipStream_t; NULL = default stream) unless stated otherwise; kernel faults
+ * surface at the next synchronisation.
+ *
+ * Errors: SL_OK (0) on success; SL_EINVAL (-1) for a bad host-side argument,
+ * detected before any launch; SL_EHIP (-2) for a HIP runtime error; SL_ENOIMPL
+ * (-3) for a size beyond the compiled limits.  sl_last_error() returns a
+ * thread-local message about the last non-zero return.  Per-member problems
+ * that live in device data (a bad genome, a source grid out of range, a lens
+ * that maps no ray onto the grid, CG hitting maxit) are reported through the
+ * per-(member, lambda) status array, never through the return code.
+ */
+#ifndef SEMILIN_H
+#define SEMILIN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { SL_OK = 0, SL_EINVAL = -1, SL_EHIP = -2, SL_ENOIMPL = -3 };
+enum { SL_F32 = 0, SL_F64 = 1 };                  /* arithmetic of the bulk work */
+enum { SL_H_IDENTITY = 0, SL_H_CURVATURE = 1 };   /* regularisation operator H */
+
+/* per-(member, lambda) status */
+enum {
+  SL_ST_OK = 0,        /* ||r|| <= tol ||b|| reached */
+  SL_ST_MAXIT = 1,     /* stopped at maxit; results written from the last iterate */
+  SL_ST_EMPTY = 2,     /* no subpixel maps onto the grid: b = 0, s = 0 */
+  SL_ST_BREAKDOWN = 3, /* <p, A p> <= 0 (loss of positive definiteness) */
+  SL_ST_INVALID = 4,   /* bad genome (non-finite, q outside (0,1], theta_E < 0) or ns out of range */
+  SL_ST_LCURVE = 5     /* (k_star status) fewer than 4 distinct L-curve points; k* = 0 */
+};
+
+#define SL_MAX_LAMBDA 64   /* longest lambda grid */
+#define SL_MAX_PSF 63      /* largest PSF side K */
+#define SL_MAX_NSUB 4      /* largest subpixel count per side */
+
+typedef struct {
+  int nx, ny;     /* image columns and rows */
+  double pix;     /* arcsec per pixel */
+  int nsub;       /* n: subpixels per pixel side (1..SL_MAX_NSUB) */
+} sl_image_grid;
+
+/*
+ * Lens tracing (Sec. 2 Eq. 1, Eqs. 10-11, Sec. 2.2 subpixels).
+ * lens: device double[n_members*7] genomes.  ns: host int32[n_members]
+ * source-grid sides (>= 2).  uv: device double[n_members][ny*nx*nsub^2][2],
+ * the grid coordinates (u, v) = ((beta_x+R)/h, (beta_y+R)/h) of every
+ * subpixel, written NaN for subpixels outside the grid.  Computed in FP64.
+ */
+int sl_lens_trace(const double* lens, int n_members, const sl_image_grid* img,
+                  const int32_t* ns, double half_width, double* uv, void* stream);
+
+/*
+ * L: unblurred lensed image of packed sources (Sec. 2.1, Sec. 2.2).
+ * dtype SL_F32 -> s, img_out are float; SL_F64 -> double.
+ * uv: as written by sl_lens_trace.  s: device packed sources.
+ * img_out: device [n_members][ny*nx], overwritten.
+ */
+int sl_apply_L(int dtype, const double* uv, int n_members, const sl_image_grid* img,
+               const int32_t* ns, const void* s, void* img_out, void* stream);
+
+/*
+ * L^T: exact transpose of sl_apply_L (Sec. 2.2).  img_in: device
+ * [n_members][ny*nx]; s_out: device packed sources, overwritten.
+ * Accumulates with atomics, so the summation order is not fixed.
+ */
+int sl_apply_LT(int dtype, const double* uv, int n_members, const sl_image_grid* img,
+                const int32_t* ns, const void* img_in, void* s_out, void* stream);
+
+/*
+ * B and B^T on n_images images of ny x nx (Sec. 2.2; zero padding).
+ * psf: device double[k*k], k odd <= SL_MAX_PSF.  in/out: device, distinct.
+ */
+int sl_apply_B(int dtype, int nx, int ny, int n_images, const double* psf, int k,
+               const void* in, void* out, void* stream);
+int sl_apply_BT(int dtype, int nx, int ny, int n_images, const double* psf, int k,
+                const void* in, void* out, void* stream);
+
+/*
+ * H^T H on packed sources (Eq. 7).  reg: SL_H_IDENTITY or SL_H_CURVATURE.
+ */
+int sl_apply_HtH(int dtype, int reg, int n_members, const int32_t* ns, const void* s, void* out,
+                 void* stream);
+
+typedef struct {
+  sl_image_grid img;
+  const double* d;     /* device double[ny*nx]: data image */
+  double sigma;        /* noise standard deviation (one value for all pixels) */
+  const double* psf;   /* device double[k*k], sums to one */
+  int k;               /* PSF side, odd, <= SL_MAX_PSF */
+  double half_width;   /* R: every member's grid spans +-R */
+  int reg;             /* SL_H_IDENTITY | SL_H_CURVATURE */
+  int dtype;           /* SL_F32: FP32 bulk, FP64 inner products / chi^2 / L-curve;
+                          SL_F64: FP64 throughout */
+} sl_problem;
+
+typedef struct {
+  double tol;          /* stop when ||r|| <= tol ||b|| */
+  int maxit;           /* iteration cap per (member, lambda) */
+} sl_solve_opts;
+
+typedef struct {
+  double* s_corner;    /* device double[sum_m ns_m^2]: solution at each member's corner */
+  int64_t* s_off;      /* device int64[n_members+1]: start of each member in s_corner */
+  double* chi2;        /* device double[n_members*n_lambda] */
+  double* reg;         /* device double[n_members*n_lambda]: ||H s||^2 */
+  int32_t* iters;      /* device int32[n_members*n_lambda] */
+  int32_t* status;     /* device int32[n_members*n_lambda], SL_ST_* */
+  int32_t* k_star;     /* device int32[n_members]: L-curve corner index */
+  int32_t* corner_status; /* device int32[n_members]: SL_ST_OK, _EMPTY, _INVALID or _LCURVE */
+} sl_result;
+
+/*
+ * Workspace bytes for sl_solve_semilinear with these sizes.  max_ns bounds
+ * every member's ns.  Returns 0 for invalid sizes (see sl_last_error()).
+ */
+size_t sl_solve_workspace_size(const sl_problem* pb, int max_ns, int n_members, int n_lambda);
+
+/*
+ * Batched regularised solve and L-curve corner of n_members lens sets
+ * against one data image (Sec. 2.1-2.6, Sec. 3: the fitness of the outer
+ * optimiser).  Every (member, lambda) pair is one CG solve from s = 0; all
+ * pairs run in one persistent launch.
+ *   lens:    device double[n_members*7]
+ *   ns:      device int32[n_members], each in [2, max_ns]
+ *   lambdas: host double[n_lambda], strictly ascending, positive, n_lambda <= SL_MAX_LAMBDA
+ *   workspace: device, >= sl_solve_workspace_size(pb, max_ns, n_members, n_lambda) bytes,
+ *              256-byte aligned; contents need not be initialised
+ * Results go to `out`.  With n_lambda < 4 the corner is index 0
+ * (corner_status SL_ST_LCURVE when n_lambda is 2 or 3).
+ */
+int sl_solve_semilinear(const sl_problem* pb, const double* lens, const int32_t* ns, int max_ns,
+                        int n_members, const double* lambdas, int n_lambda,
+                        const sl_solve_opts* opt, void* workspace, size_t workspace_bytes,
+                        sl_result* out, void* stream);
+
+/*
+ * L-curve corner (Sec. 2.6, Eq. 20) on the host, synchronous: points
+ * (log10 reg_k, log10 chi2_k) are parameterised by chord length, points whose
+ * step is <= 1e-12 of the total are dropped, not-a-knot cubic splines are
+ * fitted to both coordinates and the curvature
+ * |x'y'' - y'x''| / (x'^2 + y'^2)^(3/2) is evaluated at the knots;
+ * *k_star = argmax (ties within 1e-12 relative go to the smaller index).
+ * kappa (nullable) receives n curvatures, NaN at dropped points.
+ * Returns SL_EINVAL when n < 4, a value is not positive and finite, or fewer
+ * than 4 distinct points remain.
+ */
+int sl_lcurve_corner(const double* reg, const double* chi2, int n, int32_t* k_star, double* kappa);
+
+/* ---------------------------------------------------------------------------
+ * Surrogate MLP 7 -> 256 -> 256 -> 1 with GELU (erf form), BF16 weight copies
+ * and FP32 accumulation (not in the paper: a learned pre-screen of offspring).
+ * Parameters live in one device float buffer of SL_MLP_NPARAM floats in the
+ * order W0[7][256], b0[256], W1[256][256], b1[256], W2[256][1], b2[1]
+ * (W[in][out]).  Adam moments m, v use the same layout.
+ * ------------------------------------------------------------------------- */
+#define SL_MLP_IN 7
+#define SL_MLP_HID 256
+#define SL_MLP_NPARAM (7 * 256 + 256 + 256 * 256 + 256 + 256 + 1)
+
+/*
+ * Workspace floats for a batch (activations, gradients, BF16 weight copies).
+ */
+size_t sl_mlp_workspace_size(int batch);
+
+/*
+ * Forward pass: y[b] = MLP(x[b]) for b < batch.  x: device float[batch*7];
+ * y: device float[batch].  Weights are rounded to BF16 and hidden
+ * activations are rounded to BF16 before each matrix product; sums are FP32.
+ */
+int sl_mlp_forward(const float* params, const float* x, int batch, float* y, void* workspace,
+                   void* stream);
+
+/*
+ * One Adam step on the mean squared error (1/B) sum (y_hat - y)^2:
+ * forward, backward (same BF16 roundings), then
+ * m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2; p -= lr mhat / (sqrt(vhat) + eps)
+ * with bias corrections for step number t (>= 1).  grads_out (nullable):
+ * device float[SL_MLP_NPARAM] receives the gradient; loss_out (nullable):
+ * device float[1] receives the batch loss.
+ */
+int sl_mlp_train_step(float* params, float* adam_m, float* adam_v, const float* x, const float* y,
+                      int batch, float lr, int t, float* grads_out, float* loss_out,
+                      void* workspace, void* stream);
+
+/* Thread-local message describing the last non-zero return. */
+const char* sl_last_error(void);
+
+/* Library version string. */
+const char* sl_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SEMILIN_H */

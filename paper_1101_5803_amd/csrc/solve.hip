@@ -1,0 +1,1054 @@
+// Batched matrix-free regularised source solve (Rogers & Fiege 2011, Sec. 2.1-2.6).
+//
+// One call scores n_members lens parameter sets against one data image:
+//   k_setup   (1 block)          member offsets, XCD-sorted work queues, PSF
+//                                factorisation (rank-1 test, 1-D taps, the
+//                                banded B^T B coefficients and their image-edge
+//                                corrections), sum of d^2
+//   k_prep    (1 block/member)   FP64 subpixel trace (Eq. 1, Eqs. 10-11) of
+//                                every pixel, compaction of the pixels that map
+//                                onto the grid (Sec. 2.2: the others get no
+//                                intensity), their bounding box, and the
+//                                right-hand side b = L^T B^T d in FP64
+//   k_solve   (persistent, 1 block/CU)  each block pulls (member, lambda) items
+//                                and runs CG on (L^T B^T B L + lambda H^T H) s = b
+//                                from s = 0 (Eq. 7, Eq. 13-14, Sec. 2.2); source
+//                                vectors live in registers, the source p / q in
+//                                LDS, the image-space intermediate in an LDS
+//                                frame over the mapped bounding box; ends with
+//                                chi^2 (Eq. 4) and ||H s||^2 in FP64
+//   k_corner  (1 block/member)   L-curve corner (Sec. 2.6, Eq. 20) in FP64 and
+//                                the corner solution copy
+//
+// B^T B for a rank-1 PSF P = g_y g_x^T factorises as (C_y^T C_y) (x) (C_x^T C_x)
+// with C the truncated 1-D "same" convolutions; each factor is a symmetric
+// banded matrix equal to the autocorrelation of the 1-D taps except in the
+// ck x ck corners next to the image edges, so B^T B y is two in-place banded
+// passes over the frame (rows, then columns) with (4ck+1) taps plus a small
+// correction for outputs within ck of the image edge.  A PSF that is not
+// rank-1 takes the direct K x K path with an image-space buffer in global memory.
+#include <climits>
+#include <mutex>
+#include <vector>
+
+#include "common.h"
+
+namespace sl {
+
+constexpr int kNT = 512;      // threads per solve block
+constexpr int kWaves = kNT / kWave;
+constexpr int kSegR = 4;       // outputs per lane in a banded pass
+constexpr int kMaxCK = 31;
+
+struct alignas(16) MemberInfo {
+  int ns, I, M, r0, r1, c0, c1, status;
+  long long off;   // start in packed vectors
+  long long pad;
+};
+
+// Device constants written by k_setup (one copy per workspace).
+struct alignas(16) Consts {
+  int qhead[8];
+  int qcount[8];
+  int sep;          // PSF is rank-1
+  int pad0[3];
+  double sum_d2;
+  double pad1;
+};
+
+struct Layout {
+  size_t consts, lam, taps_d, taps_f, minfo, queues, pix, cell, fx, fy, b, s_all, gframe, gz, total;
+  int qcap, n_wg, I_max, J, n2, gframe_elems;
+};
+
+// Offsets (elements) inside the taps arrays, for a PSF of side K (ck = (K-1)/2).
+struct TapIdx {
+  int gx, gy, ax, ay, elx, erx, ely, ery, psf, total;
+  __host__ __device__ TapIdx(int K) {
+    const int ck = (K - 1) / 2;
+    const int na = 4 * kMaxCK + 1;     // autocorrelation padded to the largest window
+    gx = 0;
+    gy = gx + K;
+    ax = gy + K;
+    ay = ax + na;
+    elx = ay + na;
+    erx = elx + ck * ck;
+    ely = erx + ck * ck;
+    ery = ely + ck * ck;
+    psf = ery + ck * ck;
+    total = psf + K * K;
+  }
+};
+
+// ------------------------------------------------------------------ parameters
+struct SolveArgs {
+  int nx, ny, nsub, n2, K, ck, ckt, reg, n_members, n_lambda, max_ns, maxit, lds_frame_cap;
+  int q_off, red_off, frame_off;   // byte offsets in dynamic LDS
+  int gframe_elems;                // per-block global frame size (elements)
+  double pix, R, sigma, tol;
+  double* lamv;                    // workspace copy of the lambda grid
+  const double* lens;
+  const int32_t* ns;
+  const double* d;
+  const double* psf;
+  // results
+  double* s_corner;
+  int64_t* s_off;
+  double* chi2;
+  double* regv;
+  int32_t* iters;
+  int32_t* status;
+  int32_t* k_star;
+  int32_t* corner_status;
+  // workspace
+  Consts* consts;
+  double* taps_d;
+  void* taps_t;   // taps in the bulk type
+  MemberInfo* minfo;
+  int* queues;
+  int qcap;
+  int32_t* pix_list;
+  int32_t* cell;
+  void* fx;
+  void* fy;
+  double* b;
+  void* s_all;
+  void* gframe;
+  void* gz;
+  int I_max;
+};
+
+// ------------------------------------------------------------------ block scan
+// Exclusive prefix count of `flag` over the block; returns this thread's
+// offset and writes the block total to *total.  `scratch` >= 16 ints.
+__device__ __forceinline__ int block_excl_count(bool flag, int* scratch, int* total) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const unsigned long long bal = __ballot(flag);
+  const int in_wave = __popcll(bal & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
+  if (lane == 0) scratch[wid] = __popcll(bal);
+  __syncthreads();
+  int before = 0, tot = 0;
+  for (int i = 0; i < nw; ++i) {
+    const int c = scratch[i];
+    if (i < wid) before += c;
+    tot += c;
+  }
+  __syncthreads();
+  *total = tot;
+  return before + in_wave;
+}
+
+// ------------------------------------------------------------------ k_setup
+struct LamList {
+  double v[SL_MAX_LAMBDA];
+};
+
+template <typename T>
+__global__ void __launch_bounds__(1024) k_setup(SolveArgs a, LamList lams) {
+  __shared__ double red[32];
+  if (threadIdx.x < a.n_lambda) a.lamv[threadIdx.x] = lams.v[threadIdx.x];
+  __shared__ int counts[4097];
+  const int tid = threadIdx.x;
+  const int M = a.n_members, K = a.K, ck = a.ck;
+  // offsets of packed solutions; invalid ns contribute nothing
+  if (tid == 0) {
+    long long off = 0;
+    for (int m = 0; m < M; ++m) {
+      const int ns = a.ns[m];
+      const bool ok = ns >= 2 && ns <= a.max_ns;
+      a.s_off[m] = off;
+      a.minfo[m].ns = ok ? ns : 0;
+      a.minfo[m].I = ok ? ns * ns : 0;
+      a.minfo[m].off = off;
+      off += ok ? (long long)ns * ns : 0;
+    }
+    a.s_off[M] = off;
+  }
+  // counting sort of members by descending ns -> XCD queues round-robin
+  for (int i = tid; i <= 4096; i += blockDim.x) counts[i] = 0;
+  __syncthreads();
+  if (tid == 0) {
+    for (int m = 0; m < M; ++m) {
+      const int ns = a.ns[m];
+      counts[(ns >= 2 && ns <= a.max_ns) ? ns : 0]++;
+    }
+    int start = 0;   // exclusive prefix in descending ns order
+    for (int v = 4096; v >= 0; --v) {
+      const int c = counts[v];
+      counts[v] = start;
+      start += c;
+    }
+    // rank r -> queue r % 8; the sort is stable in member index
+    for (int m = 0; m < M; ++m) {
+      const int ns = a.ns[m];
+      const int key = (ns >= 2 && ns <= a.max_ns) ? ns : 0;
+      const int r = counts[key]++;
+      const int q = r & 7;
+      const int slot = (r >> 3) * a.n_lambda;
+      for (int k = 0; k < a.n_lambda; ++k) a.queues[q * a.qcap + slot + k] = m * a.n_lambda + k;
+    }
+    for (int q = 0; q < 8; ++q) {
+      // members with rank r = q + 8 t fill queue q densely
+      const int nm = (M > q) ? (M - q + 7) / 8 : 0;
+      a.consts->qcount[q] = nm * a.n_lambda;
+      a.consts->qhead[q] = 0;
+    }
+    // PSF: rank-1 test and factorisation P[a][b] = gy[a] * gx[b]
+    const TapIdx ti(K);
+    int am = 0, bm = 0;
+    double pmax = 0.0;
+    for (int i = 0; i < K * K; ++i)
+      if (fabs(a.psf[i]) > pmax) {
+        pmax = fabs(a.psf[i]);
+        am = i / K;
+        bm = i % K;
+      }
+    double* tp = a.taps_d;
+    for (int i = 0; i < ti.total; ++i) tp[i] = 0.0;
+    for (int i = 0; i < K * K; ++i) tp[ti.psf + i] = a.psf[i];
+    int sep = pmax > 0.0;
+    if (sep) {
+      for (int x = 0; x < K; ++x) {
+        tp[ti.gy + x] = a.psf[x * K + bm];
+        tp[ti.gx + x] = a.psf[am * K + x] / a.psf[am * K + bm];
+      }
+      for (int x = 0; x < K && sep; ++x)
+        for (int y = 0; y < K; ++y)
+          if (fabs(a.psf[x * K + y] - tp[ti.gy + x] * tp[ti.gx + y]) > 1e-12 * pmax) {
+            sep = 0;
+            break;
+          }
+    }
+    // the banded path needs the kernel's window to cover +-2ck
+    if (ck > a.ckt) sep = 0;
+    a.consts->sep = sep;
+    if (sep) {
+      // autocorrelations a[d] = sum_i g[i] g[i-d], stored at index d + 2*kMaxCK
+      for (int dd = -(K - 1); dd <= K - 1; ++dd) {
+        double sx = 0.0, sy = 0.0;
+        for (int i = 0; i < K; ++i) {
+          const int j = i - dd;
+          if (j < 0 || j >= K) continue;
+          sx += tp[ti.gx + i] * tp[ti.gx + j];
+          sy += tp[ti.gy + i] * tp[ti.gy + j];
+        }
+        tp[ti.ax + dd + 2 * kMaxCK] = sx;
+        tp[ti.ay + dd + 2 * kMaxCK] = sy;
+      }
+      // edge corrections: the truncated 1-D convolution C has (C^T C)[c][c']
+      // = a[c'-c] - sum over intermediate indices k outside the image
+      for (int p = 0; p < ck; ++p)
+        for (int q = 0; q < ck; ++q) {
+          double lx = 0.0, ly = 0.0, rx = 0.0, ry = 0.0;
+          for (int k = -ck; k < 0; ++k) {
+            const int i1 = k - p + ck, i2 = k - q + ck;
+            if (i1 >= 0 && i1 < K && i2 >= 0 && i2 < K) {
+              lx += tp[ti.gx + i1] * tp[ti.gx + i2];
+              ly += tp[ti.gy + i1] * tp[ti.gy + i2];
+            }
+          }
+          // right edge: outputs c = n - ck + p, inputs c' = n - ck + q, k = n + kk
+          for (int kk = 0; kk < ck; ++kk) {
+            const int i1 = kk + 2 * ck - p, i2 = kk + 2 * ck - q;   // k - c + ck, k - c' + ck
+            if (i1 >= 0 && i1 < K && i2 >= 0 && i2 < K) {
+              rx += tp[ti.gx + i1] * tp[ti.gx + i2];
+              ry += tp[ti.gy + i1] * tp[ti.gy + i2];
+            }
+          }
+          tp[ti.elx + p * ck + q] = lx;
+          tp[ti.ely + p * ck + q] = ly;
+          tp[ti.erx + p * ck + q] = rx;
+          tp[ti.ery + p * ck + q] = ry;
+        }
+    }
+    T* tt = reinterpret_cast<T*>(a.taps_t);
+    for (int i = 0; i < ti.total; ++i) tt[i] = (T)tp[i];
+  }
+  // sum of d^2 in FP64
+  double acc = 0.0;
+  const int J = a.nx * a.ny;
+  for (int j = tid; j < J; j += blockDim.x) acc += a.d[j] * a.d[j];
+  acc = block_sum(acc, red);
+  if (tid == 0) a.consts->sum_d2 = acc;
+}
+
+// ------------------------------------------------------------------ k_prep
+template <typename T>
+__global__ void __launch_bounds__(1024) k_prep(SolveArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  double* bacc = reinterpret_cast<double*>(smem);
+  __shared__ int scan[32];
+  __shared__ int bbox[4];
+  __shared__ double g[7];
+  const int m = blockIdx.x, tid = threadIdx.x;
+  const int nx = a.nx, ny = a.ny, J = nx * ny, nsub = a.nsub, n2 = a.n2;
+  MemberInfo mi = a.minfo[m];
+  if (tid < 7) g[tid] = a.lens[7L * m + tid];
+  if (tid == 0) {
+    bbox[0] = INT_MAX;
+    bbox[1] = INT_MIN;
+    bbox[2] = INT_MAX;
+    bbox[3] = INT_MIN;
+  }
+  __syncthreads();
+  double gl[7];
+#pragma unroll
+  for (int i = 0; i < 7; ++i) gl[i] = g[i];
+  const bool valid = mi.ns >= 2 && lens_valid(gl);
+  if (!valid) {
+    if (tid == 0) {
+      mi.M = 0;
+      mi.status = SL_ST_INVALID;
+      mi.r0 = mi.c0 = 0;
+      mi.r1 = mi.c1 = -1;
+      a.minfo[m] = mi;
+    }
+    return;
+  }
+  const Lens L = make_lens(gl);
+  const int ns = mi.ns;
+  const double h = 2.0 * a.R / (ns - 1);
+  int32_t* pix = a.pix_list + (long)m * J;
+  int32_t* cellp = a.cell + (long)m * J * n2;
+  T* fxp = reinterpret_cast<T*>(a.fx) + (long)m * J * n2;
+  T* fyp = reinterpret_cast<T*>(a.fy) + (long)m * J * n2;
+  int base = 0;
+  for (int j0 = 0; j0 < J; j0 += blockDim.x) {
+    const int j = j0 + tid;
+    const int r = j / nx, c = j % nx;
+    bool mapped = false;
+    if (j < J) {
+      for (int k = 0; k < n2; ++k) {
+        double x, y, bx, by, fx, fy;
+        int cell;
+        subpixel_xy(r, c, k / nsub, k % nsub, nx, ny, a.pix, nsub, x, y);
+        lens_map(L, x, y, bx, by);
+        mapped |= grid_cell((bx + a.R) / h, (by + a.R) / h, ns, cell, fx, fy);
+      }
+    }
+    int tot;
+    const int pos = base + block_excl_count(mapped, scan, &tot);
+    if (mapped) {
+      pix[pos] = j;
+      // second pass over the subpixels writes the compacted table directly
+      for (int k = 0; k < n2; ++k) {
+        double x, y, bx, by, fx = 0.0, fy = 0.0;
+        int cell = -1;
+        subpixel_xy(r, c, k / nsub, k % nsub, nx, ny, a.pix, nsub, x, y);
+        lens_map(L, x, y, bx, by);
+        if (!grid_cell((bx + a.R) / h, (by + a.R) / h, ns, cell, fx, fy)) {
+          cell = -1;
+          fx = fy = 0.0;
+        }
+        cellp[(long)pos * n2 + k] = cell;
+        fxp[(long)pos * n2 + k] = (T)fx;
+        fyp[(long)pos * n2 + k] = (T)fy;
+      }
+      atomicMin(&bbox[0], r);
+      atomicMax(&bbox[1], r);
+      atomicMin(&bbox[2], c);
+      atomicMax(&bbox[3], c);
+    }
+    base += tot;
+  }
+  const int Mm = base;
+  // right-hand side b = L^T B^T d (FP64)
+  const int I = ns * ns;
+  for (int i = tid; i < I; i += blockDim.x) bacc[i] = 0.0;
+  __syncthreads();
+  const int K = a.K, ck = a.ck;
+  const double inv_n2 = 1.0 / n2;
+  for (int t = tid; t < Mm; t += blockDim.x) {
+    const int j = pix[t], r = j / nx, c = j % nx;
+    double v = 0.0;
+    for (int aa = 0; aa < K; ++aa) {
+      const int rr = r + aa - ck;
+      if (rr < 0 || rr >= ny) continue;
+      for (int bb = 0; bb < K; ++bb) {
+        const int cc = c + bb - ck;
+        if (cc < 0 || cc >= nx) continue;
+        v += a.psf[aa * K + bb] * a.d[rr * nx + cc];
+      }
+    }
+    v *= inv_n2;
+    for (int k = 0; k < n2; ++k) {
+      const int cell = cellp[(long)t * n2 + k];
+      if (cell < 0) continue;
+      const double fx = (double)fxp[(long)t * n2 + k], fy = (double)fyp[(long)t * n2 + k];
+      atomicAdd(&bacc[cell], (1 - fx) * (1 - fy) * v);
+      atomicAdd(&bacc[cell + 1], fx * (1 - fy) * v);
+      atomicAdd(&bacc[cell + ns], (1 - fx) * fy * v);
+      atomicAdd(&bacc[cell + ns + 1], fx * fy * v);
+    }
+  }
+  __syncthreads();
+  double* bm = a.b + (long)m * a.I_max;
+  for (int i = tid; i < I; i += blockDim.x) bm[i] = bacc[i];
+  if (tid == 0) {
+    mi.M = Mm;
+    mi.status = Mm > 0 ? SL_ST_OK : SL_ST_EMPTY;
+    mi.r0 = Mm > 0 ? bbox[0] : 0;
+    mi.r1 = Mm > 0 ? bbox[1] : -1;
+    mi.c0 = Mm > 0 ? bbox[2] : 0;
+    mi.c1 = Mm > 0 ? bbox[3] : -1;
+    a.minfo[m] = mi;
+  }
+}
+
+// ------------------------------------------------------------------ banded pass
+// In-place pass out(p) = sum_{|d|<=2ck} a[|d|] in(p+d) - edge corrections along
+// `nlines` lines of length `len` of the frame interior.  The frame carries a
+// zero halo of 2*CKT elements on every side, so windows need no bounds tests.
+// `F0` points at interior element (0, 0).  ROW: element (line, p) at
+// F0[line*pitch + p]; else F0[p*pitch + line].  Every line is handled by the
+// lanes of one wave within one step, so all reads of a line precede its
+// writes.  acoef[d + 2*kMaxCK] = a[d].
+template <typename T, int CKT, bool ROW>
+__device__ __forceinline__ void banded_pass(T* __restrict__ F0, int pitch, int nlines, int len,
+                                            int img_off, int img_len, int ck,
+                                            const T* __restrict__ acoef, const T* __restrict__ EL,
+                                            const T* __restrict__ ER) {
+  constexpr int W = kSegR + 4 * CKT;
+  constexpr int NH = 2 * CKT;
+  T ac[NH + 1];
+#pragma unroll
+  for (int x = 0; x <= NH; ++x) ac[x] = acoef[2 * kMaxCK + x];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int S = (len + kSegR - 1) / kSegR;
+  const int LPW = 64 / S;
+  const int sub_line = lane / S, seg = lane % S;
+  const int p0 = seg * kSegR;
+  const int step = ROW ? 1 : pitch;          // distance between positions
+  const int lstride = ROW ? pitch : 1;       // distance between lines
+  const bool edges = img_off < ck || img_off + len > img_len - ck;
+  for (int l0 = wv * LPW; l0 < nlines; l0 += kWaves * LPW) {   // same trip count for the whole wave
+    const int line = l0 + sub_line;
+    const bool active = sub_line < LPW && line < nlines;
+    const T* src = F0 + (active ? line * lstride + (p0 - NH) * step : 0);
+    T win[W];
+#pragma unroll
+    for (int x = 0; x < W; ++x) win[x] = active ? src[x * step] : (T)0;
+    T out[kSegR];
+#pragma unroll
+    for (int o = 0; o < kSegR; ++o) {
+      T acc = ac[0] * win[o + NH];
+#pragma unroll
+      for (int d = 1; d <= NH; ++d) acc += ac[d] * (win[o + NH - d] + win[o + NH + d]);
+      out[o] = acc;
+    }
+    if (active && edges) {
+      // outputs within ck of the image border: subtract the part of the
+      // autocorrelation that runs through intermediate pixels outside the image
+#pragma unroll
+      for (int o = 0; o < kSegR; ++o) {
+        const int gpos = img_off + p0 + o;
+        if (gpos < ck) {
+          T corr = 0;
+          for (int q = 0; q < ck; ++q) {
+            const int pp = q - img_off;
+            if (pp >= 0 && pp < len) corr += EL[gpos * ck + q] * F0[line * lstride + pp * step];
+          }
+          out[o] -= corr;
+        }
+        if (gpos >= img_len - ck) {
+          const int pr = gpos - (img_len - ck);
+          T corr = 0;
+          for (int q = 0; q < ck; ++q) {
+            const int pp = img_len - ck + q - img_off;
+            if (pp >= 0 && pp < len) corr += ER[pr * ck + q] * F0[line * lstride + pp * step];
+          }
+          out[o] -= corr;
+        }
+      }
+    }
+    // every lane of the wave has read its window (and edge inputs) before any
+    // lane overwrites the line: keep the compiler from sinking loads below here
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (active) {
+      T* dst = F0 + line * lstride + p0 * step;
+#pragma unroll
+      for (int o = 0; o < kSegR; ++o)
+        if (p0 + o < len) dst[o * step] = out[o];
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+// ------------------------------------------------------------------ k_solve
+template <typename T>
+__device__ __forceinline__ T lds_node(const T* P, int ns, int r, int c) {
+  return (r < 0 || c < 0 || r >= ns || c >= ns) ? (T)0 : P[r * ns + c];
+}
+
+// H^T H p at node (r, c): D2 (x) I + I (x) D2 with the 1-D Dirichlet D2
+// (rows [5,-4,1], [-4,6,-4,1], [1,-4,6,-4,1], ...).
+template <typename T>
+__device__ __forceinline__ T hth_node(const T* P, int ns, int r, int c) {
+  const T ctr = P[r * ns + c];
+  const T dgx = (T)(6 - (c == 0) - (c == ns - 1));
+  const T dgy = (T)(6 - (r == 0) - (r == ns - 1));
+  const T n1 = lds_node(P, ns, r, c - 1) + lds_node(P, ns, r, c + 1) + lds_node(P, ns, r - 1, c) +
+               lds_node(P, ns, r + 1, c);
+  const T n2 = lds_node(P, ns, r, c - 2) + lds_node(P, ns, r, c + 2) + lds_node(P, ns, r - 2, c) +
+               lds_node(P, ns, r + 2, c);
+  return (dgx + dgy) * ctr - (T)4 * n1 + n2;
+}
+
+template <typename T>
+__device__ __forceinline__ double reg_node(const T* P, int ns, int r, int c, int reg) {
+  const double ctr = (double)P[r * ns + c];
+  if (reg == SL_H_IDENTITY) return ctr * ctr;
+  const double dx = (double)lds_node(P, ns, r, c - 1) - 2.0 * ctr + (double)lds_node(P, ns, r, c + 1);
+  const double dy = (double)lds_node(P, ns, r - 1, c) - 2.0 * ctr + (double)lds_node(P, ns, r + 1, c);
+  return dx * dx + dy * dy;
+}
+
+// Write L x (x in LDS P) into the frame F at the mapped pixels.
+template <typename T>
+__device__ __forceinline__ void apply_L_frame(const SolveArgs& a, const T* P, T* F, int pitch, int M,
+                                              int r0, int c0, int ns, const int32_t* pix,
+                                              const int32_t* cellp, const T* fxp, const T* fyp) {
+  const int n2 = a.n2, nx = a.nx;
+  const T inv_n2 = (T)1 / (T)n2;
+  for (int t = threadIdx.x; t < M; t += kNT) {
+    const int j = pix[t];
+    T acc = 0;
+    for (int k = 0; k < n2; ++k) {
+      const int cell = cellp[(long)t * n2 + k];
+      if (cell < 0) continue;
+      const T fx = fxp[(long)t * n2 + k], fy = fyp[(long)t * n2 + k];
+      acc += (1 - fy) * ((1 - fx) * P[cell] + fx * P[cell + 1]) +
+             fy * ((1 - fx) * P[cell + ns] + fx * P[cell + ns + 1]);
+    }
+    F[(j / nx - r0) * pitch + (j % nx - c0)] = acc * inv_n2;
+  }
+}
+
+// Block-wide FP64 sum with one barrier; consecutive calls must alternate `buf`
+// (0/1) and be separated by at least one other barrier before a buffer is reused.
+__device__ __forceinline__ double block_sum1(double v, double* scratch, int buf) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  v = wave_sum(v);
+  double* sc = scratch + 16 * buf;
+  if (lane == 0) sc[wid] = v;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int i = 0; i < kWaves; ++i) t += sc[i];
+  return t;
+}
+
+template <typename T, int CKT, int NPT, bool LDSF>
+__device__ void run_item(const SolveArgs& a, int m, int kl, unsigned char* smem) {
+  const int tid = threadIdx.x;
+  const MemberInfo mi = a.minfo[m];
+  const long out_idx = (long)m * a.n_lambda + kl;
+  T* s_dst = reinterpret_cast<T*>(a.s_all) + ((long)m * a.n_lambda + kl) * a.I_max;
+  if (mi.status != SL_ST_OK) {
+    // invalid or empty member: s = 0, chi^2 = sum d^2 / sigma^2
+    for (int i = tid; i < mi.I; i += kNT) s_dst[i] = (T)0;
+    if (tid == 0) {
+      a.chi2[out_idx] = mi.status == SL_ST_INVALID ? NAN : a.consts->sum_d2 / (a.sigma * a.sigma);
+      a.regv[out_idx] = mi.status == SL_ST_INVALID ? NAN : 0.0;
+      a.iters[out_idx] = 0;
+      a.status[out_idx] = mi.status;
+    }
+    return;
+  }
+  const int ns = mi.ns, I = mi.I, M = mi.M, r0 = mi.r0, c0 = mi.c0;
+  const int h = mi.r1 - mi.r0 + 1, w = mi.c1 - mi.c0 + 1;
+  constexpr int HALO = 2 * CKT;
+  const int pitch = (w + 2 * HALO) | 1;
+  // kSegR extra rows absorb the tail of the last column window
+  const int frame_elems = (h + 2 * HALO + kSegR) * pitch;
+  const int J = a.nx * a.ny, n2 = a.n2, nx = a.nx, ny = a.ny, K = a.K, ck = a.ck;
+  const double lam = a.lamv[kl];
+  const T lamT = (T)lam;
+  const bool ident = a.reg == SL_H_IDENTITY;
+  T* P = reinterpret_cast<T*>(smem);
+  T* Q = reinterpret_cast<T*>(smem + a.q_off);
+  double* red = reinterpret_cast<double*>(smem + a.red_off);
+  T* F;
+  if (LDSF)
+    F = reinterpret_cast<T*>(smem + a.frame_off);
+  else
+    F = reinterpret_cast<T*>(a.gframe) + (long)blockIdx.x * a.gframe_elems;
+  T* const F0 = F + HALO * pitch + HALO;        // interior (0, 0) = image (r0, c0)
+  T* const Frows = F + HALO * pitch;            // interior rows, contiguous
+  T* Z = reinterpret_cast<T*>(a.gz) + (long)blockIdx.x * J;
+  const int32_t* pix = a.pix_list + (long)m * J;
+  const int32_t* cellp = a.cell + (long)m * J * n2;
+  const T* fxp = reinterpret_cast<const T*>(a.fx) + (long)m * J * n2;
+  const T* fyp = reinterpret_cast<const T*>(a.fy) + (long)m * J * n2;
+  const T* taps = reinterpret_cast<const T*>(a.taps_t);
+  const TapIdx ti(K);
+  const bool sep = a.consts->sep != 0;
+  const T inv_n2 = (T)1 / (T)n2;
+  // dilated region (direct-blur paths): rows/cols within ck of the bbox, inside the image
+  const int Dr0 = max(mi.r0 - ck, 0), Dr1 = min(mi.r1 + ck, ny - 1);
+  const int Dc0 = max(mi.c0 - ck, 0), Dc1 = min(mi.c1 + ck, nx - 1);
+  const int Dh = Dr1 - Dr0 + 1, Dw = Dc1 - Dc0 + 1;
+
+  // s = 0, r = p = b (p in LDS P), Q = 0, frame (with its halo) = 0
+  for (int e = tid; e < frame_elems; e += kNT) F[e] = (T)0;
+  // row/column of this thread's first node, and the per-stride step
+  const int r_first = tid / ns, c_first = tid - (tid / ns) * ns;
+  const int r_step = kNT / ns, c_step = kNT - (kNT / ns) * ns;
+  T s[NPT], r[NPT];
+  double rr = 0.0;
+  const double* bm = a.b + (long)m * a.I_max;
+#pragma unroll
+  for (int k = 0; k < NPT; ++k) {
+    const int i = tid + k * kNT;
+    T bv = 0;
+    if (i < I) {
+      bv = (T)bm[i];
+      P[i] = bv;
+      Q[i] = (T)0;
+    }
+    s[k] = 0;
+    r[k] = bv;
+    rr += (double)bv * (double)bv;
+  }
+  rr = block_sum1(rr, red, 0);
+  const double stop2 = a.tol * a.tol * rr;
+  int st = SL_ST_MAXIT, it = 0;
+  for (it = 0; it < a.maxit; ++it) {
+    if (rr <= stop2) {
+      st = SL_ST_OK;
+      break;
+    }
+    // y = L p into the frame (P holds p, Q and the frame are zero)
+    apply_L_frame(a, P, F0, pitch, M, r0, c0, ns, pix, cellp, fxp, fyp);
+    __syncthreads();
+    if (sep) {
+      // w = B^T B y: banded pass along rows then along columns, in place
+      banded_pass<T, CKT, true>(F0, pitch, h, w, c0, nx, ck, taps + ti.ax, taps + ti.elx, taps + ti.erx);
+      __syncthreads();
+      banded_pass<T, CKT, false>(F0, pitch, w, h, r0, ny, ck, taps + ti.ay, taps + ti.ely, taps + ti.ery);
+      __syncthreads();
+    } else {
+      // z = B y over the dilated region into global Z
+      for (int e = tid; e < Dh * Dw; e += kNT) {
+        const int rr_ = Dr0 + e / Dw, cc_ = Dc0 + e % Dw;
+        T acc = 0;
+        for (int aa = 0; aa < K; ++aa) {
+          const int yr = rr_ - aa + ck - r0;
+          if (yr < 0 || yr >= h) continue;
+          for (int bb = 0; bb < K; ++bb) {
+            const int yc = cc_ - bb + ck - c0;
+            if (yc < 0 || yc >= w) continue;
+            acc += taps[ti.psf + aa * K + bb] * F0[yr * pitch + yc];
+          }
+        }
+        Z[e] = acc;
+      }
+      __syncthreads();
+      // w = B^T z at the mapped pixels, back into the frame
+      for (int t = tid; t < M; t += kNT) {
+        const int j = pix[t], rr_ = j / nx, cc_ = j % nx;
+        T acc = 0;
+        for (int aa = 0; aa < K; ++aa) {
+          const int zr = rr_ + aa - ck - Dr0;
+          if (zr < 0 || zr >= Dh) continue;
+          for (int bb = 0; bb < K; ++bb) {
+            const int zc = cc_ + bb - ck - Dc0;
+            if (zc < 0 || zc >= Dw) continue;
+            acc += taps[ti.psf + aa * K + bb] * Z[zr * Dw + zc];
+          }
+        }
+        F0[(rr_ - r0) * pitch + (cc_ - c0)] = acc;
+      }
+      __syncthreads();
+    }
+    // L^T w accumulated in LDS Q
+    for (int t = tid; t < M; t += kNT) {
+      const int j = pix[t];
+      const T wv = F0[(j / nx - r0) * pitch + (j % nx - c0)] * inv_n2;
+      for (int k = 0; k < n2; ++k) {
+        const int cell = cellp[(long)t * n2 + k];
+        if (cell < 0) continue;
+        const T fx = fxp[(long)t * n2 + k], fy = fyp[(long)t * n2 + k];
+        atomicAdd(&Q[cell], (1 - fx) * (1 - fy) * wv);
+        atomicAdd(&Q[cell + 1], fx * (1 - fy) * wv);
+        atomicAdd(&Q[cell + ns], (1 - fx) * fy * wv);
+        atomicAdd(&Q[cell + ns + 1], fx * fy * wv);
+      }
+    }
+    __syncthreads();
+    // q = A p (kept in Q), <p, q>; the frame returns to zero for the next iteration
+    double pq = 0.0;
+    {
+      int rn_ = r_first, cn_ = c_first;
+#pragma unroll 1
+      for (int i = tid; i < I; i += kNT) {
+        const T pv = P[i];
+        const T qv = Q[i] + lamT * (ident ? pv : hth_node(P, ns, rn_, cn_));
+        Q[i] = qv;
+        pq += (double)pv * (double)qv;
+        rn_ += r_step;
+        cn_ += c_step;
+        if (cn_ >= ns) {
+          cn_ -= ns;
+          ++rn_;
+        }
+      }
+    }
+    for (int e = tid; e < h * pitch; e += kNT) Frows[e] = (T)0;
+    pq = block_sum1(pq, red, 0);
+    if (!(pq > 0.0)) {
+      st = SL_ST_BREAKDOWN;
+      break;
+    }
+    const double alpha = rr / pq;
+    const T alT = (T)alpha;
+    double rn = 0.0;
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+      const int i = tid + k * kNT;
+      if (i < I) {
+        s[k] += alT * P[i];
+        r[k] -= alT * Q[i];
+        Q[i] = (T)0;
+        rn += (double)r[k] * (double)r[k];
+      }
+    }
+    rn = block_sum1(rn, red, 1);
+    const T beta = (T)(rn / rr);
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+      const int i = tid + k * kNT;
+      if (i < I) P[i] = r[k] + beta * P[i];
+    }
+    rr = rn;
+    __syncthreads();
+  }
+  if (st == SL_ST_MAXIT && rr <= stop2) st = SL_ST_OK;
+  // ---- chi^2 and ||H s||^2 from the explicit solution
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NPT; ++k) {
+    const int i = tid + k * kNT;
+    if (i < I) {
+      P[i] = s[k];
+      s_dst[i] = s[k];
+    }
+  }
+  for (int e = tid; e < h * pitch; e += kNT) Frows[e] = (T)0;
+  __syncthreads();
+  apply_L_frame(a, P, F0, pitch, M, r0, c0, ns, pix, cellp, fxp, fyp);
+  double regacc = 0.0;
+  for (int i = tid; i < I; i += kNT) regacc += reg_node(P, ns, i / ns, i % ns, a.reg);
+  __syncthreads();
+  double cacc = 0.0;
+  for (int e = tid; e < Dh * Dw; e += kNT) {
+    const int rr_ = Dr0 + e / Dw, cc_ = Dc0 + e % Dw;
+    T z = 0;
+    for (int aa = 0; aa < K; ++aa) {
+      const int yr = rr_ - aa + ck - r0;
+      if (yr < 0 || yr >= h) continue;
+      for (int bb = 0; bb < K; ++bb) {
+        const int yc = cc_ - bb + ck - c0;
+        if (yc < 0 || yc >= w) continue;
+        z += taps[ti.psf + aa * K + bb] * F0[yr * pitch + yc];
+      }
+    }
+    const double zd = (double)z;
+    cacc += zd * zd - 2.0 * zd * a.d[rr_ * nx + cc_];
+  }
+  block_sum2(cacc, regacc, red);
+  if (tid == 0) {
+    a.chi2[out_idx] = (a.consts->sum_d2 + cacc) / (a.sigma * a.sigma);
+    a.regv[out_idx] = regacc;
+    a.iters[out_idx] = it;
+    a.status[out_idx] = st;
+  }
+  __syncthreads();
+}
+
+template <typename T, int CKT, int NPT>
+__global__ void __launch_bounds__(kNT) k_solve(SolveArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int sh_item;
+  const int xcd = blockIdx.x & 7;
+  for (;;) {
+    if (threadIdx.x == 0) {
+      int item = -1;
+      for (int x = 0; x < 8 && item < 0; ++x) {
+        const int q = (xcd + x) & 7;
+        const int idx = atomicAdd(&a.consts->qhead[q], 1);
+        if (idx < a.consts->qcount[q]) item = a.queues[q * a.qcap + idx];
+      }
+      sh_item = item;
+    }
+    __syncthreads();
+    const int item = sh_item;
+    __syncthreads();
+    if (item < 0) break;
+    const int m = item / a.n_lambda, kl = item % a.n_lambda;
+    const MemberInfo mi = a.minfo[m];
+    const int h = mi.r1 - mi.r0 + 1, w = mi.c1 - mi.c0 + 1;
+    if (mi.status == SL_ST_OK && (h + 4 * CKT + kSegR) * ((w + 4 * CKT) | 1) > a.lds_frame_cap)
+      run_item<T, CKT, NPT, false>(a, m, kl, smem);
+    else
+      run_item<T, CKT, NPT, true>(a, m, kl, smem);
+  }
+}
+
+// ------------------------------------------------------------------ k_corner
+template <typename T>
+__global__ void __launch_bounds__(256) k_corner(SolveArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  double* scratch = reinterpret_cast<double*>(smem);
+  __shared__ int sh_k;
+  const int m = blockIdx.x;
+  const int nl = a.n_lambda;
+  const MemberInfo mi = a.minfo[m];
+  if (threadIdx.x == 0) {
+    int k = 0, cst = mi.status;
+    if (mi.status == SL_ST_OK) {
+      if (nl >= 4) {
+        const int kk = lcurve_corner_impl(a.regv + (long)m * nl, a.chi2 + (long)m * nl, nl, nullptr,
+                                          scratch);
+        if (kk >= 0)
+          k = kk;
+        else
+          cst = SL_ST_LCURVE;
+      } else if (nl > 1) {
+        cst = SL_ST_LCURVE;
+      }
+    }
+    a.k_star[m] = k;
+    a.corner_status[m] = cst;
+    sh_k = k;
+  }
+  __syncthreads();
+  const T* src = reinterpret_cast<const T*>(a.s_all) + ((long)m * nl + sh_k) * a.I_max;
+  for (int i = threadIdx.x; i < mi.I; i += blockDim.x) a.s_corner[mi.off + i] = (double)src[i];
+}
+
+// ------------------------------------------------------------------ host side
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+static int device_cus() {
+  static int cus[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  if (dev < 0 || dev >= 64) return 256;
+  if (cus[dev] == 0) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
+      n = 256;
+    cus[dev] = n;
+  }
+  return cus[dev];
+}
+
+static Layout make_layout(const sl_problem* pb, int max_ns, int M, int NL, int n_wg) {
+  Layout L{};
+  const size_t sz = pb->dtype == SL_F64 ? 8 : 4;
+  L.J = pb->img.nx * pb->img.ny;
+  L.n2 = pb->img.nsub * pb->img.nsub;
+  L.I_max = max_ns * max_ns;
+  L.n_wg = n_wg;
+  L.qcap = ((M + 7) / 8) * NL;
+  const TapIdx ti(pb->k);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  L.consts = take(sizeof(Consts));
+  L.lam = take(sizeof(double) * SL_MAX_LAMBDA);
+  L.taps_d = take(sizeof(double) * ti.total);
+  L.taps_f = take(sz * ti.total);
+  L.minfo = take(sizeof(MemberInfo) * M);
+  L.queues = take(sizeof(int) * 8 * (size_t)L.qcap);
+  L.pix = take(sizeof(int32_t) * (size_t)M * L.J);
+  L.cell = take(sizeof(int32_t) * (size_t)M * L.J * L.n2);
+  L.fx = take(sz * (size_t)M * L.J * L.n2);
+  L.fy = take(sz * (size_t)M * L.J * L.n2);
+  L.b = take(sizeof(double) * (size_t)M * L.I_max);
+  L.s_all = take(sz * (size_t)M * NL * L.I_max);
+  L.gframe_elems = (pb->img.ny + 4 * 16 + kSegR) * ((pb->img.nx + 4 * 16) | 1);   // widest window's halo
+  L.gframe = take(sz * (size_t)n_wg * L.gframe_elems);
+  L.gz = take(sz * (size_t)n_wg * L.J);
+  L.total = off;
+  return L;
+}
+
+static int check_problem(const sl_problem* pb, int max_ns, int M, int NL) {
+  SL_REQUIRE(pb != nullptr, "problem is NULL");
+  const sl_image_grid& g = pb->img;
+  SL_REQUIRE(g.nx >= 1 && g.ny >= 1 && g.nx <= 256 && g.ny <= 256,
+             "batched solve supports images up to 256 x 256 (got %d x %d)", g.nx, g.ny);
+  SL_REQUIRE(std::isfinite(g.pix) && g.pix > 0.0, "pixel size must be positive");
+  SL_REQUIRE(g.nsub >= 1 && g.nsub <= SL_MAX_NSUB, "nsub %d outside [1, %d]", g.nsub, SL_MAX_NSUB);
+  SL_REQUIRE(pb->k >= 1 && pb->k <= SL_MAX_PSF && (pb->k & 1), "PSF side %d must be odd, <= %d", pb->k,
+             SL_MAX_PSF);
+  SL_REQUIRE(std::isfinite(pb->sigma) && pb->sigma > 0.0, "sigma must be positive");
+  SL_REQUIRE(std::isfinite(pb->half_width) && pb->half_width > 0.0, "half_width must be positive");
+  SL_REQUIRE(pb->reg == SL_H_IDENTITY || pb->reg == SL_H_CURVATURE, "unknown reg %d", pb->reg);
+  SL_REQUIRE(pb->dtype == SL_F32 || pb->dtype == SL_F64, "unknown dtype %d", pb->dtype);
+  SL_REQUIRE(max_ns >= 2 && max_ns <= 128, "max_ns %d outside [2, 128]", max_ns);
+  SL_REQUIRE(M >= 1 && M <= (1 << 20), "n_members %d out of range", M);
+  SL_REQUIRE(NL >= 1 && NL <= SL_MAX_LAMBDA, "n_lambda %d outside [1, %d]", NL, SL_MAX_LAMBDA);
+  SL_REQUIRE((long)M * NL < (1L << 30), "too many (member, lambda) items");
+  return SL_OK;
+}
+
+using SolveKernel = void (*)(SolveArgs);
+
+// Kernel variants: bulk type T, banded half-width CKT (>= ck of the PSF) and
+// nodes per thread NPT (I_max <= NPT * kNT).  Returns the kernel and its CKT.
+template <typename T, int CKT>
+static SolveKernel pick_npt(int I_max) {
+  if (I_max <= 8 * kNT) return k_solve<T, CKT, 8>;
+  if (I_max <= 20 * kNT) return k_solve<T, CKT, 20>;
+  if constexpr (sizeof(T) == 4) {
+    if (I_max <= 32 * kNT) return k_solve<T, CKT, 32>;
+  }
+  return nullptr;
+}
+
+static SolveKernel pick_kernel_f(int ck, int I_max, int* ckt) {
+  if (ck <= 2) return *ckt = 2, pick_npt<float, 2>(I_max);
+  if (ck <= 4) return *ckt = 4, pick_npt<float, 4>(I_max);
+  if (ck <= 7) return *ckt = 7, pick_npt<float, 7>(I_max);
+  if (ck <= 10) return *ckt = 10, pick_npt<float, 10>(I_max);
+  if (ck <= 16) return *ckt = 16, pick_npt<float, 16>(I_max);
+  return *ckt = 2, pick_npt<float, 2>(I_max);   // wider PSFs: direct path only
+}
+
+static SolveKernel pick_kernel_d(int ck, int I_max, int* ckt) {
+  if (ck <= 2) return *ckt = 2, pick_npt<double, 2>(I_max);
+  if (ck <= 7) return *ckt = 7, pick_npt<double, 7>(I_max);
+  if (ck <= 10) return *ckt = 10, pick_npt<double, 10>(I_max);
+  return *ckt = 2, pick_npt<double, 2>(I_max);
+}
+
+template <typename T>
+static int launch_solve(SolveArgs& A, const LamList& lams, const Layout& L, hipStream_t st) {
+  const size_t sz = sizeof(T);
+  int ckt = 2;
+  SolveKernel ks = sizeof(T) == 4 ? pick_kernel_f(A.ck, L.I_max, &ckt) : pick_kernel_d(A.ck, L.I_max, &ckt);
+  SL_REQUIRE(ks != nullptr, "source grid too large for the compiled kernels (I_max = %d)", L.I_max);
+  A.ckt = ckt;
+  // dynamic LDS: source vector | reduction scratch | frame (up to the full image)
+  A.q_off = (int)align256(sz * L.I_max);
+  A.red_off = A.q_off + (int)align256(sz * L.I_max);
+  A.frame_off = A.red_off + 64 * (int)sizeof(double);
+  const size_t fixed = (size_t)A.frame_off;
+  size_t lds = fixed + sz * (size_t)(A.ny + 4 * ckt + kSegR) * (size_t)((A.nx + 4 * ckt) | 1);
+  const size_t lds_max = 160 * 1024 - 1024;
+  if (lds > lds_max) lds = lds_max;
+  SL_REQUIRE(lds > fixed + 64 * sz, "source grid too large for LDS");
+  A.lds_frame_cap = (int)((lds - fixed) / sz);
+  static std::mutex mu;
+  {
+    std::lock_guard<std::mutex> g(mu);
+    SL_HIP(hipFuncSetAttribute((const void*)ks, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    const size_t prep_lds = sizeof(double) * L.I_max;
+    SL_HIP(hipFuncSetAttribute((const void*)k_prep<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)prep_lds));
+  }
+  hipLaunchKernelGGL(k_setup<T>, dim3(1), dim3(1024), 0, st, A, lams);
+  if (int e = check_launch("k_setup")) return e;
+  hipLaunchKernelGGL(k_prep<T>, dim3(A.n_members), dim3(1024), sizeof(double) * L.I_max, st, A);
+  if (int e = check_launch("k_prep")) return e;
+  hipLaunchKernelGGL(ks, dim3(L.n_wg), dim3(kNT), lds, st, A);
+  if (int e = check_launch("k_solve")) return e;
+  const size_t corner_lds = sizeof(double) * (A.n_lambda * A.n_lambda + 12 * A.n_lambda + 16);
+  hipLaunchKernelGGL(k_corner<T>, dim3(A.n_members), dim3(256), corner_lds, st, A);
+  return check_launch("k_corner");
+}
+
+}  // namespace sl
+
+using namespace sl;
+
+extern "C" {
+
+size_t sl_solve_workspace_size(const sl_problem* pb, int max_ns, int n_members, int n_lambda) {
+  if (check_problem(pb, max_ns, n_members, n_lambda) != SL_OK) return 0;
+  return make_layout(pb, max_ns, n_members, n_lambda, device_cus()).total;
+}
+
+int sl_solve_semilinear(const sl_problem* pb, const double* lens, const int32_t* ns, int max_ns,
+                        int n_members, const double* lambdas, int n_lambda, const sl_solve_opts* opt,
+                        void* workspace, size_t workspace_bytes, sl_result* out, void* stream) {
+  if (int e = check_problem(pb, max_ns, n_members, n_lambda)) return e;
+  SL_REQUIRE(lens && ns && pb->d && pb->psf, "NULL device input");
+  SL_REQUIRE(lambdas != nullptr, "lambdas is NULL");
+  for (int k = 0; k < n_lambda; ++k) {
+    SL_REQUIRE(std::isfinite(lambdas[k]) && lambdas[k] > 0.0, "lambda[%d] must be positive", k);
+    SL_REQUIRE(k == 0 || lambdas[k] > lambdas[k - 1], "lambdas must be strictly ascending");
+  }
+  SL_REQUIRE(opt != nullptr, "opts is NULL");
+  SL_REQUIRE(std::isfinite(opt->tol) && opt->tol >= 0.0, "tol must be >= 0");
+  SL_REQUIRE(opt->maxit >= 1, "maxit must be >= 1");
+  SL_REQUIRE(out && out->s_corner && out->s_off && out->chi2 && out->reg && out->iters && out->status &&
+                 out->k_star && out->corner_status,
+             "NULL result pointer");
+  SL_REQUIRE(workspace != nullptr && ((uintptr_t)workspace & 255) == 0,
+             "workspace must be non-NULL and 256-byte aligned");
+  const Layout L = make_layout(pb, max_ns, n_members, n_lambda, device_cus());
+  SL_REQUIRE(workspace_bytes >= L.total, "workspace too small: %zu < %zu bytes", workspace_bytes, L.total);
+
+  SolveArgs A{};
+  A.nx = pb->img.nx;
+  A.ny = pb->img.ny;
+  A.nsub = pb->img.nsub;
+  A.n2 = L.n2;
+  A.K = pb->k;
+  A.ck = (pb->k - 1) / 2;
+  A.reg = pb->reg;
+  A.n_members = n_members;
+  A.n_lambda = n_lambda;
+  A.max_ns = max_ns;
+  A.maxit = opt->maxit;
+  A.pix = pb->img.pix;
+  A.R = pb->half_width;
+  A.sigma = pb->sigma;
+  A.tol = opt->tol;
+  A.lens = lens;
+  A.ns = ns;
+  A.d = pb->d;
+  A.psf = pb->psf;
+  A.s_corner = out->s_corner;
+  A.s_off = out->s_off;
+  A.chi2 = out->chi2;
+  A.regv = out->reg;
+  A.iters = out->iters;
+  A.status = out->status;
+  A.k_star = out->k_star;
+  A.corner_status = out->corner_status;
+  unsigned char* ws = (unsigned char*)workspace;
+  A.consts = (Consts*)(ws + L.consts);
+  A.lamv = (double*)(ws + L.lam);
+  A.taps_d = (double*)(ws + L.taps_d);
+  A.taps_t = ws + L.taps_f;
+  A.minfo = (MemberInfo*)(ws + L.minfo);
+  A.queues = (int*)(ws + L.queues);
+  A.qcap = L.qcap;
+  A.pix_list = (int32_t*)(ws + L.pix);
+  A.cell = (int32_t*)(ws + L.cell);
+  A.fx = ws + L.fx;
+  A.fy = ws + L.fy;
+  A.b = (double*)(ws + L.b);
+  A.s_all = ws + L.s_all;
+  A.gframe = ws + L.gframe;
+  A.gframe_elems = L.gframe_elems;
+  A.gz = ws + L.gz;
+  A.I_max = L.I_max;
+  LamList lams{};
+  for (int k = 0; k < n_lambda; ++k) lams.v[k] = lambdas[k];
+  hipStream_t st = (hipStream_t)stream;
+  if (pb->dtype == SL_F32) return launch_solve<float>(A, lams, L, st);
+  return launch_solve<double>(A, lams, L, st);
+}
+
+}  // extern "C"

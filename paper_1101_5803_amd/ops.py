@@ -1,0 +1,196 @@
+"""Python entry points with the C-ABI's names (argument marshalling only).
+
+Each function validates shapes on the host, allocates its outputs with
+torch on the input's device, and calls the matching ``sl_*`` entry point
+of libsemilin.so on torch's current stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+_DT = {torch.float32: L.SL_F32, torch.float64: L.SL_F64}
+_REG = {"identity": L.SL_H_IDENTITY, "curvature": L.SL_H_CURVATURE}
+
+
+@dataclasses.dataclass(frozen=True)
+class Grid:
+    nx: int
+    ny: int
+    pix: float
+    nsub: int
+
+    def c(self):
+        return L.ImageGrid(self.nx, self.ny, self.pix, self.nsub)
+
+    @property
+    def J(self):
+        return self.nx * self.ny
+
+
+def _dev_check(*ts):
+    for t in ts:
+        if not (isinstance(t, torch.Tensor) and t.is_cuda):
+            raise L.SemilinError("inputs must be CUDA (HIP) tensors")
+
+
+def lens_trace(lens: torch.Tensor, grid: Grid, ns, half_width: float) -> torch.Tensor:
+    """(u, v) grid coordinates of every subpixel, NaN outside; (M, J*n^2, 2) FP64."""
+    _dev_check(lens)
+    lens = lens.to(torch.float64).contiguous()
+    M = lens.shape[0]
+    ns = list(ns)
+    uv = torch.empty((M, grid.J * grid.nsub ** 2, 2), dtype=torch.float64, device=lens.device)
+    g = grid.c()
+    L.check(L.lib().sl_lens_trace(L.ptr(lens), M, ctypes.byref(g), L.i32_array(ns), half_width,
+                                  L.ptr(uv), L.stream_handle()), "sl_lens_trace")
+    return uv
+
+
+def apply_L(uv: torch.Tensor, grid: Grid, ns, s: torch.Tensor) -> torch.Tensor:
+    """Unblurred lensed images (M, J) of packed sources s."""
+    _dev_check(uv, s)
+    ns = list(ns)
+    out = torch.empty((len(ns), grid.J), dtype=s.dtype, device=s.device)
+    g = grid.c()
+    L.check(L.lib().sl_apply_L(_DT[s.dtype], L.ptr(uv), len(ns), ctypes.byref(g), L.i32_array(ns),
+                               L.ptr(s.contiguous()), L.ptr(out), L.stream_handle()), "sl_apply_L")
+    return out
+
+
+def apply_LT(uv: torch.Tensor, grid: Grid, ns, img: torch.Tensor) -> torch.Tensor:
+    """Packed L^T of images (M, J)."""
+    _dev_check(uv, img)
+    ns = list(ns)
+    out = torch.empty(int(sum(n * n for n in ns)), dtype=img.dtype, device=img.device)
+    g = grid.c()
+    L.check(L.lib().sl_apply_LT(_DT[img.dtype], L.ptr(uv), len(ns), ctypes.byref(g), L.i32_array(ns),
+                                L.ptr(img.contiguous()), L.ptr(out), L.stream_handle()), "sl_apply_LT")
+    return out
+
+
+def _blur(name, psf, x):
+    _dev_check(psf, x)
+    psf = psf.to(torch.float64).contiguous()
+    x = x.contiguous()
+    ny, nx = x.shape[-2:]
+    n = x.numel() // (nx * ny)
+    out = torch.empty_like(x)
+    L.check(getattr(L.lib(), name)(_DT[x.dtype], nx, ny, n, L.ptr(psf), psf.shape[0], L.ptr(x), L.ptr(out),
+                                   L.stream_handle()), name)
+    return out
+
+
+def apply_B(psf: torch.Tensor, x: torch.Tensor) -> torch.Tensor:
+    """PSF convolution (zero padding, same size) of images (..., ny, nx)."""
+    return _blur("sl_apply_B", psf, x)
+
+
+def apply_BT(psf: torch.Tensor, x: torch.Tensor) -> torch.Tensor:
+    """Correlation with the PSF: the transpose of apply_B."""
+    return _blur("sl_apply_BT", psf, x)
+
+
+def apply_HtH(reg: str, ns, s: torch.Tensor) -> torch.Tensor:
+    _dev_check(s)
+    ns = list(ns)
+    out = torch.empty_like(s)
+    L.check(L.lib().sl_apply_HtH(_DT[s.dtype], _REG[reg], len(ns), L.i32_array(ns), L.ptr(s.contiguous()),
+                                 L.ptr(out), L.stream_handle()), "sl_apply_HtH")
+    return out
+
+
+def lcurve_corner(reg, chi2):
+    """Host L-curve corner: returns (k_star, kappa ndarray)."""
+    reg = np.ascontiguousarray(reg, dtype=np.float64)
+    chi2 = np.ascontiguousarray(chi2, dtype=np.float64)
+    n = reg.size
+    k = ctypes.c_int32(0)
+    kap = np.zeros(n)
+    dp = ctypes.POINTER(ctypes.c_double)
+    L.check(L.lib().sl_lcurve_corner(reg.ctypes.data_as(dp), chi2.ctypes.data_as(dp), n, ctypes.byref(k),
+                                     kap.ctypes.data_as(dp)), "sl_lcurve_corner")
+    return int(k.value), kap
+
+
+class Solver:
+    """Batched semilinear solve against one data image (sl_solve_semilinear).
+
+    Holds the problem description and a workspace tensor sized for
+    (max_ns, n_members, n_lambda); the workspace is allocated by torch once
+    and grown on demand.
+    """
+
+    def __init__(self, d: torch.Tensor, sigma: float, psf: torch.Tensor, grid: Grid, half_width: float,
+                 reg: str = "curvature", dtype: torch.dtype = torch.float32):
+        _dev_check(d, psf)
+        self.d = d.to(torch.float64).contiguous().reshape(-1)
+        self.psf = psf.to(torch.float64).contiguous()
+        if self.d.numel() != grid.J:
+            raise L.SemilinError("data image does not match the grid")
+        self.grid = grid
+        self.sigma = float(sigma)
+        self.half_width = float(half_width)
+        self.reg = reg
+        self.dtype = dtype
+        self.device = d.device
+        self._ws = None
+        self._pb = L.Problem(grid.c(), ctypes.c_void_p(self.d.data_ptr()), self.sigma,
+                             ctypes.c_void_p(self.psf.data_ptr()), self.psf.shape[0], self.half_width,
+                             _REG[reg], _DT[dtype])
+
+    def workspace_bytes(self, max_ns: int, n_members: int, n_lambda: int) -> int:
+        n = L.lib().sl_solve_workspace_size(ctypes.byref(self._pb), max_ns, n_members, n_lambda)
+        if n == 0:
+            raise L.SemilinError(L.lib().sl_last_error().decode())
+        return int(n)
+
+    def workspace(self, max_ns, n_members, n_lambda):
+        need = self.workspace_bytes(max_ns, n_members, n_lambda)
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+        return self._ws
+
+    def alloc_result(self, ns_total: int, n_members: int, n_lambda: int):
+        dev = self.device
+        return dict(
+            s_corner=torch.empty(max(ns_total, 1), dtype=torch.float64, device=dev),
+            s_off=torch.empty(n_members + 1, dtype=torch.int64, device=dev),
+            chi2=torch.empty((n_members, n_lambda), dtype=torch.float64, device=dev),
+            reg=torch.empty((n_members, n_lambda), dtype=torch.float64, device=dev),
+            iters=torch.empty((n_members, n_lambda), dtype=torch.int32, device=dev),
+            status=torch.empty((n_members, n_lambda), dtype=torch.int32, device=dev),
+            k_star=torch.empty(n_members, dtype=torch.int32, device=dev),
+            corner_status=torch.empty(n_members, dtype=torch.int32, device=dev),
+        )
+
+    def solve_semilinear(self, lens: torch.Tensor, ns: torch.Tensor, lambdas, tol=1e-7, maxit=4000,
+                         max_ns: int | None = None, out=None):
+        """Run the batched solve; returns the result dict of device tensors.
+
+        lens (M, 7) FP64 and ns (M,) int32 on the device; lambdas a host
+        sequence.  ``max_ns`` bounds ns (defaults to ns.max(), which syncs).
+        """
+        _dev_check(lens, ns)
+        lens = lens.to(torch.float64).contiguous()
+        ns = ns.to(torch.int32).contiguous()
+        M = lens.shape[0]
+        lam = [float(x) for x in lambdas]
+        if max_ns is None:
+            max_ns = int(ns.max().item())
+        ws = self.workspace(max_ns, M, len(lam))
+        if out is None:
+            out = self.alloc_result(M * max_ns * max_ns, M, len(lam))
+        res = L.Result(*[ctypes.c_void_p(out[k].data_ptr()) for k in
+                         ("s_corner", "s_off", "chi2", "reg", "iters", "status", "k_star", "corner_status")])
+        opts = L.SolveOpts(float(tol), int(maxit))
+        L.check(L.lib().sl_solve_semilinear(ctypes.byref(self._pb), L.ptr(lens), L.ptr(ns), int(max_ns), M,
+                                            L.f64_array(lam), len(lam), ctypes.byref(opts), L.ptr(ws),
+                                            ws.numel(), ctypes.byref(res), L.stream_handle()),
+                "sl_solve_semilinear")
+        return out
