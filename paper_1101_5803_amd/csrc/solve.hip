@@ -274,6 +274,10 @@ __global__ void __launch_bounds__(1024) k_setup(SolveArgs a, LamList lams) {
 
 // ------------------------------------------------------------------ k_prep
 template <typename T>
+__device__ void prep_member(const SolveArgs& a, int m, MemberInfo mi, const double* gl, int* bbox, int* scan,
+                            double* bacc);
+
+template <typename T>
 __global__ void __launch_bounds__(1024) k_prep(SolveArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   double* bacc = reinterpret_cast<double*>(smem);
@@ -294,7 +298,9 @@ __global__ void __launch_bounds__(1024) k_prep(SolveArgs a) {
   double gl[7];
 #pragma unroll
   for (int i = 0; i < 7; ++i) gl[i] = g[i];
-  const bool valid = mi.ns >= 2 && lens_valid(gl);
+  // the same for every thread; readfirstlane makes that visible to the compiler,
+  // so the branch around the barriers below is a scalar (block-uniform) branch
+  const int valid = __builtin_amdgcn_readfirstlane((int)(mi.ns >= 2 && lens_valid(gl)));
   if (!valid) {
     if (tid == 0) {
       mi.M = 0;
@@ -303,8 +309,17 @@ __global__ void __launch_bounds__(1024) k_prep(SolveArgs a) {
       mi.r1 = mi.c1 = -1;
       a.minfo[m] = mi;
     }
-    return;
+  } else {
+    prep_member<T>(a, m, mi, gl, bbox, scan, bacc);
   }
+}
+
+// Trace, compaction and right-hand side of one valid member (all threads).
+template <typename T>
+__device__ void prep_member(const SolveArgs& a, int m, MemberInfo mi, const double* gl, int* bbox, int* scan,
+                            double* bacc) {
+  const int tid = threadIdx.x;
+  const int nx = a.nx, ny = a.ny, J = nx * ny, nsub = a.nsub, n2 = a.n2;
   const Lens L = make_lens(gl);
   const int ns = mi.ns;
   const double h = 2.0 * a.R / (ns - 1);
@@ -540,23 +555,27 @@ __device__ __forceinline__ double block_sum1(double v, double* scratch, int buf)
   return t;
 }
 
-template <typename T, int CKT, int NPT, bool LDSF>
-__device__ void run_item(const SolveArgs& a, int m, int kl, unsigned char* smem) {
-  const int tid = threadIdx.x;
-  const MemberInfo mi = a.minfo[m];
+// Invalid or empty member: s = 0, chi^2 = sum d^2 / sigma^2 (no barriers).
+template <typename T>
+__device__ void trivial_item(const SolveArgs& a, const MemberInfo& mi, int m, int kl) {
   const long out_idx = (long)m * a.n_lambda + kl;
-  T* s_dst = reinterpret_cast<T*>(a.s_all) + ((long)m * a.n_lambda + kl) * a.I_max;
-  if (mi.status != SL_ST_OK) {
-    // invalid or empty member: s = 0, chi^2 = sum d^2 / sigma^2
-    for (int i = tid; i < mi.I; i += kNT) s_dst[i] = (T)0;
-    if (tid == 0) {
-      a.chi2[out_idx] = mi.status == SL_ST_INVALID ? NAN : a.consts->sum_d2 / (a.sigma * a.sigma);
-      a.regv[out_idx] = mi.status == SL_ST_INVALID ? NAN : 0.0;
-      a.iters[out_idx] = 0;
-      a.status[out_idx] = mi.status;
-    }
-    return;
+  T* s_dst = reinterpret_cast<T*>(a.s_all) + out_idx * a.I_max;
+  for (int i = threadIdx.x; i < mi.I; i += kNT) s_dst[i] = (T)0;
+  if (threadIdx.x == 0) {
+    a.chi2[out_idx] = mi.status == SL_ST_INVALID ? NAN : a.consts->sum_d2 / (a.sigma * a.sigma);
+    a.regv[out_idx] = mi.status == SL_ST_INVALID ? NAN : 0.0;
+    a.iters[out_idx] = 0;
+    a.status[out_idx] = mi.status;
   }
+}
+
+// One CG solve of a valid member.  Every branch that encloses a barrier
+// depends only on block-uniform values made scalar with readfirstlane.
+template <typename T, int CKT, int NPT, bool LDSF>
+__device__ void run_item(const SolveArgs& a, const MemberInfo& mi, int m, int kl, unsigned char* smem) {
+  const int tid = threadIdx.x;
+  const long out_idx = (long)m * a.n_lambda + kl;
+  T* s_dst = reinterpret_cast<T*>(a.s_all) + out_idx * a.I_max;
   const int ns = mi.ns, I = mi.I, M = mi.M, r0 = mi.r0, c0 = mi.c0;
   const int h = mi.r1 - mi.r0 + 1, w = mi.c1 - mi.c0 + 1;
   constexpr int HALO = 2 * CKT;
@@ -616,14 +635,14 @@ __device__ void run_item(const SolveArgs& a, int m, int kl, unsigned char* smem)
   const double stop2 = a.tol * a.tol * rr;
   int st = SL_ST_MAXIT, it = 0;
   for (it = 0; it < a.maxit; ++it) {
-    if (rr <= stop2) {
+    if (__builtin_amdgcn_readfirstlane((int)(rr <= stop2))) {
       st = SL_ST_OK;
       break;
     }
     // y = L p into the frame (P holds p, Q and the frame are zero)
     apply_L_frame(a, P, F0, pitch, M, r0, c0, ns, pix, cellp, fxp, fyp);
     __syncthreads();
-    if (sep) {
+    if (sep) {   // sep comes from a scalar load: uniform
       // w = B^T B y: banded pass along rows then along columns, in place
       banded_pass<T, CKT, true>(F0, pitch, h, w, c0, nx, ck, taps + ti.ax, taps + ti.elx, taps + ti.erx);
       __syncthreads();
@@ -698,7 +717,7 @@ __device__ void run_item(const SolveArgs& a, int m, int kl, unsigned char* smem)
     }
     for (int e = tid; e < h * pitch; e += kNT) Frows[e] = (T)0;
     pq = block_sum1(pq, red, 0);
-    if (!(pq > 0.0)) {
+    if (__builtin_amdgcn_readfirstlane((int)!(pq > 0.0))) {
       st = SL_ST_BREAKDOWN;
       break;
     }
@@ -768,32 +787,42 @@ __device__ void run_item(const SolveArgs& a, int m, int kl, unsigned char* smem)
   __syncthreads();
 }
 
+// Next (member, lambda) item for this block, -1 when every queue is empty;
+// thread 0 pops, the value is broadcast through LDS and made scalar.
+__device__ __forceinline__ int fetch_item(const SolveArgs& a, int xcd, int* sh_item) {
+  if (threadIdx.x == 0) {
+    int item = -1;
+    for (int x = 0; x < 8 && item < 0; ++x) {
+      const int q = (xcd + x) & 7;
+      const int idx = atomicAdd(&a.consts->qhead[q], 1);
+      if (idx < a.consts->qcount[q]) item = a.queues[q * a.qcap + idx];
+    }
+    *sh_item = item;
+  }
+  __syncthreads();
+  const int item = __builtin_amdgcn_readfirstlane(*sh_item);
+  __syncthreads();
+  return item;
+}
+
 template <typename T, int CKT, int NPT>
 __global__ void __launch_bounds__(kNT) k_solve(SolveArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int sh_item;
   const int xcd = blockIdx.x & 7;
-  for (;;) {
-    if (threadIdx.x == 0) {
-      int item = -1;
-      for (int x = 0; x < 8 && item < 0; ++x) {
-        const int q = (xcd + x) & 7;
-        const int idx = atomicAdd(&a.consts->qhead[q], 1);
-        if (idx < a.consts->qcount[q]) item = a.queues[q * a.qcap + idx];
-      }
-      sh_item = item;
-    }
-    __syncthreads();
-    const int item = sh_item;
-    __syncthreads();
-    if (item < 0) break;
-    const int m = item / a.n_lambda, kl = item % a.n_lambda;
-    const MemberInfo mi = a.minfo[m];
+  for (int item = fetch_item(a, xcd, &sh_item); item >= 0; item = fetch_item(a, xcd, &sh_item)) {
+    const int m = item / a.n_lambda, kl = item % a.n_lambda;   // scalar
+    const MemberInfo mi = a.minfo[m];                          // uniform address: scalar loads
+    const int status = __builtin_amdgcn_readfirstlane(mi.status);
     const int h = mi.r1 - mi.r0 + 1, w = mi.c1 - mi.c0 + 1;
-    if (mi.status == SL_ST_OK && (h + 4 * CKT + kSegR) * ((w + 4 * CKT) | 1) > a.lds_frame_cap)
-      run_item<T, CKT, NPT, false>(a, m, kl, smem);
+    const int fits = __builtin_amdgcn_readfirstlane(
+        (int)((h + 4 * CKT + kSegR) * ((w + 4 * CKT) | 1) <= a.lds_frame_cap));
+    if (status != SL_ST_OK)
+      trivial_item<T>(a, mi, m, kl);
+    else if (fits)
+      run_item<T, CKT, NPT, true>(a, mi, m, kl, smem);
     else
-      run_item<T, CKT, NPT, true>(a, m, kl, smem);
+      run_item<T, CKT, NPT, false>(a, mi, m, kl, smem);
   }
 }
 
