@@ -1,0 +1,174 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the batched semilinear lens solve on one MI355X.
+
+Workload (one "step"): the c3 population -- 256 SIE + external-shear lens
+parameter sets drawn from the prior box, per-member source grids of 32..96
+nodes per side, scored against the 128x128 c2 mock image with a 15x15 PSF,
+curvature regularisation and a 16-lambda L-curve (1e-4..1e2), FP32 bulk
+arithmetic with FP64 inner products, chi^2 and L-curve, CG to 1e-7.  One
+step is the whole hot path: trace + compaction + right-hand sides, 4096 CG
+solves, chi^2/||Hs||^2 and the L-curve corner of every member.
+
+Prints one JSON line (rank 0, N = 1).  value = lens-model evaluations per
+second over the timed steps.  Also reported: the unbatched ("plain") rate of
+the same library called one member at a time, the persistent kernel's
+roofline position measured with HIP events, and the FP64 C oracle timed on
+the host cores on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "lens-model evals/s (128² image, 16-λ L-curve) vs plain; χ² rel err vs FP64"
+PEAK_FP32_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--members", type=int, default=256)
+    ap.add_argument("--plain-members", type=int, default=16)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-members", type=int, default=0, help="oracle sample size (default: cores used)")
+    return ap.parse_args()
+
+
+def algorithmic_work(info, iters, nsub, ck):
+    """Flops and table bytes of the persistent kernel for one launch.
+
+    Per CG iteration of a member with mapped-pixel bounding box h x w, M mapped
+    pixels (M n^2 table entries) and I nodes:
+      flops = 2 passes * (4ck+1) FMAs * h*w * 2      (B^T B, banded, in LDS)
+            + 2 * 12 * M n^2                          (L and L^T bilinear)
+            + 23 * I                                  (H^T H stencil and CG updates)
+      bytes = 2 * M (4 + 12 n^2)                      (trace table read by L and L^T)
+    """
+    n2 = nsub * nsub
+    flops = 0.0
+    nbytes = 0.0
+    for m in range(info.shape[0]):
+        ns, I, M, r0, r1, c0, c1, st = info[m]
+        if st != 0:
+            continue
+        h, w = r1 - r0 + 1, c1 - c0 + 1
+        it = float(iters[m].sum())
+        flops += it * (2 * (4 * ck + 1) * h * w * 2 + 2 * 12 * M * n2 + 23 * I)
+        nbytes += it * (2 * M * (4 + 12 * n2))
+    return flops, nbytes
+
+
+def cpu_baseline(w, z, pop, grids, n_members):
+    from oracle import coracle
+    cores = n_members
+    t0 = time.perf_counter()
+    coracle.evaluate(pop[:n_members], grids[:n_members], w.half_width, w.nx, w.ny, w.pix, w.nsub_model, z["d"],
+                     float(z["sigma"]), z["psf"], w.reg, w.lambdas, tol=1e-7, threads=cores)
+    dt = time.perf_counter() - t0
+    return {"value": n_members / dt, "unit": "evals/s", "cores": cores, "kind": "oracle",
+            "sample": f"first {n_members} of the 256 c3 members, full 16-lambda sweep each, plain-C FP64 "
+                      f"matrix-free CG to 1e-7, one member per OpenMP thread ({dt:.1f} s wall)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the batched solve shards "
+              "members across GPUs by design but runs on one GPU here)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_1101_5803_amd as sl
+    import synthgen
+
+    w = synthgen.C3
+    z = np.load(os.path.join(ROOT, "tests", "data", "c2.npz"))
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    M = args.members
+    pop = synthgen.population(w.seed, 256)[:M]
+    grids = synthgen.member_grids(w.seed, 256)[:M]
+    max_ns = 96
+    grid = sl.Grid(w.nx, w.ny, w.pix, w.nsub_model)
+    solver = sl.Solver(torch.tensor(z["d"], device=dev), float(z["sigma"]), torch.tensor(z["psf"], device=dev),
+                       grid, w.half_width, reg=w.reg, dtype=torch.float32)
+    lens_d = torch.tensor(pop, device=dev)
+    ns_d = torch.tensor(grids, device=dev)
+    out = solver.alloc_result(M * max_ns * max_ns, M, len(w.lambdas))
+
+    def step():
+        solver.solve_semilinear(lens_d, ns_d, w.lambdas, tol=w.tol, maxit=4000, max_ns=max_ns, out=out)
+
+    print(f"[bench] warmup {args.warmup} step(s) of {M} members", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    sl.profile_enable(True)
+    print(f"[bench] timing {args.steps} step(s)", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kern_ms, launches = sl.profile_solve_ms()
+    sl.profile_enable(False)
+    value = M * args.steps / dt
+    ms_per_step = 1e3 * dt / args.steps
+    iters = out["iters"].cpu().numpy()
+    status = out["status"].cpu().numpy()
+    info = solver.member_info(max_ns, M, len(w.lambdas))
+    flops, tbytes = algorithmic_work(info, iters, w.nsub_model, (w.k_psf - 1) // 2)
+    kern_s = kern_ms / max(launches, 1) / 1e3
+    tflops = flops / kern_s / 1e12
+    gbs = tbytes / kern_s / 1e9
+    roof = {"bound": "alu", "achieved": round(tflops, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(tflops / PEAK_FP32_TFLOPS, 4), "traffic": None,
+            "kernel": "k_solve (persistent CG)", "kernel_ms": round(kern_s * 1e3, 3),
+            "table_GBps": round(gbs, 1), "table_frac_of_hbm": round(gbs / PEAK_HBM_GBS, 4)}
+    # plain: the same library, one member per call
+    print(f"[bench] plain: {args.plain_members} members one at a time", file=sys.stderr, flush=True)
+    plain = sl.Solver(torch.tensor(z["d"], device=dev), float(z["sigma"]), torch.tensor(z["psf"], device=dev),
+                      grid, w.half_width, reg=w.reg, dtype=torch.float32)
+    pout = plain.alloc_result(max_ns * max_ns, 1, len(w.lambdas))
+    plain.solve_semilinear(lens_d[:1], ns_d[:1], w.lambdas, tol=w.tol, maxit=4000, max_ns=max_ns, out=pout)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for m in range(args.plain_members):
+        plain.solve_semilinear(lens_d[m:m + 1], ns_d[m:m + 1], w.lambdas, tol=w.tol, maxit=4000, max_ns=max_ns,
+                               out=pout)
+    torch.cuda.synchronize()
+    plain_value = args.plain_members / (time.perf_counter() - t0)
+    rec = {
+        "metric": METRIC, "value": round(value, 2), "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "fp32 (fp64 reductions)", "data": "synthetic",
+        "config": {"workload": "c3: 256 SIE+shear lens sets, 128x128 image at 0.05\", 2x2 subpixels, source "
+                               "grids 32..96 nodes per side over +-1\", 15x15 Gaussian PSF (FWHM 3 px), curvature "
+                               "H, 16 lambdas 1e-4..1e2, CG tol 1e-7",
+                   "members": M, "n_lambda": len(w.lambdas), "cg_iterations": int(iters.sum()),
+                   "status_counts": {int(k): int(v) for k, v in zip(*np.unique(status, return_counts=True))}},
+        "plain_value": round(plain_value, 3), "vs_plain": round(value / plain_value, 2),
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        ncpu = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+        n = args.cpu_members or max(1, min(16, ncpu))
+        print(f"[bench] cpu baseline: oracle on {n} members", file=sys.stderr, flush=True)
+        rec["cpu_baseline"] = cpu_baseline(w, z, pop, grids, n)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -179,6 +179,24 @@ int sl_solve_semilinear(const sl_problem* pb, const double* lens, const int32_t*
                         sl_result* out, void* stream);
 
 /*
+ * Per-member table of the last sl_solve_semilinear that used `workspace`
+ * (synchronous: waits for the device).  info_host: host int32[n_members][8]
+ * = {ns, I, M (pixels that map onto the grid), r0, r1, c0, c1 (their
+ * bounding box), status}.  Sizes must match that call.
+ */
+int sl_solve_member_info(const sl_problem* pb, int max_ns, int n_members, int n_lambda,
+                         const void* workspace, int32_t* info_host);
+
+/*
+ * Kernel timing for measurement: while enabled, every sl_solve_semilinear
+ * records HIP events around its persistent CG kernel on the call's stream.
+ * sl_profile_enable(1) clears the record; sl_profile_solve_ms() waits for the
+ * recorded events and returns the summed milliseconds and launch count.
+ */
+int sl_profile_enable(int on);
+int sl_profile_solve_ms(double* ms_total, int32_t* launches);
+
+/*
  * L-curve corner (Sec. 2.6, Eq. 20) on the host, synchronous: points
  * (log10 reg_k, log10 chi2_k) are parameterised by chord length, points whose
  * step is <= 1e-12 of the total are dropped, not-a-knot cubic splines are

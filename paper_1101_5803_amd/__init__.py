@@ -4,7 +4,8 @@ The compute lives in libsemilin.so (hand-written gfx950 HIP behind a C ABI,
 declared in include/semilin.h); this package is its thin Python binding.
 """
 from . import _lib  # noqa: F401
-from .ops import (Grid, Solver, apply_B, apply_BT, apply_HtH, apply_L, apply_LT,  # noqa: F401
+from .ops import (Grid, Solver, apply_B, apply_BT, apply_HtH, apply_L, apply_LT, profile_enable,  # noqa: F401
+                  profile_solve_ms,
                   lcurve_corner, lens_trace)
 
 __all__ = ["Grid", "Solver", "apply_B", "apply_BT", "apply_HtH", "apply_L", "apply_LT", "lcurve_corner",

@@ -73,6 +73,9 @@ def lib():
         L.sl_solve_semilinear.argtypes = [ctypes.POINTER(Problem), vp, vp, ip, ip,
                                           ctypes.POINTER(ctypes.c_double), ip, ctypes.POINTER(SolveOpts),
                                           vp, ctypes.c_size_t, ctypes.POINTER(Result), vp]
+        L.sl_solve_member_info.argtypes = [ctypes.POINTER(Problem), ip, ip, ip, vp, vp]
+        L.sl_profile_enable.argtypes = [ip]
+        L.sl_profile_solve_ms.argtypes = [ctypes.POINTER(ctypes.c_double), i32p]
         L.sl_lcurve_corner.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                        ip, i32p, ctypes.POINTER(ctypes.c_double)]
         L.sl_mlp_workspace_size.argtypes = [ip]
@@ -81,7 +84,7 @@ def lib():
         L.sl_mlp_train_step.argtypes = [vp, vp, vp, vp, vp, ip, ctypes.c_float, ip, vp, vp, vp, vp]
         for name in ("sl_lens_trace", "sl_apply_L", "sl_apply_LT", "sl_apply_B", "sl_apply_BT",
                      "sl_apply_HtH", "sl_solve_semilinear", "sl_lcurve_corner", "sl_mlp_forward",
-                     "sl_mlp_train_step"):
+                     "sl_mlp_train_step", "sl_solve_member_info", "sl_profile_enable", "sl_profile_solve_ms"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib

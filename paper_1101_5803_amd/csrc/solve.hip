@@ -959,6 +959,14 @@ static SolveKernel pick_kernel_d(int ck, int I_max, int* ckt) {
   return *ckt = 2, pick_npt<double, 2>(I_max);
 }
 
+// ------------------------------------------------------------------ profiling
+struct ProfileState {
+  std::mutex mu;
+  bool on = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+};
+static ProfileState g_prof;
+
 template <typename T>
 static int launch_solve(SolveArgs& A, const LamList& lams, const Layout& L, hipStream_t st) {
   const size_t sz = sizeof(T);
@@ -988,8 +996,22 @@ static int launch_solve(SolveArgs& A, const LamList& lams, const Layout& L, hipS
   if (int e = check_launch("k_setup")) return e;
   hipLaunchKernelGGL(k_prep<T>, dim3(A.n_members), dim3(1024), sizeof(double) * L.I_max, st, A);
   if (int e = check_launch("k_prep")) return e;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  {
+    std::lock_guard<std::mutex> g(g_prof.mu);
+    if (g_prof.on) {
+      SL_HIP(hipEventCreate(&e0));
+      SL_HIP(hipEventCreate(&e1));
+      SL_HIP(hipEventRecord(e0, st));
+    }
+  }
   hipLaunchKernelGGL(ks, dim3(L.n_wg), dim3(kNT), lds, st, A);
   if (int e = check_launch("k_solve")) return e;
+  if (e1) {
+    SL_HIP(hipEventRecord(e1, st));
+    std::lock_guard<std::mutex> g(g_prof.mu);
+    g_prof.ev.emplace_back(e0, e1);
+  }
   const size_t corner_lds = sizeof(double) * (A.n_lambda * A.n_lambda + 12 * A.n_lambda + 16);
   hipLaunchKernelGGL(k_corner<T>, dim3(A.n_members), dim3(256), corner_lds, st, A);
   return check_launch("k_corner");
@@ -1078,6 +1100,55 @@ int sl_solve_semilinear(const sl_problem* pb, const double* lens, const int32_t*
   hipStream_t st = (hipStream_t)stream;
   if (pb->dtype == SL_F32) return launch_solve<float>(A, lams, L, st);
   return launch_solve<double>(A, lams, L, st);
+}
+
+int sl_solve_member_info(const sl_problem* pb, int max_ns, int n_members, int n_lambda, const void* workspace,
+                         int32_t* info_host) {
+  if (int e = check_problem(pb, max_ns, n_members, n_lambda)) return e;
+  SL_REQUIRE(workspace && info_host, "NULL pointer");
+  const Layout L = make_layout(pb, max_ns, n_members, n_lambda, device_cus());
+  std::vector<MemberInfo> mi(n_members);
+  SL_HIP(hipDeviceSynchronize());
+  SL_HIP(hipMemcpy(mi.data(), (const unsigned char*)workspace + L.minfo, sizeof(MemberInfo) * n_members,
+                   hipMemcpyDeviceToHost));
+  for (int m = 0; m < n_members; ++m) {
+    int32_t* o = info_host + 8 * m;
+    o[0] = mi[m].ns;
+    o[1] = mi[m].I;
+    o[2] = mi[m].M;
+    o[3] = mi[m].r0;
+    o[4] = mi[m].r1;
+    o[5] = mi[m].c0;
+    o[6] = mi[m].c1;
+    o[7] = mi[m].status;
+  }
+  return SL_OK;
+}
+
+int sl_profile_enable(int on) {
+  std::lock_guard<std::mutex> g(g_prof.mu);
+  for (auto& p : g_prof.ev) {
+    (void)hipEventDestroy(p.first);
+    (void)hipEventDestroy(p.second);
+  }
+  g_prof.ev.clear();
+  g_prof.on = on != 0;
+  return SL_OK;
+}
+
+int sl_profile_solve_ms(double* ms_total, int32_t* launches) {
+  SL_REQUIRE(ms_total && launches, "NULL pointer");
+  std::lock_guard<std::mutex> g(g_prof.mu);
+  double tot = 0.0;
+  for (auto& p : g_prof.ev) {
+    SL_HIP(hipEventSynchronize(p.second));
+    float ms = 0.f;
+    SL_HIP(hipEventElapsedTime(&ms, p.first, p.second));
+    tot += ms;
+  }
+  *ms_total = tot;
+  *launches = (int32_t)g_prof.ev.size();
+  return SL_OK;
 }
 
 }  // extern "C"

@@ -105,6 +105,19 @@ def apply_HtH(reg: str, ns, s: torch.Tensor) -> torch.Tensor:
     return out
 
 
+def profile_enable(on: bool = True) -> None:
+    """Record HIP events around every persistent solve kernel (clears the record)."""
+    L.check(L.lib().sl_profile_enable(1 if on else 0), "sl_profile_enable")
+
+
+def profile_solve_ms():
+    """(summed milliseconds, launches) of the recorded solve kernels; synchronises."""
+    ms = ctypes.c_double(0.0)
+    n = ctypes.c_int32(0)
+    L.check(L.lib().sl_profile_solve_ms(ctypes.byref(ms), ctypes.byref(n)), "sl_profile_solve_ms")
+    return float(ms.value), int(n.value)
+
+
 def lcurve_corner(reg, chi2):
     """Host L-curve corner: returns (k_star, kappa ndarray)."""
     reg = np.ascontiguousarray(reg, dtype=np.float64)
@@ -168,6 +181,13 @@ class Solver:
             k_star=torch.empty(n_members, dtype=torch.int32, device=dev),
             corner_status=torch.empty(n_members, dtype=torch.int32, device=dev),
         )
+
+    def member_info(self, max_ns: int, n_members: int, n_lambda: int) -> np.ndarray:
+        """(n_members, 8) int32 table {ns, I, M, r0, r1, c0, c1, status} of the last solve."""
+        info = np.zeros((n_members, 8), dtype=np.int32)
+        L.check(L.lib().sl_solve_member_info(ctypes.byref(self._pb), max_ns, n_members, n_lambda, L.ptr(self._ws),
+                                             info.ctypes.data_as(ctypes.c_void_p)), "sl_solve_member_info")
+        return info
 
     def solve_semilinear(self, lens: torch.Tensor, ns: torch.Tensor, lambdas, tol=1e-7, maxit=4000,
                          max_ns: int | None = None, out=None):
