@@ -35,7 +35,7 @@
 
 namespace sl {
 
-constexpr int kNT = 512;      // threads per solve block
+constexpr int kNT = 1024;     // threads per solve block
 constexpr int kWaves = kNT / kWave;
 constexpr int kSegR = 4;       // outputs per lane in a banded pass
 constexpr int kMaxCK = 31;
@@ -57,7 +57,7 @@ struct alignas(16) Consts {
 };
 
 struct Layout {
-  size_t consts, lam, taps_d, taps_f, minfo, queues, pix, cell, fx, fy, b, s_all, gframe, gz, total;
+  size_t consts, lam, taps_d, taps_f, minfo, queues, pix, cell, fx, fy, b, s_all, gframe, gz, rbuf, total;
   int qcap, n_wg, I_max, J, n2, gframe_elems;
 };
 
@@ -115,6 +115,7 @@ struct SolveArgs {
   void* s_all;
   void* gframe;
   void* gz;
+  void* rbuf;       // per-block CG residual
   int I_max;
 };
 
@@ -344,7 +345,7 @@ __device__ void prep_member(const SolveArgs& a, int m, MemberInfo mi, const doub
     int tot;
     const int pos = base + block_excl_count(mapped, scan, &tot);
     if (mapped) {
-      pix[pos] = j;
+      pix[pos] = (r << 16) | c;   // packed row/column of the mapped pixel
       // second pass over the subpixels writes the compacted table directly
       for (int k = 0; k < n2; ++k) {
         double x, y, bx, by, fx = 0.0, fy = 0.0;
@@ -374,7 +375,7 @@ __device__ void prep_member(const SolveArgs& a, int m, MemberInfo mi, const doub
   const int K = a.K, ck = a.ck;
   const double inv_n2 = 1.0 / n2;
   for (int t = tid; t < Mm; t += blockDim.x) {
-    const int j = pix[t], r = j / nx, c = j % nx;
+    const int r = pix[t] >> 16, c = pix[t] & 0xFFFF;
     double v = 0.0;
     for (int aa = 0; aa < K; ++aa) {
       const int rr = r + aa - ck;
@@ -431,14 +432,16 @@ __device__ __forceinline__ void banded_pass(T* __restrict__ F0, int pitch, int n
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int S = (len + kSegR - 1) / kSegR;
   const int LPW = 64 / S;
-  const int sub_line = lane / S, seg = lane % S;
+  // consecutive lanes walk consecutive lines (odd pitch / unit stride: no LDS
+  // bank conflicts); the segments of one line stay in one wave step
+  const int sub_line = lane % LPW, seg = lane / LPW;
   const int p0 = seg * kSegR;
   const int step = ROW ? 1 : pitch;          // distance between positions
   const int lstride = ROW ? pitch : 1;       // distance between lines
   const bool edges = img_off < ck || img_off + len > img_len - ck;
   for (int l0 = wv * LPW; l0 < nlines; l0 += kWaves * LPW) {   // same trip count for the whole wave
     const int line = l0 + sub_line;
-    const bool active = sub_line < LPW && line < nlines;
+    const bool active = seg < S && line < nlines;
     const T* src = F0 + (active ? line * lstride + (p0 - NH) * step : 0);
     T win[W];
 #pragma unroll
@@ -520,27 +523,6 @@ __device__ __forceinline__ double reg_node(const T* P, int ns, int r, int c, int
   return dx * dx + dy * dy;
 }
 
-// Write L x (x in LDS P) into the frame F at the mapped pixels.
-template <typename T>
-__device__ __forceinline__ void apply_L_frame(const SolveArgs& a, const T* P, T* F, int pitch, int M,
-                                              int r0, int c0, int ns, const int32_t* pix,
-                                              const int32_t* cellp, const T* fxp, const T* fyp) {
-  const int n2 = a.n2, nx = a.nx;
-  const T inv_n2 = (T)1 / (T)n2;
-  for (int t = threadIdx.x; t < M; t += kNT) {
-    const int j = pix[t];
-    T acc = 0;
-    for (int k = 0; k < n2; ++k) {
-      const int cell = cellp[(long)t * n2 + k];
-      if (cell < 0) continue;
-      const T fx = fxp[(long)t * n2 + k], fy = fyp[(long)t * n2 + k];
-      acc += (1 - fy) * ((1 - fx) * P[cell] + fx * P[cell + 1]) +
-             fy * ((1 - fx) * P[cell + ns] + fx * P[cell + ns + 1]);
-    }
-    F[(j / nx - r0) * pitch + (j % nx - c0)] = acc * inv_n2;
-  }
-}
-
 // Block-wide FP64 sum with one barrier; consecutive calls must alternate `buf`
 // (0/1) and be separated by at least one other barrier before a buffer is reused.
 __device__ __forceinline__ double block_sum1(double v, double* scratch, int buf) {
@@ -553,6 +535,88 @@ __device__ __forceinline__ double block_sum1(double v, double* scratch, int buf)
 #pragma unroll
   for (int i = 0; i < kWaves; ++i) t += sc[i];
   return t;
+}
+
+// Bilinear value of the n x n subpixels of mapped pixel t: sum_k w_k . x[cell_k..]
+template <typename T>
+__device__ __forceinline__ T pixel_gather(const T* X, int ns, int n2, int t, const int32_t* cellp, const T* fxp,
+                                          const T* fyp) {
+  T acc = 0;
+  if (n2 == 4) {
+    const int4 c4 = reinterpret_cast<const int4*>(cellp)[t];
+    T fx[4], fy[4];
+    if constexpr (sizeof(T) == 4) {
+      const float4 a4 = reinterpret_cast<const float4*>(fxp)[t];
+      const float4 b4 = reinterpret_cast<const float4*>(fyp)[t];
+      fx[0] = a4.x; fx[1] = a4.y; fx[2] = a4.z; fx[3] = a4.w;
+      fy[0] = b4.x; fy[1] = b4.y; fy[2] = b4.z; fy[3] = b4.w;
+    } else {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        fx[k] = fxp[4L * t + k];
+        fy[k] = fyp[4L * t + k];
+      }
+    }
+    const int cl[4] = {c4.x, c4.y, c4.z, c4.w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (cl[k] < 0) continue;
+      const int c = cl[k];
+      acc += (1 - fy[k]) * ((1 - fx[k]) * X[c] + fx[k] * X[c + 1]) +
+             fy[k] * ((1 - fx[k]) * X[c + ns] + fx[k] * X[c + ns + 1]);
+    }
+    return acc;
+  }
+  for (int k = 0; k < n2; ++k) {
+    const int c = cellp[(long)t * n2 + k];
+    if (c < 0) continue;
+    const T fx = fxp[(long)t * n2 + k], fy = fyp[(long)t * n2 + k];
+    acc += (1 - fy) * ((1 - fx) * X[c] + fx * X[c + 1]) + fy * ((1 - fx) * X[c + ns] + fx * X[c + ns + 1]);
+  }
+  return acc;
+}
+
+// x[cell_k..] += w_k * v for the subpixels of mapped pixel t (LDS atomics).
+template <typename T>
+__device__ __forceinline__ void pixel_scatter(T* X, int ns, int n2, int t, T v, const int32_t* cellp, const T* fxp,
+                                              const T* fyp) {
+  if (n2 == 4) {
+    const int4 c4 = reinterpret_cast<const int4*>(cellp)[t];
+    T fx[4], fy[4];
+    if constexpr (sizeof(T) == 4) {
+      const float4 a4 = reinterpret_cast<const float4*>(fxp)[t];
+      const float4 b4 = reinterpret_cast<const float4*>(fyp)[t];
+      fx[0] = a4.x; fx[1] = a4.y; fx[2] = a4.z; fx[3] = a4.w;
+      fy[0] = b4.x; fy[1] = b4.y; fy[2] = b4.z; fy[3] = b4.w;
+    } else {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        fx[k] = fxp[4L * t + k];
+        fy[k] = fyp[4L * t + k];
+      }
+    }
+    const int cl[4] = {c4.x, c4.y, c4.z, c4.w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (cl[k] < 0) continue;
+      const int c = cl[k];
+      const T vy0 = (1 - fy[k]) * v, vy1 = fy[k] * v;
+      atomicAdd(&X[c], (1 - fx[k]) * vy0);
+      atomicAdd(&X[c + 1], fx[k] * vy0);
+      atomicAdd(&X[c + ns], (1 - fx[k]) * vy1);
+      atomicAdd(&X[c + ns + 1], fx[k] * vy1);
+    }
+    return;
+  }
+  for (int k = 0; k < n2; ++k) {
+    const int c = cellp[(long)t * n2 + k];
+    if (c < 0) continue;
+    const T fx = fxp[(long)t * n2 + k], fy = fyp[(long)t * n2 + k];
+    atomicAdd(&X[c], (1 - fx) * (1 - fy) * v);
+    atomicAdd(&X[c + 1], fx * (1 - fy) * v);
+    atomicAdd(&X[c + ns], (1 - fx) * fy * v);
+    atomicAdd(&X[c + ns + 1], fx * fy * v);
+  }
 }
 
 // Invalid or empty member: s = 0, chi^2 = sum d^2 / sigma^2 (no barriers).
@@ -571,11 +635,15 @@ __device__ void trivial_item(const SolveArgs& a, const MemberInfo& mi, int m, in
 
 // One CG solve of a valid member.  Every branch that encloses a barrier
 // depends only on block-uniform values made scalar with readfirstlane.
-template <typename T, int CKT, int NPT, bool LDSF>
+// LDS: P = search direction p, Q = A p accumulator, the image frame (LDSF)
+// and reduction scratch.  The iterate s (in its output slot) and the
+// residual r live in global memory, read and written by their owner thread.
+template <typename T, int CKT, bool LDSF>
 __device__ void run_item(const SolveArgs& a, const MemberInfo& mi, int m, int kl, unsigned char* smem) {
   const int tid = threadIdx.x;
   const long out_idx = (long)m * a.n_lambda + kl;
-  T* s_dst = reinterpret_cast<T*>(a.s_all) + out_idx * a.I_max;
+  T* __restrict__ s_g = reinterpret_cast<T*>(a.s_all) + out_idx * a.I_max;
+  T* __restrict__ r_g = reinterpret_cast<T*>(a.rbuf) + (long)blockIdx.x * a.I_max;
   const int ns = mi.ns, I = mi.I, M = mi.M, r0 = mi.r0, c0 = mi.c0;
   const int h = mi.r1 - mi.r0 + 1, w = mi.c1 - mi.c0 + 1;
   constexpr int HALO = 2 * CKT;
@@ -583,8 +651,7 @@ __device__ void run_item(const SolveArgs& a, const MemberInfo& mi, int m, int kl
   // kSegR extra rows absorb the tail of the last column window
   const int frame_elems = (h + 2 * HALO + kSegR) * pitch;
   const int J = a.nx * a.ny, n2 = a.n2, nx = a.nx, ny = a.ny, K = a.K, ck = a.ck;
-  const double lam = a.lamv[kl];
-  const T lamT = (T)lam;
+  const T lamT = (T)a.lamv[kl];
   const bool ident = a.reg == SL_H_IDENTITY;
   T* P = reinterpret_cast<T*>(smem);
   T* Q = reinterpret_cast<T*>(smem + a.q_off);
@@ -605,32 +672,27 @@ __device__ void run_item(const SolveArgs& a, const MemberInfo& mi, int m, int kl
   const TapIdx ti(K);
   const bool sep = a.consts->sep != 0;
   const T inv_n2 = (T)1 / (T)n2;
+  const int fo = -r0 * pitch - c0;             // frame offset of image pixel (r, c): r*pitch + c + fo
   // dilated region (direct-blur paths): rows/cols within ck of the bbox, inside the image
   const int Dr0 = max(mi.r0 - ck, 0), Dr1 = min(mi.r1 + ck, ny - 1);
   const int Dc0 = max(mi.c0 - ck, 0), Dc1 = min(mi.c1 + ck, nx - 1);
   const int Dh = Dr1 - Dr0 + 1, Dw = Dc1 - Dc0 + 1;
 
-  // s = 0, r = p = b (p in LDS P), Q = 0, frame (with its halo) = 0
+  // s = 0, r = p = b, Q = 0, frame (with its halo) = 0
   for (int e = tid; e < frame_elems; e += kNT) F[e] = (T)0;
+  double rr = 0.0;
+  const double* bm = a.b + (long)m * a.I_max;
+  for (int i = tid; i < I; i += kNT) {
+    const T bv = (T)bm[i];
+    P[i] = bv;
+    Q[i] = (T)0;
+    s_g[i] = (T)0;
+    r_g[i] = bv;
+    rr += (double)bv * (double)bv;
+  }
   // row/column of this thread's first node, and the per-stride step
   const int r_first = tid / ns, c_first = tid - (tid / ns) * ns;
   const int r_step = kNT / ns, c_step = kNT - (kNT / ns) * ns;
-  T s[NPT], r[NPT];
-  double rr = 0.0;
-  const double* bm = a.b + (long)m * a.I_max;
-#pragma unroll
-  for (int k = 0; k < NPT; ++k) {
-    const int i = tid + k * kNT;
-    T bv = 0;
-    if (i < I) {
-      bv = (T)bm[i];
-      P[i] = bv;
-      Q[i] = (T)0;
-    }
-    s[k] = 0;
-    r[k] = bv;
-    rr += (double)bv * (double)bv;
-  }
   rr = block_sum1(rr, red, 0);
   const double stop2 = a.tol * a.tol * rr;
   int st = SL_ST_MAXIT, it = 0;
@@ -640,7 +702,10 @@ __device__ void run_item(const SolveArgs& a, const MemberInfo& mi, int m, int kl
       break;
     }
     // y = L p into the frame (P holds p, Q and the frame are zero)
-    apply_L_frame(a, P, F0, pitch, M, r0, c0, ns, pix, cellp, fxp, fyp);
+    for (int t = tid; t < M; t += kNT) {
+      const int rc = pix[t];
+      F0[(rc >> 16) * pitch + (rc & 0xFFFF) + fo] = pixel_gather(P, ns, n2, t, cellp, fxp, fyp) * inv_n2;
+    }
     __syncthreads();
     if (sep) {   // sep comes from a scalar load: uniform
       // w = B^T B y: banded pass along rows then along columns, in place
@@ -667,7 +732,7 @@ __device__ void run_item(const SolveArgs& a, const MemberInfo& mi, int m, int kl
       __syncthreads();
       // w = B^T z at the mapped pixels, back into the frame
       for (int t = tid; t < M; t += kNT) {
-        const int j = pix[t], rr_ = j / nx, cc_ = j % nx;
+        const int rr_ = pix[t] >> 16, cc_ = pix[t] & 0xFFFF;
         T acc = 0;
         for (int aa = 0; aa < K; ++aa) {
           const int zr = rr_ + aa - ck - Dr0;
@@ -678,30 +743,20 @@ __device__ void run_item(const SolveArgs& a, const MemberInfo& mi, int m, int kl
             acc += taps[ti.psf + aa * K + bb] * Z[zr * Dw + zc];
           }
         }
-        F0[(rr_ - r0) * pitch + (cc_ - c0)] = acc;
+        F0[rr_ * pitch + cc_ + fo] = acc;
       }
       __syncthreads();
     }
     // L^T w accumulated in LDS Q
     for (int t = tid; t < M; t += kNT) {
-      const int j = pix[t];
-      const T wv = F0[(j / nx - r0) * pitch + (j % nx - c0)] * inv_n2;
-      for (int k = 0; k < n2; ++k) {
-        const int cell = cellp[(long)t * n2 + k];
-        if (cell < 0) continue;
-        const T fx = fxp[(long)t * n2 + k], fy = fyp[(long)t * n2 + k];
-        atomicAdd(&Q[cell], (1 - fx) * (1 - fy) * wv);
-        atomicAdd(&Q[cell + 1], fx * (1 - fy) * wv);
-        atomicAdd(&Q[cell + ns], (1 - fx) * fy * wv);
-        atomicAdd(&Q[cell + ns + 1], fx * fy * wv);
-      }
+      const int rc = pix[t];
+      pixel_scatter(Q, ns, n2, t, F0[(rc >> 16) * pitch + (rc & 0xFFFF) + fo] * inv_n2, cellp, fxp, fyp);
     }
     __syncthreads();
     // q = A p (kept in Q), <p, q>; the frame returns to zero for the next iteration
     double pq = 0.0;
     {
       int rn_ = r_first, cn_ = c_first;
-#pragma unroll 1
       for (int i = tid; i < I; i += kNT) {
         const T pv = P[i];
         const T qv = Q[i] + lamT * (ident ? pv : hth_node(P, ns, rn_, cn_));
@@ -721,43 +776,31 @@ __device__ void run_item(const SolveArgs& a, const MemberInfo& mi, int m, int kl
       st = SL_ST_BREAKDOWN;
       break;
     }
-    const double alpha = rr / pq;
-    const T alT = (T)alpha;
+    const T alT = (T)(rr / pq);
     double rn = 0.0;
-#pragma unroll
-    for (int k = 0; k < NPT; ++k) {
-      const int i = tid + k * kNT;
-      if (i < I) {
-        s[k] += alT * P[i];
-        r[k] -= alT * Q[i];
-        Q[i] = (T)0;
-        rn += (double)r[k] * (double)r[k];
-      }
+    for (int i = tid; i < I; i += kNT) {
+      s_g[i] += alT * P[i];
+      const T rv = r_g[i] - alT * Q[i];
+      r_g[i] = rv;
+      Q[i] = (T)0;
+      rn += (double)rv * (double)rv;
     }
     rn = block_sum1(rn, red, 1);
     const T beta = (T)(rn / rr);
-#pragma unroll
-    for (int k = 0; k < NPT; ++k) {
-      const int i = tid + k * kNT;
-      if (i < I) P[i] = r[k] + beta * P[i];
-    }
+    for (int i = tid; i < I; i += kNT) P[i] = r_g[i] + beta * P[i];
     rr = rn;
     __syncthreads();
   }
   if (st == SL_ST_MAXIT && rr <= stop2) st = SL_ST_OK;
   // ---- chi^2 and ||H s||^2 from the explicit solution
   __syncthreads();
-#pragma unroll
-  for (int k = 0; k < NPT; ++k) {
-    const int i = tid + k * kNT;
-    if (i < I) {
-      P[i] = s[k];
-      s_dst[i] = s[k];
-    }
-  }
+  for (int i = tid; i < I; i += kNT) P[i] = s_g[i];
   for (int e = tid; e < h * pitch; e += kNT) Frows[e] = (T)0;
   __syncthreads();
-  apply_L_frame(a, P, F0, pitch, M, r0, c0, ns, pix, cellp, fxp, fyp);
+  for (int t = tid; t < M; t += kNT) {
+    const int rc = pix[t];
+    F0[(rc >> 16) * pitch + (rc & 0xFFFF) + fo] = pixel_gather(P, ns, n2, t, cellp, fxp, fyp) * inv_n2;
+  }
   double regacc = 0.0;
   for (int i = tid; i < I; i += kNT) regacc += reg_node(P, ns, i / ns, i % ns, a.reg);
   __syncthreads();
@@ -805,7 +848,7 @@ __device__ __forceinline__ int fetch_item(const SolveArgs& a, int xcd, int* sh_i
   return item;
 }
 
-template <typename T, int CKT, int NPT>
+template <typename T, int CKT>
 __global__ void __launch_bounds__(kNT) k_solve(SolveArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int sh_item;
@@ -820,9 +863,9 @@ __global__ void __launch_bounds__(kNT) k_solve(SolveArgs a) {
     if (status != SL_ST_OK)
       trivial_item<T>(a, mi, m, kl);
     else if (fits)
-      run_item<T, CKT, NPT, true>(a, mi, m, kl, smem);
+      run_item<T, CKT, true>(a, mi, m, kl, smem);
     else
-      run_item<T, CKT, NPT, false>(a, mi, m, kl, smem);
+      run_item<T, CKT, false>(a, mi, m, kl, smem);
   }
 }
 
@@ -905,6 +948,7 @@ static Layout make_layout(const sl_problem* pb, int max_ns, int M, int NL, int n
   L.gframe_elems = (pb->img.ny + 4 * 16 + kSegR) * ((pb->img.nx + 4 * 16) | 1);   // widest window's halo
   L.gframe = take(sz * (size_t)n_wg * L.gframe_elems);
   L.gz = take(sz * (size_t)n_wg * L.J);
+  L.rbuf = take(sz * (size_t)n_wg * L.I_max);
   L.total = off;
   return L;
 }
@@ -931,32 +975,21 @@ static int check_problem(const sl_problem* pb, int max_ns, int M, int NL) {
 
 using SolveKernel = void (*)(SolveArgs);
 
-// Kernel variants: bulk type T, banded half-width CKT (>= ck of the PSF) and
-// nodes per thread NPT (I_max <= NPT * kNT).  Returns the kernel and its CKT.
-template <typename T, int CKT>
-static SolveKernel pick_npt(int I_max) {
-  if (I_max <= 8 * kNT) return k_solve<T, CKT, 8>;
-  if (I_max <= 20 * kNT) return k_solve<T, CKT, 20>;
-  if constexpr (sizeof(T) == 4) {
-    if (I_max <= 32 * kNT) return k_solve<T, CKT, 32>;
-  }
-  return nullptr;
+// Kernel variants: bulk type T and banded half-width CKT (>= ck of the PSF).
+static SolveKernel pick_kernel_f(int ck, int* ckt) {
+  if (ck <= 2) { *ckt = 2; return k_solve<float, 2>; }
+  if (ck <= 4) { *ckt = 4; return k_solve<float, 4>; }
+  if (ck <= 7) { *ckt = 7; return k_solve<float, 7>; }
+  if (ck <= 10) { *ckt = 10; return k_solve<float, 10>; }
+  if (ck <= 16) { *ckt = 16; return k_solve<float, 16>; }
+  { *ckt = 2; return k_solve<float, 2>; }   // wider PSFs: direct path only
 }
 
-static SolveKernel pick_kernel_f(int ck, int I_max, int* ckt) {
-  if (ck <= 2) return *ckt = 2, pick_npt<float, 2>(I_max);
-  if (ck <= 4) return *ckt = 4, pick_npt<float, 4>(I_max);
-  if (ck <= 7) return *ckt = 7, pick_npt<float, 7>(I_max);
-  if (ck <= 10) return *ckt = 10, pick_npt<float, 10>(I_max);
-  if (ck <= 16) return *ckt = 16, pick_npt<float, 16>(I_max);
-  return *ckt = 2, pick_npt<float, 2>(I_max);   // wider PSFs: direct path only
-}
-
-static SolveKernel pick_kernel_d(int ck, int I_max, int* ckt) {
-  if (ck <= 2) return *ckt = 2, pick_npt<double, 2>(I_max);
-  if (ck <= 7) return *ckt = 7, pick_npt<double, 7>(I_max);
-  if (ck <= 10) return *ckt = 10, pick_npt<double, 10>(I_max);
-  return *ckt = 2, pick_npt<double, 2>(I_max);
+static SolveKernel pick_kernel_d(int ck, int* ckt) {
+  if (ck <= 2) { *ckt = 2; return k_solve<double, 2>; }
+  if (ck <= 7) { *ckt = 7; return k_solve<double, 7>; }
+  if (ck <= 10) { *ckt = 10; return k_solve<double, 10>; }
+  { *ckt = 2; return k_solve<double, 2>; }
 }
 
 // ------------------------------------------------------------------ profiling
@@ -971,8 +1004,7 @@ template <typename T>
 static int launch_solve(SolveArgs& A, const LamList& lams, const Layout& L, hipStream_t st) {
   const size_t sz = sizeof(T);
   int ckt = 2;
-  SolveKernel ks = sizeof(T) == 4 ? pick_kernel_f(A.ck, L.I_max, &ckt) : pick_kernel_d(A.ck, L.I_max, &ckt);
-  SL_REQUIRE(ks != nullptr, "source grid too large for the compiled kernels (I_max = %d)", L.I_max);
+  SolveKernel ks = sizeof(T) == 4 ? pick_kernel_f(A.ck, &ckt) : pick_kernel_d(A.ck, &ckt);
   A.ckt = ckt;
   // dynamic LDS: source vector | reduction scratch | frame (up to the full image)
   A.q_off = (int)align256(sz * L.I_max);
@@ -1094,6 +1126,7 @@ int sl_solve_semilinear(const sl_problem* pb, const double* lens, const int32_t*
   A.gframe = ws + L.gframe;
   A.gframe_elems = L.gframe_elems;
   A.gz = ws + L.gz;
+  A.rbuf = ws + L.rbuf;
   A.I_max = L.I_max;
   LamList lams{};
   for (int k = 0; k < n_lambda; ++k) lams.v[k] = lambdas[k];
