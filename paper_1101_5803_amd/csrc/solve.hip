@@ -41,9 +41,10 @@ constexpr int kSegR = 4;       // outputs per lane in a banded pass
 constexpr int kMaxCK = 31;
 
 struct alignas(16) MemberInfo {
-  int ns, I, M, r0, r1, c0, c1, status;
+  int ns, I, M, r0, r1, c0, c1, status;   // M: interleaved table slots (>= mapped pixels)
   long long off;   // start in packed vectors
-  long long pad;
+  int Mtrue;       // pixels with at least one subpixel on the grid
+  int pad;
 };
 
 // Device constants written by k_setup (one copy per workspace).
@@ -58,7 +59,7 @@ struct alignas(16) Consts {
 
 struct Layout {
   size_t consts, lam, taps_d, taps_f, minfo, queues, pix, cell, fx, fy, b, s_all, gframe, gz, rbuf, total;
-  int qcap, n_wg, I_max, J, n2, gframe_elems;
+  int qcap, n_wg, I_max, J, n2, gframe_elems, slot_cap;
 };
 
 // Offsets (elements) inside the taps arrays, for a PSF of side K (ck = (K-1)/2).
@@ -85,6 +86,7 @@ struct SolveArgs {
   int nx, ny, nsub, n2, K, ck, ckt, reg, n_members, n_lambda, max_ns, maxit, lds_frame_cap;
   int q_off, red_off, frame_off;   // byte offsets in dynamic LDS
   int gframe_elems;                // per-block global frame size (elements)
+  int slot_cap;                    // trace-table slots per member (J + 64)
   double pix, R, sigma, tol;
   double* lamv;                    // workspace copy of the lambda grid
   const double* lens;
@@ -305,6 +307,7 @@ __global__ void __launch_bounds__(1024) k_prep(SolveArgs a) {
   if (!valid) {
     if (tid == 0) {
       mi.M = 0;
+      mi.Mtrue = 0;
       mi.status = SL_ST_INVALID;
       mi.r0 = mi.c0 = 0;
       mi.r1 = mi.c1 = -1;
@@ -324,10 +327,42 @@ __device__ void prep_member(const SolveArgs& a, int m, MemberInfo mi, const doub
   const Lens L = make_lens(gl);
   const int ns = mi.ns;
   const double h = 2.0 * a.R / (ns - 1);
-  int32_t* pix = a.pix_list + (long)m * J;
-  int32_t* cellp = a.cell + (long)m * J * n2;
-  T* fxp = reinterpret_cast<T*>(a.fx) + (long)m * J * n2;
-  T* fyp = reinterpret_cast<T*>(a.fy) + (long)m * J * n2;
+  int32_t* pix = a.pix_list + (long)m * a.slot_cap;
+  int32_t* cellp = a.cell + (long)m * a.slot_cap * n2;
+  T* fxp = reinterpret_cast<T*>(a.fx) + (long)m * a.slot_cap * n2;
+  T* fyp = reinterpret_cast<T*>(a.fy) + (long)m * a.slot_cap * n2;
+  // pass 1: count the pixels with at least one subpixel on the grid, and their bounding box
+  int count = 0;
+  for (int j0 = 0; j0 < J; j0 += blockDim.x) {
+    const int j = j0 + tid;
+    const int r = j / nx, c = j % nx;
+    bool mapped = false;
+    if (j < J) {
+      for (int k = 0; k < n2; ++k) {
+        double x, y, bx, by, fx, fy;
+        int cell;
+        subpixel_xy(r, c, k / nsub, k % nsub, nx, ny, a.pix, nsub, x, y);
+        lens_map(L, x, y, bx, by);
+        mapped |= grid_cell((bx + a.R) / h, (by + a.R) / h, ns, cell, fx, fy);
+      }
+    }
+    if (mapped) {
+      atomicMin(&bbox[0], r);
+      atomicMax(&bbox[1], r);
+      atomicMin(&bbox[2], c);
+      atomicMax(&bbox[3], c);
+    }
+    int tot;
+    (void)block_excl_count(mapped, scan, &tot);
+    count += tot;
+  }
+  // The table is interleaved: compacted entry pos goes to slot (pos % S) * 64 + pos / S,
+  // so the 64 lanes of a wave take pixels spread over the whole mapped region and
+  // their L^T atomics rarely hit the same source node; slots past the last entry
+  // hold -1.
+  const int Mtrue = count;
+  const int S = (Mtrue + 63) / 64;
+  const int slots = 64 * S;
   int base = 0;
   for (int j0 = 0; j0 < J; j0 += blockDim.x) {
     const int j = j0 + tid;
@@ -345,8 +380,8 @@ __device__ void prep_member(const SolveArgs& a, int m, MemberInfo mi, const doub
     int tot;
     const int pos = base + block_excl_count(mapped, scan, &tot);
     if (mapped) {
-      pix[pos] = (r << 16) | c;   // packed row/column of the mapped pixel
-      // second pass over the subpixels writes the compacted table directly
+      const int slot = (pos % S) * 64 + pos / S;
+      pix[slot] = (r << 16) | c;   // packed row/column of the mapped pixel
       for (int k = 0; k < n2; ++k) {
         double x, y, bx, by, fx = 0.0, fy = 0.0;
         int cell = -1;
@@ -356,18 +391,25 @@ __device__ void prep_member(const SolveArgs& a, int m, MemberInfo mi, const doub
           cell = -1;
           fx = fy = 0.0;
         }
-        cellp[(long)pos * n2 + k] = cell;
-        fxp[(long)pos * n2 + k] = (T)fx;
-        fyp[(long)pos * n2 + k] = (T)fy;
+        cellp[(long)slot * n2 + k] = cell;
+        fxp[(long)slot * n2 + k] = (T)fx;
+        fyp[(long)slot * n2 + k] = (T)fy;
       }
-      atomicMin(&bbox[0], r);
-      atomicMax(&bbox[1], r);
-      atomicMin(&bbox[2], c);
-      atomicMax(&bbox[3], c);
     }
     base += tot;
   }
-  const int Mm = base;
+  for (int sl_ = tid; sl_ < slots; sl_ += blockDim.x) {
+    if ((sl_ % 64) * S + sl_ / 64 >= Mtrue) {
+      pix[sl_] = -1;
+      for (int k = 0; k < n2; ++k) {
+        cellp[(long)sl_ * n2 + k] = -1;
+        fxp[(long)sl_ * n2 + k] = (T)0;
+        fyp[(long)sl_ * n2 + k] = (T)0;
+      }
+    }
+  }
+  __syncthreads();
+  const int Mm = slots;
   // right-hand side b = L^T B^T d (FP64)
   const int I = ns * ns;
   for (int i = tid; i < I; i += blockDim.x) bacc[i] = 0.0;
@@ -375,6 +417,7 @@ __device__ void prep_member(const SolveArgs& a, int m, MemberInfo mi, const doub
   const int K = a.K, ck = a.ck;
   const double inv_n2 = 1.0 / n2;
   for (int t = tid; t < Mm; t += blockDim.x) {
+    if (pix[t] < 0) continue;
     const int r = pix[t] >> 16, c = pix[t] & 0xFFFF;
     double v = 0.0;
     for (int aa = 0; aa < K; ++aa) {
@@ -402,11 +445,12 @@ __device__ void prep_member(const SolveArgs& a, int m, MemberInfo mi, const doub
   for (int i = tid; i < I; i += blockDim.x) bm[i] = bacc[i];
   if (tid == 0) {
     mi.M = Mm;
-    mi.status = Mm > 0 ? SL_ST_OK : SL_ST_EMPTY;
-    mi.r0 = Mm > 0 ? bbox[0] : 0;
-    mi.r1 = Mm > 0 ? bbox[1] : -1;
-    mi.c0 = Mm > 0 ? bbox[2] : 0;
-    mi.c1 = Mm > 0 ? bbox[3] : -1;
+    mi.Mtrue = Mtrue;
+    mi.status = Mtrue > 0 ? SL_ST_OK : SL_ST_EMPTY;
+    mi.r0 = Mtrue > 0 ? bbox[0] : 0;
+    mi.r1 = Mtrue > 0 ? bbox[1] : -1;
+    mi.c0 = Mtrue > 0 ? bbox[2] : 0;
+    mi.c1 = Mtrue > 0 ? bbox[3] : -1;
     a.minfo[m] = mi;
   }
 }
@@ -595,6 +639,22 @@ __device__ __forceinline__ void pixel_scatter(T* X, int ns, int n2, int t, T v, 
         fy[k] = fyp[4L * t + k];
       }
     }
+    if (c4.x >= 0 && c4.x == c4.y && c4.x == c4.z && c4.x == c4.w) {
+      // all four subpixels in one cell: merge their weights, 4 atomics instead of 16
+      T w00 = 0, w01 = 0, w10 = 0, w11 = 0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        w00 += (1 - fx[k]) * (1 - fy[k]);
+        w01 += fx[k] * (1 - fy[k]);
+        w10 += (1 - fx[k]) * fy[k];
+        w11 += fx[k] * fy[k];
+      }
+      atomicAdd(&X[c4.x], w00 * v);
+      atomicAdd(&X[c4.x + 1], w01 * v);
+      atomicAdd(&X[c4.x + ns], w10 * v);
+      atomicAdd(&X[c4.x + ns + 1], w11 * v);
+      return;
+    }
     const int cl[4] = {c4.x, c4.y, c4.z, c4.w};
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -664,10 +724,10 @@ __device__ void run_item(const SolveArgs& a, const MemberInfo& mi, int m, int kl
   T* const F0 = F + HALO * pitch + HALO;        // interior (0, 0) = image (r0, c0)
   T* const Frows = F + HALO * pitch;            // interior rows, contiguous
   T* Z = reinterpret_cast<T*>(a.gz) + (long)blockIdx.x * J;
-  const int32_t* pix = a.pix_list + (long)m * J;
-  const int32_t* cellp = a.cell + (long)m * J * n2;
-  const T* fxp = reinterpret_cast<const T*>(a.fx) + (long)m * J * n2;
-  const T* fyp = reinterpret_cast<const T*>(a.fy) + (long)m * J * n2;
+  const int32_t* pix = a.pix_list + (long)m * a.slot_cap;
+  const int32_t* cellp = a.cell + (long)m * a.slot_cap * n2;
+  const T* fxp = reinterpret_cast<const T*>(a.fx) + (long)m * a.slot_cap * n2;
+  const T* fyp = reinterpret_cast<const T*>(a.fy) + (long)m * a.slot_cap * n2;
   const T* taps = reinterpret_cast<const T*>(a.taps_t);
   const TapIdx ti(K);
   const bool sep = a.consts->sep != 0;
@@ -704,7 +764,7 @@ __device__ void run_item(const SolveArgs& a, const MemberInfo& mi, int m, int kl
     // y = L p into the frame (P holds p, Q and the frame are zero)
     for (int t = tid; t < M; t += kNT) {
       const int rc = pix[t];
-      F0[(rc >> 16) * pitch + (rc & 0xFFFF) + fo] = pixel_gather(P, ns, n2, t, cellp, fxp, fyp) * inv_n2;
+      if (rc >= 0) F0[(rc >> 16) * pitch + (rc & 0xFFFF) + fo] = pixel_gather(P, ns, n2, t, cellp, fxp, fyp) * inv_n2;
     }
     __syncthreads();
     if (sep) {   // sep comes from a scalar load: uniform
@@ -732,6 +792,7 @@ __device__ void run_item(const SolveArgs& a, const MemberInfo& mi, int m, int kl
       __syncthreads();
       // w = B^T z at the mapped pixels, back into the frame
       for (int t = tid; t < M; t += kNT) {
+        if (pix[t] < 0) continue;
         const int rr_ = pix[t] >> 16, cc_ = pix[t] & 0xFFFF;
         T acc = 0;
         for (int aa = 0; aa < K; ++aa) {
@@ -750,7 +811,8 @@ __device__ void run_item(const SolveArgs& a, const MemberInfo& mi, int m, int kl
     // L^T w accumulated in LDS Q
     for (int t = tid; t < M; t += kNT) {
       const int rc = pix[t];
-      pixel_scatter(Q, ns, n2, t, F0[(rc >> 16) * pitch + (rc & 0xFFFF) + fo] * inv_n2, cellp, fxp, fyp);
+      if (rc >= 0)
+        pixel_scatter(Q, ns, n2, t, F0[(rc >> 16) * pitch + (rc & 0xFFFF) + fo] * inv_n2, cellp, fxp, fyp);
     }
     __syncthreads();
     // q = A p (kept in Q), <p, q>; the frame returns to zero for the next iteration
@@ -799,7 +861,7 @@ __device__ void run_item(const SolveArgs& a, const MemberInfo& mi, int m, int kl
   __syncthreads();
   for (int t = tid; t < M; t += kNT) {
     const int rc = pix[t];
-    F0[(rc >> 16) * pitch + (rc & 0xFFFF) + fo] = pixel_gather(P, ns, n2, t, cellp, fxp, fyp) * inv_n2;
+    if (rc >= 0) F0[(rc >> 16) * pitch + (rc & 0xFFFF) + fo] = pixel_gather(P, ns, n2, t, cellp, fxp, fyp) * inv_n2;
   }
   double regacc = 0.0;
   for (int i = tid; i < I; i += kNT) regacc += reg_node(P, ns, i / ns, i % ns, a.reg);
@@ -939,10 +1001,11 @@ static Layout make_layout(const sl_problem* pb, int max_ns, int M, int NL, int n
   L.taps_f = take(sz * ti.total);
   L.minfo = take(sizeof(MemberInfo) * M);
   L.queues = take(sizeof(int) * 8 * (size_t)L.qcap);
-  L.pix = take(sizeof(int32_t) * (size_t)M * L.J);
-  L.cell = take(sizeof(int32_t) * (size_t)M * L.J * L.n2);
-  L.fx = take(sz * (size_t)M * L.J * L.n2);
-  L.fy = take(sz * (size_t)M * L.J * L.n2);
+  L.slot_cap = L.J + 64;
+  L.pix = take(sizeof(int32_t) * (size_t)M * L.slot_cap);
+  L.cell = take(sizeof(int32_t) * (size_t)M * L.slot_cap * L.n2);
+  L.fx = take(sz * (size_t)M * L.slot_cap * L.n2);
+  L.fy = take(sz * (size_t)M * L.slot_cap * L.n2);
   L.b = take(sizeof(double) * (size_t)M * L.I_max);
   L.s_all = take(sz * (size_t)M * NL * L.I_max);
   L.gframe_elems = (pb->img.ny + 4 * 16 + kSegR) * ((pb->img.nx + 4 * 16) | 1);   // widest window's halo
@@ -1125,6 +1188,7 @@ int sl_solve_semilinear(const sl_problem* pb, const double* lens, const int32_t*
   A.s_all = ws + L.s_all;
   A.gframe = ws + L.gframe;
   A.gframe_elems = L.gframe_elems;
+  A.slot_cap = L.slot_cap;
   A.gz = ws + L.gz;
   A.rbuf = ws + L.rbuf;
   A.I_max = L.I_max;
@@ -1148,7 +1212,7 @@ int sl_solve_member_info(const sl_problem* pb, int max_ns, int n_members, int n_
     int32_t* o = info_host + 8 * m;
     o[0] = mi[m].ns;
     o[1] = mi[m].I;
-    o[2] = mi[m].M;
+    o[2] = mi[m].Mtrue;
     o[3] = mi[m].r0;
     o[4] = mi[m].r1;
     o[5] = mi[m].c0;
