@@ -58,7 +58,9 @@ struct alignas(16) Consts {
 };
 
 struct Layout {
-  size_t consts, lam, taps_d, taps_f, minfo, queues, pix, cell, fx, fy, b, s_all, gframe, gz, rbuf, total;
+  size_t consts, lam, taps_d, taps_f, minfo, queues, pix, cell, fx, fy, b, s_all, gframe, gz, rbuf, lt_ptr, lt_ent,
+      total;
+  long long lt_cap;
   int qcap, n_wg, I_max, J, n2, gframe_elems, slot_cap;
 };
 
@@ -79,6 +81,14 @@ struct TapIdx {
     psf = ery + ck * ck;
     total = psf + K * K;
   }
+};
+
+// One entry of the transposed lens operator: L^T w at a node is the sum of
+// w[off] * weight over the node's entries (off = frame offset of the pixel).
+template <typename T>
+struct alignas(2 * sizeof(T) > 8 ? 16 : 8) LtEntry {
+  int off;
+  T w;
 };
 
 // ------------------------------------------------------------------ parameters
@@ -118,6 +128,9 @@ struct SolveArgs {
   void* gframe;
   void* gz;
   void* rbuf;       // per-block CG residual
+  int32_t* lt_ptr;  // [member][I_max + 1] row starts of the transposed operator
+  void* lt_ent;     // [member][lt_cap] LtEntry<T>
+  long long lt_cap; // entries per member
   int I_max;
 };
 
@@ -319,6 +332,107 @@ __global__ void __launch_bounds__(1024) k_prep(SolveArgs a) {
 }
 
 // Trace, compaction and right-hand side of one valid member (all threads).
+// Unique (node, weight) pairs of the subpixels of mapped slot t, weights
+// including the 1/n^2 subpixel average; returns the pair count (<= 4 n^2).
+template <typename T>
+__device__ int pixel_pairs(int t, int ns, int n2, const int32_t* cellp, const T* fxp, const T* fyp, int* node,
+                           double* wt) {
+  int cnt = 0;
+  const double inv = 1.0 / n2;
+  for (int k = 0; k < n2; ++k) {
+    const int c = cellp[(long)t * n2 + k];
+    if (c < 0) continue;
+    const double fx = (double)fxp[(long)t * n2 + k], fy = (double)fyp[(long)t * n2 + k];
+    const int nd[4] = {c, c + 1, c + ns, c + ns + 1};
+    const double ww[4] = {(1 - fx) * (1 - fy), fx * (1 - fy), (1 - fx) * fy, fx * fy};
+    for (int q = 0; q < 4; ++q) {
+      int f = 0;
+      while (f < cnt && node[f] != nd[q]) ++f;
+      if (f == cnt) {
+        node[cnt] = nd[q];
+        wt[cnt] = 0.0;
+        ++cnt;
+      }
+      wt[f] += ww[q] * inv;
+    }
+  }
+  return cnt;
+}
+
+// Node-major (CSR) form of L^T for one member: for every node, the frame
+// offsets of the pixels whose subpixels touch it and the merged weights,
+// sorted by offset so the per-node sum has a fixed order.  cnt: LDS ints (>= I).
+template <typename T>
+__device__ void build_transpose(const SolveArgs& a, int m, int ns, int slots, const int* bbox, int* scan, int* cnt,
+                                const int32_t* pix, const int32_t* cellp, const T* fxp, const T* fyp) {
+  const int tid = threadIdx.x, n2 = a.n2, I = ns * ns;
+  const int halo = 2 * a.ckt;
+  const int pitch = (bbox[3] - bbox[2] + 1 + 2 * halo) | 1;
+  int32_t* rp = a.lt_ptr + (long)m * (a.I_max + 1);
+  LtEntry<T>* ent = reinterpret_cast<LtEntry<T>*>(a.lt_ent) + (long)m * a.lt_cap;
+  int node[4 * SL_MAX_NSUB * SL_MAX_NSUB];
+  double wt[4 * SL_MAX_NSUB * SL_MAX_NSUB];
+  for (int i = tid; i < I; i += blockDim.x) cnt[i] = 0;
+  __syncthreads();
+  for (int t = tid; t < slots; t += blockDim.x) {
+    if (pix[t] < 0) continue;
+    const int np = pixel_pairs(t, ns, n2, cellp, fxp, fyp, node, wt);
+    for (int q = 0; q < np; ++q) atomicAdd(&cnt[node[q]], 1);
+  }
+  __syncthreads();
+  // exclusive scan of the counts: each thread sums a contiguous chunk
+  const int chunk = (I + blockDim.x - 1) / blockDim.x;
+  const int i0 = min(I, tid * chunk), i1 = min(I, i0 + chunk);
+  int local = 0;
+  for (int i = i0; i < i1; ++i) local += cnt[i];
+  const int lane = tid & 63, wid = tid >> 6, nw = blockDim.x >> 6;
+  int incl = local;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int v = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += v;
+  }
+  if (lane == 63) scan[wid] = incl;
+  __syncthreads();
+  int before = 0;
+  for (int i = 0; i < wid; ++i) before += scan[i];
+  int run = before + incl - local;
+  for (int i = i0; i < i1; ++i) {
+    const int c = cnt[i];
+    rp[i] = run;
+    cnt[i] = run;      // becomes the fill cursor
+    run += c;
+  }
+  if (tid == blockDim.x - 1) rp[I] = run;
+  (void)nw;
+  __syncthreads();
+  for (int t = tid; t < slots; t += blockDim.x) {
+    const int rc = pix[t];
+    if (rc < 0) continue;
+    const int off = ((rc >> 16) - bbox[0] + halo) * pitch + ((rc & 0xFFFF) - bbox[2] + halo);
+    const int np = pixel_pairs(t, ns, n2, cellp, fxp, fyp, node, wt);
+    for (int q = 0; q < np; ++q) {
+      const int e = atomicAdd(&cnt[node[q]], 1);
+      ent[e].off = off;
+      ent[e].w = (T)wt[q];
+    }
+  }
+  __syncthreads();
+  // fixed summation order: sort every row by frame offset (rows are short)
+  for (int i = tid; i < I; i += blockDim.x) {
+    const int e0 = rp[i], e1 = rp[i + 1];
+    for (int e = e0 + 1; e < e1; ++e) {
+      const LtEntry<T> x = ent[e];
+      int f = e - 1;
+      while (f >= e0 && ent[f].off > x.off) {
+        ent[f + 1] = ent[f];
+        --f;
+      }
+      ent[f + 1] = x;
+    }
+  }
+  __syncthreads();
+}
+
 template <typename T>
 __device__ void prep_member(const SolveArgs& a, int m, MemberInfo mi, const double* gl, int* bbox, int* scan,
                             double* bacc) {
@@ -360,7 +474,7 @@ __device__ void prep_member(const SolveArgs& a, int m, MemberInfo mi, const doub
   // so the 64 lanes of a wave take pixels spread over the whole mapped region and
   // their L^T atomics rarely hit the same source node; slots past the last entry
   // hold -1.
-  const int Mtrue = count;
+  const int Mtrue = __builtin_amdgcn_readfirstlane(count);   // block-uniform: branches below enclose barriers
   const int S = (Mtrue + 63) / 64;
   const int slots = 64 * S;
   int base = 0;
@@ -443,6 +557,8 @@ __device__ void prep_member(const SolveArgs& a, int m, MemberInfo mi, const doub
   __syncthreads();
   double* bm = a.b + (long)m * a.I_max;
   for (int i = tid; i < I; i += blockDim.x) bm[i] = bacc[i];
+  __syncthreads();
+  if (Mtrue > 0) build_transpose<T>(a, m, ns, Mm, bbox, scan, reinterpret_cast<int*>(bacc), pix, cellp, fxp, fyp);
   if (tid == 0) {
     mi.M = Mm;
     mi.Mtrue = Mtrue;
@@ -733,6 +849,8 @@ __device__ void run_item(const SolveArgs& a, const MemberInfo& mi, int m, int kl
   const bool sep = a.consts->sep != 0;
   const T inv_n2 = (T)1 / (T)n2;
   const int fo = -r0 * pitch - c0;             // frame offset of image pixel (r, c): r*pitch + c + fo
+  const int32_t* lt_rp = a.lt_ptr + (long)m * (a.I_max + 1);
+  const LtEntry<T>* lt_e = reinterpret_cast<const LtEntry<T>*>(a.lt_ent) + (long)m * a.lt_cap;
   // dilated region (direct-blur paths): rows/cols within ck of the bbox, inside the image
   const int Dr0 = max(mi.r0 - ck, 0), Dr1 = min(mi.r1 + ck, ny - 1);
   const int Dc0 = max(mi.c0 - ck, 0), Dc1 = min(mi.c1 + ck, nx - 1);
@@ -808,20 +926,22 @@ __device__ void run_item(const SolveArgs& a, const MemberInfo& mi, int m, int kl
       }
       __syncthreads();
     }
-    // L^T w accumulated in LDS Q
-    for (int t = tid; t < M; t += kNT) {
-      const int rc = pix[t];
-      if (rc >= 0)
-        pixel_scatter(Q, ns, n2, t, F0[(rc >> 16) * pitch + (rc & 0xFFFF) + fo] * inv_n2, cellp, fxp, fyp);
-    }
-    __syncthreads();
-    // q = A p (kept in Q), <p, q>; the frame returns to zero for the next iteration
+    // q = L^T w + lambda H^T H p gathered per node from the transposed operator
+    // (no atomics, fixed order), stored in Q; <p, q>
     double pq = 0.0;
     {
       int rn_ = r_first, cn_ = c_first;
       for (int i = tid; i < I; i += kNT) {
+        const int e0 = lt_rp[i], e1 = lt_rp[i + 1];
+        T acc = 0;
+        int e = e0;
+        for (; e + 1 < e1; e += 2) {
+          const LtEntry<T> x0 = lt_e[e], x1 = lt_e[e + 1];
+          acc += x0.w * F[x0.off] + x1.w * F[x1.off];
+        }
+        if (e < e1) acc += lt_e[e].w * F[lt_e[e].off];
         const T pv = P[i];
-        const T qv = Q[i] + lamT * (ident ? pv : hth_node(P, ns, rn_, cn_));
+        const T qv = acc + lamT * (ident ? pv : hth_node(P, ns, rn_, cn_));
         Q[i] = qv;
         pq += (double)pv * (double)qv;
         rn_ += r_step;
@@ -832,8 +952,9 @@ __device__ void run_item(const SolveArgs& a, const MemberInfo& mi, int m, int kl
         }
       }
     }
-    for (int e = tid; e < h * pitch; e += kNT) Frows[e] = (T)0;
     pq = block_sum1(pq, red, 0);
+    // every gather has read the frame (barrier above): back to zero for the next iteration
+    for (int e = tid; e < h * pitch; e += kNT) Frows[e] = (T)0;
     if (__builtin_amdgcn_readfirstlane((int)!(pq > 0.0))) {
       st = SL_ST_BREAKDOWN;
       break;
@@ -844,7 +965,6 @@ __device__ void run_item(const SolveArgs& a, const MemberInfo& mi, int m, int kl
       s_g[i] += alT * P[i];
       const T rv = r_g[i] - alT * Q[i];
       r_g[i] = rv;
-      Q[i] = (T)0;
       rn += (double)rv * (double)rv;
     }
     rn = block_sum1(rn, red, 1);
@@ -1012,6 +1132,9 @@ static Layout make_layout(const sl_problem* pb, int max_ns, int M, int NL, int n
   L.gframe = take(sz * (size_t)n_wg * L.gframe_elems);
   L.gz = take(sz * (size_t)n_wg * L.J);
   L.rbuf = take(sz * (size_t)n_wg * L.I_max);
+  L.lt_ptr = take(sizeof(int32_t) * (size_t)M * (L.I_max + 1));
+  L.lt_cap = 4LL * L.n2 * L.slot_cap;
+  L.lt_ent = take((sz == 8 ? 16 : 8) * (size_t)M * (size_t)L.lt_cap);
   L.total = off;
   return L;
 }
@@ -1191,6 +1314,9 @@ int sl_solve_semilinear(const sl_problem* pb, const double* lens, const int32_t*
   A.slot_cap = L.slot_cap;
   A.gz = ws + L.gz;
   A.rbuf = ws + L.rbuf;
+  A.lt_ptr = (int32_t*)(ws + L.lt_ptr);
+  A.lt_ent = ws + L.lt_ent;
+  A.lt_cap = L.lt_cap;
   A.I_max = L.I_max;
   LamList lams{};
   for (int k = 0; k < n_lambda; ++k) lams.v[k] = lambdas[k];
