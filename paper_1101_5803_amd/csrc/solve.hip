@@ -27,6 +27,7 @@
 // passes over the frame (rows, then columns) with (4ck+1) taps plus a small
 // correction for outputs within ck of the image edge.  A PSF that is not
 // rank-1 takes the direct K x K path with an image-space buffer in global memory.
+#include <algorithm>
 #include <climits>
 #include <mutex>
 #include <vector>
@@ -44,7 +45,7 @@ struct alignas(16) MemberInfo {
   int ns, I, M, r0, r1, c0, c1, status;   // M: interleaved table slots (>= mapped pixels)
   long long off;   // start in packed vectors
   int Mtrue;       // pixels with at least one subpixel on the grid
-  int pad;
+  int sell;        // transposed operator stored as sliced-ELL (1) or CSR (0)
 };
 
 // Device constants written by k_setup (one copy per workspace).
@@ -359,20 +360,28 @@ __device__ int pixel_pairs(int t, int ns, int n2, const int32_t* cellp, const T*
   return cnt;
 }
 
-// Node-major (CSR) form of L^T for one member: for every node, the frame
-// offsets of the pixels whose subpixels touch it and the merged weights,
-// sorted by offset so the per-node sum has a fixed order.  cnt: LDS ints (>= I).
+// Node-major form of L^T for one member in sliced-ELL layout (slices of 64
+// consecutive nodes, one per wave): entry j of node i sits at
+// ptr[i/64] + 64 j + i%64, every slice padded to its longest row with entries
+// (offset 0, weight 0) -- offset 0 is a frame halo element, always zero.  A
+// wave's j-th load is then one contiguous 64-entry block.  Entries of a node
+// are sorted by frame offset, so the per-node sum has a fixed order.  Falls
+// back to plain CSR (ptr = row starts) when the padded form exceeds the
+// capacity; returns 1 for sliced-ELL, 0 for CSR.  cnt: LDS ints (>= I + 64).
 template <typename T>
-__device__ void build_transpose(const SolveArgs& a, int m, int ns, int slots, const int* bbox, int* scan, int* cnt,
-                                const int32_t* pix, const int32_t* cellp, const T* fxp, const T* fyp) {
+__device__ int build_transpose(const SolveArgs& a, int m, int ns, int slots, const int* bbox, int* scan, int* cnt,
+                               const int32_t* pix, const int32_t* cellp, const T* fxp, const T* fyp) {
   const int tid = threadIdx.x, n2 = a.n2, I = ns * ns;
   const int halo = 2 * a.ckt;
   const int pitch = (bbox[3] - bbox[2] + 1 + 2 * halo) | 1;
-  int32_t* rp = a.lt_ptr + (long)m * (a.I_max + 1);
+  const int ngroups = (I + 63) / 64;
+  int32_t* rp = a.lt_ptr + (long)m * (a.I_max + 65);
   LtEntry<T>* ent = reinterpret_cast<LtEntry<T>*>(a.lt_ent) + (long)m * a.lt_cap;
   int node[4 * SL_MAX_NSUB * SL_MAX_NSUB];
   double wt[4 * SL_MAX_NSUB * SL_MAX_NSUB];
-  for (int i = tid; i < I; i += blockDim.x) cnt[i] = 0;
+  __shared__ int totals[2];
+  for (int i = tid; i < 64 * ngroups; i += blockDim.x) cnt[i] = 0;
+  if (tid == 0) totals[0] = totals[1] = 0;
   __syncthreads();
   for (int t = tid; t < slots; t += blockDim.x) {
     if (pix[t] < 0) continue;
@@ -380,12 +389,33 @@ __device__ void build_transpose(const SolveArgs& a, int m, int ns, int slots, co
     for (int q = 0; q < np; ++q) atomicAdd(&cnt[node[q]], 1);
   }
   __syncthreads();
-  // exclusive scan of the counts: each thread sums a contiguous chunk
-  const int chunk = (I + blockDim.x - 1) / blockDim.x;
-  const int i0 = min(I, tid * chunk), i1 = min(I, i0 + chunk);
+  // padded size of every slice, and the plain total
+  for (int g = tid; g < ngroups; g += blockDim.x) {
+    int mx = 0, sum = 0;
+    for (int l = 0; l < 64; ++l) {
+      mx = max(mx, cnt[64 * g + l]);
+      sum += cnt[64 * g + l];
+    }
+    atomicAdd(&totals[0], 64 * mx);
+    atomicAdd(&totals[1], sum);
+  }
+  __syncthreads();
+  const int sell = __builtin_amdgcn_readfirstlane((int)((long long)totals[0] <= a.lt_cap));
+  // exclusive scan over units: slices (padded sizes) for sliced-ELL, rows for CSR
+  const int nunits = sell ? ngroups : I;
+  const int chunk = (nunits + blockDim.x - 1) / blockDim.x;
+  const int u0 = min(nunits, tid * chunk), u1 = min(nunits, u0 + chunk);
   int local = 0;
-  for (int i = i0; i < i1; ++i) local += cnt[i];
-  const int lane = tid & 63, wid = tid >> 6, nw = blockDim.x >> 6;
+  for (int u = u0; u < u1; ++u) {
+    if (sell) {
+      int mx = 0;
+      for (int l = 0; l < 64; ++l) mx = max(mx, cnt[64 * u + l]);
+      local += 64 * mx;
+    } else {
+      local += cnt[u];
+    }
+  }
+  const int lane = tid & 63, wid = tid >> 6;
   int incl = local;
   for (int o = 1; o < 64; o <<= 1) {
     const int v = __shfl_up(incl, o, 64);
@@ -396,14 +426,26 @@ __device__ void build_transpose(const SolveArgs& a, int m, int ns, int slots, co
   int before = 0;
   for (int i = 0; i < wid; ++i) before += scan[i];
   int run = before + incl - local;
-  for (int i = i0; i < i1; ++i) {
-    const int c = cnt[i];
-    rp[i] = run;
-    cnt[i] = run;      // becomes the fill cursor
-    run += c;
+  for (int u = u0; u < u1; ++u) {
+    rp[u] = run;
+    if (sell) {
+      int mx = 0;
+      for (int l = 0; l < 64; ++l) mx = max(mx, cnt[64 * u + l]);
+      run += 64 * mx;
+    } else {
+      run += cnt[u];
+    }
   }
-  if (tid == blockDim.x - 1) rp[I] = run;
-  (void)nw;
+  if (tid == blockDim.x - 1) rp[nunits] = run;
+  __syncthreads();
+  // padding: every slot of a slice starts as (0, 0); rows are then filled in
+  if (sell)
+    for (int e = tid; e < rp[ngroups]; e += blockDim.x) {
+      ent[e].off = 0;
+      ent[e].w = (T)0;
+    }
+  __syncthreads();
+  for (int i = tid; i < I; i += blockDim.x) cnt[i] = 0;   // fill cursors
   __syncthreads();
   for (int t = tid; t < slots; t += blockDim.x) {
     const int rc = pix[t];
@@ -411,26 +453,31 @@ __device__ void build_transpose(const SolveArgs& a, int m, int ns, int slots, co
     const int off = ((rc >> 16) - bbox[0] + halo) * pitch + ((rc & 0xFFFF) - bbox[2] + halo);
     const int np = pixel_pairs(t, ns, n2, cellp, fxp, fyp, node, wt);
     for (int q = 0; q < np; ++q) {
-      const int e = atomicAdd(&cnt[node[q]], 1);
+      const int i = node[q];
+      const int j = atomicAdd(&cnt[i], 1);
+      const long e = sell ? (long)rp[i >> 6] + 64L * j + (i & 63) : (long)rp[i] + j;
       ent[e].off = off;
       ent[e].w = (T)wt[q];
     }
   }
   __syncthreads();
-  // fixed summation order: sort every row by frame offset (rows are short)
+  // fixed summation order: insertion-sort every row by frame offset
   for (int i = tid; i < I; i += blockDim.x) {
-    const int e0 = rp[i], e1 = rp[i + 1];
-    for (int e = e0 + 1; e < e1; ++e) {
-      const LtEntry<T> x = ent[e];
-      int f = e - 1;
-      while (f >= e0 && ent[f].off > x.off) {
-        ent[f + 1] = ent[f];
+    const int n = cnt[i];
+    const long base = sell ? (long)rp[i >> 6] + (i & 63) : (long)rp[i];
+    const int step = sell ? 64 : 1;
+    for (int j = 1; j < n; ++j) {
+      const LtEntry<T> x = ent[base + (long)j * step];
+      int f = j - 1;
+      while (f >= 0 && ent[base + (long)f * step].off > x.off) {
+        ent[base + (long)(f + 1) * step] = ent[base + (long)f * step];
         --f;
       }
-      ent[f + 1] = x;
+      ent[base + (long)(f + 1) * step] = x;
     }
   }
   __syncthreads();
+  return sell;
 }
 
 template <typename T>
@@ -558,8 +605,11 @@ __device__ void prep_member(const SolveArgs& a, int m, MemberInfo mi, const doub
   double* bm = a.b + (long)m * a.I_max;
   for (int i = tid; i < I; i += blockDim.x) bm[i] = bacc[i];
   __syncthreads();
-  if (Mtrue > 0) build_transpose<T>(a, m, ns, Mm, bbox, scan, reinterpret_cast<int*>(bacc), pix, cellp, fxp, fyp);
+  int sell = 0;
+  if (Mtrue > 0)
+    sell = build_transpose<T>(a, m, ns, Mm, bbox, scan, reinterpret_cast<int*>(bacc), pix, cellp, fxp, fyp);
   if (tid == 0) {
+    mi.sell = sell;
     mi.M = Mm;
     mi.Mtrue = Mtrue;
     mi.status = Mtrue > 0 ? SL_ST_OK : SL_ST_EMPTY;
@@ -849,7 +899,8 @@ __device__ void run_item(const SolveArgs& a, const MemberInfo& mi, int m, int kl
   const bool sep = a.consts->sep != 0;
   const T inv_n2 = (T)1 / (T)n2;
   const int fo = -r0 * pitch - c0;             // frame offset of image pixel (r, c): r*pitch + c + fo
-  const int32_t* lt_rp = a.lt_ptr + (long)m * (a.I_max + 1);
+  const int32_t* lt_rp = a.lt_ptr + (long)m * (a.I_max + 65);
+  const int sell = __builtin_amdgcn_readfirstlane(mi.sell);
   const LtEntry<T>* lt_e = reinterpret_cast<const LtEntry<T>*>(a.lt_ent) + (long)m * a.lt_cap;
   // dilated region (direct-blur paths): rows/cols within ck of the bbox, inside the image
   const int Dr0 = max(mi.r0 - ck, 0), Dr1 = min(mi.r1 + ck, ny - 1);
@@ -932,14 +983,25 @@ __device__ void run_item(const SolveArgs& a, const MemberInfo& mi, int m, int kl
     {
       int rn_ = r_first, cn_ = c_first;
       for (int i = tid; i < I; i += kNT) {
-        const int e0 = lt_rp[i], e1 = lt_rp[i + 1];
         T acc = 0;
-        int e = e0;
-        for (; e + 1 < e1; e += 2) {
-          const LtEntry<T> x0 = lt_e[e], x1 = lt_e[e + 1];
-          acc += x0.w * F[x0.off] + x1.w * F[x1.off];
+        if (sell) {
+          // sliced-ELL: the wave's 64 nodes read 64 consecutive entries per step
+          const long base = lt_rp[i >> 6] + (i & 63);
+          const int len = (lt_rp[(i >> 6) + 1] - lt_rp[i >> 6]) >> 6;
+          int j = 0;
+          for (; j + 3 < len; j += 4) {
+            const LtEntry<T> x0 = lt_e[base + 64L * j], x1 = lt_e[base + 64L * (j + 1)];
+            const LtEntry<T> x2 = lt_e[base + 64L * (j + 2)], x3 = lt_e[base + 64L * (j + 3)];
+            acc += x0.w * F[x0.off] + x1.w * F[x1.off] + x2.w * F[x2.off] + x3.w * F[x3.off];
+          }
+          for (; j < len; ++j) {
+            const LtEntry<T> x0 = lt_e[base + 64L * j];
+            acc += x0.w * F[x0.off];
+          }
+        } else {
+          const int e0 = lt_rp[i], e1 = lt_rp[i + 1];
+          for (int e = e0; e < e1; ++e) acc += lt_e[e].w * F[lt_e[e].off];
         }
-        if (e < e1) acc += lt_e[e].w * F[lt_e[e].off];
         const T pv = P[i];
         const T qv = acc + lamT * (ident ? pv : hth_node(P, ns, rn_, cn_));
         Q[i] = qv;
@@ -1132,8 +1194,8 @@ static Layout make_layout(const sl_problem* pb, int max_ns, int M, int NL, int n
   L.gframe = take(sz * (size_t)n_wg * L.gframe_elems);
   L.gz = take(sz * (size_t)n_wg * L.J);
   L.rbuf = take(sz * (size_t)n_wg * L.I_max);
-  L.lt_ptr = take(sizeof(int32_t) * (size_t)M * (L.I_max + 1));
-  L.lt_cap = 4LL * L.n2 * L.slot_cap;
+  L.lt_ptr = take(sizeof(int32_t) * (size_t)M * (L.I_max + 65));
+  L.lt_cap = 8LL * L.n2 * L.slot_cap;   // twice the unpadded bound: room for slice padding
   L.lt_ent = take((sz == 8 ? 16 : 8) * (size_t)M * (size_t)L.lt_cap);
   L.total = off;
   return L;
@@ -1206,13 +1268,15 @@ static int launch_solve(SolveArgs& A, const LamList& lams, const Layout& L, hipS
   {
     std::lock_guard<std::mutex> g(mu);
     SL_HIP(hipFuncSetAttribute((const void*)ks, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    const size_t prep_lds = sizeof(double) * L.I_max;
+    // FP64 right-hand-side accumulator, reused for the transposed-operator counts (I + 64 ints)
+    const size_t prep_lds = std::max(sizeof(double) * L.I_max, sizeof(int) * (L.I_max + 64));
     SL_HIP(hipFuncSetAttribute((const void*)k_prep<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)prep_lds));
   }
   hipLaunchKernelGGL(k_setup<T>, dim3(1), dim3(1024), 0, st, A, lams);
   if (int e = check_launch("k_setup")) return e;
-  hipLaunchKernelGGL(k_prep<T>, dim3(A.n_members), dim3(1024), sizeof(double) * L.I_max, st, A);
+  hipLaunchKernelGGL(k_prep<T>, dim3(A.n_members), dim3(1024),
+                     std::max(sizeof(double) * L.I_max, sizeof(int) * (L.I_max + 64)), st, A);
   if (int e = check_launch("k_prep")) return e;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   {
