@@ -59,7 +59,8 @@ struct alignas(16) Consts {
 };
 
 struct Layout {
-  size_t consts, lam, taps_d, taps_f, minfo, queues, pix, cell, fx, fy, b, s_all, gframe, gz, rbuf, lt_ptr, lt_ent,
+  size_t consts, lam, taps_d, taps_f, minfo, queues, pix, cell, fx, fy, b, s_all, gframe, gz, rbuf, lt_ptr, lt_perm,
+      lt_ent,
       total;
   long long lt_cap;
   int qcap, n_wg, I_max, J, n2, gframe_elems, slot_cap;
@@ -129,7 +130,8 @@ struct SolveArgs {
   void* gframe;
   void* gz;
   void* rbuf;       // per-block CG residual
-  int32_t* lt_ptr;  // [member][I_max + 1] row starts of the transposed operator
+  int32_t* lt_ptr;  // [member][I_max + 65] slice (or row) starts of the transposed operator
+  int32_t* lt_perm; // [member][I_max] nodes in slice order, packed (row << 16 | col)
   void* lt_ent;     // [member][lt_cap] LtEntry<T>
   long long lt_cap; // entries per member
   int I_max;
@@ -360,27 +362,43 @@ __device__ int pixel_pairs(int t, int ns, int n2, const int32_t* cellp, const T*
   return cnt;
 }
 
-// Node-major form of L^T for one member in sliced-ELL layout (slices of 64
-// consecutive nodes, one per wave): entry j of node i sits at
-// ptr[i/64] + 64 j + i%64, every slice padded to its longest row with entries
-// (offset 0, weight 0) -- offset 0 is a frame halo element, always zero.  A
-// wave's j-th load is then one contiguous 64-entry block.  Entries of a node
-// are sorted by frame offset, so the per-node sum has a fixed order.  Falls
-// back to plain CSR (ptr = row starts) when the padded form exceeds the
-// capacity; returns 1 for sliced-ELL, 0 for CSR.  cnt: LDS ints (>= I + 64).
+// Quarter-octave bucket of a row length (0 for empty rows): rows in one
+// bucket differ by less than 19%.
+__device__ __forceinline__ int len_bucket(int c) {
+  if (c <= 0) return 0;
+  const int msb = 31 - __clz(c);
+  const int frac = msb >= 2 ? (c >> (msb - 2)) & 3 : (c << (2 - msb)) & 3;
+  return 4 * msb + frac + 1;
+}
+
+// Node-major form of L^T for one member, sliced-ELL with rows sorted by length
+// (SELL-C-sigma with C = 64, one slice per wave): nodes are ordered by
+// descending length bucket (stable in node index) into perm[] = packed
+// (row << 16 | col); entry j of the node at position p sits at
+// ptr[p/64] + 64 j + p%64, every slice padded to its longest row with
+// entries (offset 0, weight 0) -- offset 0 is a frame halo element, always
+// zero.  Entries of a node are sorted by frame offset, so the per-node sum
+// has a fixed order.  Falls back to plain CSR in node order (ptr = row
+// starts) when the padded form exceeds the capacity; returns 1 for
+// sliced-ELL, 0 for CSR.  lds: LDS ints (>= 2 I + 64 + 128).
 template <typename T>
-__device__ int build_transpose(const SolveArgs& a, int m, int ns, int slots, const int* bbox, int* scan, int* cnt,
+__device__ int build_transpose(const SolveArgs& a, int m, int ns, int slots, const int* bbox, int* scan, int* lds,
                                const int32_t* pix, const int32_t* cellp, const T* fxp, const T* fyp) {
   const int tid = threadIdx.x, n2 = a.n2, I = ns * ns;
   const int halo = 2 * a.ckt;
   const int pitch = (bbox[3] - bbox[2] + 1 + 2 * halo) | 1;
   const int ngroups = (I + 63) / 64;
+  int* cnt = lds;                       // [I + 64] row lengths, later fill cursors
+  int* ipos = lds + I + 64;             // [I] sorted position of every node
+  int* hist = ipos + I;                 // [128] bucket histogram
   int32_t* rp = a.lt_ptr + (long)m * (a.I_max + 65);
+  int32_t* perm = a.lt_perm + (long)m * a.I_max;
   LtEntry<T>* ent = reinterpret_cast<LtEntry<T>*>(a.lt_ent) + (long)m * a.lt_cap;
   int node[4 * SL_MAX_NSUB * SL_MAX_NSUB];
   double wt[4 * SL_MAX_NSUB * SL_MAX_NSUB];
   __shared__ int totals[2];
-  for (int i = tid; i < 64 * ngroups; i += blockDim.x) cnt[i] = 0;
+  for (int i = tid; i < I + 64; i += blockDim.x) cnt[i] = 0;
+  for (int i = tid; i < 128; i += blockDim.x) hist[i] = 0;
   if (tid == 0) totals[0] = totals[1] = 0;
   __syncthreads();
   for (int t = tid; t < slots; t += blockDim.x) {
@@ -389,15 +407,49 @@ __device__ int build_transpose(const SolveArgs& a, int m, int ns, int slots, con
     for (int q = 0; q < np; ++q) atomicAdd(&cnt[node[q]], 1);
   }
   __syncthreads();
-  // padded size of every slice, and the plain total
+  for (int i = tid; i < I; i += blockDim.x) atomicAdd(&hist[len_bucket(cnt[i])], 1);
+  __syncthreads();
+  if (tid == 0) {   // descending buckets -> start positions
+    int run = 0;
+    for (int b = 127; b >= 0; --b) {
+      const int c = hist[b];
+      hist[b] = run;
+      run += c;
+    }
+  }
+  __syncthreads();
+  // stable placement in node order: one wave per bucket pass keeps it deterministic
+  if (tid < 64) {
+    for (int i0 = 0; i0 < I; i0 += 64) {
+      const int i = i0 + tid;
+      const int b = i < I ? len_bucket(cnt[i]) : -1;
+      // rank of lane among lower lanes with the same bucket
+      int before = 0;
+      for (int l = 0; l < 64; ++l) {
+        const int bl = __shfl(b, l, 64);
+        if (l < tid && bl == b) ++before;
+      }
+      if (i < I) {
+        const int p = hist[b] + before;
+        ipos[i] = p;
+        perm[p] = ((i / ns) << 16) | (i % ns);
+      }
+      // advance every bucket by its count in this group of 64 (lanes hold distinct buckets)
+      for (int l = 0; l < 64; ++l) {
+        const int bl = __shfl(b, l, 64);
+        if (tid == 0 && bl >= 0) hist[bl] += 1;
+      }
+    }
+  }
+  __syncthreads();
+  // slice lengths (rows sorted by length: little padding) and the plain total
   for (int g = tid; g < ngroups; g += blockDim.x) {
-    int mx = 0, sum = 0;
-    for (int l = 0; l < 64; ++l) {
-      mx = max(mx, cnt[64 * g + l]);
-      sum += cnt[64 * g + l];
+    int mx = 0;
+    for (int l = 0; l < 64 && 64 * g + l < I; ++l) {
+      const int i = (perm[64 * g + l] >> 16) * ns + (perm[64 * g + l] & 0xFFFF);
+      mx = max(mx, cnt[i]);
     }
     atomicAdd(&totals[0], 64 * mx);
-    atomicAdd(&totals[1], sum);
   }
   __syncthreads();
   const int sell = __builtin_amdgcn_readfirstlane((int)((long long)totals[0] <= a.lt_cap));
@@ -405,16 +457,17 @@ __device__ int build_transpose(const SolveArgs& a, int m, int ns, int slots, con
   const int nunits = sell ? ngroups : I;
   const int chunk = (nunits + blockDim.x - 1) / blockDim.x;
   const int u0 = min(nunits, tid * chunk), u1 = min(nunits, u0 + chunk);
-  int local = 0;
-  for (int u = u0; u < u1; ++u) {
-    if (sell) {
-      int mx = 0;
-      for (int l = 0; l < 64; ++l) mx = max(mx, cnt[64 * u + l]);
-      local += 64 * mx;
-    } else {
-      local += cnt[u];
+  auto unit_size = [&](int u) {
+    if (!sell) return cnt[u];
+    int mx = 0;
+    for (int l = 0; l < 64 && 64 * u + l < I; ++l) {
+      const int i = (perm[64 * u + l] >> 16) * ns + (perm[64 * u + l] & 0xFFFF);
+      mx = max(mx, cnt[i]);
     }
-  }
+    return 64 * mx;
+  };
+  int local = 0;
+  for (int u = u0; u < u1; ++u) local += unit_size(u);
   const int lane = tid & 63, wid = tid >> 6;
   int incl = local;
   for (int o = 1; o < 64; o <<= 1) {
@@ -428,23 +481,15 @@ __device__ int build_transpose(const SolveArgs& a, int m, int ns, int slots, con
   int run = before + incl - local;
   for (int u = u0; u < u1; ++u) {
     rp[u] = run;
-    if (sell) {
-      int mx = 0;
-      for (int l = 0; l < 64; ++l) mx = max(mx, cnt[64 * u + l]);
-      run += 64 * mx;
-    } else {
-      run += cnt[u];
-    }
+    run += unit_size(u);
   }
   if (tid == blockDim.x - 1) rp[nunits] = run;
   __syncthreads();
-  // padding: every slot of a slice starts as (0, 0); rows are then filled in
   if (sell)
     for (int e = tid; e < rp[ngroups]; e += blockDim.x) {
       ent[e].off = 0;
       ent[e].w = (T)0;
     }
-  __syncthreads();
   for (int i = tid; i < I; i += blockDim.x) cnt[i] = 0;   // fill cursors
   __syncthreads();
   for (int t = tid; t < slots; t += blockDim.x) {
@@ -455,7 +500,8 @@ __device__ int build_transpose(const SolveArgs& a, int m, int ns, int slots, con
     for (int q = 0; q < np; ++q) {
       const int i = node[q];
       const int j = atomicAdd(&cnt[i], 1);
-      const long e = sell ? (long)rp[i >> 6] + 64L * j + (i & 63) : (long)rp[i] + j;
+      const int p = ipos[i];
+      const long e = sell ? (long)rp[p >> 6] + 64L * j + (p & 63) : (long)rp[i] + j;
       ent[e].off = off;
       ent[e].w = (T)wt[q];
     }
@@ -464,7 +510,8 @@ __device__ int build_transpose(const SolveArgs& a, int m, int ns, int slots, con
   // fixed summation order: insertion-sort every row by frame offset
   for (int i = tid; i < I; i += blockDim.x) {
     const int n = cnt[i];
-    const long base = sell ? (long)rp[i >> 6] + (i & 63) : (long)rp[i];
+    const int p = ipos[i];
+    const long base = sell ? (long)rp[p >> 6] + (p & 63) : (long)rp[i];
     const int step = sell ? 64 : 1;
     for (int j = 1; j < n; ++j) {
       const LtEntry<T> x = ent[base + (long)j * step];
@@ -919,9 +966,6 @@ __device__ void run_item(const SolveArgs& a, const MemberInfo& mi, int m, int kl
     r_g[i] = bv;
     rr += (double)bv * (double)bv;
   }
-  // row/column of this thread's first node, and the per-stride step
-  const int r_first = tid / ns, c_first = tid - (tid / ns) * ns;
-  const int r_step = kNT / ns, c_step = kNT - (kNT / ns) * ns;
   rr = block_sum1(rr, red, 0);
   const double stop2 = a.tol * a.tol * rr;
   int st = SL_ST_MAXIT, it = 0;
@@ -981,13 +1025,18 @@ __device__ void run_item(const SolveArgs& a, const MemberInfo& mi, int m, int kl
     // (no atomics, fixed order), stored in Q; <p, q>
     double pq = 0.0;
     {
-      int rn_ = r_first, cn_ = c_first;
-      for (int i = tid; i < I; i += kNT) {
+      const int32_t* perm = a.lt_perm + (long)m * a.I_max;
+      for (int idx = tid; idx < I; idx += kNT) {
         T acc = 0;
+        int i, rn_, cn_;
         if (sell) {
-          // sliced-ELL: the wave's 64 nodes read 64 consecutive entries per step
-          const long base = lt_rp[i >> 6] + (i & 63);
-          const int len = (lt_rp[(i >> 6) + 1] - lt_rp[i >> 6]) >> 6;
+          // sliced-ELL in length-sorted node order: one contiguous 64-entry block per step
+          const int pk = perm[idx];
+          rn_ = pk >> 16;
+          cn_ = pk & 0xFFFF;
+          i = rn_ * ns + cn_;
+          const long base = lt_rp[idx >> 6] + (idx & 63);
+          const int len = (lt_rp[(idx >> 6) + 1] - lt_rp[idx >> 6]) >> 6;
           int j = 0;
           for (; j + 3 < len; j += 4) {
             const LtEntry<T> x0 = lt_e[base + 64L * j], x1 = lt_e[base + 64L * (j + 1)];
@@ -999,6 +1048,9 @@ __device__ void run_item(const SolveArgs& a, const MemberInfo& mi, int m, int kl
             acc += x0.w * F[x0.off];
           }
         } else {
+          i = idx;
+          rn_ = i / ns;
+          cn_ = i - rn_ * ns;
           const int e0 = lt_rp[i], e1 = lt_rp[i + 1];
           for (int e = e0; e < e1; ++e) acc += lt_e[e].w * F[lt_e[e].off];
         }
@@ -1006,12 +1058,6 @@ __device__ void run_item(const SolveArgs& a, const MemberInfo& mi, int m, int kl
         const T qv = acc + lamT * (ident ? pv : hth_node(P, ns, rn_, cn_));
         Q[i] = qv;
         pq += (double)pv * (double)qv;
-        rn_ += r_step;
-        cn_ += c_step;
-        if (cn_ >= ns) {
-          cn_ -= ns;
-          ++rn_;
-        }
       }
     }
     pq = block_sum1(pq, red, 0);
@@ -1195,6 +1241,7 @@ static Layout make_layout(const sl_problem* pb, int max_ns, int M, int NL, int n
   L.gz = take(sz * (size_t)n_wg * L.J);
   L.rbuf = take(sz * (size_t)n_wg * L.I_max);
   L.lt_ptr = take(sizeof(int32_t) * (size_t)M * (L.I_max + 65));
+  L.lt_perm = take(sizeof(int32_t) * (size_t)M * L.I_max);
   L.lt_cap = 8LL * L.n2 * L.slot_cap;   // twice the unpadded bound: room for slice padding
   L.lt_ent = take((sz == 8 ? 16 : 8) * (size_t)M * (size_t)L.lt_cap);
   L.total = off;
@@ -1268,15 +1315,15 @@ static int launch_solve(SolveArgs& A, const LamList& lams, const Layout& L, hipS
   {
     std::lock_guard<std::mutex> g(mu);
     SL_HIP(hipFuncSetAttribute((const void*)ks, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    // FP64 right-hand-side accumulator, reused for the transposed-operator counts (I + 64 ints)
-    const size_t prep_lds = std::max(sizeof(double) * L.I_max, sizeof(int) * (L.I_max + 64));
+    // FP64 right-hand-side accumulator, reused by the transposed-operator build (2 I + 192 ints)
+    const size_t prep_lds = std::max(sizeof(double) * L.I_max, sizeof(int) * (2 * L.I_max + 192));
     SL_HIP(hipFuncSetAttribute((const void*)k_prep<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)prep_lds));
   }
   hipLaunchKernelGGL(k_setup<T>, dim3(1), dim3(1024), 0, st, A, lams);
   if (int e = check_launch("k_setup")) return e;
   hipLaunchKernelGGL(k_prep<T>, dim3(A.n_members), dim3(1024),
-                     std::max(sizeof(double) * L.I_max, sizeof(int) * (L.I_max + 64)), st, A);
+                     std::max(sizeof(double) * L.I_max, sizeof(int) * (2 * L.I_max + 192)), st, A);
   if (int e = check_launch("k_prep")) return e;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   {
@@ -1379,6 +1426,7 @@ int sl_solve_semilinear(const sl_problem* pb, const double* lens, const int32_t*
   A.gz = ws + L.gz;
   A.rbuf = ws + L.rbuf;
   A.lt_ptr = (int32_t*)(ws + L.lt_ptr);
+  A.lt_perm = (int32_t*)(ws + L.lt_perm);
   A.lt_ent = ws + L.lt_ent;
   A.lt_cap = L.lt_cap;
   A.I_max = L.I_max;
