@@ -42,6 +42,9 @@ def parse():
     ap.add_argument("--plain-members", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-members", type=int, default=0, help="oracle sample size (default: cores used)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="also run one device-to-device copy of MIB MiB (a known-size kernel that scales "
+                         "hardware byte counters)")
     return ap.parse_args()
 
 
@@ -110,6 +113,13 @@ def main():
     def step():
         solver.solve_semilinear(lens_d, ns_d, w.lambdas, tol=w.tol, maxit=4000, max_ns=max_ns, out=out)
 
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     print(f"[bench] warmup {args.warmup} step(s) of {M} members", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         step()
@@ -139,6 +149,8 @@ def main():
             "table_GBps": round(gbs, 1), "table_frac_of_hbm": round(gbs / PEAK_HBM_GBS, 4)}
     # plain: the same library, one member per call
     print(f"[bench] plain: {args.plain_members} members one at a time", file=sys.stderr, flush=True)
+    if args.plain_members <= 0:
+        args.plain_members = 1
     plain = sl.Solver(torch.tensor(z["d"], device=dev), float(z["sigma"]), torch.tensor(z["psf"], device=dev),
                       grid, w.half_width, reg=w.reg, dtype=torch.float32)
     pout = plain.alloc_result(max_ns * max_ns, 1, len(w.lambdas))
