@@ -38,7 +38,8 @@ namespace sl {
 
 constexpr int kNT = 1024;     // threads per solve block
 constexpr int kWaves = kNT / kWave;
-constexpr int kSegR = 4;       // outputs per lane in a banded pass
+constexpr int kSegR = 4;
+constexpr int kUpd = 4;   // CG vector-update chunk (nodes per thread)       // outputs per lane in a banded pass
 constexpr int kMaxCK = 31;
 
 struct alignas(16) MemberInfo {
@@ -1068,16 +1069,54 @@ __device__ void run_item(const SolveArgs& a, const MemberInfo& mi, int m, int kl
       break;
     }
     const T alT = (T)(rr / pq);
+    // Updates in chunks of kUpd nodes per thread: every global load of a chunk
+    // is issued before the first use, and the updated residual stays in
+    // registers for the direction update when the chunk covers all of I.
     double rn = 0.0;
-    for (int i = tid; i < I; i += kNT) {
-      s_g[i] += alT * P[i];
-      const T rv = r_g[i] - alT * Q[i];
-      r_g[i] = rv;
-      rn += (double)rv * (double)rv;
+    T rk[kUpd];
+    for (int i0 = tid; i0 < I; i0 += kUpd * kNT) {
+      T sk[kUpd];
+#pragma unroll
+      for (int k = 0; k < kUpd; ++k) {
+        const int i = i0 + k * kNT;
+        if (i < I) {
+          sk[k] = s_g[i];
+          rk[k] = r_g[i];
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < kUpd; ++k) {
+        const int i = i0 + k * kNT;
+        if (i < I) {
+          s_g[i] = sk[k] + alT * P[i];
+          rk[k] -= alT * Q[i];
+          r_g[i] = rk[k];
+          rn += (double)rk[k] * (double)rk[k];
+        }
+      }
     }
     rn = block_sum1(rn, red, 1);
     const T beta = (T)(rn / rr);
-    for (int i = tid; i < I; i += kNT) P[i] = r_g[i] + beta * P[i];
+    if (I <= kUpd * kNT) {
+#pragma unroll
+      for (int k = 0; k < kUpd; ++k) {
+        const int i = tid + k * kNT;
+        if (i < I) P[i] = rk[k] + beta * P[i];
+      }
+    } else {
+      for (int i0 = tid; i0 < I; i0 += kUpd * kNT) {
+#pragma unroll
+        for (int k = 0; k < kUpd; ++k) {
+          const int i = i0 + k * kNT;
+          if (i < I) rk[k] = r_g[i];
+        }
+#pragma unroll
+        for (int k = 0; k < kUpd; ++k) {
+          const int i = i0 + k * kNT;
+          if (i < I) P[i] = rk[k] + beta * P[i];
+        }
+      }
+    }
     rr = rn;
     __syncthreads();
   }
