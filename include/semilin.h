@@ -210,36 +210,58 @@ int sl_profile_solve_ms(double* ms_total, int32_t* launches);
 int sl_lcurve_corner(const double* reg, const double* chi2, int n, int32_t* k_star, double* kappa);
 
 /* ---------------------------------------------------------------------------
- * Surrogate MLP 7 -> 256 -> 256 -> 1 with GELU (erf form), BF16 weight copies
- * and FP32 accumulation (not in the paper: a learned pre-screen of offspring).
+ * Surrogate MLP 7 -> 256 -> 256 -> 1 with GELU in its erf form,
+ * gelu(z) = z Phi(z).  It is not part of the paper's method: a learned
+ * pre-screen that predicts ln chi^2 at the L-curve corner from the seven lens
+ * parameters, so that a genetic search (Appendix A.1) can send only its most
+ * promising offspring to the full solve.
+ *
  * Parameters live in one device float buffer of SL_MLP_NPARAM floats in the
  * order W0[7][256], b0[256], W1[256][256], b1[256], W2[256][1], b2[1]
- * (W[in][out]).  Adam moments m, v use the same layout.
+ * (W[in][out], row-major).  Adam moments m, v use the same layout.
+ * Numerics: FP32 master weights.  Products take BF16 copies (round to nearest
+ * even) of the weights W0, W1, W2 and of every layer input (x, h1, h2) and
+ * accumulate in FP32; biases stay FP32.  The forward 256 x 256 product uses
+ * the BF16 matrix cores; the backward products keep the gradient signals in
+ * FP32 and treat the BF16 rounding of an activation as the identity.
+ * Every sum has a fixed order: results are bitwise reproducible.
+ * All calls are asynchronous on `stream`; argument errors return SL_EINVAL
+ * before any launch.
  * ------------------------------------------------------------------------- */
 #define SL_MLP_IN 7
 #define SL_MLP_HID 256
 #define SL_MLP_NPARAM (7 * 256 + 256 + 256 * 256 + 256 + 256 + 1)
+#define SL_MLP_MAX_BATCH (1 << 20)
 
 /*
- * Workspace floats for a batch (activations, gradients, BF16 weight copies).
+ * Bytes of device workspace that a call with this batch size needs (BF16
+ * and FP32 transposed copies of W1, activations, GELU derivatives and partial
+ * sums of the training step).  Returns 0, with sl_last_error set, for a
+ * batch outside [0, SL_MLP_MAX_BATCH].  The caller allocates it; calls that
+ * share a workspace must not overlap in time.
  */
 size_t sl_mlp_workspace_size(int batch);
 
 /*
- * Forward pass: y[b] = MLP(x[b]) for b < batch.  x: device float[batch*7];
- * y: device float[batch].  Weights are rounded to BF16 and hidden
- * activations are rounded to BF16 before each matrix product; sums are FP32.
+ * Forward pass: y[b] = MLP(x[b]) for 0 <= b < batch (1 <= batch <=
+ * SL_MLP_MAX_BATCH).  params: device float[SL_MLP_NPARAM]; x: device
+ * float[batch][7]; y: device float[batch]; workspace: device buffer of at
+ * least sl_mlp_workspace_size(batch) bytes (256-byte aligned).
  */
 int sl_mlp_forward(const float* params, const float* x, int batch, float* y, void* workspace,
                    void* stream);
 
 /*
- * One Adam step on the mean squared error (1/B) sum (y_hat - y)^2:
- * forward, backward (same BF16 roundings), then
- * m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2; p -= lr mhat / (sqrt(vhat) + eps)
- * with bias corrections for step number t (>= 1).  grads_out (nullable):
- * device float[SL_MLP_NPARAM] receives the gradient; loss_out (nullable):
- * device float[1] receives the batch loss.
+ * One Adam step on the mean squared error L = (1/B) sum_b (y_hat_b - y_b)^2:
+ * forward, backward (same BF16 roundings), then with g = dL/dparams
+ *   m = 0.9 m + 0.1 g;  v = 0.999 v + 0.001 g^2;
+ *   p -= lr (m / (1 - 0.9^t)) / (sqrt(v / (1 - 0.999^t)) + 1e-8)
+ * for step number t >= 1 and lr > 0.  params, adam_m, adam_v: device
+ * float[SL_MLP_NPARAM], updated in place; x: device float[batch][7]; y:
+ * device float[batch] targets.  grads_out (nullable): device
+ * float[SL_MLP_NPARAM] receives g; loss_out (nullable): device float[1]
+ * receives L of the batch before the update.  workspace as for
+ * sl_mlp_forward.
  */
 int sl_mlp_train_step(float* params, float* adam_m, float* adam_v, const float* x, const float* y,
                       int batch, float lr, int t, float* grads_out, float* loss_out,

@@ -4,9 +4,10 @@ The compute lives in libsemilin.so (hand-written gfx950 HIP behind a C ABI,
 declared in include/semilin.h); this package is its thin Python binding.
 """
 from . import _lib  # noqa: F401
-from .ops import (Grid, Solver, apply_B, apply_BT, apply_HtH, apply_L, apply_LT, profile_enable,  # noqa: F401
-                  profile_solve_ms,
-                  lcurve_corner, lens_trace)
+from .ops import (Grid, Solver, apply_B, apply_BT, apply_HtH, apply_L, apply_LT, lcurve_corner,  # noqa: F401
+                  lens_trace, mlp_forward, mlp_pack, mlp_train_step, mlp_unpack, profile_enable,
+                  profile_solve_ms)
 
 __all__ = ["Grid", "Solver", "apply_B", "apply_BT", "apply_HtH", "apply_L", "apply_LT", "lcurve_corner",
-           "lens_trace"]
+           "lens_trace", "mlp_forward", "mlp_pack", "mlp_train_step", "mlp_unpack", "profile_enable",
+           "profile_solve_ms"]

@@ -214,3 +214,79 @@ class Solver:
                                             ws.numel(), ctypes.byref(res), L.stream_handle()),
                 "sl_solve_semilinear")
         return out
+
+
+# ---------------------------------------------------------------- surrogate MLP
+MLP_SHAPES = [((7, 256), (256,)), ((256, 256), (256,)), ((256, 1), (1,))]
+_mlp_ws = {}
+
+
+def mlp_pack(weights, device=None) -> torch.Tensor:
+    """[(W0, b0), (W1, b1), (W2, b2)] (W[in][out]) -> packed FP32 parameter vector."""
+    parts = []
+    for (W, b), (sw, sb) in zip(weights, MLP_SHAPES):
+        W = torch.as_tensor(np.asarray(W, dtype=np.float32)).reshape(sw)
+        b = torch.as_tensor(np.asarray(b, dtype=np.float32)).reshape(sb)
+        parts += [W.reshape(-1), b.reshape(-1)]
+    v = torch.cat(parts)
+    assert v.numel() == L.MLP_NPARAM
+    return v.to(device) if device is not None else v
+
+
+def mlp_unpack(vec) -> list:
+    """Packed parameter vector -> [(W0, b0), (W1, b1), (W2, b2)] as FP64 numpy arrays."""
+    v = vec.detach().cpu().to(torch.float64).numpy() if isinstance(vec, torch.Tensor) else np.asarray(vec)
+    out, o = [], 0
+    for sw, sb in MLP_SHAPES:
+        nw, nb = sw[0] * sw[1], sb[0]
+        out.append((v[o:o + nw].reshape(sw), v[o + nw:o + nw + nb]))
+        o += nw + nb
+    return out
+
+
+def _mlp_workspace(batch: int, device) -> torch.Tensor:
+    need = int(L.lib().sl_mlp_workspace_size(int(batch)))
+    if need == 0:
+        raise L.SemilinError(L.lib().sl_last_error().decode())
+    key = str(device)
+    ws = _mlp_ws.get(key)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=device)
+        _mlp_ws[key] = ws
+    return ws
+
+
+def _mlp_check(params, x):
+    _dev_check(params, x)
+    if params.dtype != torch.float32 or params.numel() != L.MLP_NPARAM or not params.is_contiguous():
+        raise L.SemilinError(f"params must be a contiguous float32 vector of {L.MLP_NPARAM}")
+    if x.dtype != torch.float32 or x.dim() != 2 or x.shape[1] != 7:
+        raise L.SemilinError("x must be float32 of shape (batch, 7)")
+
+
+def mlp_forward(params: torch.Tensor, x: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Surrogate predictions y (batch,) FP32 for inputs x (batch, 7)."""
+    _mlp_check(params, x)
+    x = x.contiguous()
+    B = x.shape[0]
+    y = out if out is not None else torch.empty(B, dtype=torch.float32, device=x.device)
+    ws = _mlp_workspace(B, x.device)
+    L.check(L.lib().sl_mlp_forward(L.ptr(params), L.ptr(x), B, L.ptr(y), L.ptr(ws), L.stream_handle()),
+            "sl_mlp_forward")
+    return y
+
+
+def mlp_train_step(params: torch.Tensor, m: torch.Tensor, v: torch.Tensor, x: torch.Tensor, y: torch.Tensor,
+                   lr: float, t: int, grads: torch.Tensor | None = None, loss: torch.Tensor | None = None) -> None:
+    """One in-place Adam step of params (and moments m, v) on the batch's MSE."""
+    _mlp_check(params, x)
+    _dev_check(m, v, y)
+    x = x.contiguous()
+    y = y.to(torch.float32).contiguous()
+    B = x.shape[0]
+    if y.numel() != B:
+        raise L.SemilinError("y must hold one target per row of x")
+    ws = _mlp_workspace(B, x.device)
+    L.check(L.lib().sl_mlp_train_step(L.ptr(params), L.ptr(m), L.ptr(v), L.ptr(x), L.ptr(y), B, float(lr), int(t),
+                                      L.ptr(grads), L.ptr(loss), L.ptr(ws), L.stream_handle()),
+            "sl_mlp_train_step")
