@@ -1,0 +1,297 @@
+"""Genetic search over the seven lens parameters, with the batched solve as fitness.
+
+The outer loop of the method (Sec. 3.1.1 and App. A.1): a real-valued genetic
+algorithm proposes lens parameter sets and the semilinear solve scores each
+by chi^2 at its L-curve corner (Sec. 2.6).  This module is host logic in
+FP64; every fitness evaluation is one batched call of the device solve, and
+the optional surrogate runs on the device MLP kernels.
+
+One generation of the simplified Ferret GA:
+  * duplicate the population; each copy moves towards a partner by a fraction
+    |xi| * XOver.strength of the distance (X-type crossover, probability 1);
+  * each gene mutates with probability PMutate by a Gaussian step of
+    mutation.scale (genes live in the unit box: the prior box mapped to
+    [0, 1]; the two angle genes wrap, the others are clipped);
+  * binary tournament: modified individual perm[i] meets unmodified
+    individual i and replaces it only when its fitness is strictly lower.
+Linkage learning, niching, adaptive control and islands are not modelled.
+All random numbers are inputs (a dict of one generation's draws).
+
+Surrogate screening (not in the paper): each parent proposes `fanout`
+candidates; the device MLP predicts ln chi^2 of every candidate; only the
+`pop` candidates with the lowest prediction go to the full solve and the
+tournament.  Every full solve joins the surrogate's training set.
+"""
+from __future__ import annotations
+
+import dataclasses
+import json
+import math
+
+import numpy as np
+import torch
+
+from . import ops
+
+PERIODIC_GENES = (2, 4)   # position angle of the lens and of the shear
+
+
+@dataclasses.dataclass(frozen=True)
+class GAConfig:
+    xover_strength: float = 0.25
+    pmutate: float = 0.05
+    mutation_scale: float = 0.25
+
+    @classmethod
+    def from_json(cls, path: str) -> "GAConfig":
+        """Ferret strategy parameters from a JSON file with Ferret's key names."""
+        with open(path) as f:
+            d = json.load(f)
+        return cls(xover_strength=float(d.get("XOver.strength", 0.25)), pmutate=float(d.get("mutation.PMutate", 0.05)),
+                   mutation_scale=float(d.get("mutation.scale", 0.25)))
+
+
+@dataclasses.dataclass(frozen=True)
+class Box:
+    """Prior box: unit genes u map to lo + u (hi - lo)."""
+    lo: np.ndarray
+    hi: np.ndarray
+
+    def to_phys(self, u: np.ndarray) -> np.ndarray:
+        return self.lo + np.asarray(u, dtype=np.float64) * (self.hi - self.lo)
+
+    def to_unit(self, p: np.ndarray) -> np.ndarray:
+        return (np.asarray(p, dtype=np.float64) - self.lo) / (self.hi - self.lo)
+
+
+def make_offspring(X: np.ndarray, parent: np.ndarray, partner: np.ndarray, xi: np.ndarray, mut_u: np.ndarray,
+                   mut_z: np.ndarray, cfg: GAConfig) -> np.ndarray:
+    """Crossover + mutation of copies of X[parent] (one row per candidate)."""
+    base = X[parent]
+    step = (np.abs(xi) * cfg.xover_strength)[:, None]
+    Y = base + step * (X[partner] - base)
+    Y = Y + np.where(mut_u < cfg.pmutate, cfg.mutation_scale * mut_z, 0.0)
+    for g in range(X.shape[1]):
+        Y[:, g] = np.mod(Y[:, g], 1.0) if g in PERIODIC_GENES else np.clip(Y[:, g], 0.0, 1.0)
+    return Y
+
+
+def tournament(X, fX, Y, fY, perm):
+    """Candidate perm[i] against incumbent i; the candidate wins only when strictly better."""
+    win = fY[perm] < fX
+    return np.where(win[:, None], Y[perm], X), np.where(win, fY[perm], fX)
+
+
+class SolverFitness:
+    """chi^2 at the L-curve corner of lens parameter sets, from one batched device solve.
+
+    Every member uses the same source grid side `ns`.  A member whose solve
+    or corner is not valid (no mapped pixel, invalid parameters, degenerate
+    L-curve) gets fitness +inf.
+    """
+
+    def __init__(self, solver: ops.Solver, box: Box, ns: int, lambdas, tol: float = 1e-7, maxit: int = 4000):
+        self.solver, self.box, self.ns = solver, box, int(ns)
+        self.lambdas = [float(x) for x in lambdas]
+        self.tol, self.maxit = float(tol), int(maxit)
+        self.evals = 0
+        self._out = None
+        self._cap = 0
+
+    def __call__(self, U: np.ndarray) -> np.ndarray:
+        U = np.asarray(U, dtype=np.float64)
+        n = U.shape[0]
+        dev = self.solver.device
+        if n > self._cap:
+            self._cap = n
+            self._out = self.solver.alloc_result(n * self.ns * self.ns, n, len(self.lambdas))
+        out = {k: v for k, v in self._out.items()}
+        lens = torch.tensor(self.box.to_phys(U), dtype=torch.float64, device=dev)
+        ns = torch.full((n,), self.ns, dtype=torch.int32, device=dev)
+        res = self.solver.solve_semilinear(lens, ns, self.lambdas, tol=self.tol, maxit=self.maxit, max_ns=self.ns,
+                                           out=out)
+        chi2 = res["chi2"][:n].cpu().numpy()
+        k = res["k_star"][:n].cpu().numpy()
+        cs = res["corner_status"][:n].cpu().numpy()
+        self.evals += n
+        f = np.full(n, np.inf)
+        ok = (k >= 0) & (cs == 0)
+        f[ok] = chi2[np.nonzero(ok)[0], k[ok]]
+        return f
+
+
+class Surrogate:
+    """Device MLP predicting ln chi^2 from unit genes (inputs 2u - 1, standardised target)."""
+
+    def __init__(self, device, seed: int = 0, lr: float = 1e-3, batch: int = 1024):
+        rng = np.random.default_rng(seed)
+        w = []
+        for a, b in ((7, 256), (256, 256), (256, 1)):
+            lim = math.sqrt(6.0 / a)
+            w.append((rng.uniform(-lim, lim, size=(a, b)), np.zeros(b)))
+        self.device = device
+        self.params = ops.mlp_pack(w, device)
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.t = 0
+        self.lr, self.batch = float(lr), int(batch)
+        self.mu, self.sd = 0.0, 1.0
+
+    def predict(self, U: np.ndarray) -> np.ndarray:
+        x = torch.tensor(2.0 * np.asarray(U) - 1.0, dtype=torch.float32, device=self.device)
+        y = ops.mlp_forward(self.params, x).cpu().numpy().astype(np.float64)
+        return self.mu + self.sd * y
+
+    def train(self, U: np.ndarray, lnf: np.ndarray, steps: int, seed: int) -> float:
+        """`steps` Adam steps on minibatches drawn (seeded) from (U, ln f); returns the last batch loss."""
+        U = np.asarray(U, dtype=np.float64)
+        lnf = np.asarray(lnf, dtype=np.float64)
+        self.mu, self.sd = float(lnf.mean()), float(lnf.std() + 1e-12)
+        x = torch.tensor(2.0 * U - 1.0, dtype=torch.float32, device=self.device)
+        y = torch.tensor((lnf - self.mu) / self.sd, dtype=torch.float32, device=self.device)
+        rng = np.random.default_rng(seed)
+        loss = torch.zeros(1, dtype=torch.float32, device=self.device)
+        n = U.shape[0]
+        b = min(self.batch, n)
+        for _ in range(steps):
+            idx = torch.tensor(rng.choice(n, size=b, replace=False), device=self.device)
+            self.t += 1
+            ops.mlp_train_step(self.params, self.m, self.v, x[idx].contiguous(), y[idx].contiguous(), self.lr, self.t,
+                               loss=loss)
+        return float(loss.item())
+
+    def state(self) -> dict:
+        return dict(s_params=self.params.cpu().numpy(), s_m=self.m.cpu().numpy(), s_v=self.v.cpu().numpy(),
+                    s_t=self.t, s_mu=self.mu, s_sd=self.sd)
+
+    def load_state(self, z) -> None:
+        self.params = torch.tensor(z["s_params"], device=self.device)
+        self.m = torch.tensor(z["s_m"], device=self.device)
+        self.v = torch.tensor(z["s_v"], device=self.device)
+        self.t = int(z["s_t"])
+        self.mu, self.sd = float(z["s_mu"]), float(z["s_sd"])
+
+
+class GeneticSearch:
+    """Plain GA: every offspring is fully solved.  `fitness` maps unit genes (n, 7) -> (n,)."""
+
+    def __init__(self, fitness, X0: np.ndarray, cfg: GAConfig = GAConfig(), log=None):
+        self.fitness, self.cfg, self.log = fitness, cfg, log
+        self.X = np.array(X0, dtype=np.float64)
+        self.fX = fitness(self.X)
+        self.generation = 0
+        self.full_solves = self.X.shape[0]
+        self.history = [float(np.min(self.fX))]
+        self.data_U = [self.X.copy()]
+        self.data_f = [self.fX.copy()]
+
+    @property
+    def pop(self) -> int:
+        return self.X.shape[0]
+
+    def _record(self, Y, fY, extra=None):
+        self.data_U.append(Y)
+        self.data_f.append(fY)
+        self.generation += 1
+        self.full_solves += Y.shape[0]
+        self.history.append(float(np.min(self.fX)))
+        if self.log is not None:
+            rec = dict(generation=self.generation, full_solves=self.full_solves, best=self.history[-1],
+                       median=float(np.median(self.fX)))
+            rec.update(extra or {})
+            self.log(rec)
+
+    def step(self, draws: dict) -> None:
+        """One generation from one generation's draws (arrays of length pop)."""
+        P = self.pop
+        Y = make_offspring(self.X, np.arange(P), draws["partner"], draws["xstrength"], draws["mut_mask"],
+                           draws["mut_step"], self.cfg)
+        fY = self.fitness(Y)
+        self.X, self.fX = tournament(self.X, self.fX, Y, fY, draws["perm"])
+        self._record(Y, fY)
+
+    def training_set(self):
+        U = np.concatenate(self.data_U)
+        f = np.concatenate(self.data_f)
+        ok = np.isfinite(f) & (f > 0)
+        return U[ok], np.log(f[ok])
+
+    def save(self, path: str) -> None:
+        np.savez(path, X=self.X, fX=self.fX, generation=self.generation, full_solves=self.full_solves,
+                 history=np.array(self.history), data_U=np.concatenate(self.data_U),
+                 data_f=np.concatenate(self.data_f), **self._extra_state())
+
+    def _extra_state(self) -> dict:
+        return {}
+
+    @classmethod
+    def resume(cls, path: str, fitness, cfg: GAConfig = GAConfig(), log=None, **kw):
+        """Rebuild a search from a checkpoint without re-evaluating anything."""
+        z = np.load(path, allow_pickle=False)
+        self = cls.__new__(cls)
+        self.fitness, self.cfg, self.log = fitness, cfg, log
+        self.X, self.fX = z["X"].copy(), z["fX"].copy()
+        self.generation, self.full_solves = int(z["generation"]), int(z["full_solves"])
+        self.history = [float(v) for v in z["history"]]
+        self.data_U, self.data_f = [z["data_U"].copy()], [z["data_f"].copy()]
+        self._resume_extra(z, **kw)
+        return self
+
+    def _resume_extra(self, z, **kw) -> None:
+        pass
+
+
+class ScreenedSearch(GeneticSearch):
+    """GA whose offspring are pre-screened by the device surrogate.
+
+    Each generation: fanout * pop candidates (candidate c descends from parent
+    c mod pop), surrogate prediction of ln chi^2 for all, the pop candidates
+    with the lowest prediction (ties by index) are fully solved and enter the
+    tournament; then `train_steps` Adam steps on every full solve so far.
+    """
+
+    def __init__(self, fitness, X0, surrogate: Surrogate, fanout: int = 10, train_steps: int = 50,
+                 cfg: GAConfig = GAConfig(), log=None, pretrain_steps: int = 200):
+        super().__init__(fitness, X0, cfg, log)
+        self.surrogate, self.fanout, self.train_steps = surrogate, int(fanout), int(train_steps)
+        U, lnf = self.training_set()
+        if pretrain_steps and U.shape[0]:
+            self.surrogate.train(U, lnf, pretrain_steps, seed=0)
+
+    def step(self, draws: dict) -> None:
+        """One generation from draws of length fanout * pop."""
+        P = self.pop
+        C = self.fanout * P
+        cand = make_offspring(self.X, np.arange(C) % P, draws["partner"][:C] % P, draws["xstrength"][:C],
+                              draws["mut_mask"][:C], draws["mut_step"][:C], self.cfg)
+        pred = self.surrogate.predict(cand)
+        pick = np.argsort(pred, kind="stable")[:P]
+        Y = cand[pick]
+        fY = self.fitness(Y)
+        perm = draws["perm"][:C]
+        perm = perm[perm < P]
+        self.X, self.fX = tournament(self.X, self.fX, Y, fY, perm)
+        ok = np.isfinite(fY)
+        rmse = float(np.sqrt(np.mean((pred[pick][ok] - np.log(fY[ok])) ** 2))) if ok.any() else float("nan")
+        rank = _spearman(pred[pick][ok], fY[ok]) if ok.sum() > 2 else float("nan")
+        loss = float("nan")
+        self._record(Y, fY, dict(surrogate_rmse=rmse, surrogate_rank_corr=rank))
+        if self.train_steps:
+            U, lnf = self.training_set()
+            loss = self.surrogate.train(U, lnf, self.train_steps, seed=self.generation)
+        if self.log is not None:
+            self.log(dict(generation=self.generation, surrogate_train_loss=loss))
+
+    def _extra_state(self) -> dict:
+        return dict(fanout=self.fanout, train_steps=self.train_steps, **self.surrogate.state())
+
+    def _resume_extra(self, z, surrogate: Surrogate | None = None) -> None:
+        self.fanout, self.train_steps = int(z["fanout"]), int(z["train_steps"])
+        self.surrogate = surrogate
+        self.surrogate.load_state(z)
+
+
+def _spearman(a, b) -> float:
+    ra = np.argsort(np.argsort(a))
+    rb = np.argsort(np.argsort(b))
+    return float(np.corrcoef(ra, rb)[0, 1])
