@@ -138,9 +138,23 @@ typedef struct {
                           SL_F64: FP64 throughout */
 } sl_problem;
 
+/*
+ * Kernel variant of the batched solve.  Every variant computes the same
+ * quantities; they differ only in the order of floating-point sums, so their
+ * results agree to rounding.  All zero is the default variant.
+ */
+typedef struct {
+  int wide_window;     /* 1: banded blur window one compiled size above the minimum */
+  int lt_csr;          /* 1: transposed trace operator in CSR rows instead of sliced ELL */
+  int blur_direct;     /* 1: direct K x K blur even when the PSF is separable */
+} sl_tuning;
+
 typedef struct {
   double tol;          /* stop when ||r|| <= tol ||b|| */
   int maxit;           /* iteration cap per (member, lambda) */
+  const sl_tuning* tuning; /* nullable: NULL takes the autotuner's choice for this problem
+                              signature when sl_solve_autotune has made one in this
+                              process, else the default variant */
 } sl_solve_opts;
 
 typedef struct {
@@ -177,6 +191,41 @@ int sl_solve_semilinear(const sl_problem* pb, const double* lens, const int32_t*
                         int n_members, const double* lambdas, int n_lambda,
                         const sl_solve_opts* opt, void* workspace, size_t workspace_bytes,
                         sl_result* out, void* stream);
+
+/*
+ * Autotuner: runs the solve once per kernel variant (after one untimed run
+ * of each), timing each with HIP events on `stream`, and records the fastest
+ * for this problem signature (dtype, image size, subpixels, PSF size,
+ * regulariser, max_ns, n_members, n_lambda) in a process-wide table that
+ * later calls with opt->tuning == NULL consult.  Synchronous.  Arguments are
+ * those of sl_solve_semilinear; on return `out` holds the best variant's
+ * results, *best (nullable) its settings and ms (nullable, host
+ * double[SL_N_VARIANTS]) each variant's time, or -1 for a variant that does
+ * not exist for this PSF size and dtype.
+ */
+#define SL_N_VARIANTS 8
+int sl_solve_autotune(const sl_problem* pb, const double* lens, const int32_t* ns, int max_ns,
+                      int n_members, const double* lambdas, int n_lambda,
+                      const sl_solve_opts* opt, void* workspace, size_t workspace_bytes,
+                      sl_result* out, void* stream, sl_tuning* best, double* ms);
+
+/*
+ * Graph plan: the launches of one sl_solve_semilinear call (same
+ * arguments; the variant is resolved at creation) captured once into a HIP
+ * graph on a private stream.  sl_plan_launch replays it on `stream`; each
+ * replay re-reads the device inputs (lens, ns, data, PSF) that the pointers
+ * given at creation hold at that time, so a caller updates the lens buffer in
+ * place between replays.  The pointers, sizes and lambdas are fixed for the
+ * plan's lifetime; the workspace and result buffers must outlive it and
+ * replays that share them must not overlap.  No replay allocates.
+ */
+typedef struct sl_plan sl_plan;
+int sl_plan_create(const sl_problem* pb, const double* lens, const int32_t* ns, int max_ns,
+                   int n_members, const double* lambdas, int n_lambda,
+                   const sl_solve_opts* opt, void* workspace, size_t workspace_bytes,
+                   const sl_result* out, sl_plan** plan);
+int sl_plan_launch(sl_plan* plan, void* stream);
+int sl_plan_destroy(sl_plan* plan);
 
 /*
  * Per-member table of the last sl_solve_semilinear that used `workspace`

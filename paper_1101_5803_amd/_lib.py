@@ -38,8 +38,15 @@ class Problem(ctypes.Structure):
                 ("reg", ctypes.c_int), ("dtype", ctypes.c_int)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("wide_window", ctypes.c_int), ("lt_csr", ctypes.c_int), ("blur_direct", ctypes.c_int)]
+
+
 class SolveOpts(ctypes.Structure):
-    _fields_ = [("tol", ctypes.c_double), ("maxit", ctypes.c_int)]
+    _fields_ = [("tol", ctypes.c_double), ("maxit", ctypes.c_int), ("tuning", ctypes.POINTER(Tuning))]
+
+
+N_VARIANTS = 8
 
 
 class Result(ctypes.Structure):
@@ -73,6 +80,14 @@ def lib():
         L.sl_solve_semilinear.argtypes = [ctypes.POINTER(Problem), vp, vp, ip, ip,
                                           ctypes.POINTER(ctypes.c_double), ip, ctypes.POINTER(SolveOpts),
                                           vp, ctypes.c_size_t, ctypes.POINTER(Result), vp]
+        L.sl_solve_autotune.argtypes = [ctypes.POINTER(Problem), vp, vp, ip, ip, ctypes.POINTER(ctypes.c_double), ip,
+                                        ctypes.POINTER(SolveOpts), vp, ctypes.c_size_t, ctypes.POINTER(Result), vp,
+                                        ctypes.POINTER(Tuning), ctypes.POINTER(ctypes.c_double)]
+        L.sl_plan_create.argtypes = [ctypes.POINTER(Problem), vp, vp, ip, ip, ctypes.POINTER(ctypes.c_double), ip,
+                                     ctypes.POINTER(SolveOpts), vp, ctypes.c_size_t, ctypes.POINTER(Result),
+                                     ctypes.POINTER(vp)]
+        L.sl_plan_launch.argtypes = [vp, vp]
+        L.sl_plan_destroy.argtypes = [vp]
         L.sl_solve_member_info.argtypes = [ctypes.POINTER(Problem), ip, ip, ip, vp, vp]
         L.sl_profile_enable.argtypes = [ip]
         L.sl_profile_solve_ms.argtypes = [ctypes.POINTER(ctypes.c_double), i32p]
@@ -84,7 +99,8 @@ def lib():
         L.sl_mlp_train_step.argtypes = [vp, vp, vp, vp, vp, ip, ctypes.c_float, ip, vp, vp, vp, vp]
         for name in ("sl_lens_trace", "sl_apply_L", "sl_apply_LT", "sl_apply_B", "sl_apply_BT",
                      "sl_apply_HtH", "sl_solve_semilinear", "sl_lcurve_corner", "sl_mlp_forward",
-                     "sl_mlp_train_step", "sl_solve_member_info", "sl_profile_enable", "sl_profile_solve_ms"):
+                     "sl_mlp_train_step", "sl_solve_member_info", "sl_profile_enable", "sl_profile_solve_ms",
+                     "sl_solve_autotune", "sl_plan_create", "sl_plan_launch", "sl_plan_destroy"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib

@@ -28,6 +28,8 @@
 // correction for outputs within ck of the image edge.  A PSF that is not
 // rank-1 takes the direct K x K path with an image-space buffer in global memory.
 #include <algorithm>
+#include <array>
+#include <map>
 #include <climits>
 #include <mutex>
 #include <vector>
@@ -136,6 +138,8 @@ struct SolveArgs {
   void* lt_ent;     // [member][lt_cap] LtEntry<T>
   long long lt_cap; // entries per member
   int I_max;
+  int force_csr;    // variant: transposed operator as CSR rows
+  int force_direct; // variant: direct K x K blur for a separable PSF
 };
 
 // ------------------------------------------------------------------ block scan
@@ -240,7 +244,7 @@ __global__ void __launch_bounds__(1024) k_setup(SolveArgs a, LamList lams) {
           }
     }
     // the banded path needs the kernel's window to cover +-2ck
-    if (ck > a.ckt) sep = 0;
+    if (ck > a.ckt || a.force_direct) sep = 0;
     a.consts->sep = sep;
     if (sep) {
       // autocorrelations a[d] = sum_i g[i] g[i-d], stored at index d + 2*kMaxCK
@@ -453,7 +457,7 @@ __device__ int build_transpose(const SolveArgs& a, int m, int ns, int slots, con
     atomicAdd(&totals[0], 64 * mx);
   }
   __syncthreads();
-  const int sell = __builtin_amdgcn_readfirstlane((int)((long long)totals[0] <= a.lt_cap));
+  const int sell = __builtin_amdgcn_readfirstlane((int)(!a.force_csr && (long long)totals[0] <= a.lt_cap));
   // exclusive scan over units: slices (padded sizes) for sliced-ELL, rows for CSR
   const int nunits = sell ? ngroups : I;
   const int chunk = (nunits + blockDim.x - 1) / blockDim.x;
@@ -1310,20 +1314,35 @@ static int check_problem(const sl_problem* pb, int max_ns, int M, int NL) {
 using SolveKernel = void (*)(SolveArgs);
 
 // Kernel variants: bulk type T and banded half-width CKT (>= ck of the PSF).
-static SolveKernel pick_kernel_f(int ck, int* ckt) {
-  if (ck <= 2) { *ckt = 2; return k_solve<float, 2>; }
-  if (ck <= 4) { *ckt = 4; return k_solve<float, 4>; }
-  if (ck <= 7) { *ckt = 7; return k_solve<float, 7>; }
-  if (ck <= 10) { *ckt = 10; return k_solve<float, 10>; }
-  if (ck <= 16) { *ckt = 16; return k_solve<float, 16>; }
-  { *ckt = 2; return k_solve<float, 2>; }   // wider PSFs: direct path only
+// Compiled banded-window sizes (CKT >= ck).  `wide` takes the next size up;
+// nullptr when that variant does not exist.
+static SolveKernel pick_kernel_f(int ck, bool wide, int* ckt) {
+  static const int sizes[] = {2, 4, 7, 10, 16};
+  static const SolveKernel ks[] = {k_solve<float, 2>, k_solve<float, 4>, k_solve<float, 7>, k_solve<float, 10>,
+                                   k_solve<float, 16>};
+  int i = 0;
+  while (i < 5 && sizes[i] < ck) ++i;
+  if (i == 5) {   // wider PSFs: direct path only
+    *ckt = 2;
+    return wide ? nullptr : ks[0];
+  }
+  if (wide && ++i == 5) return nullptr;
+  *ckt = sizes[i];
+  return ks[i];
 }
 
-static SolveKernel pick_kernel_d(int ck, int* ckt) {
-  if (ck <= 2) { *ckt = 2; return k_solve<double, 2>; }
-  if (ck <= 7) { *ckt = 7; return k_solve<double, 7>; }
-  if (ck <= 10) { *ckt = 10; return k_solve<double, 10>; }
-  { *ckt = 2; return k_solve<double, 2>; }
+static SolveKernel pick_kernel_d(int ck, bool wide, int* ckt) {
+  static const int sizes[] = {2, 7, 10};
+  static const SolveKernel ks[] = {k_solve<double, 2>, k_solve<double, 7>, k_solve<double, 10>};
+  int i = 0;
+  while (i < 3 && sizes[i] < ck) ++i;
+  if (i == 3) {
+    *ckt = 2;
+    return wide ? nullptr : ks[0];
+  }
+  if (wide && ++i == 3) return nullptr;
+  *ckt = sizes[i];
+  return ks[i];
 }
 
 // ------------------------------------------------------------------ profiling
@@ -1334,12 +1353,26 @@ struct ProfileState {
 };
 static ProfileState g_prof;
 
+struct LaunchCfg {
+  SolveKernel ks = nullptr;
+  size_t lds = 0, prep_lds = 0, corner_lds = 0;
+};
+
+// Chooses the CG kernel of variant v and its LDS budget and sets the
+// kernels' LDS attributes (host-side, outside any stream capture).
 template <typename T>
-static int launch_solve(SolveArgs& A, const LamList& lams, const Layout& L, hipStream_t st) {
+static int configure(SolveArgs& A, const Layout& L, const sl_tuning& v, LaunchCfg* c) {
   const size_t sz = sizeof(T);
   int ckt = 2;
-  SolveKernel ks = sizeof(T) == 4 ? pick_kernel_f(A.ck, &ckt) : pick_kernel_d(A.ck, &ckt);
+  SolveKernel ks = sizeof(T) == 4 ? pick_kernel_f(A.ck, v.wide_window != 0, &ckt)
+                                  : pick_kernel_d(A.ck, v.wide_window != 0, &ckt);
+  if (!ks) {
+    set_error("kernel variant does not exist for this PSF size and dtype");
+    return SL_ENOIMPL;
+  }
   A.ckt = ckt;
+  A.force_csr = v.lt_csr != 0;
+  A.force_direct = v.blur_direct != 0;
   // dynamic LDS: source vector | reduction scratch | frame (up to the full image)
   A.q_off = (int)align256(sz * L.I_max);
   A.red_off = A.q_off + (int)align256(sz * L.I_max);
@@ -1350,22 +1383,30 @@ static int launch_solve(SolveArgs& A, const LamList& lams, const Layout& L, hipS
   if (lds > lds_max) lds = lds_max;
   SL_REQUIRE(lds > fixed + 64 * sz, "source grid too large for LDS");
   A.lds_frame_cap = (int)((lds - fixed) / sz);
+  c->ks = ks;
+  c->lds = lds;
+  // FP64 right-hand-side accumulator, reused by the transposed-operator build (2 I + 192 ints)
+  c->prep_lds = std::max(sizeof(double) * L.I_max, sizeof(int) * (2 * L.I_max + 192));
+  c->corner_lds = sizeof(double) * (A.n_lambda * A.n_lambda + 12 * A.n_lambda + 16);
   static std::mutex mu;
-  {
-    std::lock_guard<std::mutex> g(mu);
-    SL_HIP(hipFuncSetAttribute((const void*)ks, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    // FP64 right-hand-side accumulator, reused by the transposed-operator build (2 I + 192 ints)
-    const size_t prep_lds = std::max(sizeof(double) * L.I_max, sizeof(int) * (2 * L.I_max + 192));
-    SL_HIP(hipFuncSetAttribute((const void*)k_prep<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)prep_lds));
-  }
+  std::lock_guard<std::mutex> g(mu);
+  SL_HIP(hipFuncSetAttribute((const void*)ks, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  SL_HIP(hipFuncSetAttribute((const void*)k_prep<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)c->prep_lds));
+  return SL_OK;
+}
+
+// Enqueues the four launches of one solve on st.  `profile` records HIP
+// events around the CG kernel when profiling is on (never inside a capture).
+template <typename T>
+static int enqueue(const SolveArgs& A, const LamList& lams, const Layout& L, const LaunchCfg& c, hipStream_t st,
+                   bool profile) {
   hipLaunchKernelGGL(k_setup<T>, dim3(1), dim3(1024), 0, st, A, lams);
   if (int e = check_launch("k_setup")) return e;
-  hipLaunchKernelGGL(k_prep<T>, dim3(A.n_members), dim3(1024),
-                     std::max(sizeof(double) * L.I_max, sizeof(int) * (2 * L.I_max + 192)), st, A);
+  hipLaunchKernelGGL(k_prep<T>, dim3(A.n_members), dim3(1024), c.prep_lds, st, A);
   if (int e = check_launch("k_prep")) return e;
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  {
+  if (profile) {
     std::lock_guard<std::mutex> g(g_prof.mu);
     if (g_prof.on) {
       SL_HIP(hipEventCreate(&e0));
@@ -1373,32 +1414,53 @@ static int launch_solve(SolveArgs& A, const LamList& lams, const Layout& L, hipS
       SL_HIP(hipEventRecord(e0, st));
     }
   }
-  hipLaunchKernelGGL(ks, dim3(L.n_wg), dim3(kNT), lds, st, A);
+  hipLaunchKernelGGL(c.ks, dim3(L.n_wg), dim3(kNT), c.lds, st, A);
   if (int e = check_launch("k_solve")) return e;
   if (e1) {
     SL_HIP(hipEventRecord(e1, st));
     std::lock_guard<std::mutex> g(g_prof.mu);
     g_prof.ev.emplace_back(e0, e1);
   }
-  const size_t corner_lds = sizeof(double) * (A.n_lambda * A.n_lambda + 12 * A.n_lambda + 16);
-  hipLaunchKernelGGL(k_corner<T>, dim3(A.n_members), dim3(256), corner_lds, st, A);
+  hipLaunchKernelGGL(k_corner<T>, dim3(A.n_members), dim3(256), c.corner_lds, st, A);
   return check_launch("k_corner");
 }
 
-}  // namespace sl
-
-using namespace sl;
-
-extern "C" {
-
-size_t sl_solve_workspace_size(const sl_problem* pb, int max_ns, int n_members, int n_lambda) {
-  if (check_problem(pb, max_ns, n_members, n_lambda) != SL_OK) return 0;
-  return make_layout(pb, max_ns, n_members, n_lambda, device_cus()).total;
+static int configure_any(int dtype, SolveArgs& A, const Layout& L, const sl_tuning& v, LaunchCfg* c) {
+  return dtype == SL_F32 ? configure<float>(A, L, v, c) : configure<double>(A, L, v, c);
 }
 
-int sl_solve_semilinear(const sl_problem* pb, const double* lens, const int32_t* ns, int max_ns,
-                        int n_members, const double* lambdas, int n_lambda, const sl_solve_opts* opt,
-                        void* workspace, size_t workspace_bytes, sl_result* out, void* stream) {
+static int enqueue_any(int dtype, const SolveArgs& A, const LamList& lams, const Layout& L, const LaunchCfg& c,
+                       hipStream_t st, bool profile) {
+  return dtype == SL_F32 ? enqueue<float>(A, lams, L, c, st, profile) : enqueue<double>(A, lams, L, c, st, profile);
+}
+
+// ------------------------------------------------------------------ autotuner table
+using TuneKey = std::array<int, 9>;
+
+static TuneKey tune_key(const sl_problem* pb, int max_ns, int n_members, int n_lambda) {
+  return {pb->dtype, pb->img.nx, pb->img.ny, pb->img.nsub, pb->k, pb->reg, max_ns, n_members, n_lambda};
+}
+
+struct TuneTable {
+  std::mutex mu;
+  std::map<TuneKey, sl_tuning> best;
+};
+static TuneTable g_tune;
+
+static sl_tuning resolve_tuning(const sl_problem* pb, int max_ns, int n_members, int n_lambda,
+                                const sl_solve_opts* opt) {
+  if (opt->tuning) return *opt->tuning;
+  std::lock_guard<std::mutex> g(g_tune.mu);
+  auto it = g_tune.best.find(tune_key(pb, max_ns, n_members, n_lambda));
+  return it == g_tune.best.end() ? sl_tuning{0, 0, 0} : it->second;
+}
+
+static sl_tuning variant_of(int i) { return sl_tuning{i & 1, (i >> 1) & 1, (i >> 2) & 1}; }
+
+// Validates the arguments of a solve and fills the kernel arguments.
+static int prepare(const sl_problem* pb, const double* lens, const int32_t* ns, int max_ns, int n_members,
+                   const double* lambdas, int n_lambda, const sl_solve_opts* opt, void* workspace,
+                   size_t workspace_bytes, const sl_result* out, SolveArgs* Ap, Layout* Lp, LamList* lams) {
   if (int e = check_problem(pb, max_ns, n_members, n_lambda)) return e;
   SL_REQUIRE(lens && ns && pb->d && pb->psf, "NULL device input");
   SL_REQUIRE(lambdas != nullptr, "lambdas is NULL");
@@ -1416,7 +1478,6 @@ int sl_solve_semilinear(const sl_problem* pb, const double* lens, const int32_t*
              "workspace must be non-NULL and 256-byte aligned");
   const Layout L = make_layout(pb, max_ns, n_members, n_lambda, device_cus());
   SL_REQUIRE(workspace_bytes >= L.total, "workspace too small: %zu < %zu bytes", workspace_bytes, L.total);
-
   SolveArgs A{};
   A.nx = pb->img.nx;
   A.ny = pb->img.ny;
@@ -1469,12 +1530,172 @@ int sl_solve_semilinear(const sl_problem* pb, const double* lens, const int32_t*
   A.lt_ent = ws + L.lt_ent;
   A.lt_cap = L.lt_cap;
   A.I_max = L.I_max;
-  LamList lams{};
-  for (int k = 0; k < n_lambda; ++k) lams.v[k] = lambdas[k];
-  hipStream_t st = (hipStream_t)stream;
-  if (pb->dtype == SL_F32) return launch_solve<float>(A, lams, L, st);
-  return launch_solve<double>(A, lams, L, st);
+  *lams = LamList{};
+  for (int k = 0; k < n_lambda; ++k) lams->v[k] = lambdas[k];
+  *Ap = A;
+  *Lp = L;
+  return SL_OK;
 }
+
+}  // namespace sl
+
+using namespace sl;
+
+extern "C" {
+
+int sl_solve_semilinear(const sl_problem* pb, const double* lens, const int32_t* ns, int max_ns,
+                        int n_members, const double* lambdas, int n_lambda, const sl_solve_opts* opt,
+                        void* workspace, size_t workspace_bytes, sl_result* out, void* stream) {
+  SolveArgs A;
+  Layout L;
+  LamList lams;
+  if (int e = prepare(pb, lens, ns, max_ns, n_members, lambdas, n_lambda, opt, workspace, workspace_bytes, out, &A,
+                      &L, &lams))
+    return e;
+  LaunchCfg c;
+  if (int e = configure_any(pb->dtype, A, L, resolve_tuning(pb, max_ns, n_members, n_lambda, opt), &c)) return e;
+  return enqueue_any(pb->dtype, A, lams, L, c, (hipStream_t)stream, true);
+}
+
+int sl_solve_autotune(const sl_problem* pb, const double* lens, const int32_t* ns, int max_ns, int n_members,
+                      const double* lambdas, int n_lambda, const sl_solve_opts* opt, void* workspace,
+                      size_t workspace_bytes, sl_result* out, void* stream, sl_tuning* best, double* ms) {
+  SolveArgs A0;
+  Layout L;
+  LamList lams;
+  if (int e = prepare(pb, lens, ns, max_ns, n_members, lambdas, n_lambda, opt, workspace, workspace_bytes, out,
+                      &A0, &L, &lams))
+    return e;
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  SL_HIP(hipEventCreate(&e0));
+  SL_HIP(hipEventCreate(&e1));
+  double t_best = 1e300;
+  int i_best = -1, i_last = -1;
+  int rc = SL_OK;
+  for (int i = 0; i < SL_N_VARIANTS && rc == SL_OK; ++i) {
+    if (ms) ms[i] = -1.0;
+    SolveArgs A = A0;
+    LaunchCfg c;
+    const int ce = configure_any(pb->dtype, A, L, variant_of(i), &c);
+    if (ce == SL_ENOIMPL) continue;
+    if ((rc = ce) != SL_OK) break;
+    if ((rc = enqueue_any(pb->dtype, A, lams, L, c, st, false)) != SL_OK) break;   // untimed
+    if (hipEventRecord(e0, st) != hipSuccess) { rc = SL_EHIP; break; }
+    if ((rc = enqueue_any(pb->dtype, A, lams, L, c, st, false)) != SL_OK) break;
+    float t = 0.0f;
+    if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&t, e0, e1) != hipSuccess) {
+      set_error("autotune timing failed: %s", hipGetErrorString(hipGetLastError()));
+      rc = SL_EHIP;
+      break;
+    }
+    if (ms) ms[i] = t;
+    i_last = i;
+    if (t < t_best) {
+      t_best = t;
+      i_best = i;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != SL_OK) return rc;
+  SL_REQUIRE(i_best >= 0, "no kernel variant exists for this problem");
+  const sl_tuning v = variant_of(i_best);
+  {
+    std::lock_guard<std::mutex> g(g_tune.mu);
+    g_tune.best[tune_key(pb, max_ns, n_members, n_lambda)] = v;
+  }
+  if (best) *best = v;
+  if (i_best != i_last) {   // leave the best variant's results in `out`
+    SolveArgs A = A0;
+    LaunchCfg c;
+    if (int e = configure_any(pb->dtype, A, L, v, &c)) return e;
+    if (int e = enqueue_any(pb->dtype, A, lams, L, c, st, false)) return e;
+  }
+  return SL_OK;
+}
+
+}  // extern "C"
+
+struct sl_plan {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+extern "C" {
+
+int sl_plan_create(const sl_problem* pb, const double* lens, const int32_t* ns, int max_ns, int n_members,
+                   const double* lambdas, int n_lambda, const sl_solve_opts* opt, void* workspace,
+                   size_t workspace_bytes, const sl_result* out, sl_plan** plan) {
+  SL_REQUIRE(plan != nullptr, "plan is NULL");
+  *plan = nullptr;
+  SolveArgs A;
+  Layout L;
+  LamList lams;
+  if (int e = prepare(pb, lens, ns, max_ns, n_members, lambdas, n_lambda, opt, workspace, workspace_bytes, out, &A,
+                      &L, &lams))
+    return e;
+  LaunchCfg c;
+  if (int e = configure_any(pb->dtype, A, L, resolve_tuning(pb, max_ns, n_members, n_lambda, opt), &c)) return e;
+  hipStream_t cs;
+  SL_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  hipGraph_t g = nullptr;
+  int rc = SL_OK;
+  if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    set_error("hipStreamBeginCapture failed: %s", hipGetErrorString(hipGetLastError()));
+    rc = SL_EHIP;
+  } else {
+    rc = enqueue_any(pb->dtype, A, lams, L, c, cs, false);
+    const hipError_t ee = hipStreamEndCapture(cs, &g);
+    if (rc == SL_OK && ee != hipSuccess) {
+      set_error("hipStreamEndCapture failed: %s", hipGetErrorString(ee));
+      rc = SL_EHIP;
+    }
+  }
+  (void)hipStreamDestroy(cs);
+  hipGraphExec_t ge = nullptr;
+  if (rc == SL_OK) {
+    const hipError_t ie = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    if (ie != hipSuccess) {
+      set_error("hipGraphInstantiate failed: %s", hipGetErrorString(ie));
+      rc = SL_EHIP;
+    }
+  }
+  if (rc != SL_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  sl_plan* p = new sl_plan;
+  p->graph = g;
+  p->exec = ge;
+  *plan = p;
+  return SL_OK;
+}
+
+int sl_plan_launch(sl_plan* plan, void* stream) {
+  SL_REQUIRE(plan && plan->exec, "invalid plan");
+  SL_HIP(hipGraphLaunch(plan->exec, (hipStream_t)stream));
+  return SL_OK;
+}
+
+int sl_plan_destroy(sl_plan* plan) {
+  if (!plan) return SL_OK;
+  hipError_t e1 = plan->exec ? hipGraphExecDestroy(plan->exec) : hipSuccess;
+  hipError_t e2 = plan->graph ? hipGraphDestroy(plan->graph) : hipSuccess;
+  delete plan;
+  if (e1 != hipSuccess || e2 != hipSuccess) {
+    set_error("graph destroy failed");
+    return SL_EHIP;
+  }
+  return SL_OK;
+}
+
+size_t sl_solve_workspace_size(const sl_problem* pb, int max_ns, int n_members, int n_lambda) {
+  if (check_problem(pb, max_ns, n_members, n_lambda) != SL_OK) return 0;
+  return make_layout(pb, max_ns, n_members, n_lambda, device_cus()).total;
+}
+
 
 int sl_solve_member_info(const sl_problem* pb, int max_ns, int n_members, int n_lambda, const void* workspace,
                          int32_t* info_host) {

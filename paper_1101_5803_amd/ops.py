@@ -131,6 +131,33 @@ def lcurve_corner(reg, chi2):
     return int(k.value), kap
 
 
+class Plan:
+    """A captured solve (sl_plan_*): launch() replays it on torch's current stream."""
+
+    def __init__(self, handle, keep):
+        self._h = handle
+        self._keep = keep   # buffers whose addresses the graph holds
+        self.out = keep[3]
+
+    def launch(self):
+        if not self._h:
+            raise L.SemilinError("plan destroyed")
+        L.check(L.lib().sl_plan_launch(self._h, L.stream_handle()), "sl_plan_launch")
+        return self.out
+
+    def close(self):
+        if self._h:
+            torch.cuda.synchronize()
+            L.check(L.lib().sl_plan_destroy(self._h), "sl_plan_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Solver:
     """Batched semilinear solve against one data image (sl_solve_semilinear).
 
@@ -189,16 +216,11 @@ class Solver:
                                              info.ctypes.data_as(ctypes.c_void_p)), "sl_solve_member_info")
         return info
 
-    def solve_semilinear(self, lens: torch.Tensor, ns: torch.Tensor, lambdas, tol=1e-7, maxit=4000,
-                         max_ns: int | None = None, out=None):
-        """Run the batched solve; returns the result dict of device tensors.
-
-        lens (M, 7) FP64 and ns (M,) int32 on the device; lambdas a host
-        sequence.  ``max_ns`` bounds ns (defaults to ns.max(), which syncs).
-        """
+    def _args(self, lens, ns, lambdas, tol, maxit, max_ns, out, tuning):
         _dev_check(lens, ns)
-        lens = lens.to(torch.float64).contiguous()
-        ns = ns.to(torch.int32).contiguous()
+        if lens.dtype != torch.float64 or ns.dtype != torch.int32 or not lens.is_contiguous() \
+                or not ns.is_contiguous():
+            raise L.SemilinError("lens must be contiguous float64 (M, 7) and ns contiguous int32 (M,)")
         M = lens.shape[0]
         lam = [float(x) for x in lambdas]
         if max_ns is None:
@@ -208,12 +230,60 @@ class Solver:
             out = self.alloc_result(M * max_ns * max_ns, M, len(lam))
         res = L.Result(*[ctypes.c_void_p(out[k].data_ptr()) for k in
                          ("s_corner", "s_off", "chi2", "reg", "iters", "status", "k_star", "corner_status")])
-        opts = L.SolveOpts(float(tol), int(maxit))
-        L.check(L.lib().sl_solve_semilinear(ctypes.byref(self._pb), L.ptr(lens), L.ptr(ns), int(max_ns), M,
+        tun = None
+        if tuning is not None:
+            tun = L.Tuning(*[int(tuning.get(k, 0)) for k in ("wide_window", "lt_csr", "blur_direct")])
+        opts = L.SolveOpts(float(tol), int(maxit), ctypes.pointer(tun) if tun is not None else None)
+        return M, lam, int(max_ns), ws, out, res, opts, tun
+
+    def solve_semilinear(self, lens: torch.Tensor, ns: torch.Tensor, lambdas, tol=1e-7, maxit=4000,
+                         max_ns: int | None = None, out=None, tuning: dict | None = None):
+        """Run the batched solve; returns the result dict of device tensors.
+
+        lens (M, 7) FP64 and ns (M,) int32 on the device; lambdas a host
+        sequence.  ``max_ns`` bounds ns (defaults to ns.max(), which syncs).
+        ``tuning`` (dict with keys wide_window, lt_csr, blur_direct) forces a
+        kernel variant; None takes the autotuner's choice, if any.
+        """
+        lens = lens.to(torch.float64).contiguous()
+        ns = ns.to(torch.int32).contiguous()
+        M, lam, max_ns, ws, out, res, opts, _tun = self._args(lens, ns, lambdas, tol, maxit, max_ns, out, tuning)
+        L.check(L.lib().sl_solve_semilinear(ctypes.byref(self._pb), L.ptr(lens), L.ptr(ns), max_ns, M,
                                             L.f64_array(lam), len(lam), ctypes.byref(opts), L.ptr(ws),
                                             ws.numel(), ctypes.byref(res), L.stream_handle()),
                 "sl_solve_semilinear")
         return out
+
+    def autotune(self, lens: torch.Tensor, ns: torch.Tensor, lambdas, tol=1e-7, maxit=4000,
+                 max_ns: int | None = None, out=None):
+        """Time every kernel variant on this problem (synchronous); returns (best dict, ms per variant, out).
+
+        Later solves of the same signature with tuning=None use the best variant.
+        """
+        lens = lens.to(torch.float64).contiguous()
+        ns = ns.to(torch.int32).contiguous()
+        M, lam, max_ns, ws, out, res, opts, _tun = self._args(lens, ns, lambdas, tol, maxit, max_ns, out, None)
+        best = L.Tuning()
+        ms = (ctypes.c_double * L.N_VARIANTS)()
+        L.check(L.lib().sl_solve_autotune(ctypes.byref(self._pb), L.ptr(lens), L.ptr(ns), max_ns, M,
+                                          L.f64_array(lam), len(lam), ctypes.byref(opts), L.ptr(ws), ws.numel(),
+                                          ctypes.byref(res), L.stream_handle(), ctypes.byref(best), ms),
+                "sl_solve_autotune")
+        return (dict(wide_window=best.wide_window, lt_csr=best.lt_csr, blur_direct=best.blur_direct), list(ms), out)
+
+    def plan(self, lens: torch.Tensor, ns: torch.Tensor, lambdas, tol=1e-7, maxit=4000,
+             max_ns: int | None = None, out=None, tuning: dict | None = None) -> "Plan":
+        """Capture the solve on these buffers into a HIP graph (sl_plan_create).
+
+        lens and ns must be contiguous device tensors of the right dtypes: the
+        graph keeps their addresses, and each replay reads their contents.
+        """
+        M, lam, max_ns, ws, out, res, opts, _tun = self._args(lens, ns, lambdas, tol, maxit, max_ns, out, tuning)
+        h = ctypes.c_void_p()
+        L.check(L.lib().sl_plan_create(ctypes.byref(self._pb), L.ptr(lens), L.ptr(ns), max_ns, M, L.f64_array(lam),
+                                       len(lam), ctypes.byref(opts), L.ptr(ws), ws.numel(), ctypes.byref(res),
+                                       ctypes.byref(h)), "sl_plan_create")
+        return Plan(h, keep=(lens, ns, ws, out, self))
 
 
 # ---------------------------------------------------------------- surrogate MLP

@@ -1,0 +1,104 @@
+"""Kernel variants, the autotuner and HIP-graph plans of the batched solve.
+
+* Every variant (banded window size, transposed-operator layout, blur path)
+  matches the oracle on the c2 workload, FP32 and FP64.
+* The autotuner times every existing variant and leaves the best variant's
+  results in its output.
+* A captured plan, replayed several times with new lens parameters written
+  into its input buffer and eager solves and synchronisations in between,
+  gives on every replay what the eager solve gives.
+"""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import synthgen
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+HERE = os.path.dirname(os.path.abspath(__file__))
+GOLD = os.path.join(HERE, "golden")
+VARIANTS = [dict(wide_window=i & 1, lt_csr=(i >> 1) & 1, blur_direct=(i >> 2) & 1) for i in range(8)]
+
+
+def _c2_solver(sl, dtype):
+    w = synthgen.C2
+    z = np.load(os.path.join(HERE, "data", "c2.npz"))
+    return sl.Solver(torch.tensor(z["d"], device=DEV), float(z["sigma"]), torch.tensor(z["psf"], device=DEV),
+                     sl.Grid(w.nx, w.ny, w.pix, w.nsub_model), w.half_width, reg=w.reg, dtype=dtype), w, z
+
+
+def _np(out):
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+@pytest.mark.parametrize("vi", range(8))
+def test_variant_matches_oracle(vi, dtype):
+    import paper_1101_5803_amd as sl
+    g = np.load(os.path.join(GOLD, "c2_oracle.npz"))
+    solver, w, z = _c2_solver(sl, dtype)
+    lens = torch.tensor(np.atleast_2d(z["lens"]), device=DEV)
+    ns = torch.tensor([w.ns], dtype=torch.int32, device=DEV)
+    tol, bound = (1e-7, 1e-5) if dtype == torch.float32 else (1e-10, 1e-9)
+    v = VARIANTS[vi]
+    out = _np(solver.solve_semilinear(lens, ns, w.lambdas, tol=tol, max_ns=w.ns, tuning=v))
+    assert np.all(out["status"] == 0)
+    rel = np.abs(out["chi2"][0] - g["chi2"]) / g["chi2"]
+    assert rel.max() <= bound, (v, rel.max())
+
+
+def test_autotune_times_every_variant_and_keeps_best_results():
+    import paper_1101_5803_amd as sl
+    solver, w, z = _c2_solver(sl, torch.float32)
+    M = 24
+    pop = synthgen.population(synthgen.C3.seed, 256)[:M]
+    grids = synthgen.member_grids(synthgen.C3.seed, 256)[:M]
+    lens = torch.tensor(pop, device=DEV)
+    ns = torch.tensor(grids, device=DEV)
+    best, ms, out = solver.autotune(lens, ns, w.lambdas, tol=w.tol, max_ns=96)
+    assert len(ms) == 8 and all(t > 0 for t in ms)   # K = 15 in FP32: all eight variants exist
+    i_best = best["wide_window"] | (best["lt_csr"] << 1) | (best["blur_direct"] << 2)
+    assert ms[i_best] == min(ms)
+    tuned = _np(out)
+    ref = _np(solver.solve_semilinear(lens, ns, w.lambdas, tol=w.tol, max_ns=96, tuning=best))
+    for k in ("chi2", "reg"):
+        assert np.allclose(tuned[k], ref[k], rtol=1e-6, atol=0), k
+    dflt = _np(solver.solve_semilinear(lens, ns, w.lambdas, tol=w.tol, max_ns=96, tuning={}))
+    ok = dflt["status"] == 0
+    assert np.all(np.abs(tuned["chi2"][ok] - dflt["chi2"][ok]) <= 1e-5 * dflt["chi2"][ok])
+
+
+def test_plan_replays_match_eager():
+    import paper_1101_5803_amd as sl
+    solver, w, z = _c2_solver(sl, torch.float32)
+    M = 16
+    pop = synthgen.population(synthgen.C3.seed, 256)
+    grids = synthgen.member_grids(synthgen.C3.seed, 256)
+    lens_buf = torch.tensor(pop[:M], device=DEV)
+    ns_buf = torch.tensor(grids[:M], device=DEV)
+    plan_out = solver.alloc_result(M * 96 * 96, M, len(w.lambdas))
+    plan = solver.plan(lens_buf, ns_buf, w.lambdas, tol=w.tol, max_ns=96, out=plan_out)
+    eager_out = solver.alloc_result(M * 96 * 96, M, len(w.lambdas))
+    for rep in range(4):
+        lo = 16 * rep
+        lens_buf.copy_(torch.tensor(pop[lo:lo + M], device=DEV))
+        ns_buf.copy_(torch.tensor(grids[lo:lo + M], device=DEV))
+        got = _np(plan.launch())
+        # eager work on the same stream between replays
+        _ = torch.ones(1000, device=DEV).sum().item()
+        ref = _np(solver.solve_semilinear(lens_buf.clone(), ns_buf.clone(), w.lambdas, tol=w.tol, max_ns=96,
+                                          out=eager_out))
+        for k in ("status", "k_star", "corner_status", "s_off"):
+            assert np.array_equal(got[k], ref[k]), (rep, k)
+        assert np.allclose(got["chi2"], ref["chi2"], rtol=1e-6, atol=0), rep
+        assert np.allclose(got["reg"], ref["reg"], rtol=1e-5, atol=0), rep
+        assert np.abs(got["iters"] - ref["iters"]).max() <= 2, rep
+        n = int(ref["s_off"][-1])
+        err = np.linalg.norm(got["s_corner"][:n] - ref["s_corner"][:n]) / np.linalg.norm(ref["s_corner"][:n])
+        assert err <= 1e-5, (rep, err)
+    plan.close()
