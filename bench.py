@@ -18,6 +18,7 @@ the host cores on a bounded sample.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -31,6 +32,34 @@ sys.path.insert(0, ROOT)
 METRIC = "lens-model evals/s (128² image, 16-λ L-curve) vs plain; χ² rel err vs FP64"
 PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
+SOLVE_SRC = os.path.join(ROOT, "paper_1101_5803_amd", "csrc", "solve.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_solve_c3_hbm_traffic.txt")
+
+
+def source_hash() -> str:
+    with open(SOLVE_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per k_solve launch from the committed counter summary, or None.
+
+    The summary records the hash of the kernel source it was measured on; a
+    different source (the kernel changed since) gives None.
+    """
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("solve_hip_sha256_16") != source_hash():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def parse():
@@ -41,7 +70,9 @@ def parse():
     ap.add_argument("--members", type=int, default=256)
     ap.add_argument("--plain-members", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true", help="skip the one-member-per-call comparison")
     ap.add_argument("--cpu-members", type=int, default=0, help="oracle sample size (default: cores used)")
+    ap.add_argument("--no-autotune", action="store_true", help="default kernel variant instead of the autotuned one")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run one device-to-device copy of MIB MiB (a known-size kernel that scales "
                          "hardware byte counters)")
@@ -120,6 +151,11 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    tuned = None
+    if not args.no_autotune:
+        tuned, tms, _ = solver.autotune(lens_d, ns_d, w.lambdas, tol=w.tol, maxit=4000, max_ns=max_ns, out=out)
+        print(f"[bench] autotune: best {tuned}, ms per variant {[round(t, 2) for t in tms]}", file=sys.stderr,
+              flush=True)
     print(f"[bench] warmup {args.warmup} step(s) of {M} members", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         step()
@@ -143,11 +179,52 @@ def main():
     kern_s = kern_ms / max(launches, 1) / 1e3
     tflops = flops / kern_s / 1e12
     gbs = tbytes / kern_s / 1e9
-    roof = {"bound": "alu", "achieved": round(tflops, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(tflops / PEAK_FP32_TFLOPS, 4), "traffic": None,
+    traffic = measured_traffic()
+    roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": traffic,
             "kernel": "k_solve (persistent CG)", "kernel_ms": round(kern_s * 1e3, 3),
-            "table_GBps": round(gbs, 1), "table_frac_of_hbm": round(gbs / PEAK_HBM_GBS, 4)}
+            "algorithmic_bytes": tbytes, "fp32_TFLOPs": round(tflops, 3),
+            "fp32_frac": round(tflops / PEAK_FP32_TFLOPS, 4),
+            "measured_hbm_GBps": round(traffic / kern_s / 1e9, 1) if traffic else None}
+    # the same step replayed from a captured HIP graph
+    plan = solver.plan(lens_d, ns_d, w.lambdas, tol=w.tol, maxit=4000, max_ns=max_ns, out=out)
+    plan.launch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.launch()
+    torch.cuda.synchronize()
+    graph_ms = 1e3 * (time.perf_counter() - t0) / args.steps
+    plan.close()
     # plain: the same library, one member per call
+    plain_value = None
+    if not args.no_plain:
+        plain_value = run_plain(args, sl, torch, z, grid, w, dev, lens_d, ns_d, max_ns)
+    rec = {
+        "metric": METRIC, "value": round(value, 2), "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "c3: 256 SIE+shear lens sets, 128x128 image at 0.05\", 2x2 subpixels, source "
+                               "grids 32..96 nodes per side over +-1\", 15x15 Gaussian PSF (FWHM 3 px), curvature "
+                               "H, 16 lambdas 1e-4..1e2, CG tol 1e-7",
+                   "members": M, "n_lambda": len(w.lambdas), "reductions": "f64", "kernel_variant": tuned,
+                   "cg_iterations": int(iters.sum()),
+                   "status_counts": {int(k): int(v) for k, v in zip(*np.unique(status, return_counts=True))}},
+        "plain_value": round(plain_value, 3) if plain_value else None,
+        "vs_plain": round(value / plain_value, 2) if plain_value else None,
+        "graph_ms_per_step": round(graph_ms, 3),
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        ncpu = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+        n = args.cpu_members or max(1, min(16, ncpu))
+        print(f"[bench] cpu baseline: oracle on {n} members", file=sys.stderr, flush=True)
+        rec["cpu_baseline"] = cpu_baseline(w, z, pop, grids, n)
+    print(json.dumps(rec), flush=True)
+
+
+def run_plain(args, sl, torch, z, grid, w, dev, lens_d, ns_d, max_ns):
+    """Evals/s of the same library called with one member per call."""
     print(f"[bench] plain: {args.plain_members} members one at a time", file=sys.stderr, flush=True)
     if args.plain_members <= 0:
         args.plain_members = 1
@@ -161,25 +238,7 @@ def main():
         plain.solve_semilinear(lens_d[m:m + 1], ns_d[m:m + 1], w.lambdas, tol=w.tol, maxit=4000, max_ns=max_ns,
                                out=pout)
     torch.cuda.synchronize()
-    plain_value = args.plain_members / (time.perf_counter() - t0)
-    rec = {
-        "metric": METRIC, "value": round(value, 2), "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "fp32 (fp64 reductions)", "data": "synthetic",
-        "config": {"workload": "c3: 256 SIE+shear lens sets, 128x128 image at 0.05\", 2x2 subpixels, source "
-                               "grids 32..96 nodes per side over +-1\", 15x15 Gaussian PSF (FWHM 3 px), curvature "
-                               "H, 16 lambdas 1e-4..1e2, CG tol 1e-7",
-                   "members": M, "n_lambda": len(w.lambdas), "cg_iterations": int(iters.sum()),
-                   "status_counts": {int(k): int(v) for k, v in zip(*np.unique(status, return_counts=True))}},
-        "plain_value": round(plain_value, 3), "vs_plain": round(value / plain_value, 2),
-        "roofline": roof,
-    }
-    if not args.no_cpu_baseline:
-        ncpu = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
-        n = args.cpu_members or max(1, min(16, ncpu))
-        print(f"[bench] cpu baseline: oracle on {n} members", file=sys.stderr, flush=True)
-        rec["cpu_baseline"] = cpu_baseline(w, z, pop, grids, n)
-    print(json.dumps(rec), flush=True)
+    return args.plain_members / (time.perf_counter() - t0)
 
 
 if __name__ == "__main__":

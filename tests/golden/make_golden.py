@@ -9,6 +9,11 @@ root:  python tests/golden/make_golden.py   (about two minutes on 8 cores)
 * c3_sample.npz  -- three members of the c3 population (first, middle, last)
   scored against the c2 image, same quantities, for sampled checks of the
   256-member launch.
+* c4_sample.npz  -- the c4 workload (200x200 image, 100x100 nodes, 21x21 PSF,
+  24 lambdas): the true lens and two members of the c4 population, same
+  quantities (about ten minutes on 3 cores).
+
+`python tests/golden/make_golden.py c4` writes only c4_sample.npz.
 """
 import os
 import sys
@@ -22,6 +27,7 @@ import synthgen  # noqa: E402
 from oracle import coracle, lcurve, mock  # noqa: E402
 
 C3_SAMPLE = (0, 128, 255)
+C4_SAMPLE = (0, 511)
 
 
 def run(lens, ns, w, D, threads):
@@ -31,7 +37,23 @@ def run(lens, ns, w, D, threads):
     return out, ks
 
 
+def c4():
+    w = synthgen.C4
+    D = mock.workload_data(w)
+    pop = synthgen.population(w.seed, 1024)
+    lens = np.vstack([np.atleast_2d(D["lens"]), pop[np.array(C4_SAMPLE)]])
+    ns = [w.ns] * lens.shape[0]
+    out, ks = run(lens, ns, w, D, lens.shape[0])
+    np.savez(os.path.join(HERE, "c4_sample.npz"), lens=lens, members=np.array((-1,) + C4_SAMPLE), chi2=out["chi2"],
+             reg=out["reg"], iters=out["iters"], k_star=ks, s_corner=np.stack([out["s"][m, ks[m]] for m in
+                                                                              range(lens.shape[0])]),
+             lambdas=np.array(w.lambdas))
+
+
 def main():
+    if sys.argv[1:] == ["c4"]:
+        c4()
+        return
     w = synthgen.C2
     D = mock.workload_data(w)
     out, ks = run(np.atleast_2d(D["lens"]), [w.ns], w, D, 1)

@@ -227,3 +227,35 @@ def test_c3_full_launch_sampled(semilin):
     # Tikhonov monotonicity on every member (chi^2 non-decreasing in lambda)
     ok = np.diff(out["chi2"], axis=1) >= -1e-5 * out["chi2"][:, 1:]
     assert ok.mean() > 0.99
+
+
+def test_c4_full_launch_sampled(semilin):
+    """c4: 200x200 image (image frame in global memory), 100x100 nodes, 21x21
+    PSF, 24 lambdas; the true lens plus 1024 population members in one launch,
+    three sampled against the oracle."""
+    g = np.load(os.path.join(GOLD, "c4_sample.npz"))
+    w = synthgen.C4
+    z = np.load(os.path.join(os.path.dirname(__file__), "data", "c4.npz"))
+    pop = synthgen.population(w.seed, 1024)
+    lens = np.vstack([g["lens"][:1], pop])
+    ns = np.full(lens.shape[0], w.ns, dtype=np.int32)
+    out = _run(semilin, z["d"], float(z["sigma"]), z["psf"], semilin.Grid(w.nx, w.ny, w.pix, w.nsub_model),
+               w.half_width, w.reg, torch.float32, lens, ns, w.lambdas, w.tol, maxit=4000)
+    I = w.ns * w.ns
+    for j, m in enumerate(g["members"]):
+        row = int(m) + 1   # row 0 is the true lens
+        assert np.allclose(lens[row], g["lens"][j])
+        assert np.all(out["status"][row] == 0)
+        rel = np.abs(out["chi2"][row] - g["chi2"][j]) / g["chi2"][j]
+        assert rel.max() <= 1e-5, (m, rel)
+        k = int(out["k_star"][row])
+        assert _corner_ok(k, int(g["k_star"][j]), g["reg"][j], g["chi2"][j]), (m, k)
+        if k == int(g["k_star"][j]):
+            off = out["s_off"]
+            assert off[row + 1] - off[row] == I
+            s = out["s_corner"][off[row]:off[row + 1]]
+            err = np.linalg.norm(s - g["s_corner"][j][:I]) / np.linalg.norm(g["s_corner"][j][:I])
+            assert err <= 1e-4, (m, err)
+    assert np.all(np.isin(out["status"], [0, 1, 2]))
+    ok = out["status"] == 0
+    assert np.all(out["chi2"][ok] > 0)
