@@ -21,6 +21,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -36,9 +37,14 @@ SOLVE_SRC = os.path.join(ROOT, "paper_1101_5803_amd", "csrc", "solve.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_solve_c3_hbm_traffic.txt")
 
 
-def source_hash() -> str:
-    with open(SOLVE_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+def source_hash(text: str | None = None) -> str:
+    """Hash of the kernel source with // comments and whitespace removed."""
+    if text is None:
+        with open(SOLVE_SRC) as f:
+            text = f.read()
+    code = re.sub(r"//[^\n]*", "", text)
+    code = re.sub(r"\s+", "", code)
+    return hashlib.sha256(code.encode()).hexdigest()[:16]
 
 
 def measured_traffic():
@@ -196,6 +202,7 @@ def main():
     torch.cuda.synchronize()
     graph_ms = 1e3 * (time.perf_counter() - t0) / args.steps
     plan.close()
+    prec = precision_vs_f64(sl, torch, z, grid, w, dev, pop, grids, out, max_ns)
     # plain: the same library, one member per call
     plain_value = None
     if not args.no_plain:
@@ -213,6 +220,7 @@ def main():
         "plain_value": round(plain_value, 3) if plain_value else None,
         "vs_plain": round(value / plain_value, 2) if plain_value else None,
         "graph_ms_per_step": round(graph_ms, 3),
+        "chi2_rel_err_vs_f64": prec,
         "roofline": roof,
     }
     if not args.no_cpu_baseline:
@@ -221,6 +229,31 @@ def main():
         print(f"[bench] cpu baseline: oracle on {n} members", file=sys.stderr, flush=True)
         rec["cpu_baseline"] = cpu_baseline(w, z, pop, grids, n)
     print(json.dumps(rec), flush=True)
+
+
+def precision_vs_f64(sl, torch, z, grid, w, dev, pop, grids, out, max_ns, n=16):
+    """chi^2 of the FP32 path (the timed run's results) against the FP64 path at tol 1e-10.
+
+    Members 0, M/n, 2M/n, ... of the batch are re-solved in FP64.
+    """
+    M = pop.shape[0]
+    idx = np.arange(0, M, max(1, M // n))[:n]
+    print(f"[bench] precision: {len(idx)} members in FP64", file=sys.stderr, flush=True)
+    s64 = sl.Solver(torch.tensor(z["d"], device=dev), float(z["sigma"]), torch.tensor(z["psf"], device=dev), grid,
+                    w.half_width, reg=w.reg, dtype=torch.float64)
+    o64 = s64.solve_semilinear(torch.tensor(pop[idx], device=dev), torch.tensor(grids[idx], device=dev), w.lambdas,
+                               tol=1e-10, maxit=20000, max_ns=max_ns)
+    c64 = o64["chi2"].cpu().numpy()
+    k64 = o64["k_star"].cpu().numpy()
+    c32 = out["chi2"].cpu().numpy()[idx]
+    k32 = out["k_star"].cpu().numpy()[idx]
+    ok = (o64["status"].cpu().numpy() == 0) & (out["status"].cpu().numpy()[idx] == 0)
+    rel = np.abs(c32 - c64) / c64
+    rows = np.arange(len(idx))
+    corner = np.abs(c32[rows, k32] - c64[rows, k32]) / c64[rows, k32]
+    return {"members": int(len(idx)), "per_lambda_max": float(rel[ok].max()),
+            "per_lambda_median": float(np.median(rel[ok])), "at_corner_max": float(corner.max()),
+            "corner_index_agree": int((k32 == k64).sum())}
 
 
 def run_plain(args, sl, torch, z, grid, w, dev, lens_d, ns_d, max_ns):

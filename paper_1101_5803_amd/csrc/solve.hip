@@ -12,11 +12,12 @@
 //                                right-hand side b = L^T B^T d in FP64
 //   k_solve   (persistent, 1 block/CU)  each block pulls (member, lambda) items
 //                                and runs CG on (L^T B^T B L + lambda H^T H) s = b
-//                                from s = 0 (Eq. 7, Eq. 13-14, Sec. 2.2); source
-//                                vectors live in registers, the source p / q in
-//                                LDS, the image-space intermediate in an LDS
-//                                frame over the mapped bounding box; ends with
-//                                chi^2 (Eq. 4) and ||H s||^2 in FP64
+//                                from s = 0 (Eq. 7, Eq. 13-14, Sec. 2.2); the
+//                                iterate s and residual r in global memory (each
+//                                element touched only by its owner thread), p
+//                                and q = A p in LDS, the image-space intermediate
+//                                in an LDS frame over the mapped bounding box;
+//                                ends with chi^2 (Eq. 4) and ||H s||^2 in FP64
 //   k_corner  (1 block/member)   L-curve corner (Sec. 2.6, Eq. 20) in FP64 and
 //                                the corner solution copy
 //
