@@ -79,6 +79,15 @@ def parse():
     ap.add_argument("--no-plain", action="store_true", help="skip the one-member-per-call comparison")
     ap.add_argument("--cpu-members", type=int, default=0, help="oracle sample size (default: cores used)")
     ap.add_argument("--no-autotune", action="store_true", help="default kernel variant instead of the autotuned one")
+    ap.add_argument("--search", action="store_true",
+                    help="instead of the throughput line: plain vs surrogate-screened GA on the c5 settings")
+    ap.add_argument("--search-seeds", type=int, default=3)
+    ap.add_argument("--gens", type=int, default=30)
+    ap.add_argument("--pop", type=int, default=819)
+    ap.add_argument("--fanout", type=int, default=10)
+    ap.add_argument("--pretrain", type=int, default=20000, help="surrogate pre-training solves (c5 training set)")
+    ap.add_argument("--select", default="per_parent", choices=["per_parent", "global"])
+    ap.add_argument("--clip-quantile", type=float, default=0.1, help="surrogate targets clipped at this quantile")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run one device-to-device copy of MIB MiB (a known-size kernel that scales "
                          "hardware byte counters)")
@@ -131,6 +140,9 @@ def main():
 
     import paper_1101_5803_amd as sl
     import synthgen
+
+    if args.search:
+        return search_main(args, torch, sl, synthgen)
 
     w = synthgen.C3
     z = np.load(os.path.join(ROOT, "tests", "data", "c2.npz"))
@@ -254,6 +266,59 @@ def precision_vs_f64(sl, torch, z, grid, w, dev, pop, grids, out, max_ns, n=16):
     return {"members": int(len(idx)), "per_lambda_max": float(rel[ok].max()),
             "per_lambda_median": float(np.median(rel[ok])), "at_corner_max": float(corner.max()),
             "corner_index_agree": int((k32 == k64).sum())}
+
+
+def search_main(args, torch, sl, synthgen):
+    """c5: plain GA vs surrogate-screened GA, same seeds; counts full solves to reach the plain search's best."""
+    from paper_1101_5803_amd import search
+    w = synthgen.C5
+    z = np.load(os.path.join(ROOT, "tests", "data", "c2.npz"))
+    dev = torch.device("cuda:0")
+    solver = sl.Solver(torch.tensor(z["d"], device=dev), float(z["sigma"]), torch.tensor(z["psf"], device=dev),
+                       sl.Grid(w.nx, w.ny, w.pix, w.nsub_model), w.half_width, reg=w.reg, dtype=torch.float32)
+    box = search.Box(synthgen.PRIOR_LO, synthgen.PRIOR_HI)
+    fit = search.SolverFitness(solver, box, w.ns, w.lambdas, tol=w.tol)
+    P, G, F = args.pop, args.gens, args.fanout
+    # surrogate training set: solves of genomes drawn uniformly in the prior box
+    t0 = time.perf_counter()
+    U0 = box.to_unit(synthgen.population(w.seed, args.pretrain))
+    f0 = np.concatenate([fit(U0[i:i + 4096]) for i in range(0, len(U0), 4096)])
+    ok = np.isfinite(f0)
+    sur0 = search.Surrogate(dev, seed=w.seed, clip_quantile=args.clip_quantile)
+    sur0.train(U0[ok], np.log(f0[ok]), steps=2000, seed=0)
+    pre_s = time.perf_counter() - t0
+    print(f"[search] pre-training: {args.pretrain} solves + 2000 Adam steps in {pre_s:.1f} s", file=sys.stderr,
+          flush=True)
+    runs = []
+    for seed in range(100, 100 + args.search_seeds):
+        X0 = box.to_unit(synthgen.population(seed, P))
+        dp = synthgen.ga_draws(seed, P, G)
+        ds = synthgen.ga_draws(seed, P * F, G)
+        t1 = time.perf_counter()
+        plain = search.GeneticSearch(fit, X0)
+        for g in range(G):
+            plain.step({k: v[g] for k, v in dp.items()})
+        t_plain = time.perf_counter() - t1
+        sur = search.Surrogate(dev, seed=w.seed, clip_quantile=args.clip_quantile)
+        sur.load_state(sur0.state())
+        t1 = time.perf_counter()
+        scr = search.ScreenedSearch(fit, X0, sur, fanout=F, train_steps=50, pretrain_steps=0, select=args.select)
+        for g in range(G):
+            scr.step({k: v[g] for k, v in ds.items()})
+        t_scr = time.perf_counter() - t1
+        target = plain.history[-1] * 1.01
+        hit = [i for i, h in enumerate(scr.history) if h <= target]
+        solves_to_target = (hit[0] + 1) * P if hit else None
+        runs.append({"seed": seed, "plain_best": plain.history[-1], "screened_best": scr.history[-1],
+                     "plain_solves": plain.full_solves, "screened_solves_to_plain_best_1pct": solves_to_target,
+                     "plain_s": round(t_plain, 2), "screened_s": round(t_scr, 2),
+                     "plain_history": [round(h, 2) for h in plain.history],
+                     "screened_history": [round(h, 2) for h in scr.history]})
+        print(f"[search] seed {seed}: plain {plain.history[-1]:.1f} screened {scr.history[-1]:.1f} "
+              f"solves-to-target {solves_to_target}", file=sys.stderr, flush=True)
+    print(json.dumps({"experiment": "c5 screened vs plain GA", "pop": P, "gens": G, "fanout": F,
+                      "select": args.select, "clip_quantile": args.clip_quantile,
+                      "pretrain_solves": args.pretrain, "pretrain_s": round(pre_s, 1), "runs": runs}), flush=True)
 
 
 def run_plain(args, sl, torch, z, grid, w, dev, lens_d, ns_d, max_ns):

@@ -18,9 +18,9 @@ Linkage learning, niching, adaptive control and islands are not modelled.
 All random numbers are inputs (a dict of one generation's draws).
 
 Surrogate screening (not in the paper): each parent proposes `fanout`
-candidates; the device MLP predicts ln chi^2 of every candidate; only the
-`pop` candidates with the lowest prediction go to the full solve and the
-tournament.  Every full solve joins the surrogate's training set.
+candidates; the device MLP predicts ln chi^2 of every candidate; each
+parent's best-predicted candidate goes to the full solve and the tournament.
+Every full solve joins the surrogate's training set.
 """
 from __future__ import annotations
 
@@ -121,9 +121,14 @@ class SolverFitness:
 
 
 class Surrogate:
-    """Device MLP predicting ln chi^2 from unit genes (inputs 2u - 1, standardised target)."""
+    """Device MLP predicting ln chi^2 from unit genes (inputs 2u - 1, standardised target).
 
-    def __init__(self, device, seed: int = 0, lr: float = 1e-3, batch: int = 1024):
+    Targets above the `clip_quantile` quantile of the training set are clipped
+    to it, so the network spends its capacity on the low-chi^2 region that the
+    screen has to rank; the rest of the box only needs to predict "bad".
+    """
+
+    def __init__(self, device, seed: int = 0, lr: float = 1e-3, batch: int = 1024, clip_quantile: float = 0.1):
         rng = np.random.default_rng(seed)
         w = []
         for a, b in ((7, 256), (256, 256), (256, 1)):
@@ -135,6 +140,7 @@ class Surrogate:
         self.v = torch.zeros_like(self.params)
         self.t = 0
         self.lr, self.batch = float(lr), int(batch)
+        self.clip_quantile = float(clip_quantile)   # targets above this quantile are clipped to it
         self.mu, self.sd = 0.0, 1.0
 
     def predict(self, U: np.ndarray) -> np.ndarray:
@@ -146,6 +152,8 @@ class Surrogate:
         """`steps` Adam steps on minibatches drawn (seeded) from (U, ln f); returns the last batch loss."""
         U = np.asarray(U, dtype=np.float64)
         lnf = np.asarray(lnf, dtype=np.float64)
+        if self.clip_quantile < 1.0:
+            lnf = np.minimum(lnf, np.quantile(lnf, self.clip_quantile))
         self.mu, self.sd = float(lnf.mean()), float(lnf.std() + 1e-12)
         x = torch.tensor(2.0 * U - 1.0, dtype=torch.float32, device=self.device)
         y = torch.tensor((lnf - self.mu) / self.sd, dtype=torch.float32, device=self.device)
@@ -245,14 +253,21 @@ class ScreenedSearch(GeneticSearch):
     """GA whose offspring are pre-screened by the device surrogate.
 
     Each generation: fanout * pop candidates (candidate c descends from parent
-    c mod pop), surrogate prediction of ln chi^2 for all, the pop candidates
-    with the lowest prediction (ties by index) are fully solved and enter the
-    tournament; then `train_steps` Adam steps on every full solve so far.
+    c mod pop) and a surrogate prediction of ln chi^2 for all of them.  pop
+    candidates are fully solved and enter the tournament:
+      * select="per_parent" (default): each parent's candidate with the lowest
+        prediction (ties to the first), so every parent still has exactly one
+        child, as in the plain GA;
+      * select="global": the pop lowest predictions over all candidates.
+    Then `train_steps` Adam steps on every full solve so far.
     """
 
     def __init__(self, fitness, X0, surrogate: Surrogate, fanout: int = 10, train_steps: int = 50,
-                 cfg: GAConfig = GAConfig(), log=None, pretrain_steps: int = 200):
+                 cfg: GAConfig = GAConfig(), log=None, pretrain_steps: int = 200, select: str = "per_parent"):
         super().__init__(fitness, X0, cfg, log)
+        if select not in ("per_parent", "global"):
+            raise ValueError("select must be 'per_parent' or 'global'")
+        self.select = select
         self.surrogate, self.fanout, self.train_steps = surrogate, int(fanout), int(train_steps)
         U, lnf = self.training_set()
         if pretrain_steps and U.shape[0]:
@@ -265,7 +280,10 @@ class ScreenedSearch(GeneticSearch):
         cand = make_offspring(self.X, np.arange(C) % P, draws["partner"][:C] % P, draws["xstrength"][:C],
                               draws["mut_mask"][:C], draws["mut_step"][:C], self.cfg)
         pred = self.surrogate.predict(cand)
-        pick = np.argsort(pred, kind="stable")[:P]
+        if self.select == "global":
+            pick = np.argsort(pred, kind="stable")[:P]
+        else:   # candidates of parent p are p, p + P, p + 2P, ...
+            pick = np.arange(P) + P * np.argmin(pred.reshape(self.fanout, P), axis=0)
         Y = cand[pick]
         fY = self.fitness(Y)
         perm = draws["perm"][:C]
@@ -283,10 +301,11 @@ class ScreenedSearch(GeneticSearch):
             self.log(dict(generation=self.generation, surrogate_train_loss=loss))
 
     def _extra_state(self) -> dict:
-        return dict(fanout=self.fanout, train_steps=self.train_steps, **self.surrogate.state())
+        return dict(fanout=self.fanout, train_steps=self.train_steps, select=self.select, **self.surrogate.state())
 
     def _resume_extra(self, z, surrogate: Surrogate | None = None) -> None:
         self.fanout, self.train_steps = int(z["fanout"]), int(z["train_steps"])
+        self.select = str(z["select"])
         self.surrogate = surrogate
         self.surrogate.load_state(z)
 
