@@ -383,8 +383,8 @@ __device__ __forceinline__ int len_bucket(int c) {
 // (row << 16 | col); entry j of the node at position p sits at
 // ptr[p/64] + 64 j + p%64, every slice padded to its longest row with
 // entries (offset 0, weight 0) -- offset 0 is a frame halo element, always
-// zero.  Entries of a node are sorted by frame offset, so the per-node sum
-// has a fixed order.  Falls back to plain CSR in node order (ptr = row
+// zero.  Entries of a node are filled in a fixed order, so the per-node sum
+// is the same on every run.  Falls back to plain CSR in node order (ptr = row
 // starts) when the padded form exceeds the capacity; returns 1 for
 // sliced-ELL, 0 for CSR.  lds: LDS ints (>= 2 I + 64 + 128).
 template <typename T>
@@ -498,35 +498,50 @@ __device__ int build_transpose(const SolveArgs& a, int m, int ns, int slots, con
     }
   for (int i = tid; i < I; i += blockDim.x) cnt[i] = 0;   // fill cursors
   __syncthreads();
-  for (int t = tid; t < slots; t += blockDim.x) {
-    const int rc = pix[t];
-    if (rc < 0) continue;
-    const int off = ((rc >> 16) - bbox[0] + halo) * pitch + ((rc & 0xFFFF) - bbox[2] + halo);
-    const int np = pixel_pairs(t, ns, n2, cellp, fxp, fyp, node, wt);
-    for (int q = 0; q < np; ++q) {
-      const int i = node[q];
-      const int j = atomicAdd(&cnt[i], 1);
-      const int p = ipos[i];
-      const long e = sell ? (long)rp[p >> 6] + 64L * j + (p & 63) : (long)rp[i] + j;
-      ent[e].off = off;
-      ent[e].w = (T)wt[q];
-    }
-  }
-  __syncthreads();
-  // fixed summation order: insertion-sort every row by frame offset
-  for (int i = tid; i < I; i += blockDim.x) {
-    const int n = cnt[i];
-    const int p = ipos[i];
-    const long base = sell ? (long)rp[p >> 6] + (p & 63) : (long)rp[i];
-    const int step = sell ? 64 : 1;
-    for (int j = 1; j < n; ++j) {
-      const LtEntry<T> x = ent[base + (long)j * step];
-      int f = j - 1;
-      while (f >= 0 && ent[base + (long)f * step].off > x.off) {
-        ent[base + (long)(f + 1) * step] = ent[base + (long)f * step];
-        --f;
+  // Fill in a fixed order without sorting: one wave walks the slots 64 at a
+  // time; for pair q of every lane, lanes holding the same node take
+  // consecutive positions in lane order (a pixel's pairs have distinct nodes).
+  // Entries of a node are therefore ordered by (slot group, q, lane), the same
+  // on every run.
+  if (tid < 64) {
+    const int lane = tid;
+    for (int t0 = 0; t0 < slots; t0 += 64) {
+      const int t = t0 + lane;
+      int np = 0, off = 0;
+      if (t < slots) {
+        const int rc = pix[t];
+        if (rc >= 0) {
+          off = ((rc >> 16) - bbox[0] + halo) * pitch + ((rc & 0xFFFF) - bbox[2] + halo);
+          np = pixel_pairs(t, ns, n2, cellp, fxp, fyp, node, wt);
+        }
       }
-      ent[base + (long)(f + 1) * step] = x;
+      int npmax = np;
+      for (int o = 32; o > 0; o >>= 1) npmax = max(npmax, __shfl_xor(npmax, o, 64));
+      for (int q = 0; q < npmax; ++q) {
+        const int key = q < np ? node[q] : -1;
+        int rank = 0, total = 0;
+        for (int l = 0; l < 64; ++l) {
+          const int kl = __shfl(key, l, 64);
+          if (kl == key) {
+            ++total;
+            if (l < lane) ++rank;
+          }
+        }
+        const int j = key >= 0 ? cnt[key] + rank : 0;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        if (key >= 0 && rank == total - 1) cnt[key] = j + 1;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        if (key >= 0) {
+          const int p = ipos[key];
+          const long e = sell ? (long)rp[p >> 6] + 64L * j + (p & 63) : (long)rp[key] + j;
+          ent[e].off = off;
+          ent[e].w = (T)wt[q];
+        }
+      }
     }
   }
   __syncthreads();
