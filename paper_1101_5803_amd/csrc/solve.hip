@@ -368,6 +368,40 @@ __device__ int pixel_pairs(int t, int ns, int n2, const int32_t* cellp, const T*
   return cnt;
 }
 
+// pixel_pairs for 2 x 2 subpixels with everything in registers: the 16
+// (subpixel, corner) pairs in the same order, a pair whose node already
+// occurred folds its weight into the first occurrence (same summation order
+// as pixel_pairs); folded pairs get node -1.
+template <typename T>
+__device__ __forceinline__ void pixel_pairs4(int t, int ns, const int32_t* cellp, const T* fxp, const T* fyp,
+                                             int (&node)[16], double (&wt)[16]) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int c = cellp[(long)t * 4 + k];
+    const double fx = (double)fxp[(long)t * 4 + k], fy = (double)fyp[(long)t * 4 + k];
+    const bool in = c >= 0;
+    node[4 * k + 0] = in ? c : -1;
+    node[4 * k + 1] = in ? c + 1 : -1;
+    node[4 * k + 2] = in ? c + ns : -1;
+    node[4 * k + 3] = in ? c + ns + 1 : -1;
+    wt[4 * k + 0] = (1 - fx) * (1 - fy) * 0.25;
+    wt[4 * k + 1] = fx * (1 - fy) * 0.25;
+    wt[4 * k + 2] = (1 - fx) * fy * 0.25;
+    wt[4 * k + 3] = fx * fy * 0.25;
+  }
+#pragma unroll
+  for (int i = 1; i < 16; ++i) {
+    bool folded = node[i] < 0;
+#pragma unroll
+    for (int j = 0; j < i; ++j) {
+      const bool hit = !folded && node[j] == node[i];
+      wt[j] += hit ? wt[i] : 0.0;
+      folded = folded || hit;
+    }
+    if (folded) node[i] = -1;
+  }
+}
+
 // Quarter-octave bucket of a row length (0 for empty rows): rows in one
 // bucket differ by less than 19%.
 __device__ __forceinline__ int len_bucket(int c) {
@@ -407,10 +441,22 @@ __device__ int build_transpose(const SolveArgs& a, int m, int ns, int slots, con
   for (int i = tid; i < 128; i += blockDim.x) hist[i] = 0;
   if (tid == 0) totals[0] = totals[1] = 0;
   __syncthreads();
-  for (int t = tid; t < slots; t += blockDim.x) {
-    if (pix[t] < 0) continue;
-    const int np = pixel_pairs(t, ns, n2, cellp, fxp, fyp, node, wt);
-    for (int q = 0; q < np; ++q) atomicAdd(&cnt[node[q]], 1);
+  if (n2 == 4) {
+    for (int t = tid; t < slots; t += blockDim.x) {
+      if (pix[t] < 0) continue;
+      int nd[16];
+      double ww[16];
+      pixel_pairs4(t, ns, cellp, fxp, fyp, nd, ww);
+#pragma unroll
+      for (int q = 0; q < 16; ++q)
+        if (nd[q] >= 0) atomicAdd(&cnt[nd[q]], 1);
+    }
+  } else {
+    for (int t = tid; t < slots; t += blockDim.x) {
+      if (pix[t] < 0) continue;
+      const int np = pixel_pairs(t, ns, n2, cellp, fxp, fyp, node, wt);
+      for (int q = 0; q < np; ++q) atomicAdd(&cnt[node[q]], 1);
+    }
   }
   __syncthreads();
   for (int i = tid; i < I; i += blockDim.x) atomicAdd(&hist[len_bucket(cnt[i])], 1);
@@ -424,27 +470,36 @@ __device__ int build_transpose(const SolveArgs& a, int m, int ns, int slots, con
     }
   }
   __syncthreads();
-  // stable placement in node order: one wave per bucket pass keeps it deterministic
+  // stable placement in node order: one wave per bucket pass keeps it deterministic.
+  // Only this wave touches hist[] here, and one wave's LDS accesses complete in
+  // order, so wavefront-scope fences (compiler ordering, no wait on the global
+  // stores) around the wave barrier order its LDS read-modify-writes.
   if (tid < 64) {
     for (int i0 = 0; i0 < I; i0 += 64) {
       const int i = i0 + tid;
       const int b = i < I ? len_bucket(cnt[i]) : -1;
-      // rank of lane among lower lanes with the same bucket
-      int before = 0;
-      for (int l = 0; l < 64; ++l) {
-        const int bl = __shfl(b, l, 64);
-        if (l < tid && bl == b) ++before;
+      // rank of the lane among lower lanes with the same bucket, and the bucket's count
+      int before = 0, total = 0;
+      for (int l = 0; l < 64; ++l) {   // uniform lane index: v_readlane, no LDS round trip
+        const int bl = __builtin_amdgcn_readlane(b, l);
+        if (bl == b) {
+          ++total;
+          if (l < tid) ++before;
+        }
       }
+      const int p = i < I ? hist[b] + before : 0;
       if (i < I) {
-        const int p = hist[b] + before;
         ipos[i] = p;
         perm[p] = ((i / ns) << 16) | (i % ns);
       }
-      // advance every bucket by its count in this group of 64 (lanes hold distinct buckets)
-      for (int l = 0; l < 64; ++l) {
-        const int bl = __shfl(b, l, 64);
-        if (tid == 0 && bl >= 0) hist[bl] += 1;
-      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      // the bucket's last lane advances it past this group's nodes
+      if (i < I && before == total - 1) hist[b] = p + 1;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
   }
   __syncthreads();
@@ -496,14 +551,62 @@ __device__ int build_transpose(const SolveArgs& a, int m, int ns, int slots, con
       ent[e].off = 0;
       ent[e].w = (T)0;
     }
-  for (int i = tid; i < I; i += blockDim.x) cnt[i] = 0;   // fill cursors
+  // entry base of every node: ipos[] becomes the index of its first entry
+  for (int i = tid; i < I; i += blockDim.x) {
+    const int p = ipos[i];
+    ipos[i] = sell ? rp[p >> 6] + (p & 63) : rp[i];
+    cnt[i] = 0;   // fill cursors
+  }
   __syncthreads();
+  const int estep = sell ? 64 : 1;
   // Fill in a fixed order without sorting: one wave walks the slots 64 at a
   // time; for pair q of every lane, lanes holding the same node take
   // consecutive positions in lane order (a pixel's pairs have distinct nodes).
   // Entries of a node are therefore ordered by (slot group, q, lane), the same
   // on every run.
-  if (tid < 64) {
+  if (tid < 64 && n2 == 4) {
+    const int lane = tid;
+    for (int t0 = 0; t0 < slots; t0 += 64) {
+      const int t = t0 + lane;
+      int nd[16];
+      double ww[16];
+      int off = 0;
+      const int rc = t < slots ? pix[t] : -1;
+      if (rc >= 0) {
+        off = ((rc >> 16) - bbox[0] + halo) * pitch + ((rc & 0xFFFF) - bbox[2] + halo);
+        pixel_pairs4(t, ns, cellp, fxp, fyp, nd, ww);
+      } else {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) nd[q] = -1;
+      }
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int key = nd[q];
+        if (!__builtin_amdgcn_readfirstlane((int)(__ballot(key >= 0) != 0ull))) continue;   // uniform
+        int rank = 0, total = 0;
+        for (int l = 0; l < 64; ++l) {
+          const int kl = __builtin_amdgcn_readlane(key, l);
+          if (kl == key) {
+            ++total;
+            if (l < lane) ++rank;
+          }
+        }
+        const int j = key >= 0 ? cnt[key] + rank : 0;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (key >= 0 && rank == total - 1) cnt[key] = j + 1;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (key >= 0) {
+          const long e = (long)ipos[key] + (long)estep * j;
+          ent[e].off = off;
+          ent[e].w = (T)ww[q];
+        }
+      }
+    }
+  } else if (tid < 64) {
     const int lane = tid;
     for (int t0 = 0; t0 < slots; t0 += 64) {
       const int t = t0 + lane;
@@ -521,23 +624,22 @@ __device__ int build_transpose(const SolveArgs& a, int m, int ns, int slots, con
         const int key = q < np ? node[q] : -1;
         int rank = 0, total = 0;
         for (int l = 0; l < 64; ++l) {
-          const int kl = __shfl(key, l, 64);
+          const int kl = __builtin_amdgcn_readlane(key, l);
           if (kl == key) {
             ++total;
             if (l < lane) ++rank;
           }
         }
         const int j = key >= 0 ? cnt[key] + rank : 0;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         if (key >= 0 && rank == total - 1) cnt[key] = j + 1;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         if (key >= 0) {
-          const int p = ipos[key];
-          const long e = sell ? (long)rp[p >> 6] + 64L * j + (p & 63) : (long)rp[key] + j;
+          const long e = (long)ipos[key] + (long)estep * j;
           ent[e].off = off;
           ent[e].w = (T)wt[q];
         }
