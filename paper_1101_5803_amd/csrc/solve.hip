@@ -41,8 +41,8 @@ namespace sl {
 
 constexpr int kNT = 1024;     // threads per solve block
 constexpr int kWaves = kNT / kWave;
-constexpr int kSegR = 4;
-constexpr int kUpd = 4;   // CG vector-update chunk (nodes per thread)       // outputs per lane in a banded pass
+constexpr int kSegR = 4;       // outputs per lane in a banded pass
+constexpr int kUpd = 4;        // CG vector-update chunk (nodes per thread)
 constexpr int kMaxCK = 31;
 
 struct alignas(16) MemberInfo {
@@ -938,12 +938,13 @@ __device__ __forceinline__ T pixel_gather(const T* X, int ns, int n2, int t, con
       }
     }
     const int cl[4] = {c4.x, c4.y, c4.z, c4.w};
+    // branch-free: an off-grid subpixel (cell -1) reads node 0 and adds zero
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      if (cl[k] < 0) continue;
-      const int c = cl[k];
-      acc += (1 - fy[k]) * ((1 - fx[k]) * X[c] + fx[k] * X[c + 1]) +
-             fy[k] * ((1 - fx[k]) * X[c + ns] + fx[k] * X[c + ns + 1]);
+      const int c = max(cl[k], 0);
+      const T v = (1 - fy[k]) * ((1 - fx[k]) * X[c] + fx[k] * X[c + 1]) +
+                  fy[k] * ((1 - fx[k]) * X[c + ns] + fx[k] * X[c + ns + 1]);
+      acc += cl[k] >= 0 ? v : (T)0;
     }
     return acc;
   }
@@ -1097,10 +1098,16 @@ __device__ void run_item(const SolveArgs& a, const MemberInfo& mi, int m, int kl
       st = SL_ST_OK;
       break;
     }
-    // y = L p into the frame (P holds p, Q and the frame are zero)
-    for (int t = tid; t < M; t += kNT) {
+    // y = L p into the frame (P holds p, the frame is zero); two pixels per
+    // thread and step so that their table loads are in flight together
+    for (int t = tid; t < M; t += 2 * kNT) {
+      const int t2 = t + kNT;
       const int rc = pix[t];
-      if (rc >= 0) F0[(rc >> 16) * pitch + (rc & 0xFFFF) + fo] = pixel_gather(P, ns, n2, t, cellp, fxp, fyp) * inv_n2;
+      const int rc2 = t2 < M ? pix[t2] : -1;
+      const T v1 = pixel_gather(P, ns, n2, t, cellp, fxp, fyp);
+      const T v2 = t2 < M ? pixel_gather(P, ns, n2, t2, cellp, fxp, fyp) : (T)0;
+      if (rc >= 0) F0[(rc >> 16) * pitch + (rc & 0xFFFF) + fo] = v1 * inv_n2;
+      if (rc2 >= 0) F0[(rc2 >> 16) * pitch + (rc2 & 0xFFFF) + fo] = v2 * inv_n2;
     }
     __syncthreads();
     if (sep) {   // sep comes from a scalar load: uniform
@@ -1149,38 +1156,50 @@ __device__ void run_item(const SolveArgs& a, const MemberInfo& mi, int m, int kl
     double pq = 0.0;
     {
       const int32_t* perm = a.lt_perm + (long)m * a.I_max;
-      for (int idx = tid; idx < I; idx += kNT) {
-        T acc = 0;
-        int i, rn_, cn_;
-        if (sell) {
-          // sliced-ELL in length-sorted node order: one contiguous 64-entry block per step
-          const int pk = perm[idx];
-          rn_ = pk >> 16;
-          cn_ = pk & 0xFFFF;
-          i = rn_ * ns + cn_;
-          const long base = lt_rp[idx >> 6] + (idx & 63);
-          const int len = (lt_rp[(idx >> 6) + 1] - lt_rp[idx >> 6]) >> 6;
+      if (sell) {
+        // sliced-ELL in length-sorted node order: wave w takes slices w, w + 16, ...;
+        // the slice bounds are wave-uniform (scalar loads) and every lane of a
+        // slice has `len` entries (padding reads the zero halo), eight in flight
+        const int wid = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+        const int nslices = (I + 63) >> 6;
+        for (int sl = wid; sl < nslices; sl += kNT / 64) {
+          const int idx = sl * 64 + lane;
+          const int b0 = lt_rp[sl];
+          const int len = (lt_rp[sl + 1] - b0) >> 6;
+          const int pk = idx < I ? perm[idx] : 0;
+          const LtEntry<T>* ep = lt_e + b0 + lane;
+          T acc = 0;
           int j = 0;
-          for (; j + 3 < len; j += 4) {
-            const LtEntry<T> x0 = lt_e[base + 64L * j], x1 = lt_e[base + 64L * (j + 1)];
-            const LtEntry<T> x2 = lt_e[base + 64L * (j + 2)], x3 = lt_e[base + 64L * (j + 3)];
-            acc += x0.w * F[x0.off] + x1.w * F[x1.off] + x2.w * F[x2.off] + x3.w * F[x3.off];
+          for (; j + 7 < len; j += 8) {
+            LtEntry<T> x[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) x[u] = ep[64L * (j + u)];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc += x[u].w * F[x[u].off];
           }
           for (; j < len; ++j) {
-            const LtEntry<T> x0 = lt_e[base + 64L * j];
+            const LtEntry<T> x0 = ep[64L * j];
             acc += x0.w * F[x0.off];
           }
-        } else {
-          i = idx;
-          rn_ = i / ns;
-          cn_ = i - rn_ * ns;
+          if (idx < I) {
+            const int rn_ = pk >> 16, cn_ = pk & 0xFFFF, i = rn_ * ns + cn_;
+            const T pv = P[i];
+            const T qv = acc + lamT * (ident ? pv : hth_node(P, ns, rn_, cn_));
+            Q[i] = qv;
+            pq += (double)pv * (double)qv;
+          }
+        }
+      } else {
+        for (int i = tid; i < I; i += kNT) {
+          T acc = 0;
           const int e0 = lt_rp[i], e1 = lt_rp[i + 1];
           for (int e = e0; e < e1; ++e) acc += lt_e[e].w * F[lt_e[e].off];
+          const int rn_ = i / ns, cn_ = i - rn_ * ns;
+          const T pv = P[i];
+          const T qv = acc + lamT * (ident ? pv : hth_node(P, ns, rn_, cn_));
+          Q[i] = qv;
+          pq += (double)pv * (double)qv;
         }
-        const T pv = P[i];
-        const T qv = acc + lamT * (ident ? pv : hth_node(P, ns, rn_, cn_));
-        Q[i] = qv;
-        pq += (double)pv * (double)qv;
       }
     }
     pq = block_sum1(pq, red, 0);
