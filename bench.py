@@ -73,7 +73,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--members", type=int, default=256)
+    ap.add_argument("--workload", default="c3", choices=["c3", "c4"],
+                    help="c3 (default, the headline): 256 members on the 128x128 image; c4: 1024 members on the "
+                         "200x200 image")
+    ap.add_argument("--members", type=int, default=0, help="members (default: 256 for c3, 1024 for c4)")
     ap.add_argument("--plain-members", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the one-member-per-call comparison")
@@ -144,14 +147,26 @@ def main():
     if args.search:
         return search_main(args, torch, sl, synthgen)
 
-    w = synthgen.C3
-    z = np.load(os.path.join(ROOT, "tests", "data", "c2.npz"))
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    M = args.members
-    pop = synthgen.population(w.seed, 256)[:M]
-    grids = synthgen.member_grids(w.seed, 256)[:M]
-    max_ns = 96
+    if args.workload == "c3":
+        w = synthgen.C3
+        z = np.load(os.path.join(ROOT, "tests", "data", "c2.npz"))
+        M = args.members or 256
+        pop = synthgen.population(w.seed, 256)[:M]
+        grids = synthgen.member_grids(w.seed, 256)[:M]
+        max_ns = 96
+        desc = ("c3: 256 SIE+shear lens sets, 128x128 image at 0.05\", 2x2 subpixels, source grids 32..96 nodes per "
+                "side over +-1\", 15x15 Gaussian PSF (FWHM 3 px), curvature H, 16 lambdas 1e-4..1e2, CG tol 1e-7")
+    else:
+        w = synthgen.C4
+        z = np.load(os.path.join(ROOT, "tests", "data", "c4.npz"))
+        M = args.members or 1024
+        pop = synthgen.population(w.seed, M)
+        grids = np.full(M, w.ns, dtype=np.int32)
+        max_ns = w.ns
+        desc = ("c4: 1024 SIE+shear lens sets, 200x200 image at 0.05\", 2x2 subpixels, 100x100 source nodes over "
+                "+-1\", 21x21 Gaussian PSF (FWHM 4 px), curvature H, 24 lambdas 1e-4..1e2, CG tol 1e-7")
     grid = sl.Grid(w.nx, w.ny, w.pix, w.nsub_model)
     solver = sl.Solver(torch.tensor(z["d"], device=dev), float(z["sigma"]), torch.tensor(z["psf"], device=dev),
                        grid, w.half_width, reg=w.reg, dtype=torch.float32)
@@ -197,7 +212,7 @@ def main():
     kern_s = kern_ms / max(launches, 1) / 1e3
     tflops = flops / kern_s / 1e12
     gbs = tbytes / kern_s / 1e9
-    traffic = measured_traffic()
+    traffic = measured_traffic() if args.workload == "c3" else None
     roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": traffic,
             "kernel": "k_solve (persistent CG)", "kernel_ms": round(kern_s * 1e3, 3),
@@ -223,9 +238,7 @@ def main():
         "metric": METRIC, "value": round(value, 2), "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "c3: 256 SIE+shear lens sets, 128x128 image at 0.05\", 2x2 subpixels, source "
-                               "grids 32..96 nodes per side over +-1\", 15x15 Gaussian PSF (FWHM 3 px), curvature "
-                               "H, 16 lambdas 1e-4..1e2, CG tol 1e-7",
+        "config": {"workload": desc,
                    "members": M, "n_lambda": len(w.lambdas), "reductions": "f64", "kernel_variant": tuned,
                    "cg_iterations": int(iters.sum()),
                    "status_counts": {int(k): int(v) for k, v in zip(*np.unique(status, return_counts=True))}},
@@ -235,7 +248,7 @@ def main():
         "chi2_rel_err_vs_f64": prec,
         "roofline": roof,
     }
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.workload == "c3":
         ncpu = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
         n = args.cpu_members or max(1, min(16, ncpu))
         print(f"[bench] cpu baseline: oracle on {n} members", file=sys.stderr, flush=True)
