@@ -259,3 +259,58 @@ def test_c4_full_launch_sampled(semilin):
     assert np.all(np.isin(out["status"], [0, 1, 2]))
     ok = out["status"] == 0
     assert np.all(out["chi2"][ok] > 0)
+
+
+def test_max_sizes_normal_equations(semilin):
+    """Largest image (256 x 256) and source grid (128 x 128) with a 21 x 21 PSF,
+    one member at the smallest grid (2 x 2) and one that maps nothing, in one
+    launch.  At this size the oracle is too slow, so the solution is checked
+    through properties that hold at any size, with the stand-alone operators
+    (themselves oracle-tested) in FP64: the normal-equation residual
+    ||(L^T B^T B L + lambda H^T H) s - L^T B^T d|| / ||L^T B^T d|| and chi^2."""
+    nx = ny = 256
+    pix, R = 0.025, 1.0
+    grid = semilin.Grid(nx, ny, pix, 2)
+    psf = mock.gaussian_psf(21, 3.0)
+    rng = np.random.default_rng(17)
+    d = rng.standard_normal((ny, nx))
+    sigma = 1.0
+    G = np.array([[1.0, 0.7, 0.5, 0.05, 1.0, 0.01, 0.02],
+                  [1.1, 0.9, 1.0, 0.02, 0.2, -0.02, 0.0],
+                  [20.0, 1.0, 0.0, 0.0, 0.0, 0.0, 30.0]])   # every ray lands ~20" away: maps nothing
+    ns = np.array([128, 2, 64], dtype=np.int32)
+    lams = [1e-2, 1.0]
+    out = _run(semilin, d, sigma, psf, grid, R, "curvature", torch.float32, G, ns, lams, 1e-6, maxit=6000)
+    assert np.all(out["status"][:2] == 0), out["status"]
+    assert np.all(out["status"][2] == semilin._lib.ST_EMPTY)
+    assert np.all(out["k_star"][:2] == 0) and np.all(out["corner_status"][:2] == semilin._lib.ST_LCURVE)
+    uv = semilin.lens_trace(torch.tensor(G, device=DEV), grid, ns, R)
+    dd = torch.tensor(d, device=DEV)
+    pt = torch.tensor(psf, device=DEV)
+    off = out["s_off"]
+    for m in range(2):
+        n = [int(ns[m])]
+        s = torch.tensor(out["s_corner"][off[m]:off[m + 1]], device=DEV)
+        um = uv[m:m + 1].contiguous()
+        by = semilin.apply_B(pt, semilin.apply_L(um, grid, n, s).reshape(1, ny, nx))
+        chi2 = float(((by[0] - dd) ** 2).sum()) / sigma ** 2
+        assert abs(chi2 - out["chi2"][m, 0]) <= 1e-5 * chi2, (m, chi2, out["chi2"][m, 0])
+        b = semilin.apply_LT(um, grid, n, semilin.apply_BT(pt, dd.reshape(1, ny, nx)).reshape(1, -1))
+        q = semilin.apply_LT(um, grid, n, semilin.apply_BT(pt, by).reshape(1, -1)) + \
+            lams[0] * semilin.apply_HtH("curvature", n, s)
+        res = float(torch.linalg.norm(q - b) / torch.linalg.norm(b))
+        assert res <= 1e-4, (m, res)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_max_psf_vs_oracle(semilin, prec):
+    """The largest PSF (63 x 63, wider than the 40 x 36 image): direct blur path."""
+    d, sigma, psf, (nx, ny, pix), G, ns = _small_case("gauss", K=63)
+    G, ns = G[:2], ns[:2]
+    lams = [1e-2, 1.0]
+    dtype = torch.float64 if prec == "f64" else torch.float32
+    out = _run(semilin, d, sigma, psf, semilin.Grid(nx, ny, pix, 2), 1.0, "curvature", dtype, G, ns, lams,
+               1e-12 if prec == "f64" else 1e-7)
+    ref = coracle.evaluate(G, ns, 1.0, nx, ny, pix, 2, d, sigma, psf, "curvature", lams, tol=1e-12, threads=2)
+    rel = np.abs(out["chi2"] - ref["chi2"]) / ref["chi2"]
+    assert rel.max() <= (1e-9 if prec == "f64" else 1e-5), rel
