@@ -129,3 +129,25 @@ def test_curvature_H_rows():
 def test_identity_H():
     x = np.arange(9.0)
     np.testing.assert_array_equal(ops.apply_HtH(x, 3, "identity"), x)
+
+
+@pytest.mark.parametrize("n", [0.5, 0.8, 1.0, 1.5, 2.0])
+def test_sersic_bn_against_incomplete_gamma(n):
+    """b_n is defined by gamma(2n, b_n) = Gamma(2n) / 2 (half the light inside R_e);
+    the asymptotic series must agree with that root to its known accuracy."""
+    from scipy.special import gammaincinv
+    exact = gammaincinv(2.0 * n, 0.5)
+    assert abs(mock.sersic_bn(n) - exact) <= 2e-3 * exact
+
+
+@pytest.mark.parametrize("n", [0.7, 1.6])
+def test_sersic_profile_half_light_radius(n):
+    """A circular Sersic blob holds half its flux inside R_e (quadrature of the
+    profile that source_brightness evaluates)."""
+    blob = dict(kind="sersic", xc=0.0, yc=0.0, pa=0.3, q=1.0, size=0.2, n=n, amp=1.0)
+    r = np.linspace(0.0, 40 * blob["size"], 400001)
+    I = mock.source_brightness(r, np.zeros_like(r), [blob])
+    ring = 2 * np.pi * r * I
+    cum = np.concatenate([[0.0], np.cumsum(0.5 * (ring[1:] + ring[:-1]) * np.diff(r))])
+    inside = np.interp(blob["size"], r, cum)
+    assert abs(inside / cum[-1] - 0.5) <= 3e-3
