@@ -147,6 +147,8 @@ typedef struct {
   int wide_window;     /* 1: banded blur window one compiled size above the minimum */
   int lt_csr;          /* 1: transposed trace operator in CSR rows instead of sliced ELL */
   int blur_direct;     /* 1: direct K x K blur even when the PSF is separable */
+  int plain_cg;        /* 1: plain CG even where the spectral preconditioner applies (see
+                          sl_solve_semilinear); not part of the autotuner's search */
 } sl_tuning;
 
 typedef struct {
@@ -177,8 +179,18 @@ size_t sl_solve_workspace_size(const sl_problem* pb, int max_ns, int n_members, 
 /*
  * Batched regularised solve and L-curve corner of n_members lens sets
  * against one data image (Sec. 2.1-2.6, Sec. 3: the fitness of the outer
- * optimiser).  Every (member, lambda) pair is one CG solve from s = 0; all
- * pairs run in one persistent launch.
+ * optimiser).  Every (member, lambda) pair is one conjugate-gradient solve
+ * of Eq. 7 from s = 0, stopped when ||b - A s|| <= tol ||b||; all pairs run
+ * in one persistent launch.  With SL_F32 and curvature H, a pair whose
+ * lambda >= 0.05 c (and whose n x n grid fits beside the blur frame in LDS)
+ * is solved by preconditioned CG with M = c I + lambda H^T H, applied exactly
+ * through the orthonormal 2-D sine transform that diagonalises H^T H (H^T H
+ * = D^2 (x) I + I (x) D^2 with D the second-difference matrix).  c is a
+ * per-member estimate of the data term's scale, sum_i w_i b_i^2 / sum_i b_i^2
+ * with w = L^T 1 (the bilinear weight each node receives from the image
+ * pixels, L averaging the nsub^2 subpixels of a pixel).  The result is
+ * the same Eq. 7 solution to the stopping tolerance; sl_tuning.plain_cg = 1
+ * solves every pair with plain CG.
  *   lens:    device double[n_members*7]
  *   ns:      device int32[n_members], each in [2, max_ns]
  *   lambdas: host double[n_lambda], strictly ascending, positive, n_lambda <= SL_MAX_LAMBDA

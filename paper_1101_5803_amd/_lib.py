@@ -39,7 +39,8 @@ class Problem(ctypes.Structure):
 
 
 class Tuning(ctypes.Structure):
-    _fields_ = [("wide_window", ctypes.c_int), ("lt_csr", ctypes.c_int), ("blur_direct", ctypes.c_int)]
+    _fields_ = [("wide_window", ctypes.c_int), ("lt_csr", ctypes.c_int), ("blur_direct", ctypes.c_int),
+                ("plain_cg", ctypes.c_int)]
 
 
 class SolveOpts(ctypes.Structure):

@@ -18,6 +18,10 @@
 //                                and q = A p in LDS, the image-space intermediate
 //                                in an LDS frame over the mapped bounding box;
 //                                ends with chi^2 (Eq. 4) and ||H s||^2 in FP64
+//   k_split   (1 block)          moves the items that take the spectral
+//                                preconditioner to their own queues (FP32,
+//                                curvature H); k_solve<.., true> runs them as
+//                                preconditioned CG before the plain k_solve
 //   k_corner  (1 block/member)   L-curve corner (Sec. 2.6, Eq. 20) in FP64 and
 //                                the corner solution copy
 //
@@ -43,6 +47,9 @@ constexpr int kNT = 1024;     // threads per solve block
 constexpr int kWaves = kNT / kWave;
 constexpr int kSegR = 4;       // outputs per lane in a banded pass
 constexpr int kUpd = 4;        // CG vector-update chunk (nodes per thread)
+// The spectral preconditioner pays for its four n x n transforms only where
+// lambda H^T H dominates the spectrum: it is used when lambda >= kPcTheta c.
+constexpr float kPcTheta = 0.05f;
 constexpr int kMaxCK = 31;
 
 struct alignas(16) MemberInfo {
@@ -50,12 +57,16 @@ struct alignas(16) MemberInfo {
   long long off;   // start in packed vectors
   int Mtrue;       // pixels with at least one subpixel on the grid
   int sell;        // transposed operator stored as sliced-ELL (1) or CSR (0)
+  float pc_c;      // scale c of the spectral preconditioner (see k_prep)
+  int pad_[3];
 };
 
 // Device constants written by k_setup (one copy per workspace).
 struct alignas(16) Consts {
   int qhead[8];
   int qcount[8];
+  int pqhead[8];    // queues of the preconditioned items (filled by k_split)
+  int pqcount[8];
   int sep;          // PSF is rank-1
   int pad0[3];
   double sum_d2;
@@ -63,7 +74,7 @@ struct alignas(16) Consts {
 };
 
 struct Layout {
-  size_t consts, lam, taps_d, taps_f, minfo, queues, pix, cell, fx, fy, b, s_all, gframe, gz, rbuf, lt_ptr, lt_perm,
+  size_t consts, lam, taps_d, taps_f, minfo, queues, pqueues, pix, cell, fx, fy, b, s_all, gframe, gz, rbuf, lt_ptr, lt_perm,
       lt_ent,
       total;
   long long lt_cap;
@@ -100,7 +111,7 @@ struct alignas(2 * sizeof(T) > 8 ? 16 : 8) LtEntry {
 // ------------------------------------------------------------------ parameters
 struct SolveArgs {
   int nx, ny, nsub, n2, K, ck, ckt, reg, n_members, n_lambda, max_ns, maxit, lds_frame_cap;
-  int q_off, red_off, frame_off;   // byte offsets in dynamic LDS
+  int q_off, red_off, pc_off, frame_off;   // byte offsets in dynamic LDS
   int gframe_elems;                // per-block global frame size (elements)
   int slot_cap;                    // trace-table slots per member (J + 64)
   double pix, R, sigma, tol;
@@ -124,6 +135,7 @@ struct SolveArgs {
   void* taps_t;   // taps in the bulk type
   MemberInfo* minfo;
   int* queues;
+  int* pqueues;     // [8][qcap] items of the preconditioned solve
   int qcap;
   int32_t* pix_list;
   int32_t* cell;
@@ -141,6 +153,7 @@ struct SolveArgs {
   int I_max;
   int force_csr;    // variant: transposed operator as CSR rows
   int force_direct; // variant: direct K x K blur for a separable PSF
+  int plain_cg;     // variant: no spectral preconditioner
 };
 
 // ------------------------------------------------------------------ block scan
@@ -217,6 +230,8 @@ __global__ void __launch_bounds__(1024) k_setup(SolveArgs a, LamList lams) {
       const int nm = (M > q) ? (M - q + 7) / 8 : 0;
       a.consts->qcount[q] = nm * a.n_lambda;
       a.consts->qhead[q] = 0;
+      a.consts->pqcount[q] = 0;
+      a.consts->pqhead[q] = 0;
     }
     // PSF: rank-1 test and factorisation P[a][b] = gy[a] * gx[b]
     const TapIdx ti(K);
@@ -772,6 +787,27 @@ __device__ void prep_member(const SolveArgs& a, int m, MemberInfo mi, const doub
     }
   }
   __syncthreads();
+  // scale of the spectral preconditioner: c = sum_i cov_i b_i^2 / sum_i b_i^2
+  // with cov = L^T 1 (the bilinear weight each node receives), a cheap
+  // stand-in for the Rayleigh quotient <b, L^T B^T B L b> / <b, b>
+  {
+    __shared__ double pcred[32];
+    double num = 0.0, den = 0.0;
+    for (int t = tid; t < Mm; t += blockDim.x) {
+      if (pix[t] < 0) continue;
+      for (int k = 0; k < n2; ++k) {
+        const int cell = cellp[(long)t * n2 + k];
+        if (cell < 0) continue;
+        const double fx = (double)fxp[(long)t * n2 + k], fy = (double)fyp[(long)t * n2 + k];
+        const double b0 = bacc[cell], b1 = bacc[cell + 1], b2 = bacc[cell + ns], b3 = bacc[cell + ns + 1];
+        num += ((1 - fx) * (1 - fy) * b0 * b0 + fx * (1 - fy) * b1 * b1 + (1 - fx) * fy * b2 * b2 +
+                fx * fy * b3 * b3) * inv_n2;
+      }
+    }
+    for (int i = tid; i < I; i += blockDim.x) den += bacc[i] * bacc[i];
+    block_sum2(num, den, pcred);
+    if (tid == 0) mi.pc_c = den > 0.0 ? (float)(num / den) : 0.0f;
+  }
   double* bm = a.b + (long)m * a.I_max;
   for (int i = tid; i < I; i += blockDim.x) bm[i] = bacc[i];
   __syncthreads();
@@ -917,6 +953,99 @@ __device__ __forceinline__ double block_sum1(double v, double* scratch, int buf)
   return t;
 }
 
+// ---------------------------------------------------------------- spectral preconditioner
+// H^T H = D^2 (x) I + I (x) D^2 with D = tridiag(1, -2, 1) (Dirichlet second
+// differences on an n x n grid).  The orthonormal sine transform S,
+// S_jk = sqrt(2/(n+1)) sin(pi (j+1)(k+1) / (n+1)) (symmetric, S S = I),
+// diagonalises D: D = S diag(-4 sin^2(pi (k+1) / (2(n+1)))) S, so
+// M = c I + lambda H^T H = (S (x) S) diag(c + lambda (mu_j + mu_k)) (S (x) S)
+// with mu_k the eigenvalues of D^2, and M^-1 x is two 2-D transforms and a
+// division.  With x an n x n array X, (S (x) S) x = S X S.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// C = S B (n x n, row-major B in LDS) on the FP32 matrix cores, stored
+// row-major (trans = 0) or transposed (trans = 1); with `scale`, element
+// (j, k) is divided by c + lambda (mu_j + mu_k).  S comes from the table
+// tab[m] = sqrt(2/(n+1)) sin(pi m / (n+1)), m = (j+1)(k+1) mod 2(n+1).
+// All waves of the block take 16 x 16 output tiles in turn.
+// v_mfma_f32_16x16x4f32: lane l supplies A[l%16][l/16] and B[l/16][l%16];
+// accumulator element r is C[4 (l/16) + r][l%16].
+__device__ __forceinline__ void sine_mul(const float* tab, const float* mu, int n, const float* B, float* C, int trans, int scale,
+                         float c, float lam) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int lc = lane & 15, lq = lane >> 4;
+  const int nt = (n + 15) >> 4, nn2 = 2 * (n + 1);
+  for (int tile = wv; tile < nt * nt; tile += kWaves) {
+    const int i0 = (tile / nt) << 4, j0 = (tile % nt) << 4;
+    const int i = i0 + lc, j = j0 + lc;
+    // k-steps t0 = 0, 4, 8, ...: the operands of the next step are loaded
+    // before the current MFMA, and two accumulator chains alternate
+    f32x4 acc0 = {0.0f, 0.0f, 0.0f, 0.0f}, acc1 = {0.0f, 0.0f, 0.0f, 0.0f};
+    int mi = ((i + 1) * (lq + 1)) % nn2;          // table index of S[i][t], t = t0 + lq
+    const int step = (4 * (i + 1)) % nn2;
+    float av = (i < n && lq < n) ? tab[mi] : 0.0f;
+    float bv = (lq < n && j < n) ? B[lq * n + j] : 0.0f;
+    int t0 = 0;
+    for (; t0 + 4 < n; t0 += 8) {
+      mi += step;
+      if (mi >= nn2) mi -= nn2;
+      const int t1 = t0 + 4 + lq;
+      const float av1 = (i < n && t1 < n) ? tab[mi] : 0.0f;
+      const float bv1 = (t1 < n && j < n) ? B[t1 * n + j] : 0.0f;
+      acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc0, 0, 0, 0);
+      mi += step;
+      if (mi >= nn2) mi -= nn2;
+      const int t2 = t0 + 8 + lq;
+      av = (i < n && t2 < n) ? tab[mi] : 0.0f;
+      bv = (t2 < n && j < n) ? B[t2 * n + j] : 0.0f;
+      acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(av1, bv1, acc1, 0, 0, 0);
+    }
+    if (t0 < n) acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc0, 0, 0, 0);
+    const f32x4 acc = acc0 + acc1;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = i0 + 4 * lq + r, col = j0 + lc;
+      if (row < n && col < n) {
+        float v = acc[r];
+        if (scale) v = v / (c + lam * (mu[row] + mu[col]));
+        if (trans)
+          C[col * n + row] = v;
+        else
+          C[row * n + col] = v;
+      }
+    }
+  }
+}
+
+// One preconditioned-CG direction update, all threads of the block:
+// z = M^-1 r (r from r_g, the n x n scratch T in the frame, X = the Q region),
+// rz_new = <r, z>, p = z + beta p with beta = rz_new / rz_old (0 when
+// `restart`), and the scratch zeroed again.  Returns rz_new.  Kept out of
+// line so that its registers do not add to the CG loop's pressure.
+__device__ __attribute__((noinline)) double pc_apply(float* P, float* X, float* Tb, const float* tab,
+                                                     const float* mu, int n, const float* r_g, float c, float lam,
+                                                     double rz_old, int restart, double* red) {
+  const int tid = threadIdx.x, nn = n * n;
+  for (int i = tid; i < nn; i += kNT) X[(i % n) * n + i / n] = r_g[i];   // X^T
+  __syncthreads();
+  // every product is S B; the stored transposes make the next B row-major
+  sine_mul(tab, mu, n, X, Tb, 1, 0, 0.0f, 0.0f);     // (S X^T)^T = X S
+  __syncthreads();
+  sine_mul(tab, mu, n, Tb, X, 0, 1, c, lam);         // Y = S X S over the eigenvalues of M
+  __syncthreads();
+  sine_mul(tab, mu, n, X, Tb, 1, 0, 0.0f, 0.0f);     // (S Y)^T
+  __syncthreads();
+  sine_mul(tab, mu, n, Tb, X, 1, 0, 0.0f, 0.0f);     // (S (S Y)^T)^T = S Y S = z, node order
+  __syncthreads();
+  double rzn = 0.0;
+  for (int i = tid; i < nn; i += kNT) rzn += (double)r_g[i] * (double)X[i];
+  rzn = block_sum1(rzn, red, 2);
+  const float beta = restart ? 0.0f : (float)(rzn / rz_old);
+  for (int i = tid; i < nn; i += kNT) P[i] = X[i] + beta * P[i];
+  for (int e = tid; e < nn; e += kNT) Tb[e] = 0.0f;   // the scratch lies in the frame
+  return rzn;
+}
+
 // Bilinear value of the n x n subpixels of mapped pixel t: sum_k w_k . x[cell_k..]
 template <typename T>
 __device__ __forceinline__ T pixel_gather(const T* X, int ns, int n2, int t, const int32_t* cellp, const T* fxp,
@@ -1035,8 +1164,8 @@ __device__ void trivial_item(const SolveArgs& a, const MemberInfo& mi, int m, in
 // LDS: P = search direction p, Q = A p accumulator, the image frame (LDSF)
 // and reduction scratch.  The iterate s (in its output slot) and the
 // residual r live in global memory, read and written by their owner thread.
-template <typename T, int CKT, bool LDSF>
-__device__ void run_item(const SolveArgs& a, const MemberInfo& mi, int m, int kl, unsigned char* smem) {
+template <typename T, int CKT, bool LDSF, bool PC>
+__device__ __forceinline__ void run_item(const SolveArgs& a, const MemberInfo& mi, int m, int kl, unsigned char* smem) {
   const int tid = threadIdx.x;
   const long out_idx = (long)m * a.n_lambda + kl;
   T* __restrict__ s_g = reinterpret_cast<T*>(a.s_all) + out_idx * a.I_max;
@@ -1092,6 +1221,22 @@ __device__ void run_item(const SolveArgs& a, const MemberInfo& mi, int m, int kl
   }
   rr = block_sum1(rr, red, 0);
   const double stop2 = a.tol * a.tol * rr;
+  // PC: preconditioned CG with M = c I + lambda H^T H (FP32, curvature H; the
+  // caller checks that the frame holds the n x n scratch): p0 = z0 = M^-1 b.
+  double rz = rr;                                       // <r, z>
+  if constexpr (PC && sizeof(T) == 4) {
+    float* tab = reinterpret_cast<float*>(smem + a.pc_off);
+    float* mu = tab + 2 * (ns + 1);
+    const double nrm = sqrt(2.0 / (ns + 1)), pi = 3.14159265358979323846;
+    for (int e = tid; e < 2 * (ns + 1); e += kNT) tab[e] = (float)(nrm * sin(pi * e / (ns + 1)));
+    for (int e = tid; e < ns; e += kNT) {
+      const double sn = sin(pi * (e + 1) / (2.0 * (ns + 1)));
+      mu[e] = (float)(16.0 * sn * sn * sn * sn);
+    }
+    rz = pc_apply(reinterpret_cast<float*>(P), reinterpret_cast<float*>(Q), reinterpret_cast<float*>(F), tab, mu, ns,
+                  reinterpret_cast<const float*>(r_g), mi.pc_c, (float)a.lamv[kl], 0.0, 1, red);
+    __syncthreads();
+  }
   int st = SL_ST_MAXIT, it = 0;
   for (it = 0; it < a.maxit; ++it) {
     if (__builtin_amdgcn_readfirstlane((int)(rr <= stop2))) {
@@ -1209,7 +1354,7 @@ __device__ void run_item(const SolveArgs& a, const MemberInfo& mi, int m, int kl
       st = SL_ST_BREAKDOWN;
       break;
     }
-    const T alT = (T)(rr / pq);
+    const T alT = (T)((PC ? rz : rr) / pq);
     // Updates in chunks of kUpd nodes per thread: every global load of a chunk
     // is issued before the first use, and the updated residual stays in
     // registers for the direction update when the chunk covers all of I.
@@ -1237,24 +1382,31 @@ __device__ void run_item(const SolveArgs& a, const MemberInfo& mi, int m, int kl
       }
     }
     rn = block_sum1(rn, red, 1);
-    const T beta = (T)(rn / rr);
-    if (I <= kUpd * kNT) {
-#pragma unroll
-      for (int k = 0; k < kUpd; ++k) {
-        const int i = tid + k * kNT;
-        if (i < I) P[i] = rk[k] + beta * P[i];
-      }
+    if constexpr (PC && sizeof(T) == 4) {
+      float* tab = reinterpret_cast<float*>(smem + a.pc_off);
+      rz = pc_apply(reinterpret_cast<float*>(P), reinterpret_cast<float*>(Q), reinterpret_cast<float*>(F), tab,
+                    tab + 2 * (ns + 1), ns, reinterpret_cast<const float*>(r_g), mi.pc_c, (float)a.lamv[kl], rz, 0,
+                    red);
     } else {
-      for (int i0 = tid; i0 < I; i0 += kUpd * kNT) {
+      const T beta = (T)(rn / rr);
+      if (I <= kUpd * kNT) {
 #pragma unroll
         for (int k = 0; k < kUpd; ++k) {
-          const int i = i0 + k * kNT;
-          if (i < I) rk[k] = r_g[i];
-        }
-#pragma unroll
-        for (int k = 0; k < kUpd; ++k) {
-          const int i = i0 + k * kNT;
+          const int i = tid + k * kNT;
           if (i < I) P[i] = rk[k] + beta * P[i];
+        }
+      } else {
+        for (int i0 = tid; i0 < I; i0 += kUpd * kNT) {
+#pragma unroll
+          for (int k = 0; k < kUpd; ++k) {
+            const int i = i0 + k * kNT;
+            if (i < I) rk[k] = r_g[i];
+          }
+#pragma unroll
+          for (int k = 0; k < kUpd; ++k) {
+            const int i = i0 + k * kNT;
+            if (i < I) P[i] = rk[k] + beta * P[i];
+          }
         }
       }
     }
@@ -1302,13 +1454,17 @@ __device__ void run_item(const SolveArgs& a, const MemberInfo& mi, int m, int kl
 
 // Next (member, lambda) item for this block, -1 when every queue is empty;
 // thread 0 pops, the value is broadcast through LDS and made scalar.
+template <bool PC>
 __device__ __forceinline__ int fetch_item(const SolveArgs& a, int xcd, int* sh_item) {
+  int* head = PC ? a.consts->pqhead : a.consts->qhead;
+  const int* count = PC ? a.consts->pqcount : a.consts->qcount;
+  const int* queues = PC ? a.pqueues : a.queues;
   if (threadIdx.x == 0) {
     int item = -1;
     for (int x = 0; x < 8 && item < 0; ++x) {
       const int q = (xcd + x) & 7;
-      const int idx = atomicAdd(&a.consts->qhead[q], 1);
-      if (idx < a.consts->qcount[q]) item = a.queues[q * a.qcap + idx];
+      const int idx = atomicAdd(&head[q], 1);
+      if (idx < count[q]) item = queues[q * a.qcap + idx];
     }
     *sh_item = item;
   }
@@ -1318,24 +1474,63 @@ __device__ __forceinline__ int fetch_item(const SolveArgs& a, int xcd, int* sh_i
   return item;
 }
 
-template <typename T, int CKT>
+// Persistent CG kernel: each block pulls (member, lambda) items from its XCD's
+// queue (then the others').  PC = true takes the preconditioned items that
+// k_split selected (FP32 only); PC = false all the others.
+template <typename T, int CKT, bool PC>
 __global__ void __launch_bounds__(kNT) k_solve(SolveArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int sh_item;
   const int xcd = blockIdx.x & 7;
-  for (int item = fetch_item(a, xcd, &sh_item); item >= 0; item = fetch_item(a, xcd, &sh_item)) {
+  for (int item = fetch_item<PC>(a, xcd, &sh_item); item >= 0; item = fetch_item<PC>(a, xcd, &sh_item)) {
     const int m = item / a.n_lambda, kl = item % a.n_lambda;   // scalar
     const MemberInfo mi = a.minfo[m];                          // uniform address: scalar loads
-    const int status = __builtin_amdgcn_readfirstlane(mi.status);
-    const int h = mi.r1 - mi.r0 + 1, w = mi.c1 - mi.c0 + 1;
-    const int fits = __builtin_amdgcn_readfirstlane(
-        (int)((h + 4 * CKT + kSegR) * ((w + 4 * CKT) | 1) <= a.lds_frame_cap));
-    if (status != SL_ST_OK)
-      trivial_item<T>(a, mi, m, kl);
-    else if (fits)
-      run_item<T, CKT, true>(a, mi, m, kl, smem);
-    else
-      run_item<T, CKT, false>(a, mi, m, kl, smem);
+    if constexpr (PC) {
+      run_item<T, CKT, true, true>(a, mi, m, kl, smem);
+    } else {
+      const int status = __builtin_amdgcn_readfirstlane(mi.status);
+      const int h = mi.r1 - mi.r0 + 1, w = mi.c1 - mi.c0 + 1;
+      const int fits = __builtin_amdgcn_readfirstlane(
+          (int)((h + 4 * CKT + kSegR) * ((w + 4 * CKT) | 1) <= a.lds_frame_cap));
+      if (status != SL_ST_OK)
+        trivial_item<T>(a, mi, m, kl);
+      else if (fits)
+        run_item<T, CKT, true, false>(a, mi, m, kl, smem);
+      else
+        run_item<T, CKT, false, false>(a, mi, m, kl, smem);
+    }
+  }
+}
+
+// Moves the items that take the spectral preconditioner into their own queues
+// (stable, per XCD queue): valid member, FP32, curvature H, frame in LDS with
+// room for the n x n scratch, and lambda >= kPcTheta c.  One block.
+template <typename T>
+__global__ void __launch_bounds__(64) k_split(SolveArgs a) {
+  const int q = threadIdx.x;
+  if (q < 8) {
+    const int n = a.consts->qcount[q];
+    int keep = 0, moved = 0;
+    for (int k = 0; k < n; ++k) {   // in place: keep <= k, so no unread item is overwritten
+      const int item = a.queues[q * a.qcap + k];
+      const MemberInfo mi = a.minfo[item / a.n_lambda];
+      const double lam = a.lamv[item % a.n_lambda];
+      const int h = mi.r1 - mi.r0 + 1, w = mi.c1 - mi.c0 + 1;
+      const bool fits = (h + 4 * a.ckt + kSegR) * ((w + 4 * a.ckt) | 1) <= a.lds_frame_cap;
+      const bool pc = sizeof(T) == 4 && a.reg == SL_H_CURVATURE && !a.plain_cg && mi.status == SL_ST_OK && fits &&
+                      mi.ns * mi.ns <= a.lds_frame_cap && lam >= (double)kPcTheta * mi.pc_c;
+      // Both stores unconditionally, then bump one count: the store not
+      // taken lands at or past its queue's final count, where nothing reads.
+      // (The if/else form selected the base pointer per lane, and hipcc put
+      // the preconditioned base on lanes that only failed the lambda test.)
+      a.pqueues[q * a.qcap + moved] = item;
+      a.queues[q * a.qcap + keep] = item;
+      moved += pc ? 1 : 0;
+      keep += pc ? 0 : 1;
+    }
+    a.consts->qcount[q] = keep;
+    a.consts->pqcount[q] = moved;
+    a.consts->pqhead[q] = 0;
   }
 }
 
@@ -1409,6 +1604,7 @@ static Layout make_layout(const sl_problem* pb, int max_ns, int M, int NL, int n
   L.taps_f = take(sz * ti.total);
   L.minfo = take(sizeof(MemberInfo) * M);
   L.queues = take(sizeof(int) * 8 * (size_t)L.qcap);
+  L.pqueues = take(sizeof(int) * 8 * (size_t)L.qcap);
   L.slot_cap = L.J + 64;
   L.pix = take(sizeof(int32_t) * (size_t)M * L.slot_cap);
   L.cell = take(sizeof(int32_t) * (size_t)M * L.slot_cap * L.n2);
@@ -1453,24 +1649,28 @@ using SolveKernel = void (*)(SolveArgs);
 // Kernel variants: bulk type T and banded half-width CKT (>= ck of the PSF).
 // Compiled banded-window sizes (CKT >= ck).  `wide` takes the next size up;
 // nullptr when that variant does not exist.
-static SolveKernel pick_kernel_f(int ck, bool wide, int* ckt) {
+// pc selects the preconditioned kernel of the same window size.
+static SolveKernel pick_kernel_f(int ck, bool wide, int* ckt, bool pc = false) {
   static const int sizes[] = {2, 4, 7, 10, 16};
-  static const SolveKernel ks[] = {k_solve<float, 2>, k_solve<float, 4>, k_solve<float, 7>, k_solve<float, 10>,
-                                   k_solve<float, 16>};
+  static const SolveKernel ks[] = {k_solve<float, 2, false>, k_solve<float, 4, false>, k_solve<float, 7, false>,
+                                   k_solve<float, 10, false>, k_solve<float, 16, false>};
+  static const SolveKernel kp[] = {k_solve<float, 2, true>, k_solve<float, 4, true>, k_solve<float, 7, true>,
+                                   k_solve<float, 10, true>, k_solve<float, 16, true>};
+  const SolveKernel* k = pc ? kp : ks;
   int i = 0;
   while (i < 5 && sizes[i] < ck) ++i;
   if (i == 5) {   // wider PSFs: direct path only
     *ckt = 2;
-    return wide ? nullptr : ks[0];
+    return wide ? nullptr : k[0];
   }
   if (wide && ++i == 5) return nullptr;
   *ckt = sizes[i];
-  return ks[i];
+  return k[i];
 }
 
 static SolveKernel pick_kernel_d(int ck, bool wide, int* ckt) {
   static const int sizes[] = {2, 7, 10};
-  static const SolveKernel ks[] = {k_solve<double, 2>, k_solve<double, 7>, k_solve<double, 10>};
+  static const SolveKernel ks[] = {k_solve<double, 2, false>, k_solve<double, 7, false>, k_solve<double, 10, false>};
   int i = 0;
   while (i < 3 && sizes[i] < ck) ++i;
   if (i == 3) {
@@ -1492,6 +1692,7 @@ static ProfileState g_prof;
 
 struct LaunchCfg {
   SolveKernel ks = nullptr;
+  SolveKernel kpc = nullptr;   // preconditioned kernel, when some items may take it
   size_t lds = 0, prep_lds = 0, corner_lds = 0;
 };
 
@@ -1510,10 +1711,13 @@ static int configure(SolveArgs& A, const Layout& L, const sl_tuning& v, LaunchCf
   A.ckt = ckt;
   A.force_csr = v.lt_csr != 0;
   A.force_direct = v.blur_direct != 0;
+  A.plain_cg = v.plain_cg != 0;
   // dynamic LDS: source vector | reduction scratch | frame (up to the full image)
   A.q_off = (int)align256(sz * L.I_max);
   A.red_off = A.q_off + (int)align256(sz * L.I_max);
-  A.frame_off = A.red_off + 64 * (int)sizeof(double);
+  A.pc_off = A.red_off + 64 * (int)sizeof(double);
+  // sine table 2 (max_ns + 1) and eigenvalues max_ns of the spectral preconditioner
+  A.frame_off = A.pc_off + (int)align256(sizeof(float) * (3 * A.max_ns + 8));
   const size_t fixed = (size_t)A.frame_off;
   size_t lds = fixed + sz * (size_t)(A.ny + 4 * ckt + kSegR) * (size_t)((A.nx + 4 * ckt) | 1);
   const size_t lds_max = 160 * 1024 - 1024;
@@ -1521,6 +1725,10 @@ static int configure(SolveArgs& A, const Layout& L, const sl_tuning& v, LaunchCf
   SL_REQUIRE(lds > fixed + 64 * sz, "source grid too large for LDS");
   A.lds_frame_cap = (int)((lds - fixed) / sz);
   c->ks = ks;
+  if (sizeof(T) == 4 && A.reg == SL_H_CURVATURE && !A.plain_cg) {
+    int ckt2 = 0;
+    c->kpc = pick_kernel_f(A.ck, v.wide_window != 0, &ckt2, true);
+  }
   c->lds = lds;
   // FP64 right-hand-side accumulator, reused by the transposed-operator build (2 I + 192 ints)
   c->prep_lds = std::max(sizeof(double) * L.I_max, sizeof(int) * (2 * L.I_max + 192));
@@ -1528,13 +1736,16 @@ static int configure(SolveArgs& A, const Layout& L, const sl_tuning& v, LaunchCf
   static std::mutex mu;
   std::lock_guard<std::mutex> g(mu);
   SL_HIP(hipFuncSetAttribute((const void*)ks, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  if (c->kpc)
+    SL_HIP(hipFuncSetAttribute((const void*)c->kpc, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   SL_HIP(hipFuncSetAttribute((const void*)k_prep<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)c->prep_lds));
   return SL_OK;
 }
 
-// Enqueues the four launches of one solve on st.  `profile` records HIP
-// events around the CG kernel when profiling is on (never inside a capture).
+// Enqueues the launches of one solve on st: k_setup, k_prep, [k_split and the
+// preconditioned k_solve], k_solve, k_corner.  `profile` records HIP events
+// around the CG kernels when profiling is on (never inside a capture).
 template <typename T>
 static int enqueue(const SolveArgs& A, const LamList& lams, const Layout& L, const LaunchCfg& c, hipStream_t st,
                    bool profile) {
@@ -1550,6 +1761,12 @@ static int enqueue(const SolveArgs& A, const LamList& lams, const Layout& L, con
       SL_HIP(hipEventCreate(&e1));
       SL_HIP(hipEventRecord(e0, st));
     }
+  }
+  if (c.kpc) {
+    hipLaunchKernelGGL(k_split<T>, dim3(1), dim3(64), 0, st, A);
+    if (int e = check_launch("k_split")) return e;
+    hipLaunchKernelGGL(c.kpc, dim3(L.n_wg), dim3(kNT), c.lds, st, A);
+    if (int e = check_launch("k_solve (preconditioned)")) return e;
   }
   hipLaunchKernelGGL(c.ks, dim3(L.n_wg), dim3(kNT), c.lds, st, A);
   if (int e = check_launch("k_solve")) return e;
@@ -1589,10 +1806,10 @@ static sl_tuning resolve_tuning(const sl_problem* pb, int max_ns, int n_members,
   if (opt->tuning) return *opt->tuning;
   std::lock_guard<std::mutex> g(g_tune.mu);
   auto it = g_tune.best.find(tune_key(pb, max_ns, n_members, n_lambda));
-  return it == g_tune.best.end() ? sl_tuning{0, 0, 0} : it->second;
+  return it == g_tune.best.end() ? sl_tuning{0, 0, 0, 0} : it->second;
 }
 
-static sl_tuning variant_of(int i) { return sl_tuning{i & 1, (i >> 1) & 1, (i >> 2) & 1}; }
+static sl_tuning variant_of(int i) { return sl_tuning{i & 1, (i >> 1) & 1, (i >> 2) & 1, 0}; }
 
 // Validates the arguments of a solve and fills the kernel arguments.
 static int prepare(const sl_problem* pb, const double* lens, const int32_t* ns, int max_ns, int n_members,
@@ -1650,6 +1867,7 @@ static int prepare(const sl_problem* pb, const double* lens, const int32_t* ns, 
   A.taps_t = ws + L.taps_f;
   A.minfo = (MemberInfo*)(ws + L.minfo);
   A.queues = (int*)(ws + L.queues);
+  A.pqueues = (int*)(ws + L.pqueues);
   A.qcap = L.qcap;
   A.pix_list = (int32_t*)(ws + L.pix);
   A.cell = (int32_t*)(ws + L.cell);

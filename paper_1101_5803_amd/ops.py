@@ -232,7 +232,7 @@ class Solver:
                          ("s_corner", "s_off", "chi2", "reg", "iters", "status", "k_star", "corner_status")])
         tun = None
         if tuning is not None:
-            tun = L.Tuning(*[int(tuning.get(k, 0)) for k in ("wide_window", "lt_csr", "blur_direct")])
+            tun = L.Tuning(*[int(tuning.get(k, 0)) for k in ("wide_window", "lt_csr", "blur_direct", "plain_cg")])
         opts = L.SolveOpts(float(tol), int(maxit), ctypes.pointer(tun) if tun is not None else None)
         return M, lam, int(max_ns), ws, out, res, opts, tun
 
@@ -269,7 +269,8 @@ class Solver:
                                           L.f64_array(lam), len(lam), ctypes.byref(opts), L.ptr(ws), ws.numel(),
                                           ctypes.byref(res), L.stream_handle(), ctypes.byref(best), ms),
                 "sl_solve_autotune")
-        return (dict(wide_window=best.wide_window, lt_csr=best.lt_csr, blur_direct=best.blur_direct), list(ms), out)
+        return (dict(wide_window=best.wide_window, lt_csr=best.lt_csr, blur_direct=best.blur_direct,
+                     plain_cg=best.plain_cg), list(ms), out)
 
     def plan(self, lens: torch.Tensor, ns: torch.Tensor, lambdas, tol=1e-7, maxit=4000,
              max_ns: int | None = None, out=None, tuning: dict | None = None) -> "Plan":
