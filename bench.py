@@ -98,10 +98,12 @@ def parse():
 
 
 def algorithmic_work(info, iters, nsub, ck):
-    """Flops and table bytes of the persistent kernel for one launch.
+    """Flops and table bytes of the CG phase (the persistent kernels) for one step.
 
     Per CG iteration of a member with mapped-pixel bounding box h x w, M mapped
-    pixels (M n^2 table entries) and I nodes:
+    pixels (M n^2 table entries) and I nodes (preconditioned iterations read
+    the same tables; the sine transforms of their preconditioner run in LDS on
+    MFMA and their 8 n^3 flops are not counted here):
       flops = 2 passes * (4ck+1) FMAs * h*w * 2      (B^T B, banded, in LDS)
             + 2 * 12 * M n^2                          (L and L^T bilinear)
             + 23 * I                                  (H^T H stencil and CG updates)
@@ -215,7 +217,7 @@ def main():
     traffic = measured_traffic() if args.workload == "c3" else None
     roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": traffic,
-            "kernel": "k_solve (persistent CG)", "kernel_ms": round(kern_s * 1e3, 3),
+            "kernel": "CG phase: k_split + preconditioned and plain persistent k_solve", "kernel_ms": round(kern_s * 1e3, 3),
             "algorithmic_bytes": tbytes, "fp32_TFLOPs": round(tflops, 3),
             "fp32_frac": round(tflops / PEAK_FP32_TFLOPS, 4),
             "measured_hbm_GBps": round(traffic / kern_s / 1e9, 1) if traffic else None}

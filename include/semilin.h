@@ -250,7 +250,8 @@ int sl_solve_member_info(const sl_problem* pb, int max_ns, int n_members, int n_
 
 /*
  * Kernel timing for measurement: while enabled, every sl_solve_semilinear
- * records HIP events around its persistent CG kernel on the call's stream.
+ * records HIP events around its CG phase (k_split and the persistent CG
+ * kernels, preconditioned and plain) on the call's stream.
  * sl_profile_enable(1) clears the record; sl_profile_solve_ms() waits for the
  * recorded events and returns the summed milliseconds and launch count.
  */

@@ -242,8 +242,10 @@ class Solver:
 
         lens (M, 7) FP64 and ns (M,) int32 on the device; lambdas a host
         sequence.  ``max_ns`` bounds ns (defaults to ns.max(), which syncs).
-        ``tuning`` (dict with keys wide_window, lt_csr, blur_direct) forces a
-        kernel variant; None takes the autotuner's choice, if any.
+        ``tuning`` (dict with keys wide_window, lt_csr, blur_direct, plain_cg)
+        forces a kernel variant; None takes the autotuner's choice, if any.
+        plain_cg = 1 turns the spectral preconditioner of the FP32 curvature
+        solve off.
         """
         lens = lens.to(torch.float64).contiguous()
         ns = ns.to(torch.int32).contiguous()

@@ -52,6 +52,21 @@ def test_variant_matches_oracle(vi, dtype):
     assert rel.max() <= bound, (v, rel.max())
 
 
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_plain_cg_matches_oracle(dtype):
+    """tuning plain_cg = 1 (no spectral preconditioner) on c2."""
+    import paper_1101_5803_amd as sl
+    g = np.load(os.path.join(GOLD, "c2_oracle.npz"))
+    solver, w, z = _c2_solver(sl, dtype)
+    lens = torch.tensor(np.atleast_2d(z["lens"]), device=DEV)
+    ns = torch.tensor([w.ns], dtype=torch.int32, device=DEV)
+    tol, bound = (1e-7, 1e-5) if dtype == torch.float32 else (1e-10, 1e-9)
+    out = _np(solver.solve_semilinear(lens, ns, w.lambdas, tol=tol, max_ns=w.ns, tuning={"plain_cg": 1}))
+    assert np.all(out["status"] == 0)
+    rel = np.abs(out["chi2"][0] - g["chi2"]) / g["chi2"]
+    assert rel.max() <= bound, rel.max()
+
+
 def test_autotune_times_every_variant_and_keeps_best_results():
     import paper_1101_5803_amd as sl
     solver, w, z = _c2_solver(sl, torch.float32)

@@ -126,6 +126,27 @@ def test_curvature_H_rows():
     assert abs(hx @ ops.apply_H(y, ns, "curvature") - x @ ops.apply_HtH(y, ns, "curvature")) < 1e-11
 
 
+@pytest.mark.parametrize("ns", [2, 7, 12])
+def test_curvature_HtH_diagonalised_by_sine_transform(ns):
+    """The spectral preconditioner of the FP32 solve applies (c I + lambda H^T H)^-1
+    through the 2-D type-I sine transform: S = DST-I (orthonormal, scipy's own
+    routine) must diagonalise the oracle's dense H^T H with eigenvalues
+    mu_j + mu_k, mu_k = 16 sin^4(pi (k+1) / (2 (ns+1)))."""
+    from scipy.fft import dst
+    Hm = ops.dense_H(ns, "curvature")
+    HtH = Hm.T @ Hm
+    S = dst(np.eye(ns), type=1, norm="ortho", axis=0)
+    np.testing.assert_allclose(S @ S, np.eye(ns), atol=1e-13)
+    S2 = np.kron(S, S)
+    mu = 16.0 * np.sin(np.pi * np.arange(1, ns + 1) / (2.0 * (ns + 1))) ** 4
+    lam2 = (mu[:, None] + mu[None, :]).reshape(-1)
+    np.testing.assert_allclose(S2 @ HtH @ S2, np.diag(lam2), atol=1e-11)
+    # the preconditioner's inverse through the transform equals the dense inverse
+    c, lam = 0.37, 2.5
+    Minv = S2 @ np.diag(1.0 / (c + lam * lam2)) @ S2
+    np.testing.assert_allclose(Minv @ (c * np.eye(ns * ns) + lam * HtH), np.eye(ns * ns), atol=1e-11)
+
+
 def test_identity_H():
     x = np.arange(9.0)
     np.testing.assert_array_equal(ops.apply_HtH(x, 3, "identity"), x)
