@@ -50,6 +50,7 @@ constexpr int kUpd = 4;        // CG vector-update chunk (nodes per thread)
 // The spectral preconditioner pays for its four n x n transforms only where
 // lambda H^T H dominates the spectrum: it is used when lambda >= kPcTheta c.
 constexpr float kPcTheta = 0.05f;
+constexpr int kHeavy = 3;      // smallest lambdas of each member queued ahead of the rest
 constexpr int kMaxCK = 31;
 
 struct alignas(16) MemberInfo {
@@ -216,14 +217,21 @@ __global__ void __launch_bounds__(1024) k_setup(SolveArgs a, LamList lams) {
       counts[v] = start;
       start += c;
     }
-    // rank r -> queue r % 8; the sort is stable in member index
+    // rank r -> queue r % 8; the sort is stable in member index.  Within a
+    // queue the kHeavy smallest lambdas of every member come first (their
+    // solves take the most CG iterations, so starting them early shortens
+    // the tail of the launch), then the other lambdas; both parts keep the
+    // members in order, so the blocks of an XCD share few members at a time
+    // and their tables stay in its L2.
     for (int m = 0; m < M; ++m) {
       const int ns = a.ns[m];
       const int key = (ns >= 2 && ns <= a.max_ns) ? ns : 0;
       const int r = counts[key]++;
-      const int q = r & 7;
-      const int slot = (r >> 3) * a.n_lambda;
-      for (int k = 0; k < a.n_lambda; ++k) a.queues[q * a.qcap + slot + k] = m * a.n_lambda + k;
+      const int q = r & 7, t = r >> 3;
+      const int nmq = (M - q + 7) / 8;   // members in queue q
+      const int H = a.n_lambda < kHeavy ? a.n_lambda : kHeavy;
+      for (int k = 0; k < a.n_lambda; ++k)
+        a.queues[q * a.qcap + (k < H ? t * H + k : nmq * H + t * (a.n_lambda - H) + (k - H))] = m * a.n_lambda + k;
     }
     for (int q = 0; q < 8; ++q) {
       // members with rank r = q + 8 t fill queue q densely
