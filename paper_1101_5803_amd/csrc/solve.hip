@@ -975,51 +975,57 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 // row-major (trans = 0) or transposed (trans = 1); with `scale`, element
 // (j, k) is divided by c + lambda (mu_j + mu_k).  S comes from the table
 // tab[m] = sqrt(2/(n+1)) sin(pi m / (n+1)), m = (j+1)(k+1) mod 2(n+1).
-// All waves of the block take 16 x 16 output tiles in turn.
+// Each wave takes 16 x 48 output strips (three 16 x 16 tiles sharing the S
+// operand, three independent accumulator chains); the operands of the next
+// k-step are loaded before the current step's MFMAs.
 // v_mfma_f32_16x16x4f32: lane l supplies A[l%16][l/16] and B[l/16][l%16];
 // accumulator element r is C[4 (l/16) + r][l%16].
 __device__ __forceinline__ void sine_mul(const float* tab, const float* mu, int n, const float* B, float* C, int trans, int scale,
                          float c, float lam) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int lc = lane & 15, lq = lane >> 4;
-  const int nt = (n + 15) >> 4, nn2 = 2 * (n + 1);
-  for (int tile = wv; tile < nt * nt; tile += kWaves) {
-    const int i0 = (tile / nt) << 4, j0 = (tile % nt) << 4;
-    const int i = i0 + lc, j = j0 + lc;
-    // k-steps t0 = 0, 4, 8, ...: the operands of the next step are loaded
-    // before the current MFMA, and two accumulator chains alternate
-    f32x4 acc0 = {0.0f, 0.0f, 0.0f, 0.0f}, acc1 = {0.0f, 0.0f, 0.0f, 0.0f};
+  const int nt = (n + 15) >> 4, ng = (nt + 2) / 3, nn2 = 2 * (n + 1);
+  for (int strip = wv; strip < nt * ng; strip += kWaves) {
+    const int i0 = (strip / ng) << 4, jg = (strip % ng) * 48;
+    const int i = i0 + lc;
+    const int j0 = jg + lc, j1 = j0 + 16, j2 = j0 + 32;
+    f32x4 acc0 = {0.0f, 0.0f, 0.0f, 0.0f}, acc1 = acc0, acc2 = acc0;
     int mi = ((i + 1) * (lq + 1)) % nn2;          // table index of S[i][t], t = t0 + lq
     const int step = (4 * (i + 1)) % nn2;
     float av = (i < n && lq < n) ? tab[mi] : 0.0f;
-    float bv = (lq < n && j < n) ? B[lq * n + j] : 0.0f;
-    int t0 = 0;
-    for (; t0 + 4 < n; t0 += 8) {
+    float b0 = (lq < n && j0 < n) ? B[lq * n + j0] : 0.0f;
+    float b1 = (lq < n && j1 < n) ? B[lq * n + j1] : 0.0f;
+    float b2 = (lq < n && j2 < n) ? B[lq * n + j2] : 0.0f;
+    for (int t0 = 0; t0 < n; t0 += 4) {
       mi += step;
       if (mi >= nn2) mi -= nn2;
-      const int t1 = t0 + 4 + lq;
-      const float av1 = (i < n && t1 < n) ? tab[mi] : 0.0f;
-      const float bv1 = (t1 < n && j < n) ? B[t1 * n + j] : 0.0f;
-      acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc0, 0, 0, 0);
-      mi += step;
-      if (mi >= nn2) mi -= nn2;
-      const int t2 = t0 + 8 + lq;
-      av = (i < n && t2 < n) ? tab[mi] : 0.0f;
-      bv = (t2 < n && j < n) ? B[t2 * n + j] : 0.0f;
-      acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(av1, bv1, acc1, 0, 0, 0);
+      const int tn = t0 + 4 + lq;
+      const float avn = (i < n && tn < n) ? tab[mi] : 0.0f;
+      const float b0n = (tn < n && j0 < n) ? B[tn * n + j0] : 0.0f;
+      const float b1n = (tn < n && j1 < n) ? B[tn * n + j1] : 0.0f;
+      const float b2n = (tn < n && j2 < n) ? B[tn * n + j2] : 0.0f;
+      acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(av, b0, acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(av, b1, acc1, 0, 0, 0);
+      acc2 = __builtin_amdgcn_mfma_f32_16x16x4f32(av, b2, acc2, 0, 0, 0);
+      av = avn;
+      b0 = b0n;
+      b1 = b1n;
+      b2 = b2n;
     }
-    if (t0 < n) acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc0, 0, 0, 0);
-    const f32x4 acc = acc0 + acc1;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = i0 + 4 * lq + r, col = j0 + lc;
-      if (row < n && col < n) {
-        float v = acc[r];
-        if (scale) v = v / (c + lam * (mu[row] + mu[col]));
-        if (trans)
-          C[col * n + row] = v;
-        else
-          C[row * n + col] = v;
+    for (int g = 0; g < 3; ++g) {
+      const f32x4 acc = g == 0 ? acc0 : (g == 1 ? acc1 : acc2);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = i0 + 4 * lq + r, col = jg + 16 * g + lc;
+        if (row < n && col < n) {
+          float v = acc[r];
+          if (scale) v = v / (c + lam * (mu[row] + mu[col]));
+          if (trans)
+            C[col * n + row] = v;
+          else
+            C[row * n + col] = v;
+        }
       }
     }
   }
