@@ -217,7 +217,7 @@ def main():
     traffic = measured_traffic() if args.workload == "c3" else None
     roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": traffic,
-            "kernel": "CG phase: k_split + preconditioned and plain persistent k_solve", "kernel_ms": round(kern_s * 1e3, 3),
+            "kernel": "CG phase: k_split, then the plain and the preconditioned persistent k_solve side by side", "kernel_ms": round(kern_s * 1e3, 3),
             "algorithmic_bytes": tbytes, "fp32_TFLOPs": round(tflops, 3),
             "fp32_frac": round(tflops / PEAK_FP32_TFLOPS, 4),
             "measured_hbm_GBps": round(traffic / kern_s / 1e9, 1) if traffic else None}

@@ -1183,7 +1183,10 @@ __device__ __forceinline__ void run_item(const SolveArgs& a, const MemberInfo& m
   const int tid = threadIdx.x;
   const long out_idx = (long)m * a.n_lambda + kl;
   T* __restrict__ s_g = reinterpret_cast<T*>(a.s_all) + out_idx * a.I_max;
-  T* __restrict__ r_g = reinterpret_cast<T*>(a.rbuf) + (long)blockIdx.x * a.I_max;
+  // per-block scratch: the preconditioned launch runs beside the plain one and
+  // takes the second half of the slots
+  const long slot = (long)blockIdx.x + (PC ? (long)gridDim.x : 0L);
+  T* __restrict__ r_g = reinterpret_cast<T*>(a.rbuf) + slot * a.I_max;
   const int ns = mi.ns, I = mi.I, M = mi.M, r0 = mi.r0, c0 = mi.c0;
   const int h = mi.r1 - mi.r0 + 1, w = mi.c1 - mi.c0 + 1;
   constexpr int HALO = 2 * CKT;
@@ -1203,7 +1206,7 @@ __device__ __forceinline__ void run_item(const SolveArgs& a, const MemberInfo& m
     F = reinterpret_cast<T*>(a.gframe) + (long)blockIdx.x * a.gframe_elems;
   T* const F0 = F + HALO * pitch + HALO;        // interior (0, 0) = image (r0, c0)
   T* const Frows = F + HALO * pitch;            // interior rows, contiguous
-  T* Z = reinterpret_cast<T*>(a.gz) + (long)blockIdx.x * J;
+  T* Z = reinterpret_cast<T*>(a.gz) + slot * J;
   const int32_t* pix = a.pix_list + (long)m * a.slot_cap;
   const int32_t* cellp = a.cell + (long)m * a.slot_cap * n2;
   const T* fxp = reinterpret_cast<const T*>(a.fx) + (long)m * a.slot_cap * n2;
@@ -1628,8 +1631,8 @@ static Layout make_layout(const sl_problem* pb, int max_ns, int M, int NL, int n
   L.s_all = take(sz * (size_t)M * NL * L.I_max);
   L.gframe_elems = (pb->img.ny + 4 * 16 + kSegR) * ((pb->img.nx + 4 * 16) | 1);   // widest window's halo
   L.gframe = take(sz * (size_t)n_wg * L.gframe_elems);
-  L.gz = take(sz * (size_t)n_wg * L.J);
-  L.rbuf = take(sz * (size_t)n_wg * L.I_max);
+  L.gz = take(sz * 2 * (size_t)n_wg * L.J);          // plain | preconditioned launch
+  L.rbuf = take(sz * 2 * (size_t)n_wg * L.I_max);
   L.lt_ptr = take(sizeof(int32_t) * (size_t)M * (L.I_max + 65));
   L.lt_perm = take(sizeof(int32_t) * (size_t)M * L.I_max);
   L.lt_cap = 8LL * L.n2 * L.slot_cap;   // twice the unpadded bound: room for slice padding
@@ -1704,6 +1707,30 @@ struct ProfileState {
 };
 static ProfileState g_prof;
 
+// Per-device side stream for the preconditioned launch and the events that
+// fork it from, and join it to, the caller's stream; created on first use
+// (default priority, non-blocking).
+struct SideStream {
+  hipStream_t s = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
+static std::mutex g_side_mu;
+static SideStream g_side[64];
+
+static int side_stream(SideStream** out) {
+  int dev = 0;
+  SL_HIP(hipGetDevice(&dev));
+  SL_REQUIRE(dev >= 0 && dev < 64, "device index %d out of range", dev);
+  SideStream& x = g_side[dev];
+  if (!x.s) {
+    SL_HIP(hipStreamCreateWithFlags(&x.s, hipStreamNonBlocking));
+    SL_HIP(hipEventCreateWithFlags(&x.fork, hipEventDisableTiming));
+    SL_HIP(hipEventCreateWithFlags(&x.join, hipEventDisableTiming));
+  }
+  *out = &x;
+  return SL_OK;
+}
+
 struct LaunchCfg {
   SolveKernel ks = nullptr;
   SolveKernel kpc = nullptr;   // preconditioned kernel, when some items may take it
@@ -1757,9 +1784,10 @@ static int configure(SolveArgs& A, const Layout& L, const sl_tuning& v, LaunchCf
   return SL_OK;
 }
 
-// Enqueues the launches of one solve on st: k_setup, k_prep, [k_split and the
-// preconditioned k_solve], k_solve, k_corner.  `profile` records HIP events
-// around the CG kernels when profiling is on (never inside a capture).
+// Enqueues the launches of one solve on st: k_setup, k_prep, [k_split], the
+// plain k_solve [beside the preconditioned k_solve on the side stream, joined
+// back to st], k_corner.  `profile` records HIP events on st around the CG
+// phase when profiling is on (never inside a capture).
 template <typename T>
 static int enqueue(const SolveArgs& A, const LamList& lams, const Layout& L, const LaunchCfg& c, hipStream_t st,
                    bool profile) {
@@ -1779,11 +1807,25 @@ static int enqueue(const SolveArgs& A, const LamList& lams, const Layout& L, con
   if (c.kpc) {
     hipLaunchKernelGGL(k_split<T>, dim3(1), dim3(64), 0, st, A);
     if (int e = check_launch("k_split")) return e;
-    hipLaunchKernelGGL(c.kpc, dim3(L.n_wg), dim3(kNT), c.lds, st, A);
+    // The plain launch first on st, the preconditioned one on the side
+    // stream: both are persistent, so its blocks take the CUs that the plain
+    // launch's last long items leave idle.  They share no queue and no
+    // per-block scratch.
+    std::lock_guard<std::mutex> g(g_side_mu);
+    SideStream* ss = nullptr;
+    if (int e = side_stream(&ss)) return e;
+    SL_HIP(hipEventRecord(ss->fork, st));
+    hipLaunchKernelGGL(c.ks, dim3(L.n_wg), dim3(kNT), c.lds, st, A);
+    if (int e = check_launch("k_solve")) return e;
+    SL_HIP(hipStreamWaitEvent(ss->s, ss->fork, 0));
+    hipLaunchKernelGGL(c.kpc, dim3(L.n_wg), dim3(kNT), c.lds, ss->s, A);
     if (int e = check_launch("k_solve (preconditioned)")) return e;
+    SL_HIP(hipEventRecord(ss->join, ss->s));
+    SL_HIP(hipStreamWaitEvent(st, ss->join, 0));
+  } else {
+    hipLaunchKernelGGL(c.ks, dim3(L.n_wg), dim3(kNT), c.lds, st, A);
+    if (int e = check_launch("k_solve")) return e;
   }
-  hipLaunchKernelGGL(c.ks, dim3(L.n_wg), dim3(kNT), c.lds, st, A);
-  if (int e = check_launch("k_solve")) return e;
   if (e1) {
     SL_HIP(hipEventRecord(e1, st));
     std::lock_guard<std::mutex> g(g_prof.mu);
