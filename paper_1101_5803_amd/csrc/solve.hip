@@ -2049,6 +2049,11 @@ int sl_plan_create(const sl_problem* pb, const double* lens, const int32_t* ns, 
     return e;
   LaunchCfg c;
   if (int e = configure_any(pb->dtype, A, L, resolve_tuning(pb, max_ns, n_members, n_lambda, opt), &c)) return e;
+  if (c.kpc) {   // the side stream and its events exist before the capture starts
+    std::lock_guard<std::mutex> gs(g_side_mu);
+    SideStream* ss = nullptr;
+    if (int e = side_stream(&ss)) return e;
+  }
   hipStream_t cs;
   SL_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
   hipGraph_t g = nullptr;
