@@ -182,7 +182,7 @@ size_t sl_solve_workspace_size(const sl_problem* pb, int max_ns, int n_members, 
  * optimiser).  Every (member, lambda) pair is one conjugate-gradient solve
  * of Eq. 7 from s = 0, stopped when ||b - A s|| <= tol ||b||; all pairs run
  * in one persistent launch.  With SL_F32 and curvature H, a pair whose
- * lambda >= 0.05 c (and whose n x n grid fits beside the blur frame in LDS)
+ * lambda >= 0.15 c (and whose n x n grid fits beside the blur frame in LDS)
  * is solved by preconditioned CG with M = c I + lambda H^T H, applied exactly
  * through the orthonormal 2-D sine transform that diagonalises H^T H (H^T H
  * = D^2 (x) I + I (x) D^2 with D the second-difference matrix).  c is a

@@ -49,7 +49,7 @@ constexpr int kSegR = 4;       // outputs per lane in a banded pass
 constexpr int kUpd = 4;        // CG vector-update chunk (nodes per thread)
 // The spectral preconditioner pays for its four n x n transforms only where
 // lambda H^T H dominates the spectrum: it is used when lambda >= kPcTheta c.
-constexpr float kPcTheta = 0.05f;
+constexpr float kPcTheta = 0.15f;
 constexpr int kHeavy = 4;      // smallest lambdas of each member queued ahead of the rest
 constexpr int kMaxCK = 31;
 
