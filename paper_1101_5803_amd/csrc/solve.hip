@@ -21,7 +21,8 @@
 //   k_split   (1 block)          moves the items that take the spectral
 //                                preconditioner to their own queues (FP32,
 //                                curvature H); k_solve<.., true> runs them as
-//                                preconditioned CG before the plain k_solve
+//                                preconditioned CG on a side stream, beside
+//                                the plain k_solve
 //   k_corner  (1 block/member)   L-curve corner (Sec. 2.6, Eq. 20) in FP64 and
 //                                the corner solution copy
 //
