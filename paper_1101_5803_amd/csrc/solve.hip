@@ -58,7 +58,7 @@ struct alignas(16) MemberInfo {
   int ns, I, M, r0, r1, c0, c1, status;   // M: interleaved table slots (>= mapped pixels)
   long long off;   // start in packed vectors
   int Mtrue;       // pixels with at least one subpixel on the grid
-  int sell;        // transposed operator stored as sliced-ELL (1) or CSR (0)
+  int sell;        // transposed operator: CSR (0), sliced-ELL (1), sliced-ELL with paired 16-bit offsets (2)
   float pc_c;      // scale c of the spectral preconditioner (see k_prep)
   int pad_[3];
 };
@@ -527,6 +527,14 @@ __device__ int build_transpose(const SolveArgs& a, int m, int ns, int slots, con
     }
   }
   __syncthreads();
+  // FP32 members whose frame fits in LDS (frame offsets below 2^16) store the
+  // sliced-ELL entries in pairs: slices of even length, one dword holding the
+  // 16-bit offsets of entries 2k and 2k + 1 of a lane and one float2 their
+  // weights (6 bytes per entry instead of 8)
+  const int fh = bbox[1] - bbox[0] + 1, fw = bbox[3] - bbox[2] + 1;
+  const int pair_ok = __builtin_amdgcn_readfirstlane(
+      (int)(sizeof(T) == 4 && (long)(fh + 4 * a.ckt + kSegR) * ((fw + 4 * a.ckt) | 1) <= a.lds_frame_cap &&
+            a.lds_frame_cap <= 65536));
   // slice lengths (rows sorted by length: little padding) and the plain total
   for (int g = tid; g < ngroups; g += blockDim.x) {
     int mx = 0;
@@ -534,10 +542,12 @@ __device__ int build_transpose(const SolveArgs& a, int m, int ns, int slots, con
       const int i = (perm[64 * g + l] >> 16) * ns + (perm[64 * g + l] & 0xFFFF);
       mx = max(mx, cnt[i]);
     }
+    if (pair_ok) mx = (mx + 1) & ~1;
     atomicAdd(&totals[0], 64 * mx);
   }
   __syncthreads();
   const int sell = __builtin_amdgcn_readfirstlane((int)(!a.force_csr && (long long)totals[0] <= a.lt_cap));
+  const int paired = sell && pair_ok;
   // exclusive scan over units: slices (padded sizes) for sliced-ELL, rows for CSR
   const int nunits = sell ? ngroups : I;
   const int chunk = (nunits + blockDim.x - 1) / blockDim.x;
@@ -549,6 +559,7 @@ __device__ int build_transpose(const SolveArgs& a, int m, int ns, int slots, con
       const int i = (perm[64 * u + l] >> 16) * ns + (perm[64 * u + l] & 0xFFFF);
       mx = max(mx, cnt[i]);
     }
+    if (paired) mx = (mx + 1) & ~1;
     return 64 * mx;
   };
   int local = 0;
@@ -570,8 +581,14 @@ __device__ int build_transpose(const SolveArgs& a, int m, int ns, int slots, con
   }
   if (tid == blockDim.x - 1) rp[nunits] = run;
   __syncthreads();
-  if (sell)
-    for (int e = tid; e < rp[ngroups]; e += blockDim.x) {
+  // padding entries: offset 0 (a halo corner of the frame, always zero), weight 0
+  const int E = rp[ngroups];   // sliced-ELL entries (a multiple of 128 when paired)
+  unsigned short* off16 = reinterpret_cast<unsigned short*>(ent);
+  float* w32 = reinterpret_cast<float*>(off16 + E);
+  if (paired)
+    for (int e = tid; e < 3 * (E >> 1); e += blockDim.x) reinterpret_cast<unsigned*>(ent)[e] = 0u;
+  else if (sell)
+    for (int e = tid; e < E; e += blockDim.x) {
       ent[e].off = 0;
       ent[e].w = (T)0;
     }
@@ -624,9 +641,15 @@ __device__ int build_transpose(const SolveArgs& a, int m, int ns, int slots, con
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         if (key >= 0) {
-          const long e = (long)ipos[key] + (long)estep * j;
-          ent[e].off = off;
-          ent[e].w = (T)ww[q];
+          if (paired) {
+            const long ps = ((long)(ipos[key] & ~63) >> 1) + 64L * (j >> 1) + (ipos[key] & 63);
+            off16[2 * ps + (j & 1)] = (unsigned short)off;
+            w32[2 * ps + (j & 1)] = (float)ww[q];
+          } else {
+            const long e = (long)ipos[key] + (long)estep * j;
+            ent[e].off = off;
+            ent[e].w = (T)ww[q];
+          }
         }
       }
     }
@@ -663,15 +686,21 @@ __device__ int build_transpose(const SolveArgs& a, int m, int ns, int slots, con
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         if (key >= 0) {
-          const long e = (long)ipos[key] + (long)estep * j;
-          ent[e].off = off;
-          ent[e].w = (T)wt[q];
+          if (paired) {
+            const long ps = ((long)(ipos[key] & ~63) >> 1) + 64L * (j >> 1) + (ipos[key] & 63);
+            off16[2 * ps + (j & 1)] = (unsigned short)off;
+            w32[2 * ps + (j & 1)] = (float)wt[q];
+          } else {
+            const long e = (long)ipos[key] + (long)estep * j;
+            ent[e].off = off;
+            ent[e].w = (T)wt[q];
+          }
         }
       }
     }
   }
   __syncthreads();
-  return sell;
+  return paired ? 2 : sell;
 }
 
 template <typename T>
@@ -1325,24 +1354,54 @@ __device__ __forceinline__ void run_item(const SolveArgs& a, const MemberInfo& m
         // slice has `len` entries (padding reads the zero halo), eight in flight
         const int wid = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
         const int nslices = (I + 63) >> 6;
+        const int lt_E = lt_rp[nslices];   // sliced-ELL entries of the member
         for (int sl = wid; sl < nslices; sl += kNT / 64) {
           const int idx = sl * 64 + lane;
           const int b0 = lt_rp[sl];
           const int len = (lt_rp[sl + 1] - b0) >> 6;
           const int pk = idx < I ? perm[idx] : 0;
-          const LtEntry<T>* ep = lt_e + b0 + lane;
           T acc = 0;
-          int j = 0;
-          for (; j + 7 < len; j += 8) {
-            LtEntry<T> x[8];
+          if (sizeof(T) == 4 && sell == 2) {
+            // paired entries (even `len`, entries summed in the same order)
+            const unsigned* op = reinterpret_cast<const unsigned*>(lt_e) + (b0 >> 1) + lane;
+            const float2* wq = reinterpret_cast<const float2*>(reinterpret_cast<const unsigned*>(lt_e) + (lt_E >> 1)) +
+                               (b0 >> 1) + lane;
+            const int npair = len >> 1;
+            int j = 0;
+            for (; j + 7 < npair; j += 8) {   // sixteen entries in flight
+              unsigned o[8];
+              float2 wv[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) x[u] = ep[64L * (j + u)];
+              for (int u = 0; u < 8; ++u) {
+                o[u] = op[64L * (j + u)];
+                wv[u] = wq[64L * (j + u)];
+              }
 #pragma unroll
-            for (int u = 0; u < 8; ++u) acc += x[u].w * F[x[u].off];
-          }
-          for (; j < len; ++j) {
-            const LtEntry<T> x0 = ep[64L * j];
-            acc += x0.w * F[x0.off];
+              for (int u = 0; u < 8; ++u) {
+                acc += (T)wv[u].x * F[o[u] & 0xFFFFu];
+                acc += (T)wv[u].y * F[o[u] >> 16];
+              }
+            }
+            for (; j < npair; ++j) {
+              const unsigned o0 = op[64L * j];
+              const float2 w0 = wq[64L * j];
+              acc += (T)w0.x * F[o0 & 0xFFFFu];
+              acc += (T)w0.y * F[o0 >> 16];
+            }
+          } else {
+            const LtEntry<T>* ep = lt_e + b0 + lane;
+            int j = 0;
+            for (; j + 7 < len; j += 8) {
+              LtEntry<T> x[8];
+#pragma unroll
+              for (int u = 0; u < 8; ++u) x[u] = ep[64L * (j + u)];
+#pragma unroll
+              for (int u = 0; u < 8; ++u) acc += x[u].w * F[x[u].off];
+            }
+            for (; j < len; ++j) {
+              const LtEntry<T> x0 = ep[64L * j];
+              acc += x0.w * F[x0.off];
+            }
           }
           if (idx < I) {
             const int rn_ = pk >> 16, cn_ = pk & 0xFFFF, i = rn_ * ns + cn_;
