@@ -44,8 +44,13 @@
 
 namespace sl {
 
-constexpr int kNT = 1024;     // threads per solve block
+constexpr int kNT = 1024;     // threads per FP32 solve block (kNTof below)
 constexpr int kWaves = kNT / kWave;
+// Threads per solve block by bulk type: FP64 blocks run 512 threads, which
+// leaves 256 VGPRs per lane and no spills; FP32 keeps 1024, whose extra waves
+// hide the gathers' latency better than an unspilled 512-thread block does.
+template <typename T>
+constexpr int kNTof = sizeof(T) == 8 ? 512 : kNT;
 constexpr int kSegR = 4;       // outputs per lane in a banded pass
 constexpr int kUpd = 4;        // CG vector-update chunk (nodes per thread)
 // The spectral preconditioner pays for its four n x n transforms only where
@@ -893,7 +898,7 @@ __device__ __forceinline__ void banded_pass(T* __restrict__ F0, int pitch, int n
   const int step = ROW ? 1 : pitch;          // distance between positions
   const int lstride = ROW ? pitch : 1;       // distance between lines
   const bool edges = img_off < ck || img_off + len > img_len - ck;
-  for (int l0 = wv * LPW; l0 < nlines; l0 += kWaves * LPW) {   // same trip count for the whole wave
+  for (int l0 = wv * LPW; l0 < nlines; l0 += (kNTof<T> / kWave) * LPW) {   // same trip count for the whole wave
     const int line = l0 + sub_line;
     const bool active = seg < S && line < nlines;
     const T* src = F0 + (active ? line * lstride + (p0 - NH) * step : 0);
@@ -979,6 +984,7 @@ __device__ __forceinline__ double reg_node(const T* P, int ns, int r, int c, int
 
 // Block-wide FP64 sum with one barrier; consecutive calls must alternate `buf`
 // (0/1) and be separated by at least one other barrier before a buffer is reused.
+template <int NW = kWaves>
 __device__ __forceinline__ double block_sum1(double v, double* scratch, int buf) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   v = wave_sum(v);
@@ -987,7 +993,7 @@ __device__ __forceinline__ double block_sum1(double v, double* scratch, int buf)
   __syncthreads();
   double t = 0.0;
 #pragma unroll
-  for (int i = 0; i < kWaves; ++i) t += sc[i];
+  for (int i = 0; i < NW; ++i) t += sc[i];
   return t;
 }
 
@@ -1194,7 +1200,7 @@ template <typename T>
 __device__ void trivial_item(const SolveArgs& a, const MemberInfo& mi, int m, int kl) {
   const long out_idx = (long)m * a.n_lambda + kl;
   T* s_dst = reinterpret_cast<T*>(a.s_all) + out_idx * a.I_max;
-  for (int i = threadIdx.x; i < mi.I; i += kNT) s_dst[i] = (T)0;
+  for (int i = threadIdx.x; i < mi.I; i += kNTof<T>) s_dst[i] = (T)0;
   if (threadIdx.x == 0) {
     a.chi2[out_idx] = mi.status == SL_ST_INVALID ? NAN : a.consts->sum_d2 / (a.sigma * a.sigma);
     a.regv[out_idx] = mi.status == SL_ST_INVALID ? NAN : 0.0;
@@ -1210,6 +1216,7 @@ __device__ void trivial_item(const SolveArgs& a, const MemberInfo& mi, int m, in
 // residual r live in global memory, read and written by their owner thread.
 template <typename T, int CKT, bool LDSF, bool PC>
 __device__ __forceinline__ void run_item(const SolveArgs& a, const MemberInfo& mi, int m, int kl, unsigned char* smem) {
+  constexpr int NT = kNTof<T>;   // threads of this block
   const int tid = threadIdx.x;
   const long out_idx = (long)m * a.n_lambda + kl;
   T* __restrict__ s_g = reinterpret_cast<T*>(a.s_all) + out_idx * a.I_max;
@@ -1255,10 +1262,10 @@ __device__ __forceinline__ void run_item(const SolveArgs& a, const MemberInfo& m
   const int Dh = Dr1 - Dr0 + 1, Dw = Dc1 - Dc0 + 1;
 
   // s = 0, r = p = b, Q = 0, frame (with its halo) = 0
-  for (int e = tid; e < frame_elems; e += kNT) F[e] = (T)0;
+  for (int e = tid; e < frame_elems; e += NT) F[e] = (T)0;
   double rr = 0.0;
   const double* bm = a.b + (long)m * a.I_max;
-  for (int i = tid; i < I; i += kNT) {
+  for (int i = tid; i < I; i += NT) {
     const T bv = (T)bm[i];
     P[i] = bv;
     Q[i] = (T)0;
@@ -1266,7 +1273,7 @@ __device__ __forceinline__ void run_item(const SolveArgs& a, const MemberInfo& m
     r_g[i] = bv;
     rr += (double)bv * (double)bv;
   }
-  rr = block_sum1(rr, red, 0);
+  rr = block_sum1<NT / kWave>(rr, red, 0);
   const double stop2 = a.tol * a.tol * rr;
   // PC: preconditioned CG with M = c I + lambda H^T H (FP32, curvature H; the
   // caller checks that the frame holds the n x n scratch): p0 = z0 = M^-1 b.
@@ -1275,8 +1282,8 @@ __device__ __forceinline__ void run_item(const SolveArgs& a, const MemberInfo& m
     float* tab = reinterpret_cast<float*>(smem + a.pc_off);
     float* mu = tab + 2 * (ns + 1);
     const double nrm = sqrt(2.0 / (ns + 1)), pi = 3.14159265358979323846;
-    for (int e = tid; e < 2 * (ns + 1); e += kNT) tab[e] = (float)(nrm * sin(pi * e / (ns + 1)));
-    for (int e = tid; e < ns; e += kNT) {
+    for (int e = tid; e < 2 * (ns + 1); e += NT) tab[e] = (float)(nrm * sin(pi * e / (ns + 1)));
+    for (int e = tid; e < ns; e += NT) {
       const double sn = sin(pi * (e + 1) / (2.0 * (ns + 1)));
       mu[e] = (float)(16.0 * sn * sn * sn * sn);
     }
@@ -1292,8 +1299,8 @@ __device__ __forceinline__ void run_item(const SolveArgs& a, const MemberInfo& m
     }
     // y = L p into the frame (P holds p, the frame is zero); two pixels per
     // thread and step so that their table loads are in flight together
-    for (int t = tid; t < M; t += 2 * kNT) {
-      const int t2 = t + kNT;
+    for (int t = tid; t < M; t += 2 * NT) {
+      const int t2 = t + NT;
       const int rc = pix[t];
       const int rc2 = t2 < M ? pix[t2] : -1;
       const T v1 = pixel_gather(P, ns, n2, t, cellp, fxp, fyp);
@@ -1310,7 +1317,7 @@ __device__ __forceinline__ void run_item(const SolveArgs& a, const MemberInfo& m
       __syncthreads();
     } else {
       // z = B y over the dilated region into global Z
-      for (int e = tid; e < Dh * Dw; e += kNT) {
+      for (int e = tid; e < Dh * Dw; e += NT) {
         const int rr_ = Dr0 + e / Dw, cc_ = Dc0 + e % Dw;
         T acc = 0;
         for (int aa = 0; aa < K; ++aa) {
@@ -1326,7 +1333,7 @@ __device__ __forceinline__ void run_item(const SolveArgs& a, const MemberInfo& m
       }
       __syncthreads();
       // w = B^T z at the mapped pixels, back into the frame
-      for (int t = tid; t < M; t += kNT) {
+      for (int t = tid; t < M; t += NT) {
         if (pix[t] < 0) continue;
         const int rr_ = pix[t] >> 16, cc_ = pix[t] & 0xFFFF;
         T acc = 0;
@@ -1355,7 +1362,7 @@ __device__ __forceinline__ void run_item(const SolveArgs& a, const MemberInfo& m
         const int wid = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
         const int nslices = (I + 63) >> 6;
         const int lt_E = lt_rp[nslices];   // sliced-ELL entries of the member
-        for (int sl = wid; sl < nslices; sl += kNT / 64) {
+        for (int sl = wid; sl < nslices; sl += NT / 64) {
           const int idx = sl * 64 + lane;
           const int b0 = lt_rp[sl];
           const int len = (lt_rp[sl + 1] - b0) >> 6;
@@ -1412,7 +1419,7 @@ __device__ __forceinline__ void run_item(const SolveArgs& a, const MemberInfo& m
           }
         }
       } else {
-        for (int i = tid; i < I; i += kNT) {
+        for (int i = tid; i < I; i += NT) {
           T acc = 0;
           const int e0 = lt_rp[i], e1 = lt_rp[i + 1];
           for (int e = e0; e < e1; ++e) acc += lt_e[e].w * F[lt_e[e].off];
@@ -1424,9 +1431,9 @@ __device__ __forceinline__ void run_item(const SolveArgs& a, const MemberInfo& m
         }
       }
     }
-    pq = block_sum1(pq, red, 0);
+    pq = block_sum1<NT / kWave>(pq, red, 0);
     // every gather has read the frame (barrier above): back to zero for the next iteration
-    for (int e = tid; e < h * pitch; e += kNT) Frows[e] = (T)0;
+    for (int e = tid; e < h * pitch; e += NT) Frows[e] = (T)0;
     if (__builtin_amdgcn_readfirstlane((int)!(pq > 0.0))) {
       st = SL_ST_BREAKDOWN;
       break;
@@ -1437,11 +1444,11 @@ __device__ __forceinline__ void run_item(const SolveArgs& a, const MemberInfo& m
     // registers for the direction update when the chunk covers all of I.
     double rn = 0.0;
     T rk[kUpd];
-    for (int i0 = tid; i0 < I; i0 += kUpd * kNT) {
+    for (int i0 = tid; i0 < I; i0 += kUpd * NT) {
       T sk[kUpd];
 #pragma unroll
       for (int k = 0; k < kUpd; ++k) {
-        const int i = i0 + k * kNT;
+        const int i = i0 + k * NT;
         if (i < I) {
           sk[k] = s_g[i];
           rk[k] = r_g[i];
@@ -1449,7 +1456,7 @@ __device__ __forceinline__ void run_item(const SolveArgs& a, const MemberInfo& m
       }
 #pragma unroll
       for (int k = 0; k < kUpd; ++k) {
-        const int i = i0 + k * kNT;
+        const int i = i0 + k * NT;
         if (i < I) {
           s_g[i] = sk[k] + alT * P[i];
           rk[k] -= alT * Q[i];
@@ -1458,7 +1465,7 @@ __device__ __forceinline__ void run_item(const SolveArgs& a, const MemberInfo& m
         }
       }
     }
-    rn = block_sum1(rn, red, 1);
+    rn = block_sum1<NT / kWave>(rn, red, 1);
     if constexpr (PC && sizeof(T) == 4) {
       float* tab = reinterpret_cast<float*>(smem + a.pc_off);
       rz = pc_apply(reinterpret_cast<float*>(P), reinterpret_cast<float*>(Q), reinterpret_cast<float*>(F), tab,
@@ -1466,22 +1473,22 @@ __device__ __forceinline__ void run_item(const SolveArgs& a, const MemberInfo& m
                     red);
     } else {
       const T beta = (T)(rn / rr);
-      if (I <= kUpd * kNT) {
+      if (I <= kUpd * NT) {
 #pragma unroll
         for (int k = 0; k < kUpd; ++k) {
-          const int i = tid + k * kNT;
+          const int i = tid + k * NT;
           if (i < I) P[i] = rk[k] + beta * P[i];
         }
       } else {
-        for (int i0 = tid; i0 < I; i0 += kUpd * kNT) {
+        for (int i0 = tid; i0 < I; i0 += kUpd * NT) {
 #pragma unroll
           for (int k = 0; k < kUpd; ++k) {
-            const int i = i0 + k * kNT;
+            const int i = i0 + k * NT;
             if (i < I) rk[k] = r_g[i];
           }
 #pragma unroll
           for (int k = 0; k < kUpd; ++k) {
-            const int i = i0 + k * kNT;
+            const int i = i0 + k * NT;
             if (i < I) P[i] = rk[k] + beta * P[i];
           }
         }
@@ -1493,18 +1500,18 @@ __device__ __forceinline__ void run_item(const SolveArgs& a, const MemberInfo& m
   if (st == SL_ST_MAXIT && rr <= stop2) st = SL_ST_OK;
   // ---- chi^2 and ||H s||^2 from the explicit solution
   __syncthreads();
-  for (int i = tid; i < I; i += kNT) P[i] = s_g[i];
-  for (int e = tid; e < h * pitch; e += kNT) Frows[e] = (T)0;
+  for (int i = tid; i < I; i += NT) P[i] = s_g[i];
+  for (int e = tid; e < h * pitch; e += NT) Frows[e] = (T)0;
   __syncthreads();
-  for (int t = tid; t < M; t += kNT) {
+  for (int t = tid; t < M; t += NT) {
     const int rc = pix[t];
     if (rc >= 0) F0[(rc >> 16) * pitch + (rc & 0xFFFF) + fo] = pixel_gather(P, ns, n2, t, cellp, fxp, fyp) * inv_n2;
   }
   double regacc = 0.0;
-  for (int i = tid; i < I; i += kNT) regacc += reg_node(P, ns, i / ns, i % ns, a.reg);
+  for (int i = tid; i < I; i += NT) regacc += reg_node(P, ns, i / ns, i % ns, a.reg);
   __syncthreads();
   double cacc = 0.0;
-  for (int e = tid; e < Dh * Dw; e += kNT) {
+  for (int e = tid; e < Dh * Dw; e += NT) {
     const int rr_ = Dr0 + e / Dw, cc_ = Dc0 + e % Dw;
     T z = 0;
     for (int aa = 0; aa < K; ++aa) {
@@ -1555,7 +1562,7 @@ __device__ __forceinline__ int fetch_item(const SolveArgs& a, int xcd, int* sh_i
 // queue (then the others').  PC = true takes the preconditioned items that
 // k_split selected (FP32 only); PC = false all the others.
 template <typename T, int CKT, bool PC>
-__global__ void __launch_bounds__(kNT) k_solve(SolveArgs a) {
+__global__ void __launch_bounds__(kNTof<T>) k_solve(SolveArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int sh_item;
   const int xcd = blockIdx.x & 7;
@@ -1875,15 +1882,15 @@ static int enqueue(const SolveArgs& A, const LamList& lams, const Layout& L, con
     SideStream* ss = nullptr;
     if (int e = side_stream(&ss)) return e;
     SL_HIP(hipEventRecord(ss->fork, st));
-    hipLaunchKernelGGL(c.ks, dim3(L.n_wg), dim3(kNT), c.lds, st, A);
+    hipLaunchKernelGGL(c.ks, dim3(L.n_wg), dim3(kNTof<T>), c.lds, st, A);
     if (int e = check_launch("k_solve")) return e;
     SL_HIP(hipStreamWaitEvent(ss->s, ss->fork, 0));
-    hipLaunchKernelGGL(c.kpc, dim3(L.n_wg), dim3(kNT), c.lds, ss->s, A);
+    hipLaunchKernelGGL(c.kpc, dim3(L.n_wg), dim3(kNTof<T>), c.lds, ss->s, A);
     if (int e = check_launch("k_solve (preconditioned)")) return e;
     SL_HIP(hipEventRecord(ss->join, ss->s));
     SL_HIP(hipStreamWaitEvent(st, ss->join, 0));
   } else {
-    hipLaunchKernelGGL(c.ks, dim3(L.n_wg), dim3(kNT), c.lds, st, A);
+    hipLaunchKernelGGL(c.ks, dim3(L.n_wg), dim3(kNTof<T>), c.lds, st, A);
     if (int e = check_launch("k_solve")) return e;
   }
   if (e1) {
