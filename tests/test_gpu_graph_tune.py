@@ -7,6 +7,8 @@
 * A captured plan, replayed several times with new lens parameters written
   into its input buffer and eager solves and synchronisations in between,
   gives on every replay what the eager solve gives.
+* Two host threads solving at once on two streams (the library's per-device
+  side stream and tuning cache are shared) get what sequential solves get.
 """
 import os
 
@@ -117,3 +119,43 @@ def test_plan_replays_match_eager():
         err = np.linalg.norm(got["s_corner"][:n] - ref["s_corner"][:n]) / np.linalg.norm(ref["s_corner"][:n])
         assert err <= 1e-5, (rep, err)
     plan.close()
+
+
+def test_two_threads_on_two_streams_match_sequential():
+    import threading
+    import paper_1101_5803_amd as sl
+    w = synthgen.C2
+    pop = synthgen.population(synthgen.C3.seed, 256)
+    grids = synthgen.member_grids(synthgen.C3.seed, 256)
+    M = 24
+    solvers = [_c2_solver(sl, torch.float32)[0] for _ in range(2)]
+    ins = [(torch.tensor(pop[M * i:M * (i + 1)], device=DEV), torch.tensor(grids[M * i:M * (i + 1)], device=DEV))
+           for i in range(2)]
+    refs = [_np(solvers[i].solve_semilinear(*ins[i], w.lambdas, tol=w.tol, max_ns=96)) for i in range(2)]
+    outs = [solvers[i].alloc_result(M * 96 * 96, M, len(w.lambdas)) for i in range(2)]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    torch.cuda.synchronize()
+    errs = []
+
+    def run(i):
+        try:
+            with torch.cuda.stream(streams[i]):
+                for _ in range(3):
+                    solvers[i].solve_semilinear(*ins[i], w.lambdas, tol=w.tol, max_ns=96, out=outs[i])
+            streams[i].synchronize()
+        except Exception as e:   # reported below
+            errs.append(e)
+
+    th = [threading.Thread(target=run, args=(i,)) for i in range(2)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    assert not errs, errs
+    for i in range(2):
+        got = _np(outs[i])
+        for k in ("status", "k_star", "corner_status", "iters", "s_off"):
+            assert np.array_equal(got[k], refs[i][k]), (i, k)
+        assert np.array_equal(got["chi2"], refs[i]["chi2"]), i
+        n = int(refs[i]["s_off"][-1])
+        assert np.array_equal(got["s_corner"][:n], refs[i]["s_corner"][:n]), i
