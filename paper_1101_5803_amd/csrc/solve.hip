@@ -1320,13 +1320,24 @@ __device__ __forceinline__ void run_item(const SolveArgs& a, const MemberInfo& m
       for (int e = tid; e < Dh * Dw; e += NT) {
         const int rr_ = Dr0 + e / Dw, cc_ = Dc0 + e % Dw;
         T acc = 0;
-        for (int aa = 0; aa < K; ++aa) {
-          const int yr = rr_ - aa + ck - r0;
-          if (yr < 0 || yr >= h) continue;
-          for (int bb = 0; bb < K; ++bb) {
-            const int yc = cc_ - bb + ck - c0;
-            if (yc < 0 || yc >= w) continue;
-            acc += taps[ti.psf + aa * K + bb] * F0[yr * pitch + yc];
+        if (ck <= CKT) {
+          // every tap of an output in the dilated region lands in the bounding
+          // box or its zero halo (2 CKT >= 2 ck on each side): no bounds tests
+          const T* yrow = F0 + (rr_ + ck - r0) * pitch + (cc_ + ck - c0);
+          const T* tp = taps + ti.psf;
+          for (int aa = 0; aa < K; ++aa) {
+            const T* y = yrow - aa * pitch;
+            for (int bb = 0; bb < K; ++bb) acc += tp[aa * K + bb] * y[-bb];
+          }
+        } else {   // PSFs wider than the widest compiled window: the halo is narrower than ck
+          for (int aa = 0; aa < K; ++aa) {
+            const int yr = rr_ - aa + ck - r0;
+            if (yr < 0 || yr >= h) continue;
+            for (int bb = 0; bb < K; ++bb) {
+              const int yc = cc_ - bb + ck - c0;
+              if (yc < 0 || yc >= w) continue;
+              acc += taps[ti.psf + aa * K + bb] * F0[yr * pitch + yc];
+            }
           }
         }
         Z[e] = acc;
