@@ -113,7 +113,7 @@ def algorithmic_work(info, iters, nsub, ck):
     flops = 0.0
     nbytes = 0.0
     for m in range(info.shape[0]):
-        ns, I, M, r0, r1, c0, c1, st = info[m]
+        ns, I, M, r0, r1, c0, c1, st = info[m][:8]
         if st != 0:
             continue
         h, w = r1 - r0 + 1, c1 - c0 + 1

@@ -106,10 +106,27 @@ int sl_apply_L(int dtype, const double* uv, int n_members, const sl_image_grid* 
 /*
  * L^T: exact transpose of sl_apply_L (Sec. 2.2).  img_in: device
  * [n_members][ny*nx]; s_out: device packed sources, overwritten.
- * Accumulates with atomics, so the summation order is not fixed.
+ * Accumulates with atomics, so the summation order is not fixed
+ * (sl_apply_LT_ordered below is the reproducible form).
  */
 int sl_apply_LT(int dtype, const double* uv, int n_members, const sl_image_grid* img,
                 const int32_t* ns, const void* img_in, void* s_out, void* stream);
+
+/*
+ * L^T in a fixed summation order: the same operator as sl_apply_LT, with
+ * every node's terms added in ascending (pixel, subpixel, corner) order --
+ * the order of a sequential scatter over the image -- so the result is
+ * bitwise reproducible.  The terms of each node are found by a counting sort
+ * in `workspace` (device, 4-byte aligned, at least
+ * sl_apply_LT_ordered_workspace_size(img, ns, n_members) bytes; contents
+ * need not be initialised; calls sharing it must not overlap).  Other
+ * arguments as sl_apply_LT.  The workspace-size query returns 0 for invalid
+ * arguments.
+ */
+size_t sl_apply_LT_ordered_workspace_size(const sl_image_grid* img, const int32_t* ns, int n_members);
+int sl_apply_LT_ordered(int dtype, const double* uv, int n_members, const sl_image_grid* img,
+                        const int32_t* ns, const void* img_in, void* s_out, void* workspace,
+                        size_t workspace_bytes, void* stream);
 
 /*
  * B and B^T on n_images images of ny x nx (Sec. 2.2; zero padding).
@@ -167,7 +184,9 @@ typedef struct {
   int32_t* iters;      /* device int32[n_members*n_lambda] */
   int32_t* status;     /* device int32[n_members*n_lambda], SL_ST_* */
   int32_t* k_star;     /* device int32[n_members]: L-curve corner index */
-  int32_t* corner_status; /* device int32[n_members]: SL_ST_OK, _EMPTY, _INVALID or _LCURVE */
+  int32_t* corner_status; /* device int32[n_members]: SL_ST_OK, _EMPTY, _INVALID or _LCURVE; or
+                              SL_ST_MAXIT / SL_ST_BREAKDOWN when some lambda of the member's curve
+                              did not converge (k_star is still its curve's corner) */
 } sl_result;
 
 /*
@@ -241,9 +260,13 @@ int sl_plan_destroy(sl_plan* plan);
 
 /*
  * Per-member table of the last sl_solve_semilinear that used `workspace`
- * (synchronous: waits for the device).  info_host: host int32[n_members][8]
+ * (synchronous: waits for the device).  info_host: host int32[n_members][10]
  * = {ns, I, M (pixels that map onto the grid), r0, r1, c0, c1 (their
- * bounding box), status}.  Sizes must match that call.
+ * bounding box), status, Lt (layout of the transposed operator: 0 CSR rows,
+ * 1 sliced ELL, 2 sliced ELL with paired 16-bit offsets), frame (1: the
+ * member's image frame lives in LDS, 0: in global memory)}; the last two
+ * are -1 for a member whose status is not SL_ST_OK.  Sizes must match that
+ * call.
  */
 int sl_solve_member_info(const sl_problem* pb, int max_ns, int n_members, int n_lambda,
                          const void* workspace, int32_t* info_host);

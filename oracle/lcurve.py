@@ -106,3 +106,22 @@ def corner(reg, chi2):
         if kappa[j] > kappa[best] * (1.0 + 1e-12):
             best = j
     return int(keep[best]), kap_full
+
+
+def corner_set(reg, chi2, rel=1e-5, draws=64, seed=12345):
+    """Indices that are the corner of the curve for some small perturbation.
+
+    The corner is a discrete argmax, so two knots of nearly equal curvature
+    make it unstable.  Returns the set of corners of the unperturbed points
+    and of ``draws`` seeded copies whose reg and chi^2 are scaled by
+    independent factors 1 + rel * N(0, 1) (rel 1e-5 is the FP32 path's chi^2
+    tolerance).  For a well-separated maximum the set is one index.
+    """
+    reg = np.asarray(reg, dtype=np.float64)
+    chi2 = np.asarray(chi2, dtype=np.float64)
+    rng = np.random.default_rng(seed)
+    ks = {corner(reg, chi2)[0]}
+    for _ in range(draws):
+        ks.add(corner(reg * (1 + rel * rng.standard_normal(reg.size)),
+                      chi2 * (1 + rel * rng.standard_normal(chi2.size)))[0])
+    return ks

@@ -73,6 +73,10 @@ def lib():
         L.sl_lens_trace.argtypes = [vp, ip, ctypes.POINTER(ImageGrid), i32p, dp, vp, vp]
         for name in ("sl_apply_L", "sl_apply_LT"):
             getattr(L, name).argtypes = [ip, vp, ip, ctypes.POINTER(ImageGrid), i32p, vp, vp, vp]
+        L.sl_apply_LT_ordered_workspace_size.argtypes = [ctypes.POINTER(ImageGrid), i32p, ip]
+        L.sl_apply_LT_ordered_workspace_size.restype = ctypes.c_size_t
+        L.sl_apply_LT_ordered.argtypes = [ip, vp, ip, ctypes.POINTER(ImageGrid), i32p, vp, vp, vp, ctypes.c_size_t,
+                                          vp]
         for name in ("sl_apply_B", "sl_apply_BT"):
             getattr(L, name).argtypes = [ip, ip, ip, ip, vp, ip, vp, vp, vp]
         L.sl_apply_HtH.argtypes = [ip, ip, ip, i32p, vp, vp, vp]
@@ -98,7 +102,7 @@ def lib():
         L.sl_mlp_workspace_size.restype = ctypes.c_size_t
         L.sl_mlp_forward.argtypes = [vp, vp, ip, vp, vp, vp]
         L.sl_mlp_train_step.argtypes = [vp, vp, vp, vp, vp, ip, ctypes.c_float, ip, vp, vp, vp, vp]
-        for name in ("sl_lens_trace", "sl_apply_L", "sl_apply_LT", "sl_apply_B", "sl_apply_BT",
+        for name in ("sl_lens_trace", "sl_apply_L", "sl_apply_LT", "sl_apply_LT_ordered", "sl_apply_B", "sl_apply_BT",
                      "sl_apply_HtH", "sl_solve_semilinear", "sl_lcurve_corner", "sl_mlp_forward",
                      "sl_mlp_train_step", "sl_solve_member_info", "sl_profile_enable", "sl_profile_solve_ms",
                      "sl_solve_autotune", "sl_plan_create", "sl_plan_launch", "sl_plan_destroy"):

@@ -5,6 +5,7 @@
 // solve.hip fuses the same operators into one persistent kernel; the kernels
 // here are straightforward one-thread-per-output launches over global memory,
 // except B/B^T which stage input tiles and the PSF in LDS.
+#include <algorithm>
 #include <cstdarg>
 #include <vector>
 
@@ -87,6 +88,98 @@ __global__ void k_apply_LT(const double* __restrict__ uv, int J, int nsub, int n
     atomicAdd(&s[cell + ns], (1 - tx) * ty * val);
     atomicAdd(&s[cell + ns + 1], tx * ty * val);
   }
+}
+
+// Ordered L^T (fixed summation order).  A counting sort by node of the keys
+// key = 4 t + corner (t = subpixel index j n^2 + k, corner 0..3 for the
+// nodes cell, cell + 1, cell + ns, cell + ns + 1), then one thread per node
+// sums its terms in ascending key order, i.e. by pixel, subpixel, corner:
+// the order of a sequential scatter over the pixels.
+__global__ void k_lt_count(const double* __restrict__ uv, long nsubpix, int ns, int* __restrict__ cnt) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nsubpix) return;
+  int cell;
+  double fx, fy;
+  if (!grid_cell(uv[2 * t], uv[2 * t + 1], ns, cell, fx, fy)) return;
+  atomicAdd(&cnt[cell], 1);
+  atomicAdd(&cnt[cell + 1], 1);
+  atomicAdd(&cnt[cell + ns], 1);
+  atomicAdd(&cnt[cell + ns + 1], 1);
+}
+
+// Exclusive scan of cnt[0..I) into ptr[0..I] and the fill cursors cur (one block).
+__global__ void __launch_bounds__(1024) k_lt_scan(const int* __restrict__ cnt, int I, int* __restrict__ ptr,
+                                                  int* __restrict__ cur) {
+  __shared__ int wsum[16];
+  __shared__ int carry;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  if (tid == 0) carry = 0;
+  __syncthreads();
+  for (int i0 = 0; i0 < I; i0 += 1024) {
+    const int i = i0 + tid;
+    const int v = i < I ? cnt[i] : 0;
+    int incl = v;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int u = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += u;
+    }
+    if (lane == 63) wsum[wid] = incl;
+    __syncthreads();
+    int before = carry;
+    for (int w = 0; w < wid; ++w) before += wsum[w];
+    if (i < I) {
+      ptr[i] = before + incl - v;
+      cur[i] = before + incl - v;
+    }
+    __syncthreads();
+    if (tid == 1023) carry = before + incl;
+    __syncthreads();
+  }
+  if (tid == 0) ptr[I] = carry;
+}
+
+__global__ void k_lt_fill(const double* __restrict__ uv, long nsubpix, int ns, int* __restrict__ cur,
+                          int* __restrict__ keys) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nsubpix) return;
+  int cell;
+  double fx, fy;
+  if (!grid_cell(uv[2 * t], uv[2 * t + 1], ns, cell, fx, fy)) return;
+  const int nd[4] = {cell, cell + 1, cell + ns, cell + ns + 1};
+#pragma unroll
+  for (int q = 0; q < 4; ++q) keys[atomicAdd(&cur[nd[q]], 1)] = (int)(4 * t + q);
+}
+
+template <typename T>
+__global__ void k_lt_gather(const double* __restrict__ uv, int n2, int ns, const int* __restrict__ ptr,
+                            int* __restrict__ keys, const T* __restrict__ img, T* __restrict__ s) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ns * ns) return;
+  const int e0 = ptr[i], e1 = ptr[i + 1];
+  // insertion sort of this node's keys (the segment belongs to this thread)
+  for (int e = e0 + 1; e < e1; ++e) {
+    const int k = keys[e];
+    int f = e - 1;
+    while (f >= e0 && keys[f] > k) {
+      keys[f + 1] = keys[f];
+      --f;
+    }
+    keys[f + 1] = k;
+  }
+  T acc = 0;
+  for (int e = e0; e < e1; ++e) {
+    const int key = keys[e];
+    const long t = key >> 2;
+    const int q = key & 3;
+    int cell;
+    double fx, fy;
+    grid_cell(uv[2 * t], uv[2 * t + 1], ns, cell, fx, fy);
+    const T tx = (T)fx, ty = (T)fy;
+    const T val = img[t / n2] / (T)n2;
+    const T w = q == 0 ? (1 - tx) * (1 - ty) : q == 1 ? tx * (1 - ty) : q == 2 ? (1 - tx) * ty : tx * ty;
+    acc += w * val;
+  }
+  s[i] = acc;
 }
 
 template <typename T>
@@ -211,6 +304,43 @@ static int apply_LT_impl(const double* uv, int n_members, const sl_image_grid* i
   return check_launch("k_apply_LT");
 }
 
+// Workspace of the ordered L^T: per member (I + 1) + I ints of row starts and
+// cursors and 4 J n^2 keys; members are processed one after another, so
+// the largest member sets the size.
+static size_t lt_ordered_ws(const sl_image_grid* img, const int32_t* ns, int n_members) {
+  long I = 0;
+  for (int m = 0; m < n_members; ++m) I = std::max(I, (long)ns[m] * ns[m]);
+  const long keys = 4L * img->nx * img->ny * img->nsub * img->nsub;
+  return sizeof(int) * (size_t)(2 * I + 1 + I + keys);
+}
+
+template <typename T>
+static int apply_LT_ordered_impl(const double* uv, int n_members, const sl_image_grid* img, const int32_t* ns,
+                                 const void* in, void* s, void* ws, hipStream_t st) {
+  const int J = img->nx * img->ny, n2 = img->nsub * img->nsub;
+  const long nsp = (long)J * n2;
+  long I_max = 0;
+  for (int m = 0; m < n_members; ++m) I_max = std::max(I_max, (long)ns[m] * ns[m]);
+  int* cnt = (int*)ws;
+  int* ptr = cnt + I_max;
+  int* cur = ptr + I_max + 1;
+  int* keys = cur + I_max;
+  long soff = 0;
+  for (int m = 0; m < n_members; ++m) {
+    const int I = ns[m] * ns[m];
+    const double* uvm = uv + (long)m * nsp * 2;
+    hipLaunchKernelGGL(k_fill<int>, dim3(nblocks(I, 256)), dim3(256), 0, st, cnt, (long)I, 0);
+    hipLaunchKernelGGL(k_lt_count, dim3(nblocks(nsp, 256)), dim3(256), 0, st, uvm, nsp, ns[m], cnt);
+    hipLaunchKernelGGL(k_lt_scan, dim3(1), dim3(1024), 0, st, cnt, I, ptr, cur);
+    hipLaunchKernelGGL(k_lt_fill, dim3(nblocks(nsp, 256)), dim3(256), 0, st, uvm, nsp, ns[m], cur, keys);
+    hipLaunchKernelGGL(k_lt_gather<T>, dim3(nblocks(I, 256)), dim3(256), 0, st, uvm, n2, ns[m], ptr, keys,
+                       (const T*)in + (long)m * J, (T*)s + soff);
+    if (int e = check_launch("ordered L^T")) return e;
+    soff += I;
+  }
+  return SL_OK;
+}
+
 template <typename T, bool TR>
 static int blur_impl(int nx, int ny, int n_images, const double* psf, int k, const void* in, void* out,
                      hipStream_t st) {
@@ -264,6 +394,27 @@ int sl_apply_LT(int dtype, const double* uv, int n_members, const sl_image_grid*
     return apply_LT_impl<float>(uv, n_members, img, ns, img_in, s_out, (hipStream_t)stream);
   if (dtype == SL_F64)
     return apply_LT_impl<double>(uv, n_members, img, ns, img_in, s_out, (hipStream_t)stream);
+  SL_REQUIRE(false, "unknown dtype %d", dtype);
+}
+
+size_t sl_apply_LT_ordered_workspace_size(const sl_image_grid* img, const int32_t* ns, int n_members) {
+  if (check_grid(img) != SL_OK || check_ns(ns, n_members) != SL_OK) return 0;
+  return lt_ordered_ws(img, ns, n_members);
+}
+
+int sl_apply_LT_ordered(int dtype, const double* uv, int n_members, const sl_image_grid* img, const int32_t* ns,
+                        const void* img_in, void* s_out, void* workspace, size_t workspace_bytes, void* stream) {
+  if (int e = check_grid(img)) return e;
+  if (int e = check_ns(ns, n_members)) return e;
+  SL_REQUIRE(uv && img_in && s_out && workspace, "NULL device pointer");
+  SL_REQUIRE(((uintptr_t)workspace & 3) == 0, "workspace must be 4-byte aligned");
+  SL_REQUIRE(4L * img->nx * img->ny * img->nsub * img->nsub < (1L << 31), "image too large for 32-bit keys");
+  const size_t need = lt_ordered_ws(img, ns, n_members);
+  SL_REQUIRE(workspace_bytes >= need, "workspace too small: %zu < %zu bytes", workspace_bytes, need);
+  if (dtype == SL_F32)
+    return apply_LT_ordered_impl<float>(uv, n_members, img, ns, img_in, s_out, workspace, (hipStream_t)stream);
+  if (dtype == SL_F64)
+    return apply_LT_ordered_impl<double>(uv, n_members, img, ns, img_in, s_out, workspace, (hipStream_t)stream);
   SL_REQUIRE(false, "unknown dtype %d", dtype);
 }
 

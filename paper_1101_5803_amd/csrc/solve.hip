@@ -65,7 +65,8 @@ struct alignas(16) MemberInfo {
   int Mtrue;       // pixels with at least one subpixel on the grid
   int sell;        // transposed operator: CSR (0), sliced-ELL (1), sliced-ELL with paired 16-bit offsets (2)
   float pc_c;      // scale c of the spectral preconditioner (see k_prep)
-  int pad_[3];
+  int lds_frame;   // 1: the member's image frame fits in LDS beside p and q; 0: global frame
+  int pad_[2];
 };
 
 // Device constants written by k_setup (one copy per workspace).
@@ -708,6 +709,78 @@ __device__ int build_transpose(const SolveArgs& a, int m, int ns, int slots, con
   return paired ? 2 : sell;
 }
 
+// bacc[key] += val on the lanes of one wave with key >= 0; lanes that share
+// a key add in lane order (they take turns by their rank among the lanes
+// with that key), so every node's sum has the same order on every run.
+__device__ __forceinline__ void wave_ordered_add(double* bacc, int key, double val) {
+  const int lane = threadIdx.x & 63;
+  if (!__builtin_amdgcn_readfirstlane((int)(__ballot(key >= 0) != 0ull))) return;   // uniform
+  int rank = 0;
+  for (int l = 0; l < 64; ++l) {   // uniform lane index: v_readlane
+    const int kl = __builtin_amdgcn_readlane(key, l);
+    rank += (l < lane && kl == key) ? 1 : 0;
+  }
+  for (int r = 0; __ballot(key >= 0 && rank >= r) != 0ull; ++r) {
+    if (key >= 0 && rank == r) bacc[key] += val;
+    // this round's LDS writes precede the next round's reads
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+}
+
+// Right-hand side b = L^T B^T d in FP64 (Eq. 7) into bacc[I] (zeroed), by
+// one wave: it walks the mapped slots 64 at a time; each lane correlates
+// the data with the PSF at its pixel (B^T d) and spreads the value over the
+// pixel's (node, weight) pairs, pair by pair, through wave_ordered_add.  The
+// order of every node's terms is therefore (slot group, pair, lane), the
+// same on every run.  `slots` is a multiple of 64.
+template <typename T>
+__device__ void rhs_fixed_order(const SolveArgs& a, int ns, int slots, const int32_t* pix, const int32_t* cellp,
+                                const T* fxp, const T* fyp, double* bacc) {
+  const int lane = threadIdx.x & 63;
+  const int nx = a.nx, ny = a.ny, K = a.K, ck = a.ck, n2 = a.n2;
+  for (int t0 = 0; t0 < slots; t0 += 64) {
+    const int t = t0 + lane;
+    const int rc = pix[t];
+    double v = 0.0;
+    if (rc >= 0) {
+      const int r = rc >> 16, c = rc & 0xFFFF;
+      for (int aa = 0; aa < K; ++aa) {
+        const int rr = r + aa - ck;
+        if (rr < 0 || rr >= ny) continue;
+        for (int bb = 0; bb < K; ++bb) {
+          const int cc = c + bb - ck;
+          if (cc < 0 || cc >= nx) continue;
+          v += a.psf[aa * K + bb] * a.d[rr * nx + cc];
+        }
+      }
+    }
+    if (n2 == 4) {
+      int nd[16];
+      double ww[16];
+      if (rc >= 0) {
+        pixel_pairs4(t, ns, cellp, fxp, fyp, nd, ww);
+      } else {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          nd[q] = -1;
+          ww[q] = 0.0;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 16; ++q) wave_ordered_add(bacc, nd[q], ww[q] * v);
+    } else {
+      int node[4 * SL_MAX_NSUB * SL_MAX_NSUB];
+      double wt[4 * SL_MAX_NSUB * SL_MAX_NSUB];
+      const int np = rc >= 0 ? pixel_pairs(t, ns, n2, cellp, fxp, fyp, node, wt) : 0;
+      int npmax = np;
+      for (int o = 32; o > 0; o >>= 1) npmax = max(npmax, __shfl_xor(npmax, o, 64));
+      for (int q = 0; q < npmax; ++q) wave_ordered_add(bacc, q < np ? node[q] : -1, q < np ? wt[q] * v : 0.0);
+    }
+  }
+}
+
 template <typename T>
 __device__ void prep_member(const SolveArgs& a, int m, MemberInfo mi, const double* gl, int* bbox, int* scan,
                             double* bacc) {
@@ -799,37 +872,13 @@ __device__ void prep_member(const SolveArgs& a, int m, MemberInfo mi, const doub
   }
   __syncthreads();
   const int Mm = slots;
-  // right-hand side b = L^T B^T d (FP64)
+  // right-hand side b = L^T B^T d (FP64), summed in a fixed order by wave 0
   const int I = ns * ns;
   for (int i = tid; i < I; i += blockDim.x) bacc[i] = 0.0;
   __syncthreads();
-  const int K = a.K, ck = a.ck;
-  const double inv_n2 = 1.0 / n2;
-  for (int t = tid; t < Mm; t += blockDim.x) {
-    if (pix[t] < 0) continue;
-    const int r = pix[t] >> 16, c = pix[t] & 0xFFFF;
-    double v = 0.0;
-    for (int aa = 0; aa < K; ++aa) {
-      const int rr = r + aa - ck;
-      if (rr < 0 || rr >= ny) continue;
-      for (int bb = 0; bb < K; ++bb) {
-        const int cc = c + bb - ck;
-        if (cc < 0 || cc >= nx) continue;
-        v += a.psf[aa * K + bb] * a.d[rr * nx + cc];
-      }
-    }
-    v *= inv_n2;
-    for (int k = 0; k < n2; ++k) {
-      const int cell = cellp[(long)t * n2 + k];
-      if (cell < 0) continue;
-      const double fx = (double)fxp[(long)t * n2 + k], fy = (double)fyp[(long)t * n2 + k];
-      atomicAdd(&bacc[cell], (1 - fx) * (1 - fy) * v);
-      atomicAdd(&bacc[cell + 1], fx * (1 - fy) * v);
-      atomicAdd(&bacc[cell + ns], (1 - fx) * fy * v);
-      atomicAdd(&bacc[cell + ns + 1], fx * fy * v);
-    }
-  }
+  if (tid < 64) rhs_fixed_order<T>(a, ns, Mm, pix, cellp, fxp, fyp, bacc);
   __syncthreads();
+  const double inv_n2 = 1.0 / n2;
   // scale of the spectral preconditioner: c = sum_i cov_i b_i^2 / sum_i b_i^2
   // with cov = L^T 1 (the bilinear weight each node receives), a cheap
   // stand-in for the Rayleigh quotient <b, L^T B^T B L b> / <b, b>
@@ -858,6 +907,8 @@ __device__ void prep_member(const SolveArgs& a, int m, MemberInfo mi, const doub
   if (Mtrue > 0)
     sell = build_transpose<T>(a, m, ns, Mm, bbox, scan, reinterpret_cast<int*>(bacc), pix, cellp, fxp, fyp);
   if (tid == 0) {
+    const int fh = Mtrue > 0 ? bbox[1] - bbox[0] + 1 : 0, fw = Mtrue > 0 ? bbox[3] - bbox[2] + 1 : 0;
+    mi.lds_frame = (long)(fh + 4 * a.ckt + kSegR) * ((fw + 4 * a.ckt) | 1) <= a.lds_frame_cap;
     mi.sell = sell;
     mi.M = Mm;
     mi.Mtrue = Mtrue;
@@ -1584,9 +1635,7 @@ __global__ void __launch_bounds__(kNTof<T>) k_solve(SolveArgs a) {
       run_item<T, CKT, true, true>(a, mi, m, kl, smem);
     } else {
       const int status = __builtin_amdgcn_readfirstlane(mi.status);
-      const int h = mi.r1 - mi.r0 + 1, w = mi.c1 - mi.c0 + 1;
-      const int fits = __builtin_amdgcn_readfirstlane(
-          (int)((h + 4 * CKT + kSegR) * ((w + 4 * CKT) | 1) <= a.lds_frame_cap));
+      const int fits = __builtin_amdgcn_readfirstlane(mi.lds_frame);
       if (status != SL_ST_OK)
         trivial_item<T>(a, mi, m, kl);
       else if (fits)
@@ -1610,8 +1659,7 @@ __global__ void __launch_bounds__(64) k_split(SolveArgs a) {
       const int item = a.queues[q * a.qcap + k];
       const MemberInfo mi = a.minfo[item / a.n_lambda];
       const double lam = a.lamv[item % a.n_lambda];
-      const int h = mi.r1 - mi.r0 + 1, w = mi.c1 - mi.c0 + 1;
-      const bool fits = (h + 4 * a.ckt + kSegR) * ((w + 4 * a.ckt) | 1) <= a.lds_frame_cap;
+      const bool fits = mi.lds_frame != 0;
       const bool pc = sizeof(T) == 4 && a.reg == SL_H_CURVATURE && !a.plain_cg && mi.status == SL_ST_OK && fits &&
                       mi.ns * mi.ns <= a.lds_frame_cap && lam >= (double)kPcTheta * mi.pc_c;
       // Both stores unconditionally, then bump one count: the store not
@@ -1652,6 +1700,15 @@ __global__ void __launch_bounds__(256) k_corner(SolveArgs a) {
         cst = SL_ST_LCURVE;
       }
     }
+    // a curve through an unconverged point is flagged (its corner is still computed)
+    if (cst == SL_ST_OK)
+      for (int j = 0; j < nl; ++j) {
+        const int sj = a.status[(long)m * nl + j];
+        if (sj == SL_ST_MAXIT || sj == SL_ST_BREAKDOWN) {
+          cst = sj;
+          break;
+        }
+      }
     a.k_star[m] = k;
     a.corner_status[m] = cst;
     sh_k = k;
@@ -1866,9 +1923,13 @@ static int configure(SolveArgs& A, const Layout& L, const sl_tuning& v, LaunchCf
 // plain k_solve [beside the preconditioned k_solve on the side stream, joined
 // back to st], k_corner.  `profile` records HIP events on st around the CG
 // phase when profiling is on (never inside a capture).
+// `priv` (nullable): a side stream and events owned by the caller (a graph
+// capture uses its own, so that no other thread's eager solve can fork onto
+// a stream that is part of the capture); NULL takes the per-device one under
+// its lock.
 template <typename T>
 static int enqueue(const SolveArgs& A, const LamList& lams, const Layout& L, const LaunchCfg& c, hipStream_t st,
-                   bool profile) {
+                   bool profile, SideStream* priv = nullptr) {
   hipLaunchKernelGGL(k_setup<T>, dim3(1), dim3(1024), 0, st, A, lams);
   if (int e = check_launch("k_setup")) return e;
   hipLaunchKernelGGL(k_prep<T>, dim3(A.n_members), dim3(1024), c.prep_lds, st, A);
@@ -1889,9 +1950,12 @@ static int enqueue(const SolveArgs& A, const LamList& lams, const Layout& L, con
     // stream: both are persistent, so its blocks take the CUs that the plain
     // launch's last long items leave idle.  They share no queue and no
     // per-block scratch.
-    std::lock_guard<std::mutex> g(g_side_mu);
-    SideStream* ss = nullptr;
-    if (int e = side_stream(&ss)) return e;
+    std::unique_lock<std::mutex> g(g_side_mu, std::defer_lock);
+    SideStream* ss = priv;
+    if (!ss) {
+      g.lock();
+      if (int e = side_stream(&ss)) return e;
+    }
     SL_HIP(hipEventRecord(ss->fork, st));
     hipLaunchKernelGGL(c.ks, dim3(L.n_wg), dim3(kNTof<T>), c.lds, st, A);
     if (int e = check_launch("k_solve")) return e;
@@ -1918,8 +1982,9 @@ static int configure_any(int dtype, SolveArgs& A, const Layout& L, const sl_tuni
 }
 
 static int enqueue_any(int dtype, const SolveArgs& A, const LamList& lams, const Layout& L, const LaunchCfg& c,
-                       hipStream_t st, bool profile) {
-  return dtype == SL_F32 ? enqueue<float>(A, lams, L, c, st, profile) : enqueue<double>(A, lams, L, c, st, profile);
+                       hipStream_t st, bool profile, SideStream* priv = nullptr) {
+  return dtype == SL_F32 ? enqueue<float>(A, lams, L, c, st, profile, priv)
+                         : enqueue<double>(A, lams, L, c, st, profile, priv);
 }
 
 // ------------------------------------------------------------------ autotuner table
@@ -2127,20 +2192,32 @@ int sl_plan_create(const sl_problem* pb, const double* lens, const int32_t* ns, 
     return e;
   LaunchCfg c;
   if (int e = configure_any(pb->dtype, A, L, resolve_tuning(pb, max_ns, n_members, n_lambda, opt), &c)) return e;
-  if (c.kpc) {   // the side stream and its events exist before the capture starts
-    std::lock_guard<std::mutex> gs(g_side_mu);
-    SideStream* ss = nullptr;
-    if (int e = side_stream(&ss)) return e;
+  // The capture forks onto a side stream of its own, created before the
+  // capture starts (default priority) and destroyed once it has ended.
+  SideStream own;
+  if (c.kpc) {
+    SL_HIP(hipStreamCreateWithFlags(&own.s, hipStreamNonBlocking));
+    SL_HIP(hipEventCreateWithFlags(&own.fork, hipEventDisableTiming));
+    SL_HIP(hipEventCreateWithFlags(&own.join, hipEventDisableTiming));
   }
+  auto drop_own = [&]() {
+    if (own.s) (void)hipStreamDestroy(own.s);
+    if (own.fork) (void)hipEventDestroy(own.fork);
+    if (own.join) (void)hipEventDestroy(own.join);
+  };
   hipStream_t cs;
-  SL_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
+    drop_own();
+    set_error("hipStreamCreateWithFlags failed");
+    return SL_EHIP;
+  }
   hipGraph_t g = nullptr;
   int rc = SL_OK;
   if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
     set_error("hipStreamBeginCapture failed: %s", hipGetErrorString(hipGetLastError()));
     rc = SL_EHIP;
   } else {
-    rc = enqueue_any(pb->dtype, A, lams, L, c, cs, false);
+    rc = enqueue_any(pb->dtype, A, lams, L, c, cs, false, c.kpc ? &own : nullptr);
     const hipError_t ee = hipStreamEndCapture(cs, &g);
     if (rc == SL_OK && ee != hipSuccess) {
       set_error("hipStreamEndCapture failed: %s", hipGetErrorString(ee));
@@ -2148,6 +2225,7 @@ int sl_plan_create(const sl_problem* pb, const double* lens, const int32_t* ns, 
     }
   }
   (void)hipStreamDestroy(cs);
+  drop_own();
   hipGraphExec_t ge = nullptr;
   if (rc == SL_OK) {
     const hipError_t ie = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
@@ -2201,7 +2279,7 @@ int sl_solve_member_info(const sl_problem* pb, int max_ns, int n_members, int n_
   SL_HIP(hipMemcpy(mi.data(), (const unsigned char*)workspace + L.minfo, sizeof(MemberInfo) * n_members,
                    hipMemcpyDeviceToHost));
   for (int m = 0; m < n_members; ++m) {
-    int32_t* o = info_host + 8 * m;
+    int32_t* o = info_host + 10 * m;
     o[0] = mi[m].ns;
     o[1] = mi[m].I;
     o[2] = mi[m].Mtrue;
@@ -2210,6 +2288,8 @@ int sl_solve_member_info(const sl_problem* pb, int max_ns, int n_members, int n_
     o[5] = mi[m].c0;
     o[6] = mi[m].c1;
     o[7] = mi[m].status;
+    o[8] = mi[m].status == SL_ST_OK ? mi[m].sell : -1;
+    o[9] = mi[m].status == SL_ST_OK ? mi[m].lds_frame : -1;
   }
   return SL_OK;
 }

@@ -74,6 +74,23 @@ def apply_LT(uv: torch.Tensor, grid: Grid, ns, img: torch.Tensor) -> torch.Tenso
     return out
 
 
+def apply_LT_ordered(uv: torch.Tensor, grid: Grid, ns, img: torch.Tensor) -> torch.Tensor:
+    """Packed L^T of images (M, J) summed in a fixed order (bitwise reproducible)."""
+    _dev_check(uv, img)
+    ns = list(ns)
+    out = torch.empty(int(sum(n * n for n in ns)), dtype=img.dtype, device=img.device)
+    g = grid.c()
+    nsa = L.i32_array(ns)
+    need = int(L.lib().sl_apply_LT_ordered_workspace_size(ctypes.byref(g), nsa, len(ns)))
+    if need == 0:
+        raise L.SemilinError(L.lib().sl_last_error().decode())
+    ws = torch.empty(need, dtype=torch.uint8, device=img.device)
+    L.check(L.lib().sl_apply_LT_ordered(_DT[img.dtype], L.ptr(uv), len(ns), ctypes.byref(g), nsa,
+                                        L.ptr(img.contiguous()), L.ptr(out), L.ptr(ws), need, L.stream_handle()),
+            "sl_apply_LT_ordered")
+    return out
+
+
 def _blur(name, psf, x):
     _dev_check(psf, x)
     psf = psf.to(torch.float64).contiguous()
@@ -210,8 +227,8 @@ class Solver:
         )
 
     def member_info(self, max_ns: int, n_members: int, n_lambda: int) -> np.ndarray:
-        """(n_members, 8) int32 table {ns, I, M, r0, r1, c0, c1, status} of the last solve."""
-        info = np.zeros((n_members, 8), dtype=np.int32)
+        """(n_members, 10) int32 table {ns, I, M, r0, r1, c0, c1, status, Lt layout, LDS frame} of the last solve."""
+        info = np.zeros((n_members, 10), dtype=np.int32)
         L.check(L.lib().sl_solve_member_info(ctypes.byref(self._pb), max_ns, n_members, n_lambda, L.ptr(self._ws),
                                              info.ctypes.data_as(ctypes.c_void_p)), "sl_solve_member_info")
         return info

@@ -87,7 +87,9 @@ class SolverFitness:
 
     Every member uses the same source grid side `ns`.  A member whose solve
     or corner is not valid (no mapped pixel, invalid parameters, degenerate
-    L-curve) gets fitness +inf.
+    L-curve) or whose corner solve did not converge gets fitness +inf.  A
+    member whose curve has an unconverged point elsewhere keeps its corner
+    (its corner status says so).
     """
 
     def __init__(self, solver: ops.Solver, box: Box, ns: int, lambdas, tol: float = 1e-7, maxit: int = 4000):
@@ -113,9 +115,12 @@ class SolverFitness:
         chi2 = res["chi2"][:n].cpu().numpy()
         k = res["k_star"][:n].cpu().numpy()
         cs = res["corner_status"][:n].cpu().numpy()
+        st = res["status"][:n].cpu().numpy()
         self.evals += n
         f = np.full(n, np.inf)
-        ok = (k >= 0) & (cs == 0)
+        ok = (k >= 0) & np.isin(cs, (0, 1, 3))
+        rows = np.nonzero(ok)[0]
+        ok[rows] = st[rows, k[rows]] == 0
         f[ok] = chi2[np.nonzero(ok)[0], k[ok]]
         return f
 

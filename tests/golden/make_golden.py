@@ -12,8 +12,21 @@ root:  python tests/golden/make_golden.py   (about two minutes on 8 cores)
 * c4_sample.npz  -- the c4 workload (200x200 image, 100x100 nodes, 21x21 PSF,
   24 lambdas): the true lens and two members of the c4 population, same
   quantities (about ten minutes on 3 cores).
+* c3_full.npz    -- all 256 members of the c3 population against the c2
+  image: per-lambda chi^2, ||H s||^2, iterations, status, the curvature at
+  every knot and the corner k*, and the solution at every index of the
+  member's corner set (the corners the L-curve gives under relative 1e-5
+  perturbations of its points), packed in FP32; for the three largest grids
+  also the corner solution in FP64 (about 30 minutes on 7 cores).
 
-`python tests/golden/make_golden.py c4` writes only c4_sample.npz.
+* c2_nsub.npz    -- the c2 lens and image modelled with 1, 3 and 4 subpixels
+  per side (the other goldens use 2), 6 lambdas over 1e-3..1e1: chi^2,
+  ||H s||^2, iterations, corner and corner solution (about two minutes on
+  3 cores).
+
+`python tests/golden/make_golden.py c4` writes only c4_sample.npz;
+`python tests/golden/make_golden.py c3full` writes only c3_full.npz;
+`python tests/golden/make_golden.py c2nsub` writes only c2_nsub.npz.
 """
 import os
 import sys
@@ -50,9 +63,69 @@ def c4():
              lambdas=np.array(w.lambdas))
 
 
+def c3_full(threads=7):
+    w = synthgen.C2
+    D = mock.workload_data(w)
+    M = 256
+    pop = synthgen.population(synthgen.C3.seed, M)
+    grids = synthgen.member_grids(synthgen.C3.seed, M)
+    out = coracle.evaluate(pop, grids, w.half_width, w.nx, w.ny, w.pix, w.nsub_model, D["d"], D["sigma"], D["psf"],
+                           w.reg, w.lambdas, tol=1e-10, want_s=True, threads=threads)
+    nl = len(w.lambdas)
+    ks = np.zeros(M, dtype=np.int32)
+    kappa = np.full((M, nl), np.nan)
+    sets = np.zeros((M, nl), dtype=bool)
+    for m in range(M):
+        k, kap = lcurve.corner(out["reg"][m], out["chi2"][m])
+        ks[m] = k
+        kappa[m] = kap
+        for kk in lcurve.corner_set(out["reg"][m], out["chi2"][m]):
+            sets[m, kk] = True
+    # packed FP32 solutions at every index of every member's corner set
+    s_idx, s_pack, s_off = [], [], [0]
+    for m in range(M):
+        I = int(grids[m]) ** 2
+        for kk in np.nonzero(sets[m])[0]:
+            s_idx.append((m, kk))
+            s_pack.append(out["s"][m, kk, :I].astype(np.float32))
+            s_off.append(s_off[-1] + I)
+    big = np.argsort(-grids, kind="stable")[:3]
+    np.savez_compressed(os.path.join(HERE, "c3_full.npz"), lens=pop, ns=grids, chi2=out["chi2"], reg=out["reg"],
+                        iters=out["iters"], status=out["status"], k_star=ks, kappa=kappa, corner_sets=sets,
+                        s_index=np.array(s_idx, dtype=np.int32), s_off=np.array(s_off, dtype=np.int64),
+                        s_f32=np.concatenate(s_pack), f64_members=big.astype(np.int32),
+                        s_f64=np.stack([out["s"][m, ks[m]] for m in big]), lambdas=np.array(w.lambdas), tol=1e-10)
+
+
+def c2_nsub():
+    import concurrent.futures as cf
+    w = synthgen.C2
+    D = mock.workload_data(w)
+    lams = synthgen.log_grid(1e-3, 1e1, 6)
+    subs = (1, 3, 4)
+
+    def one(n):
+        return coracle.evaluate(np.atleast_2d(D["lens"]), [w.ns], w.half_width, w.nx, w.ny, w.pix, n, D["d"],
+                                D["sigma"], D["psf"], w.reg, lams, tol=1e-10, want_s=True, threads=1)
+
+    with cf.ThreadPoolExecutor(3) as ex:
+        outs = list(ex.map(one, subs))
+    ks = [lcurve.corner(o["reg"][0], o["chi2"][0])[0] for o in outs]
+    np.savez_compressed(os.path.join(HERE, "c2_nsub.npz"), nsub=np.array(subs), lambdas=np.array(lams),
+                        chi2=np.stack([o["chi2"][0] for o in outs]), reg=np.stack([o["reg"][0] for o in outs]),
+                        iters=np.stack([o["iters"][0] for o in outs]), k_star=np.array(ks),
+                        s_corner=np.stack([o["s"][0, k] for o, k in zip(outs, ks)]))
+
+
 def main():
+    if sys.argv[1:] == ["c2nsub"]:
+        c2_nsub()
+        return
     if sys.argv[1:] == ["c4"]:
         c4()
+        return
+    if sys.argv[1:] == ["c3full"]:
+        c3_full()
         return
     w = synthgen.C2
     D = mock.workload_data(w)

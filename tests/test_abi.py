@@ -62,3 +62,62 @@ def test_host_validation_without_gpu():
     assert L.sl_lcurve_corner(a, a, 3, ctypes.byref(k), None) == -1
     L.sl_version.restype = ctypes.c_char_p
     assert L.sl_version()
+
+
+def _host_corner(L, reg, chi2):
+    dp = ctypes.POINTER(ctypes.c_double)
+    L.sl_lcurve_corner.argtypes = [dp, dp, ctypes.c_int, ctypes.POINTER(ctypes.c_int32), dp]
+    import numpy as np
+    reg = np.ascontiguousarray(reg, dtype=np.float64)
+    chi2 = np.ascontiguousarray(chi2, dtype=np.float64)
+    kap = np.zeros(reg.size)
+    k = ctypes.c_int32(-7)
+    rc = L.sl_lcurve_corner(reg.ctypes.data_as(dp), chi2.ctypes.data_as(dp), reg.size, ctypes.byref(k),
+                            kap.ctypes.data_as(dp))
+    return rc, int(k.value), kap
+
+
+def _valid_curves():
+    """Valid L-curves: the stored oracle curves of the c2, c3 and c4 goldens and constructed curves."""
+    import numpy as np
+    gold = os.path.join(ROOT, "tests", "golden")
+    curves = []
+    g = np.load(os.path.join(gold, "c2_oracle.npz"))
+    curves.append((g["reg"], g["chi2"]))
+    for name in ("c3_sample.npz", "c4_sample.npz"):
+        g = np.load(os.path.join(gold, name))
+        curves += list(zip(g["reg"], g["chi2"]))
+    full = os.path.join(gold, "c3_full.npz")
+    if os.path.exists(full):
+        g = np.load(full)
+        curves += list(zip(g["reg"], g["chi2"]))
+    lam = np.logspace(-3, 2, 12)
+    reg = 1.0 / (1.0 + lam) ** 2 + 1e-3
+    chi2 = 1.0 + lam / (1.0 + lam)
+    curves.append((reg, chi2))
+    curves.append((np.insert(reg, 6, reg[5]), np.insert(chi2, 6, chi2[5])))   # a repeated point
+    first = np.array([(0, 4), (0.02, 3.2), (0.05, 2.5), (0.1, 2.1), (0.25, 1.95), (0.6, 1.88), (1.0, 1.8),
+                      (1.35, 1.65)], dtype=float)
+    P = np.vstack([first, [[1.5, 1.5]], first[::-1][:, ::-1]])     # two equal bends
+    curves.append((10 ** P[:, 0], 10 ** P[:, 1]))
+    return curves
+
+
+def test_host_lcurve_corner_matches_oracle():
+    """sl_lcurve_corner (host, FP64) on valid curves: the oracle's k* exactly, the same dropped
+    points, and the curvature at every kept knot within 1e-11 of the curve's largest curvature
+    (the two solve the spline systems by different eliminations; small curvatures come from a
+    cancelling difference, so the bound is on the absolute error relative to the maximum)."""
+    import numpy as np
+    from oracle import lcurve
+    L = _lib()
+    curves = _valid_curves()
+    assert len(curves) >= 8
+    for reg, chi2 in curves:
+        rc, k, kap = _host_corner(L, reg, chi2)
+        k_ref, kap_ref = lcurve.corner(reg, chi2)
+        assert rc == 0 and k_ref >= 0
+        assert k == k_ref, (k, k_ref)
+        assert np.array_equal(np.isnan(kap), np.isnan(kap_ref))
+        ok = ~np.isnan(kap_ref)
+        assert np.max(np.abs(kap[ok] - kap_ref[ok])) <= 1e-11 * np.max(kap_ref[ok])

@@ -6,7 +6,7 @@
   results in its output.
 * A captured plan, replayed several times with new lens parameters written
   into its input buffer and eager solves and synchronisations in between,
-  gives on every replay what the eager solve gives.
+  gives on every replay exactly (bit for bit) what the eager solve gives.
 * Two host threads solving at once on two streams (the library's per-device
   side stream and tuning cache are shared) get what sequential solves get.
 """
@@ -110,14 +110,11 @@ def test_plan_replays_match_eager():
         _ = torch.ones(1000, device=DEV).sum().item()
         ref = _np(solver.solve_semilinear(lens_buf.clone(), ns_buf.clone(), w.lambdas, tol=w.tol, max_ns=96,
                                           out=eager_out))
-        for k in ("status", "k_star", "corner_status", "s_off"):
+        # the solve sums in a fixed order: replay and eager agree bit for bit
+        for k in ("status", "k_star", "corner_status", "s_off", "iters", "chi2", "reg"):
             assert np.array_equal(got[k], ref[k]), (rep, k)
-        assert np.allclose(got["chi2"], ref["chi2"], rtol=1e-6, atol=0), rep
-        assert np.allclose(got["reg"], ref["reg"], rtol=1e-5, atol=0), rep
-        assert np.abs(got["iters"] - ref["iters"]).max() <= 2, rep
         n = int(ref["s_off"][-1])
-        err = np.linalg.norm(got["s_corner"][:n] - ref["s_corner"][:n]) / np.linalg.norm(ref["s_corner"][:n])
-        assert err <= 1e-5, (rep, err)
+        assert np.array_equal(got["s_corner"][:n], ref["s_corner"][:n]), rep
     plan.close()
 
 

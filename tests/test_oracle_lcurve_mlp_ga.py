@@ -51,16 +51,72 @@ def test_l_shaped_corner_on_arc():
     assert 10 <= k < 15
 
 
-def test_corner_tie_and_degenerate():
-    kappa = np.array([1.0, 3.0, 3.0, 2.0])
-    # tie goes to the smallest index: emulate via the argmax rule directly
-    best = 0
-    for j in range(1, 4):
-        if kappa[j] > kappa[best] * (1 + 1e-12):
-            best = j
-    assert best == 1
+def _with_kappa(monkeypatch, kappa):
+    """corner() with the spline stage replaced by fixed knot curvatures (all points kept)."""
+    kappa = np.asarray(kappa, dtype=np.float64)
+    monkeypatch.setattr(lcurve, "curvature_at_knots", lambda X, Y: (kappa.copy(), np.arange(kappa.size)))
+    n = kappa.size
+    return lcurve.corner(np.logspace(0, 1, n), np.logspace(1, 0, n))[0]
+
+
+def test_corner_tie_goes_to_smallest_index(monkeypatch):
+    # equal maxima, and maxima within the relative 1e-12 tie band: the first wins
+    assert _with_kappa(monkeypatch, [1.0, 3.0, 2.0, 3.0, 1.0]) == 1
+    assert _with_kappa(monkeypatch, [1.0, 3.0, 2.0, 3.0 * (1 + 5e-13), 1.0]) == 1
+    assert _with_kappa(monkeypatch, [1.0, 3.0 * (1 + 5e-13), 2.0, 3.0, 1.0]) == 1
+    # outside the band the larger one wins, wherever it is
+    assert _with_kappa(monkeypatch, [1.0, 3.0, 2.0, 3.0 * (1 + 1e-9), 1.0]) == 3
+    assert _with_kappa(monkeypatch, [3.0 * (1 + 1e-9), 3.0, 2.0, 3.0, 1.0]) == 0
+    assert _with_kappa(monkeypatch, [1.0, 2.0, 2.5, 2.0, 4.0]) == 4     # endpoints count
+
+
+def test_corner_tie_on_a_mirror_symmetric_curve():
+    # a curve with two identical bends: mirror image of itself under (X, Y) -> (Y, X) with
+    # the order reversed, so kappa_k = kappa_{n-1-k} up to rounding; the corner is the first bend
+    first = np.array([(0, 4), (0.02, 3.2), (0.05, 2.5), (0.1, 2.1), (0.25, 1.95), (0.6, 1.88), (1.0, 1.8),
+                      (1.35, 1.65)], dtype=float)
+    P = np.vstack([first, [[1.5, 1.5]], first[::-1][:, ::-1]])
+    X, Y = P[:, 0], P[:, 1]
+    kappa, keep = lcurve.curvature_at_knots(X, Y)
+    assert keep.size == X.size
+    np.testing.assert_allclose(kappa, kappa[::-1], rtol=1e-12)
+    k, kap = lcurve.corner(10 ** X, 10 ** Y)
+    i, j = np.argsort(-kappa)[:2]
+    assert abs(kappa[i] - kappa[j]) <= 1e-12 * kappa[i]
+    assert k == min(i, j) < X.size // 2
+
+
+def test_corner_drops_repeated_points():
+    # an L-curve with one point repeated exactly, and one repeated to within 1e-13 of the
+    # total chord length: both repeats are dropped (NaN curvature) and the corner is that of
+    # the curve without them; a point 1e-6 of the length away is kept
+    lam = np.logspace(-3, 2, 12)
+    reg = 1.0 / (1.0 + lam) ** 2 + 1e-3
+    chi2 = 1.0 + lam / (1.0 + lam)
+    k0, kap0 = lcurve.corner(reg, chi2)
+    X, Y = np.log10(reg), np.log10(chi2)
+    total = np.hypot(np.diff(X), np.diff(Y)).sum()
+    reg2 = np.insert(reg, 6, reg[5])
+    chi22 = np.insert(chi2, 6, chi2[5])
+    k, kap = lcurve.corner(reg2, chi22)
+    assert np.isnan(kap[6]) and np.isfinite(kap[5]) and np.sum(np.isnan(kap)) == 1
+    assert k == (k0 if k0 <= 5 else k0 + 1)
+    np.testing.assert_allclose(np.delete(kap, 6), kap0, rtol=1e-12)
+    eps = 1e-13 * total / np.log10(np.e)
+    reg3 = np.insert(reg, 3, reg[2] * (1 + eps))
+    chi23 = np.insert(chi2, 3, chi2[2])
+    _, kap3 = lcurve.corner(reg3, chi23)
+    assert np.isnan(kap3[3]) and np.sum(np.isnan(kap3)) == 1
+    reg4 = np.insert(reg, 3, reg[2] * (1 + 1e-6 * total / np.log10(np.e)))
+    _, kap4 = lcurve.corner(reg4, np.insert(chi2, 3, chi2[2]))
+    assert not np.isnan(kap4).any()
+
+
+def test_corner_degenerate():
     assert lcurve.corner([1.0, 2.0, 3.0], [3.0, 2.0, 1.0])[0] == -1
     assert lcurve.corner([1.0, 0.0, 3.0, 4.0], [3.0, 2.0, 1.0, 0.5])[0] == -1
+    # fewer than 4 distinct points after dropping repeats
+    assert lcurve.corner([1.0, 1.0, 2.0, 3.0], [3.0, 3.0, 2.0, 1.0])[0] == -1
 
 
 # --------------------------------------------------------------------------- MLP
