@@ -80,7 +80,8 @@ def parse():
     ap.add_argument("--plain-members", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the one-member-per-call comparison")
-    ap.add_argument("--cpu-members", type=int, default=0, help="oracle sample size (default: cores used)")
+    ap.add_argument("--cpu-members", type=int, default=0, help="oracle sample size (default: one per host core, "
+                                                                "at most 16)")
     ap.add_argument("--no-autotune", action="store_true", help="default kernel variant instead of the autotuned one")
     ap.add_argument("--search", action="store_true",
                     help="instead of the throughput line: plain vs surrogate-screened GA on the c5 settings")
@@ -88,7 +89,7 @@ def parse():
     ap.add_argument("--gens", type=int, default=30)
     ap.add_argument("--pop", type=int, default=819)
     ap.add_argument("--fanout", type=int, default=10)
-    ap.add_argument("--pretrain", type=int, default=20000, help="surrogate pre-training solves (c5 training set)")
+    ap.add_argument("--pretrain", type=int, default=100000, help="surrogate pre-training solves (the c5 training set)")
     ap.add_argument("--select", default="per_parent", choices=["per_parent", "global"])
     ap.add_argument("--clip-quantile", type=float, default=0.1, help="surrogate targets clipped at this quantile")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -98,20 +99,29 @@ def parse():
 
 
 def algorithmic_work(info, iters, nsub, ck):
-    """Flops and table bytes of the CG phase (the persistent kernels) for one step.
+    """Bytes and flops of the CG phase (the persistent kernels) for one step.
 
-    Per CG iteration of a member with mapped-pixel bounding box h x w, M mapped
-    pixels (M n^2 table entries) and I nodes (preconditioned iterations read
-    the same tables; the sine transforms of their preconditioner run in LDS on
-    MFMA and their 8 n^3 flops are not counted here):
-      flops = 2 passes * (4ck+1) FMAs * h*w * 2      (B^T B, banded, in LDS)
-            + 2 * 12 * M n^2                          (L and L^T bilinear)
-            + 23 * I                                  (H^T H stencil and CG updates)
-      bytes = 2 * M (4 + 12 n^2)                      (trace table read by L and L^T)
+    The unit of work is one member's CG iteration.  Its algorithmic bytes are
+    the per-iteration traffic of the matrix-free CG of Sec. 2.2 with the image
+    restricted to the M pixels that map onto the source grid (the only pixels
+    that enter L, Sec. 2.2), for a member of I nodes and n x n subpixels:
+        bytes_it = 16 M n^2      the (u, v) positions of the M n^2 subpixels, FP32, read by L and by L^T
+                 + 8 M           one image-space vector written by B and read by B^T
+                 + 56 I          CG vectors (s, r, p, q and the H^T H and update passes), FP32
+    Also returned: the bytes of this implementation's own table encoding
+    (cell index and two FP32 fractions per subpixel plus the packed pixel
+    index, read once by L and once by L^T: 2 M (4 + 12 n^2)), and the flops
+        flops_it = 2 passes * (4ck+1) FMAs * h*w * 2      (B^T B, banded, in LDS)
+                 + 2 * 12 * M n^2                          (L and L^T bilinear)
+                 + 23 * I                                  (H^T H stencil and CG updates)
+    for a mapped bounding box of h x w pixels.  Preconditioned iterations read
+    the same tables and count the same; the sine transforms of their
+    preconditioner run in LDS on MFMA and their 8 n^3 flops are not counted.
     """
     n2 = nsub * nsub
     flops = 0.0
     nbytes = 0.0
+    tbytes = 0.0
     for m in range(info.shape[0]):
         ns, I, M, r0, r1, c0, c1, st = info[m][:8]
         if st != 0:
@@ -119,20 +129,66 @@ def algorithmic_work(info, iters, nsub, ck):
         h, w = r1 - r0 + 1, c1 - c0 + 1
         it = float(iters[m].sum())
         flops += it * (2 * (4 * ck + 1) * h * w * 2 + 2 * 12 * M * n2 + 23 * I)
-        nbytes += it * (2 * M * (4 + 12 * n2))
-    return flops, nbytes
+        nbytes += it * (16.0 * M * n2 + 8.0 * M + 56.0 * I)
+        tbytes += it * (2 * M * (4 + 12 * n2))
+    return nbytes, tbytes, flops
 
 
-def cpu_baseline(w, z, pop, grids, n_members):
-    from oracle import coracle
-    cores = n_members
+def host_cores():
+    """Cores this process may use (its affinity set, capped at the box's 16-core share) and lscpu's count."""
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    lscpu = None
+    try:
+        import subprocess
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in txt.splitlines():
+            if line.startswith("CPU(s):"):
+                lscpu = int(line.split(":")[1])
+    except Exception:   # lscpu missing: report the affinity count only
+        pass
+    return min(avail, 16), lscpu
+
+
+def cpu_baseline(w, z, pop, grids, n_members, gpu):
+    """The plain-C FP64 oracle on the host cores, on a bounded sample of the c3 step.
+
+    All cores: the first n_members members (one per OpenMP thread), full
+    16-lambda sweep each, CG to 1e-10 (the oracle's own tolerance).  Single
+    core: member 0 at CG tol 1e-6 (about the work of the FP32 GPU path).  The
+    all-core results also serve as a parity check of the timed GPU run on the
+    same members: chi^2 at every lambda, ||H s||^2 from two indices below the
+    corner, and the corner solution.
+    """
+    from oracle import coracle, lcurve
+    cores, lscpu = host_cores()
+    n = min(n_members, cores) if n_members else cores
     t0 = time.perf_counter()
-    coracle.evaluate(pop[:n_members], grids[:n_members], w.half_width, w.nx, w.ny, w.pix, w.nsub_model, z["d"],
-                     float(z["sigma"]), z["psf"], w.reg, w.lambdas, tol=1e-7, threads=cores)
+    ref = coracle.evaluate(pop[:n], grids[:n], w.half_width, w.nx, w.ny, w.pix, w.nsub_model, z["d"],
+                           float(z["sigma"]), z["psf"], w.reg, w.lambdas, tol=1e-10, want_s=True, threads=n)
     dt = time.perf_counter() - t0
-    return {"value": n_members / dt, "unit": "evals/s", "cores": cores, "kind": "oracle",
-            "sample": f"first {n_members} of the 256 c3 members, full 16-lambda sweep each, plain-C FP64 "
-                      f"matrix-free CG to 1e-7, one member per OpenMP thread ({dt:.1f} s wall)"}
+    t1 = time.perf_counter()
+    coracle.evaluate(pop[:1], grids[:1], w.half_width, w.nx, w.ny, w.pix, w.nsub_model, z["d"], float(z["sigma"]),
+                     z["psf"], w.reg, w.lambdas, tol=1e-6, threads=1)
+    dt1 = time.perf_counter() - t1
+    chi2, reg, ks, s, off = gpu
+    rel = np.abs(chi2[:n] - ref["chi2"]) / ref["chi2"]
+    reg_err, s_err, agree = 0.0, 0.0, 0
+    for m in range(n):
+        k = int(ks[m])
+        agree += int(k == lcurve.corner(ref["reg"][m], ref["chi2"][m])[0])
+        lo = max(0, k - 2)
+        reg_err = max(reg_err, float(np.max(np.abs(reg[m, lo:] - ref["reg"][m, lo:]) / ref["reg"][m, lo:])))
+        sr = ref["s"][m, k, :grids[m] ** 2]
+        s_err = max(s_err, float(np.linalg.norm(s[off[m]:off[m + 1]] - sr) / np.linalg.norm(sr)))
+    return {"value": n / dt, "unit": "evals/s", "cores": n, "kind": "oracle",
+            "sample": f"first {n} of the 256 c3 members, full 16-lambda sweep each, plain-C FP64 matrix-free CG to "
+                      f"1e-10, one member per OpenMP thread ({dt:.1f} s wall)",
+            "host_cpus_lscpu": lscpu, "host_cpus_available": cores,
+            "single_core_tol1e-6": {"value": 1.0 / dt1, "unit": "evals/s", "cores": 1,
+                                    "sample": f"member 0, full 16-lambda sweep, CG to 1e-6 ({dt1:.1f} s)"},
+            "gpu_fp32_vs_oracle_on_sample": {"members": n, "chi2_rel_max": float(rel.max()),
+                                             "reg_rel_max_from_kstar_minus_2": reg_err,
+                                             "s_corner_rel_l2_max": s_err, "corner_index_agree": agree}}
 
 
 def main():
@@ -176,8 +232,14 @@ def main():
     ns_d = torch.tensor(grids, device=dev)
     out = solver.alloc_result(M * max_ns * max_ns, M, len(w.lambdas))
 
+    chi2_h = torch.empty((M, len(w.lambdas)), dtype=torch.float64, pin_memory=True)
+    k_h = torch.empty(M, dtype=torch.int32, pin_memory=True)
+
     def step():
+        # one evaluation of every member: the solve, and its fitness (chi^2, k*) back on the host
         solver.solve_semilinear(lens_d, ns_d, w.lambdas, tol=w.tol, maxit=4000, max_ns=max_ns, out=out)
+        chi2_h.copy_(out["chi2"], non_blocking=True)
+        k_h.copy_(out["k_star"], non_blocking=True)
 
     if args.copy_calibration:
         n = args.copy_calibration * (1 << 20) // 4
@@ -210,17 +272,21 @@ def main():
     iters = out["iters"].cpu().numpy()
     status = out["status"].cpu().numpy()
     info = solver.member_info(max_ns, M, len(w.lambdas))
-    flops, tbytes = algorithmic_work(info, iters, w.nsub_model, (w.k_psf - 1) // 2)
+    abytes, tbytes, flops = algorithmic_work(info, iters, w.nsub_model, (w.k_psf - 1) // 2)
     kern_s = kern_ms / max(launches, 1) / 1e3
     tflops = flops / kern_s / 1e12
-    gbs = tbytes / kern_s / 1e9
+    gbs = abytes / kern_s / 1e9
     traffic = measured_traffic() if args.workload == "c3" else None
     roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": traffic,
-            "kernel": "CG phase: k_split, then the plain and the preconditioned persistent k_solve side by side", "kernel_ms": round(kern_s * 1e3, 3),
-            "algorithmic_bytes": tbytes, "fp32_TFLOPs": round(tflops, 3),
-            "fp32_frac": round(tflops / PEAK_FP32_TFLOPS, 4),
-            "measured_hbm_GBps": round(traffic / kern_s / 1e9, 1) if traffic else None}
+            "kernel": "CG phase: k_split, then the plain and the preconditioned persistent k_solve side by side",
+            "kernel_ms": round(kern_s * 1e3, 3), "launches_timed": launches,
+            "algorithmic_bytes": abytes,
+            "byte_model": "per member CG iteration 16 M n^2 + 8 M + 56 I (M mapped pixels, n^2 subpixels, I nodes)",
+            "table_encoding_bytes": tbytes, "table_encoding_GBps": round(tbytes / kern_s / 1e9, 1),
+            "measured_hbm_GBps": round(traffic / kern_s / 1e9, 1) if traffic else None,
+            "measured_hbm_frac": round(traffic / kern_s / 1e9 / PEAK_HBM_GBS, 4) if traffic else None,
+            "fp32_TFLOPs": round(tflops, 3), "fp32_frac": round(tflops / PEAK_FP32_TFLOPS, 4)}
     # the same step replayed from a captured HIP graph
     plan = solver.plan(lens_d, ns_d, w.lambdas, tol=w.tol, maxit=4000, max_ns=max_ns, out=out)
     plan.launch()
@@ -232,6 +298,7 @@ def main():
     graph_ms = 1e3 * (time.perf_counter() - t0) / args.steps
     plan.close()
     prec = precision_vs_f64(sl, torch, z, grid, w, dev, pop, grids, out, max_ns)
+    mc = mc_dof_step(sl, torch, solver, lens_d, ns_d, w, max_ns, M, args.steps)
     # plain: the same library, one member per call
     plain_value = None
     if not args.no_plain:
@@ -248,14 +315,43 @@ def main():
         "vs_plain": round(value / plain_value, 2) if plain_value else None,
         "graph_ms_per_step": round(graph_ms, 3),
         "chi2_rel_err_vs_f64": prec,
+        "mc_dof": mc,
         "roofline": roof,
     }
     if not args.no_cpu_baseline and args.workload == "c3":
-        ncpu = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
-        n = args.cpu_members or max(1, min(16, ncpu))
-        print(f"[bench] cpu baseline: oracle on {n} members", file=sys.stderr, flush=True)
-        rec["cpu_baseline"] = cpu_baseline(w, z, pop, grids, n)
+        print(f"[bench] cpu baseline: oracle on the host cores", file=sys.stderr, flush=True)
+        gpu = (out["chi2"].cpu().numpy(), out["reg"].cpu().numpy(), out["k_star"].cpu().numpy(),
+               out["s_corner"].cpu().numpy(), out["s_off"].cpu().numpy())
+        rec["cpu_baseline"] = cpu_baseline(w, z, pop, grids, args.cpu_members, gpu)
     print(json.dumps(rec), flush=True)
+
+
+def mc_dof_step(sl, torch, solver, lens_d, ns_d, w, max_ns, M, steps):
+    """The same step with the Monte Carlo degrees of freedom at every corner (Sec. 2.5).
+
+    Returns its time per step and the reduced chi^2 = chi^2(k*) / dof over the
+    members (one seeded Gaussian draw bhat for the whole batch).
+    """
+    import synthgen
+    print("[bench] Monte Carlo degrees of freedom", file=sys.stderr, flush=True)
+    noise = torch.tensor(synthgen.mc_draws(w.seed, w.ny, w.nx).reshape(-1), device=lens_d.device)
+    out = solver.alloc_result(M * max_ns * max_ns, M, len(w.lambdas))
+    solver.solve_semilinear(lens_d, ns_d, w.lambdas, tol=w.tol, maxit=4000, max_ns=max_ns, out=out, mc_noise=noise)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        solver.solve_semilinear(lens_d, ns_d, w.lambdas, tol=w.tol, maxit=4000, max_ns=max_ns, out=out,
+                                mc_noise=noise)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / steps
+    dof = out["dof"].cpu().numpy()
+    k = out["k_star"].cpu().numpy()
+    chi2 = out["chi2"].cpu().numpy()[np.arange(M), k]
+    ok = np.isfinite(dof) & (dof > 0)
+    chi2r = chi2[ok] / dof[ok]
+    return {"ms_per_step": round(ms, 3), "evals_per_s": round(M / ms * 1e3, 2), "members": int(ok.sum()),
+            "dof_median": float(np.median(dof[ok])), "chi2_r_min": float(chi2r.min()),
+            "chi2_r_median": float(np.median(chi2r))}
 
 
 def precision_vs_f64(sl, torch, z, grid, w, dev, pop, grids, out, max_ns, n=16):

@@ -174,6 +174,10 @@ typedef struct {
   const sl_tuning* tuning; /* nullable: NULL takes the autotuner's choice for this problem
                               signature when sl_solve_autotune has made one in this
                               process, else the default variant */
+  const double* mc_noise;  /* nullable; device double[ny*nx]: the zero-mean, unit-variance
+                              Gaussian draws bhat of the Monte Carlo estimate of the effective
+                              degrees of freedom (Sec. 2.5).  When given, the solve also writes
+                              sl_result.dof (see sl_solve_semilinear). */
 } sl_solve_opts;
 
 typedef struct {
@@ -187,6 +191,9 @@ typedef struct {
   int32_t* corner_status; /* device int32[n_members]: SL_ST_OK, _EMPTY, _INVALID or _LCURVE; or
                               SL_ST_MAXIT / SL_ST_BREAKDOWN when some lambda of the member's curve
                               did not converge (k_star is still its curve's corner) */
+  double* dof;         /* device double[n_members], written when opts->mc_noise is given (else
+                          unused, may be NULL): the Monte Carlo degrees of freedom nu at the
+                          corner lambda (Sec. 2.5); NaN for a member without a solve */
 } sl_result;
 
 /*
@@ -217,6 +224,20 @@ size_t sl_solve_workspace_size(const sl_problem* pb, int max_ns, int n_members, 
  *              256-byte aligned; contents need not be initialised
  * Results go to `out`.  With n_lambda < 4 the corner is index 0
  * (corner_status SL_ST_LCURVE when n_lambda is 2 or 3).
+ *
+ * Monte Carlo degrees of freedom (Sec. 2.5; opts->mc_noise = bhat): after
+ * the corners are known, a second system (A^T A + lambda H^T H) x = A^T bhat
+ * (A = B L) is solved at every member's corner lambda, and
+ * dof[m] = bhat^T (bhat - A xhat), computed as bhat^T bhat - <A^T bhat, xhat>
+ * in FP64.  SL_F64: as the paper does, the corner lambda's data system is
+ * solved again by plain CG from s = 0 and the second system is advanced in
+ * lockstep with the data system's coefficients alpha_k, beta_k (about two
+ * solves per member).  SL_F32: that fixed-coefficient recurrence amplifies
+ * FP32 rounding without bound on long solves, so the second system is solved
+ * by its own CG to the same relative tolerance (one solve per member); both
+ * converge to the same xhat.  The expectation of dof over bhat is J - gamma,
+ * gamma the trace of the influence matrix (Eq. 19 for H = I), so
+ * chi2[m][k_star] / dof[m] is the reduced chi^2.
  */
 int sl_solve_semilinear(const sl_problem* pb, const double* lens, const int32_t* ns, int max_ns,
                         int n_members, const double* lambdas, int n_lambda,

@@ -44,7 +44,8 @@ class Tuning(ctypes.Structure):
 
 
 class SolveOpts(ctypes.Structure):
-    _fields_ = [("tol", ctypes.c_double), ("maxit", ctypes.c_int), ("tuning", ctypes.POINTER(Tuning))]
+    _fields_ = [("tol", ctypes.c_double), ("maxit", ctypes.c_int), ("tuning", ctypes.POINTER(Tuning)),
+                ("mc_noise", ctypes.c_void_p)]
 
 
 N_VARIANTS = 8
@@ -53,7 +54,7 @@ N_VARIANTS = 8
 class Result(ctypes.Structure):
     _fields_ = [("s_corner", ctypes.c_void_p), ("s_off", ctypes.c_void_p), ("chi2", ctypes.c_void_p),
                 ("reg", ctypes.c_void_p), ("iters", ctypes.c_void_p), ("status", ctypes.c_void_p),
-                ("k_star", ctypes.c_void_p), ("corner_status", ctypes.c_void_p)]
+                ("k_star", ctypes.c_void_p), ("corner_status", ctypes.c_void_p), ("dof", ctypes.c_void_p)]
 
 
 _lib = None

@@ -76,13 +76,15 @@ struct alignas(16) Consts {
   int pqhead[8];    // queues of the preconditioned items (filled by k_split)
   int pqcount[8];
   int sep;          // PSF is rank-1
-  int pad0[3];
+  int mchead;       // next member of the Monte Carlo degrees-of-freedom pass
+  int pad0[2];
   double sum_d2;
-  double pad1;
+  double sum_n2;    // sum of the squared Monte Carlo draws
 };
 
 struct Layout {
-  size_t consts, lam, taps_d, taps_f, minfo, queues, pqueues, pix, cell, fx, fy, b, s_all, gframe, gz, rbuf, lt_ptr, lt_perm,
+  size_t consts, lam, taps_d, taps_f, minfo, queues, pqueues, pix, cell, fx, fy, b, bh, s_all, gframe, gz, rbuf, mcbuf,
+      lt_ptr, lt_perm,
       lt_ent,
       total;
   long long lt_cap;
@@ -162,6 +164,11 @@ struct SolveArgs {
   int force_csr;    // variant: transposed operator as CSR rows
   int force_direct; // variant: direct K x K blur for a separable PSF
   int plain_cg;     // variant: no spectral preconditioner
+  // Monte Carlo degrees of freedom (Sec. 2.5), when mcn is not NULL
+  const double* mcn; // [ny*nx] Gaussian draws bhat
+  double* dofv;      // [n_members] result: bhat^T (bhat - A xhat) at the corner
+  double* bh;        // [member][I_max] A^T bhat (FP64)
+  void* mcbuf;       // [n_wg][5][I_max] r, xhat, rhat, phat, saved p of the pass
 };
 
 // ------------------------------------------------------------------ block scan
@@ -319,12 +326,20 @@ __global__ void __launch_bounds__(1024) k_setup(SolveArgs a, LamList lams) {
     T* tt = reinterpret_cast<T*>(a.taps_t);
     for (int i = 0; i < ti.total; ++i) tt[i] = (T)tp[i];
   }
-  // sum of d^2 in FP64
-  double acc = 0.0;
+  // sums of d^2 and of the Monte Carlo draws squared, in FP64
+  double acc = 0.0, accn = 0.0;
   const int J = a.nx * a.ny;
-  for (int j = tid; j < J; j += blockDim.x) acc += a.d[j] * a.d[j];
+  for (int j = tid; j < J; j += blockDim.x) {
+    acc += a.d[j] * a.d[j];
+    if (a.mcn) accn += a.mcn[j] * a.mcn[j];
+  }
   acc = block_sum(acc, red);
-  if (tid == 0) a.consts->sum_d2 = acc;
+  accn = block_sum(accn, red);
+  if (tid == 0) {
+    a.consts->sum_d2 = acc;
+    a.consts->sum_n2 = accn;
+    a.consts->mchead = 0;
+  }
 }
 
 // ------------------------------------------------------------------ k_prep
@@ -729,19 +744,12 @@ __device__ __forceinline__ void wave_ordered_add(double* bacc, int key, double v
   }
 }
 
-// Right-hand side b = L^T B^T d in FP64 (Eq. 7) into bacc[I] (zeroed), by
-// one wave: it walks the mapped slots 64 at a time; each lane correlates
-// the data with the PSF at its pixel (B^T d) and spreads the value over the
-// pixel's (node, weight) pairs, pair by pair, through wave_ordered_add.  The
-// order of every node's terms is therefore (slot group, pair, lane), the
-// same on every run.  `slots` is a multiple of 64.
-template <typename T>
-__device__ void rhs_fixed_order(const SolveArgs& a, int ns, int slots, const int32_t* pix, const int32_t* cellp,
-                                const T* fxp, const T* fyp, double* bacc) {
-  const int lane = threadIdx.x & 63;
-  const int nx = a.nx, ny = a.ny, K = a.K, ck = a.ck, n2 = a.n2;
-  for (int t0 = 0; t0 < slots; t0 += 64) {
-    const int t = t0 + lane;
+// (B^T img)[pixel of slot t] for every slot (0 for empty slots), FP64, by all
+// threads of the block, into vbuf[slots] (global memory of this member).
+__device__ void correlate_slots(const SolveArgs& a, const double* img, int slots, const int32_t* pix,
+                                double* vbuf) {
+  const int nx = a.nx, ny = a.ny, K = a.K, ck = a.ck;
+  for (int t = threadIdx.x; t < slots; t += blockDim.x) {
     const int rc = pix[t];
     double v = 0.0;
     if (rc >= 0) {
@@ -752,10 +760,29 @@ __device__ void rhs_fixed_order(const SolveArgs& a, int ns, int slots, const int
         for (int bb = 0; bb < K; ++bb) {
           const int cc = c + bb - ck;
           if (cc < 0 || cc >= nx) continue;
-          v += a.psf[aa * K + bb] * a.d[rr * nx + cc];
+          v += a.psf[aa * K + bb] * img[rr * nx + cc];
         }
       }
     }
+    vbuf[t] = v;
+  }
+}
+
+// Right-hand side b = L^T B^T img in FP64 (Eq. 7: img = d) into bacc[I] (zeroed), by
+// one wave, from v = B^T img at the mapped pixels (vbuf, correlate_slots): it
+// walks the slots 64 at a time and spreads each lane's value over its
+// pixel's (node, weight) pairs, pair by pair, through wave_ordered_add.  The
+// order of every node's terms is therefore (slot group, pair, lane), the
+// same on every run.  `slots` is a multiple of 64.
+template <typename T>
+__device__ void rhs_fixed_order(const SolveArgs& a, const double* vbuf, int ns, int slots, const int32_t* pix,
+                                const int32_t* cellp, const T* fxp, const T* fyp, double* bacc) {
+  const int lane = threadIdx.x & 63;
+  const int n2 = a.n2;
+  for (int t0 = 0; t0 < slots; t0 += 64) {
+    const int t = t0 + lane;
+    const int rc = pix[t];
+    const double v = vbuf[t];
     if (n2 == 4) {
       int nd[16];
       double ww[16];
@@ -872,11 +899,16 @@ __device__ void prep_member(const SolveArgs& a, int m, MemberInfo mi, const doub
   }
   __syncthreads();
   const int Mm = slots;
-  // right-hand side b = L^T B^T d (FP64), summed in a fixed order by wave 0
+  // right-hand side b = L^T B^T d (FP64): B^T d at the mapped pixels by every
+  // thread, then the scatter over the nodes in a fixed order by wave 0.  The
+  // per-slot values go to this member's L^T entry region, which
+  // build_transpose fills only later (it holds >= 8 slot_cap bytes).
   const int I = ns * ns;
+  double* vbuf = reinterpret_cast<double*>(reinterpret_cast<LtEntry<T>*>(a.lt_ent) + (long)m * a.lt_cap);
   for (int i = tid; i < I; i += blockDim.x) bacc[i] = 0.0;
+  correlate_slots(a, a.d, Mm, pix, vbuf);
   __syncthreads();
-  if (tid < 64) rhs_fixed_order<T>(a, ns, Mm, pix, cellp, fxp, fyp, bacc);
+  if (tid < 64) rhs_fixed_order<T>(a, vbuf, ns, Mm, pix, cellp, fxp, fyp, bacc);
   __syncthreads();
   const double inv_n2 = 1.0 / n2;
   // scale of the spectral preconditioner: c = sum_i cov_i b_i^2 / sum_i b_i^2
@@ -903,6 +935,16 @@ __device__ void prep_member(const SolveArgs& a, int m, MemberInfo mi, const doub
   double* bm = a.b + (long)m * a.I_max;
   for (int i = tid; i < I; i += blockDim.x) bm[i] = bacc[i];
   __syncthreads();
+  if (a.mcn) {   // A^T bhat of the Monte Carlo degrees of freedom, in the same fixed order
+    for (int i = tid; i < I; i += blockDim.x) bacc[i] = 0.0;
+    correlate_slots(a, a.mcn, Mm, pix, vbuf);
+    __syncthreads();
+    if (tid < 64) rhs_fixed_order<T>(a, vbuf, ns, Mm, pix, cellp, fxp, fyp, bacc);
+    __syncthreads();
+    double* bhm = a.bh + (long)m * a.I_max;
+    for (int i = tid; i < I; i += blockDim.x) bhm[i] = bacc[i];
+    __syncthreads();
+  }
   int sell = 0;
   if (Mtrue > 0)
     sell = build_transpose<T>(a, m, ns, Mm, bbox, scan, reinterpret_cast<int*>(bacc), pix, cellp, fxp, fyp);
@@ -1265,6 +1307,199 @@ __device__ void trivial_item(const SolveArgs& a, const MemberInfo& mi, int m, in
 // LDS: P = search direction p, Q = A p accumulator, the image frame (LDSF)
 // and reduction scratch.  The iterate s (in its output slot) and the
 // residual r live in global memory, read and written by their owner thread.
+// The operands of one item's regularised normal operator (see apply_normal).
+template <typename T>
+struct OpView {
+  const int32_t* pix;        // mapped-pixel slots: packed (row << 16 | col), -1 past the end
+  const int32_t* cellp;      // [slot][n^2] bilinear cell of each subpixel, -1 off the grid
+  const T* fxp;
+  const T* fyp;
+  T* F;                      // image frame with its zero halo (LDS or global)
+  T* F0;                     // frame interior (0, 0) = image pixel (r0, c0)
+  T* Z;                      // per-block image buffer of the direct blur
+  const T* taps;
+  const int32_t* lt_rp;      // transposed operator: slice (or row) starts
+  const LtEntry<T>* lt_e;    //                      entries
+  const int32_t* perm;       //                      nodes in slice order
+  int ns, I, M, r0, c0, h, w, pitch, fo, n2, nx, ny, K, ck, sell, Dr0, Dc0, Dh, Dw;
+  bool sep, ident;
+  T inv_n2, lamT;
+};
+
+// Q = (L^T B^T B L + lambda H^T H) P for one item, all threads of the block:
+// L as a gather into the frame (zero on entry), B^T B in place (banded passes
+// for a rank-1 PSF, else the direct K x K form through Z), then L^T as a
+// gather over the transposed operator (fixed order, no atomics) fused with
+// lambda H^T H.  On return the frame holds B^T B L P; the caller zeroes it
+// again after a barrier.  Returns this thread's part of <P, Q>.
+template <typename T, int CKT, int NT>
+__device__ __forceinline__ double apply_normal(const OpView<T>& o, const T* __restrict__ P, T* __restrict__ Q) {
+  const int tid = threadIdx.x;
+  const int32_t* pix = o.pix;
+  const int32_t* cellp = o.cellp;
+  const T* fxp = o.fxp;
+  const T* fyp = o.fyp;
+  T* const F = o.F;
+  T* const F0 = o.F0;
+  T* const Z = o.Z;
+  const T* taps = o.taps;
+  const int32_t* lt_rp = o.lt_rp;
+  const LtEntry<T>* lt_e = o.lt_e;
+  const int32_t* perm = o.perm;
+  const int ns = o.ns, I = o.I, M = o.M, r0 = o.r0, c0 = o.c0, h = o.h, w = o.w, pitch = o.pitch, fo = o.fo;
+  const int n2 = o.n2, nx = o.nx, ny = o.ny, K = o.K, ck = o.ck, sell = o.sell;
+  const int Dr0 = o.Dr0, Dc0 = o.Dc0, Dh = o.Dh, Dw = o.Dw;
+  const bool sep = o.sep, ident = o.ident;
+  const T inv_n2 = o.inv_n2, lamT = o.lamT;
+  const TapIdx ti(K);
+  (void)ny;
+  // y = L p into the frame (P holds p, the frame is zero); two pixels per
+  // thread and step so that their table loads are in flight together
+  for (int t = tid; t < M; t += 2 * NT) {
+    const int t2 = t + NT;
+    const int rc = pix[t];
+    const int rc2 = t2 < M ? pix[t2] : -1;
+    const T v1 = pixel_gather(P, ns, n2, t, cellp, fxp, fyp);
+    const T v2 = t2 < M ? pixel_gather(P, ns, n2, t2, cellp, fxp, fyp) : (T)0;
+    if (rc >= 0) F0[(rc >> 16) * pitch + (rc & 0xFFFF) + fo] = v1 * inv_n2;
+    if (rc2 >= 0) F0[(rc2 >> 16) * pitch + (rc2 & 0xFFFF) + fo] = v2 * inv_n2;
+  }
+  __syncthreads();
+  if (sep) {   // sep comes from a scalar load: uniform
+    // w = B^T B y: banded pass along rows then along columns, in place
+    banded_pass<T, CKT, true>(F0, pitch, h, w, c0, nx, ck, taps + ti.ax, taps + ti.elx, taps + ti.erx);
+    __syncthreads();
+    banded_pass<T, CKT, false>(F0, pitch, w, h, r0, ny, ck, taps + ti.ay, taps + ti.ely, taps + ti.ery);
+    __syncthreads();
+  } else {
+    // z = B y over the dilated region into global Z
+    for (int e = tid; e < Dh * Dw; e += NT) {
+      const int rr_ = Dr0 + e / Dw, cc_ = Dc0 + e % Dw;
+      T acc = 0;
+      if (ck <= CKT) {
+        // every tap of an output in the dilated region lands in the bounding
+        // box or its zero halo (2 CKT >= 2 ck on each side): no bounds tests
+        const T* yrow = F0 + (rr_ + ck - r0) * pitch + (cc_ + ck - c0);
+        const T* tp = taps + ti.psf;
+        for (int aa = 0; aa < K; ++aa) {
+          const T* y = yrow - aa * pitch;
+          for (int bb = 0; bb < K; ++bb) acc += tp[aa * K + bb] * y[-bb];
+        }
+      } else {   // PSFs wider than the widest compiled window: the halo is narrower than ck
+        for (int aa = 0; aa < K; ++aa) {
+          const int yr = rr_ - aa + ck - r0;
+          if (yr < 0 || yr >= h) continue;
+          for (int bb = 0; bb < K; ++bb) {
+            const int yc = cc_ - bb + ck - c0;
+            if (yc < 0 || yc >= w) continue;
+            acc += taps[ti.psf + aa * K + bb] * F0[yr * pitch + yc];
+          }
+        }
+      }
+      Z[e] = acc;
+    }
+    __syncthreads();
+    // w = B^T z at the mapped pixels, back into the frame
+    for (int t = tid; t < M; t += NT) {
+      if (pix[t] < 0) continue;
+      const int rr_ = pix[t] >> 16, cc_ = pix[t] & 0xFFFF;
+      T acc = 0;
+      for (int aa = 0; aa < K; ++aa) {
+        const int zr = rr_ + aa - ck - Dr0;
+        if (zr < 0 || zr >= Dh) continue;
+        for (int bb = 0; bb < K; ++bb) {
+          const int zc = cc_ + bb - ck - Dc0;
+          if (zc < 0 || zc >= Dw) continue;
+          acc += taps[ti.psf + aa * K + bb] * Z[zr * Dw + zc];
+        }
+      }
+      F0[rr_ * pitch + cc_ + fo] = acc;
+    }
+    __syncthreads();
+  }
+  // q = L^T w + lambda H^T H p gathered per node from the transposed operator
+  // (no atomics, fixed order), stored in Q; <p, q>
+  double pq = 0.0;
+  {
+    if (sell) {
+      // sliced-ELL in length-sorted node order: wave w takes slices w, w + 16, ...;
+      // the slice bounds are wave-uniform (scalar loads) and every lane of a
+      // slice has `len` entries (padding reads the zero halo), eight in flight
+      const int wid = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+      const int nslices = (I + 63) >> 6;
+      const int lt_E = lt_rp[nslices];   // sliced-ELL entries of the member
+      for (int sl = wid; sl < nslices; sl += NT / 64) {
+        const int idx = sl * 64 + lane;
+        const int b0 = lt_rp[sl];
+        const int len = (lt_rp[sl + 1] - b0) >> 6;
+        const int pk = idx < I ? perm[idx] : 0;
+        T acc = 0;
+        if (sizeof(T) == 4 && sell == 2) {
+          // paired entries (even `len`, entries summed in the same order)
+          const unsigned* op = reinterpret_cast<const unsigned*>(lt_e) + (b0 >> 1) + lane;
+          const float2* wq = reinterpret_cast<const float2*>(reinterpret_cast<const unsigned*>(lt_e) + (lt_E >> 1)) +
+                             (b0 >> 1) + lane;
+          const int npair = len >> 1;
+          int j = 0;
+          for (; j + 7 < npair; j += 8) {   // sixteen entries in flight
+            unsigned o[8];
+            float2 wv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+              o[u] = op[64L * (j + u)];
+              wv[u] = wq[64L * (j + u)];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+              acc += (T)wv[u].x * F[o[u] & 0xFFFFu];
+              acc += (T)wv[u].y * F[o[u] >> 16];
+            }
+          }
+          for (; j < npair; ++j) {
+            const unsigned o0 = op[64L * j];
+            const float2 w0 = wq[64L * j];
+            acc += (T)w0.x * F[o0 & 0xFFFFu];
+            acc += (T)w0.y * F[o0 >> 16];
+          }
+        } else {
+          const LtEntry<T>* ep = lt_e + b0 + lane;
+          int j = 0;
+          for (; j + 7 < len; j += 8) {
+            LtEntry<T> x[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) x[u] = ep[64L * (j + u)];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc += x[u].w * F[x[u].off];
+          }
+          for (; j < len; ++j) {
+            const LtEntry<T> x0 = ep[64L * j];
+            acc += x0.w * F[x0.off];
+          }
+        }
+        if (idx < I) {
+          const int rn_ = pk >> 16, cn_ = pk & 0xFFFF, i = rn_ * ns + cn_;
+          const T pv = P[i];
+          const T qv = acc + lamT * (ident ? pv : hth_node(P, ns, rn_, cn_));
+          Q[i] = qv;
+          pq += (double)pv * (double)qv;
+        }
+      }
+    } else {
+      for (int i = tid; i < I; i += NT) {
+        T acc = 0;
+        const int e0 = lt_rp[i], e1 = lt_rp[i + 1];
+        for (int e = e0; e < e1; ++e) acc += lt_e[e].w * F[lt_e[e].off];
+        const int rn_ = i / ns, cn_ = i - rn_ * ns;
+        const T pv = P[i];
+        const T qv = acc + lamT * (ident ? pv : hth_node(P, ns, rn_, cn_));
+        Q[i] = qv;
+        pq += (double)pv * (double)qv;
+      }
+    }
+  }
+  return pq;
+}
+
 template <typename T, int CKT, bool LDSF, bool PC>
 __device__ __forceinline__ void run_item(const SolveArgs& a, const MemberInfo& mi, int m, int kl, unsigned char* smem) {
   constexpr int NT = kNTof<T>;   // threads of this block
@@ -1348,151 +1583,9 @@ __device__ __forceinline__ void run_item(const SolveArgs& a, const MemberInfo& m
       st = SL_ST_OK;
       break;
     }
-    // y = L p into the frame (P holds p, the frame is zero); two pixels per
-    // thread and step so that their table loads are in flight together
-    for (int t = tid; t < M; t += 2 * NT) {
-      const int t2 = t + NT;
-      const int rc = pix[t];
-      const int rc2 = t2 < M ? pix[t2] : -1;
-      const T v1 = pixel_gather(P, ns, n2, t, cellp, fxp, fyp);
-      const T v2 = t2 < M ? pixel_gather(P, ns, n2, t2, cellp, fxp, fyp) : (T)0;
-      if (rc >= 0) F0[(rc >> 16) * pitch + (rc & 0xFFFF) + fo] = v1 * inv_n2;
-      if (rc2 >= 0) F0[(rc2 >> 16) * pitch + (rc2 & 0xFFFF) + fo] = v2 * inv_n2;
-    }
-    __syncthreads();
-    if (sep) {   // sep comes from a scalar load: uniform
-      // w = B^T B y: banded pass along rows then along columns, in place
-      banded_pass<T, CKT, true>(F0, pitch, h, w, c0, nx, ck, taps + ti.ax, taps + ti.elx, taps + ti.erx);
-      __syncthreads();
-      banded_pass<T, CKT, false>(F0, pitch, w, h, r0, ny, ck, taps + ti.ay, taps + ti.ely, taps + ti.ery);
-      __syncthreads();
-    } else {
-      // z = B y over the dilated region into global Z
-      for (int e = tid; e < Dh * Dw; e += NT) {
-        const int rr_ = Dr0 + e / Dw, cc_ = Dc0 + e % Dw;
-        T acc = 0;
-        if (ck <= CKT) {
-          // every tap of an output in the dilated region lands in the bounding
-          // box or its zero halo (2 CKT >= 2 ck on each side): no bounds tests
-          const T* yrow = F0 + (rr_ + ck - r0) * pitch + (cc_ + ck - c0);
-          const T* tp = taps + ti.psf;
-          for (int aa = 0; aa < K; ++aa) {
-            const T* y = yrow - aa * pitch;
-            for (int bb = 0; bb < K; ++bb) acc += tp[aa * K + bb] * y[-bb];
-          }
-        } else {   // PSFs wider than the widest compiled window: the halo is narrower than ck
-          for (int aa = 0; aa < K; ++aa) {
-            const int yr = rr_ - aa + ck - r0;
-            if (yr < 0 || yr >= h) continue;
-            for (int bb = 0; bb < K; ++bb) {
-              const int yc = cc_ - bb + ck - c0;
-              if (yc < 0 || yc >= w) continue;
-              acc += taps[ti.psf + aa * K + bb] * F0[yr * pitch + yc];
-            }
-          }
-        }
-        Z[e] = acc;
-      }
-      __syncthreads();
-      // w = B^T z at the mapped pixels, back into the frame
-      for (int t = tid; t < M; t += NT) {
-        if (pix[t] < 0) continue;
-        const int rr_ = pix[t] >> 16, cc_ = pix[t] & 0xFFFF;
-        T acc = 0;
-        for (int aa = 0; aa < K; ++aa) {
-          const int zr = rr_ + aa - ck - Dr0;
-          if (zr < 0 || zr >= Dh) continue;
-          for (int bb = 0; bb < K; ++bb) {
-            const int zc = cc_ + bb - ck - Dc0;
-            if (zc < 0 || zc >= Dw) continue;
-            acc += taps[ti.psf + aa * K + bb] * Z[zr * Dw + zc];
-          }
-        }
-        F0[rr_ * pitch + cc_ + fo] = acc;
-      }
-      __syncthreads();
-    }
-    // q = L^T w + lambda H^T H p gathered per node from the transposed operator
-    // (no atomics, fixed order), stored in Q; <p, q>
-    double pq = 0.0;
-    {
-      const int32_t* perm = a.lt_perm + (long)m * a.I_max;
-      if (sell) {
-        // sliced-ELL in length-sorted node order: wave w takes slices w, w + 16, ...;
-        // the slice bounds are wave-uniform (scalar loads) and every lane of a
-        // slice has `len` entries (padding reads the zero halo), eight in flight
-        const int wid = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
-        const int nslices = (I + 63) >> 6;
-        const int lt_E = lt_rp[nslices];   // sliced-ELL entries of the member
-        for (int sl = wid; sl < nslices; sl += NT / 64) {
-          const int idx = sl * 64 + lane;
-          const int b0 = lt_rp[sl];
-          const int len = (lt_rp[sl + 1] - b0) >> 6;
-          const int pk = idx < I ? perm[idx] : 0;
-          T acc = 0;
-          if (sizeof(T) == 4 && sell == 2) {
-            // paired entries (even `len`, entries summed in the same order)
-            const unsigned* op = reinterpret_cast<const unsigned*>(lt_e) + (b0 >> 1) + lane;
-            const float2* wq = reinterpret_cast<const float2*>(reinterpret_cast<const unsigned*>(lt_e) + (lt_E >> 1)) +
-                               (b0 >> 1) + lane;
-            const int npair = len >> 1;
-            int j = 0;
-            for (; j + 7 < npair; j += 8) {   // sixteen entries in flight
-              unsigned o[8];
-              float2 wv[8];
-#pragma unroll
-              for (int u = 0; u < 8; ++u) {
-                o[u] = op[64L * (j + u)];
-                wv[u] = wq[64L * (j + u)];
-              }
-#pragma unroll
-              for (int u = 0; u < 8; ++u) {
-                acc += (T)wv[u].x * F[o[u] & 0xFFFFu];
-                acc += (T)wv[u].y * F[o[u] >> 16];
-              }
-            }
-            for (; j < npair; ++j) {
-              const unsigned o0 = op[64L * j];
-              const float2 w0 = wq[64L * j];
-              acc += (T)w0.x * F[o0 & 0xFFFFu];
-              acc += (T)w0.y * F[o0 >> 16];
-            }
-          } else {
-            const LtEntry<T>* ep = lt_e + b0 + lane;
-            int j = 0;
-            for (; j + 7 < len; j += 8) {
-              LtEntry<T> x[8];
-#pragma unroll
-              for (int u = 0; u < 8; ++u) x[u] = ep[64L * (j + u)];
-#pragma unroll
-              for (int u = 0; u < 8; ++u) acc += x[u].w * F[x[u].off];
-            }
-            for (; j < len; ++j) {
-              const LtEntry<T> x0 = ep[64L * j];
-              acc += x0.w * F[x0.off];
-            }
-          }
-          if (idx < I) {
-            const int rn_ = pk >> 16, cn_ = pk & 0xFFFF, i = rn_ * ns + cn_;
-            const T pv = P[i];
-            const T qv = acc + lamT * (ident ? pv : hth_node(P, ns, rn_, cn_));
-            Q[i] = qv;
-            pq += (double)pv * (double)qv;
-          }
-        }
-      } else {
-        for (int i = tid; i < I; i += NT) {
-          T acc = 0;
-          const int e0 = lt_rp[i], e1 = lt_rp[i + 1];
-          for (int e = e0; e < e1; ++e) acc += lt_e[e].w * F[lt_e[e].off];
-          const int rn_ = i / ns, cn_ = i - rn_ * ns;
-          const T pv = P[i];
-          const T qv = acc + lamT * (ident ? pv : hth_node(P, ns, rn_, cn_));
-          Q[i] = qv;
-          pq += (double)pv * (double)qv;
-        }
-      }
-    }
+    const OpView<T> ov{pix, cellp, fxp, fyp, F, F0, Z, taps, lt_rp, lt_e, a.lt_perm + (long)m * a.I_max, ns, I, M,
+                       r0, c0, h, w, pitch, fo, n2, nx, ny, K, ck, sell, Dr0, Dc0, Dh, Dw, sep, ident, inv_n2, lamT};
+    double pq = apply_normal<T, CKT, NT>(ov, P, Q);
     pq = block_sum1<NT / kWave>(pq, red, 0);
     // every gather has read the frame (barrier above): back to zero for the next iteration
     for (int e = tid; e < h * pitch; e += NT) Frows[e] = (T)0;
@@ -1646,6 +1739,182 @@ __global__ void __launch_bounds__(kNTof<T>) k_solve(SolveArgs a) {
   }
 }
 
+// ------------------------------------------------------------------ k_mcdof
+// Next member of the Monte Carlo pass for this block (thread 0 takes it, the
+// value is broadcast through LDS and made scalar), as fetch_item does.
+__device__ __forceinline__ int fetch_member(const SolveArgs& a, int* sh_m) {
+  if (threadIdx.x == 0) *sh_m = atomicAdd(&a.consts->mchead, 1);
+  __syncthreads();
+  const int m = __builtin_amdgcn_readfirstlane(*sh_m);
+  __syncthreads();
+  return m;
+}
+
+// Monte Carlo degrees of freedom of one member at its corner lambda (Sec. 2.5).
+// FP64: plain CG on the data system, and in lockstep the system with
+// right-hand side A^T bhat advanced with the data system's alpha_k and beta_k
+// (not its own); p of the data system stays in LDS (P), and the second
+// system's direction is swapped into P for its operator application.  FP32:
+// the second system by its own CG (see below).  Then gamma = <A^T bhat, xhat>
+// = bhat^T A xhat and dof = bhat^T bhat - gamma.  Per-block scratch (global):
+// r, xhat, rhat, phat and the saved p.
+template <typename T, int CKT, bool LDSF>
+__device__ __forceinline__ void run_mc_item(const SolveArgs& a, const MemberInfo& mi, int m, int kl,
+                                            unsigned char* smem) {
+  constexpr int NT = kNTof<T>;
+  const int tid = threadIdx.x;
+  const long slot = (long)blockIdx.x;
+  T* __restrict__ r_g = reinterpret_cast<T*>(a.mcbuf) + slot * 5L * a.I_max;
+  T* __restrict__ xh_g = r_g + a.I_max;
+  T* __restrict__ rh_g = xh_g + a.I_max;
+  T* __restrict__ ph_g = rh_g + a.I_max;
+  T* __restrict__ pd_g = ph_g + a.I_max;
+  const int ns = mi.ns, I = mi.I, M = mi.M, r0 = mi.r0, c0 = mi.c0;
+  const int h = mi.r1 - mi.r0 + 1, w = mi.c1 - mi.c0 + 1;
+  constexpr int HALO = 2 * CKT;
+  const int pitch = (w + 2 * HALO) | 1;
+  const int frame_elems = (h + 2 * HALO + kSegR) * pitch;
+  const int J = a.nx * a.ny, n2 = a.n2, nx = a.nx, ny = a.ny, K = a.K, ck = a.ck;
+  T* P = reinterpret_cast<T*>(smem);
+  T* Q = reinterpret_cast<T*>(smem + a.q_off);
+  double* red = reinterpret_cast<double*>(smem + a.red_off);
+  T* F = LDSF ? reinterpret_cast<T*>(smem + a.frame_off) : reinterpret_cast<T*>(a.gframe) + slot * a.gframe_elems;
+  T* const F0 = F + HALO * pitch + HALO;
+  T* const Frows = F + HALO * pitch;
+  const int Dr0 = max(mi.r0 - ck, 0), Dr1 = min(mi.r1 + ck, ny - 1);
+  const int Dc0 = max(mi.c0 - ck, 0), Dc1 = min(mi.c1 + ck, nx - 1);
+  const OpView<T> ov{a.pix_list + (long)m * a.slot_cap, a.cell + (long)m * a.slot_cap * n2,
+                     reinterpret_cast<const T*>(a.fx) + (long)m * a.slot_cap * n2,
+                     reinterpret_cast<const T*>(a.fy) + (long)m * a.slot_cap * n2, F, F0,
+                     reinterpret_cast<T*>(a.gz) + slot * J, reinterpret_cast<const T*>(a.taps_t),
+                     a.lt_ptr + (long)m * (a.I_max + 65),
+                     reinterpret_cast<const LtEntry<T>*>(a.lt_ent) + (long)m * a.lt_cap, a.lt_perm + (long)m * a.I_max,
+                     ns, I, M, r0, c0, h, w, pitch, -r0 * pitch - c0, n2, nx, ny, K, ck,
+                     __builtin_amdgcn_readfirstlane(mi.sell), Dr0, Dc0, Dr1 - Dr0 + 1, Dc1 - Dc0 + 1,
+                     a.consts->sep != 0, a.reg == SL_H_IDENTITY, (T)1 / (T)n2, (T)a.lamv[kl]};
+  for (int e = tid; e < frame_elems; e += NT) F[e] = (T)0;
+  const double* bm = a.b + (long)m * a.I_max;
+  const double* bhm = a.bh + (long)m * a.I_max;
+  if constexpr (sizeof(T) == 4) {
+    // FP32: the lockstep recurrence is linear in the second system with fixed
+    // coefficients, so FP32 rounding injected at one step grows with the data
+    // polynomial's later factors; here the second system is solved by its own
+    // CG instead (same operator, same stopping rule relative to ||A^T bhat||),
+    // which estimates the same Tikhonov gamma (Eq. 19) once converged.
+    double rr = 0.0;
+    for (int i = tid; i < I; i += NT) {
+      const T nv = (T)bhm[i];
+      P[i] = nv;
+      rh_g[i] = nv;
+      xh_g[i] = (T)0;
+      rr += (double)nv * (double)nv;
+    }
+    rr = block_sum1<NT / kWave>(rr, red, 0);
+    const double stop2 = a.tol * a.tol * rr;
+    for (int it = 0; it < a.maxit; ++it) {
+      if (__builtin_amdgcn_readfirstlane((int)(rr <= stop2))) break;
+      double pq = apply_normal<T, CKT, NT>(ov, P, Q);
+      pq = block_sum1<NT / kWave>(pq, red, 0);
+      for (int e = tid; e < h * pitch; e += NT) Frows[e] = (T)0;
+      if (__builtin_amdgcn_readfirstlane((int)!(pq > 0.0))) break;
+      const T alT = (T)(rr / pq);
+      double rn = 0.0;
+      for (int i = tid; i < I; i += NT) {
+        xh_g[i] += alT * P[i];
+        const T rk = rh_g[i] - alT * Q[i];
+        rh_g[i] = rk;
+        rn += (double)rk * (double)rk;
+      }
+      rn = block_sum1<NT / kWave>(rn, red, 1);
+      const T beta = (T)(rn / rr);
+      for (int i = tid; i < I; i += NT) P[i] = rh_g[i] + beta * P[i];
+      rr = rn;
+      __syncthreads();
+    }
+  } else {
+  double rr = 0.0;
+  for (int i = tid; i < I; i += NT) {
+    const T bv = (T)bm[i], nv = (T)bhm[i];
+    P[i] = bv;
+    r_g[i] = bv;
+    rr += (double)bv * (double)bv;
+    xh_g[i] = (T)0;
+    rh_g[i] = nv;
+    ph_g[i] = nv;
+  }
+  rr = block_sum1<NT / kWave>(rr, red, 0);
+  const double stop2 = a.tol * a.tol * rr;
+  for (int it = 0; it < a.maxit; ++it) {
+    if (__builtin_amdgcn_readfirstlane((int)(rr <= stop2))) break;
+    // data system: q = A p, alpha, r update, beta, new p (saved to global)
+    double pq = apply_normal<T, CKT, NT>(ov, P, Q);
+    pq = block_sum1<NT / kWave>(pq, red, 0);
+    for (int e = tid; e < h * pitch; e += NT) Frows[e] = (T)0;
+    if (__builtin_amdgcn_readfirstlane((int)!(pq > 0.0))) break;
+    const T alT = (T)(rr / pq);
+    double rn = 0.0;
+    for (int i = tid; i < I; i += NT) {
+      const T rk = r_g[i] - alT * Q[i];
+      r_g[i] = rk;
+      rn += (double)rk * (double)rk;
+    }
+    rn = block_sum1<NT / kWave>(rn, red, 1);
+    const T beta = (T)(rn / rr);
+    for (int i = tid; i < I; i += NT) {
+      pd_g[i] = r_g[i] + beta * P[i];
+      P[i] = ph_g[i];
+    }
+    __syncthreads();
+    // second system with the same alpha and beta
+    double pqh = apply_normal<T, CKT, NT>(ov, P, Q);
+    pqh = block_sum1<NT / kWave>(pqh, red, 0);   // its barrier: every gather has read P and the frame
+    (void)pqh;
+    for (int e = tid; e < h * pitch; e += NT) Frows[e] = (T)0;
+    for (int i = tid; i < I; i += NT) {
+      const T ph = P[i];
+      xh_g[i] += alT * ph;
+      const T rk = rh_g[i] - alT * Q[i];
+      rh_g[i] = rk;
+      ph_g[i] = rk + beta * ph;
+      P[i] = pd_g[i];
+    }
+    rr = rn;
+    __syncthreads();
+  }
+  }
+  double g = 0.0;
+  for (int i = tid; i < I; i += NT) g += bhm[i] * (double)xh_g[i];
+  g = block_sum1<NT / kWave>(g, red, 1);
+  // every thread stores the same value: no lane-predicated store in the member loop
+  a.dofv[m] = a.consts->sum_n2 - g;
+  __syncthreads();
+}
+
+// One member per item, in member order, at the member's L-curve corner; a
+// member without a solve (invalid, or no pixel maps) gets NaN.  The member
+// loop holds no lane-predicated code besides the fetch (the form k_solve
+// uses): a store under `threadIdx.x == 0` followed by `continue` was compiled
+// into an inner loop that thread 0's lane left to do the store while the
+// other lanes went on re-reading an item index that only thread 0 advances.
+template <typename T, int CKT>
+__global__ void __launch_bounds__(kNTof<T>) k_mcdof(SolveArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int sh_m;
+  for (int m = fetch_member(a, &sh_m); m < a.n_members; m = fetch_member(a, &sh_m)) {
+    const MemberInfo mi = a.minfo[m];
+    const int status = __builtin_amdgcn_readfirstlane(mi.status);
+    if (status != SL_ST_OK) {
+      a.dofv[m] = NAN;   // the same value from every thread
+    } else {
+      const int kl = __builtin_amdgcn_readfirstlane(a.k_star[m]);
+      if (__builtin_amdgcn_readfirstlane(mi.lds_frame))
+        run_mc_item<T, CKT, true>(a, mi, m, kl, smem);
+      else
+        run_mc_item<T, CKT, false>(a, mi, m, kl, smem);
+    }
+  }
+}
+
 // Moves the items that take the spectral preconditioner into their own queues
 // (stable, per XCD queue): valid member, FP32, curvature H, frame in LDS with
 // room for the n x n scratch, and lambda >= kPcTheta c.  One block.
@@ -1763,11 +2032,13 @@ static Layout make_layout(const sl_problem* pb, int max_ns, int M, int NL, int n
   L.fx = take(sz * (size_t)M * L.slot_cap * L.n2);
   L.fy = take(sz * (size_t)M * L.slot_cap * L.n2);
   L.b = take(sizeof(double) * (size_t)M * L.I_max);
+  L.bh = take(sizeof(double) * (size_t)M * L.I_max);   // A^T bhat (Monte Carlo degrees of freedom)
   L.s_all = take(sz * (size_t)M * NL * L.I_max);
   L.gframe_elems = (pb->img.ny + 4 * 16 + kSegR) * ((pb->img.nx + 4 * 16) | 1);   // widest window's halo
   L.gframe = take(sz * (size_t)n_wg * L.gframe_elems);
   L.gz = take(sz * 2 * (size_t)n_wg * L.J);          // plain | preconditioned launch
   L.rbuf = take(sz * 2 * (size_t)n_wg * L.I_max);
+  L.mcbuf = take(sz * 5 * (size_t)n_wg * L.I_max);
   L.lt_ptr = take(sizeof(int32_t) * (size_t)M * (L.I_max + 65));
   L.lt_perm = take(sizeof(int32_t) * (size_t)M * L.I_max);
   L.lt_cap = 8LL * L.n2 * L.slot_cap;   // twice the unpadded bound: room for slice padding
@@ -1820,6 +2091,27 @@ static SolveKernel pick_kernel_f(int ck, bool wide, int* ckt, bool pc = false) {
   return k[i];
 }
 
+// The Monte Carlo degrees-of-freedom kernel of the same bulk type and window as the solve.
+template <typename T>
+static SolveKernel pick_mc_kernel(int ckt) {
+  if (sizeof(T) == 4) {
+    switch (ckt) {
+      case 2: return k_mcdof<float, 2>;
+      case 4: return k_mcdof<float, 4>;
+      case 7: return k_mcdof<float, 7>;
+      case 10: return k_mcdof<float, 10>;
+      case 16: return k_mcdof<float, 16>;
+    }
+  } else {
+    switch (ckt) {
+      case 2: return k_mcdof<double, 2>;
+      case 7: return k_mcdof<double, 7>;
+      case 10: return k_mcdof<double, 10>;
+    }
+  }
+  return nullptr;
+}
+
 static SolveKernel pick_kernel_d(int ck, bool wide, int* ckt) {
   static const int sizes[] = {2, 7, 10};
   static const SolveKernel ks[] = {k_solve<double, 2, false>, k_solve<double, 7, false>, k_solve<double, 10, false>};
@@ -1869,6 +2161,7 @@ static int side_stream(SideStream** out) {
 struct LaunchCfg {
   SolveKernel ks = nullptr;
   SolveKernel kpc = nullptr;   // preconditioned kernel, when some items may take it
+  SolveKernel kmc = nullptr;   // Monte Carlo degrees-of-freedom pass, when requested
   size_t lds = 0, prep_lds = 0, corner_lds = 0;
 };
 
@@ -1906,6 +2199,13 @@ static int configure(SolveArgs& A, const Layout& L, const sl_tuning& v, LaunchCf
     c->kpc = pick_kernel_f(A.ck, v.wide_window != 0, &ckt2, true);
   }
   c->lds = lds;
+  if (A.mcn) {
+    c->kmc = pick_mc_kernel<T>(ckt);
+    if (!c->kmc) {
+      set_error("no Monte Carlo degrees-of-freedom kernel for window %d", ckt);
+      return SL_ENOIMPL;
+    }
+  }
   // FP64 right-hand-side accumulator, reused by the transposed-operator build (2 I + 192 ints)
   c->prep_lds = std::max(sizeof(double) * L.I_max, sizeof(int) * (2 * L.I_max + 192));
   c->corner_lds = sizeof(double) * (A.n_lambda * A.n_lambda + 12 * A.n_lambda + 16);
@@ -1914,6 +2214,8 @@ static int configure(SolveArgs& A, const Layout& L, const sl_tuning& v, LaunchCf
   SL_HIP(hipFuncSetAttribute((const void*)ks, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   if (c->kpc)
     SL_HIP(hipFuncSetAttribute((const void*)c->kpc, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  if (c->kmc)
+    SL_HIP(hipFuncSetAttribute((const void*)c->kmc, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   SL_HIP(hipFuncSetAttribute((const void*)k_prep<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)c->prep_lds));
   return SL_OK;
@@ -1974,7 +2276,12 @@ static int enqueue(const SolveArgs& A, const LamList& lams, const Layout& L, con
     g_prof.ev.emplace_back(e0, e1);
   }
   hipLaunchKernelGGL(k_corner<T>, dim3(A.n_members), dim3(256), c.corner_lds, st, A);
-  return check_launch("k_corner");
+  if (int e = check_launch("k_corner")) return e;
+  if (c.kmc) {
+    hipLaunchKernelGGL(c.kmc, dim3(L.n_wg), dim3(kNTof<T>), c.lds, st, A);
+    return check_launch("k_mcdof");
+  }
+  return SL_OK;
 }
 
 static int configure_any(int dtype, SolveArgs& A, const Layout& L, const sl_tuning& v, LaunchCfg* c) {
@@ -2027,6 +2334,7 @@ static int prepare(const sl_problem* pb, const double* lens, const int32_t* ns, 
   SL_REQUIRE(out && out->s_corner && out->s_off && out->chi2 && out->reg && out->iters && out->status &&
                  out->k_star && out->corner_status,
              "NULL result pointer");
+  SL_REQUIRE(!opt->mc_noise || out->dof, "mc_noise given but the result has no dof array");
   SL_REQUIRE(workspace != nullptr && ((uintptr_t)workspace & 255) == 0,
              "workspace must be non-NULL and 256-byte aligned");
   const Layout L = make_layout(pb, max_ns, n_members, n_lambda, device_cus());
@@ -2073,6 +2381,10 @@ static int prepare(const sl_problem* pb, const double* lens, const int32_t* ns, 
   A.fx = ws + L.fx;
   A.fy = ws + L.fy;
   A.b = (double*)(ws + L.b);
+  A.bh = (double*)(ws + L.bh);
+  A.mcbuf = ws + L.mcbuf;
+  A.mcn = opt->mc_noise;
+  A.dofv = opt->mc_noise ? out->dof : nullptr;
   A.s_all = ws + L.s_all;
   A.gframe = ws + L.gframe;
   A.gframe_elems = L.gframe_elems;

@@ -224,6 +224,7 @@ class Solver:
             status=torch.empty((n_members, n_lambda), dtype=torch.int32, device=dev),
             k_star=torch.empty(n_members, dtype=torch.int32, device=dev),
             corner_status=torch.empty(n_members, dtype=torch.int32, device=dev),
+            dof=torch.empty(n_members, dtype=torch.float64, device=dev),
         )
 
     def member_info(self, max_ns: int, n_members: int, n_lambda: int) -> np.ndarray:
@@ -233,7 +234,7 @@ class Solver:
                                              info.ctypes.data_as(ctypes.c_void_p)), "sl_solve_member_info")
         return info
 
-    def _args(self, lens, ns, lambdas, tol, maxit, max_ns, out, tuning):
+    def _args(self, lens, ns, lambdas, tol, maxit, max_ns, out, tuning, mc_noise=None):
         _dev_check(lens, ns)
         if lens.dtype != torch.float64 or ns.dtype != torch.int32 or not lens.is_contiguous() \
                 or not ns.is_contiguous():
@@ -246,15 +247,22 @@ class Solver:
         if out is None:
             out = self.alloc_result(M * max_ns * max_ns, M, len(lam))
         res = L.Result(*[ctypes.c_void_p(out[k].data_ptr()) for k in
-                         ("s_corner", "s_off", "chi2", "reg", "iters", "status", "k_star", "corner_status")])
+                         ("s_corner", "s_off", "chi2", "reg", "iters", "status", "k_star", "corner_status", "dof")])
         tun = None
         if tuning is not None:
             tun = L.Tuning(*[int(tuning.get(k, 0)) for k in ("wide_window", "lt_csr", "blur_direct", "plain_cg")])
-        opts = L.SolveOpts(float(tol), int(maxit), ctypes.pointer(tun) if tun is not None else None)
+        noise = None
+        if mc_noise is not None:
+            _dev_check(mc_noise)
+            if mc_noise.dtype != torch.float64 or not mc_noise.is_contiguous() or mc_noise.numel() != self.grid.J:
+                raise L.SemilinError("mc_noise must be a contiguous float64 device tensor of ny*nx draws")
+            noise = ctypes.c_void_p(mc_noise.data_ptr())
+        opts = L.SolveOpts(float(tol), int(maxit), ctypes.pointer(tun) if tun is not None else None, noise)
         return M, lam, int(max_ns), ws, out, res, opts, tun
 
     def solve_semilinear(self, lens: torch.Tensor, ns: torch.Tensor, lambdas, tol=1e-7, maxit=4000,
-                         max_ns: int | None = None, out=None, tuning: dict | None = None):
+                         max_ns: int | None = None, out=None, tuning: dict | None = None,
+                         mc_noise: torch.Tensor | None = None):
         """Run the batched solve; returns the result dict of device tensors.
 
         lens (M, 7) FP64 and ns (M,) int32 on the device; lambdas a host
@@ -262,11 +270,13 @@ class Solver:
         ``tuning`` (dict with keys wide_window, lt_csr, blur_direct, plain_cg)
         forces a kernel variant; None takes the autotuner's choice, if any.
         plain_cg = 1 turns the spectral preconditioner of the FP32 curvature
-        solve off.
+        solve off.  ``mc_noise`` (ny*nx FP64 Gaussian draws on the device)
+        adds the Monte Carlo degrees of freedom at each corner to out["dof"].
         """
         lens = lens.to(torch.float64).contiguous()
         ns = ns.to(torch.int32).contiguous()
-        M, lam, max_ns, ws, out, res, opts, _tun = self._args(lens, ns, lambdas, tol, maxit, max_ns, out, tuning)
+        M, lam, max_ns, ws, out, res, opts, _tun = self._args(lens, ns, lambdas, tol, maxit, max_ns, out, tuning,
+                                                              mc_noise)
         L.check(L.lib().sl_solve_semilinear(ctypes.byref(self._pb), L.ptr(lens), L.ptr(ns), max_ns, M,
                                             L.f64_array(lam), len(lam), ctypes.byref(opts), L.ptr(ws),
                                             ws.numel(), ctypes.byref(res), L.stream_handle()),

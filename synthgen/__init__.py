@@ -174,3 +174,10 @@ def mlp_batch(seed: int, batch: int) -> tuple:
 def random_vector(seed: int, n: int) -> np.ndarray:
     rng = np.random.default_rng(seed)
     return rng.standard_normal(n)
+
+
+def mc_draws(seed: int, ny: int, nx: int) -> np.ndarray:
+    """Zero-mean, unit-variance Gaussian image (ny, nx): the random vector of the
+    Monte Carlo degrees-of-freedom estimate, drawn once and handed to both sides."""
+    rng = np.random.default_rng(seed + 1000)
+    return rng.standard_normal((ny, nx))

@@ -210,7 +210,8 @@ def test_solve_is_bitwise_repeatable(sl, dtype):
     n = int(a["s_off"][-1])
     a["s_corner"], b["s_corner"] = a["s_corner"][:n], b["s_corner"][:n]
     for k in a:
-        assert np.array_equal(a[k], b[k]), k
+        if k != "dof":   # written only by the Monte Carlo pass
+            assert np.array_equal(a[k], b[k]), k
 
 
 def test_apply_LT_ordered_repeatable_and_vs_oracle(sl):
@@ -291,10 +292,10 @@ def test_plan_capture_beside_eager_solves(sl):
         t.join()
     assert not errs, errs
     assert len(got_a) == 3
-    def same(x, y):   # s_corner past s_off[-1] is not written
+    def same(x, y):   # s_corner past s_off[-1] and dof (no Monte Carlo pass) are not written
         n = int(y["s_off"][-1])
         return all(np.array_equal(x[k][:n] if k == "s_corner" else x[k], y[k][:n] if k == "s_corner" else y[k])
-                   for k in y)
+                   for k in y if k != "dof")
 
     assert all(same(got, ref_a) for got in got_a)
     assert same(_np(out_b), ref_b)
