@@ -358,6 +358,19 @@ int sl_mlp_forward(const float* params, const float* x, int batch, float* y, voi
                    void* stream);
 
 /*
+ * sl_mlp_forward without a workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  Same results as sl_mlp_forward, bit
+ * for bit.  Its scratch (the BF16 and FP32 transposed copies of W1,
+ * 384 KiB, whatever the batch) is a static device array of the library,
+ * one per GPU, held until the process ends; the call allocates nothing.
+ * Every call on a GPU shares that GPU's array, so calls that overlap in
+ * time on one GPU (two streams, two threads) race and must be serialised by
+ * the caller.  batch in [1, SL_MLP_MAX_BATCH], else SL_EINVAL.
+ */
+int sl_mlp_forward_noalloc(const float* params, const float* x, int batch, float* y, void* stream);
+
+/*
  * One Adam step on the mean squared error L = (1/B) sum_b (y_hat_b - y_b)^2:
  * forward, backward (same BF16 roundings), then with g = dL/dparams
  *   m = 0.9 m + 0.1 g;  v = 0.999 v + 0.001 g^2;

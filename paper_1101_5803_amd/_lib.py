@@ -21,6 +21,7 @@ SL_H_IDENTITY, SL_H_CURVATURE = 0, 1
 ST_OK, ST_MAXIT, ST_EMPTY, ST_BREAKDOWN, ST_INVALID, ST_LCURVE = range(6)
 MAX_LAMBDA = 64
 MLP_NPARAM = 7 * 256 + 256 + 256 * 256 + 256 + 256 + 1
+MLP_MAX_BATCH = 1 << 20
 
 
 class SemilinError(RuntimeError):
@@ -102,9 +103,10 @@ def lib():
         L.sl_mlp_workspace_size.argtypes = [ip]
         L.sl_mlp_workspace_size.restype = ctypes.c_size_t
         L.sl_mlp_forward.argtypes = [vp, vp, ip, vp, vp, vp]
+        L.sl_mlp_forward_noalloc.argtypes = [vp, vp, ip, vp, vp]
         L.sl_mlp_train_step.argtypes = [vp, vp, vp, vp, vp, ip, ctypes.c_float, ip, vp, vp, vp, vp]
         for name in ("sl_lens_trace", "sl_apply_L", "sl_apply_LT", "sl_apply_LT_ordered", "sl_apply_B", "sl_apply_BT",
-                     "sl_apply_HtH", "sl_solve_semilinear", "sl_lcurve_corner", "sl_mlp_forward",
+                     "sl_apply_HtH", "sl_solve_semilinear", "sl_lcurve_corner", "sl_mlp_forward", "sl_mlp_forward_noalloc",
                      "sl_mlp_train_step", "sl_solve_member_info", "sl_profile_enable", "sl_profile_solve_ms",
                      "sl_solve_autotune", "sl_plan_create", "sl_plan_launch", "sl_plan_destroy"):
             getattr(L, name).restype = ctypes.c_int

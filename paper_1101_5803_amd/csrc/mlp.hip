@@ -18,6 +18,8 @@
 //                reduction of the per-tile partials
 //   k_mlp_adam   Adam with bias correction, elementwise
 // Every sum has a fixed order, so results are bitwise reproducible.
+#include <mutex>
+
 #include "common.h"
 
 namespace sl {
@@ -447,6 +449,33 @@ __global__ void __launch_bounds__(kThr) k_mlp_adam(float* __restrict__ p, float*
   p[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
 }
 
+// Scratch of sl_mlp_forward_noalloc: the BF16 and FP32 transposed copies of
+// W1 that k_mlp_prep writes and k_mlp_fwd reads (the forward pass needs no
+// other scratch, whatever the batch).  Every call rewrites all of it.
+constexpr size_t kNoallocBf = sizeof(unsigned short) * kH * kH;   // 128 KiB
+constexpr size_t kNoallocBytes = kNoallocBf + sizeof(float) * kH * kH;   // 384 KiB
+static_assert(kNoallocBf % 256 == 0, "FP32 copy stays 256-byte aligned");
+static __device__ __align__(256) unsigned char scratch[kNoallocBytes];
+
+// Device address of `scratch` on the current device, looked up once per
+// device with that device current (each GPU holds its own copy).
+int noalloc_scratch(unsigned char** out) {
+  static std::mutex mu;
+  static unsigned char* ptr[64] = {nullptr};
+  int dev = 0;
+  SL_HIP(hipGetDevice(&dev));
+  SL_REQUIRE(dev >= 0 && dev < 64, "device index %d out of range", dev);
+  std::lock_guard<std::mutex> g(mu);
+  if (!ptr[dev]) {
+    void* p = nullptr;
+    SL_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    SL_REQUIRE(p != nullptr, "no device address for the forward scratch");
+    ptr[dev] = static_cast<unsigned char*>(p);
+  }
+  *out = ptr[dev];
+  return SL_OK;
+}
+
 int validate(const void* params, const float* x, int batch, const void* ws) {
   SL_REQUIRE(batch >= 1 && batch <= kMaxBatch, "batch %d outside [1, %d]", batch, kMaxBatch);
   SL_REQUIRE(params && x && ws, "null pointer argument");
@@ -474,6 +503,22 @@ int sl_mlp_forward(const float* params, const float* x, int batch, float* y, voi
   hipStream_t st = static_cast<hipStream_t>(stream);
   Ws w;
   carve(batch, static_cast<unsigned char*>(workspace), &w);
+  k_mlp_prep<<<16, kThr, 0, st>>>(params, w.w1t_bf, w.w1t_f);
+  if (int rc = check_launch("k_mlp_prep")) return rc;
+  FwdArgs fa{params, x, nullptr, batch, 0.0f, y, w};
+  k_mlp_fwd<false><<<(batch + kBM - 1) / kBM, kThr, 0, st>>>(fa);
+  return check_launch("k_mlp_fwd");
+}
+
+int sl_mlp_forward_noalloc(const float* params, const float* x, int batch, float* y, void* stream) {
+  SL_REQUIRE(batch >= 1 && batch <= kMaxBatch, "batch %d outside [1, %d]", batch, kMaxBatch);
+  SL_REQUIRE(params && x && y, "null pointer argument");
+  unsigned char* sc = nullptr;
+  if (int rc = noalloc_scratch(&sc)) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Ws w{};
+  w.w1t_bf = reinterpret_cast<unsigned short*>(sc);
+  w.w1t_f = reinterpret_cast<float*>(sc + kNoallocBf);
   k_mlp_prep<<<16, kThr, 0, st>>>(params, w.w1t_bf, w.w1t_f);
   if (int rc = check_launch("k_mlp_prep")) return rc;
   FwdArgs fa{params, x, nullptr, batch, 0.0f, y, w};

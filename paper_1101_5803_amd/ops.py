@@ -376,6 +376,20 @@ def mlp_forward(params: torch.Tensor, x: torch.Tensor, out: torch.Tensor | None 
     return y
 
 
+def mlp_forward_noalloc(params: torch.Tensor, x: torch.Tensor, out: torch.Tensor) -> torch.Tensor:
+    """mlp_forward through sl_mlp_forward_noalloc: the library allocates nothing (its scratch is a static
+    device array); the caller passes the output buffer.  Overlapping calls on one GPU race."""
+    _mlp_check(params, x)
+    _dev_check(out)
+    x = x.contiguous()
+    B = x.shape[0]
+    if out.dtype != torch.float32 or out.numel() < B or not out.is_contiguous():
+        raise L.SemilinError("out must be a contiguous float32 tensor of at least batch elements")
+    L.check(L.lib().sl_mlp_forward_noalloc(L.ptr(params), L.ptr(x), B, L.ptr(out), L.stream_handle()),
+            "sl_mlp_forward_noalloc")
+    return out
+
+
 def mlp_train_step(params: torch.Tensor, m: torch.Tensor, v: torch.Tensor, x: torch.Tensor, y: torch.Tensor,
                    lr: float, t: int, grads: torch.Tensor | None = None, loss: torch.Tensor | None = None) -> None:
     """One in-place Adam step of params (and moments m, v) on the batch's MSE."""
