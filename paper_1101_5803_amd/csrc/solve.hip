@@ -163,6 +163,7 @@ struct SolveArgs {
   int I_max;
   int force_csr;    // variant: transposed operator as CSR rows
   int force_direct; // variant: direct K x K blur for a separable PSF
+  int prep_tags;    // k_prep has one LDS int per node after its 8 I_max + 768 bytes (conflict tags)
   int plain_cg;     // variant: no spectral preconditioner
   // Monte Carlo degrees of freedom (Sec. 2.5), when mcn is not NULL
   const double* mcn; // [ny*nx] Gaussian draws bhat
@@ -447,6 +448,44 @@ __device__ __forceinline__ void pixel_pairs4(int t, int ns, const int32_t* cellp
   }
 }
 
+// Rank of this lane among the lanes of its wave that hold the same key
+// (key >= 0), and their count.  With an LDS tag array (one int per key), a
+// step in which no two lanes share a key is recognised in one store/load
+// round trip: every lane writes its lane id at its key and reads it back, and
+// a lane that reads another id shares its key.  Whether some lane does is the
+// same whichever store won, so the outcome, and every summation order built
+// on it, is the same on every run.  Only when keys are shared are the ranks
+// counted lane by lane (64 readlane steps).
+__device__ __forceinline__ void lane_rank(int key, int* tag, int& rank, int& total) {
+  const int lane = threadIdx.x & 63;
+  if (tag) {
+    if (key >= 0) tag[key] = lane;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int seen = key >= 0 ? reinterpret_cast<volatile int*>(tag)[key] : lane;
+    const int clash = __builtin_amdgcn_readfirstlane((int)(__ballot(seen != lane) != 0ull));
+    // every lane has read its tag before a later step writes the array again
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (!clash) {
+      rank = 0;
+      total = 1;
+      return;
+    }
+  }
+  rank = 0;
+  total = 0;
+  for (int l = 0; l < 64; ++l) {   // uniform lane index: v_readlane
+    const int kl = __builtin_amdgcn_readlane(key, l);
+    if (kl == key) {
+      ++total;
+      if (l < lane) ++rank;
+    }
+  }
+}
+
 // Quarter-octave bucket of a row length (0 for empty rows): rows in one
 // bucket differ by less than 19%.
 __device__ __forceinline__ int len_bucket(int c) {
@@ -468,7 +507,7 @@ __device__ __forceinline__ int len_bucket(int c) {
 // sliced-ELL, 0 for CSR.  lds: LDS ints (>= 2 I + 64 + 128).
 template <typename T>
 __device__ int build_transpose(const SolveArgs& a, int m, int ns, int slots, const int* bbox, int* scan, int* lds,
-                               const int32_t* pix, const int32_t* cellp, const T* fxp, const T* fyp) {
+                               const int32_t* pix, const int32_t* cellp, const T* fxp, const T* fyp, int* tag) {
   const int tid = threadIdx.x, n2 = a.n2, I = ns * ns;
   const int halo = 2 * a.ckt;
   const int pitch = (bbox[3] - bbox[2] + 1 + 2 * halo) | 1;
@@ -645,14 +684,8 @@ __device__ int build_transpose(const SolveArgs& a, int m, int ns, int slots, con
       for (int q = 0; q < 16; ++q) {
         const int key = nd[q];
         if (!__builtin_amdgcn_readfirstlane((int)(__ballot(key >= 0) != 0ull))) continue;   // uniform
-        int rank = 0, total = 0;
-        for (int l = 0; l < 64; ++l) {
-          const int kl = __builtin_amdgcn_readlane(key, l);
-          if (kl == key) {
-            ++total;
-            if (l < lane) ++rank;
-          }
-        }
+        int rank, total;
+        lane_rank(key, tag, rank, total);
         const int j = key >= 0 ? cnt[key] + rank : 0;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -690,14 +723,8 @@ __device__ int build_transpose(const SolveArgs& a, int m, int ns, int slots, con
       for (int o = 32; o > 0; o >>= 1) npmax = max(npmax, __shfl_xor(npmax, o, 64));
       for (int q = 0; q < npmax; ++q) {
         const int key = q < np ? node[q] : -1;
-        int rank = 0, total = 0;
-        for (int l = 0; l < 64; ++l) {
-          const int kl = __builtin_amdgcn_readlane(key, l);
-          if (kl == key) {
-            ++total;
-            if (l < lane) ++rank;
-          }
-        }
+        int rank, total;
+        lane_rank(key, tag, rank, total);
         const int j = key >= 0 ? cnt[key] + rank : 0;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -727,14 +754,11 @@ __device__ int build_transpose(const SolveArgs& a, int m, int ns, int slots, con
 // bacc[key] += val on the lanes of one wave with key >= 0; lanes that share
 // a key add in lane order (they take turns by their rank among the lanes
 // with that key), so every node's sum has the same order on every run.
-__device__ __forceinline__ void wave_ordered_add(double* bacc, int key, double val) {
-  const int lane = threadIdx.x & 63;
+__device__ __forceinline__ void wave_ordered_add(double* bacc, int* tag, int key, double val) {
   if (!__builtin_amdgcn_readfirstlane((int)(__ballot(key >= 0) != 0ull))) return;   // uniform
-  int rank = 0;
-  for (int l = 0; l < 64; ++l) {   // uniform lane index: v_readlane
-    const int kl = __builtin_amdgcn_readlane(key, l);
-    rank += (l < lane && kl == key) ? 1 : 0;
-  }
+  int rank, total;
+  lane_rank(key, tag, rank, total);
+  (void)total;
   for (int r = 0; __ballot(key >= 0 && rank >= r) != 0ull; ++r) {
     if (key >= 0 && rank == r) bacc[key] += val;
     // this round's LDS writes precede the next round's reads
@@ -776,7 +800,7 @@ __device__ void correlate_slots(const SolveArgs& a, const double* img, int slots
 // same on every run.  `slots` is a multiple of 64.
 template <typename T>
 __device__ void rhs_fixed_order(const SolveArgs& a, const double* vbuf, int ns, int slots, const int32_t* pix,
-                                const int32_t* cellp, const T* fxp, const T* fyp, double* bacc) {
+                                const int32_t* cellp, const T* fxp, const T* fyp, double* bacc, int* tag) {
   const int lane = threadIdx.x & 63;
   const int n2 = a.n2;
   for (int t0 = 0; t0 < slots; t0 += 64) {
@@ -796,14 +820,14 @@ __device__ void rhs_fixed_order(const SolveArgs& a, const double* vbuf, int ns, 
         }
       }
 #pragma unroll
-      for (int q = 0; q < 16; ++q) wave_ordered_add(bacc, nd[q], ww[q] * v);
+      for (int q = 0; q < 16; ++q) wave_ordered_add(bacc, tag, nd[q], ww[q] * v);
     } else {
       int node[4 * SL_MAX_NSUB * SL_MAX_NSUB];
       double wt[4 * SL_MAX_NSUB * SL_MAX_NSUB];
       const int np = rc >= 0 ? pixel_pairs(t, ns, n2, cellp, fxp, fyp, node, wt) : 0;
       int npmax = np;
       for (int o = 32; o > 0; o >>= 1) npmax = max(npmax, __shfl_xor(npmax, o, 64));
-      for (int q = 0; q < npmax; ++q) wave_ordered_add(bacc, q < np ? node[q] : -1, q < np ? wt[q] * v : 0.0);
+      for (int q = 0; q < npmax; ++q) wave_ordered_add(bacc, tag, q < np ? node[q] : -1, q < np ? wt[q] * v : 0.0);
     }
   }
 }
@@ -905,10 +929,13 @@ __device__ void prep_member(const SolveArgs& a, int m, MemberInfo mi, const doub
   // build_transpose fills only later (it holds >= 8 slot_cap bytes).
   const int I = ns * ns;
   double* vbuf = reinterpret_cast<double*>(reinterpret_cast<LtEntry<T>*>(a.lt_ent) + (long)m * a.lt_cap);
+  // conflict tags of lane_rank, past the accumulator and the transpose build's arrays
+  int* tag = a.prep_tags ? reinterpret_cast<int*>(reinterpret_cast<unsigned char*>(bacc) + 8L * a.I_max + 768)
+                         : nullptr;
   for (int i = tid; i < I; i += blockDim.x) bacc[i] = 0.0;
   correlate_slots(a, a.d, Mm, pix, vbuf);
   __syncthreads();
-  if (tid < 64) rhs_fixed_order<T>(a, vbuf, ns, Mm, pix, cellp, fxp, fyp, bacc);
+  if (tid < 64) rhs_fixed_order<T>(a, vbuf, ns, Mm, pix, cellp, fxp, fyp, bacc, tag);
   __syncthreads();
   const double inv_n2 = 1.0 / n2;
   // scale of the spectral preconditioner: c = sum_i cov_i b_i^2 / sum_i b_i^2
@@ -939,7 +966,7 @@ __device__ void prep_member(const SolveArgs& a, int m, MemberInfo mi, const doub
     for (int i = tid; i < I; i += blockDim.x) bacc[i] = 0.0;
     correlate_slots(a, a.mcn, Mm, pix, vbuf);
     __syncthreads();
-    if (tid < 64) rhs_fixed_order<T>(a, vbuf, ns, Mm, pix, cellp, fxp, fyp, bacc);
+    if (tid < 64) rhs_fixed_order<T>(a, vbuf, ns, Mm, pix, cellp, fxp, fyp, bacc, tag);
     __syncthreads();
     double* bhm = a.bh + (long)m * a.I_max;
     for (int i = tid; i < I; i += blockDim.x) bhm[i] = bacc[i];
@@ -947,7 +974,7 @@ __device__ void prep_member(const SolveArgs& a, int m, MemberInfo mi, const doub
   }
   int sell = 0;
   if (Mtrue > 0)
-    sell = build_transpose<T>(a, m, ns, Mm, bbox, scan, reinterpret_cast<int*>(bacc), pix, cellp, fxp, fyp);
+    sell = build_transpose<T>(a, m, ns, Mm, bbox, scan, reinterpret_cast<int*>(bacc), pix, cellp, fxp, fyp, tag);
   if (tid == 0) {
     const int fh = Mtrue > 0 ? bbox[1] - bbox[0] + 1 : 0, fw = Mtrue > 0 ? bbox[3] - bbox[2] + 1 : 0;
     mi.lds_frame = (long)(fh + 4 * a.ckt + kSegR) * ((fw + 4 * a.ckt) | 1) <= a.lds_frame_cap;
@@ -2206,8 +2233,12 @@ static int configure(SolveArgs& A, const Layout& L, const sl_tuning& v, LaunchCf
       return SL_ENOIMPL;
     }
   }
-  // FP64 right-hand-side accumulator, reused by the transposed-operator build (2 I + 192 ints)
+  // FP64 right-hand-side accumulator, reused by the transposed-operator build (2 I + 192 ints),
+  // then one conflict tag per node when that fits in LDS
   c->prep_lds = std::max(sizeof(double) * L.I_max, sizeof(int) * (2 * L.I_max + 192));
+  const size_t tagged = 8 * (size_t)L.I_max + 768 + sizeof(int) * (size_t)L.I_max;
+  A.prep_tags = tagged <= 159 * 1024;
+  if (A.prep_tags) c->prep_lds = tagged;
   c->corner_lds = sizeof(double) * (A.n_lambda * A.n_lambda + 12 * A.n_lambda + 16);
   static std::mutex mu;
   std::lock_guard<std::mutex> g(mu);
