@@ -1,0 +1,68 @@
+"""Pins of the oracle's implicit regularisation by iteration count (Sec. 2.4, Sec. 2.6).
+
+* Each CGLS iterate s_k is the least-squares minimiser of ||A s - d|| over the
+  Krylov space K_k(A^T A, A^T d) (the defining property of CG applied to the
+  normal equations), computed here from explicit matrices with an
+  orthonormal Krylov basis.
+* chi^2 of the iterates does not increase and ||s_k|| does not decrease
+  (Hestenes and Stiefel's monotonicity of the CG iterate norm from zero).
+* Run long enough on a tiny full-rank problem, the iterates reach the
+  unregularised least-squares solution (in exact arithmetic after as many
+  iterations as unknowns; in floating point CG needs some more).
+"""
+import numpy as np
+import pytest
+
+from oracle import implicit, mock, solve
+
+
+def _tiny(ns=5, seed=0):
+    nx = ny = 12
+    psf = mock.gaussian_psf(5, 1.2)
+    rng = np.random.default_rng(seed)
+    d = rng.uniform(0, 1, (ny, nx))
+    return solve.Problem(np.array([0.2, 0.7, 0.4, 0.03, 0.2, 0.02, -0.01]), d, 0.1, psf, nx, ny, 0.08, 2, ns, 0.3,
+                         "identity")
+
+
+def test_iterates_minimise_over_krylov_spaces():
+    pb = _tiny()
+    A = pb.dense_F()
+    d = pb.d.reshape(-1)
+    it = implicit.cgls_iterates(pb, 8)
+    AtA = A.T @ A
+    v = A.T @ d
+    basis = []
+    for k in range(1, 9):
+        basis.append(v)
+        v = AtA @ v
+        Q, _ = np.linalg.qr(np.stack(basis, axis=1))
+        c, *_ = np.linalg.lstsq(A @ Q, d, rcond=None)
+        s_k = Q @ c
+        assert np.linalg.norm(it["s"][k - 1] - s_k) <= 1e-7 * np.linalg.norm(s_k), k
+        r = A @ s_k - d
+        assert abs(it["chi2"][k - 1] - (r @ r) / pb.sigma ** 2) <= 1e-9 * it["chi2"][k - 1]
+        assert abs(it["reg"][k - 1] - s_k @ s_k) <= 1e-7 * (s_k @ s_k)
+
+
+def test_monotone_chi2_and_norm():
+    pb = _tiny(ns=7, seed=3)
+    it = implicit.cgls_iterates(pb, 30)
+    assert np.all(np.diff(it["chi2"]) <= 1e-12 * it["chi2"][:-1])
+    assert np.all(np.diff(it["reg"]) >= -1e-12 * it["reg"][1:])
+
+
+def test_full_krylov_space_gives_least_squares():
+    pb = _tiny(ns=4)
+    A = pb.dense_F()
+    assert np.linalg.matrix_rank(A) == pb.I
+    it = implicit.cgls_iterates(pb, 4 * pb.I)
+    s_ls, *_ = np.linalg.lstsq(A, pb.d.reshape(-1), rcond=None)
+    assert np.linalg.norm(it["s"][-1] - s_ls) <= 1e-6 * np.linalg.norm(s_ls)
+
+
+def test_fitness_is_chi2_at_the_corner():
+    pb = _tiny(ns=7, seed=5)
+    f = implicit.implicit_fitness(pb, 25)
+    assert 0 <= f["k_star"] < 25
+    assert f["fitness"] == pytest.approx(pb.chi2(f["s"][f["k_star"]]), rel=1e-12)
