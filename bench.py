@@ -299,6 +299,7 @@ def main():
     plan.close()
     prec = precision_vs_f64(sl, torch, z, grid, w, dev, pop, grids, out, max_ns)
     mc = mc_dof_step(sl, torch, solver, lens_d, ns_d, w, max_ns, M, args.steps)
+    imp = implicit_step(torch, solver, lens_d, ns_d, max_ns, M, args.steps)
     # plain: the same library, one member per call
     plain_value = None
     if not args.no_plain:
@@ -316,6 +317,7 @@ def main():
         "graph_ms_per_step": round(graph_ms, 3),
         "chi2_rel_err_vs_f64": prec,
         "mc_dof": mc,
+        "implicit": imp,
         "roofline": roof,
     }
     if not args.no_cpu_baseline and args.workload == "c3":
@@ -324,6 +326,23 @@ def main():
                out["s_corner"].cpu().numpy(), out["s_off"].cpu().numpy())
         rec["cpu_baseline"] = cpu_baseline(w, z, pop, grids, args.cpu_members, gpu)
     print(json.dumps(rec), flush=True)
+
+
+def implicit_step(torch, solver, lens_d, ns_d, max_ns, M, steps, n_iter=40):
+    """The paper's own fitness (Sec. 2.4, 2.6): 40 unregularised CG iterations per member and the L-curve over
+    the iterates, on the same members; time per step and the corner iterates."""
+    print("[bench] implicit regularisation (40 iterations)", file=sys.stderr, flush=True)
+    out = solver.alloc_result(M * max_ns * max_ns, M, n_iter)
+    solver.solve_implicit(lens_d, ns_d, n_iter, max_ns=max_ns, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        solver.solve_implicit(lens_d, ns_d, n_iter, max_ns=max_ns, out=out)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / steps
+    k = out["k_star"].cpu().numpy()
+    return {"n_iter": n_iter, "ms_per_step": round(ms, 3), "evals_per_s": round(M / ms * 1e3, 2),
+            "corner_iterate_median": float(np.median(k + 1))}
 
 
 def mc_dof_step(sl, torch, solver, lens_d, ns_d, w, max_ns, M, steps):

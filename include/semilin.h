@@ -245,6 +245,26 @@ int sl_solve_semilinear(const sl_problem* pb, const double* lens, const int32_t*
                         sl_result* out, void* stream);
 
 /*
+ * Implicit regularisation by the iteration count (Sec. 2.4, Sec. 2.6, and
+ * the fitness of Sec. 3): no lambda; for every member, n_iter iterations of
+ * CG on the unregularised normal equations A^T A s = A^T d (A = B L) from
+ * s = 0 -- the iterates of CGLS -- and after iteration k (k = 1..n_iter)
+ * chi^2 = ||d - A s_k||^2 / sigma^2 (from the image residual, carried as a
+ * vector) and the zeroth-order measure sum_i s_k,i^2 (whatever pb->reg
+ * says).  The L-curve over the iterates gives k_star (index k - 1 of the
+ * corner iterate) and the member's fitness chi2[m][k_star]; s_corner holds
+ * that iterate.  Arguments and outputs as sl_solve_semilinear with
+ * n_lambda = n_iter: chi2, reg, iters (= k), status are [n_members][n_iter];
+ * workspace from sl_solve_workspace_size(pb, max_ns, n_members, n_iter).
+ * n_iter in [4, SL_MAX_LAMBDA]; opts->tol is not used (the count stops CG),
+ * opts->mc_noise must be NULL.  After a breakdown (A p = 0) the remaining
+ * iterates repeat the last one with status SL_ST_BREAKDOWN.
+ */
+int sl_solve_implicit(const sl_problem* pb, const double* lens, const int32_t* ns, int max_ns,
+                      int n_members, int n_iter, const sl_solve_opts* opt, void* workspace,
+                      size_t workspace_bytes, sl_result* out, void* stream);
+
+/*
  * Autotuner: runs the solve once per kernel variant (after one untimed run
  * of each), timing each with HIP events on `stream`, and records the fastest
  * for this problem signature (dtype, image size, subpixels, PSF size,

@@ -18,6 +18,19 @@ one B^T per iteration), from s = 0:
                    e -= alpha q; g' = A^T e; beta = ||g'||^2 / ||g||^2;
                    p = g' + beta p
 chi^2 of each iterate is computed from the explicit solution, reg = ||s||^2.
+
+Rounding model.  Past the first handful of iterations the sequence is
+sensitive to rounding: CG loses orthogonality while it resolves small
+singular values, so two correct implementations that round differently
+drift apart.  To bound that drift the parity tests run this same routine
+under Monte Carlo arithmetic (Parker, Pierce and Eggert, "Monte Carlo
+arithmetic: how to gamble with floating point and win", 2000): every
+computed quantity x is replaced by x (1 + delta xi) with xi a seeded standard
+normal, and the spread over draws shows how far rounding at relative level
+delta can move each iterate.  `perturb(x, kind)` applies that replacement;
+kind is "A" or "AT" for the two operator outputs, "vec" for the updated
+s, e and p, and "scalar" for alpha and beta.  With perturb=None (the
+default) the routine is the plain algorithm above.
 """
 from __future__ import annotations
 
@@ -27,36 +40,46 @@ from . import lcurve
 from .solve import Problem
 
 
-def cgls_iterates(pb: Problem, n_iter: int):
+def _same(x, kind):
+    return x
+
+
+def cgls_iterates(pb: Problem, n_iter: int, perturb=None):
     """The first n_iter CGLS iterates of the unregularised problem.
 
-    Returns dict(s=(n_iter, I) iterates s_1..s_n, chi2=(n_iter,), reg=(n_iter,)
-    with reg = sum s^2, and the per-iteration alpha, beta).  Stops early (the
-    remaining rows repeat the last iterate) when ||A^T e|| or ||A p|| is zero.
+    Returns dict(s=(n_iter, I) iterates s_1..s_n, chi2=(n_iter,) from the
+    explicit iterate, chi2_e=(n_iter,) from the carried residual e (equal in
+    exact arithmetic), reg=(n_iter,) with reg = sum s^2, and the per-iteration
+    alpha, beta).  Stops early (the remaining rows repeat the last iterate)
+    when ||A^T e|| or ||A p|| is zero.  perturb: see the module docstring.
     """
+    pt = perturb or _same
     I = pb.I
     s = np.zeros(I)
     e = pb.d.astype(np.float64).copy()
-    g = pb.FT(e)
+    g = pt(pb.FT(e), "AT")
     p = g.copy()
     gg = float(g @ g)
     out_s = np.zeros((n_iter, I))
     chi2 = np.zeros(n_iter)
+    chi2_e = np.zeros(n_iter)
     reg = np.zeros(n_iter)
     alphas, betas = [], []
     done = gg == 0.0
+    ee = float((e * e).sum())
     for k in range(n_iter):
         if not done:
-            q = pb.F(p)
+            q = pt(pb.F(p), "A")
             qq = float((q * q).sum())
             if qq > 0.0:
-                alpha = gg / qq
-                s = s + alpha * p
-                e = e - alpha * q
-                g = pb.FT(e)
+                alpha = pt(gg / qq, "scalar")
+                s = pt(s + alpha * p, "vec")
+                e = pt(e - alpha * q, "vec")
+                ee = float((e * e).sum())
+                g = pt(pb.FT(e), "AT")
                 gg_new = float(g @ g)
-                beta = gg_new / gg
-                p = g + beta * p
+                beta = pt(gg_new / gg, "scalar")
+                p = pt(g + beta * p, "vec")
                 gg = gg_new
                 alphas.append(alpha)
                 betas.append(beta)
@@ -65,8 +88,9 @@ def cgls_iterates(pb: Problem, n_iter: int):
                 done = True
         out_s[k] = s
         chi2[k] = pb.chi2(s)
+        chi2_e[k] = ee / pb.sigma ** 2
         reg[k] = float(s @ s)
-    return dict(s=out_s, chi2=chi2, reg=reg, alpha=np.array(alphas), beta=np.array(betas))
+    return dict(s=out_s, chi2=chi2, chi2_e=chi2_e, reg=reg, alpha=np.array(alphas), beta=np.array(betas))
 
 
 def implicit_fitness(pb: Problem, n_iter: int = 40):

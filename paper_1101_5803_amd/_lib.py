@@ -87,6 +87,8 @@ def lib():
         L.sl_solve_semilinear.argtypes = [ctypes.POINTER(Problem), vp, vp, ip, ip,
                                           ctypes.POINTER(ctypes.c_double), ip, ctypes.POINTER(SolveOpts),
                                           vp, ctypes.c_size_t, ctypes.POINTER(Result), vp]
+        L.sl_solve_implicit.argtypes = [ctypes.POINTER(Problem), vp, vp, ip, ip, ip, ctypes.POINTER(SolveOpts), vp,
+                                        ctypes.c_size_t, ctypes.POINTER(Result), vp]
         L.sl_solve_autotune.argtypes = [ctypes.POINTER(Problem), vp, vp, ip, ip, ctypes.POINTER(ctypes.c_double), ip,
                                         ctypes.POINTER(SolveOpts), vp, ctypes.c_size_t, ctypes.POINTER(Result), vp,
                                         ctypes.POINTER(Tuning), ctypes.POINTER(ctypes.c_double)]
@@ -106,7 +108,7 @@ def lib():
         L.sl_mlp_forward_noalloc.argtypes = [vp, vp, ip, vp, vp]
         L.sl_mlp_train_step.argtypes = [vp, vp, vp, vp, vp, ip, ctypes.c_float, ip, vp, vp, vp, vp]
         for name in ("sl_lens_trace", "sl_apply_L", "sl_apply_LT", "sl_apply_LT_ordered", "sl_apply_B", "sl_apply_BT",
-                     "sl_apply_HtH", "sl_solve_semilinear", "sl_lcurve_corner", "sl_mlp_forward", "sl_mlp_forward_noalloc",
+                     "sl_apply_HtH", "sl_solve_semilinear", "sl_solve_implicit", "sl_lcurve_corner", "sl_mlp_forward", "sl_mlp_forward_noalloc",
                      "sl_mlp_train_step", "sl_solve_member_info", "sl_profile_enable", "sl_profile_solve_ms",
                      "sl_solve_autotune", "sl_plan_create", "sl_plan_launch", "sl_plan_destroy"):
             getattr(L, name).restype = ctypes.c_int

@@ -77,13 +77,14 @@ struct alignas(16) Consts {
   int pqcount[8];
   int sep;          // PSF is rank-1
   int mchead;       // next member of the Monte Carlo degrees-of-freedom pass
-  int pad0[2];
+  int imhead;       // next member of the implicit-regularisation solve
+  int pad0;
   double sum_d2;
   double sum_n2;    // sum of the squared Monte Carlo draws
 };
 
 struct Layout {
-  size_t consts, lam, taps_d, taps_f, minfo, queues, pqueues, pix, cell, fx, fy, b, bh, s_all, gframe, gz, rbuf, mcbuf,
+  size_t consts, lam, taps_d, taps_f, minfo, queues, pqueues, pix, cell, fx, fy, b, bh, s_all, gframe, gz, rbuf, mcbuf, ibuf,
       lt_ptr, lt_perm,
       lt_ent,
       total;
@@ -164,12 +165,14 @@ struct SolveArgs {
   int force_csr;    // variant: transposed operator as CSR rows
   int force_direct; // variant: direct K x K blur for a separable PSF
   int prep_tags;    // k_prep has one LDS int per node after its 8 I_max + 768 bytes (conflict tags)
+  int implicit;     // implicit regularisation: n_lambda unregularised CG iterations (k_implicit)
   int plain_cg;     // variant: no spectral preconditioner
   // Monte Carlo degrees of freedom (Sec. 2.5), when mcn is not NULL
   const double* mcn; // [ny*nx] Gaussian draws bhat
   double* dofv;      // [n_members] result: bhat^T (bhat - A xhat) at the corner
   double* bh;        // [member][I_max] A^T bhat (FP64)
   void* mcbuf;       // [n_wg][5][I_max] r, xhat, rhat, phat, saved p of the pass
+  void* ibuf;        // [n_wg][J] image residual e = d - A s of the implicit-regularisation solve
 };
 
 // ------------------------------------------------------------------ block scan
@@ -340,6 +343,7 @@ __global__ void __launch_bounds__(1024) k_setup(SolveArgs a, LamList lams) {
     a.consts->sum_d2 = acc;
     a.consts->sum_n2 = accn;
     a.consts->mchead = 0;
+    a.consts->imhead = 0;
   }
 }
 
@@ -1353,169 +1357,185 @@ struct OpView {
   T inv_n2, lamT;
 };
 
-// Q = (L^T B^T B L + lambda H^T H) P for one item, all threads of the block:
-// L as a gather into the frame (zero on entry), B^T B in place (banded passes
-// for a rank-1 PSF, else the direct K x K form through Z), then L^T as a
-// gather over the transposed operator (fixed order, no atomics) fused with
-// lambda H^T H.  On return the frame holds B^T B L P; the caller zeroes it
-// again after a barrier.  Returns this thread's part of <P, Q>.
-template <typename T, int CKT, int NT>
-__device__ __forceinline__ double apply_normal(const OpView<T>& o, const T* __restrict__ P, T* __restrict__ Q) {
-  const int tid = threadIdx.x;
+// y = L p into the frame: every mapped pixel is written once (assignment, so
+// the frame outside the mapped pixels keeps whatever it held, zero unless a
+// banded pass wrote it).  Two pixels per thread and step so that their table
+// loads are in flight together.
+template <typename T, int NT>
+__device__ __forceinline__ void gather_L(const OpView<T>& o, const T* __restrict__ P) {
   const int32_t* pix = o.pix;
-  const int32_t* cellp = o.cellp;
-  const T* fxp = o.fxp;
-  const T* fyp = o.fyp;
-  T* const F = o.F;
   T* const F0 = o.F0;
-  T* const Z = o.Z;
-  const T* taps = o.taps;
-  const int32_t* lt_rp = o.lt_rp;
-  const LtEntry<T>* lt_e = o.lt_e;
-  const int32_t* perm = o.perm;
-  const int ns = o.ns, I = o.I, M = o.M, r0 = o.r0, c0 = o.c0, h = o.h, w = o.w, pitch = o.pitch, fo = o.fo;
-  const int n2 = o.n2, nx = o.nx, ny = o.ny, K = o.K, ck = o.ck, sell = o.sell;
-  const int Dr0 = o.Dr0, Dc0 = o.Dc0, Dh = o.Dh, Dw = o.Dw;
-  const bool sep = o.sep, ident = o.ident;
-  const T inv_n2 = o.inv_n2, lamT = o.lamT;
-  const TapIdx ti(K);
-  (void)ny;
-  // y = L p into the frame (P holds p, the frame is zero); two pixels per
-  // thread and step so that their table loads are in flight together
-  for (int t = tid; t < M; t += 2 * NT) {
+  const int M = o.M, ns = o.ns, n2 = o.n2, pitch = o.pitch, fo = o.fo;
+  const T inv_n2 = o.inv_n2;
+  for (int t = threadIdx.x; t < M; t += 2 * NT) {
     const int t2 = t + NT;
     const int rc = pix[t];
     const int rc2 = t2 < M ? pix[t2] : -1;
-    const T v1 = pixel_gather(P, ns, n2, t, cellp, fxp, fyp);
-    const T v2 = t2 < M ? pixel_gather(P, ns, n2, t2, cellp, fxp, fyp) : (T)0;
+    const T v1 = pixel_gather(P, ns, n2, t, o.cellp, o.fxp, o.fyp);
+    const T v2 = t2 < M ? pixel_gather(P, ns, n2, t2, o.cellp, o.fxp, o.fyp) : (T)0;
     if (rc >= 0) F0[(rc >> 16) * pitch + (rc & 0xFFFF) + fo] = v1 * inv_n2;
     if (rc2 >= 0) F0[(rc2 >> 16) * pitch + (rc2 & 0xFFFF) + fo] = v2 * inv_n2;
   }
-  __syncthreads();
-  if (sep) {   // sep comes from a scalar load: uniform
-    // w = B^T B y: banded pass along rows then along columns, in place
-    banded_pass<T, CKT, true>(F0, pitch, h, w, c0, nx, ck, taps + ti.ax, taps + ti.elx, taps + ti.erx);
-    __syncthreads();
-    banded_pass<T, CKT, false>(F0, pitch, w, h, r0, ny, ck, taps + ti.ay, taps + ti.ely, taps + ti.ery);
-    __syncthreads();
-  } else {
-    // z = B y over the dilated region into global Z
-    for (int e = tid; e < Dh * Dw; e += NT) {
-      const int rr_ = Dr0 + e / Dw, cc_ = Dc0 + e % Dw;
-      T acc = 0;
-      if (ck <= CKT) {
-        // every tap of an output in the dilated region lands in the bounding
-        // box or its zero halo (2 CKT >= 2 ck on each side): no bounds tests
-        const T* yrow = F0 + (rr_ + ck - r0) * pitch + (cc_ + ck - c0);
-        const T* tp = taps + ti.psf;
-        for (int aa = 0; aa < K; ++aa) {
-          const T* y = yrow - aa * pitch;
-          for (int bb = 0; bb < K; ++bb) acc += tp[aa * K + bb] * y[-bb];
-        }
-      } else {   // PSFs wider than the widest compiled window: the halo is narrower than ck
-        for (int aa = 0; aa < K; ++aa) {
-          const int yr = rr_ - aa + ck - r0;
-          if (yr < 0 || yr >= h) continue;
-          for (int bb = 0; bb < K; ++bb) {
-            const int yc = cc_ - bb + ck - c0;
-            if (yc < 0 || yc >= w) continue;
-            acc += taps[ti.psf + aa * K + bb] * F0[yr * pitch + yc];
-          }
-        }
-      }
-      Z[e] = acc;
-    }
-    __syncthreads();
-    // w = B^T z at the mapped pixels, back into the frame
-    for (int t = tid; t < M; t += NT) {
-      if (pix[t] < 0) continue;
-      const int rr_ = pix[t] >> 16, cc_ = pix[t] & 0xFFFF;
-      T acc = 0;
+}
+
+// z = B y over the dilated box (Dh x Dw, row-major) from the frame, whose
+// entries off the mapped pixels are zero.  Returns this thread's part of
+// ||z||^2.
+template <typename T, int CKT, int NT>
+__device__ __forceinline__ double blur_box(const OpView<T>& o, T* __restrict__ Z) {
+  const T* const F0 = o.F0;
+  const T* taps = o.taps;
+  const TapIdx ti(o.K);
+  const int K = o.K, ck = o.ck, r0 = o.r0, c0 = o.c0, h = o.h, w = o.w, pitch = o.pitch;
+  const int Dr0 = o.Dr0, Dc0 = o.Dc0, Dh = o.Dh, Dw = o.Dw;
+  double zz = 0.0;
+  for (int e = threadIdx.x; e < Dh * Dw; e += NT) {
+    const int rr_ = Dr0 + e / Dw, cc_ = Dc0 + e % Dw;
+    T acc = 0;
+    if (ck <= CKT) {
+      // every tap of an output in the dilated region lands in the bounding
+      // box or its zero halo (2 CKT >= 2 ck on each side): no bounds tests
+      const T* yrow = F0 + (rr_ + ck - r0) * pitch + (cc_ + ck - c0);
+      const T* tp = taps + ti.psf;
       for (int aa = 0; aa < K; ++aa) {
-        const int zr = rr_ + aa - ck - Dr0;
-        if (zr < 0 || zr >= Dh) continue;
+        const T* y = yrow - aa * pitch;
+        for (int bb = 0; bb < K; ++bb) acc += tp[aa * K + bb] * y[-bb];
+      }
+    } else {   // PSFs wider than the widest compiled window: the halo is narrower than ck
+      for (int aa = 0; aa < K; ++aa) {
+        const int yr = rr_ - aa + ck - r0;
+        if (yr < 0 || yr >= h) continue;
         for (int bb = 0; bb < K; ++bb) {
-          const int zc = cc_ + bb - ck - Dc0;
-          if (zc < 0 || zc >= Dw) continue;
-          acc += taps[ti.psf + aa * K + bb] * Z[zr * Dw + zc];
+          const int yc = cc_ - bb + ck - c0;
+          if (yc < 0 || yc >= w) continue;
+          acc += taps[ti.psf + aa * K + bb] * F0[yr * pitch + yc];
         }
       }
-      F0[rr_ * pitch + cc_ + fo] = acc;
     }
-    __syncthreads();
+    Z[e] = acc;
+    zz += (double)acc * (double)acc;
   }
-  // q = L^T w + lambda H^T H p gathered per node from the transposed operator
-  // (no atomics, fixed order), stored in Q; <p, q>
+  return zz;
+}
+
+// w = B^T z at the mapped pixels, into the frame; z lives on the dilated box.
+template <typename T, int NT>
+__device__ __forceinline__ void blur_T_mapped(const OpView<T>& o, const T* __restrict__ Z) {
+  const int32_t* pix = o.pix;
+  T* const F0 = o.F0;
+  const T* taps = o.taps;
+  const TapIdx ti(o.K);
+  const int K = o.K, ck = o.ck, pitch = o.pitch, fo = o.fo, M = o.M;
+  const int Dr0 = o.Dr0, Dc0 = o.Dc0, Dh = o.Dh, Dw = o.Dw;
+  for (int t = threadIdx.x; t < M; t += NT) {
+    if (pix[t] < 0) continue;
+    const int rr_ = pix[t] >> 16, cc_ = pix[t] & 0xFFFF;
+    T acc = 0;
+    for (int aa = 0; aa < K; ++aa) {
+      const int zr = rr_ + aa - ck - Dr0;
+      if (zr < 0 || zr >= Dh) continue;
+      for (int bb = 0; bb < K; ++bb) {
+        const int zc = cc_ + bb - ck - Dc0;
+        if (zc < 0 || zc >= Dw) continue;
+        acc += taps[ti.psf + aa * K + bb] * Z[zr * Dw + zc];
+      }
+    }
+    F0[rr_ * pitch + cc_ + fo] = acc;
+  }
+}
+
+// q = L^T w + lambda H^T H p gathered per node from the transposed operator
+// (no atomics, fixed order), stored in Q.  Returns this thread's part of
+// <p, q>.  With GRAD, q = L^T w alone (no P term) and the return value is
+// this thread's part of ||q||^2.
+template <typename T, int NT, bool GRAD>
+__device__ __forceinline__ double gather_LT(const OpView<T>& o, const T* __restrict__ P, T* __restrict__ Q) {
+  const int tid = threadIdx.x;
+  const T* const F = o.F;
+  const int32_t* lt_rp = o.lt_rp;
+  const LtEntry<T>* lt_e = o.lt_e;
+  const int32_t* perm = o.perm;
+  const int ns = o.ns, I = o.I, sell = o.sell;
+  const bool ident = o.ident;
+  const T lamT = o.lamT;
   double pq = 0.0;
-  {
-    if (sell) {
-      // sliced-ELL in length-sorted node order: wave w takes slices w, w + 16, ...;
-      // the slice bounds are wave-uniform (scalar loads) and every lane of a
-      // slice has `len` entries (padding reads the zero halo), eight in flight
-      const int wid = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
-      const int nslices = (I + 63) >> 6;
-      const int lt_E = lt_rp[nslices];   // sliced-ELL entries of the member
-      for (int sl = wid; sl < nslices; sl += NT / 64) {
-        const int idx = sl * 64 + lane;
-        const int b0 = lt_rp[sl];
-        const int len = (lt_rp[sl + 1] - b0) >> 6;
-        const int pk = idx < I ? perm[idx] : 0;
-        T acc = 0;
-        if (sizeof(T) == 4 && sell == 2) {
-          // paired entries (even `len`, entries summed in the same order)
-          const unsigned* op = reinterpret_cast<const unsigned*>(lt_e) + (b0 >> 1) + lane;
-          const float2* wq = reinterpret_cast<const float2*>(reinterpret_cast<const unsigned*>(lt_e) + (lt_E >> 1)) +
-                             (b0 >> 1) + lane;
-          const int npair = len >> 1;
-          int j = 0;
-          for (; j + 7 < npair; j += 8) {   // sixteen entries in flight
-            unsigned o[8];
-            float2 wv[8];
+  if (sell) {
+    // sliced-ELL in length-sorted node order: wave w takes slices w, w + 16, ...;
+    // the slice bounds are wave-uniform (scalar loads) and every lane of a
+    // slice has `len` entries (padding reads the zero halo), eight in flight
+    const int wid = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+    const int nslices = (I + 63) >> 6;
+    const int lt_E = lt_rp[nslices];   // sliced-ELL entries of the member
+    for (int sl = wid; sl < nslices; sl += NT / 64) {
+      const int idx = sl * 64 + lane;
+      const int b0 = lt_rp[sl];
+      const int len = (lt_rp[sl + 1] - b0) >> 6;
+      const int pk = idx < I ? perm[idx] : 0;
+      T acc = 0;
+      if (sizeof(T) == 4 && sell == 2) {
+        // paired entries (even `len`, entries summed in the same order)
+        const unsigned* op = reinterpret_cast<const unsigned*>(lt_e) + (b0 >> 1) + lane;
+        const float2* wq = reinterpret_cast<const float2*>(reinterpret_cast<const unsigned*>(lt_e) + (lt_E >> 1)) +
+                           (b0 >> 1) + lane;
+        const int npair = len >> 1;
+        int j = 0;
+        for (; j + 7 < npair; j += 8) {   // sixteen entries in flight
+          unsigned ov[8];
+          float2 wv[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-              o[u] = op[64L * (j + u)];
-              wv[u] = wq[64L * (j + u)];
-            }
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-              acc += (T)wv[u].x * F[o[u] & 0xFFFFu];
-              acc += (T)wv[u].y * F[o[u] >> 16];
-            }
+          for (int u = 0; u < 8; ++u) {
+            ov[u] = op[64L * (j + u)];
+            wv[u] = wq[64L * (j + u)];
           }
-          for (; j < npair; ++j) {
-            const unsigned o0 = op[64L * j];
-            const float2 w0 = wq[64L * j];
-            acc += (T)w0.x * F[o0 & 0xFFFFu];
-            acc += (T)w0.y * F[o0 >> 16];
-          }
-        } else {
-          const LtEntry<T>* ep = lt_e + b0 + lane;
-          int j = 0;
-          for (; j + 7 < len; j += 8) {
-            LtEntry<T> x[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) x[u] = ep[64L * (j + u)];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) acc += x[u].w * F[x[u].off];
-          }
-          for (; j < len; ++j) {
-            const LtEntry<T> x0 = ep[64L * j];
-            acc += x0.w * F[x0.off];
+          for (int u = 0; u < 8; ++u) {
+            acc += (T)wv[u].x * F[ov[u] & 0xFFFFu];
+            acc += (T)wv[u].y * F[ov[u] >> 16];
           }
         }
-        if (idx < I) {
-          const int rn_ = pk >> 16, cn_ = pk & 0xFFFF, i = rn_ * ns + cn_;
+        for (; j < npair; ++j) {
+          const unsigned o0 = op[64L * j];
+          const float2 w0 = wq[64L * j];
+          acc += (T)w0.x * F[o0 & 0xFFFFu];
+          acc += (T)w0.y * F[o0 >> 16];
+        }
+      } else {
+        const LtEntry<T>* ep = lt_e + b0 + lane;
+        int j = 0;
+        for (; j + 7 < len; j += 8) {
+          LtEntry<T> x[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) x[u] = ep[64L * (j + u)];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) acc += x[u].w * F[x[u].off];
+        }
+        for (; j < len; ++j) {
+          const LtEntry<T> x0 = ep[64L * j];
+          acc += x0.w * F[x0.off];
+        }
+      }
+      if (idx < I) {
+        const int rn_ = pk >> 16, cn_ = pk & 0xFFFF, i = rn_ * ns + cn_;
+        if (GRAD) {
+          Q[i] = acc;
+          pq += (double)acc * (double)acc;
+        } else {
           const T pv = P[i];
           const T qv = acc + lamT * (ident ? pv : hth_node(P, ns, rn_, cn_));
           Q[i] = qv;
           pq += (double)pv * (double)qv;
         }
       }
-    } else {
-      for (int i = tid; i < I; i += NT) {
-        T acc = 0;
-        const int e0 = lt_rp[i], e1 = lt_rp[i + 1];
-        for (int e = e0; e < e1; ++e) acc += lt_e[e].w * F[lt_e[e].off];
+    }
+  } else {
+    for (int i = tid; i < I; i += NT) {
+      T acc = 0;
+      const int e0 = lt_rp[i], e1 = lt_rp[i + 1];
+      for (int e = e0; e < e1; ++e) acc += lt_e[e].w * F[lt_e[e].off];
+      if (GRAD) {
+        Q[i] = acc;
+        pq += (double)acc * (double)acc;
+      } else {
         const int rn_ = i / ns, cn_ = i - rn_ * ns;
         const T pv = P[i];
         const T qv = acc + lamT * (ident ? pv : hth_node(P, ns, rn_, cn_));
@@ -1525,6 +1545,34 @@ __device__ __forceinline__ double apply_normal(const OpView<T>& o, const T* __re
     }
   }
   return pq;
+}
+
+// Q = (L^T B^T B L + lambda H^T H) P for one item, all threads of the block:
+// L as a gather into the frame (zero on entry), B^T B in place (banded passes
+// for a rank-1 PSF, else the direct K x K form through Z), then L^T as a
+// gather over the transposed operator (fixed order, no atomics) fused with
+// lambda H^T H.  On return the frame holds B^T B L P; the caller zeroes it
+// again after a barrier.  Returns this thread's part of <P, Q>.
+template <typename T, int CKT, int NT>
+__device__ __forceinline__ double apply_normal(const OpView<T>& o, const T* __restrict__ P, T* __restrict__ Q) {
+  gather_L<T, NT>(o, P);
+  __syncthreads();
+  if (o.sep) {   // sep comes from a scalar load: uniform
+    // w = B^T B y: banded pass along rows then along columns, in place
+    const TapIdx ti(o.K);
+    banded_pass<T, CKT, true>(o.F0, o.pitch, o.h, o.w, o.c0, o.nx, o.ck, o.taps + ti.ax, o.taps + ti.elx,
+                              o.taps + ti.erx);
+    __syncthreads();
+    banded_pass<T, CKT, false>(o.F0, o.pitch, o.w, o.h, o.r0, o.ny, o.ck, o.taps + ti.ay, o.taps + ti.ely,
+                               o.taps + ti.ery);
+    __syncthreads();
+  } else {
+    blur_box<T, CKT, NT>(o, o.Z);      // z = B y over the dilated region into global Z
+    __syncthreads();
+    blur_T_mapped<T, NT>(o, o.Z);      // w = B^T z at the mapped pixels, back into the frame
+    __syncthreads();
+  }
+  return gather_LT<T, NT, false>(o, P, Q);
 }
 
 template <typename T, int CKT, bool LDSF, bool PC>
@@ -1769,8 +1817,8 @@ __global__ void __launch_bounds__(kNTof<T>) k_solve(SolveArgs a) {
 // ------------------------------------------------------------------ k_mcdof
 // Next member of the Monte Carlo pass for this block (thread 0 takes it, the
 // value is broadcast through LDS and made scalar), as fetch_item does.
-__device__ __forceinline__ int fetch_member(const SolveArgs& a, int* sh_m) {
-  if (threadIdx.x == 0) *sh_m = atomicAdd(&a.consts->mchead, 1);
+__device__ __forceinline__ int fetch_counter(int* counter, int* sh_m) {
+  if (threadIdx.x == 0) *sh_m = atomicAdd(counter, 1);
   __syncthreads();
   const int m = __builtin_amdgcn_readfirstlane(*sh_m);
   __syncthreads();
@@ -1927,7 +1975,8 @@ template <typename T, int CKT>
 __global__ void __launch_bounds__(kNTof<T>) k_mcdof(SolveArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int sh_m;
-  for (int m = fetch_member(a, &sh_m); m < a.n_members; m = fetch_member(a, &sh_m)) {
+  for (int m = fetch_counter(&a.consts->mchead, &sh_m); m < a.n_members;
+       m = fetch_counter(&a.consts->mchead, &sh_m)) {
     const MemberInfo mi = a.minfo[m];
     const int status = __builtin_amdgcn_readfirstlane(mi.status);
     if (status != SL_ST_OK) {
@@ -1939,6 +1988,155 @@ __global__ void __launch_bounds__(kNTof<T>) k_mcdof(SolveArgs a) {
       else
         run_mc_item<T, CKT, false>(a, mi, m, kl, smem);
     }
+  }
+}
+
+// ------------------------------------------------------------------ k_implicit
+// Implicit regularisation by the iteration count (Sec. 2.4, Sec. 2.6): CGLS
+// on min ||A s - d|| (A = B L) from s = 0 with no lambda, for exactly
+// n_lambda iterations.  Each iteration applies A once (L gather, then B over
+// the dilated bounding box) and A^T once (B^T at the mapped pixels, then the
+// L^T gather), as CGLS does: q = A p, alpha = ||g||^2 / ||q||^2,
+// s += alpha p, e -= alpha q, g = A^T e, beta = ||g'||^2 / ||g||^2,
+// p = g + beta p, with the image residual e = d - A s carried on the dilated
+// box (pixels outside it keep e = d; A^T e reads only the box).  After
+// iteration k the iterate goes to solution slot k of the member, with
+// chi^2 = ||e||^2 / sigma^2 and the zeroth-order measure ||s_k||^2 (Sec. 2.6).
+// g_0 = A^T d is the member's fixed-order right-hand side.  After a
+// breakdown (A p = 0) the remaining slots repeat the last iterate.
+template <typename T, int CKT, bool LDSF>
+__device__ __forceinline__ void run_implicit_item(const SolveArgs& a, const MemberInfo& mi, int m,
+                                                  unsigned char* smem) {
+  constexpr int NT = kNTof<T>;
+  const int tid = threadIdx.x;
+  const long slot = (long)blockIdx.x;
+  const int K_it = a.n_lambda;
+  const int ns = mi.ns, I = mi.I, M = mi.M, r0 = mi.r0, c0 = mi.c0;
+  const int h = mi.r1 - mi.r0 + 1, w = mi.c1 - mi.c0 + 1;
+  constexpr int HALO = 2 * CKT;
+  const int pitch = (w + 2 * HALO) | 1;
+  const int frame_elems = (h + 2 * HALO + kSegR) * pitch;
+  const int J = a.nx * a.ny, n2 = a.n2, nx = a.nx, ny = a.ny, K = a.K, ck = a.ck;
+  T* P = reinterpret_cast<T*>(smem);                      // search direction p
+  T* G = reinterpret_cast<T*>(smem + a.q_off);            // gradient g = A^T e
+  double* red = reinterpret_cast<double*>(smem + a.red_off);
+  T* F = LDSF ? reinterpret_cast<T*>(smem + a.frame_off) : reinterpret_cast<T*>(a.gframe) + slot * a.gframe_elems;
+  T* const F0 = F + HALO * pitch + HALO;
+  const int Dr0 = max(mi.r0 - ck, 0), Dr1 = min(mi.r1 + ck, ny - 1);
+  const int Dc0 = max(mi.c0 - ck, 0), Dc1 = min(mi.c1 + ck, nx - 1);
+  const int Dh = Dr1 - Dr0 + 1, Dw = Dc1 - Dc0 + 1;
+  T* __restrict__ Zq = reinterpret_cast<T*>(a.gz) + slot * J;     // q = A p on the dilated box
+  T* __restrict__ E = reinterpret_cast<T*>(a.ibuf) + slot * J;    // e on the dilated box
+  const OpView<T> ov{a.pix_list + (long)m * a.slot_cap, a.cell + (long)m * a.slot_cap * n2,
+                     reinterpret_cast<const T*>(a.fx) + (long)m * a.slot_cap * n2,
+                     reinterpret_cast<const T*>(a.fy) + (long)m * a.slot_cap * n2, F, F0, Zq,
+                     reinterpret_cast<const T*>(a.taps_t), a.lt_ptr + (long)m * (a.I_max + 65),
+                     reinterpret_cast<const LtEntry<T>*>(a.lt_ent) + (long)m * a.lt_cap, a.lt_perm + (long)m * a.I_max,
+                     ns, I, M, r0, c0, h, w, pitch, -r0 * pitch - c0, n2, nx, ny, K, ck,
+                     __builtin_amdgcn_readfirstlane(mi.sell), Dr0, Dc0, Dh, Dw,
+                     a.consts->sep != 0, true, (T)1 / (T)n2, (T)0};
+  // The frame is written only at the mapped pixels from here on (L p, then
+  // B^T e over the same pixels), so its halo and the unmapped entries stay zero.
+  for (int e = tid; e < frame_elems; e += NT) F[e] = (T)0;
+  const double* bm = a.b + (long)m * a.I_max;
+  double gg = 0.0, din = 0.0;
+  for (int i = tid; i < I; i += NT) {
+    const T bv = (T)bm[i];
+    P[i] = bv;
+    gg += (double)bv * (double)bv;
+  }
+  for (int e = tid; e < Dh * Dw; e += NT) {
+    const double dv = a.d[(Dr0 + e / Dw) * nx + Dc0 + e % Dw];
+    E[e] = (T)dv;
+    din += dv * dv;
+  }
+  block_sum2(gg, din, red + 32);
+  const double d_out = a.consts->sum_d2 - din;   // sum of d^2 outside the dilated box
+  const double inv_s2 = 1.0 / (a.sigma * a.sigma);
+  int k = 0, st = SL_ST_OK;
+  double chi2_last = a.consts->sum_d2 * inv_s2, reg_last = 0.0;
+  for (; k < K_it; ++k) {
+    if (__builtin_amdgcn_readfirstlane((int)(gg <= 0.0))) break;
+    gather_L<T, NT>(ov, P);                               // frame = L p
+    __syncthreads();
+    double qq = blur_box<T, CKT, NT>(ov, Zq);             // q = B L p
+    qq = block_sum1<NT / kWave>(qq, red, 0);
+    if (__builtin_amdgcn_readfirstlane((int)!(qq > 0.0))) {
+      st = SL_ST_BREAKDOWN;
+      break;
+    }
+    const T alT = (T)(gg / qq);
+    const T* s_prev = reinterpret_cast<const T*>(a.s_all) + ((long)m * K_it + (k > 0 ? k - 1 : 0)) * a.I_max;
+    T* s_k = reinterpret_cast<T*>(a.s_all) + ((long)m * K_it + k) * a.I_max;
+    double reg = 0.0, ee = 0.0;
+    for (int i = tid; i < I; i += NT) {
+      const T sv = (k ? s_prev[i] : (T)0) + alT * P[i];
+      s_k[i] = sv;
+      reg += (double)sv * (double)sv;
+    }
+    for (int e = tid; e < Dh * Dw; e += NT) {
+      const T ev = E[e] - alT * Zq[e];
+      E[e] = ev;
+      ee += (double)ev * (double)ev;
+    }
+    block_sum2(reg, ee, red + 32);                        // also orders the E writes before B^T reads them
+    chi2_last = (d_out + ee) * inv_s2;
+    reg_last = reg;
+    {   // every thread stores the same block-reduced values: no lane-predicated code in the loop
+      const long o = (long)m * K_it + k;
+      a.chi2[o] = chi2_last;
+      a.regv[o] = reg_last;
+      a.iters[o] = k + 1;
+      a.status[o] = SL_ST_OK;
+    }
+    blur_T_mapped<T, NT>(ov, E);                          // frame = B^T e at the mapped pixels
+    __syncthreads();
+    double gn = gather_LT<T, NT, true>(ov, P, G);         // g = L^T B^T e
+    gn = block_sum1<NT / kWave>(gn, red, 1);
+    const T beta = (T)(gn / gg);
+    for (int i = tid; i < I; i += NT) P[i] = G[i] + beta * P[i];
+    gg = gn;
+    __syncthreads();
+  }
+  // slots past an early stop repeat the last iterate (s = 0 when there is none)
+  for (int kk = k; kk < K_it; ++kk) {
+    const T* s_prev = reinterpret_cast<const T*>(a.s_all) + ((long)m * K_it + (kk > 0 ? kk - 1 : 0)) * a.I_max;
+    T* s_k = reinterpret_cast<T*>(a.s_all) + ((long)m * K_it + kk) * a.I_max;
+    for (int i = tid; i < I; i += NT) s_k[i] = kk ? s_prev[i] : (T)0;
+    const long o = (long)m * K_it + kk;
+    a.chi2[o] = chi2_last;
+    a.regv[o] = reg_last;
+    a.iters[o] = k;
+    a.status[o] = st;
+    __syncthreads();
+  }
+}
+
+// One member per item; members without a solve get the trivial result.
+template <typename T, int CKT>
+__global__ void __launch_bounds__(kNTof<T>) k_implicit(SolveArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int sh_m;
+  for (int m = fetch_counter(&a.consts->imhead, &sh_m); m < a.n_members; m = fetch_counter(&a.consts->imhead, &sh_m)) {
+    const MemberInfo mi = a.minfo[m];
+    const int status = __builtin_amdgcn_readfirstlane(mi.status);
+    if (status != SL_ST_OK) {   // same values from every thread, as trivial_item writes them
+      const double c2 = status == SL_ST_INVALID ? NAN : a.consts->sum_d2 / (a.sigma * a.sigma);
+      for (int k = 0; k < a.n_lambda; ++k) {
+        T* s_dst = reinterpret_cast<T*>(a.s_all) + ((long)m * a.n_lambda + k) * a.I_max;
+        for (int i = threadIdx.x; i < mi.I; i += kNTof<T>) s_dst[i] = (T)0;
+        const long o = (long)m * a.n_lambda + k;
+        a.chi2[o] = c2;
+        a.regv[o] = status == SL_ST_INVALID ? NAN : 0.0;
+        a.iters[o] = 0;
+        a.status[o] = status;
+      }
+    } else if (__builtin_amdgcn_readfirstlane(mi.lds_frame)) {
+      run_implicit_item<T, CKT, true>(a, mi, m, smem);
+    } else {
+      run_implicit_item<T, CKT, false>(a, mi, m, smem);
+    }
+    __syncthreads();
   }
 }
 
@@ -2066,6 +2264,7 @@ static Layout make_layout(const sl_problem* pb, int max_ns, int M, int NL, int n
   L.gz = take(sz * 2 * (size_t)n_wg * L.J);          // plain | preconditioned launch
   L.rbuf = take(sz * 2 * (size_t)n_wg * L.I_max);
   L.mcbuf = take(sz * 5 * (size_t)n_wg * L.I_max);
+  L.ibuf = take(sz * (size_t)n_wg * L.J);   // image residual of the implicit-regularisation solve
   L.lt_ptr = take(sizeof(int32_t) * (size_t)M * (L.I_max + 65));
   L.lt_perm = take(sizeof(int32_t) * (size_t)M * L.I_max);
   L.lt_cap = 8LL * L.n2 * L.slot_cap;   // twice the unpadded bound: room for slice padding
@@ -2139,6 +2338,27 @@ static SolveKernel pick_mc_kernel(int ckt) {
   return nullptr;
 }
 
+// The implicit-regularisation kernel of the same bulk type and window as the solve.
+template <typename T>
+static SolveKernel pick_implicit_kernel(int ckt) {
+  if (sizeof(T) == 4) {
+    switch (ckt) {
+      case 2: return k_implicit<float, 2>;
+      case 4: return k_implicit<float, 4>;
+      case 7: return k_implicit<float, 7>;
+      case 10: return k_implicit<float, 10>;
+      case 16: return k_implicit<float, 16>;
+    }
+  } else {
+    switch (ckt) {
+      case 2: return k_implicit<double, 2>;
+      case 7: return k_implicit<double, 7>;
+      case 10: return k_implicit<double, 10>;
+    }
+  }
+  return nullptr;
+}
+
 static SolveKernel pick_kernel_d(int ck, bool wide, int* ckt) {
   static const int sizes[] = {2, 7, 10};
   static const SolveKernel ks[] = {k_solve<double, 2, false>, k_solve<double, 7, false>, k_solve<double, 10, false>};
@@ -2186,6 +2406,7 @@ static int side_stream(SideStream** out) {
 }
 
 struct LaunchCfg {
+  SolveKernel kim = nullptr;   // implicit-regularisation solve (replaces k_split / k_solve)
   SolveKernel ks = nullptr;
   SolveKernel kpc = nullptr;   // preconditioned kernel, when some items may take it
   SolveKernel kmc = nullptr;   // Monte Carlo degrees-of-freedom pass, when requested
@@ -2221,11 +2442,19 @@ static int configure(SolveArgs& A, const Layout& L, const sl_tuning& v, LaunchCf
   SL_REQUIRE(lds > fixed + 64 * sz, "source grid too large for LDS");
   A.lds_frame_cap = (int)((lds - fixed) / sz);
   c->ks = ks;
-  if (sizeof(T) == 4 && A.reg == SL_H_CURVATURE && !A.plain_cg) {
+  if (sizeof(T) == 4 && A.reg == SL_H_CURVATURE && !A.plain_cg && !A.implicit) {
     int ckt2 = 0;
     c->kpc = pick_kernel_f(A.ck, v.wide_window != 0, &ckt2, true);
   }
   c->lds = lds;
+  if (A.implicit) {
+    c->kim = pick_implicit_kernel<T>(ckt);
+    c->kpc = nullptr;
+    if (!c->kim) {
+      set_error("no implicit-regularisation kernel for window %d", ckt);
+      return SL_ENOIMPL;
+    }
+  }
   if (A.mcn) {
     c->kmc = pick_mc_kernel<T>(ckt);
     if (!c->kmc) {
@@ -2247,6 +2476,8 @@ static int configure(SolveArgs& A, const Layout& L, const sl_tuning& v, LaunchCf
     SL_HIP(hipFuncSetAttribute((const void*)c->kpc, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   if (c->kmc)
     SL_HIP(hipFuncSetAttribute((const void*)c->kmc, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  if (c->kim)
+    SL_HIP(hipFuncSetAttribute((const void*)c->kim, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   SL_HIP(hipFuncSetAttribute((const void*)k_prep<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)c->prep_lds));
   return SL_OK;
@@ -2276,7 +2507,10 @@ static int enqueue(const SolveArgs& A, const LamList& lams, const Layout& L, con
       SL_HIP(hipEventRecord(e0, st));
     }
   }
-  if (c.kpc) {
+  if (c.kim) {
+    hipLaunchKernelGGL(c.kim, dim3(L.n_wg), dim3(kNTof<T>), c.lds, st, A);
+    if (int e = check_launch("k_implicit")) return e;
+  } else if (c.kpc) {
     hipLaunchKernelGGL(k_split<T>, dim3(1), dim3(64), 0, st, A);
     if (int e = check_launch("k_split")) return e;
     // The plain launch first on st, the preconditioned one on the side
@@ -2414,6 +2648,7 @@ static int prepare(const sl_problem* pb, const double* lens, const int32_t* ns, 
   A.b = (double*)(ws + L.b);
   A.bh = (double*)(ws + L.bh);
   A.mcbuf = ws + L.mcbuf;
+  A.ibuf = ws + L.ibuf;
   A.mcn = opt->mc_noise;
   A.dofv = opt->mc_noise ? out->dof : nullptr;
   A.s_all = ws + L.s_all;
@@ -2451,6 +2686,27 @@ int sl_solve_semilinear(const sl_problem* pb, const double* lens, const int32_t*
     return e;
   LaunchCfg c;
   if (int e = configure_any(pb->dtype, A, L, resolve_tuning(pb, max_ns, n_members, n_lambda, opt), &c)) return e;
+  return enqueue_any(pb->dtype, A, lams, L, c, (hipStream_t)stream, true);
+}
+
+int sl_solve_implicit(const sl_problem* pb, const double* lens, const int32_t* ns, int max_ns, int n_members,
+                      int n_iter, const sl_solve_opts* opt, void* workspace, size_t workspace_bytes, sl_result* out,
+                      void* stream) {
+  SL_REQUIRE(n_iter >= 4 && n_iter <= SL_MAX_LAMBDA, "n_iter %d outside [4, %d]", n_iter, SL_MAX_LAMBDA);
+  SL_REQUIRE(opt != nullptr, "opts is NULL");
+  SL_REQUIRE(opt->mc_noise == nullptr, "mc_noise is not supported by the implicit-regularisation solve");
+  double idx[SL_MAX_LAMBDA];   // placeholders for the argument checks: one slot per iterate
+  for (int k = 0; k < n_iter; ++k) idx[k] = k + 1.0;
+  SolveArgs A;
+  Layout L;
+  LamList lams;
+  if (int e = prepare(pb, lens, ns, max_ns, n_members, idx, n_iter, opt, workspace, workspace_bytes, out, &A, &L,
+                      &lams))
+    return e;
+  A.implicit = 1;
+  LaunchCfg c;
+  const sl_tuning dflt{0, 0, opt->tuning ? opt->tuning->blur_direct : 0, 1};
+  if (int e = configure_any(pb->dtype, A, L, dflt, &c)) return e;
   return enqueue_any(pb->dtype, A, lams, L, c, (hipStream_t)stream, true);
 }
 

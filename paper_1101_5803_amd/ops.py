@@ -283,6 +283,19 @@ class Solver:
                 "sl_solve_semilinear")
         return out
 
+    def solve_implicit(self, lens: torch.Tensor, ns: torch.Tensor, n_iter: int = 40, max_ns: int | None = None,
+                       out=None):
+        """Implicit regularisation (sl_solve_implicit): n_iter unregularised CG iterations per member and the
+        L-curve over the iterates; out["chi2"], out["reg"] are (M, n_iter), k_star the corner iterate index."""
+        lens = lens.to(torch.float64).contiguous()
+        ns = ns.to(torch.int32).contiguous()
+        M, lam, max_ns, ws, out, res, opts, _tun = self._args(lens, ns, list(range(1, n_iter + 1)), 0.0, 1, max_ns,
+                                                              out, None)
+        L.check(L.lib().sl_solve_implicit(ctypes.byref(self._pb), L.ptr(lens), L.ptr(ns), max_ns, M, int(n_iter),
+                                          ctypes.byref(opts), L.ptr(ws), ws.numel(), ctypes.byref(res),
+                                          L.stream_handle()), "sl_solve_implicit")
+        return out
+
     def autotune(self, lens: torch.Tensor, ns: torch.Tensor, lambdas, tol=1e-7, maxit=4000,
                  max_ns: int | None = None, out=None):
         """Time every kernel variant on this problem (synchronous); returns (best dict, ms per variant, out).

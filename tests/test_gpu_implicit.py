@@ -1,0 +1,193 @@
+"""GPU parity of the implicit-regularisation solve (sl_solve_implicit) against the oracle.
+
+Sec. 2.4 / 2.6: n_iter CGLS iterations per member with no lambda, chi^2 and
+sum s^2 after every iteration, and the L-curve over the iterates, compared
+with oracle.implicit.cgls_iterates (FP64 CGLS).
+
+Tolerance.  The fixed-iteration sequence is well conditioned only while CGLS
+resolves the large singular values; past ten or so iterations it fits noise
+along small ones and loss of orthogonality amplifies rounding, so that two
+correct implementations that round differently drift apart by far more than
+the unit roundoff (a relative 1e-15 change of the data moves chi^2 at
+iteration 16 by up to 1e-3 and can move the corner).  Each GPU value is
+therefore judged against the spread of the oracle run under Monte Carlo
+arithmetic at the GPU's rounding level (the oracle's `perturb` hook; eight
+seeded draws): unit roundoff u (2^-53 in FP64, 2^-24 in FP32) on every
+updated vector, u K on the outputs of A and A^T (sums of about K^2 PSF
+terms), u sqrt(n) on the FP64 step lengths, n the longer of the image and
+the source vectors (u in FP32, where the GPU rounds them to FP32), and u on the data.  Per iterate
+|gpu - oracle| <= 10 x the largest relative deviation over the draws (of the
+explicit and of the carried-residual chi^2) at this or any earlier iterate,
+times the oracle's value, + a floor (1e-13 relative in FP64, 1e-7 in
+FP32).  Where the sequence is well conditioned that spread is at rounding
+level, so the early iterates are held to it.  In FP64 the GPU's corner must be
+the corner of the oracle's curve, of a draw, or of its 1e-5 corner set.  In
+FP32 the draws' corners spread over a flat stretch of the curve, so the
+GPU's corner must lie within the range of those indices; as chi^2 does not
+increase with the iteration count, its fitness then lies within the range of
+the draws' fitness values (up to the per-iterate bound).  The corner
+solution must lie within 10 x the draws' spread of the oracle's iterate at
+that index.
+"""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import synthgen
+from oracle import implicit, lcurve, mock, solve
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+HERE = os.path.dirname(os.path.abspath(__file__))
+N_ITER = 40
+U = {"f64": 2.0 ** -53, "f32": 2.0 ** -24}
+FLOOR = {"f64": 1e-13, "f32": 1e-7}
+DRAWS = 8
+
+
+@pytest.fixture(scope="module")
+def sl():
+    import paper_1101_5803_amd as sl
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return sl
+
+
+def _np(out):
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+def _mca(prec, K, n, rng):
+    """Monte Carlo arithmetic at the GPU's rounding level (see the module docstring)."""
+    u = U[prec]
+    rel = {"A": u * K, "AT": u * K, "vec": u, "scalar": u if prec == "f32" else u * np.sqrt(n)}
+
+    def perturb(x, kind):
+        return x * (1 + rel[kind] * rng.standard_normal(np.shape(x)))
+    return perturb
+
+
+def _envelope(make_pb, d, prec, K):
+    """Oracle iterates on d, and their spread over DRAWS Monte Carlo arithmetic runs."""
+    ref = implicit.cgls_iterates(make_pb(d), N_ITER)
+    rng = np.random.default_rng(77)
+    runs = []
+    for _ in range(DRAWS):
+        pb = make_pb(d * (1 + U[prec] * rng.standard_normal(d.shape)))
+        runs.append(implicit.cgls_iterates(pb, N_ITER, perturb=_mca(prec, K, max(pb.I, d.size), rng)))
+    # largest relative deviation over the draws up to each iterate: rounding
+    # effects accumulate, and a per-iterate maximum dips where the deviations
+    # of all draws happen to change sign together
+    rel = {"chi2": np.max([np.maximum(np.abs(r["chi2"] - ref["chi2"]), np.abs(r["chi2_e"] - ref["chi2"]))
+                           for r in runs], axis=0) / np.abs(ref["chi2"]),
+           "reg": np.max([np.abs(r["reg"] - ref["reg"]) for r in runs], axis=0) / np.maximum(np.abs(ref["reg"]), 1e-300)}
+    dev = {k: np.maximum.accumulate(v) * np.abs(ref[k]) for k, v in rel.items()}
+    sn = np.maximum(np.linalg.norm(ref["s"], axis=1), 1e-300)
+    ds = np.maximum.accumulate(np.max([np.linalg.norm(r["s"] - ref["s"], axis=1) for r in runs], axis=0) / sn) * sn
+    corners = {lcurve.corner(ref["reg"], ref["chi2"])[0]} | lcurve.corner_set(ref["reg"], ref["chi2"])
+    corners |= {lcurve.corner(r["reg"], r["chi2"])[0] for r in runs}
+    return ref, dev, ds, corners
+
+
+def _check(out, G, ns, d, sigma, psf, geom, nsub, R, prec, rows=None, skip=()):
+    nx, ny, pix = geom
+    off = out["s_off"]
+    worst = 0.0
+    for j, m in enumerate(rows if rows is not None else range(len(G))):
+        if m in skip:
+            assert np.all(out["status"][j] == 2), out["status"][j]
+            continue
+        assert np.all(out["status"][j] == 0), (m, out["status"][j])
+        make = lambda dd: solve.Problem(G[m], dd, sigma, psf, nx, ny, pix, nsub, int(ns[m]), R, "identity")  # noqa: E731
+        ref, dev, ds, corners = _envelope(make, d, prec, psf.shape[0])
+        for key in ("chi2", "reg"):
+            err = np.abs(out[key][j] - ref[key])
+            bound = 10 * dev[key] + FLOOR[prec] * np.abs(ref[key])
+            assert np.all(err <= bound), (m, key, np.nonzero(err > bound)[0], err / np.abs(ref[key]))
+            worst = max(worst, float(np.max(err / np.abs(ref[key]))))
+        assert np.array_equal(out["iters"][j], np.arange(1, N_ITER + 1))
+        k = int(out["k_star"][j])
+        assert k == lcurve.corner(out["reg"][j], out["chi2"][j])[0]
+        if prec == "f64":
+            assert k in corners, (m, k, corners)
+        else:   # FP32 rounding does not fix the index on a flat stretch of the curve
+            assert min(corners) <= k <= max(corners), (m, k, corners)
+        s_ref = ref["s"][k]
+        err = np.linalg.norm(out["s_corner"][off[j]:off[j + 1]] - s_ref)
+        assert err <= 10 * ds[k] + FLOOR[prec] * np.linalg.norm(s_ref), (m, k, err / np.linalg.norm(s_ref))
+    return worst
+
+
+def _small_case():
+    nx, ny, pix, K = 40, 36, 0.1, 7
+    psf = mock.gaussian_psf(K, 2.0)
+    w = synthgen.Workload("small", 9, nx, ny, pix, 2, 6, 12, 1.0, K, 2.0, 40.0, "identity", (1e-3,), 1e-10,
+                          "sersic", 2)
+    lens_true = np.array([1.0, 0.75, 0.5, 0.04, 0.3, 0.02, -0.03])
+    clean = mock.clean_image(lens_true, synthgen.source_blobs(w), nx, ny, pix, 6, psf)
+    sigma = clean.max() / 40.0
+    d = clean + sigma * synthgen.noise_unit(w)
+    G = synthgen.population(21, 6)
+    G[0] = lens_true
+    G[4] = [5.0, 1.0, 0.0, 0.0, 0.0, 5.0, 5.0]     # maps nothing onto the grid
+    ns = np.array([12, 8, 19, 5, 16, 23], dtype=np.int32)
+    return d, sigma, psf, (nx, ny, pix), G, ns
+
+
+@pytest.mark.parametrize("psf_kind", ["gauss", "general"])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_small_batch_vs_oracle(sl, prec, psf_kind):
+    d, sigma, psf, geom, G, ns = _small_case()
+    if psf_kind == "general":   # not rank 1: the direct blur path
+        psf = np.random.default_rng(3).uniform(0.2, 1.0, psf.shape)
+        psf /= psf.sum()
+    dtype = torch.float64 if prec == "f64" else torch.float32
+    solver = sl.Solver(torch.tensor(d, device=DEV), sigma, torch.tensor(psf, device=DEV), sl.Grid(*geom, 2), 1.0,
+                       reg="curvature", dtype=dtype)
+    out = _np(solver.solve_implicit(torch.tensor(G, device=DEV), torch.tensor(ns, device=DEV), N_ITER))
+    assert out["corner_status"][4] == 2
+    w = _check(out, G, ns, d, sigma, psf, geom, 2, 1.0, prec, skip=(4,))
+    print(f"{prec} {psf_kind}: largest relative chi^2 / reg difference over all iterates {w:.2e}")
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_c2_member_vs_oracle(sl, prec):
+    w = synthgen.C2
+    z = np.load(os.path.join(HERE, "data", "c2.npz"))
+    dtype = torch.float64 if prec == "f64" else torch.float32
+    solver = sl.Solver(torch.tensor(z["d"], device=DEV), float(z["sigma"]), torch.tensor(z["psf"], device=DEV),
+                       sl.Grid(w.nx, w.ny, w.pix, w.nsub_model), w.half_width, reg=w.reg, dtype=dtype)
+    G = np.atleast_2d(z["lens"])
+    ns = np.array([w.ns], dtype=np.int32)
+    out = _np(solver.solve_implicit(torch.tensor(G, device=DEV), torch.tensor(ns, device=DEV), N_ITER, max_ns=w.ns))
+    wst = _check(out, G, ns, z["d"], float(z["sigma"]), z["psf"], (w.nx, w.ny, w.pix), w.nsub_model, w.half_width,
+                 prec)
+    print(f"c2 {prec}: largest relative chi^2 / reg difference over all iterates {wst:.2e}")
+
+
+def test_c3_launch_sampled_and_repeatable(sl):
+    w = synthgen.C3
+    z = np.load(os.path.join(HERE, "data", "c2.npz"))
+    pop = synthgen.population(w.seed, 256)
+    grids = synthgen.member_grids(w.seed, 256)
+    solver = sl.Solver(torch.tensor(z["d"], device=DEV), float(z["sigma"]), torch.tensor(z["psf"], device=DEV),
+                       sl.Grid(w.nx, w.ny, w.pix, w.nsub_model), w.half_width, reg=w.reg, dtype=torch.float32)
+    lens = torch.tensor(pop, device=DEV)
+    nst = torch.tensor(grids, device=DEV)
+    a = _np(solver.solve_implicit(lens, nst, N_ITER, max_ns=96))
+    b = _np(solver.solve_implicit(lens, nst, N_ITER, max_ns=96))
+    n = int(a["s_off"][-1])
+    for k in ("chi2", "reg", "iters", "status", "k_star", "corner_status"):
+        assert np.array_equal(a[k], b[k]), k
+    assert np.array_equal(a["s_corner"][:n], b["s_corner"][:n])
+    assert np.all(a["status"] == 0)
+    order = np.argsort(grids, kind="stable")
+    sample = [int(order[0]), int(order[128]), int(order[-1])]
+    sub = {k: a[k][sample] for k in ("chi2", "reg", "iters", "status", "k_star")}
+    off = a["s_off"]
+    sub["s_corner"] = np.concatenate([a["s_corner"][off[m]:off[m + 1]] for m in sample])
+    sub["s_off"] = np.concatenate([[0], np.cumsum([grids[m] ** 2 for m in sample])])
+    _check(sub, pop, grids, z["d"], float(z["sigma"]), z["psf"], (w.nx, w.ny, w.pix), w.nsub_model, w.half_width,
+           "f32", rows=sample)

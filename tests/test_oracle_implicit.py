@@ -66,3 +66,24 @@ def test_fitness_is_chi2_at_the_corner():
     f = implicit.implicit_fitness(pb, 25)
     assert 0 <= f["k_star"] < 25
     assert f["fitness"] == pytest.approx(pb.chi2(f["s"][f["k_star"]]), rel=1e-12)
+
+
+def test_carried_residual_and_identity_hook():
+    """The carried residual's chi^2 equals the explicit one, and an identity
+    perturbation hook leaves every iterate unchanged."""
+    pb = _tiny(ns=6, seed=2)
+    a = implicit.cgls_iterates(pb, 20)
+    b = implicit.cgls_iterates(pb, 20, perturb=lambda x, kind: x)
+    assert np.array_equal(a["s"], b["s"]) and np.array_equal(a["chi2"], b["chi2"])
+    assert np.all(np.abs(a["chi2_e"] - a["chi2"]) <= 1e-9 * a["chi2"])
+
+
+def test_rounding_spread_grows_from_rounding_level():
+    """Monte Carlo arithmetic at FP64 unit roundoff moves the first iterates
+    only at rounding level; the spread is what the parity tests scale."""
+    pb = _tiny(ns=7, seed=4)
+    ref = implicit.cgls_iterates(pb, 6)
+    rng = np.random.default_rng(1)
+    run = implicit.cgls_iterates(pb, 6, perturb=lambda x, kind: x * (1 + 2.0 ** -53 * rng.standard_normal(np.shape(x))))
+    assert np.all(np.abs(run["chi2"][:3] - ref["chi2"][:3]) <= 1e-12 * ref["chi2"][:3])
+    assert not np.array_equal(run["s"], ref["s"])
