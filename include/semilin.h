@@ -246,9 +246,9 @@ int sl_solve_semilinear(const sl_problem* pb, const double* lens, const int32_t*
 
 /*
  * Implicit regularisation by the iteration count (Sec. 2.4, Sec. 2.6, and
- * the fitness of Sec. 3): no lambda; for every member, n_iter iterations of
- * CG on the unregularised normal equations A^T A s = A^T d (A = B L) from
- * s = 0 -- the iterates of CGLS -- and after iteration k (k = 1..n_iter)
+ * the fitness of Sec. 3): no lambda; for every member, n_iter CGLS
+ * iterations on min ||A s - d|| (A = B L) from s = 0, each applying A once
+ * and A^T once, and after iteration k (k = 1..n_iter)
  * chi^2 = ||d - A s_k||^2 / sigma^2 (from the image residual, carried as a
  * vector) and the zeroth-order measure sum_i s_k,i^2 (whatever pb->reg
  * says).  The L-curve over the iterates gives k_star (index k - 1 of the
@@ -256,9 +256,19 @@ int sl_solve_semilinear(const sl_problem* pb, const double* lens, const int32_t*
  * that iterate.  Arguments and outputs as sl_solve_semilinear with
  * n_lambda = n_iter: chi2, reg, iters (= k), status are [n_members][n_iter];
  * workspace from sl_solve_workspace_size(pb, max_ns, n_members, n_iter).
- * n_iter in [4, SL_MAX_LAMBDA]; opts->tol is not used (the count stops CG),
- * opts->mc_noise must be NULL.  After a breakdown (A p = 0) the remaining
- * iterates repeat the last one with status SL_ST_BREAKDOWN.
+ * n_iter in [4, SL_MAX_LAMBDA]; opts->tol is not used (the count stops the
+ * iteration).  After a breakdown (A p = 0) the remaining iterates repeat
+ * the last one with status SL_ST_BREAKDOWN.
+ *
+ * Monte Carlo degrees of freedom (Sec. 2.5, as the paper runs it inside
+ * CGLS; opts->mc_noise = bhat, SL_F64 only, else SL_EINVAL): a second system
+ * with data bhat is advanced with the data system's step lengths alpha_k,
+ * beta_k, and dof[m] = bhat^T (bhat - A xhat_k*) at the corner iterate
+ * (computed as bhat^T bhat - <A^T bhat, xhat> in FP64).  Its expectation over
+ * bhat is J minus the sum of the CGLS filter factors after k* iterations.
+ * The fixed-coefficient recurrence amplifies rounding of the step lengths
+ * geometrically with k; FP32 rounding already spoils it within a few
+ * iterations, hence FP64 only.  About twice the work of the solve alone.
  */
 int sl_solve_implicit(const sl_problem* pb, const double* lens, const int32_t* ns, int max_ns,
                       int n_members, int n_iter, const sl_solve_opts* opt, void* workspace,

@@ -101,3 +101,31 @@ def implicit_fitness(pb: Problem, n_iter: int = 40):
     it = cgls_iterates(pb, n_iter)
     k, kappa = lcurve.corner(it["reg"], it["chi2"])
     return dict(k_star=k, fitness=float(it["chi2"][k]) if k >= 0 else float("inf"), kappa=kappa, **it)
+
+
+def lockstep_dof(pb: Problem, bhat: np.ndarray, alpha, beta, n_iter: int):
+    """Monte Carlo degrees of freedom along the CGLS iterates (Sec. 2.5).
+
+    A second system with data bhat (standard normal draws, image shaped) is
+    advanced with the data system's CGLS step lengths alpha_k and beta_k
+    rather than its own, so that its iterate xhat_k is the data system's
+    k-step filter applied to bhat.  After each iteration the estimate is
+    bhat^T (bhat - A xhat_k), evaluated from the explicit xhat_k.  alpha and
+    beta come from cgls_iterates; past the last recorded step (an early stop)
+    the estimate repeats.  Returns (n_iter,)."""
+    b = np.asarray(bhat, dtype=np.float64)
+    bb = float((b * b).sum())
+    xh = np.zeros(pb.I)
+    eh = b.copy()
+    ph = pb.FT(eh)
+    out = np.full(n_iter, bb)
+    for k in range(n_iter):
+        if k < len(alpha):
+            qh = pb.F(ph)
+            xh = xh + alpha[k] * ph
+            eh = eh - alpha[k] * qh
+            ph = pb.FT(eh) + beta[k] * ph
+            out[k] = bb - float((b * pb.F(xh)).sum())
+        elif k > 0:
+            out[k] = out[k - 1]
+    return out

@@ -84,7 +84,7 @@ struct alignas(16) Consts {
 };
 
 struct Layout {
-  size_t consts, lam, taps_d, taps_f, minfo, queues, pqueues, pix, cell, fx, fy, b, bh, s_all, gframe, gz, rbuf, mcbuf, ibuf,
+  size_t consts, lam, taps_d, taps_f, minfo, queues, pqueues, pix, cell, fx, fy, b, bh, dofk, s_all, gframe, gz, rbuf, mcbuf, ibuf,
       lt_ptr, lt_perm,
       lt_ent,
       total;
@@ -171,6 +171,7 @@ struct SolveArgs {
   const double* mcn; // [ny*nx] Gaussian draws bhat
   double* dofv;      // [n_members] result: bhat^T (bhat - A xhat) at the corner
   double* bh;        // [member][I_max] A^T bhat (FP64)
+  double* dofk;      // [member][n_lambda] implicit solve: the estimate after each iterate
   void* mcbuf;       // [n_wg][5][I_max] r, xhat, rhat, phat, saved p of the pass
   void* ibuf;        // [n_wg][J] image residual e = d - A s of the implicit-regularisation solve
 };
@@ -2004,6 +2005,16 @@ __global__ void __launch_bounds__(kNTof<T>) k_mcdof(SolveArgs a) {
 // chi^2 = ||e||^2 / sigma^2 and the zeroth-order measure ||s_k||^2 (Sec. 2.6).
 // g_0 = A^T d is the member's fixed-order right-hand side.  After a
 // breakdown (A p = 0) the remaining slots repeat the last iterate.
+//
+// Monte Carlo degrees of freedom (Sec. 2.5; FP64 only, mcn not NULL): a
+// second system with data bhat advanced with the data system's alpha_k and
+// beta_k, not its own (xhat += alpha phat, ehat -= alpha A phat,
+// phat = A^T ehat + beta phat, from xhat = 0, ehat = bhat, phat = A^T bhat),
+// so that xhat_k is the data system's k-step filter applied to bhat; after
+// every iteration bhat^T (bhat - A xhat_k) = ||bhat||^2 - <A^T bhat, xhat_k>
+// goes to dofk, and k_corner takes the value at the corner.  Its vectors
+// live in the block's global scratch: xhat, phat and A^T ehat in mcbuf, ehat
+// on the dilated box in the second half of gz.
 template <typename T, int CKT, bool LDSF>
 __device__ __forceinline__ void run_implicit_item(const SolveArgs& a, const MemberInfo& mi, int m,
                                                   unsigned char* smem) {
@@ -2027,6 +2038,12 @@ __device__ __forceinline__ void run_implicit_item(const SolveArgs& a, const Memb
   const int Dh = Dr1 - Dr0 + 1, Dw = Dc1 - Dc0 + 1;
   T* __restrict__ Zq = reinterpret_cast<T*>(a.gz) + slot * J;     // q = A p on the dilated box
   T* __restrict__ E = reinterpret_cast<T*>(a.ibuf) + slot * J;    // e on the dilated box
+  const bool mc = sizeof(T) == 8 && a.mcn != nullptr;               // uniform: a kernel argument
+  T* __restrict__ xh = reinterpret_cast<T*>(a.mcbuf) + slot * 5L * a.I_max;
+  T* __restrict__ ph = xh + a.I_max;
+  T* __restrict__ gh = ph + a.I_max;
+  T* __restrict__ Eh = reinterpret_cast<T*>(a.gz) + ((long)gridDim.x + slot) * J;   // ehat on the dilated box
+  const double* bhm = a.bh + (long)m * a.I_max;
   const OpView<T> ov{a.pix_list + (long)m * a.slot_cap, a.cell + (long)m * a.slot_cap * n2,
                      reinterpret_cast<const T*>(a.fx) + (long)m * a.slot_cap * n2,
                      reinterpret_cast<const T*>(a.fy) + (long)m * a.slot_cap * n2, F, F0, Zq,
@@ -2050,11 +2067,18 @@ __device__ __forceinline__ void run_implicit_item(const SolveArgs& a, const Memb
     E[e] = (T)dv;
     din += dv * dv;
   }
+  if (mc) {
+    for (int i = tid; i < I; i += NT) {
+      xh[i] = (T)0;
+      ph[i] = (T)bhm[i];
+    }
+    for (int e = tid; e < Dh * Dw; e += NT) Eh[e] = (T)a.mcn[(Dr0 + e / Dw) * nx + Dc0 + e % Dw];
+  }
   block_sum2(gg, din, red + 32);
   const double d_out = a.consts->sum_d2 - din;   // sum of d^2 outside the dilated box
   const double inv_s2 = 1.0 / (a.sigma * a.sigma);
   int k = 0, st = SL_ST_OK;
-  double chi2_last = a.consts->sum_d2 * inv_s2, reg_last = 0.0;
+  double chi2_last = a.consts->sum_d2 * inv_s2, reg_last = 0.0, dof_last = a.consts->sum_n2;
   for (; k < K_it; ++k) {
     if (__builtin_amdgcn_readfirstlane((int)(gg <= 0.0))) break;
     gather_L<T, NT>(ov, P);                               // frame = L p
@@ -2096,6 +2120,27 @@ __device__ __forceinline__ void run_implicit_item(const SolveArgs& a, const Memb
     const T beta = (T)(gn / gg);
     for (int i = tid; i < I; i += NT) P[i] = G[i] + beta * P[i];
     gg = gn;
+    if (mc) {   // the second system with this iteration's alpha and beta
+      gather_L<T, NT>(ov, ph);                            // every thread has read the frame (barrier above)
+      __syncthreads();
+      blur_box<T, CKT, NT>(ov, Zq);                       // A phat
+      __syncthreads();
+      double gam = 0.0;
+      for (int i = tid; i < I; i += NT) {
+        const T xv = xh[i] + alT * ph[i];
+        xh[i] = xv;
+        gam += bhm[i] * (double)xv;
+      }
+      for (int e = tid; e < Dh * Dw; e += NT) Eh[e] -= alT * Zq[e];
+      gam = block_sum1<NT / kWave>(gam, red, 0);          // its barrier: ehat complete
+      blur_T_mapped<T, NT>(ov, Eh);
+      __syncthreads();
+      gather_LT<T, NT, true>(ov, ph, gh);                 // A^T ehat
+      __syncthreads();
+      for (int i = tid; i < I; i += NT) ph[i] = gh[i] + beta * ph[i];
+      dof_last = a.consts->sum_n2 - gam;
+      a.dofk[(long)m * K_it + k] = dof_last;              // the same value from every thread
+    }
     __syncthreads();
   }
   // slots past an early stop repeat the last iterate (s = 0 when there is none)
@@ -2108,6 +2153,7 @@ __device__ __forceinline__ void run_implicit_item(const SolveArgs& a, const Memb
     a.regv[o] = reg_last;
     a.iters[o] = k;
     a.status[o] = st;
+    if (mc) a.dofk[o] = dof_last;
     __syncthreads();
   }
 }
@@ -2205,6 +2251,7 @@ __global__ void __launch_bounds__(256) k_corner(SolveArgs a) {
       }
     a.k_star[m] = k;
     a.corner_status[m] = cst;
+    if (a.implicit && a.dofv) a.dofv[m] = mi.status == SL_ST_OK ? a.dofk[(long)m * nl + k] : NAN;
     sh_k = k;
   }
   __syncthreads();
@@ -2258,6 +2305,7 @@ static Layout make_layout(const sl_problem* pb, int max_ns, int M, int NL, int n
   L.fy = take(sz * (size_t)M * L.slot_cap * L.n2);
   L.b = take(sizeof(double) * (size_t)M * L.I_max);
   L.bh = take(sizeof(double) * (size_t)M * L.I_max);   // A^T bhat (Monte Carlo degrees of freedom)
+  L.dofk = take(sizeof(double) * (size_t)M * NL);      // per-iterate estimate of the implicit solve
   L.s_all = take(sz * (size_t)M * NL * L.I_max);
   L.gframe_elems = (pb->img.ny + 4 * 16 + kSegR) * ((pb->img.nx + 4 * 16) | 1);   // widest window's halo
   L.gframe = take(sz * (size_t)n_wg * L.gframe_elems);
@@ -2455,7 +2503,7 @@ static int configure(SolveArgs& A, const Layout& L, const sl_tuning& v, LaunchCf
       return SL_ENOIMPL;
     }
   }
-  if (A.mcn) {
+  if (A.mcn && !A.implicit) {   // the implicit solve runs its own lockstep system
     c->kmc = pick_mc_kernel<T>(ckt);
     if (!c->kmc) {
       set_error("no Monte Carlo degrees-of-freedom kernel for window %d", ckt);
@@ -2647,6 +2695,7 @@ static int prepare(const sl_problem* pb, const double* lens, const int32_t* ns, 
   A.fy = ws + L.fy;
   A.b = (double*)(ws + L.b);
   A.bh = (double*)(ws + L.bh);
+  A.dofk = (double*)(ws + L.dofk);
   A.mcbuf = ws + L.mcbuf;
   A.ibuf = ws + L.ibuf;
   A.mcn = opt->mc_noise;
@@ -2694,7 +2743,9 @@ int sl_solve_implicit(const sl_problem* pb, const double* lens, const int32_t* n
                       void* stream) {
   SL_REQUIRE(n_iter >= 4 && n_iter <= SL_MAX_LAMBDA, "n_iter %d outside [4, %d]", n_iter, SL_MAX_LAMBDA);
   SL_REQUIRE(opt != nullptr, "opts is NULL");
-  SL_REQUIRE(opt->mc_noise == nullptr, "mc_noise is not supported by the implicit-regularisation solve");
+  SL_REQUIRE(opt->mc_noise == nullptr || pb->dtype == SL_F64,
+             "mc_noise with the implicit-regularisation solve needs FP64: its lockstep system amplifies FP32 "
+             "rounding of the step lengths past the first few iterations");
   double idx[SL_MAX_LAMBDA];   // placeholders for the argument checks: one slot per iterate
   for (int k = 0; k < n_iter; ++k) idx[k] = k + 1.0;
   SolveArgs A;

@@ -284,13 +284,15 @@ class Solver:
         return out
 
     def solve_implicit(self, lens: torch.Tensor, ns: torch.Tensor, n_iter: int = 40, max_ns: int | None = None,
-                       out=None):
-        """Implicit regularisation (sl_solve_implicit): n_iter unregularised CG iterations per member and the
-        L-curve over the iterates; out["chi2"], out["reg"] are (M, n_iter), k_star the corner iterate index."""
+                       out=None, mc_noise: torch.Tensor | None = None):
+        """Implicit regularisation (sl_solve_implicit): n_iter CGLS iterations per member with no lambda and the
+        L-curve over the iterates; out["chi2"], out["reg"] are (M, n_iter), k_star the corner iterate index.
+        ``mc_noise`` (FP64 solves only: ny*nx FP64 Gaussian draws on the device) adds the lockstep Monte Carlo
+        degrees-of-freedom system; out["dof"][m] is then its estimate at the member's corner iterate."""
         lens = lens.to(torch.float64).contiguous()
         ns = ns.to(torch.int32).contiguous()
         M, lam, max_ns, ws, out, res, opts, _tun = self._args(lens, ns, list(range(1, n_iter + 1)), 0.0, 1, max_ns,
-                                                              out, None)
+                                                              out, None, mc_noise)
         L.check(L.lib().sl_solve_implicit(ctypes.byref(self._pb), L.ptr(lens), L.ptr(ns), max_ns, M, int(n_iter),
                                           ctypes.byref(opts), L.ptr(ws), ws.numel(), ctypes.byref(res),
                                           L.stream_handle()), "sl_solve_implicit")

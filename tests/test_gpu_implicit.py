@@ -191,3 +191,54 @@ def test_c3_launch_sampled_and_repeatable(sl):
     sub["s_off"] = np.concatenate([[0], np.cumsum([grids[m] ** 2 for m in sample])])
     _check(sub, pop, grids, z["d"], float(z["sigma"]), z["psf"], (w.nx, w.ny, w.pix), w.nsub_model, w.half_width,
            "f32", rows=sample)
+
+
+def _dof_envelope(make_pb, d, bhat, K):
+    """Oracle lockstep estimate per iterate, and its spread when the data system
+    runs under FP64 Monte Carlo arithmetic (its step lengths then carry the
+    rounding that the GPU's do)."""
+    it = implicit.cgls_iterates(make_pb(d), N_ITER)
+    ref = implicit.lockstep_dof(make_pb(d), bhat, it["alpha"], it["beta"], N_ITER)
+    rng = np.random.default_rng(78)
+    devs = []
+    for _ in range(DRAWS):
+        pb = make_pb(d * (1 + U["f64"] * rng.standard_normal(d.shape)))
+        r = implicit.cgls_iterates(pb, N_ITER, perturb=_mca("f64", K, max(pb.I, d.size), rng))
+        devs.append(np.abs(implicit.lockstep_dof(pb, bhat, r["alpha"], r["beta"], N_ITER) - ref))
+    scale = float((bhat * bhat).sum())
+    return ref, np.maximum.accumulate(np.max(devs, axis=0) / scale) * scale, scale
+
+
+def test_mc_dof_small_batch_vs_oracle(sl):
+    """Sec. 2.5 inside CGLS: the lockstep estimate at the corner iterate (FP64)
+    against the oracle's lockstep on the same draws at the GPU's corner index,
+    within 10 x its Monte Carlo arithmetic spread + 1e-12 ||bhat||^2."""
+    d, sigma, psf, geom, G, ns = _small_case()
+    nx, ny, pix = geom
+    bhat = synthgen.mc_draws(9, ny, nx)
+    solver = sl.Solver(torch.tensor(d, device=DEV), sigma, torch.tensor(psf, device=DEV), sl.Grid(*geom, 2), 1.0,
+                       reg="curvature", dtype=torch.float64)
+    noise = torch.tensor(bhat.reshape(-1), device=DEV)
+    out = _np(solver.solve_implicit(torch.tensor(G, device=DEV), torch.tensor(ns, device=DEV), N_ITER,
+                                    mc_noise=noise))
+    plain = _np(solver.solve_implicit(torch.tensor(G, device=DEV), torch.tensor(ns, device=DEV), N_ITER))
+    for key in ("chi2", "reg", "k_star", "status"):   # the second system leaves the data system alone
+        assert np.array_equal(out[key], plain[key]), key
+    assert np.isnan(out["dof"][4])
+    for m in (0, 1, 2, 3, 5):
+        make = lambda dd: solve.Problem(G[m], dd, sigma, psf, nx, ny, pix, 2, int(ns[m]), 1.0, "identity")  # noqa: E731
+        ref, dev, scale = _dof_envelope(make, d, bhat, psf.shape[0])
+        k = int(out["k_star"][m])
+        err = abs(out["dof"][m] - ref[k])
+        assert err <= 10 * dev[k] + 1e-12 * scale, (m, k, out["dof"][m], ref[k], dev[k])
+        assert 0.0 < out["dof"][m] < scale
+        print(f"member {m}: corner {k}, dof {out['dof'][m]:.6f}, oracle {ref[k]:.6f}, |diff| {err:.2e}")
+
+
+def test_mc_dof_refused_in_fp32(sl):
+    d, sigma, psf, geom, G, ns = _small_case()
+    solver = sl.Solver(torch.tensor(d, device=DEV), sigma, torch.tensor(psf, device=DEV), sl.Grid(*geom, 2), 1.0,
+                       reg="curvature", dtype=torch.float32)
+    noise = torch.zeros(d.size, dtype=torch.float64, device=DEV)
+    with pytest.raises(sl._lib.SemilinError, match="FP64"):
+        solver.solve_implicit(torch.tensor(G, device=DEV), torch.tensor(ns, device=DEV), N_ITER, mc_noise=noise)

@@ -87,3 +87,48 @@ def test_rounding_spread_grows_from_rounding_level():
     run = implicit.cgls_iterates(pb, 6, perturb=lambda x, kind: x * (1 + 2.0 ** -53 * rng.standard_normal(np.shape(x))))
     assert np.all(np.abs(run["chi2"][:3] - ref["chi2"][:3]) <= 1e-12 * ref["chi2"][:3])
     assert not np.array_equal(run["s"], ref["s"])
+
+
+def test_lockstep_dof_matches_ritz_filter_factors():
+    """Sec. 2.5 in the iterative form: the second system advanced with the data
+    system's CGLS step lengths applies the data system's k-step filter to bhat,
+    so bhat^T (bhat - A xhat_k) = ||bhat||^2 - sum_i f_i (u_i^T bhat)^2 with
+    the CGLS filter factors f_i = 1 - prod_j (1 - sigma_i^2 / theta_j), theta_j
+    the Ritz values of A^T A on K_k(A^T A, A^T d) (Hansen, Rank-Deficient and
+    Discrete Ill-Posed Problems, 1998, Sec. 6.3), from a dense SVD."""
+    pb = _tiny(ns=5, seed=7)
+    A = pb.dense_F()
+    d = pb.d.reshape(-1)
+    bhat = np.random.default_rng(11).standard_normal(pb.d.shape)
+    n = 6
+    it = implicit.cgls_iterates(pb, n)
+    got = implicit.lockstep_dof(pb, bhat, it["alpha"], it["beta"], n)
+    U, sv, _ = np.linalg.svd(A, full_matrices=False)
+    ub = U.T @ bhat.reshape(-1)
+    AtA = A.T @ A
+    basis, v = [], A.T @ d
+    for k in range(1, n + 1):
+        basis.append(v)
+        v = AtA @ v
+        Q, _ = np.linalg.qr(np.stack(basis, axis=1))
+        theta = np.linalg.eigvalsh(Q.T @ AtA @ Q)
+        f = 1.0 - np.prod(1.0 - sv[:, None] ** 2 / theta[None, :], axis=1)
+        want = bhat.reshape(-1) @ bhat.reshape(-1) - np.sum(f * ub ** 2)
+        assert abs(got[k - 1] - want) <= 1e-7 * abs(want), (k, got[k - 1], want)
+
+
+def test_lockstep_dof_mean_is_trace():
+    """The estimate is unbiased: over draws its mean approaches
+    m - sum_i f_i, the trace of I - A X_k (Girard; Hutchinson)."""
+    pb = _tiny(ns=4, seed=8)
+    it = implicit.cgls_iterates(pb, 3)
+    A = pb.dense_F()
+    rng = np.random.default_rng(12)
+    vals = [implicit.lockstep_dof(pb, rng.standard_normal(pb.d.shape), it["alpha"], it["beta"], 3)[-1]
+            for _ in range(400)]
+    # the estimate is the quadratic form of I - A X_k, so its values on the
+    # unit vectors are the diagonal of that matrix
+    m = A.shape[0]
+    tr = sum(implicit.lockstep_dof(pb, np.eye(m)[j].reshape(pb.d.shape), it["alpha"], it["beta"], 3)[-1]
+             for j in range(m))
+    assert abs(np.mean(vals) - tr) <= 4 * np.std(vals) / np.sqrt(len(vals)), (np.mean(vals), tr)
