@@ -1348,7 +1348,8 @@ struct OpView {
   const T* fyp;
   T* F;                      // image frame with its zero halo (LDS or global)
   T* F0;                     // frame interior (0, 0) = image pixel (r0, c0)
-  T* Z;                      // per-block image buffer of the direct blur
+  T* Z;                      // per-block image buffer of the direct blur (z = B y on the dilated box)
+  T* W;                      // per-block image buffer of the direct blur (B^T z on the bounding box)
   const T* taps;
   const int32_t* lt_rp;      // transposed operator: slice (or row) starts
   const LtEntry<T>* lt_e;    //                      entries
@@ -1548,17 +1549,169 @@ __device__ __forceinline__ double gather_LT(const OpView<T>& o, const T* __restr
   return pq;
 }
 
+// Register-tiled direct K x K forms, for a PSF of exactly KT = 2 CKT + 1
+// taps per side.  Each thread computes eight consecutive outputs of one row
+// from a window of KT + 7 values per input row, so that one load serves up
+// to eight products; consecutive lanes take consecutive rows, so with the
+// odd frame pitch their LDS reads fall in distinct banks.  The last tile of a
+// row starts at width - 8: tiles overlap there and write the same values
+// twice.  Each output sums its taps in the order of the per-output forms
+// (row of the PSF outer, column inner), so the results are the same.
+// Usable when ck == CKT and both the box and the dilated box are at least 8
+// wide (tiled_ok).
+template <typename T, int CKT>
+__device__ __forceinline__ bool tiled_ok(const OpView<T>& o) {
+  return o.ck == CKT && o.w >= 8 && o.Dw >= 8;
+}
+
+// z = B y over the dilated box into Z (Dh x Dw, row-major), y in the frame
+// with its zero halo.  Returns this thread's part of ||z||^2 (each output
+// counted once).
+template <typename T, int CKT, int NT>
+__device__ __forceinline__ double blur_box_t8(const OpView<T>& o, T* __restrict__ Z) {
+  constexpr int KT = 2 * CKT + 1, NV = KT + 7;
+  const int Dh = o.Dh, Dw = o.Dw, pitch = o.pitch;
+  const T* tp = o.taps + TapIdx(KT).psf;
+  // output (r, c) of the dilated box reads base[(r - aa) * pitch + (c - bb)]
+  const T* base = o.F0 + (o.Dr0 + CKT - o.r0) * pitch + (o.Dc0 + CKT - o.c0);
+  const int nct = (Dw + 7) >> 3;
+  double zz = 0.0;
+  for (int t = threadIdx.x; t < Dh * nct; t += NT) {
+    const int r = t % Dh;
+    const int cn = (t / Dh) * 8;          // nominal tile start
+    const int c = min(cn, Dw - 8);
+    T acc[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) acc[i] = 0;
+    for (int aa = 0; aa < KT; ++aa) {
+      const T* row = base + (r - aa) * pitch + c - (KT - 1);
+      T v[NV];
+#pragma unroll
+      for (int j = 0; j < NV; ++j) v[j] = row[j];
+      const T* ta = tp + aa * KT;
+#pragma unroll
+      for (int bb = 0; bb < KT; ++bb) {
+        const T tv = ta[bb];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) acc[i] += tv * v[i - bb + KT - 1];
+      }
+    }
+    T* zo = Z + r * Dw + c;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      zo[i] = acc[i];
+      if (c + i >= cn) zz += (double)acc[i] * (double)acc[i];
+    }
+  }
+  return zz;
+}
+
+// w = B^T z over the bounding box (h x w) into W (row-major, pitch w), z
+// staged in the frame over the dilated box with zeros beyond it.
+template <typename T, int CKT, int NT>
+__device__ __forceinline__ void blurT_box_t8(const OpView<T>& o, T* __restrict__ W) {
+  constexpr int KT = 2 * CKT + 1, NV = KT + 7;
+  const int h = o.h, w = o.w, pitch = o.pitch;
+  const T* tp = o.taps + TapIdx(KT).psf;
+  // output (r, c) of the box reads base[(r + aa) * pitch + (c + bb)]
+  const T* base = o.F0 - CKT * pitch - CKT;
+  const int nct = (w + 7) >> 3;
+  for (int t = threadIdx.x; t < h * nct; t += NT) {
+    const int r = t % h;
+    const int c = min((t / h) * 8, w - 8);
+    T acc[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) acc[i] = 0;
+    for (int aa = 0; aa < KT; ++aa) {
+      const T* row = base + (r + aa) * pitch + c;
+      T v[NV];
+#pragma unroll
+      for (int j = 0; j < NV; ++j) v[j] = row[j];
+      const T* ta = tp + aa * KT;
+#pragma unroll
+      for (int bb = 0; bb < KT; ++bb) {
+        const T tv = ta[bb];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) acc[i] += tv * v[i + bb];
+      }
+    }
+    T* wo = W + r * w + c;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) wo[i] = acc[i];
+  }
+}
+
+// frame over the dilated box = Z (Dh x Dw, row-major)
+template <typename T, int NT>
+__device__ __forceinline__ void stage_dilated(const OpView<T>& o, const T* __restrict__ Z) {
+  const int Dw = o.Dw, pitch = o.pitch;
+  T* const D0 = o.F0 + (o.Dr0 - o.r0) * pitch + (o.Dc0 - o.c0);
+  for (int e = threadIdx.x; e < o.Dh * Dw; e += NT) D0[(e / Dw) * pitch + e % Dw] = Z[e];
+}
+
+// frame over the bounding box = W (h x w, row-major)
+template <typename T, int NT>
+__device__ __forceinline__ void stage_box(const OpView<T>& o, const T* __restrict__ W) {
+  const int w = o.w, pitch = o.pitch;
+  for (int e = threadIdx.x; e < o.h * w; e += NT) o.F0[(e / w) * pitch + e % w] = W[e];
+}
+
+// Frame = B^T z at (at least) the mapped pixels, z on the dilated box in Zs.
+// The tiled form writes the whole dilated box (z there, B^T z over the
+// bounding box), so afterwards the rows of the dilated box must be zeroed
+// before the next L gather (clear_rows); the per-output form writes the
+// mapped pixels only.  Ends with a barrier.
+template <typename T, int CKT, int NT>
+__device__ __forceinline__ void adjoint_blur(const OpView<T>& o, const T* __restrict__ Zs) {
+  if (tiled_ok<T, CKT>(o)) {   // uniform: scalar member values
+    stage_dilated<T, NT>(o, Zs);
+    __syncthreads();
+    blurT_box_t8<T, CKT, NT>(o, o.W);
+    __syncthreads();
+    stage_box<T, NT>(o, o.W);
+  } else {
+    blur_T_mapped<T, NT>(o, Zs);
+  }
+  __syncthreads();
+}
+
+// z = B y over the dilated box into Z; returns this thread's part of ||z||^2.
+template <typename T, int CKT, int NT>
+__device__ __forceinline__ double forward_blur(const OpView<T>& o, T* __restrict__ Z) {
+  if (tiled_ok<T, CKT>(o)) return blur_box_t8<T, CKT, NT>(o, Z);
+  return blur_box<T, CKT, NT>(o, Z);
+}
+
+// Zero the frame rows that an operator application wrote, after every
+// gather has read the frame: the bounding box's rows (full pitch), and after
+// the tiled direct blur (DIR: the direct forms ran; the tiled one stages z
+// there) also the ck rows above and below them.  The tiled form needs
+// ck == CKT, so those rows lie inside the frame's 2 CKT halo; the other forms
+// write inside the box only.
+template <typename T, int CKT, int NT, bool DIR>
+__device__ __forceinline__ void clear_rows(const OpView<T>& o) {
+  const int up = (DIR && tiled_ok<T, CKT>(o)) ? o.ck : 0;
+  T* const R0 = o.F0 - (up * o.pitch + 2 * CKT);   // column 0 of frame row 2 CKT - up
+  const int n = (o.h + 2 * up) * o.pitch;
+  for (int e = threadIdx.x; e < n; e += NT) R0[e] = (T)0;
+}
+
 // Q = (L^T B^T B L + lambda H^T H) P for one item, all threads of the block:
 // L as a gather into the frame (zero on entry), B^T B in place (banded passes
 // for a rank-1 PSF, else the direct K x K form through Z), then L^T as a
 // gather over the transposed operator (fixed order, no atomics) fused with
-// lambda H^T H.  On return the frame holds B^T B L P; the caller zeroes it
-// again after a barrier.  Returns this thread's part of <P, Q>.
-template <typename T, int CKT, int NT>
+// lambda H^T H.  DIR selects the form (a kernel instantiation of each runs,
+// the one that does not match the problem returning at entry, so that the
+// banded kernels carry none of the direct form's registers).  On return the
+// frame holds B^T B L P (the direct form also
+// leaves z in the rows of the dilated box); the caller zeroes the rows of the
+// dilated box (clear_rows) after a barrier.  Returns this thread's part of
+// <P, Q>.
+template <typename T, int CKT, int NT, bool DIR>
 __device__ __forceinline__ double apply_normal(const OpView<T>& o, const T* __restrict__ P, T* __restrict__ Q) {
   gather_L<T, NT>(o, P);
   __syncthreads();
-  if (o.sep) {   // sep comes from a scalar load: uniform
+  if constexpr (!DIR) {   // the kernels of the banded form run only when the PSF is separable
     // w = B^T B y: banded pass along rows then along columns, in place
     const TapIdx ti(o.K);
     banded_pass<T, CKT, true>(o.F0, o.pitch, o.h, o.w, o.c0, o.nx, o.ck, o.taps + ti.ax, o.taps + ti.elx,
@@ -1568,15 +1721,14 @@ __device__ __forceinline__ double apply_normal(const OpView<T>& o, const T* __re
                                o.taps + ti.ery);
     __syncthreads();
   } else {
-    blur_box<T, CKT, NT>(o, o.Z);      // z = B y over the dilated region into global Z
+    forward_blur<T, CKT, NT>(o, o.Z);  // z = B y over the dilated region into global Z
     __syncthreads();
-    blur_T_mapped<T, NT>(o, o.Z);      // w = B^T z at the mapped pixels, back into the frame
-    __syncthreads();
+    adjoint_blur<T, CKT, NT>(o, o.Z);  // w = B^T z (at least) at the mapped pixels, in the frame
   }
   return gather_LT<T, NT, false>(o, P, Q);
 }
 
-template <typename T, int CKT, bool LDSF, bool PC>
+template <typename T, int CKT, bool LDSF, bool PC, bool DIR>
 __device__ __forceinline__ void run_item(const SolveArgs& a, const MemberInfo& mi, int m, int kl, unsigned char* smem) {
   constexpr int NT = kNTof<T>;   // threads of this block
   const int tid = threadIdx.x;
@@ -1605,7 +1757,7 @@ __device__ __forceinline__ void run_item(const SolveArgs& a, const MemberInfo& m
     F = reinterpret_cast<T*>(a.gframe) + (long)blockIdx.x * a.gframe_elems;
   T* const F0 = F + HALO * pitch + HALO;        // interior (0, 0) = image (r0, c0)
   T* const Frows = F + HALO * pitch;            // interior rows, contiguous
-  T* Z = reinterpret_cast<T*>(a.gz) + slot * J;
+  T* Z = reinterpret_cast<T*>(a.gz) + slot * 2L * J;   // z, then W = B^T z (direct blur)
   const int32_t* pix = a.pix_list + (long)m * a.slot_cap;
   const int32_t* cellp = a.cell + (long)m * a.slot_cap * n2;
   const T* fxp = reinterpret_cast<const T*>(a.fx) + (long)m * a.slot_cap * n2;
@@ -1659,12 +1811,13 @@ __device__ __forceinline__ void run_item(const SolveArgs& a, const MemberInfo& m
       st = SL_ST_OK;
       break;
     }
-    const OpView<T> ov{pix, cellp, fxp, fyp, F, F0, Z, taps, lt_rp, lt_e, a.lt_perm + (long)m * a.I_max, ns, I, M,
-                       r0, c0, h, w, pitch, fo, n2, nx, ny, K, ck, sell, Dr0, Dc0, Dh, Dw, sep, ident, inv_n2, lamT};
-    double pq = apply_normal<T, CKT, NT>(ov, P, Q);
+    const OpView<T> ov{pix, cellp, fxp, fyp, F, F0, Z, Z + J, taps, lt_rp, lt_e, a.lt_perm + (long)m * a.I_max, ns,
+                       I, M, r0, c0, h, w, pitch, fo, n2, nx, ny, K, ck, sell, Dr0, Dc0, Dh, Dw, sep, ident, inv_n2,
+                       lamT};
+    double pq = apply_normal<T, CKT, NT, DIR>(ov, P, Q);
     pq = block_sum1<NT / kWave>(pq, red, 0);
     // every gather has read the frame (barrier above): back to zero for the next iteration
-    for (int e = tid; e < h * pitch; e += NT) Frows[e] = (T)0;
+    clear_rows<T, CKT, NT, DIR>(ov);
     if (__builtin_amdgcn_readfirstlane((int)!(pq > 0.0))) {
       st = SL_ST_BREAKDOWN;
       break;
@@ -1792,25 +1945,26 @@ __device__ __forceinline__ int fetch_item(const SolveArgs& a, int xcd, int* sh_i
 // Persistent CG kernel: each block pulls (member, lambda) items from its XCD's
 // queue (then the others').  PC = true takes the preconditioned items that
 // k_split selected (FP32 only); PC = false all the others.
-template <typename T, int CKT, bool PC>
+template <typename T, int CKT, bool PC, bool DIR>
 __global__ void __launch_bounds__(kNTof<T>) k_solve(SolveArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int sh_item;
+  if (__builtin_amdgcn_readfirstlane(a.consts->sep) == (int)DIR) return;   // the other form's launch does the work
   const int xcd = blockIdx.x & 7;
   for (int item = fetch_item<PC>(a, xcd, &sh_item); item >= 0; item = fetch_item<PC>(a, xcd, &sh_item)) {
     const int m = item / a.n_lambda, kl = item % a.n_lambda;   // scalar
     const MemberInfo mi = a.minfo[m];                          // uniform address: scalar loads
     if constexpr (PC) {
-      run_item<T, CKT, true, true>(a, mi, m, kl, smem);
+      run_item<T, CKT, true, true, DIR>(a, mi, m, kl, smem);
     } else {
       const int status = __builtin_amdgcn_readfirstlane(mi.status);
       const int fits = __builtin_amdgcn_readfirstlane(mi.lds_frame);
       if (status != SL_ST_OK)
         trivial_item<T>(a, mi, m, kl);
       else if (fits)
-        run_item<T, CKT, true, false>(a, mi, m, kl, smem);
+        run_item<T, CKT, true, false, DIR>(a, mi, m, kl, smem);
       else
-        run_item<T, CKT, false, false>(a, mi, m, kl, smem);
+        run_item<T, CKT, false, false, DIR>(a, mi, m, kl, smem);
     }
   }
 }
@@ -1834,7 +1988,7 @@ __device__ __forceinline__ int fetch_counter(int* counter, int* sh_m) {
 // the second system by its own CG (see below).  Then gamma = <A^T bhat, xhat>
 // = bhat^T A xhat and dof = bhat^T bhat - gamma.  Per-block scratch (global):
 // r, xhat, rhat, phat and the saved p.
-template <typename T, int CKT, bool LDSF>
+template <typename T, int CKT, bool LDSF, bool DIR>
 __device__ __forceinline__ void run_mc_item(const SolveArgs& a, const MemberInfo& mi, int m, int kl,
                                             unsigned char* smem) {
   constexpr int NT = kNTof<T>;
@@ -1856,14 +2010,13 @@ __device__ __forceinline__ void run_mc_item(const SolveArgs& a, const MemberInfo
   double* red = reinterpret_cast<double*>(smem + a.red_off);
   T* F = LDSF ? reinterpret_cast<T*>(smem + a.frame_off) : reinterpret_cast<T*>(a.gframe) + slot * a.gframe_elems;
   T* const F0 = F + HALO * pitch + HALO;
-  T* const Frows = F + HALO * pitch;
   const int Dr0 = max(mi.r0 - ck, 0), Dr1 = min(mi.r1 + ck, ny - 1);
   const int Dc0 = max(mi.c0 - ck, 0), Dc1 = min(mi.c1 + ck, nx - 1);
   const OpView<T> ov{a.pix_list + (long)m * a.slot_cap, a.cell + (long)m * a.slot_cap * n2,
                      reinterpret_cast<const T*>(a.fx) + (long)m * a.slot_cap * n2,
                      reinterpret_cast<const T*>(a.fy) + (long)m * a.slot_cap * n2, F, F0,
-                     reinterpret_cast<T*>(a.gz) + slot * J, reinterpret_cast<const T*>(a.taps_t),
-                     a.lt_ptr + (long)m * (a.I_max + 65),
+                     reinterpret_cast<T*>(a.gz) + slot * 2L * J, reinterpret_cast<T*>(a.gz) + slot * 2L * J + J,
+                     reinterpret_cast<const T*>(a.taps_t), a.lt_ptr + (long)m * (a.I_max + 65),
                      reinterpret_cast<const LtEntry<T>*>(a.lt_ent) + (long)m * a.lt_cap, a.lt_perm + (long)m * a.I_max,
                      ns, I, M, r0, c0, h, w, pitch, -r0 * pitch - c0, n2, nx, ny, K, ck,
                      __builtin_amdgcn_readfirstlane(mi.sell), Dr0, Dc0, Dr1 - Dr0 + 1, Dc1 - Dc0 + 1,
@@ -1889,9 +2042,9 @@ __device__ __forceinline__ void run_mc_item(const SolveArgs& a, const MemberInfo
     const double stop2 = a.tol * a.tol * rr;
     for (int it = 0; it < a.maxit; ++it) {
       if (__builtin_amdgcn_readfirstlane((int)(rr <= stop2))) break;
-      double pq = apply_normal<T, CKT, NT>(ov, P, Q);
+      double pq = apply_normal<T, CKT, NT, DIR>(ov, P, Q);
       pq = block_sum1<NT / kWave>(pq, red, 0);
-      for (int e = tid; e < h * pitch; e += NT) Frows[e] = (T)0;
+      clear_rows<T, CKT, NT, DIR>(ov);
       if (__builtin_amdgcn_readfirstlane((int)!(pq > 0.0))) break;
       const T alT = (T)(rr / pq);
       double rn = 0.0;
@@ -1923,9 +2076,9 @@ __device__ __forceinline__ void run_mc_item(const SolveArgs& a, const MemberInfo
   for (int it = 0; it < a.maxit; ++it) {
     if (__builtin_amdgcn_readfirstlane((int)(rr <= stop2))) break;
     // data system: q = A p, alpha, r update, beta, new p (saved to global)
-    double pq = apply_normal<T, CKT, NT>(ov, P, Q);
+    double pq = apply_normal<T, CKT, NT, DIR>(ov, P, Q);
     pq = block_sum1<NT / kWave>(pq, red, 0);
-    for (int e = tid; e < h * pitch; e += NT) Frows[e] = (T)0;
+    clear_rows<T, CKT, NT, DIR>(ov);
     if (__builtin_amdgcn_readfirstlane((int)!(pq > 0.0))) break;
     const T alT = (T)(rr / pq);
     double rn = 0.0;
@@ -1942,10 +2095,10 @@ __device__ __forceinline__ void run_mc_item(const SolveArgs& a, const MemberInfo
     }
     __syncthreads();
     // second system with the same alpha and beta
-    double pqh = apply_normal<T, CKT, NT>(ov, P, Q);
+    double pqh = apply_normal<T, CKT, NT, DIR>(ov, P, Q);
     pqh = block_sum1<NT / kWave>(pqh, red, 0);   // its barrier: every gather has read P and the frame
     (void)pqh;
-    for (int e = tid; e < h * pitch; e += NT) Frows[e] = (T)0;
+    clear_rows<T, CKT, NT, DIR>(ov);
     for (int i = tid; i < I; i += NT) {
       const T ph = P[i];
       xh_g[i] += alT * ph;
@@ -1972,10 +2125,11 @@ __device__ __forceinline__ void run_mc_item(const SolveArgs& a, const MemberInfo
 // uses): a store under `threadIdx.x == 0` followed by `continue` was compiled
 // into an inner loop that thread 0's lane left to do the store while the
 // other lanes went on re-reading an item index that only thread 0 advances.
-template <typename T, int CKT>
+template <typename T, int CKT, bool DIR>
 __global__ void __launch_bounds__(kNTof<T>) k_mcdof(SolveArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int sh_m;
+  if (__builtin_amdgcn_readfirstlane(a.consts->sep) == (int)DIR) return;   // the other form's launch does the work
   for (int m = fetch_counter(&a.consts->mchead, &sh_m); m < a.n_members;
        m = fetch_counter(&a.consts->mchead, &sh_m)) {
     const MemberInfo mi = a.minfo[m];
@@ -1985,9 +2139,9 @@ __global__ void __launch_bounds__(kNTof<T>) k_mcdof(SolveArgs a) {
     } else {
       const int kl = __builtin_amdgcn_readfirstlane(a.k_star[m]);
       if (__builtin_amdgcn_readfirstlane(mi.lds_frame))
-        run_mc_item<T, CKT, true>(a, mi, m, kl, smem);
+        run_mc_item<T, CKT, true, DIR>(a, mi, m, kl, smem);
       else
-        run_mc_item<T, CKT, false>(a, mi, m, kl, smem);
+        run_mc_item<T, CKT, false, DIR>(a, mi, m, kl, smem);
     }
   }
 }
@@ -2036,24 +2190,24 @@ __device__ __forceinline__ void run_implicit_item(const SolveArgs& a, const Memb
   const int Dr0 = max(mi.r0 - ck, 0), Dr1 = min(mi.r1 + ck, ny - 1);
   const int Dc0 = max(mi.c0 - ck, 0), Dc1 = min(mi.c1 + ck, nx - 1);
   const int Dh = Dr1 - Dr0 + 1, Dw = Dc1 - Dc0 + 1;
-  T* __restrict__ Zq = reinterpret_cast<T*>(a.gz) + slot * J;     // q = A p on the dilated box
-  T* __restrict__ E = reinterpret_cast<T*>(a.ibuf) + slot * J;    // e on the dilated box
+  T* __restrict__ Zq = reinterpret_cast<T*>(a.gz) + slot * 2L * J;   // q = A p on the dilated box, then W
+  T* __restrict__ E = reinterpret_cast<T*>(a.ibuf) + slot * J;        // e on the dilated box
   const bool mc = sizeof(T) == 8 && a.mcn != nullptr;               // uniform: a kernel argument
   T* __restrict__ xh = reinterpret_cast<T*>(a.mcbuf) + slot * 5L * a.I_max;
   T* __restrict__ ph = xh + a.I_max;
   T* __restrict__ gh = ph + a.I_max;
-  T* __restrict__ Eh = reinterpret_cast<T*>(a.gz) + ((long)gridDim.x + slot) * J;   // ehat on the dilated box
+  T* __restrict__ Eh = reinterpret_cast<T*>(a.gz) + ((long)gridDim.x + slot) * 2L * J;   // ehat on the dilated box
   const double* bhm = a.bh + (long)m * a.I_max;
   const OpView<T> ov{a.pix_list + (long)m * a.slot_cap, a.cell + (long)m * a.slot_cap * n2,
                      reinterpret_cast<const T*>(a.fx) + (long)m * a.slot_cap * n2,
-                     reinterpret_cast<const T*>(a.fy) + (long)m * a.slot_cap * n2, F, F0, Zq,
+                     reinterpret_cast<const T*>(a.fy) + (long)m * a.slot_cap * n2, F, F0, Zq, Zq + J,
                      reinterpret_cast<const T*>(a.taps_t), a.lt_ptr + (long)m * (a.I_max + 65),
                      reinterpret_cast<const LtEntry<T>*>(a.lt_ent) + (long)m * a.lt_cap, a.lt_perm + (long)m * a.I_max,
                      ns, I, M, r0, c0, h, w, pitch, -r0 * pitch - c0, n2, nx, ny, K, ck,
                      __builtin_amdgcn_readfirstlane(mi.sell), Dr0, Dc0, Dh, Dw,
                      a.consts->sep != 0, true, (T)1 / (T)n2, (T)0};
-  // The frame is written only at the mapped pixels from here on (L p, then
-  // B^T e over the same pixels), so its halo and the unmapped entries stay zero.
+  // Frame: zero outside the mapped pixels whenever L p is gathered into it
+  // (the adjoint blur's other writes are cleared after each L^T gather).
   for (int e = tid; e < frame_elems; e += NT) F[e] = (T)0;
   const double* bm = a.b + (long)m * a.I_max;
   double gg = 0.0, din = 0.0;
@@ -2083,7 +2237,7 @@ __device__ __forceinline__ void run_implicit_item(const SolveArgs& a, const Memb
     if (__builtin_amdgcn_readfirstlane((int)(gg <= 0.0))) break;
     gather_L<T, NT>(ov, P);                               // frame = L p
     __syncthreads();
-    double qq = blur_box<T, CKT, NT>(ov, Zq);             // q = B L p
+    double qq = forward_blur<T, CKT, NT>(ov, Zq);         // q = B L p
     qq = block_sum1<NT / kWave>(qq, red, 0);
     if (__builtin_amdgcn_readfirstlane((int)!(qq > 0.0))) {
       st = SL_ST_BREAKDOWN;
@@ -2113,17 +2267,18 @@ __device__ __forceinline__ void run_implicit_item(const SolveArgs& a, const Memb
       a.iters[o] = k + 1;
       a.status[o] = SL_ST_OK;
     }
-    blur_T_mapped<T, NT>(ov, E);                          // frame = B^T e at the mapped pixels
-    __syncthreads();
+    adjoint_blur<T, CKT, NT>(ov, E);                      // frame = B^T e at the mapped pixels
     double gn = gather_LT<T, NT, true>(ov, P, G);         // g = L^T B^T e
     gn = block_sum1<NT / kWave>(gn, red, 1);
+    clear_rows<T, CKT, NT, true>(ov);                           // every gather has read the frame
     const T beta = (T)(gn / gg);
     for (int i = tid; i < I; i += NT) P[i] = G[i] + beta * P[i];
     gg = gn;
     if (mc) {   // the second system with this iteration's alpha and beta
-      gather_L<T, NT>(ov, ph);                            // every thread has read the frame (barrier above)
+      __syncthreads();                                    // the frame is clear again
+      gather_L<T, NT>(ov, ph);
       __syncthreads();
-      blur_box<T, CKT, NT>(ov, Zq);                       // A phat
+      forward_blur<T, CKT, NT>(ov, Zq);                   // A phat
       __syncthreads();
       double gam = 0.0;
       for (int i = tid; i < I; i += NT) {
@@ -2133,10 +2288,10 @@ __device__ __forceinline__ void run_implicit_item(const SolveArgs& a, const Memb
       }
       for (int e = tid; e < Dh * Dw; e += NT) Eh[e] -= alT * Zq[e];
       gam = block_sum1<NT / kWave>(gam, red, 0);          // its barrier: ehat complete
-      blur_T_mapped<T, NT>(ov, Eh);
-      __syncthreads();
+      adjoint_blur<T, CKT, NT>(ov, Eh);
       gather_LT<T, NT, true>(ov, ph, gh);                 // A^T ehat
       __syncthreads();
+      clear_rows<T, CKT, NT, true>(ov);
       for (int i = tid; i < I; i += NT) ph[i] = gh[i] + beta * ph[i];
       dof_last = a.consts->sum_n2 - gam;
       a.dofk[(long)m * K_it + k] = dof_last;              // the same value from every thread
@@ -2309,7 +2464,7 @@ static Layout make_layout(const sl_problem* pb, int max_ns, int M, int NL, int n
   L.s_all = take(sz * (size_t)M * NL * L.I_max);
   L.gframe_elems = (pb->img.ny + 4 * 16 + kSegR) * ((pb->img.nx + 4 * 16) | 1);   // widest window's halo
   L.gframe = take(sz * (size_t)n_wg * L.gframe_elems);
-  L.gz = take(sz * 2 * (size_t)n_wg * L.J);          // plain | preconditioned launch
+  L.gz = take(sz * 4 * (size_t)n_wg * L.J);          // [plain | preconditioned launch][slot]: z, B^T z
   L.rbuf = take(sz * 2 * (size_t)n_wg * L.I_max);
   L.mcbuf = take(sz * 5 * (size_t)n_wg * L.I_max);
   L.ibuf = take(sz * (size_t)n_wg * L.J);   // image residual of the implicit-regularisation solve
@@ -2347,12 +2502,15 @@ using SolveKernel = void (*)(SolveArgs);
 // Compiled banded-window sizes (CKT >= ck).  `wide` takes the next size up;
 // nullptr when that variant does not exist.
 // pc selects the preconditioned kernel of the same window size.
+template <bool DIR>
 static SolveKernel pick_kernel_f(int ck, bool wide, int* ckt, bool pc = false) {
   static const int sizes[] = {2, 4, 7, 10, 16};
-  static const SolveKernel ks[] = {k_solve<float, 2, false>, k_solve<float, 4, false>, k_solve<float, 7, false>,
-                                   k_solve<float, 10, false>, k_solve<float, 16, false>};
-  static const SolveKernel kp[] = {k_solve<float, 2, true>, k_solve<float, 4, true>, k_solve<float, 7, true>,
-                                   k_solve<float, 10, true>, k_solve<float, 16, true>};
+  static const SolveKernel ks[] = {k_solve<float, 2, false, DIR>, k_solve<float, 4, false, DIR>,
+                                   k_solve<float, 7, false, DIR>, k_solve<float, 10, false, DIR>,
+                                   k_solve<float, 16, false, DIR>};
+  static const SolveKernel kp[] = {k_solve<float, 2, true, DIR>, k_solve<float, 4, true, DIR>,
+                                   k_solve<float, 7, true, DIR>, k_solve<float, 10, true, DIR>,
+                                   k_solve<float, 16, true, DIR>};
   const SolveKernel* k = pc ? kp : ks;
   int i = 0;
   while (i < 5 && sizes[i] < ck) ++i;
@@ -2366,21 +2524,21 @@ static SolveKernel pick_kernel_f(int ck, bool wide, int* ckt, bool pc = false) {
 }
 
 // The Monte Carlo degrees-of-freedom kernel of the same bulk type and window as the solve.
-template <typename T>
+template <typename T, bool DIR>
 static SolveKernel pick_mc_kernel(int ckt) {
   if (sizeof(T) == 4) {
     switch (ckt) {
-      case 2: return k_mcdof<float, 2>;
-      case 4: return k_mcdof<float, 4>;
-      case 7: return k_mcdof<float, 7>;
-      case 10: return k_mcdof<float, 10>;
-      case 16: return k_mcdof<float, 16>;
+      case 2: return k_mcdof<float, 2, DIR>;
+      case 4: return k_mcdof<float, 4, DIR>;
+      case 7: return k_mcdof<float, 7, DIR>;
+      case 10: return k_mcdof<float, 10, DIR>;
+      case 16: return k_mcdof<float, 16, DIR>;
     }
   } else {
     switch (ckt) {
-      case 2: return k_mcdof<double, 2>;
-      case 7: return k_mcdof<double, 7>;
-      case 10: return k_mcdof<double, 10>;
+      case 2: return k_mcdof<double, 2, DIR>;
+      case 7: return k_mcdof<double, 7, DIR>;
+      case 10: return k_mcdof<double, 10, DIR>;
     }
   }
   return nullptr;
@@ -2407,9 +2565,11 @@ static SolveKernel pick_implicit_kernel(int ckt) {
   return nullptr;
 }
 
+template <bool DIR>
 static SolveKernel pick_kernel_d(int ck, bool wide, int* ckt) {
   static const int sizes[] = {2, 7, 10};
-  static const SolveKernel ks[] = {k_solve<double, 2, false>, k_solve<double, 7, false>, k_solve<double, 10, false>};
+  static const SolveKernel ks[] = {k_solve<double, 2, false, DIR>, k_solve<double, 7, false, DIR>,
+                                   k_solve<double, 10, false, DIR>};
   int i = 0;
   while (i < 3 && sizes[i] < ck) ++i;
   if (i == 3) {
@@ -2453,11 +2613,14 @@ static int side_stream(SideStream** out) {
   return SL_OK;
 }
 
+// Each solve kernel comes as a pair: the banded-blur form and the direct
+// form (suffix d); both are launched and the one that does not match the
+// problem returns at entry.
 struct LaunchCfg {
   SolveKernel kim = nullptr;   // implicit-regularisation solve (replaces k_split / k_solve)
-  SolveKernel ks = nullptr;
-  SolveKernel kpc = nullptr;   // preconditioned kernel, when some items may take it
-  SolveKernel kmc = nullptr;   // Monte Carlo degrees-of-freedom pass, when requested
+  SolveKernel ks = nullptr, ksd = nullptr;
+  SolveKernel kpc = nullptr, kpcd = nullptr;   // preconditioned kernels, when some items may take them
+  SolveKernel kmc = nullptr, kmcd = nullptr;   // Monte Carlo degrees-of-freedom pass, when requested
   size_t lds = 0, prep_lds = 0, corner_lds = 0;
 };
 
@@ -2467,8 +2630,11 @@ template <typename T>
 static int configure(SolveArgs& A, const Layout& L, const sl_tuning& v, LaunchCfg* c) {
   const size_t sz = sizeof(T);
   int ckt = 2;
-  SolveKernel ks = sizeof(T) == 4 ? pick_kernel_f(A.ck, v.wide_window != 0, &ckt)
-                                  : pick_kernel_d(A.ck, v.wide_window != 0, &ckt);
+  SolveKernel ks = sizeof(T) == 4 ? pick_kernel_f<false>(A.ck, v.wide_window != 0, &ckt)
+                                  : pick_kernel_d<false>(A.ck, v.wide_window != 0, &ckt);
+  int ckt_d = 2;
+  SolveKernel ksd = sizeof(T) == 4 ? pick_kernel_f<true>(A.ck, v.wide_window != 0, &ckt_d)
+                                   : pick_kernel_d<true>(A.ck, v.wide_window != 0, &ckt_d);
   if (!ks) {
     set_error("kernel variant does not exist for this PSF size and dtype");
     return SL_ENOIMPL;
@@ -2490,22 +2656,25 @@ static int configure(SolveArgs& A, const Layout& L, const sl_tuning& v, LaunchCf
   SL_REQUIRE(lds > fixed + 64 * sz, "source grid too large for LDS");
   A.lds_frame_cap = (int)((lds - fixed) / sz);
   c->ks = ks;
+  c->ksd = ksd;
   if (sizeof(T) == 4 && A.reg == SL_H_CURVATURE && !A.plain_cg && !A.implicit) {
     int ckt2 = 0;
-    c->kpc = pick_kernel_f(A.ck, v.wide_window != 0, &ckt2, true);
+    c->kpc = pick_kernel_f<false>(A.ck, v.wide_window != 0, &ckt2, true);
+    c->kpcd = pick_kernel_f<true>(A.ck, v.wide_window != 0, &ckt2, true);
   }
   c->lds = lds;
   if (A.implicit) {
     c->kim = pick_implicit_kernel<T>(ckt);
-    c->kpc = nullptr;
+    c->kpc = c->kpcd = nullptr;
     if (!c->kim) {
       set_error("no implicit-regularisation kernel for window %d", ckt);
       return SL_ENOIMPL;
     }
   }
   if (A.mcn && !A.implicit) {   // the implicit solve runs its own lockstep system
-    c->kmc = pick_mc_kernel<T>(ckt);
-    if (!c->kmc) {
+    c->kmc = pick_mc_kernel<T, false>(ckt);
+    c->kmcd = pick_mc_kernel<T, true>(ckt);
+    if (!c->kmc || !c->kmcd) {
       set_error("no Monte Carlo degrees-of-freedom kernel for window %d", ckt);
       return SL_ENOIMPL;
     }
@@ -2519,16 +2688,25 @@ static int configure(SolveArgs& A, const Layout& L, const sl_tuning& v, LaunchCf
   c->corner_lds = sizeof(double) * (A.n_lambda * A.n_lambda + 12 * A.n_lambda + 16);
   static std::mutex mu;
   std::lock_guard<std::mutex> g(mu);
-  SL_HIP(hipFuncSetAttribute((const void*)ks, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  if (c->kpc)
-    SL_HIP(hipFuncSetAttribute((const void*)c->kpc, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  if (c->kmc)
-    SL_HIP(hipFuncSetAttribute((const void*)c->kmc, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  for (SolveKernel k : {c->ks, c->ksd, c->kpc, c->kpcd, c->kmc, c->kmcd})
+    if (k) SL_HIP(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   if (c->kim)
     SL_HIP(hipFuncSetAttribute((const void*)c->kim, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   SL_HIP(hipFuncSetAttribute((const void*)k_prep<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)c->prep_lds));
   return SL_OK;
+}
+
+// Launches the banded and the direct form of a persistent kernel on st, the
+// banded one first; the one that does not match the problem (the separability
+// flag k_setup leaves in the workspace) returns at entry.
+template <typename T>
+static int launch_pair(SolveKernel kb, SolveKernel kd, const Layout& L, const LaunchCfg& c, hipStream_t st,
+                       const SolveArgs& A, const char* what) {
+  hipLaunchKernelGGL(kb, dim3(L.n_wg), dim3(kNTof<T>), c.lds, st, A);
+  if (int e = check_launch(what)) return e;
+  hipLaunchKernelGGL(kd, dim3(L.n_wg), dim3(kNTof<T>), c.lds, st, A);
+  return check_launch(what);
 }
 
 // Enqueues the launches of one solve on st: k_setup, k_prep, [k_split], the
@@ -2572,16 +2750,13 @@ static int enqueue(const SolveArgs& A, const LamList& lams, const Layout& L, con
       if (int e = side_stream(&ss)) return e;
     }
     SL_HIP(hipEventRecord(ss->fork, st));
-    hipLaunchKernelGGL(c.ks, dim3(L.n_wg), dim3(kNTof<T>), c.lds, st, A);
-    if (int e = check_launch("k_solve")) return e;
+    if (int e = launch_pair<T>(c.ks, c.ksd, L, c, st, A, "k_solve")) return e;
     SL_HIP(hipStreamWaitEvent(ss->s, ss->fork, 0));
-    hipLaunchKernelGGL(c.kpc, dim3(L.n_wg), dim3(kNTof<T>), c.lds, ss->s, A);
-    if (int e = check_launch("k_solve (preconditioned)")) return e;
+    if (int e = launch_pair<T>(c.kpc, c.kpcd, L, c, ss->s, A, "k_solve (preconditioned)")) return e;
     SL_HIP(hipEventRecord(ss->join, ss->s));
     SL_HIP(hipStreamWaitEvent(st, ss->join, 0));
   } else {
-    hipLaunchKernelGGL(c.ks, dim3(L.n_wg), dim3(kNTof<T>), c.lds, st, A);
-    if (int e = check_launch("k_solve")) return e;
+    if (int e = launch_pair<T>(c.ks, c.ksd, L, c, st, A, "k_solve")) return e;
   }
   if (e1) {
     SL_HIP(hipEventRecord(e1, st));
@@ -2590,10 +2765,7 @@ static int enqueue(const SolveArgs& A, const LamList& lams, const Layout& L, con
   }
   hipLaunchKernelGGL(k_corner<T>, dim3(A.n_members), dim3(256), c.corner_lds, st, A);
   if (int e = check_launch("k_corner")) return e;
-  if (c.kmc) {
-    hipLaunchKernelGGL(c.kmc, dim3(L.n_wg), dim3(kNTof<T>), c.lds, st, A);
-    return check_launch("k_mcdof");
-  }
+  if (c.kmc) return launch_pair<T>(c.kmc, c.kmcd, L, c, st, A, "k_mcdof");
   return SL_OK;
 }
 

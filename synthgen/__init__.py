@@ -181,3 +181,23 @@ def mc_draws(seed: int, ny: int, nx: int) -> np.ndarray:
     Monte Carlo degrees-of-freedom estimate, drawn once and handed to both sides."""
     rng = np.random.default_rng(seed + 1000)
     return rng.standard_normal((ny, nx))
+
+
+def sinc_moffat_psf(K: int, fwhm_px: float = 3.0, q: float = 0.7, pa: float = 0.6, beta: float = 2.5,
+                    sinc_period_px: float = 6.0) -> np.ndarray:
+    """A non-separable K x K PSF of the kind the paper's large test uses
+    (Sec. 4): an elliptical Moffat profile (axis ratio q, major axis at angle
+    pa from +x, FWHM fwhm_px along the major axis, index beta) times the
+    square of a radial sinc (so that it stays non-negative), sampled at pixel
+    centres about (K-1)/2 and normalised to sum 1.
+    Rotated and elliptical, so it is not rank 1 and takes the direct blur."""
+    ck = (K - 1) / 2.0
+    a = np.arange(K) - ck
+    x, y = np.meshgrid(a, a)
+    c, s = np.cos(pa), np.sin(pa)
+    u, v = c * x + s * y, -s * x + c * y
+    alpha = fwhm_px / (2.0 * np.sqrt(2.0 ** (1.0 / beta) - 1.0))
+    moffat = (1.0 + (u * u + (v / q) ** 2) / (alpha * alpha)) ** (-beta)
+    r = np.hypot(x, y)
+    P = moffat * np.sinc(r / sinc_period_px) ** 2
+    return P / P.sum()

@@ -24,7 +24,14 @@ root:  python tests/golden/make_golden.py   (about two minutes on 8 cores)
   ||H s||^2, iterations, corner and corner solution (about two minutes on
   3 cores).
 
+* c2_radial.npz  -- the c2 lens and image with a non-separable 15x15 PSF
+  (synthgen.sinc_moffat_psf: elliptical Moffat times a squared radial sinc),
+  so that the solve takes the direct K x K blur: chi^2, ||H s||^2,
+  iterations, corner, and the solution at every lambda in FP32 (about a
+  minute on 8 cores).
+
 `python tests/golden/make_golden.py c4` writes only c4_sample.npz;
+`python tests/golden/make_golden.py c2radial` writes only c2_radial.npz;
 `python tests/golden/make_golden.py c3full` writes only c3_full.npz;
 `python tests/golden/make_golden.py c2nsub` writes only c2_nsub.npz.
 """
@@ -117,7 +124,31 @@ def c2_nsub():
                         s_corner=np.stack([o["s"][0, k] for o, k in zip(outs, ks)]))
 
 
+def c2_radial():
+    import concurrent.futures as cf
+    w = synthgen.C2
+    D = mock.workload_data(w)
+    psf = synthgen.sinc_moffat_psf(w.k_psf)
+
+    def one(lam):
+        return coracle.evaluate(np.atleast_2d(D["lens"]), [w.ns], w.half_width, w.nx, w.ny, w.pix, w.nsub_model,
+                                D["d"], D["sigma"], psf, w.reg, [lam], tol=1e-10, want_s=True, threads=1)
+
+    with cf.ThreadPoolExecutor(8) as ex:
+        outs = list(ex.map(one, w.lambdas))
+    chi2 = np.array([o["chi2"][0, 0] for o in outs])
+    reg = np.array([o["reg"][0, 0] for o in outs])
+    k = lcurve.corner(reg, chi2)[0]
+    np.savez_compressed(os.path.join(HERE, "c2_radial.npz"), psf=psf, lambdas=np.array(w.lambdas), chi2=chi2,
+                        reg=reg, iters=np.array([o["iters"][0, 0] for o in outs]), k_star=k,
+                        s=np.stack([o["s"][0, 0] for o in outs]).astype(np.float32),
+                        s_corner=outs[k]["s"][0, 0])
+
+
 def main():
+    if sys.argv[1:] == ["c2radial"]:
+        c2_radial()
+        return
     if sys.argv[1:] == ["c2nsub"]:
         c2_nsub()
         return

@@ -299,3 +299,37 @@ def test_plan_capture_beside_eager_solves(sl):
 
     assert all(same(got, ref_a) for got in got_a)
     assert same(_np(out_b), ref_b)
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_c2_radial_psf_direct_blur_vs_oracle(sl, dtype):
+    """The direct K x K blur at the c2 size: the c2 lens and image with a
+    non-separable 15x15 PSF (elliptical Moffat times a squared radial sinc,
+    the kind of PSF of the paper's Sec. 4 large test), against the oracle
+    (tests/golden/c2_radial.npz, FP64 CG to 1e-10).  FP32: chi^2 within 1e-5
+    at every lambda, ||H s||^2 within 1e-3 from k* - 2, the corner solution
+    within 1e-4; FP64 (CG to 1e-10): 1e-9, 1e-7 and 1e-7."""
+    g = np.load(os.path.join(GOLD, "c2_radial.npz"))
+    psf = g["psf"]
+    assert np.linalg.svd(psf, compute_uv=False)[1] > 1e-3 * psf.max()   # not rank 1: the direct form runs
+    w = synthgen.C2
+    z = np.load(os.path.join(HERE, "data", "c2.npz"))
+    solver = sl.Solver(torch.tensor(z["d"], device=DEV), float(z["sigma"]), torch.tensor(psf, device=DEV),
+                       sl.Grid(w.nx, w.ny, w.pix, w.nsub_model), w.half_width, reg=w.reg, dtype=dtype)
+    f64 = dtype == torch.float64
+    out = _np(solver.solve_semilinear(torch.tensor(np.atleast_2d(z["lens"]), device=DEV),
+                                      torch.tensor([w.ns], dtype=torch.int32, device=DEV), w.lambdas,
+                                      tol=1e-10 if f64 else 1e-7, maxit=4000))
+    assert np.all(out["status"] == 0) and out["corner_status"][0] == 0
+    rel = np.abs(out["chi2"][0] - g["chi2"]) / g["chi2"]
+    assert rel.max() <= (1e-9 if f64 else 1e-5), rel
+    k = int(out["k_star"][0])
+    assert k == lcurve.corner(out["reg"][0], out["chi2"][0])[0]
+    assert k in lcurve.corner_set(g["reg"], g["chi2"]) | {int(g["k_star"])}, (k, int(g["k_star"]))
+    lo = max(0, min(k, int(g["k_star"])) - 2)
+    rr = np.abs(out["reg"][0, lo:] - g["reg"][lo:]) / g["reg"][lo:]
+    assert rr.max() <= (1e-7 if f64 else 1e-3), rr
+    s_ref = g["s_corner"] if k == int(g["k_star"]) else g["s"][k].astype(np.float64)
+    err = np.linalg.norm(out["s_corner"][:w.ns * w.ns] - s_ref) / np.linalg.norm(s_ref)
+    assert err <= (1e-7 if f64 and k == int(g["k_star"]) else 1e-4), err
+    print(f"radial PSF {dtype}: chi2 max rel {rel.max():.2e}, reg max rel {rr.max():.2e}, s rel {err:.2e}")
