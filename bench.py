@@ -32,6 +32,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "lens-model evals/s (128² image, 16-λ L-curve) vs plain; χ² rel err vs FP64"
 PEAK_FP32_TFLOPS = 157.3
+PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 SOLVE_SRC = os.path.join(ROOT, "paper_1101_5803_amd", "csrc", "solve.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_solve_c3_hbm_traffic.txt")
@@ -83,6 +84,11 @@ def parse():
     ap.add_argument("--cpu-members", type=int, default=0, help="oracle sample size (default: one per host core, "
                                                                 "at most 16)")
     ap.add_argument("--no-autotune", action="store_true", help="default kernel variant instead of the autotuned one")
+    ap.add_argument("--dtype", default="f32", choices=["f32", "f64"],
+                    help="bulk arithmetic of the timed solve (f32: FP32 with FP64 reductions)")
+    ap.add_argument("--psf", default="gauss", choices=["gauss", "sinc-moffat"],
+                    help="gauss: the workload's Gaussian PSF (separable: banded blur); sinc-moffat: a non-separable "
+                         "PSF of the same size (direct K x K blur)")
     ap.add_argument("--search", action="store_true",
                     help="instead of the throughput line: plain vs surrogate-screened GA on the c5 settings")
     ap.add_argument("--search-seeds", type=int, default=3)
@@ -98,7 +104,7 @@ def parse():
     return ap.parse_args()
 
 
-def algorithmic_work(info, iters, nsub, ck):
+def algorithmic_work(info, iters, nsub, ck, elem=4, direct=False):
     """Bytes and flops of the CG phase (the persistent kernels) for one step.
 
     The unit of work is one member's CG iteration.  Its algorithmic bytes are
@@ -117,6 +123,9 @@ def algorithmic_work(info, iters, nsub, ck):
     for a mapped bounding box of h x w pixels.  Preconditioned iterations read
     the same tables and count the same; the sine transforms of their
     preconditioner run in LDS on MFMA and their 8 n^3 flops are not counted.
+    With the direct blur (a non-separable PSF) the blur term is
+    2 K^2 ((h + 2ck)(w + 2ck) + h w) instead.  elem = 8 (FP64 bulk) doubles
+    every FP32 vector and table term.
     """
     n2 = nsub * nsub
     flops = 0.0
@@ -128,9 +137,11 @@ def algorithmic_work(info, iters, nsub, ck):
             continue
         h, w = r1 - r0 + 1, c1 - c0 + 1
         it = float(iters[m].sum())
-        flops += it * (2 * (4 * ck + 1) * h * w * 2 + 2 * 12 * M * n2 + 23 * I)
-        nbytes += it * (16.0 * M * n2 + 8.0 * M + 56.0 * I)
-        tbytes += it * (2 * M * (4 + 12 * n2))
+        K = 2 * ck + 1
+        blur = (2 * K * K * ((h + 2 * ck) * (w + 2 * ck) + h * w)) if direct else (2 * (4 * ck + 1) * h * w * 2)
+        flops += it * (blur + 2 * 12 * M * n2 + 23 * I)
+        nbytes += it * (16.0 * M * n2 + 8.0 * M + 56.0 * I) * (elem / 4.0)
+        tbytes += it * (2 * M * (4 + 12 * n2)) * (elem / 4.0)
     return nbytes, tbytes, flops
 
 
@@ -225,9 +236,17 @@ def main():
         max_ns = w.ns
         desc = ("c4: 1024 SIE+shear lens sets, 200x200 image at 0.05\", 2x2 subpixels, 100x100 source nodes over "
                 "+-1\", 21x21 Gaussian PSF (FWHM 4 px), curvature H, 24 lambdas 1e-4..1e2, CG tol 1e-7")
+    f64 = args.dtype == "f64"
+    psf = z["psf"]
+    if args.psf == "sinc-moffat":
+        psf = synthgen.sinc_moffat_psf(w.k_psf)
+        desc = desc.replace("Gaussian PSF", "non-separable sinc x elliptical-Moffat PSF (direct blur)")
+        desc = desc.replace(" (FWHM 3 px)", "").replace(" (FWHM 4 px)", "")
+    if f64:
+        desc = desc.replace("CG tol 1e-7", "CG tol 1e-7, FP64 throughout")
     grid = sl.Grid(w.nx, w.ny, w.pix, w.nsub_model)
-    solver = sl.Solver(torch.tensor(z["d"], device=dev), float(z["sigma"]), torch.tensor(z["psf"], device=dev),
-                       grid, w.half_width, reg=w.reg, dtype=torch.float32)
+    solver = sl.Solver(torch.tensor(z["d"], device=dev), float(z["sigma"]), torch.tensor(psf, device=dev),
+                       grid, w.half_width, reg=w.reg, dtype=torch.float64 if f64 else torch.float32)
     lens_d = torch.tensor(pop, device=dev)
     ns_d = torch.tensor(grids, device=dev)
     out = solver.alloc_result(M * max_ns * max_ns, M, len(w.lambdas))
@@ -237,7 +256,7 @@ def main():
 
     def step():
         # one evaluation of every member: the solve, and its fitness (chi^2, k*) back on the host
-        solver.solve_semilinear(lens_d, ns_d, w.lambdas, tol=w.tol, maxit=4000, max_ns=max_ns, out=out)
+        solver.solve_semilinear(lens_d, ns_d, w.lambdas, tol=w.tol, maxit=4000, max_ns=max_ns, out=out, tuning={})
         chi2_h.copy_(out["chi2"], non_blocking=True)
         k_h.copy_(out["k_star"], non_blocking=True)
 
@@ -248,11 +267,6 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    tuned = None
-    if not args.no_autotune:
-        tuned, tms, _ = solver.autotune(lens_d, ns_d, w.lambdas, tol=w.tol, maxit=4000, max_ns=max_ns, out=out)
-        print(f"[bench] autotune: best {tuned}, ms per variant {[round(t, 2) for t in tms]}", file=sys.stderr,
-              flush=True)
     print(f"[bench] warmup {args.warmup} step(s) of {M} members", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         step()
@@ -272,23 +286,40 @@ def main():
     iters = out["iters"].cpu().numpy()
     status = out["status"].cpu().numpy()
     info = solver.member_info(max_ns, M, len(w.lambdas))
-    abytes, tbytes, flops = algorithmic_work(info, iters, w.nsub_model, (w.k_psf - 1) // 2)
+    abytes, tbytes, flops = algorithmic_work(info, iters, w.nsub_model, (w.k_psf - 1) // 2, 8 if f64 else 4,
+                                             args.psf != "gauss")
     kern_s = kern_ms / max(launches, 1) / 1e3
     tflops = flops / kern_s / 1e12
     gbs = abytes / kern_s / 1e9
-    traffic = measured_traffic() if args.workload == "c3" else None
+    traffic = measured_traffic() if args.workload == "c3" and not f64 and args.psf == "gauss" else None
     roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": traffic,
             "kernel": "CG phase: k_split, then the plain and the preconditioned persistent k_solve side by side",
             "kernel_ms": round(kern_s * 1e3, 3), "launches_timed": launches,
             "algorithmic_bytes": abytes,
-            "byte_model": "per member CG iteration 16 M n^2 + 8 M + 56 I (M mapped pixels, n^2 subpixels, I nodes)",
+            "byte_model": "per member CG iteration 16 M n^2 + 8 M + 56 I (M mapped pixels, n^2 subpixels, I nodes)"
+                          + (", doubled for FP64" if f64 else ""),
             "table_encoding_bytes": tbytes, "table_encoding_GBps": round(tbytes / kern_s / 1e9, 1),
             "measured_hbm_GBps": round(traffic / kern_s / 1e9, 1) if traffic else None,
             "measured_hbm_frac": round(traffic / kern_s / 1e9 / PEAK_HBM_GBS, 4) if traffic else None,
             "fp32_TFLOPs": round(tflops, 3), "fp32_frac": round(tflops / PEAK_FP32_TFLOPS, 4)}
+    if f64:
+        roof["fp64_TFLOPs"] = roof.pop("fp32_TFLOPs")
+        roof["fp64_frac"] = round(tflops / PEAK_FP64_TFLOPS, 4)
+        roof.pop("fp32_frac")
+    # the autotuner's table on the same problem, after the timed region (the timed steps run the default
+    # variant, the one the committed counter profiles describe)
+    tune = None
+    if not args.no_autotune:
+        os.environ.setdefault("SL_AUTOTUNE_VERBOSE", "1")
+        print("[bench] autotune", file=sys.stderr, flush=True)
+        tout = solver.alloc_result(M * max_ns * max_ns, M, len(w.lambdas))
+        tuned, tms, _ = solver.autotune(lens_d, ns_d, w.lambdas, tol=w.tol, maxit=4000, max_ns=max_ns, out=tout)
+        tune = {"best": tuned, "ms_per_variant": [round(t, 2) for t in tms],
+                "best_vs_default": round(min(t for t in tms if t > 0) / tms[0], 4) if tms[0] > 0 else None}
+        del tout
     # the same step replayed from a captured HIP graph
-    plan = solver.plan(lens_d, ns_d, w.lambdas, tol=w.tol, maxit=4000, max_ns=max_ns, out=out)
+    plan = solver.plan(lens_d, ns_d, w.lambdas, tol=w.tol, maxit=4000, max_ns=max_ns, out=out, tuning={})
     plan.launch()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -297,7 +328,8 @@ def main():
     torch.cuda.synchronize()
     graph_ms = 1e3 * (time.perf_counter() - t0) / args.steps
     plan.close()
-    prec = precision_vs_f64(sl, torch, z, grid, w, dev, pop, grids, out, max_ns)
+    prec = None if f64 or args.psf != "gauss" else precision_vs_f64(sl, torch, z, grid, w, dev, pop, grids, out,
+                                                                     max_ns)
     mc = mc_dof_step(sl, torch, solver, lens_d, ns_d, w, max_ns, M, args.steps)
     imp = implicit_step(torch, solver, lens_d, ns_d, max_ns, M, args.steps)
     # plain: the same library, one member per call
@@ -307,20 +339,21 @@ def main():
     rec = {
         "metric": METRIC, "value": round(value, 2), "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "vs_baseline": None, "dtype": args.dtype, "data": "synthetic",
         "config": {"workload": desc,
-                   "members": M, "n_lambda": len(w.lambdas), "reductions": "f64", "kernel_variant": tuned,
+                   "members": M, "n_lambda": len(w.lambdas), "reductions": "f64", "kernel_variant": "default",
                    "cg_iterations": int(iters.sum()),
                    "status_counts": {int(k): int(v) for k, v in zip(*np.unique(status, return_counts=True))}},
         "plain_value": round(plain_value, 3) if plain_value else None,
         "vs_plain": round(value / plain_value, 2) if plain_value else None,
         "graph_ms_per_step": round(graph_ms, 3),
         "chi2_rel_err_vs_f64": prec,
+        "autotune": tune,
         "mc_dof": mc,
         "implicit": imp,
         "roofline": roof,
     }
-    if not args.no_cpu_baseline and args.workload == "c3":
+    if not args.no_cpu_baseline and args.workload == "c3" and not f64 and args.psf == "gauss":
         print(f"[bench] cpu baseline: oracle on the host cores", file=sys.stderr, flush=True)
         gpu = (out["chi2"].cpu().numpy(), out["reg"].cpu().numpy(), out["k_star"].cpu().numpy(),
                out["s_corner"].cpu().numpy(), out["s_off"].cpu().numpy())
@@ -355,12 +388,13 @@ def mc_dof_step(sl, torch, solver, lens_d, ns_d, w, max_ns, M, steps):
     print("[bench] Monte Carlo degrees of freedom", file=sys.stderr, flush=True)
     noise = torch.tensor(synthgen.mc_draws(w.seed, w.ny, w.nx).reshape(-1), device=lens_d.device)
     out = solver.alloc_result(M * max_ns * max_ns, M, len(w.lambdas))
-    solver.solve_semilinear(lens_d, ns_d, w.lambdas, tol=w.tol, maxit=4000, max_ns=max_ns, out=out, mc_noise=noise)
+    solver.solve_semilinear(lens_d, ns_d, w.lambdas, tol=w.tol, maxit=4000, max_ns=max_ns, out=out, mc_noise=noise,
+                            tuning={})
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
         solver.solve_semilinear(lens_d, ns_d, w.lambdas, tol=w.tol, maxit=4000, max_ns=max_ns, out=out,
-                                mc_noise=noise)
+                                mc_noise=noise, tuning={})
     torch.cuda.synchronize()
     ms = 1e3 * (time.perf_counter() - t0) / steps
     dof = out["dof"].cpu().numpy()

@@ -166,6 +166,10 @@ typedef struct {
   int blur_direct;     /* 1: direct K x K blur even when the PSF is separable */
   int plain_cg;        /* 1: plain CG even where the spectral preconditioner applies (see
                           sl_solve_semilinear); not part of the autotuner's search */
+  int pc_theta_pct;    /* preconditioner threshold theta in percent: items with
+                          lambda >= theta c take it (see sl_solve_semilinear); 0: 15 */
+  int heavy;           /* count of each member's smallest lambdas queued ahead of the
+                          other lambdas (their solves take the most iterations); 0: 4 */
 } sl_tuning;
 
 typedef struct {
@@ -275,17 +279,24 @@ int sl_solve_implicit(const sl_problem* pb, const double* lens, const int32_t* n
                       size_t workspace_bytes, sl_result* out, void* stream);
 
 /*
- * Autotuner: runs the solve once per kernel variant (after one untimed run
- * of each), timing each with HIP events on `stream`, and records the fastest
- * for this problem signature (dtype, image size, subpixels, PSF size,
- * regulariser, max_ns, n_members, n_lambda) in a process-wide table that
- * later calls with opt->tuning == NULL consult.  Synchronous.  Arguments are
- * those of sl_solve_semilinear; on return `out` holds the best variant's
- * results, *best (nullable) its settings and ms (nullable, host
+ * Autotuner: a staged search over the solve's settings.  Variants 0..7 are
+ * the structural switches (wide_window, lt_csr, blur_direct as the bits of
+ * the index) at the default threshold and queue order; variants 8..11 set
+ * pc_theta_pct to 5, 10, 25, 40 on the best of 0..7 (FP32 with curvature H
+ * only: elsewhere the preconditioner never runs); variants 12..15 set heavy
+ * to 2, 3, 6, 8 on the best of 0..11.  Each variant runs once untimed and
+ * twice timed with HIP events on `stream` (the faster counts).  The fastest
+ * is recorded for this problem signature (dtype, image size, subpixels, PSF
+ * size, regulariser, max_ns, n_members, n_lambda) in a process-wide table
+ * that later calls with opt->tuning == NULL consult.  Synchronous.  With the
+ * environment variable SL_AUTOTUNE_VERBOSE=1 it prints one line per variant
+ * to stderr as that variant is timed.
+ * Arguments are those of sl_solve_semilinear; on return `out` holds the best
+ * variant's results, *best (nullable) its settings and ms (nullable, host
  * double[SL_N_VARIANTS]) each variant's time, or -1 for a variant that does
- * not exist for this PSF size and dtype.
+ * not exist for this PSF size and dtype or was skipped.
  */
-#define SL_N_VARIANTS 8
+#define SL_N_VARIANTS 16
 int sl_solve_autotune(const sl_problem* pb, const double* lens, const int32_t* ns, int max_ns,
                       int n_members, const double* lambdas, int n_lambda,
                       const sl_solve_opts* opt, void* workspace, size_t workspace_bytes,

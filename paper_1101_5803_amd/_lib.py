@@ -41,7 +41,7 @@ class Problem(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("wide_window", ctypes.c_int), ("lt_csr", ctypes.c_int), ("blur_direct", ctypes.c_int),
-                ("plain_cg", ctypes.c_int)]
+                ("plain_cg", ctypes.c_int), ("pc_theta_pct", ctypes.c_int), ("heavy", ctypes.c_int)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -49,7 +49,7 @@ class SolveOpts(ctypes.Structure):
                 ("mc_noise", ctypes.c_void_p)]
 
 
-N_VARIANTS = 8
+N_VARIANTS = 16
 
 
 class Result(ctypes.Structure):

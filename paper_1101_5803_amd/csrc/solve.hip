@@ -37,6 +37,8 @@
 #include <array>
 #include <map>
 #include <climits>
+#include <cstdio>
+#include <cstdlib>
 #include <mutex>
 #include <vector>
 
@@ -55,8 +57,8 @@ constexpr int kSegR = 4;       // outputs per lane in a banded pass
 constexpr int kUpd = 4;        // CG vector-update chunk (nodes per thread)
 // The spectral preconditioner pays for its four n x n transforms only where
 // lambda H^T H dominates the spectrum: it is used when lambda >= kPcTheta c.
-constexpr float kPcTheta = 0.15f;
-constexpr int kHeavy = 4;      // smallest lambdas of each member queued ahead of the rest
+constexpr int kPcThetaPct = 15;   // default theta = 0.15 (sl_tuning.pc_theta_pct = 0)
+constexpr int kHeavy = 4;      // default count of smallest lambdas of each member queued ahead of the rest
 constexpr int kMaxCK = 31;
 
 struct alignas(16) MemberInfo {
@@ -166,6 +168,8 @@ struct SolveArgs {
   int force_direct; // variant: direct K x K blur for a separable PSF
   int prep_tags;    // k_prep has one LDS int per node after its 8 I_max + 768 bytes (conflict tags)
   int implicit;     // implicit regularisation: n_lambda unregularised CG iterations (k_implicit)
+  int heavy;        // smallest lambdas of each member queued ahead of the rest
+  float pc_theta;   // items with lambda >= pc_theta c take the spectral preconditioner
   int plain_cg;     // variant: no spectral preconditioner
   // Monte Carlo degrees of freedom (Sec. 2.5), when mcn is not NULL
   const double* mcn; // [ny*nx] Gaussian draws bhat
@@ -237,7 +241,7 @@ __global__ void __launch_bounds__(1024) k_setup(SolveArgs a, LamList lams) {
       start += c;
     }
     // rank r -> queue r % 8; the sort is stable in member index.  Within a
-    // queue the kHeavy smallest lambdas of every member come first (their
+    // queue the `heavy` smallest lambdas of every member come first (their
     // solves take the most CG iterations, so starting them early shortens
     // the tail of the launch), then the other lambdas; both parts keep the
     // members in order, so the blocks of an XCD share few members at a time
@@ -248,7 +252,7 @@ __global__ void __launch_bounds__(1024) k_setup(SolveArgs a, LamList lams) {
       const int r = counts[key]++;
       const int q = r & 7, t = r >> 3;
       const int nmq = (M - q + 7) / 8;   // members in queue q
-      const int H = a.n_lambda < kHeavy ? a.n_lambda : kHeavy;
+      const int H = a.n_lambda < a.heavy ? a.n_lambda : a.heavy;
       for (int k = 0; k < a.n_lambda; ++k)
         a.queues[q * a.qcap + (k < H ? t * H + k : nmq * H + t * (a.n_lambda - H) + (k - H))] = m * a.n_lambda + k;
     }
@@ -2343,7 +2347,7 @@ __global__ void __launch_bounds__(kNTof<T>) k_implicit(SolveArgs a) {
 
 // Moves the items that take the spectral preconditioner into their own queues
 // (stable, per XCD queue): valid member, FP32, curvature H, frame in LDS with
-// room for the n x n scratch, and lambda >= kPcTheta c.  One block.
+// room for the n x n scratch, and lambda >= pc_theta c.  One block.
 template <typename T>
 __global__ void __launch_bounds__(64) k_split(SolveArgs a) {
   const int q = threadIdx.x;
@@ -2356,7 +2360,7 @@ __global__ void __launch_bounds__(64) k_split(SolveArgs a) {
       const double lam = a.lamv[item % a.n_lambda];
       const bool fits = mi.lds_frame != 0;
       const bool pc = sizeof(T) == 4 && a.reg == SL_H_CURVATURE && !a.plain_cg && mi.status == SL_ST_OK && fits &&
-                      mi.ns * mi.ns <= a.lds_frame_cap && lam >= (double)kPcTheta * mi.pc_c;
+                      mi.ns * mi.ns <= a.lds_frame_cap && lam >= (double)a.pc_theta * mi.pc_c;
       // Both stores unconditionally, then bump one count: the store not
       // taken lands at or past its queue's final count, where nothing reads.
       // (The if/else form selected the base pointer per lane, and hipcc put
@@ -2643,6 +2647,8 @@ static int configure(SolveArgs& A, const Layout& L, const sl_tuning& v, LaunchCf
   A.force_csr = v.lt_csr != 0;
   A.force_direct = v.blur_direct != 0;
   A.plain_cg = v.plain_cg != 0;
+  A.pc_theta = (v.pc_theta_pct > 0 ? v.pc_theta_pct : kPcThetaPct) * 0.01f;
+  A.heavy = v.heavy > 0 ? v.heavy : kHeavy;
   // dynamic LDS: source vector | reduction scratch | frame (up to the full image)
   A.q_off = (int)align256(sz * L.I_max);
   A.red_off = A.q_off + (int)align256(sz * L.I_max);
@@ -2797,10 +2803,25 @@ static sl_tuning resolve_tuning(const sl_problem* pb, int max_ns, int n_members,
   if (opt->tuning) return *opt->tuning;
   std::lock_guard<std::mutex> g(g_tune.mu);
   auto it = g_tune.best.find(tune_key(pb, max_ns, n_members, n_lambda));
-  return it == g_tune.best.end() ? sl_tuning{0, 0, 0, 0} : it->second;
+  return it == g_tune.best.end() ? sl_tuning{0, 0, 0, 0, 0, 0} : it->second;
 }
 
-static sl_tuning variant_of(int i) { return sl_tuning{i & 1, (i >> 1) & 1, (i >> 2) & 1, 0}; }
+// The autotuner's search, in three stages.  Variants 0..7: the structural
+// switches (window, L^T layout, blur form) at the default threshold and
+// queue order.  8..11: the preconditioner threshold theta (percent of c) on
+// the best of 0..7.  12..15: the count of smallest lambdas queued first on
+// the best of 0..11.
+static const int kThetaPct[4] = {5, 10, 25, 40};
+static const int kHeavyN[4] = {2, 3, 6, 8};
+static sl_tuning variant_of(int i, const sl_tuning& base) {
+  if (i < 8) return sl_tuning{i & 1, (i >> 1) & 1, (i >> 2) & 1, 0, 0, 0};
+  sl_tuning v = base;
+  if (i < 12)
+    v.pc_theta_pct = kThetaPct[i - 8];
+  else
+    v.heavy = kHeavyN[i - 12];
+  return v;
+}
 
 // Validates the arguments of a solve and fills the kernel arguments.
 static int prepare(const sl_problem* pb, const double* lens, const int32_t* ns, int max_ns, int n_members,
@@ -2928,7 +2949,7 @@ int sl_solve_implicit(const sl_problem* pb, const double* lens, const int32_t* n
     return e;
   A.implicit = 1;
   LaunchCfg c;
-  const sl_tuning dflt{0, 0, opt->tuning ? opt->tuning->blur_direct : 0, 1};
+  const sl_tuning dflt{0, 0, opt->tuning ? opt->tuning->blur_direct : 0, 1, 0, 0};
   if (int e = configure_any(pb->dtype, A, L, dflt, &c)) return e;
   return enqueue_any(pb->dtype, A, lams, L, c, (hipStream_t)stream, true);
 }
@@ -2948,36 +2969,57 @@ int sl_solve_autotune(const sl_problem* pb, const double* lens, const int32_t* n
   SL_HIP(hipEventCreate(&e1));
   double t_best = 1e300;
   int i_best = -1, i_last = -1;
+  sl_tuning v_best{0, 0, 0, 0, 0, 0}, base{0, 0, 0, 0, 0, 0};
+  // the threshold matters only where the preconditioner can run
+  const bool pc_possible = pb->dtype == SL_F32 && pb->reg == SL_H_CURVATURE;
+  // SL_AUTOTUNE_VERBOSE=1: one line per variant on stderr as it is timed
+  const char* ve = std::getenv("SL_AUTOTUNE_VERBOSE");
+  const bool verbose = ve && ve[0] == '1';
   int rc = SL_OK;
   for (int i = 0; i < SL_N_VARIANTS && rc == SL_OK; ++i) {
     if (ms) ms[i] = -1.0;
+    if (i == 8 || i == 12) base = v_best;   // the next stage starts from the best so far
+    if (i >= 8 && i < 12 && !pc_possible) continue;
+    const sl_tuning vi = variant_of(i, base);
     SolveArgs A = A0;
     LaunchCfg c;
-    const int ce = configure_any(pb->dtype, A, L, variant_of(i), &c);
+    const int ce = configure_any(pb->dtype, A, L, vi, &c);
     if (ce == SL_ENOIMPL) continue;
     if ((rc = ce) != SL_OK) break;
     if ((rc = enqueue_any(pb->dtype, A, lams, L, c, st, false)) != SL_OK) break;   // untimed
-    if (hipEventRecord(e0, st) != hipSuccess) { rc = SL_EHIP; break; }
-    if ((rc = enqueue_any(pb->dtype, A, lams, L, c, st, false)) != SL_OK) break;
-    float t = 0.0f;
-    if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-        hipEventElapsedTime(&t, e0, e1) != hipSuccess) {
-      set_error("autotune timing failed: %s", hipGetErrorString(hipGetLastError()));
-      rc = SL_EHIP;
-      break;
+    float t = 1e30f;
+    for (int rep = 0; rep < 2 && rc == SL_OK; ++rep) {   // the faster of two timed runs
+      float tr = 0.0f;
+      if (hipEventRecord(e0, st) != hipSuccess) { rc = SL_EHIP; break; }
+      if ((rc = enqueue_any(pb->dtype, A, lams, L, c, st, false)) != SL_OK) break;
+      if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&tr, e0, e1) != hipSuccess) {
+        set_error("autotune timing failed: %s", hipGetErrorString(hipGetLastError()));
+        rc = SL_EHIP;
+        break;
+      }
+      t = std::min(t, tr);
     }
+    if (rc != SL_OK) break;
     if (ms) ms[i] = t;
+    if (verbose) {
+      std::fprintf(stderr, "sl_solve_autotune: variant %d {%d %d %d theta %d%% heavy %d}: %.2f ms\n", i,
+                   vi.wide_window, vi.lt_csr, vi.blur_direct, vi.pc_theta_pct ? vi.pc_theta_pct : kPcThetaPct,
+                   vi.heavy ? vi.heavy : kHeavy, t);
+      std::fflush(stderr);
+    }
     i_last = i;
     if (t < t_best) {
       t_best = t;
       i_best = i;
+      v_best = vi;
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc != SL_OK) return rc;
   SL_REQUIRE(i_best >= 0, "no kernel variant exists for this problem");
-  const sl_tuning v = variant_of(i_best);
+  const sl_tuning v = v_best;
   {
     std::lock_guard<std::mutex> g(g_tune.mu);
     g_tune.best[tune_key(pb, max_ns, n_members, n_lambda)] = v;

@@ -16,6 +16,7 @@ from . import _lib as L
 
 _DT = {torch.float32: L.SL_F32, torch.float64: L.SL_F64}
 _REG = {"identity": L.SL_H_IDENTITY, "curvature": L.SL_H_CURVATURE}
+TUNING_KEYS = ("wide_window", "lt_csr", "blur_direct", "plain_cg", "pc_theta_pct", "heavy")
 
 
 @dataclasses.dataclass(frozen=True)
@@ -250,7 +251,7 @@ class Solver:
                          ("s_corner", "s_off", "chi2", "reg", "iters", "status", "k_star", "corner_status", "dof")])
         tun = None
         if tuning is not None:
-            tun = L.Tuning(*[int(tuning.get(k, 0)) for k in ("wide_window", "lt_csr", "blur_direct", "plain_cg")])
+            tun = L.Tuning(*[int(tuning.get(k, 0)) for k in TUNING_KEYS])
         noise = None
         if mc_noise is not None:
             _dev_check(mc_noise)
@@ -313,8 +314,7 @@ class Solver:
                                           L.f64_array(lam), len(lam), ctypes.byref(opts), L.ptr(ws), ws.numel(),
                                           ctypes.byref(res), L.stream_handle(), ctypes.byref(best), ms),
                 "sl_solve_autotune")
-        return (dict(wide_window=best.wide_window, lt_csr=best.lt_csr, blur_direct=best.blur_direct,
-                     plain_cg=best.plain_cg), list(ms), out)
+        return ({k: getattr(best, k) for k in TUNING_KEYS}, list(ms), out)
 
     def plan(self, lens: torch.Tensor, ns: torch.Tensor, lambdas, tol=1e-7, maxit=4000,
              max_ns: int | None = None, out=None, tuning: dict | None = None) -> "Plan":

@@ -2,8 +2,10 @@
 
 * Every variant (banded window size, transposed-operator layout, blur path)
   matches the oracle on the c2 workload, FP32 and FP64.
-* The autotuner times every existing variant and leaves the best variant's
-  results in its output.
+* The autotuner times every existing variant (the structural switches, then
+  the preconditioner threshold, then the queue order) and leaves the best
+  variant's results in its output; other thresholds give the oracle's
+  solutions to the tolerance, and another queue order the same bits.
 * A captured plan, replayed several times with new lens parameters written
   into its input buffer and eager solves and synchronisations in between,
   gives on every replay exactly (bit for bit) what the eager solve gives.
@@ -78,9 +80,15 @@ def test_autotune_times_every_variant_and_keeps_best_results():
     lens = torch.tensor(pop, device=DEV)
     ns = torch.tensor(grids, device=DEV)
     best, ms, out = solver.autotune(lens, ns, w.lambdas, tol=w.tol, max_ns=96)
-    assert len(ms) == 8 and all(t > 0 for t in ms)   # K = 15 in FP32: all eight variants exist
-    i_best = best["wide_window"] | (best["lt_csr"] << 1) | (best["blur_direct"] << 2)
-    assert ms[i_best] == min(ms)
+    # K = 15 in FP32 with curvature H: every structural variant exists and every stage runs
+    assert len(ms) == 16 and all(t > 0 for t in ms), ms
+    if best["heavy"]:
+        i_best = 12 + (2, 3, 6, 8).index(best["heavy"])
+    elif best["pc_theta_pct"]:
+        i_best = 8 + (5, 10, 25, 40).index(best["pc_theta_pct"])
+    else:
+        i_best = best["wide_window"] | (best["lt_csr"] << 1) | (best["blur_direct"] << 2)
+    assert ms[i_best] == min(ms), (best, ms)
     tuned = _np(out)
     ref = _np(solver.solve_semilinear(lens, ns, w.lambdas, tol=w.tol, max_ns=96, tuning=best))
     for k in ("chi2", "reg"):
@@ -88,6 +96,36 @@ def test_autotune_times_every_variant_and_keeps_best_results():
     dflt = _np(solver.solve_semilinear(lens, ns, w.lambdas, tol=w.tol, max_ns=96, tuning={}))
     ok = dflt["status"] == 0
     assert np.all(np.abs(tuned["chi2"][ok] - dflt["chi2"][ok]) <= 1e-5 * dflt["chi2"][ok])
+
+
+@pytest.mark.parametrize("theta", [5, 40])
+def test_preconditioner_threshold_matches_oracle(theta):
+    """pc_theta_pct moves items between plain and preconditioned CG: the
+    same Eq. 7 solutions to the tolerance (c2 against the oracle)."""
+    import paper_1101_5803_amd as sl
+    g = np.load(os.path.join(GOLD, "c2_oracle.npz"))
+    solver, w, z = _c2_solver(sl, torch.float32)
+    lens = torch.tensor(np.atleast_2d(z["lens"]), device=DEV)
+    ns = torch.tensor([w.ns], dtype=torch.int32, device=DEV)
+    out = _np(solver.solve_semilinear(lens, ns, w.lambdas, tol=1e-7, max_ns=w.ns, tuning={"pc_theta_pct": theta}))
+    assert np.all(out["status"] == 0)
+    rel = np.abs(out["chi2"][0] - g["chi2"]) / g["chi2"]
+    assert rel.max() <= 1e-5, rel.max()
+
+
+def test_queue_order_leaves_results_bitwise():
+    """heavy changes only the order in which blocks take the items; every
+    item's arithmetic is the same, so the results are bit for bit the same."""
+    import paper_1101_5803_amd as sl
+    solver, w, z = _c2_solver(sl, torch.float32)
+    M = 24
+    lens = torch.tensor(synthgen.population(synthgen.C3.seed, 256)[:M], device=DEV)
+    ns = torch.tensor(synthgen.member_grids(synthgen.C3.seed, 256)[:M], device=DEV)
+    a = _np(solver.solve_semilinear(lens, ns, w.lambdas, tol=w.tol, max_ns=96, tuning={}))
+    for h in (2, 8):
+        b = _np(solver.solve_semilinear(lens, ns, w.lambdas, tol=w.tol, max_ns=96, tuning={"heavy": h}))
+        for k in ("chi2", "reg", "iters", "status", "k_star"):
+            assert np.array_equal(a[k], b[k]), (h, k)
 
 
 def test_plan_replays_match_eager():
