@@ -153,6 +153,12 @@ typedef struct {
   int reg;             /* SL_H_IDENTITY | SL_H_CURVATURE */
   int dtype;           /* SL_F32: FP32 bulk, FP64 inner products / chi^2 / L-curve;
                           SL_F64: FP64 throughout */
+  int psf_general;     /* 0: the solve tests the PSF for rank 1 on the device and launches
+                          the banded and the direct form of each persistent kernel, the one
+                          that does not apply returning at entry; 1: the caller states that
+                          the PSF is not rank 1, and only the direct form is launched (as
+                          with sl_tuning.blur_direct; correct for any PSF, slower for a
+                          separable one) */
 } sl_problem;
 
 /*

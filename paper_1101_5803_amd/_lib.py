@@ -36,7 +36,7 @@ class ImageGrid(ctypes.Structure):
 class Problem(ctypes.Structure):
     _fields_ = [("img", ImageGrid), ("d", ctypes.c_void_p), ("sigma", ctypes.c_double),
                 ("psf", ctypes.c_void_p), ("k", ctypes.c_int), ("half_width", ctypes.c_double),
-                ("reg", ctypes.c_int), ("dtype", ctypes.c_int)]
+                ("reg", ctypes.c_int), ("dtype", ctypes.c_int), ("psf_general", ctypes.c_int)]
 
 
 class Tuning(ctypes.Structure):

@@ -165,7 +165,8 @@ struct SolveArgs {
   long long lt_cap; // entries per member
   int I_max;
   int force_csr;    // variant: transposed operator as CSR rows
-  int force_direct; // variant: direct K x K blur for a separable PSF
+  int force_direct; // direct K x K blur only (variant, or the caller's hint that the PSF is not rank 1)
+  int psf_general;  // the caller's hint: the PSF is not rank 1
   int prep_tags;    // k_prep has one LDS int per node after its 8 I_max + 768 bytes (conflict tags)
   int implicit;     // implicit regularisation: n_lambda unregularised CG iterations (k_implicit)
   int heavy;        // smallest lambdas of each member queued ahead of the rest
@@ -2493,6 +2494,7 @@ static int check_problem(const sl_problem* pb, int max_ns, int M, int NL) {
   SL_REQUIRE(std::isfinite(pb->half_width) && pb->half_width > 0.0, "half_width must be positive");
   SL_REQUIRE(pb->reg == SL_H_IDENTITY || pb->reg == SL_H_CURVATURE, "unknown reg %d", pb->reg);
   SL_REQUIRE(pb->dtype == SL_F32 || pb->dtype == SL_F64, "unknown dtype %d", pb->dtype);
+  SL_REQUIRE(pb->psf_general == 0 || pb->psf_general == 1, "psf_general must be 0 or 1");
   SL_REQUIRE(max_ns >= 2 && max_ns <= 128, "max_ns %d outside [2, 128]", max_ns);
   SL_REQUIRE(M >= 1 && M <= (1 << 20), "n_members %d out of range", M);
   SL_REQUIRE(NL >= 1 && NL <= SL_MAX_LAMBDA, "n_lambda %d outside [1, %d]", NL, SL_MAX_LAMBDA);
@@ -2596,9 +2598,12 @@ static ProfileState g_prof;
 // Per-device side stream for the preconditioned launch and the events that
 // fork it from, and join it to, the caller's stream; created on first use
 // (default priority, non-blocking).
+// Two side streams: the banded and the direct form of the preconditioned
+// launch go on separate streams, so that the form that returns at entry
+// never holds the other back while its blocks wait for CUs.
 struct SideStream {
-  hipStream_t s = nullptr;
-  hipEvent_t fork = nullptr, join = nullptr;
+  hipStream_t s = nullptr, s2 = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr, join2 = nullptr;
 };
 static std::mutex g_side_mu;
 static SideStream g_side[64];
@@ -2610,8 +2615,10 @@ static int side_stream(SideStream** out) {
   SideStream& x = g_side[dev];
   if (!x.s) {
     SL_HIP(hipStreamCreateWithFlags(&x.s, hipStreamNonBlocking));
+    SL_HIP(hipStreamCreateWithFlags(&x.s2, hipStreamNonBlocking));
     SL_HIP(hipEventCreateWithFlags(&x.fork, hipEventDisableTiming));
     SL_HIP(hipEventCreateWithFlags(&x.join, hipEventDisableTiming));
+    SL_HIP(hipEventCreateWithFlags(&x.join2, hipEventDisableTiming));
   }
   *out = &x;
   return SL_OK;
@@ -2645,7 +2652,7 @@ static int configure(SolveArgs& A, const Layout& L, const sl_tuning& v, LaunchCf
   }
   A.ckt = ckt;
   A.force_csr = v.lt_csr != 0;
-  A.force_direct = v.blur_direct != 0;
+  A.force_direct = v.blur_direct != 0 || A.psf_general != 0;
   A.plain_cg = v.plain_cg != 0;
   A.pc_theta = (v.pc_theta_pct > 0 ? v.pc_theta_pct : kPcThetaPct) * 0.01f;
   A.heavy = v.heavy > 0 ? v.heavy : kHeavy;
@@ -2706,11 +2713,15 @@ static int configure(SolveArgs& A, const Layout& L, const sl_tuning& v, LaunchCf
 // Launches the banded and the direct form of a persistent kernel on st, the
 // banded one first; the one that does not match the problem (the separability
 // flag k_setup leaves in the workspace) returns at entry.
+// With force_direct the device's separability flag is 0 and the banded form
+// would return at entry, so only the direct form is launched.
 template <typename T>
 static int launch_pair(SolveKernel kb, SolveKernel kd, const Layout& L, const LaunchCfg& c, hipStream_t st,
                        const SolveArgs& A, const char* what) {
-  hipLaunchKernelGGL(kb, dim3(L.n_wg), dim3(kNTof<T>), c.lds, st, A);
-  if (int e = check_launch(what)) return e;
+  if (!A.force_direct) {
+    hipLaunchKernelGGL(kb, dim3(L.n_wg), dim3(kNTof<T>), c.lds, st, A);
+    if (int e = check_launch(what)) return e;
+  }
   hipLaunchKernelGGL(kd, dim3(L.n_wg), dim3(kNTof<T>), c.lds, st, A);
   return check_launch(what);
 }
@@ -2758,9 +2769,17 @@ static int enqueue(const SolveArgs& A, const LamList& lams, const Layout& L, con
     SL_HIP(hipEventRecord(ss->fork, st));
     if (int e = launch_pair<T>(c.ks, c.ksd, L, c, st, A, "k_solve")) return e;
     SL_HIP(hipStreamWaitEvent(ss->s, ss->fork, 0));
-    if (int e = launch_pair<T>(c.kpc, c.kpcd, L, c, ss->s, A, "k_solve (preconditioned)")) return e;
+    SL_HIP(hipStreamWaitEvent(ss->s2, ss->fork, 0));
+    if (!A.force_direct) {
+      hipLaunchKernelGGL(c.kpc, dim3(L.n_wg), dim3(kNTof<T>), c.lds, ss->s, A);
+      if (int e = check_launch("k_solve (preconditioned)")) return e;
+    }
+    hipLaunchKernelGGL(c.kpcd, dim3(L.n_wg), dim3(kNTof<T>), c.lds, ss->s2, A);
+    if (int e = check_launch("k_solve (preconditioned, direct blur)")) return e;
     SL_HIP(hipEventRecord(ss->join, ss->s));
+    SL_HIP(hipEventRecord(ss->join2, ss->s2));
     SL_HIP(hipStreamWaitEvent(st, ss->join, 0));
+    SL_HIP(hipStreamWaitEvent(st, ss->join2, 0));
   } else {
     if (int e = launch_pair<T>(c.ks, c.ksd, L, c, st, A, "k_solve")) return e;
   }
@@ -2853,6 +2872,7 @@ static int prepare(const sl_problem* pb, const double* lens, const int32_t* ns, 
   A.K = pb->k;
   A.ck = (pb->k - 1) / 2;
   A.reg = pb->reg;
+  A.psf_general = pb->psf_general != 0;
   A.n_members = n_members;
   A.n_lambda = n_lambda;
   A.max_ns = max_ns;
@@ -3061,13 +3081,17 @@ int sl_plan_create(const sl_problem* pb, const double* lens, const int32_t* ns, 
   SideStream own;
   if (c.kpc) {
     SL_HIP(hipStreamCreateWithFlags(&own.s, hipStreamNonBlocking));
+    SL_HIP(hipStreamCreateWithFlags(&own.s2, hipStreamNonBlocking));
     SL_HIP(hipEventCreateWithFlags(&own.fork, hipEventDisableTiming));
     SL_HIP(hipEventCreateWithFlags(&own.join, hipEventDisableTiming));
+    SL_HIP(hipEventCreateWithFlags(&own.join2, hipEventDisableTiming));
   }
   auto drop_own = [&]() {
     if (own.s) (void)hipStreamDestroy(own.s);
+    if (own.s2) (void)hipStreamDestroy(own.s2);
     if (own.fork) (void)hipEventDestroy(own.fork);
     if (own.join) (void)hipEventDestroy(own.join);
+    if (own.join2) (void)hipEventDestroy(own.join2);
   };
   hipStream_t cs;
   if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {

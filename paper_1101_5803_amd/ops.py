@@ -198,9 +198,13 @@ class Solver:
         self.dtype = dtype
         self.device = d.device
         self._ws = None
+        # launch hint: a PSF whose second singular value is not negligible is not rank 1, so the solve
+        # launches only the direct blur form (the device's own rank-1 test decides every other case)
+        sv = np.linalg.svd(self.psf.cpu().numpy(), compute_uv=False)
+        general = int(sv.size > 1 and sv[1] > 1e-8 * sv[0])
         self._pb = L.Problem(grid.c(), ctypes.c_void_p(self.d.data_ptr()), self.sigma,
                              ctypes.c_void_p(self.psf.data_ptr()), self.psf.shape[0], self.half_width,
-                             _REG[reg], _DT[dtype])
+                             _REG[reg], _DT[dtype], general)
 
     def workspace_bytes(self, max_ns: int, n_members: int, n_lambda: int) -> int:
         n = L.lib().sl_solve_workspace_size(ctypes.byref(self._pb), max_ns, n_members, n_lambda)

@@ -333,3 +333,32 @@ def test_c2_radial_psf_direct_blur_vs_oracle(sl, dtype):
     err = np.linalg.norm(out["s_corner"][:w.ns * w.ns] - s_ref) / np.linalg.norm(s_ref)
     assert err <= (1e-7 if f64 and k == int(g["k_star"]) else 1e-4), err
     print(f"radial PSF {dtype}: chi2 max rel {rel.max():.2e}, reg max rel {rr.max():.2e}, s rel {err:.2e}")
+
+
+def test_psf_general_hint_changes_no_result(sl):
+    """sl_problem.psf_general only selects which kernel forms are launched:
+    for the non-separable PSF the binding sets it, and clearing it (both
+    forms launched, the device deciding) gives the same bits; for the
+    separable c2 PSF setting it runs the direct form, within the FP32 bar of
+    the banded one."""
+    g = np.load(os.path.join(GOLD, "c2_radial.npz"))
+    w = synthgen.C2
+    z = np.load(os.path.join(HERE, "data", "c2.npz"))
+    lens = torch.tensor(synthgen.population(synthgen.C3.seed, 256)[:12], device=DEV)
+    ns = torch.tensor(synthgen.member_grids(synthgen.C3.seed, 256)[:12], device=DEV)
+    res = {}
+    psfs = {"radial": g["psf"], "gauss": z["psf"]}
+    for name, hint in (("radial", None), ("radial", 0), ("gauss", None), ("gauss", 1)):
+        solver = sl.Solver(torch.tensor(z["d"], device=DEV), float(z["sigma"]), torch.tensor(psfs[name], device=DEV),
+                           sl.Grid(w.nx, w.ny, w.pix, w.nsub_model), w.half_width, reg=w.reg, dtype=torch.float32)
+        key = (name, solver._pb.psf_general if hint is None else hint)
+        if hint is not None:
+            solver._pb.psf_general = hint
+        res[key] = _np(solver.solve_semilinear(lens, ns, w.lambdas, tol=1e-7, max_ns=96))
+    assert ("radial", 1) in res and ("gauss", 0) in res   # the binding's own setting
+    a, b = res[("radial", 1)], res[("radial", 0)]
+    for k in ("chi2", "reg", "iters", "status", "k_star"):
+        assert np.array_equal(a[k], b[k]), k
+    c, d = res[("gauss", 0)], res[("gauss", 1)]
+    assert np.all(c["status"] == 0) and np.all(d["status"] == 0)
+    assert np.all(np.abs(c["chi2"] - d["chi2"]) <= 2e-5 * c["chi2"])
