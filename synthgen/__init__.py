@@ -201,3 +201,11 @@ def sinc_moffat_psf(K: int, fwhm_px: float = 3.0, q: float = 0.7, pa: float = 0.
     r = np.hypot(x, y)
     P = moffat * np.sinc(r / sinc_period_px) ** 2
     return P / P.sum()
+
+
+def pso_draws(seed: int, n: int, steps: int, dims: int = 7) -> dict:
+    """Random numbers of a particle swarm run: initial unit-box positions x0
+    (n, dims) and the spring draws xi_p, xi_g (steps, n), all U(0, 1)."""
+    rng = np.random.default_rng(seed + 2000)
+    return dict(x0=rng.uniform(size=(n, dims)), xi_p=rng.uniform(size=(steps, n)),
+                xi_g=rng.uniform(size=(steps, n)))
