@@ -17,6 +17,10 @@ One generation of the simplified Ferret GA:
 Linkage learning, niching, adaptive control and islands are not modelled.
 All random numbers are inputs (a dict of one generation's draws).
 
+The swarm (SwarmSearch, Sec. 3.1.2 and App. A.2) is the second outer loop:
+particles pulled towards their own and the swarm's best positions, moved
+along Locust's exact damped-oscillator orbits or by Eq. 21 itself.
+
 Surrogate screening (not in the paper): each parent proposes `fanout`
 candidates; the device MLP predicts ln chi^2 of every candidate; each
 parent's best-predicted candidate goes to the full solve and the tournament.
@@ -313,6 +317,124 @@ class ScreenedSearch(GeneticSearch):
         self.select = str(z["select"])
         self.surrogate = surrogate
         self.surrogate.load_state(z)
+
+
+@dataclasses.dataclass(frozen=True)
+class SwarmConfig:
+    """Locust strategy parameters (App. A.2) and the orbit form."""
+    cp: float = 1.0        # personal-best spring constant
+    cg: float = 0.5        # swarm-best spring constant
+    dt: float = 1.0        # time step
+    tdamp: float = 10.0    # damping time in units of the critical one
+    exact: bool = True     # exact damped-oscillator orbits (Locust); False: the Euler form of Eq. 21
+
+
+class SwarmSearch:
+    """Particle swarm over unit genes (Sec. 3.1.2, Eq. 21; App. A.2).
+
+    Every particle is pulled towards its own best position and the swarm's
+    best by springs c_p xi_p and c_g xi_g and damped over t_damp =
+    TDamp / (2 sqrt((c_p + c_g) / 2)) (TDamp = 1: critical damping at the
+    mean spring constant).  With `exact` each step moves the particles along
+    the exact solution of that damped oscillator with the springs held fixed
+    (as Locust does); otherwise by Eq. 21 itself, the position moving with
+    the velocity of the start of the step.  The angle genes wrap; another
+    gene that leaves the unit box stops on the wall with zero velocity there.
+    Velocities start at zero; a particle's best moves only on a strictly lower
+    fitness; the swarm's best is the lowest personal best (first on a tie).
+    `fitness` maps unit genes (n, 7) -> (n,); every step is one batched call.
+    All random numbers are inputs (xi_p, xi_g: one U(0, 1) draw per particle
+    and step).
+    """
+
+    def __init__(self, fitness, X0: np.ndarray, cfg: SwarmConfig = SwarmConfig(), log=None):
+        self.fitness, self.cfg, self.log = fitness, cfg, log
+        self.X = np.array(X0, dtype=np.float64)
+        self.V = np.zeros_like(self.X)
+        f = np.asarray(fitness(self.X), dtype=np.float64)
+        self.P, self.fP = self.X.copy(), f.copy()
+        self.g = int(np.argmin(self.fP))
+        self.steps = 0
+        self.evals = self.X.shape[0]
+        self.history = [float(self.fP[self.g])]
+        self.t_damp = cfg.tdamp / (2.0 * math.sqrt(0.5 * (cfg.cp + cfg.cg)))
+
+    @property
+    def best(self):
+        return self.P[self.g].copy(), float(self.fP[self.g])
+
+    def _move(self, xi_p: np.ndarray, xi_g: np.ndarray):
+        c, dt = self.cfg, self.cfg.dt
+        X, V = self.X, self.V
+        kp = (c.cp * xi_p)[:, None]
+        kg = (c.cg * xi_g)[:, None]
+        G = self.P[self.g][None, :]
+        if not c.exact:
+            Vn = V * (1.0 - dt / self.t_damp) + (kp * (self.P - X) + kg * (G - X)) * dt
+            return X + V * dt, Vn
+        # exact orbit of y'' = -gamma y' - k y about the spring centre, per particle (k, gamma scalars)
+        k = kp + kg
+        kk = np.where(k > 0.0, k, 1.0)
+        ctr = np.where(k > 0.0, (kp * self.P + kg * G) / kk, X)
+        y0, v0 = X - ctr, V
+        gam = 1.0 / self.t_damp
+        disc = gam * gam - 4.0 * k
+        Xn = np.empty_like(X)
+        Vn = np.empty_like(V)
+        # no spring: free damped motion
+        free = (k <= 0.0)[:, 0]
+        e = math.exp(-gam * dt)
+        Xn[free] = X[free] + V[free] * (1.0 - e) / gam
+        Vn[free] = V[free] * e
+        under = (~free) & (disc < 0.0)[:, 0]
+        if under.any():
+            kk_ = k[under]
+            w = np.sqrt(kk_ - 0.25 * gam * gam)
+            ed = math.exp(-0.5 * gam * dt)
+            cs, sn = np.cos(w * dt), np.sin(w * dt)
+            a, b = y0[under], v0[under]
+            Xn[under] = ctr[under] + ed * (a * cs + (b + 0.5 * gam * a) / w * sn)
+            Vn[under] = ed * (b * cs - (0.5 * gam * b + kk_ * a) / w * sn)
+        over = (~free) & (disc > 0.0)[:, 0]
+        if over.any():
+            sq = np.sqrt(disc[over])
+            r1, r2 = 0.5 * (-gam + sq), 0.5 * (-gam - sq)
+            a, b = y0[over], v0[over]
+            c1 = (b - r2 * a) / (r1 - r2)
+            c2 = a - c1
+            e1, e2 = np.exp(r1 * dt), np.exp(r2 * dt)
+            Xn[over] = ctr[over] + c1 * e1 + c2 * e2
+            Vn[over] = r1 * c1 * e1 + r2 * c2 * e2
+        crit = (~free) & (disc == 0.0)[:, 0]
+        if crit.any():
+            a, b = y0[crit], v0[crit]
+            bb = b + 0.5 * gam * a
+            ed = math.exp(-0.5 * gam * dt)
+            Xn[crit] = ctr[crit] + (a + bb * dt) * ed
+            Vn[crit] = (b - 0.5 * gam * bb * dt) * ed
+        return Xn, Vn
+
+    def step(self, xi_p: np.ndarray, xi_g: np.ndarray) -> None:
+        """One swarm step from this step's draws (arrays of length N)."""
+        X, V = self._move(np.asarray(xi_p, dtype=np.float64), np.asarray(xi_g, dtype=np.float64))
+        for gdx in range(X.shape[1]):
+            if gdx in PERIODIC_GENES:
+                X[:, gdx] = np.mod(X[:, gdx], 1.0)
+            else:
+                out = (X[:, gdx] < 0.0) | (X[:, gdx] > 1.0)
+                X[:, gdx] = np.clip(X[:, gdx], 0.0, 1.0)
+                V[out, gdx] = 0.0
+        self.X, self.V = X, V
+        f = np.asarray(self.fitness(X), dtype=np.float64)
+        better = f < self.fP
+        self.P[better] = X[better]
+        self.fP[better] = f[better]
+        self.g = int(np.argmin(self.fP))
+        self.steps += 1
+        self.evals += X.shape[0]
+        self.history.append(float(self.fP[self.g]))
+        if self.log is not None:
+            self.log(dict(step=self.steps, evals=self.evals, best=self.history[-1], median=float(np.median(f))))
 
 
 def _spearman(a, b) -> float:

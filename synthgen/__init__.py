@@ -132,7 +132,7 @@ def member_grids(seed: int, n: int, lo: int = 32, hi: int = 96) -> np.ndarray:
     return rng.integers(lo, hi + 1, size=n).astype(np.int32)
 
 
-def ga_draws(seed: int, pop: int, ngen: int) -> dict:
+def ga_draws(seed: int, pop: int, ngen: int, dims: int = 7) -> dict:
     """Random numbers one GA generation consumes, for reproducible GA steps.
 
     Returned per generation g (arrays of shape (ngen, ...)):
@@ -146,8 +146,8 @@ def ga_draws(seed: int, pop: int, ngen: int) -> dict:
     return dict(
         partner=rng.integers(0, pop, size=(ngen, pop)),
         xstrength=rng.standard_normal((ngen, pop)),
-        mut_mask=rng.uniform(size=(ngen, pop, 7)),
-        mut_step=rng.standard_normal((ngen, pop, 7)),
+        mut_mask=rng.uniform(size=(ngen, pop, dims)),
+        mut_step=rng.standard_normal((ngen, pop, dims)),
         perm=np.stack([rng.permutation(pop) for _ in range(ngen)]),
     )
 

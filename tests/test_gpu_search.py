@@ -128,3 +128,26 @@ def test_screened_search_reaches_plain_best_with_fewer_solves():
         gains.append(plain.full_solves / solves)
     print("full-solve reduction per seed:", [round(x, 2) for x in gains])
     assert min(gains) >= 1.5, gains
+
+
+@pytest.mark.parametrize("exact", [True, False])
+def test_swarm_improves_and_replays_exactly(exact):
+    """The particle swarm (Sec. 3.1.2, Eq. 21, App. A.2) with the device solve as
+    fitness: the swarm's best never gets worse and improves on the initial
+    swarm, every step is one batched solve of N members, and the same draws
+    give the same run (the solve is deterministic)."""
+    from paper_1101_5803_amd import search
+    fit, *_ = _fitness()
+    N, T = 64, 6
+    d = synthgen.pso_draws(4, N, T)
+    runs = []
+    for _ in range(2):
+        s = search.SwarmSearch(fit, d["x0"], search.SwarmConfig(exact=exact))
+        for t in range(T):
+            s.step(d["xi_p"][t], d["xi_g"][t])
+        runs.append(s)
+    h = np.array(runs[0].history)
+    assert np.all(np.diff(h) <= 0)
+    assert h[-1] < h[0]
+    assert runs[0].evals == N * (T + 1)
+    assert np.array_equal(runs[0].P, runs[1].P) and np.array_equal(runs[0].history, runs[1].history)
