@@ -285,6 +285,29 @@ int sl_solve_implicit(const sl_problem* pb, const double* lens, const int32_t* n
                       size_t workspace_bytes, sl_result* out, void* stream);
 
 /*
+ * Image chi^2 of candidate sources for one lens: the fitness of the final
+ * source-refinement search (Sec. 3.2), which holds the best lens fixed and
+ * treats every source node as a free, bounded parameter.  For each source
+ * s_p (p < n_sources), chi2[p] = ||B L s_p - d||^2 / sigma^2 over all J
+ * pixels (Eq. 4), with L and B as in the solve (pixels that do not map keep
+ * their data).  One lens, one grid: the solve's trace and tables are built
+ * once per call, then the candidates run in one persistent launch.  FP32
+ * bulk with an FP64 residual sum (SL_F32) or FP64 throughout (SL_F64).
+ *   lens:    device double[7], the lens parameters
+ *   ns:      source grid side, in [2, 128]
+ *   sources: device double[n_sources][ns*ns], row-major nodes as in s_corner
+ *   chi2:    device double[n_sources]; NaN for an invalid lens, sum d^2 /
+ *            sigma^2 when no pixel maps
+ *   workspace: device, >= sl_chi2_sources_workspace_size(pb, ns) bytes,
+ *            256-byte aligned
+ * Asynchronous on `stream`; SL_EINVAL for bad host-side arguments.
+ */
+size_t sl_chi2_sources_workspace_size(const sl_problem* pb, int ns);
+int sl_chi2_sources(const sl_problem* pb, const double* lens, int ns, const double* sources,
+                    int n_sources, void* workspace, size_t workspace_bytes, double* chi2,
+                    void* stream);
+
+/*
  * Autotuner: a staged search over the solve's settings.  Variants 0..7 are
  * the structural switches (wide_window, lt_csr, blur_direct as the bits of
  * the index) at the default threshold and queue order; variants 8..11 set

@@ -96,6 +96,9 @@ def lib():
                                      ctypes.POINTER(SolveOpts), vp, ctypes.c_size_t, ctypes.POINTER(Result),
                                      ctypes.POINTER(vp)]
         L.sl_plan_launch.argtypes = [vp, vp]
+        L.sl_chi2_sources_workspace_size.argtypes = [ctypes.POINTER(Problem), ip]
+        L.sl_chi2_sources_workspace_size.restype = ctypes.c_size_t
+        L.sl_chi2_sources.argtypes = [ctypes.POINTER(Problem), vp, ip, vp, ip, vp, ctypes.c_size_t, vp, vp]
         L.sl_plan_destroy.argtypes = [vp]
         L.sl_solve_member_info.argtypes = [ctypes.POINTER(Problem), ip, ip, ip, vp, vp]
         L.sl_profile_enable.argtypes = [ip]

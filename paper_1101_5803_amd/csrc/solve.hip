@@ -2346,6 +2346,101 @@ __global__ void __launch_bounds__(kNTof<T>) k_implicit(SolveArgs a) {
   }
 }
 
+// ------------------------------------------------------------------ k_chi2_src
+// Image chi^2 of candidate sources for one lens: the fitness of the
+// source-refinement search (Sec. 3.2), where every source node is a free
+// parameter and the lens is held fixed.  chi2[p] = ||B L s_p - d||^2 / sigma^2
+// over all J pixels (Eq. 4; pixels outside the dilated bounding box of the
+// mapped pixels keep their data).  k_setup and k_prep have built member 0's
+// trace table.  Persistent over the candidates: block b takes p = b, b +
+// gridDim.x, ...; the source is staged in LDS (in the bulk type), L gathers
+// it into the frame, B runs over the dilated box into Z, and the residual
+// sum is FP64.  The frame holds values at the mapped pixels only, each of
+// which every gather overwrites, so it is zeroed once.
+template <typename T, int CKT>
+__global__ void __launch_bounds__(kNTof<T>) k_chi2_src(SolveArgs a, const double* src, int n_src, double* chi2) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int NT = kNTof<T>;
+  const int tid = threadIdx.x;
+  const MemberInfo mi = a.minfo[0];
+  const int status = __builtin_amdgcn_readfirstlane(mi.status);
+  const double inv_s2 = 1.0 / (a.sigma * a.sigma);
+  if (status != SL_ST_OK) {   // no mapped pixel (chi^2 of s = 0) or invalid lens (NaN)
+    const double c2 = status == SL_ST_INVALID ? NAN : a.consts->sum_d2 * inv_s2;
+    for (int p = blockIdx.x; p < n_src; p += gridDim.x) chi2[p] = c2;   // the same value from every thread
+    return;
+  }
+  const int ns = mi.ns, I = mi.I, M = mi.M, r0 = mi.r0, c0 = mi.c0;
+  const int h = mi.r1 - mi.r0 + 1, w = mi.c1 - mi.c0 + 1;
+  constexpr int HALO = 2 * CKT;
+  const int pitch = (w + 2 * HALO) | 1;
+  const int frame_elems = (h + 2 * HALO + kSegR) * pitch;
+  const int J = a.nx * a.ny, n2 = a.n2, nx = a.nx, ny = a.ny, K = a.K, ck = a.ck;
+  const long slot = (long)blockIdx.x;
+  T* S = reinterpret_cast<T*>(smem);
+  double* red = reinterpret_cast<double*>(smem + a.red_off);
+  T* F = __builtin_amdgcn_readfirstlane(mi.lds_frame) ? reinterpret_cast<T*>(smem + a.frame_off)
+                                                       : reinterpret_cast<T*>(a.gframe) + slot * a.gframe_elems;
+  T* const F0 = F + HALO * pitch + HALO;
+  const int Dr0 = max(mi.r0 - ck, 0), Dr1 = min(mi.r1 + ck, ny - 1);
+  const int Dc0 = max(mi.c0 - ck, 0), Dc1 = min(mi.c1 + ck, nx - 1);
+  const int Dh = Dr1 - Dr0 + 1, Dw = Dc1 - Dc0 + 1;
+  T* __restrict__ Z = reinterpret_cast<T*>(a.gz) + slot * 2L * J;
+  const OpView<T> ov{a.pix_list, a.cell, reinterpret_cast<const T*>(a.fx), reinterpret_cast<const T*>(a.fy), F, F0,
+                     Z, Z + J, reinterpret_cast<const T*>(a.taps_t), a.lt_ptr,
+                     reinterpret_cast<const LtEntry<T>*>(a.lt_ent), a.lt_perm, ns, I, M, r0, c0, h, w, pitch,
+                     -r0 * pitch - c0, n2, nx, ny, K, ck, __builtin_amdgcn_readfirstlane(mi.sell), Dr0, Dc0, Dh, Dw,
+                     a.consts->sep != 0, true, (T)1 / (T)n2, (T)0};
+  for (int e = tid; e < frame_elems; e += NT) F[e] = (T)0;
+  double din = 0.0;
+  for (int e = tid; e < Dh * Dw; e += NT) {
+    const double dv = a.d[(Dr0 + e / Dw) * nx + Dc0 + e % Dw];
+    din += dv * dv;
+  }
+  din = block_sum1<NT / kWave>(din, red, 0);
+  const double d_out = a.consts->sum_d2 - din;   // data outside the dilated box
+  for (int p = blockIdx.x; p < n_src; p += gridDim.x) {
+    const double* sp = src + (long)p * I;
+    for (int i = tid; i < I; i += NT) S[i] = (T)sp[i];
+    __syncthreads();
+    gather_L<T, NT>(ov, S);                      // frame = L s_p at the mapped pixels
+    __syncthreads();
+    forward_blur<T, CKT, NT>(ov, Z);             // Z = B L s_p over the dilated box
+    __syncthreads();
+    double acc = 0.0;
+    for (int e = tid; e < Dh * Dw; e += NT) {
+      const double r = (double)Z[e] - a.d[(Dr0 + e / Dw) * nx + Dc0 + e % Dw];
+      acc += r * r;
+    }
+    acc = block_sum1<NT / kWave>(acc, red, 1);   // its barrier: every read of S, the frame and Z is done
+    chi2[p] = (acc + d_out) * inv_s2;            // the same value from every thread
+    __syncthreads();
+  }
+}
+
+// The candidate-source chi^2 kernel of the bulk type and window (the windows
+// the solve kernels are compiled for).
+using Chi2Kernel = void (*)(SolveArgs, const double*, int, double*);
+template <typename T>
+static Chi2Kernel pick_chi2_kernel(int ckt) {
+  if (sizeof(T) == 4) {
+    switch (ckt) {
+      case 2: return k_chi2_src<float, 2>;
+      case 4: return k_chi2_src<float, 4>;
+      case 7: return k_chi2_src<float, 7>;
+      case 10: return k_chi2_src<float, 10>;
+      case 16: return k_chi2_src<float, 16>;
+    }
+  } else {
+    switch (ckt) {
+      case 2: return k_chi2_src<double, 2>;
+      case 7: return k_chi2_src<double, 7>;
+      case 10: return k_chi2_src<double, 10>;
+    }
+  }
+  return nullptr;
+}
+
 // Moves the items that take the spectral preconditioner into their own queues
 // (stable, per XCD queue): valid member, FP32, curvature H, frame in LDS with
 // room for the n x n scratch, and lambda >= pc_theta c.  One block.
@@ -2421,6 +2516,15 @@ __global__ void __launch_bounds__(256) k_corner(SolveArgs a) {
 
 // ------------------------------------------------------------------ host side
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Bytes after the solve's workspace that sl_chi2_sources uses: the device
+// copy of ns, then the member offsets k_setup writes.
+constexpr size_t kSrcTail = 512;
+
+// *p = v, from a launch argument (so that the write can be captured).
+__global__ void k_put_int(int32_t* p, int v) {
+  if (threadIdx.x == 0) *p = v;
+}
 
 static int device_cus() {
   static int cus[64] = {0};
@@ -2972,6 +3076,67 @@ int sl_solve_implicit(const sl_problem* pb, const double* lens, const int32_t* n
   const sl_tuning dflt{0, 0, opt->tuning ? opt->tuning->blur_direct : 0, 1, 0, 0};
   if (int e = configure_any(pb->dtype, A, L, dflt, &c)) return e;
   return enqueue_any(pb->dtype, A, lams, L, c, (hipStream_t)stream, true);
+}
+
+size_t sl_chi2_sources_workspace_size(const sl_problem* pb, int ns) {
+  const size_t n = sl_solve_workspace_size(pb, ns, 1, 1);
+  return n ? align256(n) + kSrcTail : 0;
+}
+
+int sl_chi2_sources(const sl_problem* pb, const double* lens, int ns, const double* sources, int n_sources,
+                    void* workspace, size_t workspace_bytes, double* chi2, void* stream) {
+  SL_REQUIRE(pb != nullptr, "problem is NULL");
+  SL_REQUIRE(ns >= 2 && ns <= 128, "ns %d outside [2, 128]", ns);
+  SL_REQUIRE(n_sources >= 1 && n_sources <= (1 << 24), "n_sources %d out of range", n_sources);
+  SL_REQUIRE(lens && sources && chi2, "NULL device pointer");
+  const size_t base = sl_solve_workspace_size(pb, ns, 1, 1);
+  SL_REQUIRE(base != 0, "%s", sl_last_error());
+  SL_REQUIRE(workspace_bytes >= align256(base) + kSrcTail, "workspace too small: %zu < %zu bytes", workspace_bytes,
+             align256(base) + kSrcTail);
+  // the tail holds the device copy of ns and the member offsets k_setup writes
+  unsigned char* tail = static_cast<unsigned char*>(workspace) + align256(base);
+  int32_t* ns_dev = reinterpret_cast<int32_t*>(tail);
+  sl_result dummy{};
+  dummy.s_off = reinterpret_cast<int64_t*>(tail + 256);
+  dummy.s_corner = reinterpret_cast<double*>(tail + 256);
+  dummy.chi2 = dummy.reg = dummy.s_corner;
+  dummy.iters = dummy.status = dummy.k_star = dummy.corner_status = ns_dev;
+  const double lam1 = 1.0;
+  const sl_solve_opts opt{0.0, 1, nullptr, nullptr};
+  SolveArgs A;
+  Layout L;
+  LamList lams;
+  if (int e = prepare(pb, lens, ns_dev, ns, 1, &lam1, 1, &opt, workspace, base, &dummy, &A, &L, &lams)) return e;
+  LaunchCfg c;
+  const sl_tuning dflt{0, 0, 0, 1, 0, 0};
+  if (int e = configure_any(pb->dtype, A, L, dflt, &c)) return e;
+  hipStream_t st = (hipStream_t)stream;
+  const int nb = std::min(L.n_wg, n_sources);
+  const int nt = pb->dtype == SL_F32 ? kNTof<float> : kNTof<double>;
+  const Chi2Kernel kc = pb->dtype == SL_F32 ? pick_chi2_kernel<float>(A.ckt) : pick_chi2_kernel<double>(A.ckt);
+  if (!kc) {
+    set_error("no candidate-source chi^2 kernel for window %d", A.ckt);
+    return SL_ENOIMPL;
+  }
+  {
+    static std::mutex mu;
+    std::lock_guard<std::mutex> g(mu);
+    SL_HIP(hipFuncSetAttribute((const void*)kc, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c.lds));
+  }
+  hipLaunchKernelGGL(k_put_int, dim3(1), dim3(64), 0, st, ns_dev, ns);
+  if (int e = check_launch("k_put_int")) return e;
+  if (pb->dtype == SL_F32) {
+    hipLaunchKernelGGL(k_setup<float>, dim3(1), dim3(1024), 0, st, A, lams);
+    if (int e = check_launch("k_setup")) return e;
+    hipLaunchKernelGGL(k_prep<float>, dim3(1), dim3(1024), c.prep_lds, st, A);
+  } else {
+    hipLaunchKernelGGL(k_setup<double>, dim3(1), dim3(1024), 0, st, A, lams);
+    if (int e = check_launch("k_setup")) return e;
+    hipLaunchKernelGGL(k_prep<double>, dim3(1), dim3(1024), c.prep_lds, st, A);
+  }
+  if (int e = check_launch("k_prep")) return e;
+  hipLaunchKernelGGL(kc, dim3(nb), dim3(nt), c.lds, st, A, sources, n_sources, chi2);
+  return check_launch("k_chi2_src");
 }
 
 int sl_solve_autotune(const sl_problem* pb, const double* lens, const int32_t* ns, int max_ns, int n_members,

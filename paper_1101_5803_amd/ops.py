@@ -198,6 +198,7 @@ class Solver:
         self.dtype = dtype
         self.device = d.device
         self._ws = None
+        self._cws = None   # workspace of chi2_sources
         # launch hint: a PSF whose second singular value is not negligible is not rank 1, so the solve
         # launches only the direct blur form (the device's own rank-1 test decides every other case)
         sv = np.linalg.svd(self.psf.cpu().numpy(), compute_uv=False)
@@ -301,6 +302,29 @@ class Solver:
         L.check(L.lib().sl_solve_implicit(ctypes.byref(self._pb), L.ptr(lens), L.ptr(ns), max_ns, M, int(n_iter),
                                           ctypes.byref(opts), L.ptr(ws), ws.numel(), ctypes.byref(res),
                                           L.stream_handle()), "sl_solve_implicit")
+        return out
+
+    def chi2_sources(self, lens, ns: int, sources: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """Image chi^2 of candidate sources for one lens (sl_chi2_sources): sources is a contiguous
+        float64 device tensor (P, ns*ns); returns (P,) float64 on the device."""
+        _dev_check(sources)
+        lens = torch.as_tensor(lens, dtype=torch.float64, device=self.device).contiguous().reshape(-1)
+        if lens.numel() != 7:
+            raise L.SemilinError("lens must hold the 7 lens parameters")
+        if sources.dtype != torch.float64 or not sources.is_contiguous() or sources.dim() != 2 \
+                or sources.shape[1] != ns * ns:
+            raise L.SemilinError("sources must be a contiguous float64 device tensor (P, ns*ns)")
+        P = sources.shape[0]
+        if out is None:
+            out = torch.empty(P, dtype=torch.float64, device=self.device)
+        need = L.lib().sl_chi2_sources_workspace_size(ctypes.byref(self._pb), int(ns))
+        if need == 0:
+            raise L.SemilinError(L.lib().sl_last_error().decode())
+        if self._cws is None or self._cws.numel() < need:
+            self._cws = torch.empty(int(need), dtype=torch.uint8, device=self.device)
+        L.check(L.lib().sl_chi2_sources(ctypes.byref(self._pb), L.ptr(lens), int(ns), L.ptr(sources), P,
+                                        L.ptr(self._cws), self._cws.numel(), L.ptr(out), L.stream_handle()),
+                "sl_chi2_sources")
         return out
 
     def autotune(self, lens: torch.Tensor, ns: torch.Tensor, lambdas, tol=1e-7, maxit=4000,

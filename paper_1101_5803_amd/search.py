@@ -17,6 +17,10 @@ One generation of the simplified Ferret GA:
 Linkage learning, niching, adaptive control and islands are not modelled.
 All random numbers are inputs (a dict of one generation's draws).
 
+The final source refinement (SourceRefinement, Sec. 3.2) runs the same GA
+over the source nodes within bounds about the regularised solution, with
+the device's batched candidate-source chi^2 as fitness.
+
 The swarm (SwarmSearch, Sec. 3.1.2 and App. A.2) is the second outer loop:
 particles pulled towards their own and the swarm's best positions, moved
 along Locust's exact damped-oscillator orbits or by Eq. 21 itself.
@@ -69,15 +73,16 @@ class Box:
 
 
 def make_offspring(X: np.ndarray, parent: np.ndarray, partner: np.ndarray, xi: np.ndarray, mut_u: np.ndarray,
-                   mut_z: np.ndarray, cfg: GAConfig) -> np.ndarray:
-    """Crossover + mutation of copies of X[parent] (one row per candidate)."""
+                   mut_z: np.ndarray, cfg: GAConfig, periodic=PERIODIC_GENES) -> np.ndarray:
+    """Crossover + mutation of copies of X[parent] (one row per candidate); the genes in `periodic`
+    wrap, the others are clipped to [0, 1]."""
     base = X[parent]
     step = (np.abs(xi) * cfg.xover_strength)[:, None]
     Y = base + step * (X[partner] - base)
     Y = Y + np.where(mut_u < cfg.pmutate, cfg.mutation_scale * mut_z, 0.0)
-    for g in range(X.shape[1]):
-        Y[:, g] = np.mod(Y[:, g], 1.0) if g in PERIODIC_GENES else np.clip(Y[:, g], 0.0, 1.0)
-    return Y
+    wrap = np.zeros(X.shape[1], dtype=bool)
+    wrap[list(periodic)] = True
+    return np.where(wrap[None, :], np.mod(Y, 1.0), np.clip(Y, 0.0, 1.0))
 
 
 def tournament(X, fX, Y, fY, perm):
@@ -435,6 +440,73 @@ class SwarmSearch:
         self.history.append(float(self.fP[self.g]))
         if self.log is not None:
             self.log(dict(step=self.steps, evals=self.evals, best=self.history[-1], median=float(np.median(f))))
+
+
+class SourceRefinement:
+    """Bounded genetic search over the source nodes for a fixed lens (Sec. 3.2).
+
+    Every node is a free parameter within bounds that keep the source
+    non-negative: a window about the optimally regularised solution s*
+    (+-25 % of s*_i for s*_i >= 0, [0, |s*_i| + 15 %] for s*_i < 0), or the
+    full box [0, 1.1 max s*] (Sec. 4).  Genes are unit coordinates, s = lo +
+    u (hi - lo); one generation is the GA of GeneticSearch over all nodes,
+    none of them periodic; the first generation holds s* (its unit
+    coordinates) as individual 0.  The fitness is the image chi^2 of every
+    candidate source, one device call per generation (sl_chi2_sources), and
+    chi2_r = chi2 / (J - I) since the nodes are the free parameters.
+    All random numbers are inputs.
+    """
+
+    def __init__(self, solver: ops.Solver | None, lens, ns: int, s_star, X0: np.ndarray, cfg: GAConfig = GAConfig(),
+                 bounds: str = "window", log=None, fitness=None, n_pixels: int | None = None):
+        """fitness (optional) maps physical sources (n, I) to chi^2 instead of the device call; n_pixels is
+        J when no solver is given."""
+        self.solver, self.cfg, self.log = solver, cfg, log
+        self._fit = fitness
+        self.lens = np.asarray(lens, dtype=np.float64)
+        self.ns = int(ns)
+        s = np.asarray(s_star, dtype=np.float64).reshape(-1)
+        if bounds == "window":
+            self.lo = np.where(s >= 0.0, 0.75 * s, 0.0)
+            self.hi = np.where(s >= 0.0, 1.25 * s, 1.15 * np.abs(s))
+        else:
+            self.lo, self.hi = np.zeros_like(s), np.full_like(s, 1.1 * s.max())
+        span = self.hi - self.lo
+        u0 = np.clip(np.divide(s - self.lo, span, out=np.zeros_like(s), where=span > 0.0), 0.0, 1.0)
+        self.X = np.array(X0, dtype=np.float64)
+        self.X[0] = u0
+        self.evals = 0
+        self.fX = self._fitness(self.X)
+        self.generation = 0
+        self.history = [float(self.fX.min())]
+        self.dof = (solver.grid.J if solver is not None else int(n_pixels)) - s.size
+
+    def sources(self, U: np.ndarray) -> np.ndarray:
+        return self.lo + np.asarray(U) * (self.hi - self.lo)
+
+    def _fitness(self, U: np.ndarray) -> np.ndarray:
+        self.evals += U.shape[0]
+        if self._fit is not None:
+            return np.asarray(self._fit(self.sources(U)), dtype=np.float64)
+        S = torch.tensor(self.sources(U), dtype=torch.float64, device=self.solver.device)
+        return self.solver.chi2_sources(self.lens, self.ns, S).cpu().numpy()
+
+    @property
+    def best(self):
+        i = int(np.argmin(self.fX))
+        return self.sources(self.X[i]), float(self.fX[i])
+
+    def step(self, draws: dict) -> None:
+        P = self.X.shape[0]
+        Y = make_offspring(self.X, np.arange(P), draws["partner"], draws["xstrength"], draws["mut_mask"],
+                           draws["mut_step"], self.cfg, periodic=())
+        fY = self._fitness(Y)
+        self.X, self.fX = tournament(self.X, self.fX, Y, fY, draws["perm"])
+        self.generation += 1
+        self.history.append(float(self.fX.min()))
+        if self.log is not None:
+            self.log(dict(generation=self.generation, evals=self.evals, best=self.history[-1],
+                          best_chi2_r=self.history[-1] / self.dof))
 
 
 def _spearman(a, b) -> float:
