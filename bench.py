@@ -332,6 +332,7 @@ def main():
                                                                      max_ns)
     mc = mc_dof_step(sl, torch, solver, lens_d, ns_d, w, max_ns, M, args.steps)
     imp = implicit_step(torch, solver, lens_d, ns_d, max_ns, M, args.steps)
+    ref = refine_step(torch, solver, z, w, args.steps)
     # plain: the same library, one member per call
     plain_value = None
     if not args.no_plain:
@@ -351,6 +352,7 @@ def main():
         "autotune": tune,
         "mc_dof": mc,
         "implicit": imp,
+        "refine": ref,
         "roofline": roof,
     }
     if not args.no_cpu_baseline and args.workload == "c3" and not f64 and args.psf == "gauss":
@@ -359,6 +361,24 @@ def main():
                out["s_corner"].cpu().numpy(), out["s_off"].cpu().numpy())
         rec["cpu_baseline"] = cpu_baseline(w, z, pop, grids, args.cpu_members, gpu)
     print(json.dumps(rec), flush=True)
+
+
+def refine_step(torch, solver, z, w, steps, P=1024):
+    """The source-refinement fitness (Sec. 3.2): image chi^2 of P candidate sources for the true lens on a
+    64 x 64 grid (c2's), one sl_chi2_sources call per generation; candidates per second."""
+    print("[bench] source-refinement chi^2", file=sys.stderr, flush=True)
+    ns = 64
+    rng = np.random.default_rng(12)
+    S = torch.tensor(rng.uniform(0.0, 1.0, (P, ns * ns)), device=solver.device)
+    out = torch.empty(P, dtype=torch.float64, device=solver.device)
+    solver.chi2_sources(z["lens"], ns, S, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        solver.chi2_sources(z["lens"], ns, S, out=out)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / steps
+    return {"candidates": P, "ns": ns, "ms_per_generation": round(ms, 3), "candidates_per_s": round(P / ms * 1e3, 1)}
 
 
 def implicit_step(torch, solver, lens_d, ns_d, max_ns, M, steps, n_iter=40):

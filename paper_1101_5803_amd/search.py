@@ -509,6 +509,37 @@ class SourceRefinement:
                           best_chi2_r=self.history[-1] / self.dof))
 
 
+def confidence_sets(P: np.ndarray, f: np.ndarray, dof: float, levels=(0.683, 0.954, 0.99), n_up: float | None = None):
+    """Optimal set and confidence regions of the lens parameters (Sec. 3).
+
+    P: (n, k) physical parameters of every evaluated solution, f: their chi^2,
+    dof: the effective degrees of freedom of the best solution (J - gamma, the
+    Monte Carlo estimate).  The fuzzy optimal set is chi^2 <= chi^2_min + N_u
+    (N_u defaults to the 99 % threshold below).  The standard method (Press
+    et al., joint confidence region of k parameters): chi^2 is rescaled by
+    the best solution's reduced chi^2 (chi^2_min / dof) so that the best fit
+    has chi^2_r = 1, and the region at level p holds the solutions within
+    Delta(p) = the p quantile of the chi^2 distribution with k degrees of
+    freedom of the minimum.  Returns dict(optimal=mask, levels={p: dict(mask,
+    lo, hi)}) with per-parameter bounds over each region."""
+    from scipy.stats import chi2 as chi2_dist
+    P = np.asarray(P, dtype=np.float64)
+    f = np.asarray(f, dtype=np.float64)
+    ok = np.isfinite(f)
+    i0 = int(np.argmin(np.where(ok, f, np.inf)))
+    fmin = f[i0]
+    scale = fmin / float(dof)
+    k = P.shape[1]
+    d99 = chi2_dist.ppf(max(levels), k)
+    n_up = d99 * scale if n_up is None else float(n_up)
+    out = {"optimal": ok & (f <= fmin + n_up), "best": P[i0].copy(), "chi2_r_min": scale, "levels": {}}
+    for p in levels:
+        m = ok & ((f - fmin) / scale <= chi2_dist.ppf(p, k))
+        out["levels"][p] = {"mask": m, "delta_chi2": float(chi2_dist.ppf(p, k)),
+                            "lo": P[m].min(axis=0), "hi": P[m].max(axis=0)}
+    return out
+
+
 def _spearman(a, b) -> float:
     ra = np.argsort(np.argsort(a))
     rb = np.argsort(np.argsort(b))

@@ -151,3 +151,32 @@ def test_swarm_improves_and_replays_exactly(exact):
     assert h[-1] < h[0]
     assert runs[0].evals == N * (T + 1)
     assert np.array_equal(runs[0].P, runs[1].P) and np.array_equal(runs[0].history, runs[1].history)
+
+
+def test_confidence_sets_from_a_ga_run():
+    """Sec. 3: the optimal set of a GA run and its confidence regions, with the
+    best solution's degrees of freedom from the Monte Carlo estimate on the
+    device.  The regions are nested, hold the best solution, and bound it."""
+    from paper_1101_5803_amd import search
+    fit, solver, box, w = _fitness()
+    P, G = 64, 4
+    X0 = np.random.default_rng(2).uniform(size=(P, 7))
+    dr = synthgen.ga_draws(3, P, G)
+    s = search.GeneticSearch(fit, X0)
+    for g in range(G):
+        s.step({k: v[g] for k, v in dr.items()})
+    U, f = np.concatenate(s.data_U), np.concatenate(s.data_f)
+    best = U[np.argmin(np.where(np.isfinite(f), f, np.inf))]
+    noise = torch.tensor(synthgen.mc_draws(5, w.ny, w.nx).reshape(-1), device=DEV)
+    out = solver.solve_semilinear(torch.tensor(box.to_phys(best[None]), device=DEV),
+                                  torch.tensor([32], dtype=torch.int32, device=DEV), w.lambdas, tol=w.tol, max_ns=32,
+                                  mc_noise=noise)
+    dof = float(out["dof"][0].item())
+    assert 0 < dof < w.nx * w.ny
+    r = search.confidence_sets(box.to_phys(U), f, dof)
+    m68, m95, m99 = (r["levels"][p]["mask"] for p in (0.683, 0.954, 0.99))
+    assert np.all(m68 <= m95) and np.all(m95 <= m99) and np.all(m99 <= r["optimal"])
+    b = box.to_phys(best[None])[0]
+    assert np.allclose(r["best"], b)
+    for p, lev in r["levels"].items():
+        assert np.all(lev["lo"] <= b + 1e-12) and np.all(b <= lev["hi"] + 1e-12), p
