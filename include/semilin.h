@@ -61,6 +61,7 @@ extern "C" {
 #endif
 
 enum { SL_OK = 0, SL_EINVAL = -1, SL_EHIP = -2, SL_ENOIMPL = -3 };
+enum { SL_INTERP_BILINEAR = 0, SL_INTERP_NEAREST = 1 };
 enum { SL_F32 = 0, SL_F64 = 1 };                  /* arithmetic of the bulk work */
 enum { SL_H_IDENTITY = 0, SL_H_CURVATURE = 1 };   /* regularisation operator H */
 
@@ -159,6 +160,9 @@ typedef struct {
                           the PSF is not rank 1, and only the direct form is launched (as
                           with sl_tuning.blur_direct; correct for any PSF, slower for a
                           separable one) */
+  int interp;          /* source interpolation in L (Sec. 2.1): SL_INTERP_BILINEAR (the four
+                          nodes around a subpixel, weighted), or SL_INTERP_NEAREST (the
+                          nearest node, weight 1; a fraction of exactly 1/2 rounds up) */
 } sl_problem;
 
 /*

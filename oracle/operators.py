@@ -31,11 +31,15 @@ import numpy as np
 # --------------------------------------------------------------------------
 # bilinear lens operator
 # --------------------------------------------------------------------------
-def bilinear_table(bx, by, ns: int, half_width: float):
+def bilinear_table(bx, by, ns: int, half_width: float, nearest: bool = False):
     """Per-subpixel node indices and weights (before the 1/n^2 average).
 
     Returns (idx, w, inside): idx int64 (J, n2, 4), w float64 (J, n2, 4),
     inside bool (J, n2).  Outside subpixels get idx 0 and weight 0.
+    nearest: nearest-neighbour interpolation instead (Sec. 2.1): the node of
+    the cell nearest the subpixel gets weight 1 (reading: a fraction of
+    exactly 1/2 goes to the upper node), written as the bilinear weights of
+    the fractions rounded to 0 or 1.
     """
     h = 2.0 * half_width / (ns - 1)
     u = (np.asarray(bx) + half_width) / h
@@ -47,6 +51,9 @@ def bilinear_table(bx, by, ns: int, half_width: float):
     r0 = np.minimum(np.floor(vs), ns - 2).astype(np.int64)
     fx = us - c0
     fy = vs - r0
+    if nearest:
+        fx = np.where(fx >= 0.5, 1.0, 0.0)
+        fy = np.where(fy >= 0.5, 1.0, 0.0)
     i00 = r0 * ns + c0
     idx = np.stack([i00, i00 + 1, i00 + ns, i00 + ns + 1], axis=-1)
     w = np.stack([(1 - fx) * (1 - fy), fx * (1 - fy), (1 - fx) * fy, fx * fy], axis=-1)

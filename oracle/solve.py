@@ -44,10 +44,11 @@ class Problem:
     ns: int
     half_width: float
     reg: str               # "identity" | "curvature"
+    interp: str = "bilinear"   # "bilinear" | "nearest" (Sec. 2.1)
 
     def __post_init__(self):
         bx, by = _lens.trace_image(self.lens, self.nx, self.ny, self.pix, self.nsub)
-        self.table = _ops.bilinear_table(bx, by, self.ns, self.half_width)
+        self.table = _ops.bilinear_table(bx, by, self.ns, self.half_width, nearest=self.interp == "nearest")
         self.I = self.ns * self.ns
 
     # operators -------------------------------------------------------------

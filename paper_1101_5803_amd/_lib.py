@@ -36,7 +36,8 @@ class ImageGrid(ctypes.Structure):
 class Problem(ctypes.Structure):
     _fields_ = [("img", ImageGrid), ("d", ctypes.c_void_p), ("sigma", ctypes.c_double),
                 ("psf", ctypes.c_void_p), ("k", ctypes.c_int), ("half_width", ctypes.c_double),
-                ("reg", ctypes.c_int), ("dtype", ctypes.c_int), ("psf_general", ctypes.c_int)]
+                ("reg", ctypes.c_int), ("dtype", ctypes.c_int), ("psf_general", ctypes.c_int),
+                ("interp", ctypes.c_int)]
 
 
 class Tuning(ctypes.Structure):
@@ -50,6 +51,7 @@ class SolveOpts(ctypes.Structure):
 
 
 N_VARIANTS = 16
+SL_INTERP_BILINEAR, SL_INTERP_NEAREST = 0, 1
 
 
 class Result(ctypes.Structure):

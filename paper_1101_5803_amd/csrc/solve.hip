@@ -167,6 +167,7 @@ struct SolveArgs {
   int force_csr;    // variant: transposed operator as CSR rows
   int force_direct; // direct K x K blur only (variant, or the caller's hint that the PSF is not rank 1)
   int psf_general;  // the caller's hint: the PSF is not rank 1
+  int interp;       // SL_INTERP_BILINEAR | SL_INTERP_NEAREST (the fractions k_prep stores)
   int prep_tags;    // k_prep has one LDS int per node after its 8 I_max + 768 bytes (conflict tags)
   int implicit;     // implicit regularisation: n_lambda unregularised CG iterations (k_implicit)
   int heavy;        // smallest lambdas of each member queued ahead of the rest
@@ -913,6 +914,9 @@ __device__ void prep_member(const SolveArgs& a, int m, MemberInfo mi, const doub
         if (!grid_cell((bx + a.R) / h, (by + a.R) / h, ns, cell, fx, fy)) {
           cell = -1;
           fx = fy = 0.0;
+        } else if (a.interp == SL_INTERP_NEAREST) {   // the nearest of the cell's four nodes, weight 1
+          fx = fx >= 0.5 ? 1.0 : 0.0;
+          fy = fy >= 0.5 ? 1.0 : 0.0;
         }
         cellp[(long)slot * n2 + k] = cell;
         fxp[(long)slot * n2 + k] = (T)fx;
@@ -2599,6 +2603,7 @@ static int check_problem(const sl_problem* pb, int max_ns, int M, int NL) {
   SL_REQUIRE(pb->reg == SL_H_IDENTITY || pb->reg == SL_H_CURVATURE, "unknown reg %d", pb->reg);
   SL_REQUIRE(pb->dtype == SL_F32 || pb->dtype == SL_F64, "unknown dtype %d", pb->dtype);
   SL_REQUIRE(pb->psf_general == 0 || pb->psf_general == 1, "psf_general must be 0 or 1");
+  SL_REQUIRE(pb->interp == SL_INTERP_BILINEAR || pb->interp == SL_INTERP_NEAREST, "unknown interp %d", pb->interp);
   SL_REQUIRE(max_ns >= 2 && max_ns <= 128, "max_ns %d outside [2, 128]", max_ns);
   SL_REQUIRE(M >= 1 && M <= (1 << 20), "n_members %d out of range", M);
   SL_REQUIRE(NL >= 1 && NL <= SL_MAX_LAMBDA, "n_lambda %d outside [1, %d]", NL, SL_MAX_LAMBDA);
@@ -2977,6 +2982,7 @@ static int prepare(const sl_problem* pb, const double* lens, const int32_t* ns, 
   A.ck = (pb->k - 1) / 2;
   A.reg = pb->reg;
   A.psf_general = pb->psf_general != 0;
+  A.interp = pb->interp;
   A.n_members = n_members;
   A.n_lambda = n_lambda;
   A.max_ns = max_ns;

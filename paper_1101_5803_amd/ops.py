@@ -16,6 +16,7 @@ from . import _lib as L
 
 _DT = {torch.float32: L.SL_F32, torch.float64: L.SL_F64}
 _REG = {"identity": L.SL_H_IDENTITY, "curvature": L.SL_H_CURVATURE}
+_INTERP = {"bilinear": L.SL_INTERP_BILINEAR, "nearest": L.SL_INTERP_NEAREST}
 TUNING_KEYS = ("wide_window", "lt_csr", "blur_direct", "plain_cg", "pc_theta_pct", "heavy")
 
 
@@ -185,7 +186,7 @@ class Solver:
     """
 
     def __init__(self, d: torch.Tensor, sigma: float, psf: torch.Tensor, grid: Grid, half_width: float,
-                 reg: str = "curvature", dtype: torch.dtype = torch.float32):
+                 reg: str = "curvature", dtype: torch.dtype = torch.float32, interp: str = "bilinear"):
         _dev_check(d, psf)
         self.d = d.to(torch.float64).contiguous().reshape(-1)
         self.psf = psf.to(torch.float64).contiguous()
@@ -205,7 +206,7 @@ class Solver:
         general = int(sv.size > 1 and sv[1] > 1e-8 * sv[0])
         self._pb = L.Problem(grid.c(), ctypes.c_void_p(self.d.data_ptr()), self.sigma,
                              ctypes.c_void_p(self.psf.data_ptr()), self.psf.shape[0], self.half_width,
-                             _REG[reg], _DT[dtype], general)
+                             _REG[reg], _DT[dtype], general, _INTERP[interp])
 
     def workspace_bytes(self, max_ns: int, n_members: int, n_lambda: int) -> int:
         n = L.lib().sl_solve_workspace_size(ctypes.byref(self._pb), max_ns, n_members, n_lambda)

@@ -30,7 +30,13 @@ root:  python tests/golden/make_golden.py   (about two minutes on 8 cores)
   iterations, corner, and the solution at every lambda in FP32 (about a
   minute on 8 cores).
 
+* c2_nearest.npz -- the c2 lens and image with nearest-neighbour source
+  interpolation (Sec. 2.1), 6 lambdas over 1e-3..1e1: chi^2, ||H s||^2,
+  iterations, corner and corner solution, from the numpy FP64 CG at tol
+  1e-10 (about two minutes on 6 cores).
+
 `python tests/golden/make_golden.py c4` writes only c4_sample.npz;
+`python tests/golden/make_golden.py c2nearest` writes only c2_nearest.npz;
 `python tests/golden/make_golden.py c2radial` writes only c2_radial.npz;
 `python tests/golden/make_golden.py c3full` writes only c3_full.npz;
 `python tests/golden/make_golden.py c2nsub` writes only c2_nsub.npz.
@@ -145,7 +151,33 @@ def c2_radial():
                         s_corner=outs[k]["s"][0, 0])
 
 
+def c2_nearest():
+    import concurrent.futures as cf
+    from oracle import solve
+    w = synthgen.C2
+    D = mock.workload_data(w)
+    lams = synthgen.log_grid(1e-3, 1e1, 6)
+    pb = solve.Problem(D["lens"], D["d"], D["sigma"], D["psf"], w.nx, w.ny, w.pix, w.nsub_model, w.ns,
+                       w.half_width, w.reg, "nearest")
+
+    def one(lam):
+        s, it, st = solve.solve_cg(pb, lam, tol=1e-10)
+        return s, it, st
+
+    with cf.ThreadPoolExecutor(6) as ex:
+        outs = list(ex.map(one, lams))
+    chi2 = np.array([pb.chi2(o[0]) for o in outs])
+    reg = np.array([pb.regterm(o[0]) for o in outs])
+    k = lcurve.corner(reg, chi2)[0]
+    np.savez_compressed(os.path.join(HERE, "c2_nearest.npz"), lambdas=np.array(lams), chi2=chi2, reg=reg,
+                        iters=np.array([o[1] for o in outs]), status=np.array([o[2] for o in outs]), k_star=k,
+                        s=np.stack([o[0] for o in outs]))
+
+
 def main():
+    if sys.argv[1:] == ["c2nearest"]:
+        c2_nearest()
+        return
     if sys.argv[1:] == ["c2radial"]:
         c2_radial()
         return

@@ -362,3 +362,38 @@ def test_psf_general_hint_changes_no_result(sl):
     c, d = res[("gauss", 0)], res[("gauss", 1)]
     assert np.all(c["status"] == 0) and np.all(d["status"] == 0)
     assert np.all(np.abs(c["chi2"] - d["chi2"]) <= 2e-5 * c["chi2"])
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_c2_nearest_neighbour_vs_oracle(sl, dtype):
+    """Nearest-neighbour source interpolation (Sec. 2.1) at the c2 size against
+    the oracle (tests/golden/c2_nearest.npz, 6 lambdas, FP64 CG to 1e-10):
+    FP32 chi^2 within 1e-5, ||H s||^2 within 1e-3 from k* - 2, the corner
+    solution within 1e-4; FP64 1e-9, 1e-7, 1e-7."""
+    g = np.load(os.path.join(GOLD, "c2_nearest.npz"))
+    w = synthgen.C2
+    z = np.load(os.path.join(HERE, "data", "c2.npz"))
+    solver = sl.Solver(torch.tensor(z["d"], device=DEV), float(z["sigma"]), torch.tensor(z["psf"], device=DEV),
+                       sl.Grid(w.nx, w.ny, w.pix, w.nsub_model), w.half_width, reg=w.reg, dtype=dtype,
+                       interp="nearest")
+    f64 = dtype == torch.float64
+    lams = [float(x) for x in g["lambdas"]]
+    out = _np(solver.solve_semilinear(torch.tensor(np.atleast_2d(z["lens"]), device=DEV),
+                                      torch.tensor([w.ns], dtype=torch.int32, device=DEV), lams,
+                                      tol=1e-10 if f64 else 1e-7, maxit=4000))
+    assert np.all(out["status"] == 0)
+    rel = np.abs(out["chi2"][0] - g["chi2"]) / g["chi2"]
+    assert rel.max() <= (1e-9 if f64 else 1e-5), rel
+    k = int(out["k_star"][0])
+    assert k in lcurve.corner_set(g["reg"], g["chi2"]) | {int(g["k_star"])}, (k, int(g["k_star"]))
+    lo = max(0, min(k, int(g["k_star"])) - 2)
+    rr = np.abs(out["reg"][0, lo:] - g["reg"][lo:]) / g["reg"][lo:]
+    assert rr.max() <= (1e-7 if f64 else 1e-3), rr
+    err = np.linalg.norm(out["s_corner"][:w.ns * w.ns] - g["s"][k]) / np.linalg.norm(g["s"][k])
+    assert err <= (1e-7 if f64 else 1e-4), err
+    # the interpolation changes the model: the bilinear solve gives other values
+    bil = _np(sl.Solver(torch.tensor(z["d"], device=DEV), float(z["sigma"]), torch.tensor(z["psf"], device=DEV),
+                        sl.Grid(w.nx, w.ny, w.pix, w.nsub_model), w.half_width, reg=w.reg, dtype=dtype)
+              .solve_semilinear(torch.tensor(np.atleast_2d(z["lens"]), device=DEV),
+                                torch.tensor([w.ns], dtype=torch.int32, device=DEV), lams, tol=1e-7, maxit=4000))
+    assert np.abs(bil["chi2"][0] - out["chi2"][0]).max() > 1e-3 * out["chi2"][0].min()

@@ -172,3 +172,25 @@ def test_sersic_profile_half_light_radius(n):
     cum = np.concatenate([[0.0], np.cumsum(0.5 * (ring[1:] + ring[:-1]) * np.diff(r))])
     inside = np.interp(blob["size"], r, cum)
     assert abs(inside / cum[-1] - 0.5) <= 3e-3
+
+
+def test_nearest_neighbour_L_picks_the_nearest_node():
+    """Nearest-neighbour interpolation (Sec. 2.1): each subpixel takes the value
+    of the grid node nearest its back-traced position (rounded half up),
+    computed here directly from the positions; L^T is its transpose."""
+    from oracle import lens as olens
+    ns, R, nsub, nx, ny, pix = 9, 0.6, 2, 16, 14, 0.08
+    g = np.array([0.3, 0.8, 0.5, 0.02, 0.1, 0.01, -0.02])
+    bx, by = olens.trace_image(g, nx, ny, pix, nsub)
+    tab = ops.bilinear_table(bx, by, ns, R, nearest=True)
+    s = np.random.default_rng(2).standard_normal(ns * ns)
+    h = 2 * R / (ns - 1)
+    u, v = (bx + R) / h, (by + R) / h
+    inside = (u >= 0) & (u <= ns - 1) & (v >= 0) & (v <= ns - 1)
+    cu = np.clip(np.floor(u + 0.5), 0, ns - 1).astype(int)
+    cv = np.clip(np.floor(v + 0.5), 0, ns - 1).astype(int)
+    want = np.where(inside, s[cv * ns + cu], 0.0).sum(axis=1) / nsub ** 2
+    got = ops.apply_L(tab, s, nsub)
+    assert np.allclose(got, want, rtol=0, atol=1e-14)
+    y = np.random.default_rng(3).standard_normal(nx * ny)
+    assert abs(got @ y - s @ ops.apply_LT(tab, y, ns * ns, nsub)) <= 1e-12 * np.abs(got).sum()
