@@ -58,6 +58,7 @@ constexpr int kUpd = 4;        // CG vector-update chunk (nodes per thread)
 // The spectral preconditioner pays for its four n x n transforms only where
 // lambda H^T H dominates the spectrum: it is used when lambda >= kPcTheta c.
 constexpr int kPcThetaPct = 15;   // default theta = 0.15 (sl_tuning.pc_theta_pct = 0)
+constexpr int kFillW = 16;     // waves that fill the transposed operator in parallel (k_prep's 1024 threads)
 constexpr int kHeavy = 4;      // default count of smallest lambdas of each member queued ahead of the rest
 constexpr int kMaxCK = 31;
 
@@ -86,7 +87,7 @@ struct alignas(16) Consts {
 };
 
 struct Layout {
-  size_t consts, lam, taps_d, taps_f, minfo, queues, pqueues, pix, cell, fx, fy, b, bh, dofk, s_all, gframe, gz, rbuf, mcbuf, ibuf,
+  size_t consts, lam, taps_d, taps_f, minfo, queues, pqueues, pix, cell, fx, fy, b, bh, dofk, ltc, s_all, gframe, gz, rbuf, mcbuf, ibuf,
       lt_ptr, lt_perm,
       lt_ent,
       total;
@@ -178,6 +179,7 @@ struct SolveArgs {
   double* dofv;      // [n_members] result: bhat^T (bhat - A xhat) at the corner
   double* bh;        // [member][I_max] A^T bhat (FP64)
   double* dofk;      // [member][n_lambda] implicit solve: the estimate after each iterate
+  int* ltc;          // [member][I_max][kFillW] per-wave fill cursors of the transposed operator
   void* mcbuf;       // [n_wg][5][I_max] r, xhat, rhat, phat, saved p of the pass
   void* ibuf;        // [n_wg][J] image residual e = d - A s of the implicit-regularisation solve
 };
@@ -671,15 +673,51 @@ __device__ int build_transpose(const SolveArgs& a, int m, int ns, int slots, con
   }
   __syncthreads();
   const int estep = sell ? 64 : 1;
-  // Fill in a fixed order without sorting: one wave walks the slots 64 at a
-  // time; for pair q of every lane, lanes holding the same node take
-  // consecutive positions in lane order (a pixel's pairs have distinct nodes).
-  // Entries of a node are therefore ordered by (slot group, q, lane), the same
-  // on every run.
-  if (tid < 64 && n2 == 4) {
-    const int lane = tid;
-    for (int t0 = 0; t0 < slots; t0 += 64) {
-      const int t = t0 + lane;
+  // Fill in a fixed order without sorting.  The entries of a node are
+  // ordered by (slot group of 64, pair q, lane): lanes holding the same node
+  // take consecutive positions in lane order (a pixel's pairs have distinct
+  // nodes), the same on every run.
+  //
+  // 2 x 2 subpixels: the kFillW waves fill in parallel, wave w taking the
+  // contiguous range of slot groups [w G / kFillW, (w + 1) G / kFillW).  A
+  // first pass counts each node's entries per wave (global atomics into the
+  // member's cursor table), an exclusive scan over the waves gives wave w the
+  // position after the entries of the groups before its range, and then each
+  // wave walks its groups as one wave would.  So the order, and every sum
+  // built on it, is the order of a single wave walking all groups.  The
+  // waves share the LDS conflict tags: a clash seen through another wave's
+  // tag only sends a step down the exact counting path.
+  if (n2 == 4) {
+    const int G = (slots + 63) / 64;
+    const int w = tid >> 6, lane = tid & 63;
+    const int g0 = (w * G) / kFillW, g1 = ((w + 1) * G) / kFillW;
+    int* cw = a.ltc + (long)m * a.I_max * kFillW;   // [node][wave]
+    for (int e = tid; e < I * kFillW; e += blockDim.x) cw[e] = 0;
+    __syncthreads();
+    for (int g = g0; g < g1; ++g) {   // counts per (node, wave)
+      const int t = g * 64 + lane;
+      if (t < slots && pix[t] >= 0) {
+        int nd[16];
+        double ww[16];
+        pixel_pairs4(t, ns, cellp, fxp, fyp, nd, ww);
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+          if (nd[q] >= 0) atomicAdd(&cw[nd[q] * kFillW + w], 1);
+      }
+    }
+    __syncthreads();
+    for (int i = tid; i < I; i += blockDim.x) {   // exclusive scan over the waves; cnt[i] keeps the total
+      int run = 0;
+      for (int v = 0; v < kFillW; ++v) {
+        const int c = __hip_atomic_load(&cw[i * kFillW + v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&cw[i * kFillW + v], run, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        run += c;
+      }
+      cnt[i] = run;
+    }
+    __syncthreads();
+    for (int g = g0; g < g1; ++g) {   // uniform per wave
+      const int t = g * 64 + lane;
       int nd[16];
       double ww[16];
       int off = 0;
@@ -697,15 +735,19 @@ __device__ int build_transpose(const SolveArgs& a, int m, int ns, int slots, con
         if (!__builtin_amdgcn_readfirstlane((int)(__ballot(key >= 0) != 0ull))) continue;   // uniform
         int rank, total;
         lane_rank(key, tag, rank, total);
-        const int j = key >= 0 ? cnt[key] + rank : 0;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        int* cur = key >= 0 ? &cw[key * kFillW + w] : nullptr;
+        const int j = key >= 0 ? __hip_atomic_load(cur, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + rank : 0;
+        // every lane has read its cursor before the last lane of a node advances it
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        if (key >= 0 && rank == total - 1) cnt[key] = j + 1;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        if (key >= 0 && rank == total - 1)
+          __hip_atomic_store(cur, j + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // the advance is complete before this wave's next step reads the cursors
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        if (key >= 0) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        if (key >= 0 && j < cnt[key]) {   // j < cnt[key] always holds; the test keeps every write in the node's rows
           if (paired) {
             const long ps = ((long)(ipos[key] & ~63) >> 1) + 64L * (j >> 1) + (ipos[key] & 63);
             off16[2 * ps + (j & 1)] = (unsigned short)off;
@@ -2574,6 +2616,7 @@ static Layout make_layout(const sl_problem* pb, int max_ns, int M, int NL, int n
   L.b = take(sizeof(double) * (size_t)M * L.I_max);
   L.bh = take(sizeof(double) * (size_t)M * L.I_max);   // A^T bhat (Monte Carlo degrees of freedom)
   L.dofk = take(sizeof(double) * (size_t)M * NL);      // per-iterate estimate of the implicit solve
+  L.ltc = take(sizeof(int) * (size_t)M * L.I_max * kFillW);   // per-wave fill cursors (k_prep)
   L.s_all = take(sz * (size_t)M * NL * L.I_max);
   L.gframe_elems = (pb->img.ny + 4 * 16 + kSegR) * ((pb->img.nx + 4 * 16) | 1);   // widest window's halo
   L.gframe = take(sz * (size_t)n_wg * L.gframe_elems);
@@ -3019,6 +3062,7 @@ static int prepare(const sl_problem* pb, const double* lens, const int32_t* ns, 
   A.b = (double*)(ws + L.b);
   A.bh = (double*)(ws + L.bh);
   A.dofk = (double*)(ws + L.dofk);
+  A.ltc = (int*)(ws + L.ltc);
   A.mcbuf = ws + L.mcbuf;
   A.ibuf = ws + L.ibuf;
   A.mcn = opt->mc_noise;
