@@ -62,6 +62,44 @@ def bilinear_table(bx, by, ns: int, half_width: float, nearest: bool = False):
     return idx, w, inside
 
 
+def keys_weights(t):
+    """Cubic convolution weights (Keys 1981, a = -1/2) of the taps at offsets
+    -1, 0, 1, 2 from the cell's first node, for the fraction t in [0, 1]."""
+    t = np.asarray(t, dtype=np.float64)
+    return np.stack([((-0.5 * t + 1.0) * t - 0.5) * t,
+                     (1.5 * t - 2.5) * t * t + 1.0,
+                     ((-1.5 * t + 2.0) * t + 0.5) * t,
+                     (0.5 * t - 0.5) * t * t], axis=-1)
+
+
+def bicubic_table(bx, by, ns: int, half_width: float):
+    """Bicubic source interpolation (Sec. 2.1): the 4 x 4 nodes about the
+    subpixel's cell, weighted by cubic convolution in x and in y (Keys, a =
+    -1/2).  Reading: the cell and its fractions are those of the bilinear
+    table; a tap on a node outside the grid takes the source there as zero
+    (weight 0).  Returns (idx, w, inside) with a last axis of 16 taps
+    (row offset j, column offset i: tap 4 (j + 1) + (i + 1))."""
+    h = 2.0 * half_width / (ns - 1)
+    u = (np.asarray(bx) + half_width) / h
+    v = (np.asarray(by) + half_width) / h
+    inside = (u >= 0.0) & (u <= ns - 1) & (v >= 0.0) & (v <= ns - 1)
+    us = np.where(inside, u, 0.0)
+    vs = np.where(inside, v, 0.0)
+    c0 = np.minimum(np.floor(us), ns - 2).astype(np.int64)
+    r0 = np.minimum(np.floor(vs), ns - 2).astype(np.int64)
+    wx = keys_weights(us - c0)
+    wy = keys_weights(vs - r0)
+    idx = np.zeros(c0.shape + (16,), dtype=np.int64)
+    w = np.zeros(c0.shape + (16,))
+    for j in range(4):
+        for i in range(4):
+            r, c = r0 + j - 1, c0 + i - 1
+            ok = inside & (r >= 0) & (r < ns) & (c >= 0) & (c < ns)
+            idx[..., 4 * j + i] = np.where(ok, r * ns + c, 0)
+            w[..., 4 * j + i] = np.where(ok, wy[..., j] * wx[..., i], 0.0)
+    return idx, w, inside
+
+
 def apply_L(table, s, nsub: int):
     """Unblurred lensed image: img_j = n^-2 sum_sub sum_corner w s[node]."""
     idx, w, _ = table

@@ -44,11 +44,14 @@ class Problem:
     ns: int
     half_width: float
     reg: str               # "identity" | "curvature"
-    interp: str = "bilinear"   # "bilinear" | "nearest" (Sec. 2.1)
+    interp: str = "bilinear"   # "bilinear" | "nearest" | "bicubic" (Sec. 2.1)
 
     def __post_init__(self):
         bx, by = _lens.trace_image(self.lens, self.nx, self.ny, self.pix, self.nsub)
-        self.table = _ops.bilinear_table(bx, by, self.ns, self.half_width, nearest=self.interp == "nearest")
+        if self.interp == "bicubic":
+            self.table = _ops.bicubic_table(bx, by, self.ns, self.half_width)
+        else:
+            self.table = _ops.bilinear_table(bx, by, self.ns, self.half_width, nearest=self.interp == "nearest")
         self.I = self.ns * self.ns
 
     # operators -------------------------------------------------------------

@@ -194,3 +194,32 @@ def test_nearest_neighbour_L_picks_the_nearest_node():
     assert np.allclose(got, want, rtol=0, atol=1e-14)
     y = np.random.default_rng(3).standard_normal(nx * ny)
     assert abs(got @ y - s @ ops.apply_LT(tab, y, ns * ns, nsub)) <= 1e-12 * np.abs(got).sum()
+
+
+def test_bicubic_weights_and_quadratic_reproduction():
+    """Bicubic interpolation (Sec. 2.1) by cubic convolution (Keys 1981,
+    a = -1/2): the four weights sum to one, t = 0 and t = 1 hit the nodes, and
+    the scheme reproduces quadratics exactly, so wherever the 4 x 4 stencil
+    lies inside the grid L returns the quadratic's value at the subpixel;
+    L^T is its transpose."""
+    t = np.linspace(0, 1, 11)
+    W = ops.keys_weights(t)
+    assert np.allclose(W.sum(axis=-1), 1.0, atol=1e-15)
+    assert np.allclose(W[0], [0, 1, 0, 0]) and np.allclose(W[-1], [0, 0, 1, 0])
+    ns, R, nsub, nx, ny, pix = 12, 0.6, 2, 18, 16, 0.06
+    g = np.array([0.3, 0.8, 0.5, 0.02, 0.1, 0.01, -0.02])
+    bx, by = lens.trace_image(g, nx, ny, pix, nsub)
+    tab = ops.bicubic_table(bx, by, ns, R)
+    h = 2 * R / (ns - 1)
+    cc, rr = np.meshgrid(np.arange(ns), np.arange(ns))
+    quad = lambda x, y: 0.3 + 0.2 * x - 0.1 * y + 0.05 * x * x + 0.07 * x * y - 0.03 * y * y   # noqa: E731
+    s = quad(cc, rr).reshape(-1).astype(np.float64)
+    idx, w, inside = tab
+    u, v = (bx + R) / h, (by + R) / h
+    interior = inside & (u >= 1) & (u <= ns - 2) & (v >= 1) & (v <= ns - 2)
+    got = (w * s[idx]).sum(axis=-1)
+    assert interior.sum() > 50
+    assert np.allclose(got[interior], quad(u, v)[interior], rtol=0, atol=1e-12)
+    y = np.random.default_rng(3).standard_normal(nx * ny)
+    Ls = ops.apply_L(tab, s, nsub)
+    assert abs(Ls @ y - s @ ops.apply_LT(tab, y, ns * ns, nsub)) <= 1e-12 * np.abs(Ls).sum()
