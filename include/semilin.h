@@ -61,7 +61,7 @@ extern "C" {
 #endif
 
 enum { SL_OK = 0, SL_EINVAL = -1, SL_EHIP = -2, SL_ENOIMPL = -3 };
-enum { SL_INTERP_BILINEAR = 0, SL_INTERP_NEAREST = 1 };
+enum { SL_INTERP_BILINEAR = 0, SL_INTERP_NEAREST = 1, SL_INTERP_BICUBIC = 2 };
 enum { SL_F32 = 0, SL_F64 = 1 };                  /* arithmetic of the bulk work */
 enum { SL_H_IDENTITY = 0, SL_H_CURVATURE = 1 };   /* regularisation operator H */
 
@@ -161,8 +161,13 @@ typedef struct {
                           with sl_tuning.blur_direct; correct for any PSF, slower for a
                           separable one) */
   int interp;          /* source interpolation in L (Sec. 2.1): SL_INTERP_BILINEAR (the four
-                          nodes around a subpixel, weighted), or SL_INTERP_NEAREST (the
-                          nearest node, weight 1; a fraction of exactly 1/2 rounds up) */
+                          nodes around a subpixel, weighted), SL_INTERP_NEAREST (the
+                          nearest node, weight 1; a fraction of exactly 1/2 rounds up), or
+                          SL_INTERP_BICUBIC (cubic convolution, Keys a = -1/2, over the
+                          4 x 4 nodes about the subpixel's cell; nodes outside the grid
+                          are zero; L then has up to 16 n^2 entries per pixel, the
+                          transposed operator four times the bilinear storage, and the
+                          solve takes the direct blur form as with psf_general = 1) */
 } sl_problem;
 
 /*

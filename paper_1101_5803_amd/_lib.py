@@ -51,7 +51,7 @@ class SolveOpts(ctypes.Structure):
 
 
 N_VARIANTS = 16
-SL_INTERP_BILINEAR, SL_INTERP_NEAREST = 0, 1
+SL_INTERP_BILINEAR, SL_INTERP_NEAREST, SL_INTERP_BICUBIC = 0, 1, 2
 
 
 class Result(ctypes.Structure):

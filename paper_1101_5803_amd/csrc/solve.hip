@@ -166,9 +166,9 @@ struct SolveArgs {
   long long lt_cap; // entries per member
   int I_max;
   int force_csr;    // variant: transposed operator as CSR rows
-  int force_direct; // direct K x K blur only (variant, or the caller's hint that the PSF is not rank 1)
+  int force_direct; // direct K x K blur only (variant, the hint that the PSF is not rank 1, or bicubic L)
   int psf_general;  // the caller's hint: the PSF is not rank 1
-  int interp;       // SL_INTERP_BILINEAR | SL_INTERP_NEAREST (the fractions k_prep stores)
+  int interp;       // SL_INTERP_BILINEAR | NEAREST (the fractions k_prep stores) | BICUBIC
   int prep_tags;    // k_prep has one LDS int per node after its 8 I_max + 768 bytes (conflict tags)
   int implicit;     // implicit regularisation: n_lambda unregularised CG iterations (k_implicit)
   int heavy;        // smallest lambdas of each member queued ahead of the rest
@@ -399,6 +399,36 @@ __global__ void __launch_bounds__(1024) k_prep(SolveArgs a) {
   }
 }
 
+// Cubic convolution kernel (Keys 1981, a = -1/2) at distance d >= 0 from a
+// node; the tap at offset o (-1..2) from a cell's first node lies at
+// distance |f - o| for the fraction f in [0, 1].
+template <typename F>
+__device__ __forceinline__ F keys_w(F d) {
+  return d <= F(1) ? (F(1.5) * d - F(2.5)) * d * d + F(1)
+                   : (d < F(2) ? ((F(-0.5) * d + F(2.5)) * d - F(4)) * d + F(2) : F(0));
+}
+
+// Pair q (q < 16 n^2) of mapped slot t under bicubic interpolation: subpixel
+// q / 16, tap q % 16 = 4 (j + 1) + (i + 1) at row offset j and column offset
+// i from the cell's first node; node -1 for an off-grid subpixel or a tap
+// outside the grid (the source is zero there).  The weight includes the
+// 1/n^2 subpixel average.  Pairs are not merged: a node can occur at several
+// q of one pixel, each q adding its own entry.
+template <typename T>
+__device__ __forceinline__ void bicubic_pair(int t, int q, int ns, int n2, const int32_t* cellp, const T* fxp,
+                                             const T* fyp, int& node, double& w) {
+  const int k = q >> 4, j = (q >> 2) & 3, i = q & 3;
+  const int c = cellp[(long)t * n2 + k];
+  node = -1;
+  w = 0.0;
+  if (c < 0) return;
+  const int r = c / ns + j - 1, col = c % ns + i - 1;
+  if (r < 0 || r >= ns || col < 0 || col >= ns) return;
+  const double fx = (double)fxp[(long)t * n2 + k], fy = (double)fyp[(long)t * n2 + k];
+  node = r * ns + col;
+  w = keys_w(fabs(fy - (j - 1))) * keys_w(fabs(fx - (i - 1))) / n2;
+}
+
 // Trace, compaction and right-hand side of one valid member (all threads).
 // Unique (node, weight) pairs of the subpixels of mapped slot t, weights
 // including the 1/n^2 subpixel average; returns the pair count (<= 4 n^2).
@@ -538,7 +568,18 @@ __device__ int build_transpose(const SolveArgs& a, int m, int ns, int slots, con
   for (int i = tid; i < 128; i += blockDim.x) hist[i] = 0;
   if (tid == 0) totals[0] = totals[1] = 0;
   __syncthreads();
-  if (n2 == 4) {
+  const bool cubic = a.interp == SL_INTERP_BICUBIC;
+  if (cubic) {
+    for (int t = tid; t < slots; t += blockDim.x) {
+      if (pix[t] < 0) continue;
+      for (int q = 0; q < 16 * n2; ++q) {
+        int nd;
+        double ww;
+        bicubic_pair(t, q, ns, n2, cellp, fxp, fyp, nd, ww);
+        if (nd >= 0) atomicAdd(&cnt[nd], 1);
+      }
+    }
+  } else if (n2 == 4) {
     for (int t = tid; t < slots; t += blockDim.x) {
       if (pix[t] < 0) continue;
       int nd[16];
@@ -687,7 +728,7 @@ __device__ int build_transpose(const SolveArgs& a, int m, int ns, int slots, con
   // built on it, is the order of a single wave walking all groups.  The
   // waves share the LDS conflict tags: a clash seen through another wave's
   // tag only sends a step down the exact counting path.
-  if (n2 == 4) {
+  if (n2 == 4 && !cubic) {
     const int G = (slots + 63) / 64;
     const int w = tid >> 6, lane = tid & 63;
     const int g0 = (w * G) / kFillW, g1 = ((w + 1) * G) / kFillW;
@@ -769,13 +810,22 @@ __device__ int build_transpose(const SolveArgs& a, int m, int ns, int slots, con
         const int rc = pix[t];
         if (rc >= 0) {
           off = ((rc >> 16) - bbox[0] + halo) * pitch + ((rc & 0xFFFF) - bbox[2] + halo);
-          np = pixel_pairs(t, ns, n2, cellp, fxp, fyp, node, wt);
+          np = cubic ? 16 * n2 : pixel_pairs(t, ns, n2, cellp, fxp, fyp, node, wt);
         }
       }
       int npmax = np;
       for (int o = 32; o > 0; o >>= 1) npmax = max(npmax, __shfl_xor(npmax, o, 64));
       for (int q = 0; q < npmax; ++q) {
-        const int key = q < np ? node[q] : -1;
+        int key = -1;
+        double wq = 0.0;
+        if (q < np) {
+          if (cubic) {
+            bicubic_pair(t, q, ns, n2, cellp, fxp, fyp, key, wq);
+          } else {
+            key = node[q];
+            wq = wt[q];
+          }
+        }
         int rank, total;
         lane_rank(key, tag, rank, total);
         const int j = key >= 0 ? cnt[key] + rank : 0;
@@ -790,11 +840,11 @@ __device__ int build_transpose(const SolveArgs& a, int m, int ns, int slots, con
           if (paired) {
             const long ps = ((long)(ipos[key] & ~63) >> 1) + 64L * (j >> 1) + (ipos[key] & 63);
             off16[2 * ps + (j & 1)] = (unsigned short)off;
-            w32[2 * ps + (j & 1)] = (float)wt[q];
+            w32[2 * ps + (j & 1)] = (float)wq;
           } else {
             const long e = (long)ipos[key] + (long)estep * j;
             ent[e].off = off;
-            ent[e].w = (T)wt[q];
+            ent[e].w = (T)wq;
           }
         }
       }
@@ -860,7 +910,14 @@ __device__ void rhs_fixed_order(const SolveArgs& a, const double* vbuf, int ns, 
     const int t = t0 + lane;
     const int rc = pix[t];
     const double v = vbuf[t];
-    if (n2 == 4) {
+    if (a.interp == SL_INTERP_BICUBIC) {
+      for (int q = 0; q < 16 * n2; ++q) {
+        int nd = -1;
+        double w = 0.0;
+        if (rc >= 0) bicubic_pair(t, q, ns, n2, cellp, fxp, fyp, nd, w);
+        wave_ordered_add(bacc, tag, nd, w * v);
+      }
+    } else if (n2 == 4) {
       int nd[16];
       double ww[16];
       if (rc >= 0) {
@@ -1002,6 +1059,15 @@ __device__ void prep_member(const SolveArgs& a, int m, MemberInfo mi, const doub
     double num = 0.0, den = 0.0;
     for (int t = tid; t < Mm; t += blockDim.x) {
       if (pix[t] < 0) continue;
+      if (a.interp == SL_INTERP_BICUBIC) {
+        for (int q = 0; q < 16 * n2; ++q) {
+          int nd;
+          double w;
+          bicubic_pair(t, q, ns, n2, cellp, fxp, fyp, nd, w);
+          if (nd >= 0) num += w * bacc[nd] * bacc[nd];
+        }
+        continue;
+      }
       for (int k = 0; k < n2; ++k) {
         const int cell = cellp[(long)t * n2 + k];
         if (cell < 0) continue;
@@ -1272,10 +1338,41 @@ __device__ __attribute__((noinline)) double pc_apply(float* P, float* X, float* 
   return rzn;
 }
 
-// Bilinear value of the n x n subpixels of mapped pixel t: sum_k w_k . x[cell_k..]
+// Bicubic value of the n x n subpixels of mapped pixel t: for each subpixel
+// the 4 x 4 nodes about its cell, weighted by the cubic convolution kernel in
+// x and y, nodes outside the grid left out.
+template <typename T>
+__device__ __forceinline__ T pixel_gather_cubic(const T* X, int ns, int n2, int t, const int32_t* cellp,
+                                                const T* fxp, const T* fyp) {
+  T acc = 0;
+#pragma unroll 1
+  for (int k = 0; k < n2; ++k) {
+    const int c = cellp[(long)t * n2 + k];
+    if (c < 0) continue;
+    const T fx = fxp[(long)t * n2 + k], fy = fyp[(long)t * n2 + k];
+    const int r = c / ns, col = c % ns;
+#pragma unroll 1
+    for (int j = 0; j < 4; ++j) {
+      const int rr = r + j - 1;
+      if (rr < 0 || rr >= ns) continue;
+      T row = 0;
+#pragma unroll 1
+      for (int i = 0; i < 4; ++i) {
+        const int cc = col + i - 1;
+        if (cc >= 0 && cc < ns) row += keys_w(fabs(fx - (T)(i - 1))) * X[rr * ns + cc];
+      }
+      acc += keys_w(fabs(fy - (T)(j - 1))) * row;
+    }
+  }
+  return acc;
+}
+
+// Interpolated value of the n x n subpixels of mapped pixel t: sum_k w_k . x[cell_k..]
+// (bilinear weights, or the nearest node's weight 1; bicubic when `cubic`)
 template <typename T>
 __device__ __forceinline__ T pixel_gather(const T* X, int ns, int n2, int t, const int32_t* cellp, const T* fxp,
-                                          const T* fyp) {
+                                          const T* fyp, bool cubic) {
+  if (cubic) return pixel_gather_cubic(X, ns, n2, t, cellp, fxp, fyp);
   T acc = 0;
   if (n2 == 4) {
     const int4 c4 = reinterpret_cast<const int4*>(cellp)[t];
@@ -1310,65 +1407,6 @@ __device__ __forceinline__ T pixel_gather(const T* X, int ns, int n2, int t, con
     acc += (1 - fy) * ((1 - fx) * X[c] + fx * X[c + 1]) + fy * ((1 - fx) * X[c + ns] + fx * X[c + ns + 1]);
   }
   return acc;
-}
-
-// x[cell_k..] += w_k * v for the subpixels of mapped pixel t (LDS atomics).
-template <typename T>
-__device__ __forceinline__ void pixel_scatter(T* X, int ns, int n2, int t, T v, const int32_t* cellp, const T* fxp,
-                                              const T* fyp) {
-  if (n2 == 4) {
-    const int4 c4 = reinterpret_cast<const int4*>(cellp)[t];
-    T fx[4], fy[4];
-    if constexpr (sizeof(T) == 4) {
-      const float4 a4 = reinterpret_cast<const float4*>(fxp)[t];
-      const float4 b4 = reinterpret_cast<const float4*>(fyp)[t];
-      fx[0] = a4.x; fx[1] = a4.y; fx[2] = a4.z; fx[3] = a4.w;
-      fy[0] = b4.x; fy[1] = b4.y; fy[2] = b4.z; fy[3] = b4.w;
-    } else {
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        fx[k] = fxp[4L * t + k];
-        fy[k] = fyp[4L * t + k];
-      }
-    }
-    if (c4.x >= 0 && c4.x == c4.y && c4.x == c4.z && c4.x == c4.w) {
-      // all four subpixels in one cell: merge their weights, 4 atomics instead of 16
-      T w00 = 0, w01 = 0, w10 = 0, w11 = 0;
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        w00 += (1 - fx[k]) * (1 - fy[k]);
-        w01 += fx[k] * (1 - fy[k]);
-        w10 += (1 - fx[k]) * fy[k];
-        w11 += fx[k] * fy[k];
-      }
-      atomicAdd(&X[c4.x], w00 * v);
-      atomicAdd(&X[c4.x + 1], w01 * v);
-      atomicAdd(&X[c4.x + ns], w10 * v);
-      atomicAdd(&X[c4.x + ns + 1], w11 * v);
-      return;
-    }
-    const int cl[4] = {c4.x, c4.y, c4.z, c4.w};
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      if (cl[k] < 0) continue;
-      const int c = cl[k];
-      const T vy0 = (1 - fy[k]) * v, vy1 = fy[k] * v;
-      atomicAdd(&X[c], (1 - fx[k]) * vy0);
-      atomicAdd(&X[c + 1], fx[k] * vy0);
-      atomicAdd(&X[c + ns], (1 - fx[k]) * vy1);
-      atomicAdd(&X[c + ns + 1], fx[k] * vy1);
-    }
-    return;
-  }
-  for (int k = 0; k < n2; ++k) {
-    const int c = cellp[(long)t * n2 + k];
-    if (c < 0) continue;
-    const T fx = fxp[(long)t * n2 + k], fy = fyp[(long)t * n2 + k];
-    atomicAdd(&X[c], (1 - fx) * (1 - fy) * v);
-    atomicAdd(&X[c + 1], fx * (1 - fy) * v);
-    atomicAdd(&X[c + ns], (1 - fx) * fy * v);
-    atomicAdd(&X[c + ns + 1], fx * fy * v);
-  }
 }
 
 // Invalid or empty member: s = 0, chi^2 = sum d^2 / sigma^2 (no barriers).
@@ -1408,24 +1446,45 @@ struct OpView {
   int ns, I, M, r0, c0, h, w, pitch, fo, n2, nx, ny, K, ck, sell, Dr0, Dc0, Dh, Dw;
   bool sep, ident;
   T inv_n2, lamT;
+  bool cubic;                // bicubic L (16 nodes per subpixel); else bilinear or nearest
 };
 
 // y = L p into the frame: every mapped pixel is written once (assignment, so
 // the frame outside the mapped pixels keeps whatever it held, zero unless a
 // banded pass wrote it).  Two pixels per thread and step so that their table
 // loads are in flight together.
+// The bicubic form, out of line: its 16 taps per subpixel stay out of the
+// register budget of the persistent kernels that inline the other forms.
 template <typename T, int NT>
+__device__ __attribute__((noinline)) void gather_L_cubic(const int32_t* pix, const int32_t* cellp, const T* fxp,
+                                                        const T* fyp, T* F0, const T* P, int M, int ns, int n2,
+                                                        int pitch, int fo, T inv_n2) {
+  for (int t = threadIdx.x; t < M; t += NT) {
+    const int rc = pix[t];
+    if (rc >= 0) F0[(rc >> 16) * pitch + (rc & 0xFFFF) + fo] = pixel_gather_cubic(P, ns, n2, t, cellp, fxp, fyp) * inv_n2;
+  }
+}
+
+// CUBIC = false compiles the bicubic branch out (the banded-blur kernels: a
+// bicubic problem always takes the direct form).
+template <typename T, int NT, bool CUBIC = true>
 __device__ __forceinline__ void gather_L(const OpView<T>& o, const T* __restrict__ P) {
   const int32_t* pix = o.pix;
   T* const F0 = o.F0;
   const int M = o.M, ns = o.ns, n2 = o.n2, pitch = o.pitch, fo = o.fo;
   const T inv_n2 = o.inv_n2;
+  if constexpr (CUBIC) {
+    if (o.cubic) {
+      gather_L_cubic<T, NT>(pix, o.cellp, o.fxp, o.fyp, F0, P, M, ns, n2, pitch, fo, inv_n2);
+      return;
+    }
+  }
   for (int t = threadIdx.x; t < M; t += 2 * NT) {
     const int t2 = t + NT;
     const int rc = pix[t];
     const int rc2 = t2 < M ? pix[t2] : -1;
-    const T v1 = pixel_gather(P, ns, n2, t, o.cellp, o.fxp, o.fyp);
-    const T v2 = t2 < M ? pixel_gather(P, ns, n2, t2, o.cellp, o.fxp, o.fyp) : (T)0;
+    const T v1 = pixel_gather(P, ns, n2, t, o.cellp, o.fxp, o.fyp, false);
+    const T v2 = t2 < M ? pixel_gather(P, ns, n2, t2, o.cellp, o.fxp, o.fyp, false) : (T)0;
     if (rc >= 0) F0[(rc >> 16) * pitch + (rc & 0xFFFF) + fo] = v1 * inv_n2;
     if (rc2 >= 0) F0[(rc2 >> 16) * pitch + (rc2 & 0xFFFF) + fo] = v2 * inv_n2;
   }
@@ -1760,7 +1819,7 @@ __device__ __forceinline__ void clear_rows(const OpView<T>& o) {
 // <P, Q>.
 template <typename T, int CKT, int NT, bool DIR>
 __device__ __forceinline__ double apply_normal(const OpView<T>& o, const T* __restrict__ P, T* __restrict__ Q) {
-  gather_L<T, NT>(o, P);
+  gather_L<T, NT, DIR>(o, P);
   __syncthreads();
   if constexpr (!DIR) {   // the kernels of the banded form run only when the PSF is separable
     // w = B^T B y: banded pass along rows then along columns, in place
@@ -1864,7 +1923,7 @@ __device__ __forceinline__ void run_item(const SolveArgs& a, const MemberInfo& m
     }
     const OpView<T> ov{pix, cellp, fxp, fyp, F, F0, Z, Z + J, taps, lt_rp, lt_e, a.lt_perm + (long)m * a.I_max, ns,
                        I, M, r0, c0, h, w, pitch, fo, n2, nx, ny, K, ck, sell, Dr0, Dc0, Dh, Dw, sep, ident, inv_n2,
-                       lamT};
+                       lamT, a.interp == SL_INTERP_BICUBIC};
     double pq = apply_normal<T, CKT, NT, DIR>(ov, P, Q);
     pq = block_sum1<NT / kWave>(pq, red, 0);
     // every gather has read the frame (barrier above): back to zero for the next iteration
@@ -1940,7 +1999,9 @@ __device__ __forceinline__ void run_item(const SolveArgs& a, const MemberInfo& m
   __syncthreads();
   for (int t = tid; t < M; t += NT) {
     const int rc = pix[t];
-    if (rc >= 0) F0[(rc >> 16) * pitch + (rc & 0xFFFF) + fo] = pixel_gather(P, ns, n2, t, cellp, fxp, fyp) * inv_n2;
+    if (rc >= 0)
+      F0[(rc >> 16) * pitch + (rc & 0xFFFF) + fo] =
+          pixel_gather(P, ns, n2, t, cellp, fxp, fyp, DIR && a.interp == SL_INTERP_BICUBIC) * inv_n2;
   }
   double regacc = 0.0;
   for (int i = tid; i < I; i += NT) regacc += reg_node(P, ns, i / ns, i % ns, a.reg);
@@ -2071,7 +2132,8 @@ __device__ __forceinline__ void run_mc_item(const SolveArgs& a, const MemberInfo
                      reinterpret_cast<const LtEntry<T>*>(a.lt_ent) + (long)m * a.lt_cap, a.lt_perm + (long)m * a.I_max,
                      ns, I, M, r0, c0, h, w, pitch, -r0 * pitch - c0, n2, nx, ny, K, ck,
                      __builtin_amdgcn_readfirstlane(mi.sell), Dr0, Dc0, Dr1 - Dr0 + 1, Dc1 - Dc0 + 1,
-                     a.consts->sep != 0, a.reg == SL_H_IDENTITY, (T)1 / (T)n2, (T)a.lamv[kl]};
+                     a.consts->sep != 0, a.reg == SL_H_IDENTITY, (T)1 / (T)n2, (T)a.lamv[kl],
+                     a.interp == SL_INTERP_BICUBIC};
   for (int e = tid; e < frame_elems; e += NT) F[e] = (T)0;
   const double* bm = a.b + (long)m * a.I_max;
   const double* bhm = a.bh + (long)m * a.I_max;
@@ -2256,7 +2318,7 @@ __device__ __forceinline__ void run_implicit_item(const SolveArgs& a, const Memb
                      reinterpret_cast<const LtEntry<T>*>(a.lt_ent) + (long)m * a.lt_cap, a.lt_perm + (long)m * a.I_max,
                      ns, I, M, r0, c0, h, w, pitch, -r0 * pitch - c0, n2, nx, ny, K, ck,
                      __builtin_amdgcn_readfirstlane(mi.sell), Dr0, Dc0, Dh, Dw,
-                     a.consts->sep != 0, true, (T)1 / (T)n2, (T)0};
+                     a.consts->sep != 0, true, (T)1 / (T)n2, (T)0, a.interp == SL_INTERP_BICUBIC};
   // Frame: zero outside the mapped pixels whenever L p is gathered into it
   // (the adjoint blur's other writes are cleared after each L^T gather).
   for (int e = tid; e < frame_elems; e += NT) F[e] = (T)0;
@@ -2436,7 +2498,7 @@ __global__ void __launch_bounds__(kNTof<T>) k_chi2_src(SolveArgs a, const double
                      Z, Z + J, reinterpret_cast<const T*>(a.taps_t), a.lt_ptr,
                      reinterpret_cast<const LtEntry<T>*>(a.lt_ent), a.lt_perm, ns, I, M, r0, c0, h, w, pitch,
                      -r0 * pitch - c0, n2, nx, ny, K, ck, __builtin_amdgcn_readfirstlane(mi.sell), Dr0, Dc0, Dh, Dw,
-                     a.consts->sep != 0, true, (T)1 / (T)n2, (T)0};
+                     a.consts->sep != 0, true, (T)1 / (T)n2, (T)0, a.interp == SL_INTERP_BICUBIC};
   for (int e = tid; e < frame_elems; e += NT) F[e] = (T)0;
   double din = 0.0;
   for (int e = tid; e < Dh * Dw; e += NT) {
@@ -2626,7 +2688,8 @@ static Layout make_layout(const sl_problem* pb, int max_ns, int M, int NL, int n
   L.ibuf = take(sz * (size_t)n_wg * L.J);   // image residual of the implicit-regularisation solve
   L.lt_ptr = take(sizeof(int32_t) * (size_t)M * (L.I_max + 65));
   L.lt_perm = take(sizeof(int32_t) * (size_t)M * L.I_max);
-  L.lt_cap = 8LL * L.n2 * L.slot_cap;   // twice the unpadded bound: room for slice padding
+  // twice the unpadded bound (4 or, bicubic, 16 nodes per subpixel): room for slice padding
+  L.lt_cap = (pb->interp == SL_INTERP_BICUBIC ? 32LL : 8LL) * L.n2 * L.slot_cap;
   L.lt_ent = take((sz == 8 ? 16 : 8) * (size_t)M * (size_t)L.lt_cap);
   L.total = off;
   return L;
@@ -2646,7 +2709,8 @@ static int check_problem(const sl_problem* pb, int max_ns, int M, int NL) {
   SL_REQUIRE(pb->reg == SL_H_IDENTITY || pb->reg == SL_H_CURVATURE, "unknown reg %d", pb->reg);
   SL_REQUIRE(pb->dtype == SL_F32 || pb->dtype == SL_F64, "unknown dtype %d", pb->dtype);
   SL_REQUIRE(pb->psf_general == 0 || pb->psf_general == 1, "psf_general must be 0 or 1");
-  SL_REQUIRE(pb->interp == SL_INTERP_BILINEAR || pb->interp == SL_INTERP_NEAREST, "unknown interp %d", pb->interp);
+  SL_REQUIRE(pb->interp == SL_INTERP_BILINEAR || pb->interp == SL_INTERP_NEAREST || pb->interp == SL_INTERP_BICUBIC,
+             "unknown interp %d", pb->interp);
   SL_REQUIRE(max_ns >= 2 && max_ns <= 128, "max_ns %d outside [2, 128]", max_ns);
   SL_REQUIRE(M >= 1 && M <= (1 << 20), "n_members %d out of range", M);
   SL_REQUIRE(NL >= 1 && NL <= SL_MAX_LAMBDA, "n_lambda %d outside [1, %d]", NL, SL_MAX_LAMBDA);
@@ -2804,7 +2868,7 @@ static int configure(SolveArgs& A, const Layout& L, const sl_tuning& v, LaunchCf
   }
   A.ckt = ckt;
   A.force_csr = v.lt_csr != 0;
-  A.force_direct = v.blur_direct != 0 || A.psf_general != 0;
+  A.force_direct = v.blur_direct != 0 || A.psf_general != 0 || A.interp == SL_INTERP_BICUBIC;
   A.plain_cg = v.plain_cg != 0;
   A.pc_theta = (v.pc_theta_pct > 0 ? v.pc_theta_pct : kPcThetaPct) * 0.01f;
   A.heavy = v.heavy > 0 ? v.heavy : kHeavy;

@@ -16,7 +16,7 @@ from . import _lib as L
 
 _DT = {torch.float32: L.SL_F32, torch.float64: L.SL_F64}
 _REG = {"identity": L.SL_H_IDENTITY, "curvature": L.SL_H_CURVATURE}
-_INTERP = {"bilinear": L.SL_INTERP_BILINEAR, "nearest": L.SL_INTERP_NEAREST}
+_INTERP = {"bilinear": L.SL_INTERP_BILINEAR, "nearest": L.SL_INTERP_NEAREST, "bicubic": L.SL_INTERP_BICUBIC}
 TUNING_KEYS = ("wide_window", "lt_csr", "blur_direct", "plain_cg", "pc_theta_pct", "heavy")
 
 

@@ -35,8 +35,13 @@ root:  python tests/golden/make_golden.py   (about two minutes on 8 cores)
   iterations, corner and corner solution, from the numpy FP64 CG at tol
   1e-10 (about two minutes on 6 cores).
 
+* c2_bicubic.npz -- the same with bicubic source interpolation (Sec. 2.1;
+  cubic convolution, Keys a = -1/2, over the 4 x 4 nodes about each
+  subpixel's cell, nodes outside the grid zero).
+
 `python tests/golden/make_golden.py c4` writes only c4_sample.npz;
 `python tests/golden/make_golden.py c2nearest` writes only c2_nearest.npz;
+`python tests/golden/make_golden.py c2bicubic` writes only c2_bicubic.npz;
 `python tests/golden/make_golden.py c2radial` writes only c2_radial.npz;
 `python tests/golden/make_golden.py c3full` writes only c3_full.npz;
 `python tests/golden/make_golden.py c2nsub` writes only c2_nsub.npz.
@@ -151,14 +156,15 @@ def c2_radial():
                         s_corner=outs[k]["s"][0, 0])
 
 
-def c2_nearest():
+def c2_interp(kind):
+    """c2 with another source interpolation: writes c2_<kind>.npz."""
     import concurrent.futures as cf
     from oracle import solve
     w = synthgen.C2
     D = mock.workload_data(w)
     lams = synthgen.log_grid(1e-3, 1e1, 6)
     pb = solve.Problem(D["lens"], D["d"], D["sigma"], D["psf"], w.nx, w.ny, w.pix, w.nsub_model, w.ns,
-                       w.half_width, w.reg, "nearest")
+                       w.half_width, w.reg, kind)
 
     def one(lam):
         s, it, st = solve.solve_cg(pb, lam, tol=1e-10)
@@ -169,14 +175,17 @@ def c2_nearest():
     chi2 = np.array([pb.chi2(o[0]) for o in outs])
     reg = np.array([pb.regterm(o[0]) for o in outs])
     k = lcurve.corner(reg, chi2)[0]
-    np.savez_compressed(os.path.join(HERE, "c2_nearest.npz"), lambdas=np.array(lams), chi2=chi2, reg=reg,
+    np.savez_compressed(os.path.join(HERE, f"c2_{kind}.npz"), lambdas=np.array(lams), chi2=chi2, reg=reg,
                         iters=np.array([o[1] for o in outs]), status=np.array([o[2] for o in outs]), k_star=k,
                         s=np.stack([o[0] for o in outs]))
 
 
 def main():
     if sys.argv[1:] == ["c2nearest"]:
-        c2_nearest()
+        c2_interp("nearest")
+        return
+    if sys.argv[1:] == ["c2bicubic"]:
+        c2_interp("bicubic")
         return
     if sys.argv[1:] == ["c2radial"]:
         c2_radial()

@@ -121,3 +121,32 @@ def test_host_lcurve_corner_matches_oracle():
         assert np.array_equal(np.isnan(kap), np.isnan(kap_ref))
         ok = ~np.isnan(kap_ref)
         assert np.max(np.abs(kap[ok] - kap_ref[ok])) <= 1e-11 * np.max(kap_ref[ok])
+
+
+def test_interp_enum_and_workspace_on_host():
+    """The header's interpolation codes match the binding's, the workspace
+    grows with bicubic L (16 nodes per subpixel instead of 4: four times the
+    transposed-operator storage), and an unknown code is refused on the host."""
+    from paper_1101_5803_amd import _lib as B
+    src = open(HEADER).read()
+    for name in ("SL_INTERP_BILINEAR", "SL_INTERP_NEAREST", "SL_INTERP_BICUBIC"):
+        m = re.search(name + r"\s*=\s*(\d+)", src)
+        assert m and int(m.group(1)) == getattr(B, name), name
+    L = _lib()
+    L.sl_last_error.restype = ctypes.c_char_p
+    L.sl_solve_workspace_size.argtypes = [ctypes.POINTER(B.Problem)] + [ctypes.c_int] * 3
+    L.sl_solve_workspace_size.restype = ctypes.c_size_t
+
+    def size(interp):
+        pb = B.Problem()
+        pb.img = B.ImageGrid(64, 64, 0.05, 2)
+        pb.sigma, pb.k, pb.half_width = 1.0, 7, 1.0
+        pb.reg, pb.dtype, pb.psf_general, pb.interp = B.SL_H_CURVATURE, B.SL_F32, 0, interp
+        return L.sl_solve_workspace_size(ctypes.byref(pb), 48, 8, 6)
+
+    bil, near, cub = size(B.SL_INTERP_BILINEAR), size(B.SL_INTERP_NEAREST), size(B.SL_INTERP_BICUBIC)
+    assert bil > 0 and near == bil
+    slot_cap_min = 64 * 64                   # every pixel may map
+    assert cub - bil >= 8 * 8 * 24 * 4 * slot_cap_min   # 8 members, 24 more entries of 8 bytes per subpixel
+    assert size(3) == 0
+    assert b"interp" in L.sl_last_error()

@@ -364,18 +364,20 @@ def test_psf_general_hint_changes_no_result(sl):
     assert np.all(np.abs(c["chi2"] - d["chi2"]) <= 2e-5 * c["chi2"])
 
 
+@pytest.mark.parametrize("kind", ["nearest", "bicubic"])
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
-def test_c2_nearest_neighbour_vs_oracle(sl, dtype):
-    """Nearest-neighbour source interpolation (Sec. 2.1) at the c2 size against
-    the oracle (tests/golden/c2_nearest.npz, 6 lambdas, FP64 CG to 1e-10):
-    FP32 chi^2 within 1e-5, ||H s||^2 within 1e-3 from k* - 2, the corner
-    solution within 1e-4; FP64 1e-9, 1e-7, 1e-7."""
-    g = np.load(os.path.join(GOLD, "c2_nearest.npz"))
+def test_c2_interp_vs_oracle(sl, dtype, kind):
+    """Nearest-neighbour and bicubic source interpolation (Sec. 2.1) at the c2
+    size against the oracle (tests/golden/c2_<kind>.npz, 6 lambdas, FP64 CG
+    to 1e-10): FP32 chi^2 within 1e-5, ||H s||^2 within 1e-3 from k* - 2, the
+    corner solution within 1e-4; FP64 1e-9, 1e-7, 1e-7."""
+    g = np.load(os.path.join(GOLD, f"c2_{kind}.npz"))
     w = synthgen.C2
     z = np.load(os.path.join(HERE, "data", "c2.npz"))
+    print(f"c2 interp {kind} {dtype}", flush=True)
     solver = sl.Solver(torch.tensor(z["d"], device=DEV), float(z["sigma"]), torch.tensor(z["psf"], device=DEV),
                        sl.Grid(w.nx, w.ny, w.pix, w.nsub_model), w.half_width, reg=w.reg, dtype=dtype,
-                       interp="nearest")
+                       interp=kind)
     f64 = dtype == torch.float64
     lams = [float(x) for x in g["lambdas"]]
     out = _np(solver.solve_semilinear(torch.tensor(np.atleast_2d(z["lens"]), device=DEV),
