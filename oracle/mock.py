@@ -65,7 +65,11 @@ def clean_image(lens, blobs, nx, ny, pix, nsub_data, psf):
 
 def mock_data(w, lens, blobs, noise_unit):
     """Noisy mock image for workload ``w``; returns (d, sigma, clean, psf)."""
-    psf = gaussian_psf(w.k_psf, w.fwhm_px)
+    if getattr(w, "psf_kind", "gauss") == "sinc-moffat":
+        import synthgen
+        psf = synthgen.sinc_moffat_psf(w.k_psf, w.fwhm_px)
+    else:
+        psf = gaussian_psf(w.k_psf, w.fwhm_px)
     clean = clean_image(lens, blobs, w.nx, w.ny, w.pix, w.nsub_data, psf)
     sigma = clean.max() / w.snr
     d = clean + sigma * noise_unit

@@ -162,6 +162,30 @@ def apply_BT(psf, img):
     return out
 
 
+def apply_B_fft(psf, img):
+    """apply_B computed in Fourier space (Sec. 2.2: the convolution with the
+    PSF is done there): the full linear convolution of the image with the PSF
+    from the product of their discrete Fourier transforms on a frame of
+    (ny + K - 1) x (nx + K - 1), large enough that nothing wraps, cropped to
+    the image: (B x)[r][c] = full[r + cK][c + cK]."""
+    P = np.asarray(psf, dtype=np.float64)
+    x = np.asarray(img, dtype=np.float64)
+    K = P.shape[0]
+    ck = (K - 1) // 2
+    ny, nx = x.shape
+    shape = (ny + K - 1, nx + K - 1)
+    full = np.fft.irfft2(np.fft.rfft2(x, shape) * np.fft.rfft2(P, shape), shape)
+    return full[ck:ck + ny, ck:ck + nx]
+
+
+def apply_BT_fft(psf, img):
+    """apply_BT in Fourier space: the correlation with P is the convolution
+    with P turned by 180 degrees, (B^T z)[r][c] = sum P[K-1-a][K-1-b]
+    z[r-a+cK][c-b+cK]."""
+    P = np.asarray(psf, dtype=np.float64)
+    return apply_B_fft(P[::-1, ::-1], img)
+
+
 def dense_B(psf, nx: int, ny: int):
     """Explicit (J, J) matrix of B, column by column from unit images."""
     J = nx * ny

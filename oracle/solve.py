@@ -45,6 +45,7 @@ class Problem:
     half_width: float
     reg: str               # "identity" | "curvature"
     interp: str = "bilinear"   # "bilinear" | "nearest" | "bicubic" (Sec. 2.1)
+    blur: str = "direct"       # "direct" (the sums of the definition) | "fft" (Sec. 2.2, same operator)
 
     def __post_init__(self):
         bx, by = _lens.trace_image(self.lens, self.nx, self.ny, self.pix, self.nsub)
@@ -61,11 +62,17 @@ class Problem:
     def LT(self, img):
         return _ops.apply_LT(self.table, img, self.I, self.nsub)
 
+    def B(self, img):
+        return _ops.apply_B_fft(self.psf, img) if self.blur == "fft" else _ops.apply_B(self.psf, img)
+
+    def BT(self, img):
+        return _ops.apply_BT_fft(self.psf, img) if self.blur == "fft" else _ops.apply_BT(self.psf, img)
+
     def F(self, s):
-        return _ops.apply_B(self.psf, self.L(s))
+        return self.B(self.L(s))
 
     def FT(self, img):
-        return self.LT(_ops.apply_BT(self.psf, img))
+        return self.LT(self.BT(np.asarray(img, dtype=np.float64).reshape(self.ny, self.nx)))
 
     def normal(self, s, lam):
         return self.FT(self.F(s)) + lam * _ops.apply_HtH(s, self.ns, self.reg)

@@ -21,6 +21,10 @@ per pixel, I = n_s^2 source nodes, K x K PSF, lambda grid of size N_lambda):
   4 px, noise sigma = peak/100, 24 lambdas, population 1024.
 * ``c5`` -- surrogate training / screening workload on the c2 image with a
   fixed 64x64 grid.
+* ``large`` -- the shape of the paper's large-scale test: 640x640 image of
+  0.008", 512x512 nodes spanning +-1.6", 65x65 sinc-Moffat PSF of FWHM 6 px,
+  twelve Sersic blobs (mock subpixels 4x4), noise sigma = peak/100, H = I,
+  40 CGLS iterations (implicit regularisation).
 """
 from __future__ import annotations
 
@@ -55,6 +59,7 @@ class Workload:
     tol: float         # CG relative-residual tolerance
     source_kind: str   # "gauss" or "sersic"
     n_blobs: int
+    psf_kind: str = "gauss"   # "gauss" or "sinc-moffat" (sinc_moffat_psf at fwhm_px)
 
 
 def log_grid(lo: float, hi: float, n: int) -> tuple:
@@ -73,7 +78,14 @@ C3 = dataclasses.replace(C2, name="c3", seed=3)
 C4 = Workload("c4", 4, 200, 200, 0.05, 2, 10, 100, 1.0, 21, 4.0, 100.0, "curvature",
               log_grid(1e-4, 1e2, 24), 1e-7, "sersic", 3)
 C5 = dataclasses.replace(C2, name="c5", seed=5)
-WORKLOADS = {w.name: w for w in (C1, C2, C3, C4, C5)}
+# The shape of the paper's large-scale test (Sec. 4, the M51 figure): a 640 x 640
+# image, a 512 x 512 source grid, a 65 x 65 PSF with low-level structure, 40
+# CGLS iterations of the implicit regularisation.  The galaxy image is not
+# available; twelve Sersic blobs stand in for it.
+LARGE = Workload("large", 6, 640, 640, 0.008, 2, 4, 512, 1.6, 65, 6.0, 100.0, "identity", (), 0.0,
+                 "sersic", 12, psf_kind="sinc-moffat")
+LARGE_ITERS = 40
+WORKLOADS = {w.name: w for w in (C1, C2, C3, C4, C5, LARGE)}
 
 # c2's lens: theta_E 1.0", q 0.7, PA 30 deg, gamma 0.05 at 60 deg; the centre
 # offset (<= 0.05") is drawn from the seed.

@@ -1,7 +1,7 @@
 """Write the seeded mock images the GPU tests and the benchmark load.
 
 Calls only the oracle's mock-data synthesis and the seeded draws; run from
-the repository root:  python tests/data/make_inputs.py
+the repository root:  python tests/data/make_inputs.py [name ...]
 Each workload file holds d (ny, nx), sigma, psf (K, K) and the true lens;
 MANIFEST.json records their SHA-256.
 """
@@ -19,18 +19,25 @@ import synthgen  # noqa: E402
 from oracle import mock  # noqa: E402
 
 
-def main():
+def main(names=("c1", "c2", "c4", "large")):
+    mpath = os.path.join(HERE, "MANIFEST.json")
     manifest = {}
-    for name in ("c1", "c2", "c4"):
+    if os.path.exists(mpath):
+        with open(mpath) as f:
+            manifest = json.load(f)
+    for name in names:
         w = synthgen.WORKLOADS[name]
         D = mock.workload_data(w)
         path = os.path.join(HERE, f"{name}.npz")
-        np.savez(path, d=D["d"], sigma=np.float64(D["sigma"]), psf=D["psf"], lens=D["lens"])
+        # the large image is stored rounded to FP32 (half the bytes); both the
+        # oracle and the GPU read these stored values
+        d = D["d"].astype(np.float32) if name == "large" else D["d"]
+        np.savez(path, d=d, sigma=np.float64(D["sigma"]), psf=D["psf"], lens=D["lens"])
         with open(path, "rb") as f:
             manifest[f"{name}.npz"] = hashlib.sha256(f.read()).hexdigest()
-    with open(os.path.join(HERE, "MANIFEST.json"), "w") as f:
+    with open(mpath, "w") as f:
         json.dump(manifest, f, indent=1, sort_keys=True)
 
 
 if __name__ == "__main__":
-    main()
+    main(tuple(sys.argv[1:]) or ("c1", "c2", "c4", "large"))

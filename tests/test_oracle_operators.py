@@ -3,6 +3,7 @@ import numpy as np
 import pytest
 
 from oracle import lens, mock
+import synthgen
 from oracle import operators as ops
 
 
@@ -223,3 +224,38 @@ def test_bicubic_weights_and_quadratic_reproduction():
     y = np.random.default_rng(3).standard_normal(nx * ny)
     Ls = ops.apply_L(tab, s, nsub)
     assert abs(Ls @ y - s @ ops.apply_LT(tab, y, ns * ns, nsub)) <= 1e-12 * np.abs(Ls).sum()
+
+
+@pytest.mark.parametrize("shape,K", [((7, 9), 3), ((11, 13), 5), ((40, 33), 15), ((24, 20), 65), ((66, 70), 65)])
+def test_fourier_blur_equals_the_direct_sums(shape, K):
+    """B and B^T through the Fourier transform (Sec. 2.2) equal the direct sums
+    of the definition, also when the PSF is wider than the image, and stay
+    adjoint."""
+    rng = np.random.default_rng(K + shape[0])
+    P = rng.uniform(0, 1, (K, K))
+    P /= P.sum()
+    x = rng.standard_normal(shape)
+    z = rng.standard_normal(shape)
+    bx = ops.apply_B(P, x)
+    btz = ops.apply_BT(P, z)
+    scale = np.abs(x).max()
+    np.testing.assert_allclose(ops.apply_B_fft(P, x), bx, rtol=0, atol=1e-13 * scale)
+    np.testing.assert_allclose(ops.apply_BT_fft(P, z), btz, rtol=0, atol=1e-13 * np.abs(z).max())
+    lhs = (ops.apply_B_fft(P, x) * z).sum()
+    rhs = (x * ops.apply_BT_fft(P, z)).sum()
+    assert abs(lhs - rhs) <= 1e-12 * (abs(lhs) + 1)
+
+
+def test_problem_fft_blur_matches_direct_problem():
+    """The oracle problem with blur="fft" gives the operator of the direct one."""
+    from oracle import solve
+    w = synthgen.C1
+    rng = np.random.default_rng(3)
+    d = rng.standard_normal((w.ny, w.nx))
+    psf = mock.gaussian_psf(9, 2.5)
+    lens = np.array([0.8, 0.8, 0.3, 0.02, 0.1, 0.01, -0.02])
+    a = solve.Problem(lens, d, 1.0, psf, w.nx, w.ny, w.pix, 2, 16, 0.5, "identity")
+    b = solve.Problem(lens, d, 1.0, psf, w.nx, w.ny, w.pix, 2, 16, 0.5, "identity", blur="fft")
+    s = rng.standard_normal(a.I)
+    np.testing.assert_allclose(b.F(s), a.F(s), rtol=0, atol=1e-12 * np.abs(a.F(s)).max())
+    np.testing.assert_allclose(b.FT(d), a.FT(d), rtol=0, atol=1e-12 * np.abs(a.FT(d)).max())
