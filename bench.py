@@ -92,6 +92,9 @@ def parse():
     ap.add_argument("--search", action="store_true",
                     help="instead of the throughput line: plain vs surrogate-screened GA on the c5 settings")
     ap.add_argument("--search-seeds", type=int, default=3)
+    ap.add_argument("--large", action="store_true",
+                    help="instead of the throughput line: the large-scale shape (640x640 image, 512x512 source, "
+                         "65x65 PSF, 40 CGLS iterations, blur in Fourier space)")
     ap.add_argument("--ga-loop", action="store_true",
                     help="c4's GA generation loop: population 1024, 50 generations, every offspring fully solved")
     ap.add_argument("--gens", type=int, default=30)
@@ -219,6 +222,8 @@ def main():
         return search_main(args, torch, sl, synthgen)
     if args.ga_loop:
         return ga_loop_main(args, torch, sl, synthgen)
+    if args.large:
+        return large_main(args, torch, sl, synthgen)
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -337,6 +342,7 @@ def main():
     mc = mc_dof_step(sl, torch, solver, lens_d, ns_d, w, max_ns, M, args.steps)
     imp = implicit_step(torch, solver, lens_d, ns_d, max_ns, M, args.steps)
     ref = refine_step(torch, solver, z, w, args.steps)
+    big = large_step(torch, sl, synthgen, dev, args.steps)
     # plain: the same library, one member per call
     plain_value = None
     kpo = None
@@ -367,6 +373,7 @@ def main():
         "mc_dof": mc,
         "implicit": imp,
         "refine": ref,
+        "large_scale": big,
         "roofline": roof,
     }
     if not args.no_cpu_baseline and args.workload == "c3" and not f64 and args.psf == "gauss":
@@ -374,6 +381,148 @@ def main():
         gpu = (out["chi2"].cpu().numpy(), out["reg"].cpu().numpy(), out["k_star"].cpu().numpy(),
                out["s_corner"].cpu().numpy(), out["s_off"].cpu().numpy())
         rec["cpu_baseline"] = cpu_baseline(w, z, pop, grids, args.cpu_members, gpu)
+    print(json.dumps(rec), flush=True)
+
+
+def large_bytes_per_iteration(w, entries, elem=4):
+    """Algorithmic HBM bytes of one CGLS iteration of the large solve (sl_solve_large).
+
+    Per iteration: the subpixel table read by the gather L p (cell int32 and
+    two fractions per subpixel: (4 + 2 elem) J n^2); two blurs, each writing,
+    reading, writing and reading the half spectrum of the ny image rows
+    (4 ny Nh 2 elem) and reading the PSF spectrum (Nh Ny 2 elem); the image
+    vectors q (written), e (read, written), q (read again) and w (written):
+    5 J elem; L^T over the node-major table (entries x (4 + elem)) and the row
+    starts (4 I), writing g (elem I); the update reading s, p, g and writing s,
+    p and the kept iterate (6 elem I).
+    """
+    J, I, n2 = w.nx * w.ny, w.ns * w.ns, w.nsub_model ** 2
+    ck = (w.k_psf - 1) // 2
+    Nx = 4
+    while Nx < w.nx + ck:
+        Nx *= 2
+    Ny = 4
+    while Ny < w.ny + ck:
+        Ny *= 2
+    Nh = Nx // 2 + 1
+    blur = 4 * w.ny * Nh * 2 * elem + Nh * Ny * 2 * elem
+    return ((4 + 2 * elem) * J * n2 + 2 * blur + 5 * J * elem + entries * (4 + elem) + 4 * I + elem * I
+            + 6 * elem * I)
+
+
+def _large_setup(torch, sl, synthgen, dev):
+    w = synthgen.LARGE
+    z = np.load(os.path.join(ROOT, "tests", "data", "large.npz"))
+    solver = sl.Solver(torch.tensor(z["d"].astype(np.float64), device=dev), float(z["sigma"]),
+                       torch.tensor(z["psf"], device=dev), sl.Grid(w.nx, w.ny, w.pix, w.nsub_model), w.half_width,
+                       reg=w.reg, dtype=torch.float32)
+    lens = torch.tensor(z["lens"], device=dev)
+    return w, z, solver, lens
+
+
+def _time_large(torch, solver, lens, ns, n_iter, reps):
+    """ms per call of sl_solve_large, HIP events on the stream it runs on (torch's current stream)."""
+    out = solver.solve_large(lens, ns, n_iter)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        solver.solve_large(lens, ns, n_iter, out=out)
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps, out
+
+
+def large_step(torch, sl, synthgen, dev, steps):
+    """GPU-only summary of the large-scale shape for the throughput line: ms per solve (trace, table, 40 CGLS
+    iterations, corner) and per CGLS iteration (the 40-iteration call minus the 1-iteration call, over 39)."""
+    print("[bench] large-scale shape (640^2 image, 512^2 source, 65^2 PSF)", file=sys.stderr, flush=True)
+    w, z, solver, lens = _large_setup(torch, sl, synthgen, dev)
+    reps = max(3, steps)
+    ms40, out = _time_large(torch, solver, lens, w.ns, synthgen.LARGE_ITERS, reps)
+    ms1, _ = _time_large(torch, solver, lens, w.ns, 1, reps)
+    it_ms = (ms40 - ms1) / (synthgen.LARGE_ITERS - 1)
+    k = int(out["k_star"].cpu().numpy()[0])
+    chi2 = out["chi2"].cpu().numpy()[0]
+    return {"ms_per_solve": round(ms40, 3), "ms_per_cgls_iteration": round(it_ms, 4),
+            "setup_ms": round(ms1 - it_ms, 3), "corner_iterate": k + 1, "chi2_corner": float(chi2[k]),
+            "chi2_r_corner": float(chi2[k] / (w.nx * w.ny))}
+
+
+def large_main(args, torch, sl, synthgen):
+    """The large-scale shape as its own JSON line: solves per second, the roofline of one CGLS iteration, and
+    the oracle (FP64, blur in Fourier space) timed on the host for the same solve."""
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    w, z, solver, lens = _large_setup(torch, sl, synthgen, dev)
+    n_iter = synthgen.LARGE_ITERS
+    print(f"[bench] large: warmup {args.warmup}, timing {args.steps} solve(s)", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        solver.solve_large(lens, w.ns, n_iter)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = solver.solve_large(lens, w.ns, n_iter)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms40, out = _time_large(torch, solver, lens, w.ns, n_iter, max(3, args.steps))
+    ms1, _ = _time_large(torch, solver, lens, w.ns, 1, max(3, args.steps))
+    it_ms = (ms40 - ms1) / (n_iter - 1)
+    # the same solve replayed from a captured HIP graph (launch overheads out of the loop)
+    gout = solver.alloc_result(w.ns * w.ns, 1, n_iter)
+    solver.solve_large(lens, w.ns, n_iter, out=gout)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        solver.solve_large(lens, w.ns, n_iter, out=gout)
+    graph.replay()
+    torch.cuda.synchronize()
+    ga, gb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ga.record()
+    for _ in range(max(3, args.steps)):
+        graph.replay()
+    gb.record()
+    torch.cuda.synchronize()
+    graph_ms = ga.elapsed_time(gb) / max(3, args.steps)
+    graph_same = bool(torch.equal(gout["chi2"], out["chi2"]) and torch.equal(gout["s_corner"], out["s_corner"]))
+    del graph
+    # L^T table entries: the four bilinear taps of every subpixel on the grid (the library's own trace)
+    uv = sl.lens_trace(lens.reshape(1, 7), sl.Grid(w.nx, w.ny, w.pix, w.nsub_model), [w.ns], w.half_width)
+    entries = 4 * int(torch.isfinite(uv.reshape(-1, 2)[:, 0]).sum().item())
+    del uv
+    res = {k: v.cpu().numpy() for k, v in out.items()}
+    rec_cpu = None
+    if not args.no_cpu_baseline:
+        print("[bench] large: oracle on the host", file=sys.stderr, flush=True)
+        from oracle import implicit, solve
+        c0 = time.perf_counter()
+        pb = solve.Problem(z["lens"], z["d"].astype(np.float64), float(z["sigma"]), z["psf"], w.nx, w.ny, w.pix,
+                           w.nsub_model, w.ns, w.half_width, w.reg, blur="fft")
+        ref = implicit.cgls_iterates(pb, n_iter)
+        cpu_s = time.perf_counter() - c0
+        k = int(res["k_star"][0])
+        rec_cpu = {"value": round(1.0 / cpu_s, 4), "unit": "solves/s", "cores": 1, "kind": "oracle",
+                   "sample": f"one full solve ({n_iter} CGLS iterations, FP64, numpy FFT blur) on one host core",
+                   "chi2_rel_diff_at_gpu_corner": float(abs(res["chi2"][0][k] - ref["chi2"][k]) / ref["chi2"][k])}
+    abytes = large_bytes_per_iteration(w, entries)
+    gbs = abytes / (it_ms * 1e-3) / 1e9
+    rec = {"metric": "large-scale CGLS solves/s (640² image, 512² source, 65² PSF, 40 iterations)",
+           "value": round(args.steps / dt, 3), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(1e3 * dt / args.steps, 3), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "large-scale shape of Sec. 4: 640x640 image at 0.008\", 2x2 subpixels, "
+                                  "512x512 nodes over +-1.6\", 65x65 sinc-Moffat PSF, identity H, 40 CGLS "
+                                  "iterations, blur in Fourier space (1024x1024 frame)"},
+           "ms_per_solve_events": round(ms40, 3), "ms_per_cgls_iteration": round(it_ms, 4),
+           "graph_ms_per_solve": round(graph_ms, 3), "graph_matches_eager": graph_same,
+           "setup_ms": round(ms1 - it_ms, 3),
+           "corner_iterate": int(res["k_star"][0]) + 1,
+           "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
+                        "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": None,
+                        "kernel": "one CGLS iteration: 8 kernels (row FFT + L p, column FFT x PSF, inverse rows, "
+                                  "row FFT + residual, column FFT x conj PSF, inverse rows, L^T, update)",
+                        "algorithmic_bytes": abytes, "table_entries": entries},
+           "cpu_baseline": rec_cpu}
     print(json.dumps(rec), flush=True)
 
 

@@ -317,6 +317,44 @@ int sl_chi2_sources(const sl_problem* pb, const double* lens, int ns, const doub
                     void* stream);
 
 /*
+ * Blur in Fourier space (Sec. 2.2: the paper convolves with the PSF there),
+ * for wide PSFs: the operator of sl_apply_B (transpose = 0) or sl_apply_BT
+ * (transpose = 1) on one ny x nx image, computed with 2-D FFTs on an
+ * Ny x Nx frame of powers of two with Ny >= ny + (k-1)/2 and
+ * Nx >= nx + (k-1)/2, on which the circular convolution equals the
+ * zero-padded one.  dtype SL_F32 (in/out float, FP32 transforms) or SL_F64.
+ * psf: device double[k*k], k odd <= 129; nx, ny <= 2048 and Nx, Ny <= 4096.
+ * in/out: device, distinct.  workspace: device, 256-byte aligned, at least
+ * sl_fft_blur_workspace_size(dtype, nx, ny, k) bytes, contents need not be
+ * initialised (the query returns 0 for invalid arguments).
+ */
+size_t sl_fft_blur_workspace_size(int dtype, int nx, int ny, int k);
+int sl_fft_blur(int dtype, int transpose, int nx, int ny, const double* psf, int k, const void* in,
+                void* out, void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * One large problem with implicit regularisation, the paper's large-scale
+ * test (Sec. 4: a 640 x 640 image, a 512 x 512 source grid, a 65 x 65 PSF,
+ * 40 CGLS iterations): one lens (device double[7]), images up to
+ * 2048 x 2048, ns up to 1024, PSF side k odd up to 129 (pb->k may exceed
+ * SL_MAX_PSF here), B and B^T applied in Fourier space as sl_fft_blur, L^T as
+ * a gather over a node-major table built and sorted on the device (each
+ * node's terms summed in ascending pixel order: bitwise reproducible).  The
+ * iteration, its outputs and statuses are those of sl_solve_implicit for
+ * one member: n_iter CGLS iterations (1..SL_MAX_LAMBDA) from s = 0, after
+ * iteration k chi2[k] = ||d - A s_k||^2 / sigma^2 from the carried residual
+ * and reg[k] = sum_i s_k,i^2, k_star the L-curve corner over the iterates,
+ * s_corner (double[ns*ns]) that iterate, s_off = {0, ns*ns}; chi2, reg,
+ * iters, status hold n_iter entries.  pb->reg and pb->psf_general are not
+ * used; pb->interp selects L as in the batched solve.  No Monte Carlo
+ * degrees of freedom (out->dof is not written).  workspace: device,
+ * 256-byte aligned, at least sl_solve_large_workspace_size(pb, ns, n_iter)
+ * bytes (0 for invalid arguments); calls sharing it must not overlap.
+ */
+size_t sl_solve_large_workspace_size(const sl_problem* pb, int ns, int n_iter);
+int sl_solve_large(const sl_problem* pb, const double* lens, int ns, int n_iter, void* workspace,
+                   size_t workspace_bytes, sl_result* out, void* stream);
+/*
  * Autotuner: a staged search over the solve's settings.  Variants 0..7 are
  * the structural switches (wide_window, lt_csr, blur_direct as the bits of
  * the index) at the default threshold and queue order; variants 8..11 set

@@ -102,6 +102,13 @@ def lib():
         L.sl_chi2_sources_workspace_size.restype = ctypes.c_size_t
         L.sl_chi2_sources.argtypes = [ctypes.POINTER(Problem), vp, ip, vp, ip, vp, ctypes.c_size_t, vp, vp]
         L.sl_plan_destroy.argtypes = [vp]
+        L.sl_fft_blur_workspace_size.argtypes = [ip, ip, ip, ip]
+        L.sl_fft_blur_workspace_size.restype = ctypes.c_size_t
+        L.sl_fft_blur.argtypes = [ip, ip, ip, ip, vp, ip, vp, vp, vp, ctypes.c_size_t, vp]
+        L.sl_solve_large_workspace_size.argtypes = [ctypes.POINTER(Problem), ip, ip]
+        L.sl_solve_large_workspace_size.restype = ctypes.c_size_t
+        L.sl_solve_large.argtypes = [ctypes.POINTER(Problem), vp, ip, ip, vp, ctypes.c_size_t,
+                                     ctypes.POINTER(Result), vp]
         L.sl_solve_member_info.argtypes = [ctypes.POINTER(Problem), ip, ip, ip, vp, vp]
         L.sl_profile_enable.argtypes = [ip]
         L.sl_profile_solve_ms.argtypes = [ctypes.POINTER(ctypes.c_double), i32p]
@@ -115,7 +122,8 @@ def lib():
         for name in ("sl_lens_trace", "sl_apply_L", "sl_apply_LT", "sl_apply_LT_ordered", "sl_apply_B", "sl_apply_BT",
                      "sl_apply_HtH", "sl_solve_semilinear", "sl_solve_implicit", "sl_lcurve_corner", "sl_mlp_forward", "sl_mlp_forward_noalloc",
                      "sl_mlp_train_step", "sl_solve_member_info", "sl_profile_enable", "sl_profile_solve_ms",
-                     "sl_solve_autotune", "sl_plan_create", "sl_plan_launch", "sl_plan_destroy"):
+                     "sl_solve_autotune", "sl_plan_create", "sl_plan_launch", "sl_plan_destroy", "sl_fft_blur",
+                     "sl_solve_large", "sl_chi2_sources"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib

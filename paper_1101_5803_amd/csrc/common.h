@@ -198,8 +198,8 @@ __host__ __device__ inline bool spline_knot_derivs(const double* t, const double
       M[piv] = tmp;
     }
     for (int r = col + 1; r < n; ++r) {
+      if (A[r * n + col] == 0.0) continue;   // the quotient would be 0 (the pivot is not)
       const double f = A[r * n + col] / A[col * n + col];
-      if (f == 0.0) continue;
       for (int c = col; c < n; ++c) A[r * n + c] -= f * A[col * n + c];
       M[r] -= f * M[col];
     }

@@ -1,0 +1,1110 @@
+// Large single-lens solve and the blur in Fourier space (gfx950).
+//
+// The paper's large-scale test (Sec. 4) fits one lens to a 640 x 640 image
+// with a 512 x 512 source grid and a 65 x 65 PSF by 40 CGLS iterations, and
+// the paper convolves with the PSF in Fourier space (Sec. 2.2).  One such
+// problem fills the GPU by itself, so it runs as a short sequence of
+// grid-wide kernels per CGLS iteration rather than as one persistent block
+// per lens:
+//
+//   k_rowfwd   row FFTs of the image (with the gather L p, or with the
+//              residual update e -= alpha q)      one block per pair of rows
+//   k_col      column FFT, product with the PSF spectrum, inverse column FFT
+//                                                 one block per frequency column
+//   k_rowinv   inverse row FFTs (q = B L p with |q|^2, or B^T e)
+//                                                 one block per pair of rows
+//   k_lt       L^T as a gather over a node-major table, with |g|^2
+//                                                 one thread per node
+//   k_update   s += alpha p, p = g + beta p, |s|^2, the iterate kept
+//                                                 one thread per node
+//
+// Images are real, so two rows go through one complex FFT (row r as the real
+// part, row r + 1 as the imaginary part) and only the columns kx = 0..Nx/2
+// of the spectrum are kept.  The frame is Ny x Nx, powers of two with
+// Ny >= ny + ck and Nx >= nx + ck: the circular convolution on that frame
+// then equals the zero-padded one on the image.  The 1/(Nx Ny) of the inverse
+// transform is folded into the PSF spectrum, which is computed once per call
+// by a separable discrete Fourier transform of the K x K PSF in FP64.
+//
+// Reductions are FP64: each block writes its partial sum, and every
+// consumer adds the partials in block order, so each run gives the same
+// bits.  L^T sums each node's terms in ascending (pixel, subpixel, tap)
+// order (the table is sorted once per call).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+
+#include "common.h"
+#include "semilin.h"
+
+namespace sl {
+namespace large {
+
+constexpr int kNT = 256;              // threads of most blocks
+constexpr int kRowNT = 512;           // threads of the row-FFT blocks
+constexpr int kLtNT = 1024;           // threads of the L^T blocks
+constexpr int kLtG = 16;              // lanes per node in L^T
+constexpr int kSortChunk = 1024;      // keys of one node staged in LDS by the sort
+constexpr int kMaxParts = 1024;       // blocks of the node kernels (grid-stride loops)
+constexpr int kMaxImage = 2048;       // image side
+constexpr int kMaxFrame = 4096;       // FFT frame side
+constexpr int kMaxNs = 1024;          // source grid side
+constexpr int kMaxPsf = 129;          // PSF side
+
+template <typename T>
+struct alignas(2 * sizeof(T)) cpx {
+  T x, y;
+};
+
+// One entry of the node-major L^T table: pixel and weight.
+template <typename T>
+struct alignas(8) LtE {
+  int32_t pix;
+  T w;
+};
+
+template <typename T>
+__device__ __forceinline__ cpx<T> cadd(cpx<T> a, cpx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+__device__ __forceinline__ cpx<T> csub(cpx<T> a, cpx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T>
+__device__ __forceinline__ cpx<T> cmul(cpx<T> a, cpx<T> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> cmulc(cpx<T> a, cpx<T> b) {   // a conj(b)
+  return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
+}
+
+static inline int frame_side(int n, int ck) {
+  int f = 4;
+  while (f < n + ck) f *= 2;
+  return f;
+}
+
+// Everything one call works on.  T is the arithmetic of the bulk work.
+template <typename T>
+struct Args {
+  int nx, ny, nsub, n2, ns, I, J, K, ck, interp, taps;
+  int Nx, Ny, Nh;
+  double pix, R, sigma;
+  const double* lens;   // device [7]
+  const double* d;      // device [ny * nx]
+  const double* psf;    // device [K * K]
+  cpx<T>* twx;          // [Nx] exp(-2 pi i m / Nx)
+  cpx<T>* twy;          // [Ny]
+  cpx<double>* twdx;    // the same in FP64 (PSF transform)
+  cpx<double>* twdy;
+  cpx<T>* H;            // [Nh][Ny] PSF spectrum / (Nx Ny)
+  cpx<T>* S;            // [Nh][Ny] spectrum of the image in flight (rows < ny used in the row passes)
+  cpx<double>* T1;      // [K][Nh] first stage of the PSF transform
+  int32_t* cell;        // [J n^2] cell of each subpixel (-1 off the grid)
+  T* fx;                // [J n^2]
+  T* fy;
+  int32_t* cnt;         // [I] entries per node
+  int32_t* tsum;        // [tiles] entries per tile of 1024 nodes, then the tile's start
+  int32_t* rowptr;      // [I + 1]
+  int32_t* cursor;      // [I]
+  int32_t* key;         // [cap] (subpixel, tap) of each entry, in fill order
+  T* wtmp;              // [cap]
+  LtE<T>* lt;           // [cap] pixel and weight (with the 1/n^2 average), sorted within each node
+  T* q;                 // [J] A p
+  T* e;                 // [J] image residual d - A s
+  T* w;                 // [J] B^T e
+  T* s;                 // [I]
+  T* p;
+  T* g;
+  T* s_iter;            // [n_iter][I] every iterate
+  double* part;         // [4][n_iter + 1][max_blocks]: qq, ee, gg, ss partials
+  double* gg;           // [n_iter + 1]: |g|^2 before iteration k
+  double* alpha;        // [n_iter]: step length of iteration k (0 when it did not move)
+  int32_t* done;        // [n_iter + 1]: the iteration stopped before iteration k
+  int32_t* upd;         // [n_iter]: iteration k updated s
+  int32_t* flags;       // [2]: invalid genome (flags[1] unused)
+  int n_iter, max_blocks, nb_row, nb_node, nb_lt;
+};
+
+enum { P_QQ = 0, P_EE = 1, P_GG = 2, P_SS = 3 };
+
+template <typename T>
+__device__ __forceinline__ double* part_of(const Args<T>& a, int which, int it) {
+  return a.part + ((long)which * (a.n_iter + 1) + it) * a.max_blocks;
+}
+
+// Sum of n block partials, the same in every block of the same size: thread
+// t adds p[t], p[t + blockDim], ... in order, then the block sum adds the
+// threads' sums in a fixed order.  Every thread receives the total; all
+// threads must call it (barriers).  The producers keep n at most kMaxParts.
+__device__ __forceinline__ double block_total(const double* p, int n) {
+  __shared__ double red[kLtNT / kWave];
+  double v = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) v += p[i];
+  return block_sum(v, red);
+}
+
+// Block FP64 sum written as this block's partial of reduction `which`, slot
+// `it` (all threads call it: barriers).
+template <typename T>
+__device__ __forceinline__ void put_partial(const Args<T>& a, double v, int which, int it) {
+  __shared__ double red[kLtNT / kWave];
+  v = block_sum(v, red);
+  if (threadIdx.x == 0) part_of(a, which, it)[blockIdx.x] = v;
+}
+
+// ---------------------------------------------------------------- FFT in LDS
+// Complex FFT of length N (a power of two >= 2) of the data in LDS buffer `a`
+// (b: a second buffer of N elements); returns the buffer with the result.
+// Stockham autosort form (Govindaraju et al. 2008): stages of span Ns = 1,
+// R, R R', ...; butterfly j of a stage reads a[j + r N/R] (r < R), turns
+// input r by w^(r (j mod Ns) N/(Ns R)) and writes its radix-R DFT to
+// b[(j - j mod Ns) R + j mod Ns + r Ns].  Radix 4 while 4 divides N/Ns, then
+// one radix-2 stage.  INV: conjugate twiddles and DFT (no 1/N).  All threads
+// of the block take part; one barrier per stage.
+template <typename T, bool INV>
+__device__ cpx<T>* fft_lds(cpx<T>* a, cpx<T>* b, int N, const cpx<T>* __restrict__ tw) {
+  for (int Ns = 1; Ns < N;) {
+    const int R = ((N / Ns) & 3) == 0 ? 4 : 2;
+    const int nb = N / R;
+    const int step = N / (Ns * R);
+    for (int j = threadIdx.x; j < nb; j += blockDim.x) {
+      const int k = j & (Ns - 1);
+      const int o = (j - k) * R + k;
+      if (R == 4) {
+        cpx<T> v0 = a[j], v1 = a[j + nb], v2 = a[j + 2 * nb], v3 = a[j + 3 * nb];
+        if (k) {
+          const cpx<T> w1 = tw[k * step], w2 = tw[2 * k * step], w3 = tw[3 * k * step];
+          if (INV) {
+            v1 = cmulc(v1, w1);
+            v2 = cmulc(v2, w2);
+            v3 = cmulc(v3, w3);
+          } else {
+            v1 = cmul(v1, w1);
+            v2 = cmul(v2, w2);
+            v3 = cmul(v3, w3);
+          }
+        }
+        const cpx<T> t0 = cadd(v0, v2), t1 = csub(v0, v2), t2 = cadd(v1, v3), d = csub(v1, v3);
+        // times -i (forward) or +i (inverse)
+        const cpx<T> t3 = INV ? cpx<T>{-d.y, d.x} : cpx<T>{d.y, -d.x};
+        b[o] = cadd(t0, t2);
+        b[o + Ns] = cadd(t1, t3);
+        b[o + 2 * Ns] = csub(t0, t2);
+        b[o + 3 * Ns] = csub(t1, t3);
+      } else {
+        cpx<T> v0 = a[j], v1 = a[j + nb];
+        if (k) v1 = INV ? cmulc(v1, tw[k * step]) : cmul(v1, tw[k * step]);
+        b[o] = cadd(v0, v1);
+        b[o + Ns] = csub(v0, v1);
+      }
+    }
+    __syncthreads();
+    cpx<T>* t = a;
+    a = b;
+    b = t;
+    Ns *= R;
+  }
+  return a;
+}
+
+// ---------------------------------------------------------------- set-up kernels
+// Twiddle tables exp(-2 pi i m / N) for both frame sides, in FP64 then rounded.
+template <typename T>
+__global__ void __launch_bounds__(kNT) k_twiddles(Args<T> a) {
+  const int i = blockIdx.x * kNT + threadIdx.x;
+  if (i < a.Nx) {
+    double sn, cs;
+    sincospi(-2.0 * i / a.Nx, &sn, &cs);
+    a.twx[i] = {(T)cs, (T)sn};
+    a.twdx[i] = {cs, sn};
+  }
+  if (i < a.Ny) {
+    double sn, cs;
+    sincospi(-2.0 * i / a.Ny, &sn, &cs);
+    a.twy[i] = {(T)cs, (T)sn};
+    a.twdy[i] = {cs, sn};
+  }
+}
+
+// exp(-2 pi i m / N) for an integer m of either sign from the FP64 table of N.
+__device__ __forceinline__ cpx<double> unit_root(const cpx<double>* tab, long m, int N) {
+  long r = m % N;
+  if (r < 0) r += N;
+  return tab[r];
+}
+
+// PSF spectrum, first stage: T1[a][kx] = sum_b P[a][b] exp(-2 pi i kx (b - ck) / Nx).
+template <typename T>
+__global__ void __launch_bounds__(kNT) k_psf_rows(Args<T> a) {
+  const int idx = blockIdx.x * kNT + threadIdx.x;
+  if (idx >= a.K * a.Nh) return;
+  const int r = idx / a.Nh, kx = idx % a.Nh;
+  double re = 0.0, im = 0.0;
+  for (int b = 0; b < a.K; ++b) {
+    const cpx<double> u = unit_root(a.twdx, (long)kx * (b - a.ck), a.Nx);
+    const double v = a.psf[r * a.K + b];
+    re += v * u.x;
+    im += v * u.y;
+  }
+  a.T1[idx] = {re, im};
+}
+
+// Second stage: H[kx][ky] = sum_a T1[a][kx] exp(-2 pi i ky (a - ck) / Ny) / (Nx Ny).
+template <typename T>
+__global__ void __launch_bounds__(kNT) k_psf_cols(Args<T> a) {
+  const long idx = (long)blockIdx.x * kNT + threadIdx.x;
+  if (idx >= (long)a.Nh * a.Ny) return;
+  const int kx = (int)(idx / a.Ny), ky = (int)(idx % a.Ny);
+  double re = 0.0, im = 0.0;
+  for (int r = 0; r < a.K; ++r) {
+    const cpx<double> u = unit_root(a.twdy, (long)ky * (r - a.ck), a.Ny);
+    const cpx<double> t = a.T1[r * a.Nh + kx];
+    re += t.x * u.x - t.y * u.y;
+    im += t.x * u.y + t.y * u.x;
+  }
+  const double sc = 1.0 / ((double)a.Nx * a.Ny);
+  a.H[idx] = {(T)(re * sc), (T)(im * sc)};
+}
+
+// ---------------------------------------------------------------- the lens operator
+// Cubic convolution kernel (Keys, a = -1/2) at distance d >= 0.
+__device__ __forceinline__ double keys(double d) {
+  return d <= 1.0 ? (1.5 * d - 2.5) * d * d + 1.0 : (d < 2.0 ? ((-0.5 * d + 2.5) * d - 4.0) * d + 2.0 : 0.0);
+}
+
+// Tap q of subpixel j: node (or -1) and weight with the 1/n^2 average.
+// Bilinear and nearest neighbour: 4 taps, the corners (q >> 1, q & 1) of the
+// cell (nearest: the fractions are stored rounded to 0 or 1).  Bicubic: 16
+// taps, row offset (q >> 2) - 1 and column offset (q & 3) - 1 from the cell's
+// first node, nodes outside the grid left out.
+template <typename T>
+__device__ __forceinline__ void tap(const Args<T>& a, long j, int q, int& node, double& wt) {
+  const int c = a.cell[j];
+  node = -1;
+  wt = 0.0;
+  if (c < 0) return;
+  const double fx = (double)a.fx[j], fy = (double)a.fy[j];
+  if (a.taps == 4) {
+    const int dr = q >> 1, dc = q & 1;
+    node = c + dr * a.ns + dc;
+    wt = (dr ? fy : 1.0 - fy) * (dc ? fx : 1.0 - fx) / a.n2;
+    return;
+  }
+  const int jr = (q >> 2) - 1, ic = (q & 3) - 1;
+  const int r = c / a.ns + jr, col = c % a.ns + ic;
+  if (r < 0 || r >= a.ns || col < 0 || col >= a.ns) return;
+  node = r * a.ns + col;
+  wt = keys(fabs(fy - jr)) * keys(fabs(fx - ic)) / a.n2;
+}
+
+// Ray trace of every subpixel (Eq. 1, Eqs. 10-11, Sec. 2.2) into the cell
+// table, and the number of table entries of each node.
+template <typename T>
+__global__ void __launch_bounds__(kNT) k_trace(Args<T> a) {
+  const long j = (long)blockIdx.x * kNT + threadIdx.x;
+  if (j >= (long)a.J * a.n2) return;
+  double g[7];
+  for (int i = 0; i < 7; ++i) g[i] = a.lens[i];
+  const bool valid = lens_valid(g);
+  if (j == 0 && !valid) a.flags[0] = 1;
+  const int pixel = (int)(j / a.n2), k = (int)(j % a.n2);
+  const int r = pixel / a.nx, c = pixel % a.nx;
+  int cell = -1;
+  double fx = 0.0, fy = 0.0;
+  if (valid) {
+    const Lens L = make_lens(g);
+    double x, y, bx, by;
+    subpixel_xy(r, c, k / a.nsub, k % a.nsub, a.nx, a.ny, a.pix, a.nsub, x, y);
+    lens_map(L, x, y, bx, by);
+    const double h = 2.0 * a.R / (a.ns - 1);
+    if (!grid_cell((bx + a.R) / h, (by + a.R) / h, a.ns, cell, fx, fy)) {
+      cell = -1;
+      fx = fy = 0.0;
+    } else if (a.interp == SL_INTERP_NEAREST) {
+      fx = fx >= 0.5 ? 1.0 : 0.0;
+      fy = fy >= 0.5 ? 1.0 : 0.0;
+    }
+  }
+  a.cell[j] = cell;
+  a.fx[j] = (T)fx;
+  a.fy[j] = (T)fy;
+  if (cell < 0) return;
+  for (int q = 0; q < a.taps; ++q) {
+    int node;
+    double wt;
+    tap(a, j, q, node, wt);
+    if (node >= 0) atomicAdd(&a.cnt[node], 1);
+  }
+}
+
+// Exclusive scan of the entry counts into row starts, in three passes over
+// tiles of 1024 nodes: the tiles' totals, their scan (one block), then each
+// tile's own scan plus its start.  Integer sums: the order does not matter.
+constexpr int kTile = 1024;
+
+// Block-wide exclusive scan of one int per thread (blockDim.x = kNT); returns
+// this thread's prefix and sets *total.
+__device__ __forceinline__ int block_scan_excl(int v, int* total) {
+  __shared__ int ws[kNT / kWave];
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  int incl = v;
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int u = __shfl_up(incl, o, kWave);
+    if (lane >= o) incl += u;
+  }
+  if (lane == kWave - 1) ws[wid] = incl;
+  __syncthreads();
+  int before = 0, all = 0;
+  for (int i = 0; i < kNT / kWave; ++i) {
+    if (i < wid) before += ws[i];
+    all += ws[i];
+  }
+  __syncthreads();
+  *total = all;
+  return before + incl - v;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kNT) k_tile_sums(Args<T> a) {
+  const int i0 = blockIdx.x * kTile;
+  int v = 0;
+  for (int k = 0; k < kTile / kNT; ++k) {
+    const int i = i0 + threadIdx.x * (kTile / kNT) + k;
+    if (i < a.I) v += a.cnt[i];
+  }
+  int total;
+  (void)block_scan_excl(v, &total);
+  if (threadIdx.x == 0) a.tsum[blockIdx.x] = total;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kNT) k_tile_scan(Args<T> a) {
+  const int tiles = (a.I + kTile - 1) / kTile;   // <= kNT * 4 for I <= 2^20
+  int v[4];
+  int loc = 0;
+  for (int k = 0; k < 4; ++k) {
+    const int t = threadIdx.x * 4 + k;
+    v[k] = t < tiles ? a.tsum[t] : 0;
+    loc += v[k];
+  }
+  int total;
+  int run = block_scan_excl(loc, &total);
+  for (int k = 0; k < 4; ++k) {
+    const int t = threadIdx.x * 4 + k;
+    if (t < tiles) a.tsum[t] = run;
+    run += v[k];
+  }
+  if (threadIdx.x == 0) a.rowptr[a.I] = total;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kNT) k_tile_write(Args<T> a) {
+  const int i0 = blockIdx.x * kTile + threadIdx.x * (kTile / kNT);
+  int v[kTile / kNT];
+  int loc = 0;
+  for (int k = 0; k < kTile / kNT; ++k) {
+    v[k] = i0 + k < a.I ? a.cnt[i0 + k] : 0;
+    loc += v[k];
+  }
+  int total;
+  int run = a.tsum[blockIdx.x] + block_scan_excl(loc, &total);
+  for (int k = 0; k < kTile / kNT; ++k) {
+    if (i0 + k < a.I) {
+      a.rowptr[i0 + k] = run;
+      a.cursor[i0 + k] = run;
+    }
+    run += v[k];
+  }
+}
+
+// Table entries in arrival order (one thread per subpixel).
+template <typename T>
+__global__ void __launch_bounds__(kNT) k_fill(Args<T> a) {
+  const long j = (long)blockIdx.x * kNT + threadIdx.x;
+  if (j >= (long)a.J * a.n2 || a.cell[j] < 0) return;
+  for (int q = 0; q < a.taps; ++q) {
+    int node;
+    double wt;
+    tap(a, j, q, node, wt);
+    if (node < 0) continue;
+    const int pos = atomicAdd(&a.cursor[node], 1);
+    a.key[pos] = (int32_t)(j * a.taps + q);
+    a.wtmp[pos] = (T)wt;
+  }
+}
+
+// Each node's entries placed in ascending key order (one wave per node): the
+// rank of an entry is the number of the node's keys below it (keys are
+// distinct).  Rows of up to kSortChunk entries are staged in the wave's LDS
+// slice; each lane holds its (at most 16) keys in registers and every staged
+// key is read once and compared with all of them.  Longer rows compare from
+// global memory one entry at a time.
+template <typename T>
+__global__ void __launch_bounds__(kNT) k_sort(Args<T> a) {
+  constexpr int kPer = kSortChunk / kWave;
+  __shared__ int32_t stage[kNT / kWave][kSortChunk];
+  const int wv = threadIdx.x / kWave;
+  const int node = blockIdx.x * (kNT / kWave) + wv;
+  const int lane = threadIdx.x & (kWave - 1);
+  if (node >= a.I) return;
+  const int b = a.rowptr[node], n = a.rowptr[node + 1] - b;
+  const int32_t* keys = a.key + b;
+  if (n <= kSortChunk) {
+    int32_t* st = stage[wv];
+    int mine[kPer], rank[kPer];
+#pragma unroll
+    for (int t = 0; t < kPer; ++t) {
+      const int e = lane + t * kWave;
+      mine[t] = e < n ? keys[e] : 0x7fffffff;
+      rank[t] = 0;
+      if (e < n) st[e] = mine[t];
+    }
+    // the wave's own LDS writes precede its reads
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int f = 0; f < n; ++f) {
+      const int kf = st[f];
+#pragma unroll
+      for (int t = 0; t < kPer; ++t) rank[t] += kf < mine[t];
+    }
+#pragma unroll
+    for (int t = 0; t < kPer; ++t) {
+      const int e = lane + t * kWave;
+      if (e < n) a.lt[b + rank[t]] = {(mine[t] / a.taps) / a.n2, a.wtmp[b + e]};
+    }
+    return;
+  }
+  for (int e = lane; e < n; e += kWave) {
+    const int ke = keys[e];
+    int rank = 0;
+    for (int f = 0; f < n; ++f) rank += keys[f] < ke;
+    a.lt[b + rank] = {(ke / a.taps) / a.n2, a.wtmp[b + e]};
+  }
+}
+
+// (L x)(pixel) in T: the subpixels' interpolated values over n^2.
+template <typename T>
+__device__ __forceinline__ T gather_L(const Args<T>& a, const T* __restrict__ x, int pixel) {
+  T acc = 0;
+  const long j0 = (long)pixel * a.n2;
+  if (a.taps == 4) {
+    for (int k = 0; k < a.n2; ++k) {
+      const int c = a.cell[j0 + k];
+      if (c < 0) continue;
+      const T fx = a.fx[j0 + k], fy = a.fy[j0 + k];
+      acc += (1 - fy) * ((1 - fx) * x[c] + fx * x[c + 1]) + fy * ((1 - fx) * x[c + a.ns] + fx * x[c + a.ns + 1]);
+    }
+  } else {
+    for (int k = 0; k < a.n2; ++k) {
+      const int c = a.cell[j0 + k];
+      if (c < 0) continue;
+      const double fx = (double)a.fx[j0 + k], fy = (double)a.fy[j0 + k];
+      const int r = c / a.ns, col = c % a.ns;
+      for (int jr = -1; jr <= 2; ++jr) {
+        const int rr = r + jr;
+        if (rr < 0 || rr >= a.ns) continue;
+        T row = 0;
+        for (int ic = -1; ic <= 2; ++ic) {
+          const int cc = col + ic;
+          if (cc >= 0 && cc < a.ns) row += (T)keys(fabs(fx - ic)) * x[rr * a.ns + cc];
+        }
+        acc += (T)keys(fabs(fy - jr)) * row;
+      }
+    }
+  }
+  return acc / (T)a.n2;
+}
+
+// ---------------------------------------------------------------- CGLS scalars
+// alpha of iteration it = |g|^2 / |A p|^2, or 0 once the iteration has stopped.
+// (every thread of the block calls it: barriers)
+template <typename T>
+__device__ __forceinline__ double alpha_of(const Args<T>& a, int it) {
+  const double qq = block_total(part_of(a, P_QQ, it), a.nb_row);
+  if (a.done[it]) return 0.0;
+  return qq > 0.0 ? a.gg[it] / qq : 0.0;
+}
+
+// ---------------------------------------------------------------- FFT passes
+enum { ROW_LP = 0, ROW_E = 1, ROW_D = 2, ROW_IMG = 3 };
+
+// Forward row FFTs of rows r0 = 2 blockIdx.x and r0 + 1 of an image, packed
+// as one complex row, split into the two half spectra and stored at
+// S[kx * Ny + r].  The image row is L p (ROW_LP), the updated residual
+// e -= alpha q written back with its |e|^2 partial (ROW_E), the data d
+// copied into e (ROW_D), or a given image (ROW_IMG, `src`).
+template <typename T, int MODE>
+__global__ void __launch_bounds__(kRowNT) k_rowfwd(Args<T> a, const T* __restrict__ src, int it) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  cpx<T>* A = reinterpret_cast<cpx<T>*>(smem);
+  cpx<T>* B = A + a.Nx;
+  const int r0 = 2 * blockIdx.x, r1 = r0 + 1;
+  const bool two = r1 < a.ny;
+  double alpha = 0.0;
+  if (MODE == ROW_E) {
+    alpha = alpha_of(a, it);
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.alpha[it] = alpha;   // the update uses the same value
+  }
+  double ee = 0.0;
+  for (int c = threadIdx.x; c < a.Nx; c += blockDim.x) {
+    T v0 = 0, v1 = 0;
+    if (c < a.nx) {
+      const long j0 = (long)r0 * a.nx + c, j1 = j0 + a.nx;
+      if (MODE == ROW_LP) {
+        v0 = gather_L(a, src, (int)j0);
+        if (two) v1 = gather_L(a, src, (int)j1);
+      } else if (MODE == ROW_E) {
+        v0 = a.e[j0] - (T)alpha * a.q[j0];
+        a.e[j0] = v0;
+        ee += (double)v0 * (double)v0;
+        if (two) {
+          v1 = a.e[j1] - (T)alpha * a.q[j1];
+          a.e[j1] = v1;
+          ee += (double)v1 * (double)v1;
+        }
+      } else if (MODE == ROW_D) {
+        v0 = (T)a.d[j0];
+        a.e[j0] = v0;
+        if (two) {
+          v1 = (T)a.d[j1];
+          a.e[j1] = v1;
+        }
+      } else {
+        v0 = src[j0];
+        if (two) v1 = src[j1];
+      }
+    }
+    A[c] = {v0, v1};
+  }
+  if (MODE == ROW_E) put_partial(a, ee, P_EE, it);   // contains the barrier the FFT needs
+  else __syncthreads();
+  const cpx<T>* Z = fft_lds<T, false>(A, B, a.Nx, a.twx);
+  // Y0[k] = (Z[k] + conj Z[N-k]) / 2, Y1[k] = -i (Z[k] - conj Z[N-k]) / 2
+  for (int k = threadIdx.x; k < a.Nh; k += blockDim.x) {
+    const cpx<T> zk = Z[k], zm = Z[(a.Nx - k) & (a.Nx - 1)];
+    const T h = (T)0.5;
+    cpx<T>* dst = a.S + (long)k * a.Ny + r0;
+    dst[0] = {h * (zk.x + zm.x), h * (zk.y - zm.y)};
+    if (two) dst[1] = {h * (zk.y + zm.y), h * (zm.x - zk.x)};
+  }
+}
+
+// Column kx = blockIdx.x of the half spectrum: FFT over the Ny rows (rows
+// >= ny are zero), product with the PSF spectrum (conjugated for B^T), inverse
+// FFT, rows < ny stored back.
+template <typename T, bool CONJ>
+__global__ void __launch_bounds__(kNT) k_col(Args<T> a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  cpx<T>* A = reinterpret_cast<cpx<T>*>(smem);
+  cpx<T>* B = A + a.Ny;
+  cpx<T>* col = a.S + (long)blockIdx.x * a.Ny;
+  const cpx<T>* Hc = a.H + (long)blockIdx.x * a.Ny;
+  for (int r = threadIdx.x; r < a.Ny; r += blockDim.x) A[r] = r < a.ny ? col[r] : cpx<T>{0, 0};
+  __syncthreads();
+  cpx<T>* Z = fft_lds<T, false>(A, B, a.Ny, a.twy);
+  for (int r = threadIdx.x; r < a.Ny; r += blockDim.x) Z[r] = CONJ ? cmulc(Z[r], Hc[r]) : cmul(Z[r], Hc[r]);
+  __syncthreads();
+  cpx<T>* Y = fft_lds<T, true>(Z, Z == A ? B : A, a.Ny, a.twy);
+  for (int r = threadIdx.x; r < a.ny; r += blockDim.x) col[r] = Y[r];
+}
+
+enum { OUT_Q = 0, OUT_W = 1, OUT_IMG = 2 };
+
+// Inverse row FFTs of rows r0 = 2 blockIdx.x and r0 + 1 from their half
+// spectra (the other half by conjugate symmetry, as the rows are real):
+// Z[k] = Q0[k] + i Q1[k], inverse FFT, row r0 the real and row r0 + 1 the
+// imaginary part.  OUT_Q: q with its |q|^2 partial; OUT_W: w; OUT_IMG: dst.
+template <typename T, int OUT>
+__global__ void __launch_bounds__(kRowNT) k_rowinv(Args<T> a, T* __restrict__ dst, int it) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  cpx<T>* A = reinterpret_cast<cpx<T>*>(smem);
+  cpx<T>* B = A + a.Nx;
+  const int r0 = 2 * blockIdx.x, r1 = r0 + 1;
+  const bool two = r1 < a.ny;
+  const int half = a.Nx / 2;
+  for (int k = threadIdx.x; k < a.Nx; k += blockDim.x) {
+    const bool mirror = k > half;
+    const int kk = mirror ? a.Nx - k : k;
+    const cpx<T>* src = a.S + (long)kk * a.Ny + r0;
+    cpx<T> q0 = src[0], q1 = two ? src[1] : cpx<T>{0, 0};
+    if (mirror) {
+      q0.y = -q0.y;
+      q1.y = -q1.y;
+    }
+    A[k] = {q0.x - q1.y, q0.y + q1.x};
+  }
+  __syncthreads();
+  const cpx<T>* z = fft_lds<T, true>(A, B, a.Nx, a.twx);
+  T* out = OUT == OUT_Q ? a.q : (OUT == OUT_W ? a.w : dst);
+  double qq = 0.0;
+  for (int c = threadIdx.x; c < a.nx; c += blockDim.x) {
+    const T v0 = z[c].x, v1 = z[c].y;
+    out[(long)r0 * a.nx + c] = v0;
+    if (two) out[(long)r1 * a.nx + c] = v1;
+    if (OUT == OUT_Q) qq += (double)v0 * (double)v0 + (two ? (double)v1 * (double)v1 : 0.0);
+  }
+  if (OUT == OUT_Q) put_partial(a, qq, P_QQ, it);
+}
+
+// ---------------------------------------------------------------- source-side kernels
+// g = L^T w over the sorted table, with its |g|^2 partial in slot `it`:
+// kLtG lanes per node, lane l adding entries l, l + kLtG, ... in order, then
+// a fixed butterfly over the group; lane 0 holds the node's value.  Grid-
+// stride over the nodes (nb_lt <= kMaxParts blocks).
+template <typename T>
+__global__ void __launch_bounds__(kLtNT) k_lt(Args<T> a, int it) {
+  const int l = threadIdx.x & (kLtG - 1);
+  const int per_block = kLtNT / kLtG;
+  double gg = 0.0;
+  for (int n0 = blockIdx.x * per_block; n0 < a.I; n0 += gridDim.x * per_block) {
+    const int node = n0 + threadIdx.x / kLtG;
+    T acc = 0;
+    if (node < a.I) {
+      const int e1 = a.rowptr[node + 1];
+      int e = a.rowptr[node] + l;
+      // four entries' loads in flight at once, added in entry order
+      for (; e + 3 * kLtG < e1; e += 4 * kLtG) {
+        const LtE<T> t0 = a.lt[e], t1 = a.lt[e + kLtG], t2 = a.lt[e + 2 * kLtG], t3 = a.lt[e + 3 * kLtG];
+        const T w0 = a.w[t0.pix], w1 = a.w[t1.pix], w2 = a.w[t2.pix], w3 = a.w[t3.pix];
+        acc += t0.w * w0;
+        acc += t1.w * w1;
+        acc += t2.w * w2;
+        acc += t3.w * w3;
+      }
+      for (; e < e1; e += kLtG) {
+        const LtE<T> t = a.lt[e];
+        acc += t.w * a.w[t.pix];
+      }
+    }
+#pragma unroll
+    for (int o = kLtG / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kLtG);
+    if (node < a.I && l == 0) {
+      a.g[node] = acc;
+      gg += (double)acc * (double)acc;
+    }
+  }
+  put_partial(a, gg, P_GG, it);
+}
+
+// Start: s = 0, p = g = A^T d, |g|^2 (slot n_iter holds its partials).
+template <typename T>
+__global__ void __launch_bounds__(kNT) k_start(Args<T> a) {
+  for (int i = blockIdx.x * kNT + threadIdx.x; i < a.I; i += gridDim.x * kNT) {
+    a.s[i] = 0;
+    a.p[i] = a.g[i];
+  }
+  const double gg = block_total(part_of(a, P_GG, a.n_iter), a.nb_lt);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    a.gg[0] = gg;
+    a.done[0] = !(gg > 0.0);
+  }
+}
+
+// End of iteration it: s += alpha p, p = g + beta p with beta = |g_new|^2 / |g|^2,
+// the iterate kept and its |s|^2 partial; block 0 records the scalars of the
+// next iteration.  Grid-stride over the nodes (nb_node <= kMaxParts blocks).
+template <typename T>
+__global__ void __launch_bounds__(kNT) k_update(Args<T> a, int it) {
+  const double alpha = a.alpha[it];
+  const bool moved = alpha > 0.0;
+  const double gn = block_total(part_of(a, P_GG, it), a.nb_lt);
+  const bool stop = !moved || !(gn > 0.0);
+  const double beta = stop ? 0.0 : gn / a.gg[it];
+  double ss = 0.0;
+  for (int i = blockIdx.x * kNT + threadIdx.x; i < a.I; i += gridDim.x * kNT) {
+    T s = a.s[i];
+    if (moved) {
+      s += (T)alpha * a.p[i];
+      a.s[i] = s;
+      a.p[i] = a.g[i] + (T)beta * a.p[i];
+    }
+    a.s_iter[(long)it * a.I + i] = s;
+    ss += (double)s * (double)s;
+  }
+  put_partial(a, ss, P_SS, it);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    a.gg[it + 1] = moved ? gn : a.gg[it];
+    a.done[it + 1] = a.done[it] || stop;
+    a.upd[it] = moved;
+  }
+}
+
+// chi^2 and sum s^2 of every iterate, statuses, the L-curve corner.
+// (each wave adds the partials of some of the 2 n_iter sums, lane l taking
+// partials l, l + 64, ... in order and a fixed butterfly combining the lanes;
+// then thread 0 does the rest with the L-curve scratch in dynamic LDS)
+template <typename T>
+__global__ void __launch_bounds__(kLtNT) k_final(Args<T> a, sl_result out) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  double* scratch = reinterpret_cast<double*>(smem);
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  for (int j = wv; j < 2 * a.n_iter; j += kLtNT / kWave) {
+    const int k = j >> 1;
+    const bool ee = (j & 1) == 0;
+    const double* p = part_of(a, ee ? P_EE : P_SS, k);
+    const int n = ee ? a.nb_row : a.nb_node;
+    double v = 0.0;
+    for (int i = lane; i < n; i += kWave) v += p[i];
+    v = wave_sum(v);
+    if (lane == 0) {
+      if (ee)
+        out.chi2[k] = v / (a.sigma * a.sigma);
+      else
+        out.reg[k] = v;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  const bool invalid = a.flags[0] != 0;
+  const bool empty = !invalid && !(a.gg[0] > 0.0);
+  int cst = invalid ? SL_ST_INVALID : (empty ? SL_ST_EMPTY : SL_ST_OK);
+  for (int k = 0; k < a.n_iter; ++k) {
+    out.iters[k] = k + 1;
+    const int st = invalid ? SL_ST_INVALID : (empty ? SL_ST_EMPTY : (a.upd[k] ? SL_ST_OK : SL_ST_BREAKDOWN));
+    out.status[k] = st;
+    if (cst == SL_ST_OK && st == SL_ST_BREAKDOWN) cst = SL_ST_BREAKDOWN;
+  }
+  int k = 0;
+  if (!invalid && !empty) {
+    if (a.n_iter >= 4) {
+      const int kk = lcurve_corner_impl(out.reg, out.chi2, a.n_iter, nullptr, scratch);
+      if (kk >= 0)
+        k = kk;
+      else if (cst == SL_ST_OK)
+        cst = SL_ST_LCURVE;
+    } else if (a.n_iter > 1 && cst == SL_ST_OK) {
+      cst = SL_ST_LCURVE;
+    }
+  }
+  out.k_star[0] = k;
+  out.corner_status[0] = cst;
+  out.s_off[0] = 0;
+  out.s_off[1] = a.I;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kNT) k_corner_copy(Args<T> a, sl_result out) {
+  const int i = blockIdx.x * kNT + threadIdx.x;
+  if (i >= a.I) return;
+  const int k = out.k_star[0];
+  out.s_corner[i] = (double)a.s_iter[(long)k * a.I + i];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kNT) k_zero_int(int32_t* p, long n) {
+  const long i = (long)blockIdx.x * kNT + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+// ---------------------------------------------------------------- host side
+struct Layout {
+  int Nx, Ny, Nh, taps;
+  long long cap;
+  size_t total;
+  size_t off[32];
+};
+
+static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Region sizes in order; both the size query and the call use this.
+static Layout make_layout(int nx, int ny, int nsub, int ns, int K, int interp, int n_iter, size_t sz,
+                          bool solve) {
+  Layout L{};
+  const int ck = (K - 1) / 2;
+  L.Nx = frame_side(nx, ck);
+  L.Ny = frame_side(ny, ck);
+  L.Nh = L.Nx / 2 + 1;
+  L.taps = interp == SL_INTERP_BICUBIC ? 16 : 4;
+  const long long J = (long long)nx * ny, n2 = (long long)nsub * nsub, I = (long long)ns * ns;
+  L.cap = J * n2 * L.taps;
+  const size_t c = 2 * sz;   // one complex element
+  const int nb_row = (ny + 1) / 2;
+  const int maxb = nb_row > kMaxParts ? nb_row : kMaxParts;
+  size_t sizes[32];
+  int n = 0;
+  sizes[n++] = c * L.Nx;                              // twx
+  sizes[n++] = c * L.Ny;                              // twy
+  sizes[n++] = 16 * (size_t)L.Nx;                     // twdx
+  sizes[n++] = 16 * (size_t)L.Ny;                     // twdy
+  sizes[n++] = c * (size_t)L.Nh * L.Ny;               // H
+  sizes[n++] = c * (size_t)L.Nh * L.Ny;               // S
+  sizes[n++] = 16 * (size_t)K * L.Nh;                 // T1
+  if (solve) {
+    sizes[n++] = 4 * (size_t)(J * n2);                // cell
+    sizes[n++] = sz * (size_t)(J * n2);               // fx
+    sizes[n++] = sz * (size_t)(J * n2);               // fy
+    sizes[n++] = 4 * (size_t)I;                       // cnt
+    sizes[n++] = 4 * (size_t)((I + kTile - 1) / kTile);   // tsum
+    sizes[n++] = 4 * (size_t)(I + 1);                 // rowptr
+    sizes[n++] = 4 * (size_t)I;                       // cursor
+    sizes[n++] = 4 * (size_t)L.cap;                   // key
+    sizes[n++] = sz * (size_t)L.cap;                  // wtmp
+    sizes[n++] = (sz == 8 ? 16 : 8) * (size_t)L.cap;  // lt
+    sizes[n++] = sz * (size_t)J;                      // q
+    sizes[n++] = sz * (size_t)J;                      // e
+    sizes[n++] = sz * (size_t)J;                      // w
+    sizes[n++] = sz * (size_t)I;                      // s
+    sizes[n++] = sz * (size_t)I;                      // p
+    sizes[n++] = sz * (size_t)I;                      // g
+    sizes[n++] = sz * (size_t)I * n_iter;             // s_iter
+    sizes[n++] = 8 * (size_t)4 * (n_iter + 1) * maxb; // part
+    sizes[n++] = 8 * (size_t)(n_iter + 1);            // gg
+    sizes[n++] = 8 * (size_t)n_iter;                  // alpha
+    sizes[n++] = 4 * (size_t)(n_iter + 1);            // done
+    sizes[n++] = 4 * (size_t)n_iter;                  // upd
+    sizes[n++] = 4 * 2;                               // flags
+  }
+  size_t off = 0;
+  for (int i = 0; i < n; ++i) {
+    L.off[i] = off;
+    off += align256(sizes[i]);
+  }
+  L.total = off;
+  return L;
+}
+
+template <typename T>
+static Args<T> bind(const Layout& L, unsigned char* ws, bool solve) {
+  Args<T> a{};
+  int i = 0;
+  a.twx = reinterpret_cast<cpx<T>*>(ws + L.off[i++]);
+  a.twy = reinterpret_cast<cpx<T>*>(ws + L.off[i++]);
+  a.twdx = reinterpret_cast<cpx<double>*>(ws + L.off[i++]);
+  a.twdy = reinterpret_cast<cpx<double>*>(ws + L.off[i++]);
+  a.H = reinterpret_cast<cpx<T>*>(ws + L.off[i++]);
+  a.S = reinterpret_cast<cpx<T>*>(ws + L.off[i++]);
+  a.T1 = reinterpret_cast<cpx<double>*>(ws + L.off[i++]);
+  if (solve) {
+    a.cell = reinterpret_cast<int32_t*>(ws + L.off[i++]);
+    a.fx = reinterpret_cast<T*>(ws + L.off[i++]);
+    a.fy = reinterpret_cast<T*>(ws + L.off[i++]);
+    a.cnt = reinterpret_cast<int32_t*>(ws + L.off[i++]);
+    a.tsum = reinterpret_cast<int32_t*>(ws + L.off[i++]);
+    a.rowptr = reinterpret_cast<int32_t*>(ws + L.off[i++]);
+    a.cursor = reinterpret_cast<int32_t*>(ws + L.off[i++]);
+    a.key = reinterpret_cast<int32_t*>(ws + L.off[i++]);
+    a.wtmp = reinterpret_cast<T*>(ws + L.off[i++]);
+    a.lt = reinterpret_cast<LtE<T>*>(ws + L.off[i++]);
+    a.q = reinterpret_cast<T*>(ws + L.off[i++]);
+    a.e = reinterpret_cast<T*>(ws + L.off[i++]);
+    a.w = reinterpret_cast<T*>(ws + L.off[i++]);
+    a.s = reinterpret_cast<T*>(ws + L.off[i++]);
+    a.p = reinterpret_cast<T*>(ws + L.off[i++]);
+    a.g = reinterpret_cast<T*>(ws + L.off[i++]);
+    a.s_iter = reinterpret_cast<T*>(ws + L.off[i++]);
+    a.part = reinterpret_cast<double*>(ws + L.off[i++]);
+    a.gg = reinterpret_cast<double*>(ws + L.off[i++]);
+    a.alpha = reinterpret_cast<double*>(ws + L.off[i++]);
+    a.done = reinterpret_cast<int32_t*>(ws + L.off[i++]);
+    a.upd = reinterpret_cast<int32_t*>(ws + L.off[i++]);
+    a.flags = reinterpret_cast<int32_t*>(ws + L.off[i++]);
+  }
+  a.Nx = L.Nx;
+  a.Ny = L.Ny;
+  a.Nh = L.Nh;
+  a.taps = L.taps;
+  return a;
+}
+
+static inline unsigned nblk(long n, int nt) { return (unsigned)((n + nt - 1) / nt); }
+
+template <typename T>
+static int set_lds(size_t bytes) {
+  const void* ks[] = {(const void*)k_rowfwd<T, ROW_LP>, (const void*)k_rowfwd<T, ROW_E>,
+                      (const void*)k_rowfwd<T, ROW_D>,  (const void*)k_rowfwd<T, ROW_IMG>,
+                      (const void*)k_col<T, false>,     (const void*)k_col<T, true>,
+                      (const void*)k_rowinv<T, OUT_Q>,  (const void*)k_rowinv<T, OUT_W>,
+                      (const void*)k_rowinv<T, OUT_IMG>};
+  for (const void* k : ks) SL_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  SL_HIP(hipFuncSetAttribute((const void*)k_final<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)(8 * kLcurveScratch)));
+  return SL_OK;
+}
+
+// PSF spectrum and twiddles (every call).
+template <typename T>
+static int spectrum(const Args<T>& a, hipStream_t st) {
+  hipLaunchKernelGGL(k_twiddles<T>, dim3(nblk(a.Nx > a.Ny ? a.Nx : a.Ny, kNT)), dim3(kNT), 0, st, a);
+  hipLaunchKernelGGL(k_psf_rows<T>, dim3(nblk((long)a.K * a.Nh, kNT)), dim3(kNT), 0, st, a);
+  hipLaunchKernelGGL(k_psf_cols<T>, dim3(nblk((long)a.Nh * a.Ny, kNT)), dim3(kNT), 0, st, a);
+  return check_launch("PSF spectrum");
+}
+
+// One blur of the image in flight: row pass (launched by the caller), column
+// pass, inverse row pass.
+template <typename T, bool CONJ, int OUT>
+static void blur_tail(const Args<T>& a, T* dst, int it, hipStream_t st) {
+  const size_t lx = 2 * sizeof(cpx<T>) * a.Nx, ly = 2 * sizeof(cpx<T>) * a.Ny;
+  hipLaunchKernelGGL((k_col<T, CONJ>), dim3(a.Nh), dim3(kNT), ly, st, a);
+  hipLaunchKernelGGL((k_rowinv<T, OUT>), dim3(a.nb_row), dim3(kRowNT), lx, st, a, dst, it);
+}
+
+template <typename T>
+static int fft_blur_impl(int transpose, int nx, int ny, const double* psf, int k, const void* in, void* out,
+                         void* workspace, hipStream_t st) {
+  const Layout L = make_layout(nx, ny, 1, 2, k, SL_INTERP_BILINEAR, 1, sizeof(T), false);
+  Args<T> a = bind<T>(L, static_cast<unsigned char*>(workspace), false);
+  a.nx = nx;
+  a.ny = ny;
+  a.K = k;
+  a.ck = (k - 1) / 2;
+  a.psf = psf;
+  a.nb_row = (ny + 1) / 2;
+  if (int e = set_lds<T>(2 * sizeof(cpx<T>) * (a.Nx > a.Ny ? a.Nx : a.Ny))) return e;
+  if (int e = spectrum(a, st)) return e;
+  hipLaunchKernelGGL((k_rowfwd<T, ROW_IMG>), dim3(a.nb_row), dim3(kRowNT), 2 * sizeof(cpx<T>) * a.Nx, st, a,
+                     static_cast<const T*>(in), 0);
+  if (transpose)
+    blur_tail<T, true, OUT_IMG>(a, static_cast<T*>(out), 0, st);
+  else
+    blur_tail<T, false, OUT_IMG>(a, static_cast<T*>(out), 0, st);
+  return check_launch("fft blur");
+}
+
+template <typename T>
+static int solve_impl(const sl_problem* pb, const double* lens, int ns, int n_iter, void* workspace,
+                      sl_result* out, hipStream_t st) {
+  const sl_image_grid& g = pb->img;
+  const Layout L = make_layout(g.nx, g.ny, g.nsub, ns, pb->k, pb->interp, n_iter, sizeof(T), true);
+  Args<T> a = bind<T>(L, static_cast<unsigned char*>(workspace), true);
+  a.nx = g.nx;
+  a.ny = g.ny;
+  a.nsub = g.nsub;
+  a.n2 = g.nsub * g.nsub;
+  a.ns = ns;
+  a.I = ns * ns;
+  a.J = g.nx * g.ny;
+  a.K = pb->k;
+  a.ck = (pb->k - 1) / 2;
+  a.interp = pb->interp;
+  a.pix = g.pix;
+  a.R = pb->half_width;
+  a.sigma = pb->sigma;
+  a.lens = lens;
+  a.d = pb->d;
+  a.psf = pb->psf;
+  a.n_iter = n_iter;
+  a.nb_row = (g.ny + 1) / 2;
+  a.nb_node = (int)std::min<long>(nblk(a.I, kNT), kMaxParts);
+  a.nb_lt = (int)std::min<long>(nblk((long)a.I * kLtG, kLtNT), kMaxParts);
+  a.max_blocks = a.nb_row > a.nb_node ? a.nb_row : a.nb_node;
+  if (a.nb_lt > a.max_blocks) a.max_blocks = a.nb_lt;
+  const size_t lx = 2 * sizeof(cpx<T>) * a.Nx;
+  if (int e = set_lds<T>(2 * sizeof(cpx<T>) * (a.Nx > a.Ny ? a.Nx : a.Ny))) return e;
+  // counters start at zero (a fill kernel: the call may be captured in a graph)
+  hipLaunchKernelGGL(k_zero_int<T>, dim3(nblk(a.I, kNT)), dim3(kNT), 0, st, a.cnt, (long)a.I);
+  hipLaunchKernelGGL(k_zero_int<T>, dim3(1), dim3(kNT), 0, st, a.flags, 2L);
+  if (int e = spectrum(a, st)) return e;
+  const long nsubpix = (long)a.J * a.n2;
+  hipLaunchKernelGGL(k_trace<T>, dim3(nblk(nsubpix, kNT)), dim3(kNT), 0, st, a);
+  const unsigned tiles = nblk(a.I, kTile);
+  hipLaunchKernelGGL(k_tile_sums<T>, dim3(tiles), dim3(kNT), 0, st, a);
+  hipLaunchKernelGGL(k_tile_scan<T>, dim3(1), dim3(kNT), 0, st, a);
+  hipLaunchKernelGGL(k_tile_write<T>, dim3(tiles), dim3(kNT), 0, st, a);
+  hipLaunchKernelGGL(k_fill<T>, dim3(nblk(nsubpix, kNT)), dim3(kNT), 0, st, a);
+  hipLaunchKernelGGL(k_sort<T>, dim3(nblk(a.I, kNT / kWave)), dim3(kNT), 0, st, a);
+  if (int e = check_launch("large solve set-up")) return e;
+  // g = A^T d, p = g
+  hipLaunchKernelGGL((k_rowfwd<T, ROW_D>), dim3(a.nb_row), dim3(kRowNT), lx, st, a, (const T*)nullptr, 0);
+  blur_tail<T, true, OUT_W>(a, nullptr, 0, st);
+  hipLaunchKernelGGL(k_lt<T>, dim3(a.nb_lt), dim3(kLtNT), 0, st, a, n_iter);
+  hipLaunchKernelGGL(k_start<T>, dim3(a.nb_node), dim3(kNT), 0, st, a);
+  for (int it = 0; it < n_iter; ++it) {
+    hipLaunchKernelGGL((k_rowfwd<T, ROW_LP>), dim3(a.nb_row), dim3(kRowNT), lx, st, a, (const T*)a.p, it);
+    blur_tail<T, false, OUT_Q>(a, nullptr, it, st);                      // q = A p, |q|^2
+    hipLaunchKernelGGL((k_rowfwd<T, ROW_E>), dim3(a.nb_row), dim3(kRowNT), lx, st, a, (const T*)nullptr, it);
+    blur_tail<T, true, OUT_W>(a, nullptr, it, st);                       // w = B^T e
+    hipLaunchKernelGGL(k_lt<T>, dim3(a.nb_lt), dim3(kLtNT), 0, st, a, it);
+    hipLaunchKernelGGL(k_update<T>, dim3(a.nb_node), dim3(kNT), 0, st, a, it);
+  }
+  if (int e = check_launch("large solve iterations")) return e;
+  hipLaunchKernelGGL(k_final<T>, dim3(1), dim3(kLtNT), 8 * kLcurveScratch, st, a, *out);
+  hipLaunchKernelGGL(k_corner_copy<T>, dim3(nblk(a.I, kNT)), dim3(kNT), 0, st, a, *out);
+  return check_launch("large solve corner");
+}
+
+static int check_large(const sl_problem* pb, int ns, int n_iter) {
+  SL_REQUIRE(pb != nullptr, "problem is NULL");
+  const sl_image_grid& g = pb->img;
+  SL_REQUIRE(g.nx >= 1 && g.ny >= 1 && g.nx <= kMaxImage && g.ny <= kMaxImage,
+             "large solve supports images up to %d x %d (got %d x %d)", kMaxImage, kMaxImage, g.nx, g.ny);
+  SL_REQUIRE(std::isfinite(g.pix) && g.pix > 0.0, "pixel size must be positive");
+  SL_REQUIRE(g.nsub >= 1 && g.nsub <= SL_MAX_NSUB, "nsub %d outside [1, %d]", g.nsub, SL_MAX_NSUB);
+  SL_REQUIRE(pb->k >= 1 && pb->k <= kMaxPsf && (pb->k & 1), "PSF side %d must be odd, <= %d", pb->k, kMaxPsf);
+  SL_REQUIRE(std::isfinite(pb->sigma) && pb->sigma > 0.0, "sigma must be positive");
+  SL_REQUIRE(std::isfinite(pb->half_width) && pb->half_width > 0.0, "half_width must be positive");
+  SL_REQUIRE(pb->dtype == SL_F32 || pb->dtype == SL_F64, "unknown dtype %d", pb->dtype);
+  SL_REQUIRE(pb->interp == SL_INTERP_BILINEAR || pb->interp == SL_INTERP_NEAREST || pb->interp == SL_INTERP_BICUBIC,
+             "unknown interp %d", pb->interp);
+  SL_REQUIRE(ns >= 2 && ns <= kMaxNs, "ns %d outside [2, %d]", ns, kMaxNs);
+  SL_REQUIRE(n_iter >= 1 && n_iter <= SL_MAX_LAMBDA, "n_iter %d outside [1, %d]", n_iter, SL_MAX_LAMBDA);
+  const int ck = (pb->k - 1) / 2;
+  SL_REQUIRE(frame_side(g.nx, ck) <= kMaxFrame && frame_side(g.ny, ck) <= kMaxFrame,
+             "FFT frame above %d for this image and PSF", kMaxFrame);
+  const long long entries = (long long)g.nx * g.ny * g.nsub * g.nsub * (pb->interp == SL_INTERP_BICUBIC ? 16 : 4);
+  SL_REQUIRE(entries < (1LL << 31), "too many L^T entries (%lld)", entries);
+  return SL_OK;
+}
+
+static int check_blur(int dtype, int nx, int ny, int k) {
+  SL_REQUIRE(dtype == SL_F32 || dtype == SL_F64, "unknown dtype %d", dtype);
+  SL_REQUIRE(nx >= 1 && ny >= 1 && nx <= kMaxImage && ny <= kMaxImage, "image %d x %d outside [1, %d]", nx, ny,
+             kMaxImage);
+  SL_REQUIRE(k >= 1 && k <= kMaxPsf && (k & 1), "PSF side %d must be odd, <= %d", k, kMaxPsf);
+  const int ck = (k - 1) / 2;
+  SL_REQUIRE(frame_side(nx, ck) <= kMaxFrame && frame_side(ny, ck) <= kMaxFrame, "FFT frame above %d", kMaxFrame);
+  return SL_OK;
+}
+
+}  // namespace large
+}  // namespace sl
+
+using namespace sl;
+using namespace sl::large;
+
+extern "C" {
+
+size_t sl_fft_blur_workspace_size(int dtype, int nx, int ny, int k) {
+  if (check_blur(dtype, nx, ny, k) != SL_OK) return 0;
+  return make_layout(nx, ny, 1, 2, k, SL_INTERP_BILINEAR, 1, dtype == SL_F64 ? 8 : 4, false).total;
+}
+
+int sl_fft_blur(int dtype, int transpose, int nx, int ny, const double* psf, int k, const void* in, void* out,
+                void* workspace, size_t workspace_bytes, void* stream) {
+  if (int e = check_blur(dtype, nx, ny, k)) return e;
+  SL_REQUIRE(transpose == 0 || transpose == 1, "transpose must be 0 or 1");
+  SL_REQUIRE(psf && in && out && in != out, "bad device pointers");
+  SL_REQUIRE(workspace != nullptr && ((uintptr_t)workspace & 255) == 0,
+             "workspace must be non-NULL and 256-byte aligned");
+  const size_t need = sl_fft_blur_workspace_size(dtype, nx, ny, k);
+  SL_REQUIRE(workspace_bytes >= need, "workspace too small: %zu < %zu bytes", workspace_bytes, need);
+  hipStream_t st = (hipStream_t)stream;
+  if (dtype == SL_F32) return fft_blur_impl<float>(transpose, nx, ny, psf, k, in, out, workspace, st);
+  return fft_blur_impl<double>(transpose, nx, ny, psf, k, in, out, workspace, st);
+}
+
+size_t sl_solve_large_workspace_size(const sl_problem* pb, int ns, int n_iter) {
+  if (check_large(pb, ns, n_iter) != SL_OK) return 0;
+  const sl_image_grid& g = pb->img;
+  return make_layout(g.nx, g.ny, g.nsub, ns, pb->k, pb->interp, n_iter, pb->dtype == SL_F64 ? 8 : 4, true).total;
+}
+
+int sl_solve_large(const sl_problem* pb, const double* lens, int ns, int n_iter, void* workspace,
+                   size_t workspace_bytes, sl_result* out, void* stream) {
+  if (int e = check_large(pb, ns, n_iter)) return e;
+  SL_REQUIRE(lens && pb->d && pb->psf, "NULL device pointer");
+  SL_REQUIRE(out && out->s_corner && out->s_off && out->chi2 && out->reg && out->iters && out->status &&
+                 out->k_star && out->corner_status,
+             "NULL result pointer");
+  SL_REQUIRE(workspace != nullptr && ((uintptr_t)workspace & 255) == 0,
+             "workspace must be non-NULL and 256-byte aligned");
+  const size_t need = sl_solve_large_workspace_size(pb, ns, n_iter);
+  SL_REQUIRE(workspace_bytes >= need, "workspace too small: %zu < %zu bytes", workspace_bytes, need);
+  hipStream_t st = (hipStream_t)stream;
+  if (pb->dtype == SL_F32) return solve_impl<float>(pb, lens, ns, n_iter, workspace, out, st);
+  return solve_impl<double>(pb, lens, ns, n_iter, workspace, out, st);
+}
+
+}  // extern "C"

@@ -115,6 +115,27 @@ def apply_BT(psf: torch.Tensor, x: torch.Tensor) -> torch.Tensor:
     return _blur("sl_apply_BT", psf, x)
 
 
+def fft_blur(psf: torch.Tensor, x: torch.Tensor, transpose: bool = False, workspace: torch.Tensor | None = None):
+    """apply_B (or, transpose, apply_BT) of one image (ny, nx) computed in Fourier space (sl_fft_blur),
+    for PSFs up to 129 x 129."""
+    _dev_check(psf, x)
+    psf = psf.to(torch.float64).contiguous()
+    x = x.contiguous()
+    if x.dim() != 2:
+        raise L.SemilinError("fft_blur takes one image (ny, nx)")
+    ny, nx = x.shape
+    dt = _DT[x.dtype]
+    need = L.lib().sl_fft_blur_workspace_size(dt, nx, ny, psf.shape[0])
+    if need == 0:
+        raise L.SemilinError(L.lib().sl_last_error().decode())
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(int(need), dtype=torch.uint8, device=x.device)
+    out = torch.empty_like(x)
+    L.check(L.lib().sl_fft_blur(dt, int(bool(transpose)), nx, ny, L.ptr(psf), psf.shape[0], L.ptr(x), L.ptr(out),
+                                L.ptr(workspace), workspace.numel(), L.stream_handle()), "sl_fft_blur")
+    return out
+
+
 def apply_HtH(reg: str, ns, s: torch.Tensor) -> torch.Tensor:
     _dev_check(s)
     ns = list(ns)
@@ -200,6 +221,7 @@ class Solver:
         self.device = d.device
         self._ws = None
         self._cws = None   # workspace of chi2_sources
+        self._lws = None   # workspace of solve_large
         # launch hint: a PSF whose second singular value is not negligible is not rank 1, so the solve
         # launches only the direct blur form (the device's own rank-1 test decides every other case)
         sv = np.linalg.svd(self.psf.cpu().numpy(), compute_uv=False)
@@ -303,6 +325,25 @@ class Solver:
         L.check(L.lib().sl_solve_implicit(ctypes.byref(self._pb), L.ptr(lens), L.ptr(ns), max_ns, M, int(n_iter),
                                           ctypes.byref(opts), L.ptr(ws), ws.numel(), ctypes.byref(res),
                                           L.stream_handle()), "sl_solve_implicit")
+        return out
+
+    def solve_large(self, lens, ns: int, n_iter: int = 40, out=None):
+        """One lens on a large image (sl_solve_large): n_iter CGLS iterations with the blur in Fourier space,
+        the L-curve over the iterates; the result dict of solve_implicit with one member."""
+        lens = torch.as_tensor(lens, dtype=torch.float64, device=self.device).contiguous().reshape(-1)
+        if lens.numel() != 7:
+            raise L.SemilinError("lens must hold the 7 lens parameters")
+        need = L.lib().sl_solve_large_workspace_size(ctypes.byref(self._pb), int(ns), int(n_iter))
+        if need == 0:
+            raise L.SemilinError(L.lib().sl_last_error().decode())
+        if self._lws is None or self._lws.numel() < need:
+            self._lws = torch.empty(int(need), dtype=torch.uint8, device=self.device)
+        if out is None:
+            out = self.alloc_result(ns * ns, 1, n_iter)
+        res = L.Result(*[ctypes.c_void_p(out[k].data_ptr()) for k in
+                         ("s_corner", "s_off", "chi2", "reg", "iters", "status", "k_star", "corner_status", "dof")])
+        L.check(L.lib().sl_solve_large(ctypes.byref(self._pb), L.ptr(lens), int(ns), int(n_iter), L.ptr(self._lws),
+                                       self._lws.numel(), ctypes.byref(res), L.stream_handle()), "sl_solve_large")
         return out
 
     def chi2_sources(self, lens, ns: int, sources: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:

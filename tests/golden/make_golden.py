@@ -35,6 +35,11 @@ root:  python tests/golden/make_golden.py   (about two minutes on 8 cores)
   iterations, corner and corner solution, from the numpy FP64 CG at tol
   1e-10 (about two minutes on 6 cores).
 
+* large_envelope.npz -- the large-scale shape (synthgen.LARGE, Sec. 4):
+  the oracle's 40 CGLS iterates with the blur in Fourier space (chi^2,
+  carried chi^2, sum s^2, ||s||) and their spread over 24 Monte Carlo
+  arithmetic runs at FP32 rounding (about five minutes).
+
 * c2_bicubic.npz -- the same with bicubic source interpolation (Sec. 2.1;
   cubic convolution, Keys a = -1/2, over the 4 x 4 nodes about each
   subpixel's cell, nodes outside the grid zero).
@@ -42,6 +47,7 @@ root:  python tests/golden/make_golden.py   (about two minutes on 8 cores)
 `python tests/golden/make_golden.py c4` writes only c4_sample.npz;
 `python tests/golden/make_golden.py c2nearest` writes only c2_nearest.npz;
 `python tests/golden/make_golden.py c2bicubic` writes only c2_bicubic.npz;
+`python tests/golden/make_golden.py large` writes only large_envelope.npz;
 `python tests/golden/make_golden.py c2radial` writes only c2_radial.npz;
 `python tests/golden/make_golden.py c3full` writes only c3_full.npz;
 `python tests/golden/make_golden.py c2nsub` writes only c2_nsub.npz.
@@ -180,7 +186,31 @@ def c2_interp(kind):
                         s=np.stack([o[0] for o in outs]))
 
 
+def large_envelope():
+    """Rounding envelope of the FP32 CGLS iterates at the large-scale shape
+    (Sec. 4): the oracle's 40 iterates with the blur in Fourier space and
+    their spread over 24 Monte Carlo arithmetic runs at FP32 rounding
+    (tests/cgls_envelope.py)."""
+    sys.path.insert(0, os.path.dirname(HERE))
+    import cgls_envelope
+    from oracle import solve
+    w = synthgen.LARGE
+    z = np.load(os.path.join(os.path.dirname(HERE), "data", "large.npz"))
+    d = z["d"].astype(np.float64)
+
+    def make(dd):
+        return solve.Problem(z["lens"], dd, float(z["sigma"]), z["psf"], w.nx, w.ny, w.pix, w.nsub_model, w.ns,
+                             w.half_width, w.reg, blur="fft")
+    ref, dev, ds, corners = cgls_envelope.envelope(make, d, "f32", w.k_psf, synthgen.LARGE_ITERS, draws=24)
+    np.savez_compressed(os.path.join(HERE, "large_envelope.npz"), chi2=ref["chi2"], chi2_e=ref["chi2_e"],
+                        reg=ref["reg"], dev_chi2=dev["chi2"], dev_reg=dev["reg"], ds=ds,
+                        corners=np.array(sorted(corners)), s_norm=np.linalg.norm(ref["s"], axis=1))
+
+
 def main():
+    if sys.argv[1:] == ["large"]:
+        large_envelope()
+        return
     if sys.argv[1:] == ["c2nearest"]:
         c2_interp("nearest")
         return

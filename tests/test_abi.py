@@ -150,3 +150,37 @@ def test_interp_enum_and_workspace_on_host():
     assert cub - bil >= 8 * 8 * 24 * 4 * slot_cap_min   # 8 members, 24 more entries of 8 bytes per subpixel
     assert size(3) == 0
     assert b"interp" in L.sl_last_error()
+
+
+def test_large_and_fft_blur_sizes_on_host():
+    """Workspace queries of the Fourier-space blur and of the large solve, and
+    their refusals, without a GPU."""
+    from paper_1101_5803_amd import _lib as B
+    L = _lib()
+    L.sl_last_error.restype = ctypes.c_char_p
+    L.sl_fft_blur_workspace_size.argtypes = [ctypes.c_int] * 4
+    L.sl_fft_blur_workspace_size.restype = ctypes.c_size_t
+    L.sl_solve_large_workspace_size.argtypes = [ctypes.POINTER(B.Problem), ctypes.c_int, ctypes.c_int]
+    L.sl_solve_large_workspace_size.restype = ctypes.c_size_t
+    small = L.sl_fft_blur_workspace_size(B.SL_F32, 640, 640, 65)
+    assert small >= 2 * 8 * 513 * 1024            # PSF spectrum and work spectrum, 1024 x 1024 frame
+    assert L.sl_fft_blur_workspace_size(B.SL_F64, 640, 640, 65) > small
+    assert L.sl_fft_blur_workspace_size(B.SL_F32, 640, 640, 64) == 0 and b"odd" in L.sl_last_error()
+    assert L.sl_fft_blur_workspace_size(B.SL_F32, 640, 640, 131) == 0
+    assert L.sl_fft_blur_workspace_size(B.SL_F32, 4097, 8, 3) == 0
+
+    def size(ns, n_iter, k=65, interp=B.SL_INTERP_BILINEAR, nx=640):
+        pb = B.Problem()
+        pb.img = B.ImageGrid(nx, 640, 0.008, 2)
+        pb.sigma, pb.k, pb.half_width = 1.0, k, 1.6
+        pb.reg, pb.dtype, pb.psf_general, pb.interp = B.SL_H_IDENTITY, B.SL_F32, 1, interp
+        return L.sl_solve_large_workspace_size(ctypes.byref(pb), ns, n_iter)
+
+    base = size(512, 40)
+    # the L^T table alone: 640^2 pixels x 4 subpixels x 4 taps x (key, weight, pixel, weight)
+    assert base > 640 * 640 * 4 * 4 * 16
+    assert size(512, 40, interp=B.SL_INTERP_BICUBIC) > base
+    assert size(1025, 40) == 0 and b"ns" in L.sl_last_error()
+    assert size(512, 65) == 0
+    assert size(512, 40, k=131) == 0
+    assert size(512, 40, nx=2049) == 0

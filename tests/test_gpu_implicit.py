@@ -35,16 +35,15 @@ import numpy as np
 import pytest
 import torch
 
+import cgls_envelope
 import synthgen
+from cgls_envelope import DRAWS, FLOOR, U
 from oracle import implicit, lcurve, mock, solve
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda"
 HERE = os.path.dirname(os.path.abspath(__file__))
 N_ITER = 40
-U = {"f64": 2.0 ** -53, "f32": 2.0 ** -24}
-FLOOR = {"f64": 1e-13, "f32": 1e-7}
-DRAWS = 8
 
 
 @pytest.fixture(scope="module")
@@ -59,36 +58,8 @@ def _np(out):
     return {k: v.cpu().numpy() for k, v in out.items()}
 
 
-def _mca(prec, K, n, rng):
-    """Monte Carlo arithmetic at the GPU's rounding level (see the module docstring)."""
-    u = U[prec]
-    rel = {"A": u * K, "AT": u * K, "vec": u, "scalar": u if prec == "f32" else u * np.sqrt(n)}
-
-    def perturb(x, kind):
-        return x * (1 + rel[kind] * rng.standard_normal(np.shape(x)))
-    return perturb
-
-
 def _envelope(make_pb, d, prec, K):
-    """Oracle iterates on d, and their spread over DRAWS Monte Carlo arithmetic runs."""
-    ref = implicit.cgls_iterates(make_pb(d), N_ITER)
-    rng = np.random.default_rng(77)
-    runs = []
-    for _ in range(DRAWS):
-        pb = make_pb(d * (1 + U[prec] * rng.standard_normal(d.shape)))
-        runs.append(implicit.cgls_iterates(pb, N_ITER, perturb=_mca(prec, K, max(pb.I, d.size), rng)))
-    # largest relative deviation over the draws up to each iterate: rounding
-    # effects accumulate, and a per-iterate maximum dips where the deviations
-    # of all draws happen to change sign together
-    rel = {"chi2": np.max([np.maximum(np.abs(r["chi2"] - ref["chi2"]), np.abs(r["chi2_e"] - ref["chi2"]))
-                           for r in runs], axis=0) / np.abs(ref["chi2"]),
-           "reg": np.max([np.abs(r["reg"] - ref["reg"]) for r in runs], axis=0) / np.maximum(np.abs(ref["reg"]), 1e-300)}
-    dev = {k: np.maximum.accumulate(v) * np.abs(ref[k]) for k, v in rel.items()}
-    sn = np.maximum(np.linalg.norm(ref["s"], axis=1), 1e-300)
-    ds = np.maximum.accumulate(np.max([np.linalg.norm(r["s"] - ref["s"], axis=1) for r in runs], axis=0) / sn) * sn
-    corners = {lcurve.corner(ref["reg"], ref["chi2"])[0]} | lcurve.corner_set(ref["reg"], ref["chi2"])
-    corners |= {lcurve.corner(r["reg"], r["chi2"])[0] for r in runs}
-    return ref, dev, ds, corners
+    return cgls_envelope.envelope(make_pb, d, prec, K, N_ITER)
 
 
 def _check(out, G, ns, d, sigma, psf, geom, nsub, R, prec, rows=None, skip=()):
@@ -203,7 +174,7 @@ def _dof_envelope(make_pb, d, bhat, K):
     devs = []
     for _ in range(DRAWS):
         pb = make_pb(d * (1 + U["f64"] * rng.standard_normal(d.shape)))
-        r = implicit.cgls_iterates(pb, N_ITER, perturb=_mca("f64", K, max(pb.I, d.size), rng))
+        r = implicit.cgls_iterates(pb, N_ITER, perturb=cgls_envelope.mca("f64", K, max(pb.I, d.size), rng))
         devs.append(np.abs(implicit.lockstep_dof(pb, bhat, r["alpha"], r["beta"], N_ITER) - ref))
     scale = float((bhat * bhat).sum())
     return ref, np.maximum.accumulate(np.max(devs, axis=0) / scale) * scale, scale
