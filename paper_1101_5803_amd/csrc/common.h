@@ -162,6 +162,11 @@ __host__ __device__ inline bool grid_cell(double u, double v, int ns, int& cell,
 // Not-a-knot cubic spline first/second derivatives at the knots; solves the
 // n x n moment system by Gaussian elimination with partial pivoting.
 // A: n*n scratch, rhs: n scratch.  Returns false on a singular system.
+// The system is banded (at most two entries below and two above the
+// diagonal: the two not-a-knot rows), so with partial pivoting the factors
+// keep at most two entries below and four above it; the loops visit only
+// those, and every entry they skip is an exact zero (the result is that of
+// the full elimination).
 __host__ __device__ inline bool spline_knot_derivs(const double* t, const double* y, int n, double* A,
                                                    double* M, double* d1) {
   for (int i = 0; i < n * n; ++i) A[i] = 0.0;
@@ -183,12 +188,14 @@ __host__ __device__ inline bool spline_knot_derivs(const double* t, const double
   A[(n - 1) * n + n - 1] = ha;
   // elimination
   for (int col = 0; col < n; ++col) {
+    const int rlast = col + 2 < n - 1 ? col + 2 : n - 1;
+    const int clast = col + 4 < n - 1 ? col + 4 : n - 1;
     int piv = col;
-    for (int r = col + 1; r < n; ++r)
+    for (int r = col + 1; r <= rlast; ++r)
       if (fabs(A[r * n + col]) > fabs(A[piv * n + col])) piv = r;
     if (A[piv * n + col] == 0.0) return false;
     if (piv != col) {
-      for (int c = 0; c < n; ++c) {
+      for (int c = col; c <= clast; ++c) {
         const double tmp = A[col * n + c];
         A[col * n + c] = A[piv * n + c];
         A[piv * n + c] = tmp;
@@ -197,16 +204,17 @@ __host__ __device__ inline bool spline_knot_derivs(const double* t, const double
       M[col] = M[piv];
       M[piv] = tmp;
     }
-    for (int r = col + 1; r < n; ++r) {
+    for (int r = col + 1; r <= rlast; ++r) {
       if (A[r * n + col] == 0.0) continue;   // the quotient would be 0 (the pivot is not)
       const double f = A[r * n + col] / A[col * n + col];
-      for (int c = col; c < n; ++c) A[r * n + c] -= f * A[col * n + c];
+      for (int c = col; c <= clast; ++c) A[r * n + c] -= f * A[col * n + c];
       M[r] -= f * M[col];
     }
   }
   for (int r = n - 1; r >= 0; --r) {
     double acc = M[r];
-    for (int c = r + 1; c < n; ++c) acc -= A[r * n + c] * M[c];
+    const int clast = r + 4 < n - 1 ? r + 4 : n - 1;
+    for (int c = r + 1; c <= clast; ++c) acc -= A[r * n + c] * M[c];
     M[r] = acc / A[r * n + r];
   }
   for (int i = 0; i < n - 1; ++i) {

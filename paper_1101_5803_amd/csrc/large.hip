@@ -58,6 +58,14 @@ struct alignas(2 * sizeof(T)) cpx {
   T x, y;
 };
 
+// One subpixel of the trace table: its cell (-1 off the grid) and fractions,
+// read together by one load.
+template <typename T>
+struct alignas(sizeof(T) == 8 ? 8 : 4) Sub {
+  int32_t cell;
+  T fx, fy;
+};
+
 // One entry of the node-major L^T table: pixel and weight.
 template <typename T>
 struct alignas(8) LtE {
@@ -100,9 +108,7 @@ struct Args {
   cpx<T>* H;            // [Nh][Ny] PSF spectrum / (Nx Ny)
   cpx<T>* S;            // [Nh][Ny] spectrum of the image in flight (rows < ny used in the row passes)
   cpx<double>* T1;      // [K][Nh] first stage of the PSF transform
-  int32_t* cell;        // [J n^2] cell of each subpixel (-1 off the grid)
-  T* fx;                // [J n^2]
-  T* fy;
+  Sub<T>* sub;          // [J n^2] cell and fractions of each subpixel
   int32_t* cnt;         // [I] entries per node
   int32_t* tsum;        // [tiles] entries per tile of 1024 nodes, then the tile's start
   int32_t* rowptr;      // [I + 1]
@@ -280,11 +286,12 @@ __device__ __forceinline__ double keys(double d) {
 // first node, nodes outside the grid left out.
 template <typename T>
 __device__ __forceinline__ void tap(const Args<T>& a, long j, int q, int& node, double& wt) {
-  const int c = a.cell[j];
+  const Sub<T> sp = a.sub[j];
+  const int c = sp.cell;
   node = -1;
   wt = 0.0;
   if (c < 0) return;
-  const double fx = (double)a.fx[j], fy = (double)a.fy[j];
+  const double fx = (double)sp.fx, fy = (double)sp.fy;
   if (a.taps == 4) {
     const int dr = q >> 1, dc = q & 1;
     node = c + dr * a.ns + dc;
@@ -326,9 +333,7 @@ __global__ void __launch_bounds__(kNT) k_trace(Args<T> a) {
       fy = fy >= 0.5 ? 1.0 : 0.0;
     }
   }
-  a.cell[j] = cell;
-  a.fx[j] = (T)fx;
-  a.fy[j] = (T)fy;
+  a.sub[j] = {cell, (T)fx, (T)fy};
   if (cell < 0) return;
   for (int q = 0; q < a.taps; ++q) {
     int node;
@@ -422,7 +427,7 @@ __global__ void __launch_bounds__(kNT) k_tile_write(Args<T> a) {
 template <typename T>
 __global__ void __launch_bounds__(kNT) k_fill(Args<T> a) {
   const long j = (long)blockIdx.x * kNT + threadIdx.x;
-  if (j >= (long)a.J * a.n2 || a.cell[j] < 0) return;
+  if (j >= (long)a.J * a.n2 || a.sub[j].cell < 0) return;
   for (int q = 0; q < a.taps; ++q) {
     int node;
     double wt;
@@ -491,16 +496,18 @@ __device__ __forceinline__ T gather_L(const Args<T>& a, const T* __restrict__ x,
   const long j0 = (long)pixel * a.n2;
   if (a.taps == 4) {
     for (int k = 0; k < a.n2; ++k) {
-      const int c = a.cell[j0 + k];
+      const Sub<T> sp = a.sub[j0 + k];
+      const int c = sp.cell;
       if (c < 0) continue;
-      const T fx = a.fx[j0 + k], fy = a.fy[j0 + k];
+      const T fx = sp.fx, fy = sp.fy;
       acc += (1 - fy) * ((1 - fx) * x[c] + fx * x[c + 1]) + fy * ((1 - fx) * x[c + a.ns] + fx * x[c + a.ns + 1]);
     }
   } else {
     for (int k = 0; k < a.n2; ++k) {
-      const int c = a.cell[j0 + k];
+      const Sub<T> sp = a.sub[j0 + k];
+      const int c = sp.cell;
       if (c < 0) continue;
-      const double fx = (double)a.fx[j0 + k], fy = (double)a.fy[j0 + k];
+      const double fx = (double)sp.fx, fy = (double)sp.fy;
       const int r = c / a.ns, col = c % a.ns;
       for (int jr = -1; jr <= 2; ++jr) {
         const int rr = r + jr;
@@ -601,10 +608,23 @@ __global__ void __launch_bounds__(kNT) k_col(Args<T> a) {
   cpx<T>* B = A + a.Ny;
   cpx<T>* col = a.S + (long)blockIdx.x * a.Ny;
   const cpx<T>* Hc = a.H + (long)blockIdx.x * a.Ny;
+  // this thread's PSF spectrum values, loaded now so that their latency
+  // overlaps the column's load and forward transform
+  constexpr int kHr = kMaxFrame / kNT;
+  cpx<T> h[kHr];
+#pragma unroll
+  for (int t = 0; t < kHr; ++t) {
+    const int r = threadIdx.x + t * kNT;
+    h[t] = r < a.Ny ? Hc[r] : cpx<T>{0, 0};
+  }
   for (int r = threadIdx.x; r < a.Ny; r += blockDim.x) A[r] = r < a.ny ? col[r] : cpx<T>{0, 0};
   __syncthreads();
   cpx<T>* Z = fft_lds<T, false>(A, B, a.Ny, a.twy);
-  for (int r = threadIdx.x; r < a.Ny; r += blockDim.x) Z[r] = CONJ ? cmulc(Z[r], Hc[r]) : cmul(Z[r], Hc[r]);
+#pragma unroll
+  for (int t = 0; t < kHr; ++t) {
+    const int r = threadIdx.x + t * kNT;
+    if (r < a.Ny) Z[r] = CONJ ? cmulc(Z[r], h[t]) : cmul(Z[r], h[t]);
+  }
   __syncthreads();
   cpx<T>* Y = fft_lds<T, true>(Z, Z == A ? B : A, a.Ny, a.twy);
   for (int r = threadIdx.x; r < a.ny; r += blockDim.x) col[r] = Y[r];
@@ -832,9 +852,7 @@ static Layout make_layout(int nx, int ny, int nsub, int ns, int K, int interp, i
   sizes[n++] = c * (size_t)L.Nh * L.Ny;               // S
   sizes[n++] = 16 * (size_t)K * L.Nh;                 // T1
   if (solve) {
-    sizes[n++] = 4 * (size_t)(J * n2);                // cell
-    sizes[n++] = sz * (size_t)(J * n2);               // fx
-    sizes[n++] = sz * (size_t)(J * n2);               // fy
+    sizes[n++] = (sz == 8 ? 24 : 12) * (size_t)(J * n2);   // sub
     sizes[n++] = 4 * (size_t)I;                       // cnt
     sizes[n++] = 4 * (size_t)((I + kTile - 1) / kTile);   // tsum
     sizes[n++] = 4 * (size_t)(I + 1);                 // rowptr
@@ -877,9 +895,7 @@ static Args<T> bind(const Layout& L, unsigned char* ws, bool solve) {
   a.S = reinterpret_cast<cpx<T>*>(ws + L.off[i++]);
   a.T1 = reinterpret_cast<cpx<double>*>(ws + L.off[i++]);
   if (solve) {
-    a.cell = reinterpret_cast<int32_t*>(ws + L.off[i++]);
-    a.fx = reinterpret_cast<T*>(ws + L.off[i++]);
-    a.fy = reinterpret_cast<T*>(ws + L.off[i++]);
+    a.sub = reinterpret_cast<Sub<T>*>(ws + L.off[i++]);
     a.cnt = reinterpret_cast<int32_t*>(ws + L.off[i++]);
     a.tsum = reinterpret_cast<int32_t*>(ws + L.off[i++]);
     a.rowptr = reinterpret_cast<int32_t*>(ws + L.off[i++]);
