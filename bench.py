@@ -486,10 +486,20 @@ def large_main(args, torch, sl, synthgen):
     graph_ms = ga.elapsed_time(gb) / max(3, args.steps)
     graph_same = bool(torch.equal(gout["chi2"], out["chi2"]) and torch.equal(gout["s_corner"], out["s_corner"]))
     del graph
-    # L^T table entries: the four bilinear taps of every subpixel on the grid (the library's own trace)
+    # L^T table entries: the distinct nodes among the four bilinear taps of a pixel's subpixels, per pixel
+    # (the library merges a pixel's terms for one node), from the library's own trace
     uv = sl.lens_trace(lens.reshape(1, 7), sl.Grid(w.nx, w.ny, w.pix, w.nsub_model), [w.ns], w.half_width)
-    entries = 4 * int(torch.isfinite(uv.reshape(-1, 2)[:, 0]).sum().item())
-    del uv
+    uv = uv.reshape(w.nx * w.ny, w.nsub_model ** 2, 2)
+    ok = torch.isfinite(uv[..., 0])
+    c0 = torch.clamp(torch.nan_to_num(uv[..., 0]).floor().long(), max=w.ns - 2)
+    r0 = torch.clamp(torch.nan_to_num(uv[..., 1]).floor().long(), max=w.ns - 2)
+    nodes = torch.stack([(r0 + dr) * w.ns + c0 + dc for dr in (0, 1) for dc in (0, 1)], dim=-1)
+    nodes = torch.where(ok[..., None], nodes, torch.full_like(nodes, -1)).reshape(w.nx * w.ny, -1)
+    nodes, _ = torch.sort(nodes, dim=1)
+    first = torch.ones_like(nodes, dtype=torch.bool)
+    first[:, 1:] = nodes[:, 1:] != nodes[:, :-1]
+    entries = int((first & (nodes >= 0)).sum().item())
+    del uv, nodes, first
     res = {k: v.cpu().numpy() for k, v in out.items()}
     rec_cpu = None
     if not args.no_cpu_baseline:

@@ -28,8 +28,9 @@
 //
 // Reductions are FP64: each block writes its partial sum, and every
 // consumer adds the partials in block order, so each run gives the same
-// bits.  L^T sums each node's terms in ascending (pixel, subpixel, tap)
-// order (the table is sorted once per call).
+// bits.  L^T sums each node's terms in ascending pixel order (the table is
+// sorted once per call); with bilinear or nearest-neighbour L and at most
+// 2 x 2 subpixels a pixel's terms for one node are merged into one entry.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -334,13 +335,63 @@ __global__ void __launch_bounds__(kNT) k_trace(Args<T> a) {
     }
   }
   a.sub[j] = {cell, (T)fx, (T)fy};
-  if (cell < 0) return;
-  for (int q = 0; q < a.taps; ++q) {
-    int node;
-    double wt;
-    tap(a, j, q, node, wt);
-    if (node >= 0) atomicAdd(&a.cnt[node], 1);
+}
+
+// The table entries of one pixel.  With four taps and at most four
+// subpixels (bilinear or nearest, n <= 2) the up to 16 (node, weight) pairs
+// are merged per node, the weights added in (subpixel, tap) order: entry u of
+// the pixel has key pixel * kpp + u.  Otherwise every (subpixel, tap) pair
+// is an entry of its own, key (pixel n^2 + subpixel) taps + tap.  Returns
+// the number of entries; nd/wt/key hold them.
+constexpr int kMergeMax = 16;
+
+template <typename T>
+__device__ __forceinline__ bool merged(const Args<T>& a) { return a.taps == 4 && a.n2 <= 4; }
+
+template <typename T>
+__device__ int pixel_entries(const Args<T>& a, int pixel, int* nd, double* wt) {
+  int np = 0;
+  const long j0 = (long)pixel * a.n2;
+  for (int k = 0; k < a.n2; ++k)
+    for (int q = 0; q < 4; ++q) {
+      int node;
+      double w;
+      tap(a, j0 + k, q, node, w);
+      if (node < 0) continue;
+      int f = -1;
+      for (int u = 0; u < np; ++u)
+        if (nd[u] == node) f = u;
+      if (f >= 0) {
+        wt[f] += w;
+      } else {
+        nd[np] = node;
+        wt[np] = w;
+        ++np;
+      }
+    }
+  return np;
+}
+
+// Entries per node (one thread per pixel; integer atomics).
+template <typename T>
+__global__ void __launch_bounds__(kNT) k_count(Args<T> a) {
+  const int pixel = blockIdx.x * kNT + threadIdx.x;
+  if (pixel >= a.J) return;
+  if (merged(a)) {
+    int nd[kMergeMax];
+    double wt[kMergeMax];
+    const int np = pixel_entries(a, pixel, nd, wt);
+    for (int u = 0; u < np; ++u) atomicAdd(&a.cnt[nd[u]], 1);
+    return;
   }
+  const long j0 = (long)pixel * a.n2;
+  for (int k = 0; k < a.n2; ++k)
+    for (int q = 0; q < a.taps; ++q) {
+      int node;
+      double w;
+      tap(a, j0 + k, q, node, w);
+      if (node >= 0) atomicAdd(&a.cnt[node], 1);
+    }
 }
 
 // Exclusive scan of the entry counts into row starts, in three passes over
@@ -423,20 +474,34 @@ __global__ void __launch_bounds__(kNT) k_tile_write(Args<T> a) {
   }
 }
 
-// Table entries in arrival order (one thread per subpixel).
+// Table entries in arrival order (one thread per pixel, the entries of
+// pixel_entries or of every (subpixel, tap) pair).
 template <typename T>
 __global__ void __launch_bounds__(kNT) k_fill(Args<T> a) {
-  const long j = (long)blockIdx.x * kNT + threadIdx.x;
-  if (j >= (long)a.J * a.n2 || a.sub[j].cell < 0) return;
-  for (int q = 0; q < a.taps; ++q) {
-    int node;
-    double wt;
-    tap(a, j, q, node, wt);
-    if (node < 0) continue;
-    const int pos = atomicAdd(&a.cursor[node], 1);
-    a.key[pos] = (int32_t)(j * a.taps + q);
-    a.wtmp[pos] = (T)wt;
+  const int pixel = blockIdx.x * kNT + threadIdx.x;
+  if (pixel >= a.J) return;
+  if (merged(a)) {
+    int nd[kMergeMax];
+    double wt[kMergeMax];
+    const int np = pixel_entries(a, pixel, nd, wt);
+    for (int u = 0; u < np; ++u) {
+      const int pos = atomicAdd(&a.cursor[nd[u]], 1);
+      a.key[pos] = pixel * kMergeMax + u;
+      a.wtmp[pos] = (T)wt[u];
+    }
+    return;
   }
+  const long j0 = (long)pixel * a.n2;
+  for (int k = 0; k < a.n2; ++k)
+    for (int q = 0; q < a.taps; ++q) {
+      int node;
+      double w;
+      tap(a, j0 + k, q, node, w);
+      if (node < 0) continue;
+      const int pos = atomicAdd(&a.cursor[node], 1);
+      a.key[pos] = (int32_t)((j0 + k) * a.taps + q);
+      a.wtmp[pos] = (T)w;
+    }
 }
 
 // Each node's entries placed in ascending key order (one wave per node): the
@@ -455,6 +520,7 @@ __global__ void __launch_bounds__(kNT) k_sort(Args<T> a) {
   if (node >= a.I) return;
   const int b = a.rowptr[node], n = a.rowptr[node + 1] - b;
   const int32_t* keys = a.key + b;
+  const int kpp = merged(a) ? kMergeMax : a.n2 * a.taps;   // keys per pixel
   if (n <= kSortChunk) {
     int32_t* st = stage[wv];
     int mine[kPer], rank[kPer];
@@ -477,7 +543,7 @@ __global__ void __launch_bounds__(kNT) k_sort(Args<T> a) {
 #pragma unroll
     for (int t = 0; t < kPer; ++t) {
       const int e = lane + t * kWave;
-      if (e < n) a.lt[b + rank[t]] = {(mine[t] / a.taps) / a.n2, a.wtmp[b + e]};
+      if (e < n) a.lt[b + rank[t]] = {mine[t] / kpp, a.wtmp[b + e]};
     }
     return;
   }
@@ -485,7 +551,7 @@ __global__ void __launch_bounds__(kNT) k_sort(Args<T> a) {
     const int ke = keys[e];
     int rank = 0;
     for (int f = 0; f < n; ++f) rank += keys[f] < ke;
-    a.lt[b + rank] = {(ke / a.taps) / a.n2, a.wtmp[b + e]};
+    a.lt[b + rank] = {ke / kpp, a.wtmp[b + e]};
   }
 }
 
@@ -1015,11 +1081,12 @@ static int solve_impl(const sl_problem* pb, const double* lens, int ns, int n_it
   if (int e = spectrum(a, st)) return e;
   const long nsubpix = (long)a.J * a.n2;
   hipLaunchKernelGGL(k_trace<T>, dim3(nblk(nsubpix, kNT)), dim3(kNT), 0, st, a);
+  hipLaunchKernelGGL(k_count<T>, dim3(nblk(a.J, kNT)), dim3(kNT), 0, st, a);
   const unsigned tiles = nblk(a.I, kTile);
   hipLaunchKernelGGL(k_tile_sums<T>, dim3(tiles), dim3(kNT), 0, st, a);
   hipLaunchKernelGGL(k_tile_scan<T>, dim3(1), dim3(kNT), 0, st, a);
   hipLaunchKernelGGL(k_tile_write<T>, dim3(tiles), dim3(kNT), 0, st, a);
-  hipLaunchKernelGGL(k_fill<T>, dim3(nblk(nsubpix, kNT)), dim3(kNT), 0, st, a);
+  hipLaunchKernelGGL(k_fill<T>, dim3(nblk(a.J, kNT)), dim3(kNT), 0, st, a);
   hipLaunchKernelGGL(k_sort<T>, dim3(nblk(a.I, kNT / kWave)), dim3(kNT), 0, st, a);
   if (int e = check_launch("large solve set-up")) return e;
   // g = A^T d, p = g
