@@ -388,13 +388,15 @@ def large_bytes_per_iteration(w, entries, elem=4):
     """Algorithmic HBM bytes of one CGLS iteration of the large solve (sl_solve_large).
 
     Per iteration: the subpixel table read by the gather L p (cell int32 and
-    two fractions per subpixel: (4 + 2 elem) J n^2); two blurs, each writing,
-    reading, writing and reading the half spectrum of the ny image rows
-    (4 ny Nh 2 elem) and reading the PSF spectrum (Nh Ny 2 elem); the image
-    vectors q (written), e (read, written), q (read again) and w (written):
-    5 J elem; L^T over the node-major table (entries x (4 + elem)) and the row
-    starts (4 I), writing g (elem I); the update reading s, p, g and writing s,
-    p and the kept iterate (6 elem I).
+    two fractions per subpixel: (4 + 2 elem) J n^2); the half spectra of the
+    ny image rows (ny Nh complex values each) written by the row FFT of L p,
+    read and written by its column pass, read by the inverse rows that write
+    q's spectra, then the residual's spectra and q's read and the residual's
+    and the column output written by the B^T column pass, which the last
+    inverse rows read: ten such arrays, plus the PSF spectrum (Nh Ny) read
+    twice; w written (J elem); L^T over the node-major table (entries x
+    (4 + elem)) and its row starts (4 I), writing g (elem I); the update
+    reading s, p, g and writing s, p and the kept iterate (6 elem I).
     """
     J, I, n2 = w.nx * w.ny, w.ns * w.ns, w.nsub_model ** 2
     ck = (w.k_psf - 1) // 2
@@ -405,8 +407,8 @@ def large_bytes_per_iteration(w, entries, elem=4):
     while Ny < w.ny + ck:
         Ny *= 2
     Nh = Nx // 2 + 1
-    blur = 4 * w.ny * Nh * 2 * elem + Nh * Ny * 2 * elem
-    return ((4 + 2 * elem) * J * n2 + 2 * blur + 5 * J * elem + entries * (4 + elem) + 4 * I + elem * I
+    spectra = 10 * w.ny * Nh * 2 * elem + 2 * Nh * Ny * 2 * elem
+    return ((4 + 2 * elem) * J * n2 + spectra + J * elem + entries * (4 + elem) + 4 * I + elem * I
             + 6 * elem * I)
 
 
@@ -529,8 +531,9 @@ def large_main(args, torch, sl, synthgen):
            "corner_iterate": int(res["k_star"][0]) + 1,
            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
                         "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": None,
-                        "kernel": "one CGLS iteration: 8 kernels (row FFT + L p, column FFT x PSF, inverse rows, "
-                                  "row FFT + residual, column FFT x conj PSF, inverse rows, L^T, update)",
+                        "kernel": "one CGLS iteration: 7 kernels (row FFT + L p, column FFT x PSF, inverse rows "
+                                  "and q's row spectra, residual update + column FFT x conj PSF, inverse rows, L^T, "
+                                  "update)",
                         "algorithmic_bytes": abytes, "table_entries": entries},
            "cpu_baseline": rec_cpu}
     print(json.dumps(rec), flush=True)

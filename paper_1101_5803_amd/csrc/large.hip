@@ -7,16 +7,22 @@
 // grid-wide kernels per CGLS iteration rather than as one persistent block
 // per lens:
 //
-//   k_rowfwd   row FFTs of the image (with the gather L p, or with the
-//              residual update e -= alpha q)      one block per pair of rows
+//   k_rowfwd   row FFTs of L p (the gather fused)  one block per pair of rows
 //   k_col      column FFT, product with the PSF spectrum, inverse column FFT
 //                                                 one block per frequency column
-//   k_rowinv   inverse row FFTs (q = B L p with |q|^2, or B^T e)
-//                                                 one block per pair of rows
+//   k_rowinv   inverse row FFTs of q = B L p, cut to the image, |q|^2, and
+//              forward again: q's row spectra     one block per pair of rows
+//   k_col      the residual update e -= alpha q on the row spectra, |e|^2 by
+//              Parseval, and the columns of B^T e
+//   k_rowinv   inverse row FFTs: w = B^T e
 //   k_lt       L^T as a gather over a node-major table, with |g|^2
-//                                                 one thread per node
+//                                                 16 lanes per node
 //   k_update   s += alpha p, p = g + beta p, |s|^2, the iterate kept
 //                                                 one thread per node
+//
+// The residual e = d - A s lives only as row spectra: it starts as those of
+// d, and q enters them cut to the image (the frame's columns from nx on are
+// zero), so e stays the spectrum of an image row padded with zeros.
 //
 // Images are real, so two rows go through one complex FFT (row r as the real
 // part, row r + 1 as the imaginary part) and only the columns kx = 0..Nx/2
@@ -108,6 +114,8 @@ struct Args {
   cpx<double>* twdy;
   cpx<T>* H;            // [Nh][Ny] PSF spectrum / (Nx Ny)
   cpx<T>* S;            // [Nh][Ny] spectrum of the image in flight (rows < ny used in the row passes)
+  cpx<T>* E;            // [Nh][Ny] row spectra of the image residual e = d - A s (rows < ny)
+  cpx<T>* SQ;           // [Nh][Ny] row spectra of q = A p (rows < ny)
   cpx<double>* T1;      // [K][Nh] first stage of the PSF transform
   Sub<T>* sub;          // [J n^2] cell and fractions of each subpixel
   int32_t* cnt;         // [I] entries per node
@@ -117,8 +125,6 @@ struct Args {
   int32_t* key;         // [cap] (subpixel, tap) of each entry, in fill order
   T* wtmp;              // [cap]
   LtE<T>* lt;           // [cap] pixel and weight (with the 1/n^2 average), sorted within each node
-  T* q;                 // [J] A p
-  T* e;                 // [J] image residual d - A s
   T* w;                 // [J] B^T e
   T* s;                 // [I]
   T* p;
@@ -601,26 +607,33 @@ __device__ __forceinline__ double alpha_of(const Args<T>& a, int it) {
 }
 
 // ---------------------------------------------------------------- FFT passes
-enum { ROW_LP = 0, ROW_E = 1, ROW_D = 2, ROW_IMG = 3 };
+enum { ROW_LP = 0, ROW_D = 2, ROW_IMG = 3 };
+
+// Two real rows packed as one complex row z = y0 + i y1 in LDS, transformed:
+// their half spectra Y0[k] = (Z[k] + conj Z[N-k]) / 2 and
+// Y1[k] = -i (Z[k] - conj Z[N-k]) / 2 go to dst[kx * Ny + r0] and r0 + 1.
+template <typename T>
+__device__ __forceinline__ void split_store(const cpx<T>* Z, cpx<T>* dst, int Nx, int Nh, int Ny, int r0, bool two) {
+  for (int k = threadIdx.x; k < Nh; k += blockDim.x) {
+    const cpx<T> zk = Z[k], zm = Z[(Nx - k) & (Nx - 1)];
+    const T h = (T)0.5;
+    cpx<T>* d = dst + (long)k * Ny + r0;
+    d[0] = {h * (zk.x + zm.x), h * (zk.y - zm.y)};
+    if (two) d[1] = {h * (zk.y + zm.y), h * (zm.x - zk.x)};
+  }
+}
 
 // Forward row FFTs of rows r0 = 2 blockIdx.x and r0 + 1 of an image, packed
-// as one complex row, split into the two half spectra and stored at
-// S[kx * Ny + r].  The image row is L p (ROW_LP), the updated residual
-// e -= alpha q written back with its |e|^2 partial (ROW_E), the data d
-// copied into e (ROW_D), or a given image (ROW_IMG, `src`).
+// as one complex row, split into the two half spectra.  The image row is
+// L p (ROW_LP, into S), the data d (ROW_D, into E: the residual of s = 0),
+// or a given image (ROW_IMG, `src`, into S).
 template <typename T, int MODE>
-__global__ void __launch_bounds__(kRowNT) k_rowfwd(Args<T> a, const T* __restrict__ src, int it) {
+__global__ void __launch_bounds__(kRowNT) k_rowfwd(Args<T> a, const T* __restrict__ src) {
   extern __shared__ __align__(16) unsigned char smem[];
   cpx<T>* A = reinterpret_cast<cpx<T>*>(smem);
   cpx<T>* B = A + a.Nx;
   const int r0 = 2 * blockIdx.x, r1 = r0 + 1;
   const bool two = r1 < a.ny;
-  double alpha = 0.0;
-  if (MODE == ROW_E) {
-    alpha = alpha_of(a, it);
-    if (blockIdx.x == 0 && threadIdx.x == 0) a.alpha[it] = alpha;   // the update uses the same value
-  }
-  double ee = 0.0;
   for (int c = threadIdx.x; c < a.Nx; c += blockDim.x) {
     T v0 = 0, v1 = 0;
     if (c < a.nx) {
@@ -628,22 +641,9 @@ __global__ void __launch_bounds__(kRowNT) k_rowfwd(Args<T> a, const T* __restric
       if (MODE == ROW_LP) {
         v0 = gather_L(a, src, (int)j0);
         if (two) v1 = gather_L(a, src, (int)j1);
-      } else if (MODE == ROW_E) {
-        v0 = a.e[j0] - (T)alpha * a.q[j0];
-        a.e[j0] = v0;
-        ee += (double)v0 * (double)v0;
-        if (two) {
-          v1 = a.e[j1] - (T)alpha * a.q[j1];
-          a.e[j1] = v1;
-          ee += (double)v1 * (double)v1;
-        }
       } else if (MODE == ROW_D) {
         v0 = (T)a.d[j0];
-        a.e[j0] = v0;
-        if (two) {
-          v1 = (T)a.d[j1];
-          a.e[j1] = v1;
-        }
+        if (two) v1 = (T)a.d[j1];
       } else {
         v0 = src[j0];
         if (two) v1 = src[j1];
@@ -651,29 +651,28 @@ __global__ void __launch_bounds__(kRowNT) k_rowfwd(Args<T> a, const T* __restric
     }
     A[c] = {v0, v1};
   }
-  if (MODE == ROW_E) put_partial(a, ee, P_EE, it);   // contains the barrier the FFT needs
-  else __syncthreads();
+  __syncthreads();
   const cpx<T>* Z = fft_lds<T, false>(A, B, a.Nx, a.twx);
-  // Y0[k] = (Z[k] + conj Z[N-k]) / 2, Y1[k] = -i (Z[k] - conj Z[N-k]) / 2
-  for (int k = threadIdx.x; k < a.Nh; k += blockDim.x) {
-    const cpx<T> zk = Z[k], zm = Z[(a.Nx - k) & (a.Nx - 1)];
-    const T h = (T)0.5;
-    cpx<T>* dst = a.S + (long)k * a.Ny + r0;
-    dst[0] = {h * (zk.x + zm.x), h * (zk.y - zm.y)};
-    if (two) dst[1] = {h * (zk.y + zm.y), h * (zm.x - zk.x)};
-  }
+  split_store(Z, MODE == ROW_D ? a.E : a.S, a.Nx, a.Nh, a.Ny, r0, two);
 }
 
-// Column kx = blockIdx.x of the half spectrum: FFT over the Ny rows (rows
+enum { COL_S = 0, COL_E = 1, COL_E_UPD = 2 };
+
+// Column kx = blockIdx.x of a half spectrum: FFT over the Ny rows (rows
 // >= ny are zero), product with the PSF spectrum (conjugated for B^T), inverse
-// FFT, rows < ny stored back.
-template <typename T, bool CONJ>
-__global__ void __launch_bounds__(kNT) k_col(Args<T> a) {
+// FFT, rows < ny stored to S.  The input column is S's own (COL_S), E's
+// (COL_E), or E's after the residual update of iteration it (COL_E_UPD):
+// E -= alpha SQ, written back, with the |e|^2 partial of this column by
+// Parseval's identity on the zero-padded real rows (weight 1 for kx = 0 and
+// Nx/2, 2 otherwise, over Nx).
+template <typename T, bool CONJ, int MODE>
+__global__ void __launch_bounds__(kNT) k_col(Args<T> a, int it) {
   extern __shared__ __align__(16) unsigned char smem[];
   cpx<T>* A = reinterpret_cast<cpx<T>*>(smem);
   cpx<T>* B = A + a.Ny;
-  cpx<T>* col = a.S + (long)blockIdx.x * a.Ny;
-  const cpx<T>* Hc = a.H + (long)blockIdx.x * a.Ny;
+  const long base = (long)blockIdx.x * a.Ny;
+  cpx<T>* col = a.S + base;
+  const cpx<T>* Hc = a.H + base;
   // this thread's PSF spectrum values, loaded now so that their latency
   // overlaps the column's load and forward transform
   constexpr int kHr = kMaxFrame / kNT;
@@ -683,8 +682,35 @@ __global__ void __launch_bounds__(kNT) k_col(Args<T> a) {
     const int r = threadIdx.x + t * kNT;
     h[t] = r < a.Ny ? Hc[r] : cpx<T>{0, 0};
   }
-  for (int r = threadIdx.x; r < a.Ny; r += blockDim.x) A[r] = r < a.ny ? col[r] : cpx<T>{0, 0};
-  __syncthreads();
+  double alpha = 0.0;
+  if (MODE == COL_E_UPD) {
+    alpha = alpha_of(a, it);
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.alpha[it] = alpha;   // the update uses the same value
+  }
+  double ee = 0.0;
+  for (int r = threadIdx.x; r < a.Ny; r += blockDim.x) {
+    cpx<T> v = {0, 0};
+    if (r < a.ny) {
+      if (MODE == COL_S) {
+        v = col[r];
+      } else {
+        v = a.E[base + r];
+        if (MODE == COL_E_UPD) {
+          const cpx<T> q = a.SQ[base + r];
+          v = {v.x - (T)alpha * q.x, v.y - (T)alpha * q.y};
+          a.E[base + r] = v;
+          ee += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+        }
+      }
+    }
+    A[r] = v;
+  }
+  if (MODE == COL_E_UPD) {
+    const double wk = (blockIdx.x == 0 || blockIdx.x == a.Nx / 2) ? 1.0 : 2.0;
+    put_partial(a, ee * wk / a.Nx, P_EE, it);   // contains the barrier the FFT needs
+  } else {
+    __syncthreads();
+  }
   cpx<T>* Z = fft_lds<T, false>(A, B, a.Ny, a.twy);
 #pragma unroll
   for (int t = 0; t < kHr; ++t) {
@@ -701,7 +727,9 @@ enum { OUT_Q = 0, OUT_W = 1, OUT_IMG = 2 };
 // Inverse row FFTs of rows r0 = 2 blockIdx.x and r0 + 1 from their half
 // spectra (the other half by conjugate symmetry, as the rows are real):
 // Z[k] = Q0[k] + i Q1[k], inverse FFT, row r0 the real and row r0 + 1 the
-// imaginary part.  OUT_Q: q with its |q|^2 partial; OUT_W: w; OUT_IMG: dst.
+// imaginary part.  OUT_W: w; OUT_IMG: dst.  OUT_Q: q = A p is kept in the
+// spectral domain: its |q|^2 partial, then the rows cut to the image (zero
+// from column nx on) and transformed forward again into SQ.
 template <typename T, int OUT>
 __global__ void __launch_bounds__(kRowNT) k_rowinv(Args<T> a, T* __restrict__ dst, int it) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -722,16 +750,28 @@ __global__ void __launch_bounds__(kRowNT) k_rowinv(Args<T> a, T* __restrict__ ds
     A[k] = {q0.x - q1.y, q0.y + q1.x};
   }
   __syncthreads();
-  const cpx<T>* z = fft_lds<T, true>(A, B, a.Nx, a.twx);
-  T* out = OUT == OUT_Q ? a.q : (OUT == OUT_W ? a.w : dst);
-  double qq = 0.0;
-  for (int c = threadIdx.x; c < a.nx; c += blockDim.x) {
-    const T v0 = z[c].x, v1 = z[c].y;
-    out[(long)r0 * a.nx + c] = v0;
-    if (two) out[(long)r1 * a.nx + c] = v1;
-    if (OUT == OUT_Q) qq += (double)v0 * (double)v0 + (two ? (double)v1 * (double)v1 : 0.0);
+  cpx<T>* z = fft_lds<T, true>(A, B, a.Nx, a.twx);
+  if (OUT == OUT_Q) {
+    double qq = 0.0;
+    for (int c = threadIdx.x; c < a.Nx; c += blockDim.x) {
+      if (c < a.nx) {
+        const T v0 = z[c].x, v1 = two ? z[c].y : (T)0;
+        z[c] = {v0, v1};
+        qq += (double)v0 * (double)v0 + (double)v1 * (double)v1;
+      } else {
+        z[c] = {0, 0};
+      }
+    }
+    put_partial(a, qq, P_QQ, it);   // its barrier orders the cut before the transform
+    const cpx<T>* Zq = fft_lds<T, false>(z, z == A ? B : A, a.Nx, a.twx);
+    split_store(Zq, a.SQ, a.Nx, a.Nh, a.Ny, r0, two);
+    return;
   }
-  if (OUT == OUT_Q) put_partial(a, qq, P_QQ, it);
+  T* out = OUT == OUT_W ? a.w : dst;
+  for (int c = threadIdx.x; c < a.nx; c += blockDim.x) {
+    out[(long)r0 * a.nx + c] = z[c].x;
+    if (two) out[(long)r1 * a.nx + c] = z[c].y;
+  }
 }
 
 // ---------------------------------------------------------------- source-side kernels
@@ -830,7 +870,7 @@ __global__ void __launch_bounds__(kLtNT) k_final(Args<T> a, sl_result out) {
     const int k = j >> 1;
     const bool ee = (j & 1) == 0;
     const double* p = part_of(a, ee ? P_EE : P_SS, k);
-    const int n = ee ? a.nb_row : a.nb_node;
+    const int n = ee ? a.Nh : a.nb_node;   // |e|^2 partials: one per frequency column
     double v = 0.0;
     for (int i = lane; i < n; i += kWave) v += p[i];
     v = wave_sum(v);
@@ -907,7 +947,7 @@ static Layout make_layout(int nx, int ny, int nsub, int ns, int K, int interp, i
   L.cap = J * n2 * L.taps;
   const size_t c = 2 * sz;   // one complex element
   const int nb_row = (ny + 1) / 2;
-  const int maxb = nb_row > kMaxParts ? nb_row : kMaxParts;
+  const int maxb = std::max(std::max(nb_row, L.Nh), kMaxParts);   // row blocks, column blocks, node blocks
   size_t sizes[32];
   int n = 0;
   sizes[n++] = c * L.Nx;                              // twx
@@ -926,8 +966,8 @@ static Layout make_layout(int nx, int ny, int nsub, int ns, int K, int interp, i
     sizes[n++] = 4 * (size_t)L.cap;                   // key
     sizes[n++] = sz * (size_t)L.cap;                  // wtmp
     sizes[n++] = (sz == 8 ? 16 : 8) * (size_t)L.cap;  // lt
-    sizes[n++] = sz * (size_t)J;                      // q
-    sizes[n++] = sz * (size_t)J;                      // e
+    sizes[n++] = c * (size_t)L.Nh * L.Ny;             // E
+    sizes[n++] = c * (size_t)L.Nh * L.Ny;             // SQ
     sizes[n++] = sz * (size_t)J;                      // w
     sizes[n++] = sz * (size_t)I;                      // s
     sizes[n++] = sz * (size_t)I;                      // p
@@ -969,8 +1009,8 @@ static Args<T> bind(const Layout& L, unsigned char* ws, bool solve) {
     a.key = reinterpret_cast<int32_t*>(ws + L.off[i++]);
     a.wtmp = reinterpret_cast<T*>(ws + L.off[i++]);
     a.lt = reinterpret_cast<LtE<T>*>(ws + L.off[i++]);
-    a.q = reinterpret_cast<T*>(ws + L.off[i++]);
-    a.e = reinterpret_cast<T*>(ws + L.off[i++]);
+    a.E = reinterpret_cast<cpx<T>*>(ws + L.off[i++]);
+    a.SQ = reinterpret_cast<cpx<T>*>(ws + L.off[i++]);
     a.w = reinterpret_cast<T*>(ws + L.off[i++]);
     a.s = reinterpret_cast<T*>(ws + L.off[i++]);
     a.p = reinterpret_cast<T*>(ws + L.off[i++]);
@@ -994,9 +1034,10 @@ static inline unsigned nblk(long n, int nt) { return (unsigned)((n + nt - 1) / n
 
 template <typename T>
 static int set_lds(size_t bytes) {
-  const void* ks[] = {(const void*)k_rowfwd<T, ROW_LP>, (const void*)k_rowfwd<T, ROW_E>,
-                      (const void*)k_rowfwd<T, ROW_D>,  (const void*)k_rowfwd<T, ROW_IMG>,
-                      (const void*)k_col<T, false>,     (const void*)k_col<T, true>,
+  const void* ks[] = {(const void*)k_rowfwd<T, ROW_LP>,       (const void*)k_rowfwd<T, ROW_D>,
+                      (const void*)k_rowfwd<T, ROW_IMG>,      (const void*)k_col<T, false, COL_S>,
+                      (const void*)k_col<T, true, COL_S>,     (const void*)k_col<T, true, COL_E>,
+                      (const void*)k_col<T, true, COL_E_UPD>,
                       (const void*)k_rowinv<T, OUT_Q>,  (const void*)k_rowinv<T, OUT_W>,
                       (const void*)k_rowinv<T, OUT_IMG>};
   for (const void* k : ks) SL_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
@@ -1016,10 +1057,10 @@ static int spectrum(const Args<T>& a, hipStream_t st) {
 
 // One blur of the image in flight: row pass (launched by the caller), column
 // pass, inverse row pass.
-template <typename T, bool CONJ, int OUT>
+template <typename T, bool CONJ, int COL, int OUT>
 static void blur_tail(const Args<T>& a, T* dst, int it, hipStream_t st) {
   const size_t lx = 2 * sizeof(cpx<T>) * a.Nx, ly = 2 * sizeof(cpx<T>) * a.Ny;
-  hipLaunchKernelGGL((k_col<T, CONJ>), dim3(a.Nh), dim3(kNT), ly, st, a);
+  hipLaunchKernelGGL((k_col<T, CONJ, COL>), dim3(a.Nh), dim3(kNT), ly, st, a, it);
   hipLaunchKernelGGL((k_rowinv<T, OUT>), dim3(a.nb_row), dim3(kRowNT), lx, st, a, dst, it);
 }
 
@@ -1037,11 +1078,11 @@ static int fft_blur_impl(int transpose, int nx, int ny, const double* psf, int k
   if (int e = set_lds<T>(2 * sizeof(cpx<T>) * (a.Nx > a.Ny ? a.Nx : a.Ny))) return e;
   if (int e = spectrum(a, st)) return e;
   hipLaunchKernelGGL((k_rowfwd<T, ROW_IMG>), dim3(a.nb_row), dim3(kRowNT), 2 * sizeof(cpx<T>) * a.Nx, st, a,
-                     static_cast<const T*>(in), 0);
+                     static_cast<const T*>(in));
   if (transpose)
-    blur_tail<T, true, OUT_IMG>(a, static_cast<T*>(out), 0, st);
+    blur_tail<T, true, COL_S, OUT_IMG>(a, static_cast<T*>(out), 0, st);
   else
-    blur_tail<T, false, OUT_IMG>(a, static_cast<T*>(out), 0, st);
+    blur_tail<T, false, COL_S, OUT_IMG>(a, static_cast<T*>(out), 0, st);
   return check_launch("fft blur");
 }
 
@@ -1071,8 +1112,7 @@ static int solve_impl(const sl_problem* pb, const double* lens, int ns, int n_it
   a.nb_row = (g.ny + 1) / 2;
   a.nb_node = (int)std::min<long>(nblk(a.I, kNT), kMaxParts);
   a.nb_lt = (int)std::min<long>(nblk((long)a.I * kLtG, kLtNT), kMaxParts);
-  a.max_blocks = a.nb_row > a.nb_node ? a.nb_row : a.nb_node;
-  if (a.nb_lt > a.max_blocks) a.max_blocks = a.nb_lt;
+  a.max_blocks = std::max(std::max(a.nb_row, a.Nh), std::max(a.nb_node, a.nb_lt));
   const size_t lx = 2 * sizeof(cpx<T>) * a.Nx;
   if (int e = set_lds<T>(2 * sizeof(cpx<T>) * (a.Nx > a.Ny ? a.Nx : a.Ny))) return e;
   // counters start at zero (a fill kernel: the call may be captured in a graph)
@@ -1090,15 +1130,14 @@ static int solve_impl(const sl_problem* pb, const double* lens, int ns, int n_it
   hipLaunchKernelGGL(k_sort<T>, dim3(nblk(a.I, kNT / kWave)), dim3(kNT), 0, st, a);
   if (int e = check_launch("large solve set-up")) return e;
   // g = A^T d, p = g
-  hipLaunchKernelGGL((k_rowfwd<T, ROW_D>), dim3(a.nb_row), dim3(kRowNT), lx, st, a, (const T*)nullptr, 0);
-  blur_tail<T, true, OUT_W>(a, nullptr, 0, st);
+  hipLaunchKernelGGL((k_rowfwd<T, ROW_D>), dim3(a.nb_row), dim3(kRowNT), lx, st, a, (const T*)nullptr);
+  blur_tail<T, true, COL_E, OUT_W>(a, nullptr, 0, st);
   hipLaunchKernelGGL(k_lt<T>, dim3(a.nb_lt), dim3(kLtNT), 0, st, a, n_iter);
   hipLaunchKernelGGL(k_start<T>, dim3(a.nb_node), dim3(kNT), 0, st, a);
   for (int it = 0; it < n_iter; ++it) {
-    hipLaunchKernelGGL((k_rowfwd<T, ROW_LP>), dim3(a.nb_row), dim3(kRowNT), lx, st, a, (const T*)a.p, it);
-    blur_tail<T, false, OUT_Q>(a, nullptr, it, st);                      // q = A p, |q|^2
-    hipLaunchKernelGGL((k_rowfwd<T, ROW_E>), dim3(a.nb_row), dim3(kRowNT), lx, st, a, (const T*)nullptr, it);
-    blur_tail<T, true, OUT_W>(a, nullptr, it, st);                       // w = B^T e
+    hipLaunchKernelGGL((k_rowfwd<T, ROW_LP>), dim3(a.nb_row), dim3(kRowNT), lx, st, a, (const T*)a.p);
+    blur_tail<T, false, COL_S, OUT_Q>(a, nullptr, it, st);               // spectra of q = A p, |q|^2
+    blur_tail<T, true, COL_E_UPD, OUT_W>(a, nullptr, it, st);            // e -= alpha q, |e|^2; w = B^T e
     hipLaunchKernelGGL(k_lt<T>, dim3(a.nb_lt), dim3(kLtNT), 0, st, a, it);
     hipLaunchKernelGGL(k_update<T>, dim3(a.nb_node), dim3(kNT), 0, st, a, it);
   }
