@@ -135,7 +135,7 @@ struct Args {
   double* alpha;        // [n_iter]: step length of iteration k (0 when it did not move)
   int32_t* done;        // [n_iter + 1]: the iteration stopped before iteration k
   int32_t* upd;         // [n_iter]: iteration k updated s
-  int32_t* flags;       // [2]: invalid genome (flags[1] unused)
+  int32_t* flags;       // [1]: invalid genome
   int n_iter, max_blocks, nb_row, nb_node, nb_lt;
 };
 
@@ -978,7 +978,7 @@ static Layout make_layout(int nx, int ny, int nsub, int ns, int K, int interp, i
     sizes[n++] = 8 * (size_t)n_iter;                  // alpha
     sizes[n++] = 4 * (size_t)(n_iter + 1);            // done
     sizes[n++] = 4 * (size_t)n_iter;                  // upd
-    sizes[n++] = 4 * 2;                               // flags
+    sizes[n++] = 4;                                   // flags
   }
   size_t off = 0;
   for (int i = 0; i < n; ++i) {
@@ -1117,7 +1117,7 @@ static int solve_impl(const sl_problem* pb, const double* lens, int ns, int n_it
   if (int e = set_lds<T>(2 * sizeof(cpx<T>) * (a.Nx > a.Ny ? a.Nx : a.Ny))) return e;
   // counters start at zero (a fill kernel: the call may be captured in a graph)
   hipLaunchKernelGGL(k_zero_int<T>, dim3(nblk(a.I, kNT)), dim3(kNT), 0, st, a.cnt, (long)a.I);
-  hipLaunchKernelGGL(k_zero_int<T>, dim3(1), dim3(kNT), 0, st, a.flags, 2L);
+  hipLaunchKernelGGL(k_zero_int<T>, dim3(1), dim3(kNT), 0, st, a.flags, 1L);
   if (int e = spectrum(a, st)) return e;
   const long nsubpix = (long)a.J * a.n2;
   hipLaunchKernelGGL(k_trace<T>, dim3(nblk(nsubpix, kNT)), dim3(kNT), 0, st, a);

@@ -100,7 +100,7 @@ def _solver(sl, d, sigma, psf, w, dtype, interp="bilinear"):
                      interp=interp)
 
 
-@pytest.mark.parametrize("interp", ["bilinear", "bicubic"])
+@pytest.mark.parametrize("interp", ["bilinear", "bicubic", "nearest"])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_large_solve_medium_vs_oracle(sl, prec, interp):
     w, lens, d, sigma, psf = _medium()
