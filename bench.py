@@ -488,6 +488,17 @@ def large_main(args, torch, sl, synthgen):
     graph_ms = ga.elapsed_time(gb) / max(3, args.steps)
     graph_same = bool(torch.equal(gout["chi2"], out["chi2"]) and torch.equal(gout["s_corner"], out["s_corner"]))
     del graph
+    # the same solve in FP64 throughout: its time, and how far the FP32 corner chi^2 lies from it
+    s64 = sl.Solver(torch.tensor(z["d"].astype(np.float64), device=dev), float(z["sigma"]),
+                    torch.tensor(z["psf"], device=dev), sl.Grid(w.nx, w.ny, w.pix, w.nsub_model), w.half_width,
+                    reg=w.reg, dtype=torch.float64)
+    ms64, out64 = _time_large(torch, s64, lens, w.ns, n_iter, max(3, args.steps))
+    c32, c64 = out["chi2"].cpu().numpy()[0], out64["chi2"].cpu().numpy()[0]
+    k32, k64 = int(out["k_star"].cpu().numpy()[0]), int(out64["k_star"].cpu().numpy()[0])
+    fp64 = {"ms_per_solve": round(ms64, 3), "corner_iterate": k64 + 1,
+            "chi2_rel_diff_fp32_vs_fp64_per_iterate_max": float(np.max(np.abs(c32 - c64) / c64)),
+            "chi2_rel_diff_first_10_iterates_max": float(np.max(np.abs(c32[:10] - c64[:10]) / c64[:10]))}
+    del s64, out64
     # L^T table entries: the distinct nodes among the four bilinear taps of a pixel's subpixels, per pixel
     # (the library merges a pixel's terms for one node), from the library's own trace
     uv = sl.lens_trace(lens.reshape(1, 7), sl.Grid(w.nx, w.ny, w.pix, w.nsub_model), [w.ns], w.half_width)
@@ -529,6 +540,7 @@ def large_main(args, torch, sl, synthgen):
            "graph_ms_per_solve": round(graph_ms, 3), "graph_matches_eager": graph_same,
            "setup_ms": round(ms1 - it_ms, 3),
            "corner_iterate": int(res["k_star"][0]) + 1,
+           "fp64": fp64,
            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
                         "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": None,
                         "kernel": "one CGLS iteration: 7 kernels (row FFT + L p, column FFT x PSF, inverse rows "

@@ -312,8 +312,8 @@ __device__ __forceinline__ void tap(const Args<T>& a, long j, int q, int& node, 
   wt = keys(fabs(fy - jr)) * keys(fabs(fx - ic)) / a.n2;
 }
 
-// Ray trace of every subpixel (Eq. 1, Eqs. 10-11, Sec. 2.2) into the cell
-// table, and the number of table entries of each node.
+// Ray trace of every subpixel (Eq. 1, Eqs. 10-11, Sec. 2.2) into the
+// subpixel table (cell and fractions).
 template <typename T>
 __global__ void __launch_bounds__(kNT) k_trace(Args<T> a) {
   const long j = (long)blockIdx.x * kNT + threadIdx.x;
