@@ -126,6 +126,15 @@ struct Args {
   T* wtmp;              // [cap]
   LtE<T>* lt;           // [cap] pixel and weight (with the 1/n^2 average), sorted within each node
   T* w;                 // [J] B^T e
+  // tiled blur (FP32, PSF side <= 65): overlap-save on 128 x 128 tiles
+  T* y;                 // [J] L p
+  T* q;                 // [J] B L p
+  T* e0;                // [J] image residual, two buffers used in turn
+  T* e1;
+  cpx<T>* Ht;           // [65][128] PSF spectrum on the tile / 128^2
+  cpx<T>* twt;          // [128] exp(-2 pi i m / 128)
+  cpx<double>* T1t;     // [K][65] first stage of the tile's PSF transform
+  int tiled, tiles_x, tiles_y, nb_qq, nb_ee;
   T* s;                 // [I]
   T* p;
   T* g;
@@ -601,7 +610,7 @@ __device__ __forceinline__ T gather_L(const Args<T>& a, const T* __restrict__ x,
 // (every thread of the block calls it: barriers)
 template <typename T>
 __device__ __forceinline__ double alpha_of(const Args<T>& a, int it) {
-  const double qq = block_total(part_of(a, P_QQ, it), a.nb_row);
+  const double qq = block_total(part_of(a, P_QQ, it), a.nb_qq);
   if (a.done[it]) return 0.0;
   return qq > 0.0 ? a.gg[it] / qq : 0.0;
 }
@@ -774,6 +783,269 @@ __global__ void __launch_bounds__(kRowNT) k_rowinv(Args<T> a, T* __restrict__ ds
   }
 }
 
+// ---------------------------------------------------------------- tiled blur
+// Overlap-save on 128 x 128 tiles (FP32, PSF side <= 65): output tile (ty, tx)
+// owns the 64 x 64 pixels from (64 ty, 64 tx); its input is the 128 x 128
+// region 32 pixels wider on every side (zero outside the image), on which the
+// circular convolution equals the zero-padded one for the owned pixels.  One
+// block per tile runs the whole 2-D transform in LDS: two real rows packed per
+// complex row FFT, their half spectra (65 columns) transformed along the
+// columns, the product with the tile's PSF spectrum, and back.  One launch per
+// blur instead of three passes through HBM.
+constexpr int kTN = 128;                      // tile side (FFT length)
+constexpr int kTV = 64;                       // owned outputs per side
+constexpr int kTHalo = (kTN - kTV) / 2;       // 32: PSF half-width it allows
+constexpr int kTH = kTN / 2 + 1;              // 65 half-spectrum columns
+constexpr int kTBuf = kTH * kTN;              // complex elements per LDS buffer
+constexpr int kTNT = 1024;
+
+// One Stockham stage (span NS, radix R) of NB independent length-kTN FFTs at
+// x[b * LD + i] into y (row stride LD): the butterflies of fft_lds on every row at once,
+// every operand of a thread's butterflies loaded before any is written, the
+// twiddles from LDS.  HM = 1 (2) multiplies each input by H (conj H) at the
+// same index first: the PSF product fused into the first inverse stage.
+template <typename T, bool INV, int NB, int LD, int NS, int R, int HM>
+__device__ __forceinline__ void tile_stage(const cpx<T>* __restrict__ x, cpx<T>* __restrict__ y, const cpx<T>* tw,
+                                           const cpx<T>* __restrict__ H) {
+  constexpr int NBF = kTN / R, STEP = kTN / (NS * R), ITEMS = NB * NBF;
+  constexpr int U = (ITEMS + kTNT - 1) / kTNT;
+  cpx<T> v[U][R];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int wi = threadIdx.x + u * kTNT;
+    if (ITEMS % kTNT == 0 || wi < ITEMS) {
+      const int b = wi / NBF, j = wi - b * NBF;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[u][r] = x[b * LD + j + r * NBF];
+      if (HM) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const cpx<T> h = H[b * kTN + j + r * NBF];
+          v[u][r] = HM == 1 ? cmul(v[u][r], h) : cmulc(v[u][r], h);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int wi = threadIdx.x + u * kTNT;
+    if (ITEMS % kTNT == 0 || wi < ITEMS) {
+      const int b = wi / NBF, j = wi - b * NBF;
+      const int k = j & (NS - 1);
+      cpx<T>* o_ = y + b * LD + (j - k) * R + k;
+      if (NS > 1 && k) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[u][r] = INV ? cmulc(v[u][r], tw[r * k * STEP]) : cmul(v[u][r], tw[r * k * STEP]);
+      }
+      if (R == 4) {
+        const cpx<T> t0 = cadd(v[u][0], v[u][2]), t1 = csub(v[u][0], v[u][2]);
+        const cpx<T> t2 = cadd(v[u][1], v[u][3]), d = csub(v[u][1], v[u][3]);
+        const cpx<T> t3 = INV ? cpx<T>{-d.y, d.x} : cpx<T>{d.y, -d.x};
+        o_[0] = cadd(t0, t2);
+        o_[NS] = cadd(t1, t3);
+        o_[2 * NS] = csub(t0, t2);
+        o_[3 * NS] = csub(t1, t3);
+      } else {
+        o_[0] = cadd(v[u][0], v[u][1]);
+        o_[NS] = csub(v[u][0], v[u][1]);
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// NB length-128 FFTs (radix 4, 4, 4, 2) from x (row stride LD), scratch y;
+// the result ends in x.
+template <typename T, bool INV, int NB, int LD, int HM = 0>
+__device__ __forceinline__ void fft_tile(cpx<T>* x, cpx<T>* y, const cpx<T>* tw, const cpx<T>* __restrict__ H = nullptr) {
+  static_assert(kTN == 128, "stage list is for length 128");
+  static_assert(HM == 0 || LD == kTN, "the PSF spectrum is stored with row stride 128");
+  tile_stage<T, INV, NB, LD, 1, 4, HM>(x, y, tw, H);
+  tile_stage<T, INV, NB, LD, 4, 4, 0>(y, x, tw, nullptr);
+  tile_stage<T, INV, NB, LD, 16, 4, 0>(x, y, tw, nullptr);
+  tile_stage<T, INV, NB, LD, 64, 2, 0>(y, x, tw, nullptr);
+}
+
+// Row stride of the packed-row buffers: one element of padding, so that the
+// transposes between packed rows and column-major half spectra (lanes along
+// the packed rows) meet distinct LDS banks.
+constexpr int kTLD = kTN + 1;
+static_assert(kTN / 2 * kTLD <= kTBuf, "packed rows fit a buffer");
+
+enum { TILE_B = 0, TILE_BT0 = 1, TILE_BT = 2 };
+
+// One tile of a blur.  TILE_B: q = B y on the owned pixels, with the block's
+// |q|^2 partial.  TILE_BT0: w = B^T e0 (e0 = d).  TILE_BT: the residual
+// update e_out = e_in - alpha q (alpha of iteration it; written on the owned
+// pixels, recomputed on the halo), the block's |e|^2 partial, and
+// w = B^T e_out.  Only the packed rows that hold owned pixels (16..47) take
+// the inverse row transform.  Packed rows are kept with row stride kTLD,
+// column-major half spectra with stride 128.
+template <typename T, int MODE>
+__global__ void __launch_bounds__(kTNT) k_tile(Args<T> a, const T* __restrict__ e_in, T* __restrict__ e_out, int it) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ cpx<T> tw[kTN];
+  cpx<T>* X = reinterpret_cast<cpx<T>*>(smem);
+  cpx<T>* Y = X + kTBuf;
+  const int ty = blockIdx.x / a.tiles_x, tx = blockIdx.x - ty * a.tiles_x;
+  const int y0 = ty * kTV - kTHalo, x0 = tx * kTV - kTHalo;   // image position of tile element (0, 0)
+  if (threadIdx.x < kTN) tw[threadIdx.x] = a.twt[threadIdx.x];
+  double alpha = 0.0;
+  if (MODE == TILE_BT) {
+    alpha = alpha_of(a, it);
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.alpha[it] = alpha;   // the update uses the same value
+  }
+  // load: packed row pr holds tile rows 2 pr (real part) and 2 pr + 1 (imaginary part);
+  // thread t takes column t mod 128 of packed rows t / 128 + 8 u
+  constexpr int LU = kTN * kTN / 2 / kTNT;
+  const int c = threadIdx.x & (kTN - 1), pr0 = threadIdx.x / kTN;
+  const int cc = x0 + c;
+  const bool col_in = cc >= 0 && cc < a.nx;
+  T v[LU][2], qv[LU][2];
+#pragma unroll
+  for (int u = 0; u < LU; ++u) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int r = y0 + 2 * (pr0 + 8 * u) + h;
+      const bool in = col_in && r >= 0 && r < a.ny;
+      const long j = (long)r * a.nx + cc;
+      const T* src = MODE == TILE_B ? a.y : e_in;
+      v[u][h] = in ? src[j] : (T)0;
+      if (MODE == TILE_BT) qv[u][h] = in ? a.q[j] : (T)0;
+    }
+  }
+  double part = 0.0;
+#pragma unroll
+  for (int u = 0; u < LU; ++u) {
+    const int pr = pr0 + 8 * u;
+    if (MODE == TILE_BT) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        v[u][h] -= (T)alpha * qv[u][h];
+        const int r = y0 + 2 * pr + h;
+        const int lr = 2 * pr + h - kTHalo, lc = c - kTHalo;
+        if (col_in && r >= 0 && r < a.ny && lr >= 0 && lr < kTV && lc >= 0 && lc < kTV) {   // owned: once
+          e_out[(long)r * a.nx + cc] = v[u][h];
+          part += (double)v[u][h] * (double)v[u][h];
+        }
+      }
+    }
+    X[pr * kTLD + c] = {v[u][0], v[u][1]};
+  }
+  if (MODE == TILE_BT) put_partial(a, part, P_EE, it);   // contains the barrier the FFT needs
+  else __syncthreads();
+  fft_tile<T, false, kTN / 2, kTLD>(X, Y, tw);
+  // half spectra of the tile rows, column-major: Y[kx * 128 + r] (lanes along the packed rows)
+  constexpr int UU = (kTH * (kTN / 2) + kTNT - 1) / kTNT;
+#pragma unroll
+  for (int u = 0; u < UU; ++u) {
+    const int i = threadIdx.x + u * kTNT;
+    if (i < kTH * (kTN / 2)) {
+      const int k = i / (kTN / 2), pr = i - k * (kTN / 2);
+      const cpx<T> zk = X[pr * kTLD + k], zm = X[pr * kTLD + ((kTN - k) & (kTN - 1))];
+      const T h = (T)0.5;
+      Y[k * kTN + 2 * pr] = {h * (zk.x + zm.x), h * (zk.y - zm.y)};
+      Y[k * kTN + 2 * pr + 1] = {h * (zk.y + zm.y), h * (zm.x - zk.x)};
+    }
+  }
+  __syncthreads();
+  fft_tile<T, false, kTH, kTN>(Y, X, tw);
+  fft_tile<T, true, kTH, kTN, MODE == TILE_B ? 1 : 2>(Y, X, tw, a.Ht);
+  // packed rows 16..47 again: Z[k] = Q0[k] + i Q1[k], the upper half by conjugate symmetry
+  constexpr int PR0 = kTHalo / 2, NPR = kTV / 2;
+#pragma unroll
+  for (int u = 0; u < NPR * kTN / kTNT; ++u) {
+    const int i = threadIdx.x + u * kTNT;
+    const int k = i / NPR, pr = PR0 + (i - k * NPR);
+    const bool mirror = k > kTN / 2;
+    const int kk = mirror ? kTN - k : k;
+    cpx<T> q0 = Y[kk * kTN + 2 * pr], q1 = Y[kk * kTN + 2 * pr + 1];
+    if (mirror) {
+      q0.y = -q0.y;
+      q1.y = -q1.y;
+    }
+    X[pr * kTLD + k] = {q0.x - q1.y, q0.y + q1.x};
+  }
+  __syncthreads();
+  fft_tile<T, true, NPR, kTLD>(X + PR0 * kTLD, Y + PR0 * kTLD, tw);
+  // the owned pixels
+  T* out = MODE == TILE_B ? a.q : a.w;
+  double qq = 0.0;
+#pragma unroll
+  for (int u = 0; u < kTV * kTV / kTNT; ++u) {
+    const int i = threadIdx.x + u * kTNT;
+    const int lr = i / kTV, lc = i - lr * kTV;
+    const int r = ty * kTV + lr, cx = tx * kTV + lc;
+    if (r < a.ny && cx < a.nx) {
+      const int tr = lr + kTHalo, tc = lc + kTHalo;
+      const cpx<T> z = X[(tr >> 1) * kTLD + tc];
+      const T val = (tr & 1) ? z.y : z.x;
+      out[(long)r * a.nx + cx] = val;
+      if (MODE == TILE_B) qq += (double)val * (double)val;
+    }
+  }
+  if (MODE == TILE_B) put_partial(a, qq, P_QQ, it);
+}
+
+// y = L p (one thread per pixel).
+template <typename T>
+__global__ void __launch_bounds__(kNT) k_gather(Args<T> a) {
+  const int pixel = blockIdx.x * kNT + threadIdx.x;
+  if (pixel < a.J) a.y[pixel] = gather_L(a, a.p, pixel);
+}
+
+// e0 = d in T.
+template <typename T>
+__global__ void __launch_bounds__(kNT) k_copy_d(Args<T> a) {
+  const int j = blockIdx.x * kNT + threadIdx.x;
+  if (j < a.J) a.e0[j] = (T)a.d[j];
+}
+
+// The tile's PSF spectrum Ht[kx][ky] = sum_{a,b} P[a][b] exp(-2 pi i (ky (a - ck) + kx (b - ck)) / 128) / 128^2
+// in FP64, separably: first T1t[a][kx] over b (and the tile twiddles), then over a.
+__device__ __forceinline__ cpx<double> root128(long m) {
+  m %= kTN;
+  if (m < 0) m += kTN;
+  double sn, cs;
+  sincospi(-2.0 * (double)m / kTN, &sn, &cs);
+  return {cs, sn};
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kNT) k_tile_psf_rows(Args<T> a) {
+  const int idx = blockIdx.x * kNT + threadIdx.x;
+  if (idx < kTN) {
+    const cpx<double> u = root128(idx);
+    a.twt[idx] = {(T)u.x, (T)u.y};
+  }
+  if (idx >= a.K * kTH) return;
+  const int r = idx / kTH, kx = idx - r * kTH;
+  double re = 0.0, im = 0.0;
+  for (int b = 0; b < a.K; ++b) {
+    const cpx<double> u = root128((long)kx * (b - a.ck));
+    const double v = a.psf[r * a.K + b];
+    re += v * u.x;
+    im += v * u.y;
+  }
+  a.T1t[idx] = {re, im};
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kNT) k_tile_psf_cols(Args<T> a) {
+  const int idx = blockIdx.x * kNT + threadIdx.x;
+  if (idx >= kTH * kTN) return;
+  const int kx = idx / kTN, ky = idx - kx * kTN;
+  double re = 0.0, im = 0.0;
+  for (int r = 0; r < a.K; ++r) {
+    const cpx<double> u = root128((long)ky * (r - a.ck));
+    const cpx<double> t = a.T1t[r * kTH + kx];
+    re += t.x * u.x - t.y * u.y;
+    im += t.x * u.y + t.y * u.x;
+  }
+  const double sc = 1.0 / ((double)kTN * kTN);
+  a.Ht[idx] = {(T)(re * sc), (T)(im * sc)};
+}
+
 // ---------------------------------------------------------------- source-side kernels
 // g = L^T w over the sorted table, with its |g|^2 partial in slot `it`:
 // kLtG lanes per node, lane l adding entries l, l + kLtG, ... in order, then
@@ -870,7 +1142,7 @@ __global__ void __launch_bounds__(kLtNT) k_final(Args<T> a, sl_result out) {
     const int k = j >> 1;
     const bool ee = (j & 1) == 0;
     const double* p = part_of(a, ee ? P_EE : P_SS, k);
-    const int n = ee ? a.Nh : a.nb_node;   // |e|^2 partials: one per frequency column
+    const int n = ee ? a.nb_ee : a.nb_node;   // |e|^2 partials: per frequency column or per tile
     double v = 0.0;
     for (int i = lane; i < n; i += kWave) v += p[i];
     v = wave_sum(v);
@@ -929,7 +1201,7 @@ struct Layout {
   int Nx, Ny, Nh, taps;
   long long cap;
   size_t total;
-  size_t off[32];
+  size_t off[40];
 };
 
 static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -947,8 +1219,10 @@ static Layout make_layout(int nx, int ny, int nsub, int ns, int K, int interp, i
   L.cap = J * n2 * L.taps;
   const size_t c = 2 * sz;   // one complex element
   const int nb_row = (ny + 1) / 2;
-  const int maxb = std::max(std::max(nb_row, L.Nh), kMaxParts);   // row blocks, column blocks, node blocks
-  size_t sizes[32];
+  const int tiles = ((nx + kTV - 1) / kTV) * ((ny + kTV - 1) / kTV);
+  // row blocks, column blocks, tiles, node blocks
+  const int maxb = std::max(std::max(nb_row, L.Nh), std::max(tiles, kMaxParts));
+  size_t sizes[40];
   int n = 0;
   sizes[n++] = c * L.Nx;                              // twx
   sizes[n++] = c * L.Ny;                              // twy
@@ -969,6 +1243,13 @@ static Layout make_layout(int nx, int ny, int nsub, int ns, int K, int interp, i
     sizes[n++] = c * (size_t)L.Nh * L.Ny;             // E
     sizes[n++] = c * (size_t)L.Nh * L.Ny;             // SQ
     sizes[n++] = sz * (size_t)J;                      // w
+    sizes[n++] = sz * (size_t)J;                      // y
+    sizes[n++] = sz * (size_t)J;                      // q
+    sizes[n++] = sz * (size_t)J;                      // e0
+    sizes[n++] = sz * (size_t)J;                      // e1
+    sizes[n++] = c * (size_t)kTBuf;                   // Ht
+    sizes[n++] = c * (size_t)kTN;                     // twt
+    sizes[n++] = 16 * (size_t)K * kTH;                // T1t
     sizes[n++] = sz * (size_t)I;                      // s
     sizes[n++] = sz * (size_t)I;                      // p
     sizes[n++] = sz * (size_t)I;                      // g
@@ -1012,6 +1293,13 @@ static Args<T> bind(const Layout& L, unsigned char* ws, bool solve) {
     a.E = reinterpret_cast<cpx<T>*>(ws + L.off[i++]);
     a.SQ = reinterpret_cast<cpx<T>*>(ws + L.off[i++]);
     a.w = reinterpret_cast<T*>(ws + L.off[i++]);
+    a.y = reinterpret_cast<T*>(ws + L.off[i++]);
+    a.q = reinterpret_cast<T*>(ws + L.off[i++]);
+    a.e0 = reinterpret_cast<T*>(ws + L.off[i++]);
+    a.e1 = reinterpret_cast<T*>(ws + L.off[i++]);
+    a.Ht = reinterpret_cast<cpx<T>*>(ws + L.off[i++]);
+    a.twt = reinterpret_cast<cpx<T>*>(ws + L.off[i++]);
+    a.T1t = reinterpret_cast<cpx<double>*>(ws + L.off[i++]);
     a.s = reinterpret_cast<T*>(ws + L.off[i++]);
     a.p = reinterpret_cast<T*>(ws + L.off[i++]);
     a.g = reinterpret_cast<T*>(ws + L.off[i++]);
@@ -1112,13 +1400,32 @@ static int solve_impl(const sl_problem* pb, const double* lens, int ns, int n_it
   a.nb_row = (g.ny + 1) / 2;
   a.nb_node = (int)std::min<long>(nblk(a.I, kNT), kMaxParts);
   a.nb_lt = (int)std::min<long>(nblk((long)a.I * kLtG, kLtNT), kMaxParts);
-  a.max_blocks = std::max(std::max(a.nb_row, a.Nh), std::max(a.nb_node, a.nb_lt));
+  // FP32 with a PSF no wider than the tile's halo: the tiled blur (k_tile)
+  a.tiles_x = (a.nx + kTV - 1) / kTV;
+  a.tiles_y = (a.ny + kTV - 1) / kTV;
+  const int ntiles = a.tiles_x * a.tiles_y;
+  a.tiled = sizeof(T) == 4 && a.ck <= kTHalo;
+  a.nb_qq = a.tiled ? ntiles : a.nb_row;
+  a.nb_ee = a.tiled ? ntiles : a.Nh;
+  a.max_blocks = std::max(std::max(std::max(a.nb_row, a.Nh), ntiles), std::max(a.nb_node, a.nb_lt));
   const size_t lx = 2 * sizeof(cpx<T>) * a.Nx;
+  const size_t lt = 2 * sizeof(cpx<T>) * (size_t)kTBuf;
   if (int e = set_lds<T>(2 * sizeof(cpx<T>) * (a.Nx > a.Ny ? a.Nx : a.Ny))) return e;
+  if constexpr (sizeof(T) == 4) {
+    const void* kt[] = {(const void*)k_tile<T, TILE_B>, (const void*)k_tile<T, TILE_BT0>,
+                        (const void*)k_tile<T, TILE_BT>};
+    for (const void* k : kt) SL_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lt));
+  }
   // counters start at zero (a fill kernel: the call may be captured in a graph)
   hipLaunchKernelGGL(k_zero_int<T>, dim3(nblk(a.I, kNT)), dim3(kNT), 0, st, a.cnt, (long)a.I);
   hipLaunchKernelGGL(k_zero_int<T>, dim3(1), dim3(kNT), 0, st, a.flags, 1L);
-  if (int e = spectrum(a, st)) return e;
+  if (a.tiled) {
+    hipLaunchKernelGGL(k_tile_psf_rows<T>, dim3(nblk(std::max(a.K * kTH, kTN), kNT)), dim3(kNT), 0, st, a);
+    hipLaunchKernelGGL(k_tile_psf_cols<T>, dim3(nblk(kTH * kTN, kNT)), dim3(kNT), 0, st, a);
+    if (int e = check_launch("tile PSF spectrum")) return e;
+  } else if (int e = spectrum(a, st)) {
+    return e;
+  }
   const long nsubpix = (long)a.J * a.n2;
   hipLaunchKernelGGL(k_trace<T>, dim3(nblk(nsubpix, kNT)), dim3(kNT), 0, st, a);
   hipLaunchKernelGGL(k_count<T>, dim3(nblk(a.J, kNT)), dim3(kNT), 0, st, a);
@@ -1129,6 +1436,29 @@ static int solve_impl(const sl_problem* pb, const double* lens, int ns, int n_it
   hipLaunchKernelGGL(k_fill<T>, dim3(nblk(a.J, kNT)), dim3(kNT), 0, st, a);
   hipLaunchKernelGGL(k_sort<T>, dim3(nblk(a.I, kNT / kWave)), dim3(kNT), 0, st, a);
   if (int e = check_launch("large solve set-up")) return e;
+  if constexpr (sizeof(T) == 4) {
+    if (a.tiled) {
+      // g = A^T d, p = g; then per iteration y = L p, q = B y, e -= alpha q with w = B^T e, g = L^T w, s and p
+      hipLaunchKernelGGL(k_copy_d<T>, dim3(nblk(a.J, kNT)), dim3(kNT), 0, st, a);
+      hipLaunchKernelGGL((k_tile<T, TILE_BT0>), dim3(ntiles), dim3(kTNT), lt, st, a, (const T*)a.e0, (T*)nullptr, 0);
+      hipLaunchKernelGGL(k_lt<T>, dim3(a.nb_lt), dim3(kLtNT), 0, st, a, n_iter);
+      hipLaunchKernelGGL(k_start<T>, dim3(a.nb_node), dim3(kNT), 0, st, a);
+      for (int it = 0; it < n_iter; ++it) {
+        T* ein = (it & 1) ? a.e1 : a.e0;
+        T* eout = (it & 1) ? a.e0 : a.e1;
+        hipLaunchKernelGGL(k_gather<T>, dim3(nblk(a.J, kNT)), dim3(kNT), 0, st, a);
+        hipLaunchKernelGGL((k_tile<T, TILE_B>), dim3(ntiles), dim3(kTNT), lt, st, a, (const T*)nullptr, (T*)nullptr,
+                           it);
+        hipLaunchKernelGGL((k_tile<T, TILE_BT>), dim3(ntiles), dim3(kTNT), lt, st, a, (const T*)ein, eout, it);
+        hipLaunchKernelGGL(k_lt<T>, dim3(a.nb_lt), dim3(kLtNT), 0, st, a, it);
+        hipLaunchKernelGGL(k_update<T>, dim3(a.nb_node), dim3(kNT), 0, st, a, it);
+      }
+      if (int e = check_launch("large solve iterations (tiled blur)")) return e;
+      hipLaunchKernelGGL(k_final<T>, dim3(1), dim3(kLtNT), 8 * kLcurveScratch, st, a, *out);
+      hipLaunchKernelGGL(k_corner_copy<T>, dim3(nblk(a.I, kNT)), dim3(kNT), 0, st, a, *out);
+      return check_launch("large solve corner");
+    }
+  }
   // g = A^T d, p = g
   hipLaunchKernelGGL((k_rowfwd<T, ROW_D>), dim3(a.nb_row), dim3(kRowNT), lx, st, a, (const T*)nullptr);
   blur_tail<T, true, COL_E, OUT_W>(a, nullptr, 0, st);
