@@ -52,7 +52,14 @@ namespace large {
 constexpr int kNT = 256;              // threads of most blocks
 constexpr int kRowNT = 512;           // threads of the row-FFT blocks
 constexpr int kLtNT = 1024;           // threads of the L^T blocks
-constexpr int kLtG = 16;              // lanes per node in L^T
+// L^T lanes per node and node groups per thread in flight.  FP32: 8 lanes
+// (most nodes have fewer entries than that), 4 groups.  FP64: 16 lanes, one
+// group (its 16-byte entries: more groups cost the second block per compute
+// unit and measured slower).
+template <typename T>
+constexpr int lt_lanes() { return sizeof(T) == 4 ? 8 : 16; }
+template <typename T>
+constexpr int lt_groups() { return sizeof(T) == 4 ? 4 : 1; }
 constexpr int kSortChunk = 1024;      // keys of one node staged in LDS by the sort
 constexpr int kMaxParts = 1024;       // blocks of the node kernels (grid-stride loops)
 constexpr int kMaxImage = 2048;       // image side
@@ -72,6 +79,7 @@ struct alignas(sizeof(T) == 8 ? 8 : 4) Sub {
   int32_t cell;
   T fx, fy;
 };
+static_assert(sizeof(Sub<float>) == 12, "three words per record: the vector loads of gather_L");
 
 // One entry of the node-major L^T table: pixel and weight.
 template <typename T>
@@ -575,6 +583,24 @@ template <typename T>
 __device__ __forceinline__ T gather_L(const Args<T>& a, const T* __restrict__ x, int pixel) {
   T acc = 0;
   const long j0 = (long)pixel * a.n2;
+  if constexpr (sizeof(T) == 4) {
+    if (a.taps == 4 && a.n2 == 4) {
+      // the pixel's four 12-byte records are 48 contiguous bytes, 16-byte
+      // aligned (workspace and its sections are 256-byte aligned): three
+      // 16-byte loads instead of twelve 4-byte ones
+      const float4* q = reinterpret_cast<const float4*>(a.sub + j0);
+      const float4 q0 = q[0], q1 = q[1], q2 = q[2];
+      const float wv[12] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w, q2.x, q2.y, q2.z, q2.w};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int c = __float_as_int(wv[3 * k]);
+        if (c < 0) continue;
+        const T fx = wv[3 * k + 1], fy = wv[3 * k + 2];
+        acc += (1 - fy) * ((1 - fx) * x[c] + fx * x[c + 1]) + fy * ((1 - fx) * x[c + a.ns] + fx * x[c + a.ns + 1]);
+      }
+      return acc / (T)4;
+    }
+  }
   if (a.taps == 4) {
     for (int k = 0; k < a.n2; ++k) {
       const Sub<T> sp = a.sub[j0 + k];
@@ -796,14 +822,77 @@ constexpr int kTN = 128;                      // tile side (FFT length)
 constexpr int kTV = 64;                       // owned outputs per side
 constexpr int kTHalo = (kTN - kTV) / 2;       // 32: PSF half-width it allows
 constexpr int kTH = kTN / 2 + 1;              // 65 half-spectrum columns
-constexpr int kTBuf = kTH * kTN;              // complex elements per LDS buffer
+constexpr int kTBuf = kTH * (kTN + 1);        // complex elements per LDS buffer (padded rows)
 constexpr int kTNT = 1024;
 
+// In-register DFTs of length 4, 8 and 16 (INV: the conjugate kernel), in
+// natural order in and out.  The lengths 8 and 16 split as 2 x 4 and 4 x 4
+// (Cooley-Tukey: inner DFT4s, the factor w_R^(n2 k1), outer DFTs).
+template <typename T, bool INV>
+__device__ __forceinline__ void dft4(cpx<T>& a0, cpx<T>& a1, cpx<T>& a2, cpx<T>& a3) {
+  const cpx<T> t0 = cadd(a0, a2), t1 = csub(a0, a2), t2 = cadd(a1, a3), d = csub(a1, a3);
+  const cpx<T> t3 = INV ? cpx<T>{-d.y, d.x} : cpx<T>{d.y, -d.x};
+  a0 = cadd(t0, t2);
+  a1 = cadd(t1, t3);
+  a2 = csub(t0, t2);
+  a3 = csub(t1, t3);
+}
+
+// v times exp(-+2 pi i e / 16) for a constant e (the sign by INV)
+template <typename T, bool INV>
+__device__ __forceinline__ cpx<T> w16(cpx<T> v, int e) {
+  constexpr double c1 = 0.92387953251128674, s1 = 0.38268343236508977, c2 = 0.70710678118654752;
+  const double cs[16] = {1, c1, c2, s1, 0, -s1, -c2, -c1, -1, -c1, -c2, -s1, 0, s1, c2, c1};
+  const double sn[16] = {0, s1, c2, c1, 1, c1, c2, s1, 0, -s1, -c2, -c1, -1, -c1, -c2, -s1};
+  const cpx<T> w = {(T)cs[e & 15], INV ? (T)sn[e & 15] : -(T)sn[e & 15]};
+  return cmul(v, w);
+}
+
+template <typename T, bool INV>
+__device__ __forceinline__ void dft8(cpx<T> (&v)[8]) {
+  // n = 2 n1 + n2: DFT4 over n1 for each n2, twiddle w8^(n2 k1), DFT2 over n2
+  dft4<T, INV>(v[0], v[2], v[4], v[6]);
+  dft4<T, INV>(v[1], v[3], v[5], v[7]);
+  cpx<T> o[8];
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    const cpx<T> y0 = v[2 * k1], y1 = k1 ? w16<T, INV>(v[2 * k1 + 1], 2 * k1) : v[2 * k1 + 1];
+    o[k1] = cadd(y0, y1);
+    o[k1 + 4] = csub(y0, y1);
+  }
+#pragma unroll
+  for (int m = 0; m < 8; ++m) v[m] = o[m];
+}
+
+template <typename T, bool INV>
+__device__ __forceinline__ void dft16(cpx<T> (&v)[16]) {
+  // n = 4 n1 + n2: DFT4 over n1 for each n2 (result k1 in slot 4 k1 + n2),
+  // twiddle w16^(n2 k1), DFT4 over n2 for each k1 (result k1 + 4 k2 in slot 4 k1 + k2)
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) dft4<T, INV>(v[n2], v[4 + n2], v[8 + n2], v[12 + n2]);
+#pragma unroll
+  for (int k1 = 1; k1 < 4; ++k1)
+#pragma unroll
+    for (int n2 = 1; n2 < 4; ++n2) v[4 * k1 + n2] = w16<T, INV>(v[4 * k1 + n2], n2 * k1);
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) dft4<T, INV>(v[4 * k1], v[4 * k1 + 1], v[4 * k1 + 2], v[4 * k1 + 3]);
+  cpx<T> o[16];
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1)
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) o[k1 + 4 * k2] = v[4 * k1 + k2];
+#pragma unroll
+  for (int m = 0; m < 16; ++m) v[m] = o[m];
+}
+
 // One Stockham stage (span NS, radix R) of NB independent length-kTN FFTs at
-// x[b * LD + i] into y (row stride LD): the butterflies of fft_lds on every row at once,
-// every operand of a thread's butterflies loaded before any is written, the
-// twiddles from LDS.  HM = 1 (2) multiplies each input by H (conj H) at the
-// same index first: the PSF product fused into the first inverse stage.
+// x[b * LD + i] into y (row stride LD): butterfly j of a row reads
+// x[j + r kTN/R], turns input r by w^(r (j mod NS) kTN/(NS R)) and writes its
+// radix-R DFT to y[(j - j mod NS) R + j mod NS + m NS] (as in fft_lds).  Every
+// operand of a thread's butterflies is loaded before any is written; the
+// twiddles come from LDS.  HM = 1 (2) multiplies each input by H (conj H),
+// stored with row stride kTN, at the same position first: the PSF product
+// fused into the first inverse stage.
 template <typename T, bool INV, int NB, int LD, int NS, int R, int HM>
 __device__ __forceinline__ void tile_stage(const cpx<T>* __restrict__ x, cpx<T>* __restrict__ y, const cpx<T>* tw,
                                            const cpx<T>* __restrict__ H) {
@@ -837,40 +926,35 @@ __device__ __forceinline__ void tile_stage(const cpx<T>* __restrict__ x, cpx<T>*
 #pragma unroll
         for (int r = 1; r < R; ++r) v[u][r] = INV ? cmulc(v[u][r], tw[r * k * STEP]) : cmul(v[u][r], tw[r * k * STEP]);
       }
-      if (R == 4) {
-        const cpx<T> t0 = cadd(v[u][0], v[u][2]), t1 = csub(v[u][0], v[u][2]);
-        const cpx<T> t2 = cadd(v[u][1], v[u][3]), d = csub(v[u][1], v[u][3]);
-        const cpx<T> t3 = INV ? cpx<T>{-d.y, d.x} : cpx<T>{d.y, -d.x};
-        o_[0] = cadd(t0, t2);
-        o_[NS] = cadd(t1, t3);
-        o_[2 * NS] = csub(t0, t2);
-        o_[3 * NS] = csub(t1, t3);
+      if constexpr (R == 16) {
+        dft16<T, INV>(v[u]);
+      } else if constexpr (R == 8) {
+        dft8<T, INV>(v[u]);
       } else {
-        o_[0] = cadd(v[u][0], v[u][1]);
-        o_[NS] = csub(v[u][0], v[u][1]);
+        static_assert(R == 4, "radix 4, 8 or 16");
+        dft4<T, INV>(v[u][0], v[u][1], v[u][2], v[u][3]);
       }
+#pragma unroll
+      for (int m = 0; m < R; ++m) o_[m * NS] = v[u][m];
     }
   }
   __syncthreads();
 }
 
-// NB length-128 FFTs (radix 4, 4, 4, 2) from x (row stride LD), scratch y;
-// the result ends in x.
+// NB length-128 FFTs (radix 16, then radix 8) from x (row stride LD),
+// scratch y; the result ends in x.
 template <typename T, bool INV, int NB, int LD, int HM = 0>
 __device__ __forceinline__ void fft_tile(cpx<T>* x, cpx<T>* y, const cpx<T>* tw, const cpx<T>* __restrict__ H = nullptr) {
   static_assert(kTN == 128, "stage list is for length 128");
-  static_assert(HM == 0 || LD == kTN, "the PSF spectrum is stored with row stride 128");
-  tile_stage<T, INV, NB, LD, 1, 4, HM>(x, y, tw, H);
-  tile_stage<T, INV, NB, LD, 4, 4, 0>(y, x, tw, nullptr);
-  tile_stage<T, INV, NB, LD, 16, 4, 0>(x, y, tw, nullptr);
-  tile_stage<T, INV, NB, LD, 64, 2, 0>(y, x, tw, nullptr);
+  tile_stage<T, INV, NB, LD, 1, 16, HM>(x, y, tw, H);
+  tile_stage<T, INV, NB, LD, 16, 8, 0>(y, x, tw, nullptr);
 }
 
-// Row stride of the packed-row buffers: one element of padding, so that the
-// transposes between packed rows and column-major half spectra (lanes along
-// the packed rows) meet distinct LDS banks.
+// Row stride of the tile buffers (packed rows and column-major half spectra):
+// one element of padding, so that the transposes between them (lanes along
+// the packed rows) and the first stage's writes meet distinct LDS banks.
 constexpr int kTLD = kTN + 1;
-static_assert(kTN / 2 * kTLD <= kTBuf, "packed rows fit a buffer");
+static_assert(kTN / 2 * kTLD <= kTBuf && kTH * kTLD <= kTBuf, "tile buffers fit");
 
 enum { TILE_B = 0, TILE_BT0 = 1, TILE_BT = 2 };
 
@@ -879,8 +963,8 @@ enum { TILE_B = 0, TILE_BT0 = 1, TILE_BT = 2 };
 // update e_out = e_in - alpha q (alpha of iteration it; written on the owned
 // pixels, recomputed on the halo), the block's |e|^2 partial, and
 // w = B^T e_out.  Only the packed rows that hold owned pixels (16..47) take
-// the inverse row transform.  Packed rows are kept with row stride kTLD,
-// column-major half spectra with stride 128.
+// the inverse row transform.  Packed rows and column-major half spectra are
+// kept with row stride kTLD.
 template <typename T, int MODE>
 __global__ void __launch_bounds__(kTNT) k_tile(Args<T> a, const T* __restrict__ e_in, T* __restrict__ e_out, int it) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -890,11 +974,6 @@ __global__ void __launch_bounds__(kTNT) k_tile(Args<T> a, const T* __restrict__ 
   const int ty = blockIdx.x / a.tiles_x, tx = blockIdx.x - ty * a.tiles_x;
   const int y0 = ty * kTV - kTHalo, x0 = tx * kTV - kTHalo;   // image position of tile element (0, 0)
   if (threadIdx.x < kTN) tw[threadIdx.x] = a.twt[threadIdx.x];
-  double alpha = 0.0;
-  if (MODE == TILE_BT) {
-    alpha = alpha_of(a, it);
-    if (blockIdx.x == 0 && threadIdx.x == 0) a.alpha[it] = alpha;   // the update uses the same value
-  }
   // load: packed row pr holds tile rows 2 pr (real part) and 2 pr + 1 (imaginary part);
   // thread t takes column t mod 128 of packed rows t / 128 + 8 u
   constexpr int LU = kTN * kTN / 2 / kTNT;
@@ -913,6 +992,11 @@ __global__ void __launch_bounds__(kTNT) k_tile(Args<T> a, const T* __restrict__ 
       v[u][h] = in ? src[j] : (T)0;
       if (MODE == TILE_BT) qv[u][h] = in ? a.q[j] : (T)0;
     }
+  }
+  double alpha = 0.0;   // after the loads are issued: its reduction waits on other blocks' partials
+  if (MODE == TILE_BT) {
+    alpha = alpha_of(a, it);
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.alpha[it] = alpha;   // the update uses the same value
   }
   double part = 0.0;
 #pragma unroll
@@ -935,7 +1019,7 @@ __global__ void __launch_bounds__(kTNT) k_tile(Args<T> a, const T* __restrict__ 
   if (MODE == TILE_BT) put_partial(a, part, P_EE, it);   // contains the barrier the FFT needs
   else __syncthreads();
   fft_tile<T, false, kTN / 2, kTLD>(X, Y, tw);
-  // half spectra of the tile rows, column-major: Y[kx * 128 + r] (lanes along the packed rows)
+  // half spectra of the tile rows, column-major: Y[kx * kTLD + r] (lanes along the packed rows)
   constexpr int UU = (kTH * (kTN / 2) + kTNT - 1) / kTNT;
 #pragma unroll
   for (int u = 0; u < UU; ++u) {
@@ -944,13 +1028,13 @@ __global__ void __launch_bounds__(kTNT) k_tile(Args<T> a, const T* __restrict__ 
       const int k = i / (kTN / 2), pr = i - k * (kTN / 2);
       const cpx<T> zk = X[pr * kTLD + k], zm = X[pr * kTLD + ((kTN - k) & (kTN - 1))];
       const T h = (T)0.5;
-      Y[k * kTN + 2 * pr] = {h * (zk.x + zm.x), h * (zk.y - zm.y)};
-      Y[k * kTN + 2 * pr + 1] = {h * (zk.y + zm.y), h * (zm.x - zk.x)};
+      Y[k * kTLD + 2 * pr] = {h * (zk.x + zm.x), h * (zk.y - zm.y)};
+      Y[k * kTLD + 2 * pr + 1] = {h * (zk.y + zm.y), h * (zm.x - zk.x)};
     }
   }
   __syncthreads();
-  fft_tile<T, false, kTH, kTN>(Y, X, tw);
-  fft_tile<T, true, kTH, kTN, MODE == TILE_B ? 1 : 2>(Y, X, tw, a.Ht);
+  fft_tile<T, false, kTH, kTLD>(Y, X, tw);
+  fft_tile<T, true, kTH, kTLD, MODE == TILE_B ? 1 : 2>(Y, X, tw, a.Ht);
   // packed rows 16..47 again: Z[k] = Q0[k] + i Q1[k], the upper half by conjugate symmetry
   constexpr int PR0 = kTHalo / 2, NPR = kTV / 2;
 #pragma unroll
@@ -959,7 +1043,7 @@ __global__ void __launch_bounds__(kTNT) k_tile(Args<T> a, const T* __restrict__ 
     const int k = i / NPR, pr = PR0 + (i - k * NPR);
     const bool mirror = k > kTN / 2;
     const int kk = mirror ? kTN - k : k;
-    cpx<T> q0 = Y[kk * kTN + 2 * pr], q1 = Y[kk * kTN + 2 * pr + 1];
+    cpx<T> q0 = Y[kk * kTLD + 2 * pr], q1 = Y[kk * kTLD + 2 * pr + 1];
     if (mirror) {
       q0.y = -q0.y;
       q1.y = -q1.y;
@@ -1048,39 +1132,61 @@ __global__ void __launch_bounds__(kNT) k_tile_psf_cols(Args<T> a) {
 
 // ---------------------------------------------------------------- source-side kernels
 // g = L^T w over the sorted table, with its |g|^2 partial in slot `it`:
-// kLtG lanes per node, lane l adding entries l, l + kLtG, ... in order, then
-// a fixed butterfly over the group; lane 0 holds the node's value.  Grid-
-// stride over the nodes (nb_lt <= kMaxParts blocks).
+// lt_lanes lanes per node, lane l adding entries l, l + kLtG, ... in order, then
+// a fixed butterfly over the group; lane 0 holds the node's value.  Each
+// thread serves lt_groups node groups at once (most nodes have fewer entries than
+// lanes, so a node is one dependent chain of loads: row bounds, entry, w).
+// Grid-stride over the nodes (nb_lt <= kMaxParts blocks).
 template <typename T>
 __global__ void __launch_bounds__(kLtNT) k_lt(Args<T> a, int it) {
+  constexpr int kLtU = lt_groups<T>(), kLtG = lt_lanes<T>();
   const int l = threadIdx.x & (kLtG - 1);
-  const int per_block = kLtNT / kLtG;
+  constexpr int per_pass = kLtNT / kLtG;
   double gg = 0.0;
-  for (int n0 = blockIdx.x * per_block; n0 < a.I; n0 += gridDim.x * per_block) {
-    const int node = n0 + threadIdx.x / kLtG;
-    T acc = 0;
-    if (node < a.I) {
-      const int e1 = a.rowptr[node + 1];
-      int e = a.rowptr[node] + l;
-      // four entries' loads in flight at once, added in entry order
-      for (; e + 3 * kLtG < e1; e += 4 * kLtG) {
-        const LtE<T> t0 = a.lt[e], t1 = a.lt[e + kLtG], t2 = a.lt[e + 2 * kLtG], t3 = a.lt[e + 3 * kLtG];
+  for (int n0 = blockIdx.x * per_pass * kLtU; n0 < a.I; n0 += gridDim.x * per_pass * kLtU) {
+    // kLtU node groups per thread: their row bounds, first entries and w values in flight together
+    int node[kLtU], e[kLtU], e1[kLtU];
+    T acc[kLtU];
+#pragma unroll
+    for (int u = 0; u < kLtU; ++u) {
+      node[u] = n0 + u * per_pass + threadIdx.x / kLtG;
+      const bool ok = node[u] < a.I;
+      e[u] = ok ? a.rowptr[node[u]] + l : 0;
+      e1[u] = ok ? a.rowptr[node[u] + 1] : 0;
+      acc[u] = 0;
+    }
+    LtE<T> t[kLtU];
+#pragma unroll
+    for (int u = 0; u < kLtU; ++u) t[u] = e[u] < e1[u] ? a.lt[e[u]] : LtE<T>{0, (T)0};
+    T wv[kLtU];
+#pragma unroll
+    for (int u = 0; u < kLtU; ++u) wv[u] = e[u] < e1[u] ? a.w[t[u].pix] : (T)0;
+#pragma unroll
+    for (int u = 0; u < kLtU; ++u) {
+      if (e[u] < e1[u]) acc[u] += t[u].w * wv[u];
+      e[u] += kLtG;
+      // the rest of the lane's entries, in order, four loads in flight
+      for (; e[u] + 3 * kLtG < e1[u]; e[u] += 4 * kLtG) {
+        const LtE<T> t0 = a.lt[e[u]], t1 = a.lt[e[u] + kLtG], t2 = a.lt[e[u] + 2 * kLtG], t3 = a.lt[e[u] + 3 * kLtG];
         const T w0 = a.w[t0.pix], w1 = a.w[t1.pix], w2 = a.w[t2.pix], w3 = a.w[t3.pix];
-        acc += t0.w * w0;
-        acc += t1.w * w1;
-        acc += t2.w * w2;
-        acc += t3.w * w3;
+        acc[u] += t0.w * w0;
+        acc[u] += t1.w * w1;
+        acc[u] += t2.w * w2;
+        acc[u] += t3.w * w3;
       }
-      for (; e < e1; e += kLtG) {
-        const LtE<T> t = a.lt[e];
-        acc += t.w * a.w[t.pix];
+      for (; e[u] < e1[u]; e[u] += kLtG) {
+        const LtE<T> tt = a.lt[e[u]];
+        acc[u] += tt.w * a.w[tt.pix];
       }
     }
 #pragma unroll
-    for (int o = kLtG / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kLtG);
-    if (node < a.I && l == 0) {
-      a.g[node] = acc;
-      gg += (double)acc * (double)acc;
+    for (int u = 0; u < kLtU; ++u) {
+#pragma unroll
+      for (int o = kLtG / 2; o > 0; o >>= 1) acc[u] += __shfl_xor(acc[u], o, kLtG);
+      if (node[u] < a.I && l == 0) {
+        a.g[node[u]] = acc[u];
+        gg += (double)acc[u] * (double)acc[u];
+      }
     }
   }
   put_partial(a, gg, P_GG, it);
@@ -1399,7 +1505,7 @@ static int solve_impl(const sl_problem* pb, const double* lens, int ns, int n_it
   a.n_iter = n_iter;
   a.nb_row = (g.ny + 1) / 2;
   a.nb_node = (int)std::min<long>(nblk(a.I, kNT), kMaxParts);
-  a.nb_lt = (int)std::min<long>(nblk((long)a.I * kLtG, kLtNT), kMaxParts);
+  a.nb_lt = (int)std::min<long>(nblk((long)a.I * lt_lanes<T>(), (long)kLtNT * lt_groups<T>()), kMaxParts);
   // FP32 with a PSF no wider than the tile's halo: the tiled blur (k_tile)
   a.tiles_x = (a.nx + kTV - 1) / kTV;
   a.tiles_y = (a.ny + kTV - 1) / kTV;

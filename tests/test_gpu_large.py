@@ -112,10 +112,10 @@ def test_large_solve_medium_vs_oracle(sl, prec, interp):
     def make(x):
         return solve.Problem(lens, x, sigma, psf, w.nx, w.ny, w.pix, w.nsub_model, w.ns, w.half_width,
                              "identity", interp, blur="fft")
-    # FP32 rounding moves the corner over a wide stretch of this curve (draws put it anywhere from the 8th to
-    # the 21st iterate), so the FP32 envelope takes 24 draws
+    # FP32 rounding moves the corner over a wide stretch of this curve (64 draws put it anywhere from the 7th
+    # to the 22nd iterate), so the FP32 envelope takes 64 draws
     ref, dev, ds, corners = cgls_envelope.envelope(make, dd, prec, psf.shape[0], 40,
-                                                   draws=8 if prec == "f64" else 24)
+                                                   draws=8 if prec == "f64" else 64)
     assert np.all(out["status"][0] == 0), out["status"]
     assert np.array_equal(out["iters"][0], np.arange(1, 41))
     for key in ("chi2", "reg"):
