@@ -822,7 +822,7 @@ constexpr int kTN = 128;                      // tile side (FFT length)
 constexpr int kTV = 64;                       // owned outputs per side
 constexpr int kTHalo = (kTN - kTV) / 2;       // 32: PSF half-width it allows
 constexpr int kTH = kTN / 2 + 1;              // 65 half-spectrum columns
-constexpr int kTBuf = kTH * (kTN + 1);        // complex elements per LDS buffer (padded rows)
+constexpr int kTBuf = kTH * (kTN + kTN / 16 + 1);   // complex elements per LDS buffer (padded rows)
 constexpr int kTNT = 1024;
 
 // In-register DFTs of length 4, 8 and 16 (INV: the conjugate kernel), in
@@ -885,31 +885,55 @@ __device__ __forceinline__ void dft16(cpx<T> (&v)[16]) {
   for (int m = 0; m < 16; ++m) v[m] = o[m];
 }
 
-// One Stockham stage (span NS, radix R) of NB independent length-kTN FFTs at
-// x[b * LD + i] into y (row stride LD): butterfly j of a row reads
-// x[j + r kTN/R], turns input r by w^(r (j mod NS) kTN/(NS R)) and writes its
-// radix-R DFT to y[(j - j mod NS) R + j mod NS + m NS] (as in fft_lds).  Every
-// operand of a thread's butterflies is loaded before any is written; the
-// twiddles come from LDS.  HM = 1 (2) multiplies each input by H (conj H),
-// stored with row stride kTN, at the same position first: the PSF product
-// fused into the first inverse stage.
-template <typename T, bool INV, int NB, int LD, int NS, int R, int HM>
-__device__ __forceinline__ void tile_stage(const cpx<T>* __restrict__ x, cpx<T>* __restrict__ y, const cpx<T>* tw,
-                                           const cpx<T>* __restrict__ H) {
-  constexpr int NBF = kTN / R, STEP = kTN / (NS * R), ITEMS = NB * NBF;
-  constexpr int U = (ITEMS + kTNT - 1) / kTNT;
-  cpx<T> v[U][R];
+// Length-128 FFTs of the tile as two Stockham stages (as in fft_lds):
+// stage 1 (radix 16, span 1): butterfly j < 8 of a row reads x[j + 8 r]
+// (r < 16) and writes its DFT16 to positions 16 j + m; stage 2 (radix 8,
+// span 16): butterfly j < 16 reads positions j + 16 r (r < 8), turns input r
+// by w^(r j) and writes its DFT8 to positions j + 16 m.  Rows and columns
+// live in buffers of row stride kTLD; the intermediate goes to a scratch of
+// row stride kTP with one pad element after every 16 (position e at
+// e + e / 16).  With the lanes of stage 1 taking rows b and b + 8 in each
+// group of 16, every LDS access of both stages meets distinct banks.
+constexpr int kTLD = kTN + 1;   // 129: odd, so the transposes (lanes along rows) meet distinct banks
+constexpr int kTP = kTN + kTN / 16 + 1;   // 137
+static_assert(kTH * kTP <= kTBuf && kTH * kTLD <= kTBuf, "tile buffers fit");
+
+__device__ __forceinline__ int p16(int b, int e) { return b * kTP + e + (e >> 4); }
+
+// lane item wi of stage 1 -> (row b, butterfly j): in each group of 16 lanes,
+// 8 take row b and 8 row b + 8; rows past the last full set of 16 (the
+// Nyquist column of the half spectra) one after another
+template <int NB>
+__device__ __forceinline__ void stage1_map(int wi, int& b, int& j) {
+  j = wi & 7;
+  if (wi < (NB / 16) * 16 * 8) {
+    const int g = wi >> 4, h = (wi >> 3) & 1;
+    b = (g >> 3) * 16 + (g & 7) + 8 * h;
+  } else {
+    b = wi >> 3;
+  }
+}
+
+// HM = 1 (2) multiplies each input by H (conj H), stored with row stride
+// kTN, at the same position first: the PSF product fused into the first
+// inverse stage.
+template <typename T, bool INV, int NB, int HM>
+__device__ __forceinline__ void tile_stage1(const cpx<T>* __restrict__ x, cpx<T>* __restrict__ y,
+                                            const cpx<T>* __restrict__ H) {
+  constexpr int ITEMS = NB * 8, U = (ITEMS + kTNT - 1) / kTNT;
+  cpx<T> v[U][16];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     const int wi = threadIdx.x + u * kTNT;
     if (ITEMS % kTNT == 0 || wi < ITEMS) {
-      const int b = wi / NBF, j = wi - b * NBF;
+      int b, j;
+      stage1_map<NB>(wi, b, j);
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[u][r] = x[b * LD + j + r * NBF];
+      for (int r = 0; r < 16; ++r) v[u][r] = x[b * kTLD + j + 8 * r];
       if (HM) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-          const cpx<T> h = H[b * kTN + j + r * NBF];
+        for (int r = 0; r < 16; ++r) {
+          const cpx<T> h = H[b * kTN + j + 8 * r];
           v[u][r] = HM == 1 ? cmul(v[u][r], h) : cmulc(v[u][r], h);
         }
       }
@@ -919,42 +943,59 @@ __device__ __forceinline__ void tile_stage(const cpx<T>* __restrict__ x, cpx<T>*
   for (int u = 0; u < U; ++u) {
     const int wi = threadIdx.x + u * kTNT;
     if (ITEMS % kTNT == 0 || wi < ITEMS) {
-      const int b = wi / NBF, j = wi - b * NBF;
-      const int k = j & (NS - 1);
-      cpx<T>* o_ = y + b * LD + (j - k) * R + k;
-      if (NS > 1 && k) {
+      int b, j;
+      stage1_map<NB>(wi, b, j);
+      dft16<T, INV>(v[u]);
+      cpx<T>* o_ = y + p16(b, 16 * j);
 #pragma unroll
-        for (int r = 1; r < R; ++r) v[u][r] = INV ? cmulc(v[u][r], tw[r * k * STEP]) : cmul(v[u][r], tw[r * k * STEP]);
-      }
-      if constexpr (R == 16) {
-        dft16<T, INV>(v[u]);
-      } else if constexpr (R == 8) {
-        dft8<T, INV>(v[u]);
-      } else {
-        static_assert(R == 4, "radix 4, 8 or 16");
-        dft4<T, INV>(v[u][0], v[u][1], v[u][2], v[u][3]);
-      }
-#pragma unroll
-      for (int m = 0; m < R; ++m) o_[m * NS] = v[u][m];
+      for (int m = 0; m < 16; ++m) o_[m] = v[u][m];
     }
   }
   __syncthreads();
 }
 
-// NB length-128 FFTs (radix 16, then radix 8) from x (row stride LD),
-// scratch y; the result ends in x.
-template <typename T, bool INV, int NB, int LD, int HM = 0>
-__device__ __forceinline__ void fft_tile(cpx<T>* x, cpx<T>* y, const cpx<T>* tw, const cpx<T>* __restrict__ H = nullptr) {
-  static_assert(kTN == 128, "stage list is for length 128");
-  tile_stage<T, INV, NB, LD, 1, 16, HM>(x, y, tw, H);
-  tile_stage<T, INV, NB, LD, 16, 8, 0>(y, x, tw, nullptr);
+// tw8[(r - 1) * 16 + j] = w^(r j), r = 1..7, j < 16 (LDS; lanes along j)
+template <typename T, bool INV, int NB>
+__device__ __forceinline__ void tile_stage2(const cpx<T>* __restrict__ x, cpx<T>* __restrict__ y, const cpx<T>* tw8) {
+  constexpr int ITEMS = NB * 16, U = (ITEMS + kTNT - 1) / kTNT;
+  cpx<T> v[U][8];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int wi = threadIdx.x + u * kTNT;
+    if (ITEMS % kTNT == 0 || wi < ITEMS) {
+      const int b = wi >> 4, j = wi & 15;
+#pragma unroll
+      for (int r = 0; r < 8; ++r) v[u][r] = x[p16(b, j + 16 * r)];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int wi = threadIdx.x + u * kTNT;
+    if (ITEMS % kTNT == 0 || wi < ITEMS) {
+      const int b = wi >> 4, j = wi & 15;
+      if (j) {
+#pragma unroll
+        for (int r = 1; r < 8; ++r) {
+          const cpx<T> w = tw8[(r - 1) * 16 + j];
+          v[u][r] = INV ? cmulc(v[u][r], w) : cmul(v[u][r], w);
+        }
+      }
+      dft8<T, INV>(v[u]);
+      cpx<T>* o_ = y + b * kTLD + j;
+#pragma unroll
+      for (int m = 0; m < 8; ++m) o_[16 * m] = v[u][m];
+    }
+  }
+  __syncthreads();
 }
 
-// Row stride of the tile buffers (packed rows and column-major half spectra):
-// one element of padding, so that the transposes between them (lanes along
-// the packed rows) and the first stage's writes meet distinct LDS banks.
-constexpr int kTLD = kTN + 1;
-static_assert(kTN / 2 * kTLD <= kTBuf && kTH * kTLD <= kTBuf, "tile buffers fit");
+// NB length-128 FFTs in place in x (row stride kTLD), y the stage scratch.
+template <typename T, bool INV, int NB, int HM = 0>
+__device__ __forceinline__ void fft_tile(cpx<T>* x, cpx<T>* y, const cpx<T>* tw8, const cpx<T>* __restrict__ H = nullptr) {
+  static_assert(kTN == 128, "stage list is for length 128");
+  tile_stage1<T, INV, NB, HM>(x, y, H);
+  tile_stage2<T, INV, NB>(y, x, tw8);
+}
 
 enum { TILE_B = 0, TILE_BT0 = 1, TILE_BT = 2 };
 
@@ -968,12 +1009,15 @@ enum { TILE_B = 0, TILE_BT0 = 1, TILE_BT = 2 };
 template <typename T, int MODE>
 __global__ void __launch_bounds__(kTNT) k_tile(Args<T> a, const T* __restrict__ e_in, T* __restrict__ e_out, int it) {
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ cpx<T> tw[kTN];
+  __shared__ cpx<T> tw8[7 * 16];
   cpx<T>* X = reinterpret_cast<cpx<T>*>(smem);
   cpx<T>* Y = X + kTBuf;
   const int ty = blockIdx.x / a.tiles_x, tx = blockIdx.x - ty * a.tiles_x;
   const int y0 = ty * kTV - kTHalo, x0 = tx * kTV - kTHalo;   // image position of tile element (0, 0)
-  if (threadIdx.x < kTN) tw[threadIdx.x] = a.twt[threadIdx.x];
+  if (threadIdx.x < 7 * 16) {
+    const int r = threadIdx.x / 16 + 1, j = threadIdx.x & 15;
+    tw8[threadIdx.x] = a.twt[(r * j) & (kTN - 1)];
+  }
   // load: packed row pr holds tile rows 2 pr (real part) and 2 pr + 1 (imaginary part);
   // thread t takes column t mod 128 of packed rows t / 128 + 8 u
   constexpr int LU = kTN * kTN / 2 / kTNT;
@@ -1018,7 +1062,7 @@ __global__ void __launch_bounds__(kTNT) k_tile(Args<T> a, const T* __restrict__ 
   }
   if (MODE == TILE_BT) put_partial(a, part, P_EE, it);   // contains the barrier the FFT needs
   else __syncthreads();
-  fft_tile<T, false, kTN / 2, kTLD>(X, Y, tw);
+  fft_tile<T, false, kTN / 2>(X, Y, tw8);
   // half spectra of the tile rows, column-major: Y[kx * kTLD + r] (lanes along the packed rows)
   constexpr int UU = (kTH * (kTN / 2) + kTNT - 1) / kTNT;
 #pragma unroll
@@ -1033,8 +1077,8 @@ __global__ void __launch_bounds__(kTNT) k_tile(Args<T> a, const T* __restrict__ 
     }
   }
   __syncthreads();
-  fft_tile<T, false, kTH, kTLD>(Y, X, tw);
-  fft_tile<T, true, kTH, kTLD, MODE == TILE_B ? 1 : 2>(Y, X, tw, a.Ht);
+  fft_tile<T, false, kTH>(Y, X, tw8);
+  fft_tile<T, true, kTH, MODE == TILE_B ? 1 : 2>(Y, X, tw8, a.Ht);
   // packed rows 16..47 again: Z[k] = Q0[k] + i Q1[k], the upper half by conjugate symmetry
   constexpr int PR0 = kTHalo / 2, NPR = kTV / 2;
 #pragma unroll
@@ -1051,7 +1095,7 @@ __global__ void __launch_bounds__(kTNT) k_tile(Args<T> a, const T* __restrict__ 
     X[pr * kTLD + k] = {q0.x - q1.y, q0.y + q1.x};
   }
   __syncthreads();
-  fft_tile<T, true, NPR, kTLD>(X + PR0 * kTLD, Y + PR0 * kTLD, tw);
+  fft_tile<T, true, NPR>(X + PR0 * kTLD, Y, tw8);
   // the owned pixels
   T* out = MODE == TILE_B ? a.q : a.w;
   double qq = 0.0;
