@@ -60,6 +60,13 @@ template <typename T>
 constexpr int lt_lanes() { return sizeof(T) == 4 ? 8 : 16; }
 template <typename T>
 constexpr int lt_groups() { return sizeof(T) == 4 ? 4 : 1; }
+// FP32: a node with more entries than this (the few nodes near the critical
+// curves, up to ~300 entries) is summed by a wave of its own in extra blocks
+// of the L^T launch instead of by lt_lanes lanes, which would make it the
+// launch's longest chain of loads
+template <typename T>
+constexpr int lt_heavy() { return sizeof(T) == 4 ? 64 : 0x7fffffff; }
+constexpr int kLtHeavyBlocks = 64;
 constexpr int kSortChunk = 1024;      // keys of one node staged in LDS by the sort
 constexpr int kMaxParts = 1024;       // blocks of the node kernels (grid-stride loops)
 constexpr int kMaxImage = 2048;       // image side
@@ -128,6 +135,9 @@ struct Args {
   Sub<T>* sub;          // [J n^2] cell and fractions of each subpixel
   int32_t* cnt;         // [I] entries per node
   int32_t* tsum;        // [tiles] entries per tile of 1024 nodes, then the tile's start
+  int32_t* hsum;        // [tiles + 1] heavy nodes (more than lt_heavy entries) per tile, then the
+                        // tile's start in heavy[]; hsum[tiles] = their count
+  int32_t* heavy;       // [I] the heavy nodes in ascending order
   int32_t* rowptr;      // [I + 1]
   int32_t* cursor;      // [I]
   int32_t* key;         // [cap] (subpixel, tap) of each entry, in fill order
@@ -153,7 +163,7 @@ struct Args {
   int32_t* done;        // [n_iter + 1]: the iteration stopped before iteration k
   int32_t* upd;         // [n_iter]: iteration k updated s
   int32_t* flags;       // [1]: invalid genome
-  int n_iter, max_blocks, nb_row, nb_node, nb_lt;
+  int n_iter, max_blocks, nb_row, nb_node, nb_lt, nb_heavy;
 };
 
 enum { P_QQ = 0, P_EE = 1, P_GG = 2, P_SS = 3 };
@@ -447,51 +457,71 @@ __device__ __forceinline__ int block_scan_excl(int v, int* total) {
 template <typename T>
 __global__ void __launch_bounds__(kNT) k_tile_sums(Args<T> a) {
   const int i0 = blockIdx.x * kTile;
-  int v = 0;
+  int v = 0, hv = 0;
   for (int k = 0; k < kTile / kNT; ++k) {
     const int i = i0 + threadIdx.x * (kTile / kNT) + k;
-    if (i < a.I) v += a.cnt[i];
+    if (i < a.I) {
+      v += a.cnt[i];
+      hv += a.cnt[i] > lt_heavy<T>();
+    }
   }
-  int total;
+  int total, htotal;
   (void)block_scan_excl(v, &total);
-  if (threadIdx.x == 0) a.tsum[blockIdx.x] = total;
+  (void)block_scan_excl(hv, &htotal);
+  if (threadIdx.x == 0) {
+    a.tsum[blockIdx.x] = total;
+    a.hsum[blockIdx.x] = htotal;
+  }
 }
 
 template <typename T>
 __global__ void __launch_bounds__(kNT) k_tile_scan(Args<T> a) {
   const int tiles = (a.I + kTile - 1) / kTile;   // <= kNT * 4 for I <= 2^20
-  int v[4];
-  int loc = 0;
+  int v[4], hv[4];
+  int loc = 0, hloc = 0;
   for (int k = 0; k < 4; ++k) {
     const int t = threadIdx.x * 4 + k;
     v[k] = t < tiles ? a.tsum[t] : 0;
+    hv[k] = t < tiles ? a.hsum[t] : 0;
     loc += v[k];
+    hloc += hv[k];
   }
-  int total;
+  int total, htotal;
   int run = block_scan_excl(loc, &total);
+  int hrun = block_scan_excl(hloc, &htotal);
   for (int k = 0; k < 4; ++k) {
     const int t = threadIdx.x * 4 + k;
-    if (t < tiles) a.tsum[t] = run;
+    if (t < tiles) {
+      a.tsum[t] = run;
+      a.hsum[t] = hrun;
+    }
     run += v[k];
+    hrun += hv[k];
   }
-  if (threadIdx.x == 0) a.rowptr[a.I] = total;
+  if (threadIdx.x == 0) {
+    a.rowptr[a.I] = total;
+    a.hsum[tiles] = htotal;
+  }
 }
 
 template <typename T>
 __global__ void __launch_bounds__(kNT) k_tile_write(Args<T> a) {
   const int i0 = blockIdx.x * kTile + threadIdx.x * (kTile / kNT);
   int v[kTile / kNT];
-  int loc = 0;
+  int loc = 0, hloc = 0;
   for (int k = 0; k < kTile / kNT; ++k) {
     v[k] = i0 + k < a.I ? a.cnt[i0 + k] : 0;
     loc += v[k];
+    hloc += v[k] > lt_heavy<T>();
   }
-  int total;
+  int total, htotal;
   int run = a.tsum[blockIdx.x] + block_scan_excl(loc, &total);
+  int hrun = a.hsum[blockIdx.x] + block_scan_excl(hloc, &htotal);
   for (int k = 0; k < kTile / kNT; ++k) {
     if (i0 + k < a.I) {
       a.rowptr[i0 + k] = run;
       a.cursor[i0 + k] = run;
+      if (v[k] > lt_heavy<T>()) a.heavy[hrun++] = i0 + k;
     }
     run += v[k];
   }
@@ -1184,19 +1214,58 @@ __global__ void __launch_bounds__(kNT) k_tile_psf_cols(Args<T> a) {
 template <typename T>
 __global__ void __launch_bounds__(kLtNT) k_lt(Args<T> a, int it) {
   constexpr int kLtU = lt_groups<T>(), kLtG = lt_lanes<T>();
+  double gg = 0.0;
+  const int nb_reg = a.nb_lt - a.nb_heavy;
+  if ((int)blockIdx.x < a.nb_heavy) {
+    // heavy nodes (the first blocks, so that their longer chains start first):
+    // one wave per node, lane l adding entries l, l + 64, ... in order (four
+    // loads in flight), then a fixed butterfly over the wave
+    const int lane = threadIdx.x & (kWave - 1);
+    const int nh = a.hsum[(a.I + kTile - 1) / kTile];
+    constexpr int waves = kLtNT / kWave;
+    for (int h = (int)blockIdx.x * waves + (int)threadIdx.x / kWave; h < nh; h += a.nb_heavy * waves) {
+      const int node = a.heavy[h];
+      const int e1 = a.rowptr[node + 1];
+      int e = a.rowptr[node] + lane;
+      T acc = 0;
+      for (; e + 3 * kWave < e1; e += 4 * kWave) {
+        const LtE<T> t0 = a.lt[e], t1 = a.lt[e + kWave], t2 = a.lt[e + 2 * kWave], t3 = a.lt[e + 3 * kWave];
+        const T w0 = a.w[t0.pix], w1 = a.w[t1.pix], w2 = a.w[t2.pix], w3 = a.w[t3.pix];
+        acc += t0.w * w0;
+        acc += t1.w * w1;
+        acc += t2.w * w2;
+        acc += t3.w * w3;
+      }
+      for (; e < e1; e += kWave) {
+        const LtE<T> tt = a.lt[e];
+        acc += tt.w * a.w[tt.pix];
+      }
+#pragma unroll
+      for (int o = kWave / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kWave);
+      if (lane == 0) {
+        a.g[node] = acc;
+        gg += (double)acc * (double)acc;
+      }
+    }
+    put_partial(a, gg, P_GG, it);
+    return;
+  }
   const int l = threadIdx.x & (kLtG - 1);
   constexpr int per_pass = kLtNT / kLtG;
-  double gg = 0.0;
-  for (int n0 = blockIdx.x * per_pass * kLtU; n0 < a.I; n0 += gridDim.x * per_pass * kLtU) {
+  const int rb = (int)blockIdx.x - a.nb_heavy;
+  for (int n0 = rb * per_pass * kLtU; n0 < a.I; n0 += nb_reg * per_pass * kLtU) {
     // kLtU node groups per thread: their row bounds, first entries and w values in flight together
     int node[kLtU], e[kLtU], e1[kLtU];
+    bool own[kLtU];   // the node is summed here (in range and not heavy)
     T acc[kLtU];
 #pragma unroll
     for (int u = 0; u < kLtU; ++u) {
       node[u] = n0 + u * per_pass + threadIdx.x / kLtG;
       const bool ok = node[u] < a.I;
-      e[u] = ok ? a.rowptr[node[u]] + l : 0;
-      e1[u] = ok ? a.rowptr[node[u] + 1] : 0;
+      const int r0 = ok ? a.rowptr[node[u]] : 0, r1 = ok ? a.rowptr[node[u] + 1] : 0;
+      own[u] = ok && r1 - r0 <= lt_heavy<T>();
+      e[u] = r0 + l;
+      e1[u] = own[u] ? r1 : 0;
       acc[u] = 0;
     }
     LtE<T> t[kLtU];
@@ -1227,7 +1296,7 @@ __global__ void __launch_bounds__(kLtNT) k_lt(Args<T> a, int it) {
     for (int u = 0; u < kLtU; ++u) {
 #pragma unroll
       for (int o = kLtG / 2; o > 0; o >>= 1) acc[u] += __shfl_xor(acc[u], o, kLtG);
-      if (node[u] < a.I && l == 0) {
+      if (own[u] && l == 0) {
         a.g[node[u]] = acc[u];
         gg += (double)acc[u] * (double)acc[u];
       }
@@ -1255,18 +1324,29 @@ __global__ void __launch_bounds__(kNT) k_start(Args<T> a) {
 // next iteration.  Grid-stride over the nodes (nb_node <= kMaxParts blocks).
 template <typename T>
 __global__ void __launch_bounds__(kNT) k_update(Args<T> a, int it) {
+  // the first node's operands are loaded before the |g|^2 total, whose
+  // partial loads and block reduction then hide their latency
+  const int i0 = blockIdx.x * kNT + threadIdx.x;
+  T s0 = 0, p0 = 0, g0 = 0;
+  if (i0 < a.I) {
+    s0 = a.s[i0];
+    p0 = a.p[i0];
+    g0 = a.g[i0];
+  }
   const double alpha = a.alpha[it];
   const bool moved = alpha > 0.0;
   const double gn = block_total(part_of(a, P_GG, it), a.nb_lt);
   const bool stop = !moved || !(gn > 0.0);
   const double beta = stop ? 0.0 : gn / a.gg[it];
   double ss = 0.0;
-  for (int i = blockIdx.x * kNT + threadIdx.x; i < a.I; i += gridDim.x * kNT) {
-    T s = a.s[i];
+  for (int i = i0; i < a.I; i += gridDim.x * kNT) {
+    const bool first = i == i0;
+    T s = first ? s0 : a.s[i];
+    const T p = first ? p0 : a.p[i], g = first ? g0 : a.g[i];
     if (moved) {
-      s += (T)alpha * a.p[i];
+      s += (T)alpha * p;
       a.s[i] = s;
-      a.p[i] = a.g[i] + (T)beta * a.p[i];
+      a.p[i] = g + (T)beta * p;
     }
     a.s_iter[(long)it * a.I + i] = s;
     ss += (double)s * (double)s;
@@ -1385,6 +1465,8 @@ static Layout make_layout(int nx, int ny, int nsub, int ns, int K, int interp, i
     sizes[n++] = (sz == 8 ? 24 : 12) * (size_t)(J * n2);   // sub
     sizes[n++] = 4 * (size_t)I;                       // cnt
     sizes[n++] = 4 * (size_t)((I + kTile - 1) / kTile);   // tsum
+    sizes[n++] = 4 * (size_t)((I + kTile - 1) / kTile + 1);   // hsum
+    sizes[n++] = 4 * (size_t)I;                       // heavy
     sizes[n++] = 4 * (size_t)(I + 1);                 // rowptr
     sizes[n++] = 4 * (size_t)I;                       // cursor
     sizes[n++] = 4 * (size_t)L.cap;                   // key
@@ -1435,6 +1517,8 @@ static Args<T> bind(const Layout& L, unsigned char* ws, bool solve) {
     a.sub = reinterpret_cast<Sub<T>*>(ws + L.off[i++]);
     a.cnt = reinterpret_cast<int32_t*>(ws + L.off[i++]);
     a.tsum = reinterpret_cast<int32_t*>(ws + L.off[i++]);
+    a.hsum = reinterpret_cast<int32_t*>(ws + L.off[i++]);
+    a.heavy = reinterpret_cast<int32_t*>(ws + L.off[i++]);
     a.rowptr = reinterpret_cast<int32_t*>(ws + L.off[i++]);
     a.cursor = reinterpret_cast<int32_t*>(ws + L.off[i++]);
     a.key = reinterpret_cast<int32_t*>(ws + L.off[i++]);
@@ -1549,7 +1633,9 @@ static int solve_impl(const sl_problem* pb, const double* lens, int ns, int n_it
   a.n_iter = n_iter;
   a.nb_row = (g.ny + 1) / 2;
   a.nb_node = (int)std::min<long>(nblk(a.I, kNT), kMaxParts);
-  a.nb_lt = (int)std::min<long>(nblk((long)a.I * lt_lanes<T>(), (long)kLtNT * lt_groups<T>()), kMaxParts);
+  a.nb_heavy = sizeof(T) == 4 ? kLtHeavyBlocks : 0;
+  a.nb_lt = (int)std::min<long>(nblk((long)a.I * lt_lanes<T>(), (long)kLtNT * lt_groups<T>()), kMaxParts - a.nb_heavy) +
+            a.nb_heavy;
   // FP32 with a PSF no wider than the tile's halo: the tiled blur (k_tile)
   a.tiles_x = (a.nx + kTV - 1) / kTV;
   a.tiles_y = (a.ny + kTV - 1) / kTV;
