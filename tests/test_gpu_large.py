@@ -134,6 +134,41 @@ def test_large_solve_medium_vs_oracle(sl, prec, interp):
     assert out["s_off"].tolist() == [0, w.ns * w.ns]
 
 
+@pytest.mark.parametrize("nx,ny,K", [(70, 130, 1), (100, 60, 15), (96, 80, 81)])
+def test_large_solve_psf_sizes_fp32(sl, nx, ny, K):
+    """FP32 solves with other PSF widths and ragged image sizes: K = 1 and
+    K = 15 take the overlap-save tiles (64 x 64 owned blocks, the image's
+    last row and column of tiles cut), K = 81 is wider than a tile's halo and
+    takes the padded frame; each against the oracle within its Monte Carlo
+    arithmetic envelope (24 draws), 16 iterations."""
+    n_iter = 16
+    psf = np.ones((1, 1)) if K == 1 else synthgen.sinc_moffat_psf(K, 3.0 if K < 30 else 6.0)
+    w = synthgen.Workload("psf-sizes", 13, nx, ny, 0.04, 2, 4, 40, 1.4, K, 3.0, 60.0, "identity", (), 0.0,
+                          "sersic", 4, psf_kind="sinc-moffat")
+    lens = np.array([1.0, 0.8, 0.4, 0.03, 0.2, 0.01, -0.02])
+    clean = mock.clean_image(lens, synthgen.source_blobs(w), nx, ny, w.pix, 4, psf)
+    sigma = clean.max() / 60.0
+    d = (clean + sigma * synthgen.noise_unit(w)).astype(np.float32).astype(np.float64)
+    print(f"large solve fp32 {nx}x{ny} K={K}", flush=True)
+    out = _np(_solver(sl, d, sigma, psf, w, torch.float32).solve_large(lens, w.ns, n_iter))
+
+    def make(x):
+        return solve.Problem(lens, x, sigma, psf, nx, ny, w.pix, w.nsub_model, w.ns, w.half_width,
+                             "identity", "bilinear", blur="fft")
+    ref, dev, ds, corners = cgls_envelope.envelope(make, d, "f32", K, n_iter, draws=24)
+    assert np.all(out["status"][0] == 0), out["status"]
+    for key in ("chi2", "reg"):
+        err = np.abs(out[key][0] - ref[key])
+        bound = 10 * dev[key] + FLOOR["f32"] * np.abs(ref[key])
+        assert np.all(err <= bound), (key, np.nonzero(err > bound)[0], err / np.abs(ref[key]))
+    k = int(out["k_star"][0])
+    assert k == lcurve.corner(out["reg"][0], out["chi2"][0])[0]
+    assert min(corners) <= k <= max(corners), (k, corners)
+    s_ref = ref["s"][k]
+    err = np.linalg.norm(out["s_corner"] - s_ref)
+    assert err <= 10 * ds[k] + FLOOR["f32"] * np.linalg.norm(s_ref), (k, err / np.linalg.norm(s_ref))
+
+
 def test_large_solve_full_shape_fp32(sl):
     """The large-scale shape (synthgen.LARGE) in FP32, the configuration bench.py
     times, against the oracle (computed here) within the stored FP32 envelope
