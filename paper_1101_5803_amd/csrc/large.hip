@@ -149,8 +149,9 @@ struct Args {
   T* q;                 // [J] B L p
   T* e0;                // [J] image residual, two buffers used in turn
   T* e1;
-  cpx<T>* Ht;           // [65][128] PSF spectrum on the tile / 128^2
+  cpx<T>* Ht;           // [65][96] PSF spectrum on the tile / (128 96)
   cpx<T>* twt;          // [128] exp(-2 pi i m / 128)
+  cpx<T>* twc;          // [96] exp(-2 pi i m / 96)
   cpx<double>* T1t;     // [K][65] first stage of the tile's PSF transform
   int tiled, tiles_x, tiles_y, nb_qq, nb_ee;
   T* s;                 // [I]
@@ -840,19 +841,23 @@ __global__ void __launch_bounds__(kRowNT) k_rowinv(Args<T> a, T* __restrict__ ds
 }
 
 // ---------------------------------------------------------------- tiled blur
-// Overlap-save on 128 x 128 tiles (FP32, PSF side <= 65): output tile (ty, tx)
-// owns the 64 x 64 pixels from (64 ty, 64 tx); its input is the 128 x 128
-// region 32 pixels wider on every side (zero outside the image), on which the
-// circular convolution equals the zero-padded one for the owned pixels.  One
-// block per tile runs the whole 2-D transform in LDS: two real rows packed per
-// complex row FFT, their half spectra (65 columns) transformed along the
-// columns, the product with the tile's PSF spectrum, and back.  One launch per
-// blur instead of three passes through HBM.
-constexpr int kTN = 128;                      // tile side (FFT length)
-constexpr int kTV = 64;                       // owned outputs per side
-constexpr int kTHalo = (kTN - kTV) / 2;       // 32: PSF half-width it allows
+// Overlap-save on 128-wide, 96-tall tiles (FP32, PSF side <= 65): output tile
+// (ty, tx) owns the 32 x 64 pixels (rows x columns) from (32 ty, 64 tx); its
+// input is the 96 x 128 region 32 pixels wider on every side (zero outside
+// the image), on which the circular convolution equals the zero-padded one for
+// the owned pixels.  One block per tile runs the whole 2-D transform in LDS:
+// two real rows packed per complex row FFT (length 128), their half spectra
+// (65 columns) transformed along the columns (length 96), the product with the
+// tile's PSF spectrum, and back.  One launch per blur instead of three passes
+// through HBM; 32-row owned blocks give 200 tiles at 640 x 640, so that most
+// compute units take one.
+constexpr int kTN = 128;                      // tile width (row FFT length)
+constexpr int kTNY = 96;                      // tile height (column FFT length)
+constexpr int kTV = 64;                       // owned columns
+constexpr int kTVY = 32;                      // owned rows
+constexpr int kTHalo = 32;                    // halo on every side: the PSF half-width it allows
+static_assert(kTN - kTV == 2 * kTHalo && kTNY - kTVY == 2 * kTHalo, "tile = owned block + halo");
 constexpr int kTH = kTN / 2 + 1;              // 65 half-spectrum columns
-constexpr int kTBuf = kTH * (kTN + kTN / 16 + 1);   // complex elements per LDS buffer (padded rows)
 constexpr int kTNT = 1024;
 
 // In-register DFTs of length 4, 8 and 16 (INV: the conjugate kernel), in
@@ -926,7 +931,6 @@ __device__ __forceinline__ void dft16(cpx<T> (&v)[16]) {
 // group of 16, every LDS access of both stages meets distinct banks.
 constexpr int kTLD = kTN + 1;   // 129: odd, so the transposes (lanes along rows) meet distinct banks
 constexpr int kTP = kTN + kTN / 16 + 1;   // 137
-static_assert(kTH * kTP <= kTBuf && kTH * kTLD <= kTBuf, "tile buffers fit");
 
 __device__ __forceinline__ int p16(int b, int e) { return b * kTP + e + (e >> 4); }
 
@@ -1027,30 +1031,151 @@ __device__ __forceinline__ void fft_tile(cpx<T>* x, cpx<T>* y, const cpx<T>* tw8
   tile_stage2<T, INV, NB>(y, x, tw8);
 }
 
+// Column transforms (length 96, the tile height) as two Stockham stages:
+// stage 1 (radix 16, span 1): butterfly j < 6 of a column reads x[j + 6 r]
+// (r < 16) and writes its DFT16 to positions 16 j + m; stage 2 (radix 6,
+// span 16): butterfly j < 16 reads positions j + 16 r (r < 6), turns input r
+// by w96^(r j) and writes its DFT6 to positions j + 16 m.  Columns live with
+// stride kTLDC, the intermediate in a scratch of stride kTPC with one pad
+// element after every 16.
+constexpr int kTLDC = kTNY + 1;                 // 97
+constexpr int kTPC = kTNY + kTNY / 16 + 1;      // 103
+constexpr int kTBuf = kTH * kTPC;               // complex elements per LDS buffer
+static_assert(kTNY / 2 * kTP <= kTBuf && kTH * kTLDC <= kTBuf && kTNY / 2 * kTLD <= kTBuf, "tile buffers fit");
+
+__device__ __forceinline__ int p16c(int b, int e) { return b * kTPC + e + (e >> 4); }
+
+// DFT3 and DFT6 (INV: the conjugate kernel), natural order in and out; the
+// length 6 splits as 3 x 2 (DFT3s, the factor w6^(n2 k1), DFT2s)
+template <typename T, bool INV>
+__device__ __forceinline__ void dft3(cpx<T>& a0, cpx<T>& a1, cpx<T>& a2) {
+  const T sn = INV ? (T)0.86602540378443865 : (T)-0.86602540378443865;   // sin of -+2 pi / 3
+  const cpx<T> sm = cadd(a1, a2), d = csub(a1, a2);
+  const cpx<T> t = {a0.x - (T)0.5 * sm.x, a0.y - (T)0.5 * sm.y};
+  const cpx<T> u = {-sn * d.y, sn * d.x};   // i sn d
+  a0 = cadd(a0, sm);
+  a1 = cadd(t, u);
+  a2 = csub(t, u);
+}
+
+template <typename T, bool INV>
+__device__ __forceinline__ void dft6(cpx<T> (&v)[6]) {
+  dft3<T, INV>(v[0], v[2], v[4]);   // n2 = 0: result k1 in slot 2 k1
+  dft3<T, INV>(v[1], v[3], v[5]);   // n2 = 1: result k1 in slot 2 k1 + 1
+  const T h = (T)0.5, r3 = INV ? (T)0.86602540378443865 : (T)-0.86602540378443865;
+  const cpx<T> w1 = {h, r3}, w2 = {-h, r3};   // w6^1, w6^2
+  cpx<T> o[6];
+#pragma unroll
+  for (int k1 = 0; k1 < 3; ++k1) {
+    const cpx<T> y0 = v[2 * k1];
+    const cpx<T> y1 = k1 == 0 ? v[1] : cmul(v[2 * k1 + 1], k1 == 1 ? w1 : w2);
+    o[k1] = cadd(y0, y1);
+    o[k1 + 3] = csub(y0, y1);
+  }
+#pragma unroll
+  for (int m = 0; m < 6; ++m) v[m] = o[m];
+}
+
+// HM = 1 (2): each input times H (conj H), stored [kx][96], first.
+template <typename T, bool INV, int HM>
+__device__ __forceinline__ void col_stage1(const cpx<T>* __restrict__ x, cpx<T>* __restrict__ y,
+                                           const cpx<T>* __restrict__ H) {
+  constexpr int ITEMS = kTH * 6;
+  static_assert(ITEMS <= kTNT, "one butterfly per thread");
+  const int wi = threadIdx.x;
+  cpx<T> v[16];
+  if (wi < ITEMS) {
+    const int b = wi / 6, j = wi - b * 6;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = x[b * kTLDC + j + 6 * r];
+    if (HM) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const cpx<T> hh = H[b * kTNY + j + 6 * r];
+        v[r] = HM == 1 ? cmul(v[r], hh) : cmulc(v[r], hh);
+      }
+    }
+  }
+  if (wi < ITEMS) {
+    const int b = wi / 6, j = wi - b * 6;
+    dft16<T, INV>(v);
+    cpx<T>* o_ = y + p16c(b, 16 * j);
+#pragma unroll
+    for (int m = 0; m < 16; ++m) o_[m] = v[m];
+  }
+  __syncthreads();
+}
+
+// tw6[(r - 1) * 16 + j] = w96^(r j), r = 1..5, j < 16 (LDS)
+template <typename T, bool INV>
+__device__ __forceinline__ void col_stage2(const cpx<T>* __restrict__ x, cpx<T>* __restrict__ y, const cpx<T>* tw6) {
+  constexpr int ITEMS = kTH * 16, U = (ITEMS + kTNT - 1) / kTNT;
+  cpx<T> v[U][6];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int wi = threadIdx.x + u * kTNT;
+    if (wi < ITEMS) {
+      const int b = wi >> 4, j = wi & 15;
+#pragma unroll
+      for (int r = 0; r < 6; ++r) v[u][r] = x[p16c(b, j + 16 * r)];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int wi = threadIdx.x + u * kTNT;
+    if (wi < ITEMS) {
+      const int b = wi >> 4, j = wi & 15;
+      if (j) {
+#pragma unroll
+        for (int r = 1; r < 6; ++r) {
+          const cpx<T> w = tw6[(r - 1) * 16 + j];
+          v[u][r] = INV ? cmulc(v[u][r], w) : cmul(v[u][r], w);
+        }
+      }
+      dft6<T, INV>(v[u]);
+      cpx<T>* o_ = y + b * kTLDC + j;
+#pragma unroll
+      for (int m = 0; m < 6; ++m) o_[16 * m] = v[u][m];
+    }
+  }
+  __syncthreads();
+}
+
+// The 65 half-spectrum columns (length 96) in place in x (stride kTLDC), y the stage scratch.
+template <typename T, bool INV, int HM = 0>
+__device__ __forceinline__ void fft_cols(cpx<T>* x, cpx<T>* y, const cpx<T>* tw6, const cpx<T>* __restrict__ H = nullptr) {
+  static_assert(kTNY == 96, "stage list is for length 96");
+  col_stage1<T, INV, HM>(x, y, H);
+  col_stage2<T, INV>(y, x, tw6);
+}
+
 enum { TILE_B = 0, TILE_BT0 = 1, TILE_BT = 2 };
 
 // One tile of a blur.  TILE_B: q = B y on the owned pixels, with the block's
 // |q|^2 partial.  TILE_BT0: w = B^T e0 (e0 = d).  TILE_BT: the residual
 // update e_out = e_in - alpha q (alpha of iteration it; written on the owned
 // pixels, recomputed on the halo), the block's |e|^2 partial, and
-// w = B^T e_out.  Only the packed rows that hold owned pixels (16..47) take
-// the inverse row transform.  Packed rows and column-major half spectra are
-// kept with row stride kTLD.
+// w = B^T e_out.  Only the packed rows that hold owned pixels (16..31) take
+// the inverse row transform.  Packed rows are kept with row stride kTLD,
+// column-major half spectra with stride kTLDC.
 template <typename T, int MODE>
 __global__ void __launch_bounds__(kTNT) k_tile(Args<T> a, const T* __restrict__ e_in, T* __restrict__ e_out, int it) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ cpx<T> tw8[7 * 16];
+  __shared__ cpx<T> tw6[5 * 16];
   cpx<T>* X = reinterpret_cast<cpx<T>*>(smem);
   cpx<T>* Y = X + kTBuf;
   const int ty = blockIdx.x / a.tiles_x, tx = blockIdx.x - ty * a.tiles_x;
-  const int y0 = ty * kTV - kTHalo, x0 = tx * kTV - kTHalo;   // image position of tile element (0, 0)
+  const int y0 = ty * kTVY - kTHalo, x0 = tx * kTV - kTHalo;   // image position of tile element (0, 0)
   if (threadIdx.x < 7 * 16) {
     const int r = threadIdx.x / 16 + 1, j = threadIdx.x & 15;
     tw8[threadIdx.x] = a.twt[(r * j) & (kTN - 1)];
+    if (r <= 5) tw6[threadIdx.x] = a.twc[(r * j) % kTNY];
   }
   // load: packed row pr holds tile rows 2 pr (real part) and 2 pr + 1 (imaginary part);
   // thread t takes column t mod 128 of packed rows t / 128 + 8 u
-  constexpr int LU = kTN * kTN / 2 / kTNT;
+  constexpr int LU = kTNY / 2 * kTN / kTNT;
+  static_assert(LU * kTNT == kTNY / 2 * kTN, "whole packed rows per pass");
   const int c = threadIdx.x & (kTN - 1), pr0 = threadIdx.x / kTN;
   const int cc = x0 + c;
   const bool col_in = cc >= 0 && cc < a.nx;
@@ -1082,7 +1207,7 @@ __global__ void __launch_bounds__(kTNT) k_tile(Args<T> a, const T* __restrict__ 
         v[u][h] -= (T)alpha * qv[u][h];
         const int r = y0 + 2 * pr + h;
         const int lr = 2 * pr + h - kTHalo, lc = c - kTHalo;
-        if (col_in && r >= 0 && r < a.ny && lr >= 0 && lr < kTV && lc >= 0 && lc < kTV) {   // owned: once
+        if (col_in && r >= 0 && r < a.ny && lr >= 0 && lr < kTVY && lc >= 0 && lc < kTV) {   // owned: once
           e_out[(long)r * a.nx + cc] = v[u][h];
           part += (double)v[u][h] * (double)v[u][h];
         }
@@ -1092,32 +1217,34 @@ __global__ void __launch_bounds__(kTNT) k_tile(Args<T> a, const T* __restrict__ 
   }
   if (MODE == TILE_BT) put_partial(a, part, P_EE, it);   // contains the barrier the FFT needs
   else __syncthreads();
-  fft_tile<T, false, kTN / 2>(X, Y, tw8);
-  // half spectra of the tile rows, column-major: Y[kx * kTLD + r] (lanes along the packed rows)
-  constexpr int UU = (kTH * (kTN / 2) + kTNT - 1) / kTNT;
+  fft_tile<T, false, kTNY / 2>(X, Y, tw8);
+  // half spectra of the tile rows, column-major: Y[kx * kTLDC + r] (lanes along the packed rows)
+  constexpr int NPK = kTNY / 2;
+  constexpr int UU = (kTH * NPK + kTNT - 1) / kTNT;
 #pragma unroll
   for (int u = 0; u < UU; ++u) {
     const int i = threadIdx.x + u * kTNT;
-    if (i < kTH * (kTN / 2)) {
-      const int k = i / (kTN / 2), pr = i - k * (kTN / 2);
+    if (i < kTH * NPK) {
+      const int k = i / NPK, pr = i - k * NPK;
       const cpx<T> zk = X[pr * kTLD + k], zm = X[pr * kTLD + ((kTN - k) & (kTN - 1))];
       const T h = (T)0.5;
-      Y[k * kTLD + 2 * pr] = {h * (zk.x + zm.x), h * (zk.y - zm.y)};
-      Y[k * kTLD + 2 * pr + 1] = {h * (zk.y + zm.y), h * (zm.x - zk.x)};
+      Y[k * kTLDC + 2 * pr] = {h * (zk.x + zm.x), h * (zk.y - zm.y)};
+      Y[k * kTLDC + 2 * pr + 1] = {h * (zk.y + zm.y), h * (zm.x - zk.x)};
     }
   }
   __syncthreads();
-  fft_tile<T, false, kTH>(Y, X, tw8);
-  fft_tile<T, true, kTH, MODE == TILE_B ? 1 : 2>(Y, X, tw8, a.Ht);
-  // packed rows 16..47 again: Z[k] = Q0[k] + i Q1[k], the upper half by conjugate symmetry
-  constexpr int PR0 = kTHalo / 2, NPR = kTV / 2;
+  fft_cols<T, false>(Y, X, tw6);
+  fft_cols<T, true, MODE == TILE_B ? 1 : 2>(Y, X, tw6, a.Ht);
+  // packed rows 16..31 again: Z[k] = Q0[k] + i Q1[k], the upper half by conjugate symmetry
+  constexpr int PR0 = kTHalo / 2, NPR = kTVY / 2;
+  static_assert(NPR * kTN % kTNT == 0, "whole passes");
 #pragma unroll
   for (int u = 0; u < NPR * kTN / kTNT; ++u) {
     const int i = threadIdx.x + u * kTNT;
     const int k = i / NPR, pr = PR0 + (i - k * NPR);
     const bool mirror = k > kTN / 2;
     const int kk = mirror ? kTN - k : k;
-    cpx<T> q0 = Y[kk * kTLD + 2 * pr], q1 = Y[kk * kTLD + 2 * pr + 1];
+    cpx<T> q0 = Y[kk * kTLDC + 2 * pr], q1 = Y[kk * kTLDC + 2 * pr + 1];
     if (mirror) {
       q0.y = -q0.y;
       q1.y = -q1.y;
@@ -1129,11 +1256,12 @@ __global__ void __launch_bounds__(kTNT) k_tile(Args<T> a, const T* __restrict__ 
   // the owned pixels
   T* out = MODE == TILE_B ? a.q : a.w;
   double qq = 0.0;
+  static_assert(kTV * kTVY % kTNT == 0, "whole passes");
 #pragma unroll
-  for (int u = 0; u < kTV * kTV / kTNT; ++u) {
+  for (int u = 0; u < kTV * kTVY / kTNT; ++u) {
     const int i = threadIdx.x + u * kTNT;
     const int lr = i / kTV, lc = i - lr * kTV;
-    const int r = ty * kTV + lr, cx = tx * kTV + lc;
+    const int r = ty * kTVY + lr, cx = tx * kTV + lc;
     if (r < a.ny && cx < a.nx) {
       const int tr = lr + kTHalo, tc = lc + kTHalo;
       const cpx<T> z = X[(tr >> 1) * kTLD + tc];
@@ -1159,13 +1287,15 @@ __global__ void __launch_bounds__(kNT) k_copy_d(Args<T> a) {
   if (j < a.J) a.e0[j] = (T)a.d[j];
 }
 
-// The tile's PSF spectrum Ht[kx][ky] = sum_{a,b} P[a][b] exp(-2 pi i (ky (a - ck) + kx (b - ck)) / 128) / 128^2
+// The tile's PSF spectrum
+//   Ht[kx][ky] = sum_{a,b} P[a][b] exp(-2 pi i (ky (a - ck) / 96 + kx (b - ck) / 128)) / (128 96)
 // in FP64, separably: first T1t[a][kx] over b (and the tile twiddles), then over a.
-__device__ __forceinline__ cpx<double> root128(long m) {
-  m %= kTN;
-  if (m < 0) m += kTN;
+// exp(-2 pi i m / n)
+__device__ __forceinline__ cpx<double> root_of(long m, int n) {
+  m %= n;
+  if (m < 0) m += n;
   double sn, cs;
-  sincospi(-2.0 * (double)m / kTN, &sn, &cs);
+  sincospi(-2.0 * (double)m / n, &sn, &cs);
   return {cs, sn};
 }
 
@@ -1173,14 +1303,18 @@ template <typename T>
 __global__ void __launch_bounds__(kNT) k_tile_psf_rows(Args<T> a) {
   const int idx = blockIdx.x * kNT + threadIdx.x;
   if (idx < kTN) {
-    const cpx<double> u = root128(idx);
+    const cpx<double> u = root_of(idx, kTN);
     a.twt[idx] = {(T)u.x, (T)u.y};
+  }
+  if (idx < kTNY) {
+    const cpx<double> u = root_of(idx, kTNY);
+    a.twc[idx] = {(T)u.x, (T)u.y};
   }
   if (idx >= a.K * kTH) return;
   const int r = idx / kTH, kx = idx - r * kTH;
   double re = 0.0, im = 0.0;
   for (int b = 0; b < a.K; ++b) {
-    const cpx<double> u = root128((long)kx * (b - a.ck));
+    const cpx<double> u = root_of((long)kx * (b - a.ck), kTN);
     const double v = a.psf[r * a.K + b];
     re += v * u.x;
     im += v * u.y;
@@ -1191,16 +1325,16 @@ __global__ void __launch_bounds__(kNT) k_tile_psf_rows(Args<T> a) {
 template <typename T>
 __global__ void __launch_bounds__(kNT) k_tile_psf_cols(Args<T> a) {
   const int idx = blockIdx.x * kNT + threadIdx.x;
-  if (idx >= kTH * kTN) return;
-  const int kx = idx / kTN, ky = idx - kx * kTN;
+  if (idx >= kTH * kTNY) return;
+  const int kx = idx / kTNY, ky = idx - kx * kTNY;
   double re = 0.0, im = 0.0;
   for (int r = 0; r < a.K; ++r) {
-    const cpx<double> u = root128((long)ky * (r - a.ck));
+    const cpx<double> u = root_of((long)ky * (r - a.ck), kTNY);
     const cpx<double> t = a.T1t[r * kTH + kx];
     re += t.x * u.x - t.y * u.y;
     im += t.x * u.y + t.y * u.x;
   }
-  const double sc = 1.0 / ((double)kTN * kTN);
+  const double sc = 1.0 / ((double)kTN * kTNY);
   a.Ht[idx] = {(T)(re * sc), (T)(im * sc)};
 }
 
@@ -1431,7 +1565,7 @@ struct Layout {
   int Nx, Ny, Nh, taps;
   long long cap;
   size_t total;
-  size_t off[40];
+  size_t off[48];
 };
 
 static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -1449,10 +1583,10 @@ static Layout make_layout(int nx, int ny, int nsub, int ns, int K, int interp, i
   L.cap = J * n2 * L.taps;
   const size_t c = 2 * sz;   // one complex element
   const int nb_row = (ny + 1) / 2;
-  const int tiles = ((nx + kTV - 1) / kTV) * ((ny + kTV - 1) / kTV);
+  const int tiles = ((nx + kTV - 1) / kTV) * ((ny + kTVY - 1) / kTVY);
   // row blocks, column blocks, tiles, node blocks
   const int maxb = std::max(std::max(nb_row, L.Nh), std::max(tiles, kMaxParts));
-  size_t sizes[40];
+  size_t sizes[48];
   int n = 0;
   sizes[n++] = c * L.Nx;                              // twx
   sizes[n++] = c * L.Ny;                              // twy
@@ -1479,8 +1613,9 @@ static Layout make_layout(int nx, int ny, int nsub, int ns, int K, int interp, i
     sizes[n++] = sz * (size_t)J;                      // q
     sizes[n++] = sz * (size_t)J;                      // e0
     sizes[n++] = sz * (size_t)J;                      // e1
-    sizes[n++] = c * (size_t)kTBuf;                   // Ht
+    sizes[n++] = c * (size_t)kTH * kTNY;              // Ht
     sizes[n++] = c * (size_t)kTN;                     // twt
+    sizes[n++] = c * (size_t)kTNY;                    // twc
     sizes[n++] = 16 * (size_t)K * kTH;                // T1t
     sizes[n++] = sz * (size_t)I;                      // s
     sizes[n++] = sz * (size_t)I;                      // p
@@ -1533,6 +1668,7 @@ static Args<T> bind(const Layout& L, unsigned char* ws, bool solve) {
     a.e1 = reinterpret_cast<T*>(ws + L.off[i++]);
     a.Ht = reinterpret_cast<cpx<T>*>(ws + L.off[i++]);
     a.twt = reinterpret_cast<cpx<T>*>(ws + L.off[i++]);
+    a.twc = reinterpret_cast<cpx<T>*>(ws + L.off[i++]);
     a.T1t = reinterpret_cast<cpx<double>*>(ws + L.off[i++]);
     a.s = reinterpret_cast<T*>(ws + L.off[i++]);
     a.p = reinterpret_cast<T*>(ws + L.off[i++]);
@@ -1638,7 +1774,7 @@ static int solve_impl(const sl_problem* pb, const double* lens, int ns, int n_it
             a.nb_heavy;
   // FP32 with a PSF no wider than the tile's halo: the tiled blur (k_tile)
   a.tiles_x = (a.nx + kTV - 1) / kTV;
-  a.tiles_y = (a.ny + kTV - 1) / kTV;
+  a.tiles_y = (a.ny + kTVY - 1) / kTVY;
   const int ntiles = a.tiles_x * a.tiles_y;
   a.tiled = sizeof(T) == 4 && a.ck <= kTHalo;
   a.nb_qq = a.tiled ? ntiles : a.nb_row;
@@ -1657,7 +1793,7 @@ static int solve_impl(const sl_problem* pb, const double* lens, int ns, int n_it
   hipLaunchKernelGGL(k_zero_int<T>, dim3(1), dim3(kNT), 0, st, a.flags, 1L);
   if (a.tiled) {
     hipLaunchKernelGGL(k_tile_psf_rows<T>, dim3(nblk(std::max(a.K * kTH, kTN), kNT)), dim3(kNT), 0, st, a);
-    hipLaunchKernelGGL(k_tile_psf_cols<T>, dim3(nblk(kTH * kTN, kNT)), dim3(kNT), 0, st, a);
+    hipLaunchKernelGGL(k_tile_psf_cols<T>, dim3(nblk(kTH * kTNY, kNT)), dim3(kNT), 0, st, a);
     if (int e = check_launch("tile PSF spectrum")) return e;
   } else if (int e = spectrum(a, st)) {
     return e;
