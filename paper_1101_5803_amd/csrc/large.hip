@@ -1151,6 +1151,73 @@ __device__ __forceinline__ void fft_cols(cpx<T>* x, cpx<T>* y, const cpx<T>* tw6
 
 enum { TILE_B = 0, TILE_BT0 = 1, TILE_BT = 2 };
 
+// First forward column stage with the unpacking of the row spectra fused in:
+// column kx, row r of the half spectra is formed from packed row r / 2 of the
+// row transforms in x (stride kTLD) at kx and 128 - kx (two real rows' spectra
+// from one complex one); writes the stage scratch y (as col_stage1).
+template <typename T>
+__device__ __forceinline__ void col_stage1_unpack(const cpx<T>* __restrict__ x, cpx<T>* __restrict__ y) {
+  constexpr int ITEMS = kTH * 6;
+  const int wi = threadIdx.x;
+  cpx<T> v[16];
+  if (wi < ITEMS) {
+    const int b = wi / 6, j = wi - b * 6;
+    const int km = (kTN - b) & (kTN - 1);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int rr = j + 6 * r, pr = rr >> 1;
+      const cpx<T> zk = x[pr * kTLD + b], zm = x[pr * kTLD + km];
+      const T h = (T)0.5;
+      v[r] = (rr & 1) ? cpx<T>{h * (zk.y + zm.y), h * (zm.x - zk.x)} : cpx<T>{h * (zk.x + zm.x), h * (zk.y - zm.y)};
+    }
+  }
+  if (wi < ITEMS) {
+    const int b = wi / 6, j = wi - b * 6;
+    dft16<T, false>(v);
+    cpx<T>* o_ = y + p16c(b, 16 * j);
+#pragma unroll
+    for (int m = 0; m < 16; ++m) o_[m] = v[m];
+  }
+  __syncthreads();
+}
+
+// First inverse row stage of packed rows PR0..PR0+NPR-1 with the repacking
+// fused in: packed row pr at column k is Q0[k] + i Q1[k] of the two tile rows
+// 2 pr, 2 pr + 1, read from the column-major spectra x (stride kTLDC), the
+// upper half by conjugate symmetry; writes the row stage scratch y (rows
+// 0..NPR-1, as tile_stage1).
+template <typename T, int PR0, int NPR>
+__device__ __forceinline__ void row_stage1_repack(const cpx<T>* __restrict__ x, cpx<T>* __restrict__ y) {
+  constexpr int ITEMS = NPR * 8;
+  static_assert(ITEMS <= kTNT && NPR % 16 == 0, "one butterfly per thread, whole sets of 16 rows");
+  const int wi = threadIdx.x;
+  cpx<T> v[16];
+  int b = 0, j = 0;
+  if (wi < ITEMS) {
+    stage1_map<NPR>(wi, b, j);
+    const int pr = PR0 + b;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int k = j + 8 * r;
+      const bool mirror = k > kTN / 2;
+      const int kk = mirror ? kTN - k : k;
+      cpx<T> q0 = x[kk * kTLDC + 2 * pr], q1 = x[kk * kTLDC + 2 * pr + 1];
+      if (mirror) {
+        q0.y = -q0.y;
+        q1.y = -q1.y;
+      }
+      v[r] = {q0.x - q1.y, q0.y + q1.x};
+    }
+  }
+  if (wi < ITEMS) {
+    dft16<T, true>(v);
+    cpx<T>* o_ = y + p16(b, 16 * j);
+#pragma unroll
+    for (int m = 0; m < 16; ++m) o_[m] = v[m];
+  }
+  __syncthreads();
+}
+
 // One tile of a blur.  TILE_B: q = B y on the owned pixels, with the block's
 // |q|^2 partial.  TILE_BT0: w = B^T e0 (e0 = d).  TILE_BT: the residual
 // update e_out = e_in - alpha q (alpha of iteration it; written on the owned
@@ -1217,57 +1284,38 @@ __global__ void __launch_bounds__(kTNT) k_tile(Args<T> a, const T* __restrict__ 
   }
   if (MODE == TILE_BT) put_partial(a, part, P_EE, it);   // contains the barrier the FFT needs
   else __syncthreads();
-  fft_tile<T, false, kTNY / 2>(X, Y, tw8);
-  // half spectra of the tile rows, column-major: Y[kx * kTLDC + r] (lanes along the packed rows)
-  constexpr int NPK = kTNY / 2;
-  constexpr int UU = (kTH * NPK + kTNT - 1) / kTNT;
-#pragma unroll
-  for (int u = 0; u < UU; ++u) {
-    const int i = threadIdx.x + u * kTNT;
-    if (i < kTH * NPK) {
-      const int k = i / NPK, pr = i - k * NPK;
-      const cpx<T> zk = X[pr * kTLD + k], zm = X[pr * kTLD + ((kTN - k) & (kTN - 1))];
-      const T h = (T)0.5;
-      Y[k * kTLDC + 2 * pr] = {h * (zk.x + zm.x), h * (zk.y - zm.y)};
-      Y[k * kTLDC + 2 * pr + 1] = {h * (zk.y + zm.y), h * (zm.x - zk.x)};
-    }
-  }
-  __syncthreads();
-  fft_cols<T, false>(Y, X, tw6);
-  fft_cols<T, true, MODE == TILE_B ? 1 : 2>(Y, X, tw6, a.Ht);
-  // packed rows 16..31 again: Z[k] = Q0[k] + i Q1[k], the upper half by conjugate symmetry
-  constexpr int PR0 = kTHalo / 2, NPR = kTVY / 2;
-  static_assert(NPR * kTN % kTNT == 0, "whole passes");
-#pragma unroll
-  for (int u = 0; u < NPR * kTN / kTNT; ++u) {
-    const int i = threadIdx.x + u * kTNT;
-    const int k = i / NPR, pr = PR0 + (i - k * NPR);
-    const bool mirror = k > kTN / 2;
-    const int kk = mirror ? kTN - k : k;
-    cpx<T> q0 = Y[kk * kTLDC + 2 * pr], q1 = Y[kk * kTLDC + 2 * pr + 1];
-    if (mirror) {
-      q0.y = -q0.y;
-      q1.y = -q1.y;
-    }
-    X[pr * kTLD + k] = {q0.x - q1.y, q0.y + q1.x};
-  }
-  __syncthreads();
-  fft_tile<T, true, NPR>(X + PR0 * kTLD, Y, tw8);
-  // the owned pixels
+  fft_tile<T, false, kTNY / 2>(X, Y, tw8);                 // row spectra in X
+  col_stage1_unpack<T>(X, Y);                               // half spectra, columns: stage 1 into Y
+  col_stage2<T, false>(Y, X, tw6);                          // columns (stride kTLDC) in X
+  fft_cols<T, true, MODE == TILE_B ? 1 : 2>(X, Y, tw6, a.Ht);   // times the PSF spectrum, inverse columns
+  constexpr int PR0 = kTHalo / 2, NPR = kTVY / 2;           // packed rows 16..31 hold the owned rows
+  row_stage1_repack<T, PR0, NPR>(X, Y);
+  // last inverse row stage (as tile_stage2), its owned outputs written to the image directly
   T* out = MODE == TILE_B ? a.q : a.w;
   double qq = 0.0;
-  static_assert(kTV * kTVY % kTNT == 0, "whole passes");
+  if (threadIdx.x < NPR * 16) {
+    const int b = threadIdx.x >> 4, j = threadIdx.x & 15;
+    cpx<T> v[8];
 #pragma unroll
-  for (int u = 0; u < kTV * kTVY / kTNT; ++u) {
-    const int i = threadIdx.x + u * kTNT;
-    const int lr = i / kTV, lc = i - lr * kTV;
-    const int r = ty * kTVY + lr, cx = tx * kTV + lc;
-    if (r < a.ny && cx < a.nx) {
-      const int tr = lr + kTHalo, tc = lc + kTHalo;
-      const cpx<T> z = X[(tr >> 1) * kTLD + tc];
-      const T val = (tr & 1) ? z.y : z.x;
-      out[(long)r * a.nx + cx] = val;
-      if (MODE == TILE_B) qq += (double)val * (double)val;
+    for (int r = 0; r < 8; ++r) v[r] = Y[p16(b, j + 16 * r)];
+    if (j) {
+#pragma unroll
+      for (int r = 1; r < 8; ++r) v[r] = cmulc(v[r], tw8[(r - 1) * 16 + j]);
+    }
+    dft8<T, true>(v);
+    const int r0 = y0 + 2 * (PR0 + b);   // image rows of the packed row's real and imaginary parts
+#pragma unroll
+    for (int m = kTHalo / 16; m < (kTHalo + kTV) / 16; ++m) {   // owned columns 32..95: m = 2..5
+      const int cx = x0 + j + 16 * m;
+      if (cx >= a.nx) continue;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int r = r0 + h;
+        if (r >= a.ny) continue;
+        const T val = h ? v[m].y : v[m].x;
+        out[(long)r * a.nx + cx] = val;
+        if (MODE == TILE_B) qq += (double)val * (double)val;
+      }
     }
   }
   if (MODE == TILE_B) put_partial(a, qq, P_QQ, it);
