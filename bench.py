@@ -397,7 +397,7 @@ def large_bytes_per_iteration(w, entries, elem=4, tiled=True):
     tiled (FP32 with a PSF of at most 65 x 65, overlap-save tiles): y = L p
     written and read, q written, the residual and q read and the new residual
     and w written by the B^T tiles (7 elem J), plus the tile's PSF spectrum
-    (65 x 128 complex) read by both blur launches.
+    (65 x 96 complex) read by both blur launches.
 
     frame (the 1024 x 1024 frame FFT): the half spectra of the ny image rows
     (ny Nh complex values each) written by the row FFT of L p, read and
@@ -410,7 +410,7 @@ def large_bytes_per_iteration(w, entries, elem=4, tiled=True):
     J, I, n2 = w.nx * w.ny, w.ns * w.ns, w.nsub_model ** 2
     common = (4 + 2 * elem) * J * n2 + elem * I + entries * (4 + elem) + 4 * I + elem * J + elem * I + 6 * elem * I
     if tiled:
-        return common + 7 * elem * J + 2 * 65 * 128 * 2 * elem
+        return common + 7 * elem * J + 2 * 65 * 96 * 2 * elem
     ck = (w.k_psf - 1) // 2
     Nx = 4
     while Nx < w.nx + ck:
@@ -546,7 +546,7 @@ def large_main(args, torch, sl, synthgen):
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": "large-scale shape of Sec. 4: 640x640 image at 0.008\", 2x2 subpixels, "
                                   "512x512 nodes over +-1.6\", 65x65 sinc-Moffat PSF, identity H, 40 CGLS "
-                                  "iterations, blur in Fourier space (overlap-save 128x128 tiles)"},
+                                  "iterations, blur in Fourier space (overlap-save 96x128 tiles)"},
            "ms_per_solve_events": round(ms40, 3), "ms_per_cgls_iteration": round(it_ms, 4),
            "graph_ms_per_solve": round(graph_ms, 3), "graph_matches_eager": graph_same,
            "setup_ms": round(ms1 - it_ms, 3),
