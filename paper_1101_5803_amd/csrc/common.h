@@ -167,26 +167,31 @@ __host__ __device__ inline bool grid_cell(double u, double v, int ns, int& cell,
 // keep at most two entries below and four above it; the loops visit only
 // those, and every entry they skip is an exact zero (the result is that of
 // the full elimination).
-__host__ __device__ inline bool spline_knot_derivs(const double* t, const double* y, int n, double* A,
-                                                   double* M, double* d1) {
-  for (int i = 0; i < n * n; ++i) A[i] = 0.0;
-  for (int i = 0; i < n; ++i) M[i] = 0.0;
-  const double h0 = t[1] - t[0], h1 = t[2] - t[1];
-  A[0] = h1;
-  A[1] = -(h0 + h1);
-  A[2] = h0;
-  for (int i = 1; i < n - 1; ++i) {
+// Row i of the system (A zeroed and M[0] = M[n - 1] = 0 beforehand): the
+// not-a-knot rows 0 and n - 1, the continuity rows between.
+__host__ __device__ inline void spline_fill_row(const double* t, const double* y, int n, double* A, double* M, int i) {
+  if (i == 0) {
+    const double h0 = t[1] - t[0], h1 = t[2] - t[1];
+    A[0] = h1;
+    A[1] = -(h0 + h1);
+    A[2] = h0;
+  } else if (i == n - 1) {
+    const double ha = t[n - 2] - t[n - 3], hb = t[n - 1] - t[n - 2];
+    A[(n - 1) * n + n - 3] = hb;
+    A[(n - 1) * n + n - 2] = -(ha + hb);
+    A[(n - 1) * n + n - 1] = ha;
+  } else {
     const double hm = t[i] - t[i - 1], hp = t[i + 1] - t[i];
     A[i * n + i - 1] = hm;
     A[i * n + i] = 2.0 * (hm + hp);
     A[i * n + i + 1] = hp;
     M[i] = 6.0 * ((y[i + 1] - y[i]) / hp - (y[i] - y[i - 1]) / hm);
   }
-  const double ha = t[n - 2] - t[n - 3], hb = t[n - 1] - t[n - 2];
-  A[(n - 1) * n + n - 3] = hb;
-  A[(n - 1) * n + n - 2] = -(ha + hb);
-  A[(n - 1) * n + n - 1] = ha;
-  // elimination
+}
+
+// Gaussian elimination with partial pivoting and back substitution: M holds
+// the second derivatives on return; false on a zero pivot.
+__host__ __device__ inline bool spline_solve(int n, double* A, double* M) {
   for (int col = 0; col < n; ++col) {
     const int rlast = col + 2 < n - 1 ? col + 2 : n - 1;
     const int clast = col + 4 < n - 1 ? col + 4 : n - 1;
@@ -217,12 +222,26 @@ __host__ __device__ inline bool spline_knot_derivs(const double* t, const double
     for (int c = r + 1; c <= clast; ++c) acc -= A[r * n + c] * M[c];
     M[r] = acc / A[r * n + r];
   }
-  for (int i = 0; i < n - 1; ++i) {
+  return true;
+}
+
+// First derivative at knot i from the second derivatives M.
+__host__ __device__ inline double spline_d1_at(const double* t, const double* y, int n, const double* M, int i) {
+  if (i < n - 1) {
     const double h = t[i + 1] - t[i];
-    d1[i] = (y[i + 1] - y[i]) / h - h * (2.0 * M[i] + M[i + 1]) / 6.0;
+    return (y[i + 1] - y[i]) / h - h * (2.0 * M[i] + M[i + 1]) / 6.0;
   }
   const double h = t[n - 1] - t[n - 2];
-  d1[n - 1] = (y[n - 1] - y[n - 2]) / h + h * (M[n - 2] + 2.0 * M[n - 1]) / 6.0;
+  return (y[n - 1] - y[n - 2]) / h + h * (M[n - 2] + 2.0 * M[n - 1]) / 6.0;
+}
+
+__host__ __device__ inline bool spline_knot_derivs(const double* t, const double* y, int n, double* A,
+                                                   double* M, double* d1) {
+  for (int i = 0; i < n * n; ++i) A[i] = 0.0;
+  for (int i = 0; i < n; ++i) M[i] = 0.0;
+  for (int i = 0; i < n; ++i) spline_fill_row(t, y, n, A, M, i);
+  if (!spline_solve(n, A, M)) return false;
+  for (int i = 0; i < n; ++i) d1[i] = spline_d1_at(t, y, n, M, i);
   return true;
 }
 
