@@ -163,7 +163,7 @@ struct Args {
   double* alpha;        // [n_iter]: step length of iteration k (0 when it did not move)
   int32_t* done;        // [n_iter + 1]: the iteration stopped before iteration k
   int32_t* upd;         // [n_iter]: iteration k updated s
-  int32_t* flags;       // [1]: invalid genome
+  int32_t* flags;       // [2]: invalid genome; count of rows the sort leaves to whole waves
   int n_iter, max_blocks, nb_row, nb_node, nb_lt, nb_heavy;
 };
 
@@ -558,25 +558,25 @@ __global__ void __launch_bounds__(kNT) k_fill(Args<T> a) {
     }
 }
 
-// Each node's entries placed in ascending key order (one wave per node): the
-// rank of an entry is the number of the node's keys below it (keys are
-// distinct).  Rows of up to kSortChunk entries are staged in the wave's LDS
-// slice; each lane holds its (at most 16) keys in registers and every staged
-// key is read once and compared with all of them.  Longer rows compare from
-// global memory one entry at a time.
+// Each node's entries placed in ascending key order: the rank of an entry is
+// the number of the node's keys below it (keys are distinct, so the order is
+// unique).  k_sort: one lane per node sorts a row of at most kSortLane
+// entries in registers (rows of at most kSortSmall with the shorter code);
+// longer rows (about 1 % of the nodes, clustered near the critical curves) go
+// to a list (a.cursor, free after k_fill; its order does not matter) that
+// k_sort_long spreads one row per wave: rows of up to kSortChunk entries
+// staged in the wave's LDS slice, each lane holding its (at most 16) keys in
+// registers and every staged key read once and compared with all of them;
+// longer rows compare from global memory.
+constexpr int kSortSmall = 8;
+constexpr int kSortLane = 32;
+constexpr int kSortLongBlocks = 256;   // k_sort_long: 4096 waves over the list
+
 template <typename T>
-__global__ void __launch_bounds__(kNT) k_sort(Args<T> a) {
+__device__ __forceinline__ void sort_row_wave(const Args<T>& a, int b, int n, int kpp, int32_t* st, int lane) {
   constexpr int kPer = kSortChunk / kWave;
-  __shared__ int32_t stage[kNT / kWave][kSortChunk];
-  const int wv = threadIdx.x / kWave;
-  const int node = blockIdx.x * (kNT / kWave) + wv;
-  const int lane = threadIdx.x & (kWave - 1);
-  if (node >= a.I) return;
-  const int b = a.rowptr[node], n = a.rowptr[node + 1] - b;
   const int32_t* keys = a.key + b;
-  const int kpp = merged(a) ? kMergeMax : a.n2 * a.taps;   // keys per pixel
   if (n <= kSortChunk) {
-    int32_t* st = stage[wv];
     int mine[kPer], rank[kPer];
 #pragma unroll
     for (int t = 0; t < kPer; ++t) {
@@ -599,6 +599,10 @@ __global__ void __launch_bounds__(kNT) k_sort(Args<T> a) {
       const int e = lane + t * kWave;
       if (e < n) a.lt[b + rank[t]] = {mine[t] / kpp, a.wtmp[b + e]};
     }
+    // every lane's reads of this slice precede the next row's writes to it
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     return;
   }
   for (int e = lane; e < n; e += kWave) {
@@ -606,6 +610,63 @@ __global__ void __launch_bounds__(kNT) k_sort(Args<T> a) {
     int rank = 0;
     for (int f = 0; f < n; ++f) rank += keys[f] < ke;
     a.lt[b + rank] = {ke / kpp, a.wtmp[b + e]};
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void sort_row_lane(const Args<T>& a, int b, int n, int kpp) {
+  constexpr int C = kSortLane;
+  int k[C];
+#pragma unroll
+  for (int t = 0; t < C; ++t) k[t] = t < n ? a.key[b + t] : 0x7fffffff;
+#pragma unroll
+  for (int t = 0; t < C; ++t) {
+    if (t < n) {
+      int rank = 0;
+#pragma unroll
+      for (int f = 0; f < C; ++f) rank += k[f] < k[t];   // padding keys are above every key
+      a.lt[b + rank] = {k[t] / kpp, a.wtmp[b + t]};
+    }
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kNT) k_sort(Args<T> a) {
+  const int node = blockIdx.x * kNT + threadIdx.x;
+  if (node >= a.I) return;
+  const int kpp = merged(a) ? kMergeMax : a.n2 * a.taps;   // keys per pixel
+  const int b = a.rowptr[node], n = a.rowptr[node + 1] - b;
+  if (n <= kSortSmall) {
+    int k[kSortSmall];
+#pragma unroll
+    for (int t = 0; t < kSortSmall; ++t) k[t] = t < n ? a.key[b + t] : 0x7fffffff;
+#pragma unroll
+    for (int t = 0; t < kSortSmall; ++t) {
+      if (t < n) {
+        int rank = 0;
+#pragma unroll
+        for (int f = 0; f < kSortSmall; ++f) rank += k[f] < k[t];
+        a.lt[b + rank] = {k[t] / kpp, a.wtmp[b + t]};
+      }
+    }
+  } else if (n <= kSortLane) {
+    sort_row_lane(a, b, n, kpp);
+  } else {
+    a.cursor[atomicAdd(&a.flags[1], 1)] = node;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kNT) k_sort_long(Args<T> a) {
+  __shared__ int32_t stage[kNT / kWave][kSortChunk];
+  const int wv = threadIdx.x / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int kpp = merged(a) ? kMergeMax : a.n2 * a.taps;
+  const int nlong = a.flags[1];
+  for (int i = blockIdx.x * (kNT / kWave) + wv; i < nlong; i += gridDim.x * (kNT / kWave)) {   // wave-uniform
+    const int node = a.cursor[i];
+    const int b = a.rowptr[node];
+    sort_row_wave(a, b, a.rowptr[node + 1] - b, kpp, stage[wv], lane);
   }
 }
 
@@ -1776,7 +1837,7 @@ static Layout make_layout(int nx, int ny, int nsub, int ns, int K, int interp, i
     sizes[n++] = 8 * (size_t)n_iter;                  // alpha
     sizes[n++] = 4 * (size_t)(n_iter + 1);            // done
     sizes[n++] = 4 * (size_t)n_iter;                  // upd
-    sizes[n++] = 4;                                   // flags
+    sizes[n++] = 8;                                   // flags
   }
   size_t off = 0;
   for (int i = 0; i < n; ++i) {
@@ -1940,7 +2001,7 @@ static int solve_impl(const sl_problem* pb, const double* lens, int ns, int n_it
   }
   // counters start at zero (a fill kernel: the call may be captured in a graph)
   hipLaunchKernelGGL(k_zero_int<T>, dim3(nblk(a.I, kNT)), dim3(kNT), 0, st, a.cnt, (long)a.I);
-  hipLaunchKernelGGL(k_zero_int<T>, dim3(1), dim3(kNT), 0, st, a.flags, 1L);
+  hipLaunchKernelGGL(k_zero_int<T>, dim3(1), dim3(kNT), 0, st, a.flags, 2L);
   if (a.tiled) {
     hipLaunchKernelGGL(k_tile_psf_rows<T>, dim3(nblk(std::max(a.K * kTH, kTN), kNT)), dim3(kNT), 0, st, a);
     hipLaunchKernelGGL(k_tile_psf_cols<T>, dim3(nblk(kTH * kTNY, kNT)), dim3(kNT), 0, st, a);
@@ -1956,7 +2017,8 @@ static int solve_impl(const sl_problem* pb, const double* lens, int ns, int n_it
   hipLaunchKernelGGL(k_tile_scan<T>, dim3(1), dim3(kNT), 0, st, a);
   hipLaunchKernelGGL(k_tile_write<T>, dim3(tiles), dim3(kNT), 0, st, a);
   hipLaunchKernelGGL(k_fill<T>, dim3(nblk(a.J, kNT)), dim3(kNT), 0, st, a);
-  hipLaunchKernelGGL(k_sort<T>, dim3(nblk(a.I, kNT / kWave)), dim3(kNT), 0, st, a);
+  hipLaunchKernelGGL(k_sort<T>, dim3(nblk(a.I, kNT)), dim3(kNT), 0, st, a);
+  hipLaunchKernelGGL(k_sort_long<T>, dim3(kSortLongBlocks), dim3(kNT), 0, st, a);
   if (int e = check_launch("large solve set-up")) return e;
   if constexpr (sizeof(T) == 4) {
     if (a.tiled) {
