@@ -52,6 +52,7 @@ namespace large {
 constexpr int kNT = 256;              // threads of most blocks
 constexpr int kRowNT = 512;           // threads of the row-FFT blocks
 constexpr int kLtNT = 1024;           // threads of the L^T blocks
+constexpr int kNodeNT = 1024;         // threads of the start and update blocks (each sums every |g|^2 partial)
 // L^T lanes per node and node groups per thread in flight.  FP32: 8 lanes
 // (most nodes have fewer entries than that), 4 groups.  FP64: 16 lanes, one
 // group (its 16-byte entries: more groups cost the second block per compute
@@ -1550,8 +1551,8 @@ __global__ void __launch_bounds__(kLtNT) k_lt(Args<T> a, int it) {
 
 // Start: s = 0, p = g = A^T d, |g|^2 (slot n_iter holds its partials).
 template <typename T>
-__global__ void __launch_bounds__(kNT) k_start(Args<T> a) {
-  for (int i = blockIdx.x * kNT + threadIdx.x; i < a.I; i += gridDim.x * kNT) {
+__global__ void __launch_bounds__(kNodeNT) k_start(Args<T> a) {
+  for (int i = blockIdx.x * kNodeNT + threadIdx.x; i < a.I; i += gridDim.x * kNodeNT) {
     a.s[i] = 0;
     a.p[i] = a.g[i];
   }
@@ -1566,10 +1567,10 @@ __global__ void __launch_bounds__(kNT) k_start(Args<T> a) {
 // the iterate kept and its |s|^2 partial; block 0 records the scalars of the
 // next iteration.  Grid-stride over the nodes (nb_node <= kMaxParts blocks).
 template <typename T>
-__global__ void __launch_bounds__(kNT) k_update(Args<T> a, int it) {
+__global__ void __launch_bounds__(kNodeNT) k_update(Args<T> a, int it) {
   // the first node's operands are loaded before the |g|^2 total, whose
   // partial loads and block reduction then hide their latency
-  const int i0 = blockIdx.x * kNT + threadIdx.x;
+  const int i0 = blockIdx.x * kNodeNT + threadIdx.x;
   T s0 = 0, p0 = 0, g0 = 0;
   if (i0 < a.I) {
     s0 = a.s[i0];
@@ -1582,7 +1583,7 @@ __global__ void __launch_bounds__(kNT) k_update(Args<T> a, int it) {
   const bool stop = !moved || !(gn > 0.0);
   const double beta = stop ? 0.0 : gn / a.gg[it];
   double ss = 0.0;
-  for (int i = i0; i < a.I; i += gridDim.x * kNT) {
+  for (int i = i0; i < a.I; i += gridDim.x * kNodeNT) {
     const bool first = i == i0;
     T s = first ? s0 : a.s[i];
     const T p = first ? p0 : a.p[i], g = first ? g0 : a.g[i];
@@ -1979,7 +1980,7 @@ static int solve_impl(const sl_problem* pb, const double* lens, int ns, int n_it
   a.psf = pb->psf;
   a.n_iter = n_iter;
   a.nb_row = (g.ny + 1) / 2;
-  a.nb_node = (int)std::min<long>(nblk(a.I, kNT), kMaxParts);
+  a.nb_node = (int)std::min<long>(nblk(a.I, kNodeNT), kMaxParts);
   a.nb_heavy = sizeof(T) == 4 ? kLtHeavyBlocks : 0;
   a.nb_lt = (int)std::min<long>(nblk((long)a.I * lt_lanes<T>(), (long)kLtNT * lt_groups<T>()), kMaxParts - a.nb_heavy) +
             a.nb_heavy;
@@ -2026,7 +2027,7 @@ static int solve_impl(const sl_problem* pb, const double* lens, int ns, int n_it
       hipLaunchKernelGGL(k_copy_d<T>, dim3(nblk(a.J, kNT)), dim3(kNT), 0, st, a);
       hipLaunchKernelGGL((k_tile<T, TILE_BT0>), dim3(ntiles), dim3(kTNT), lt, st, a, (const T*)a.e0, (T*)nullptr, 0);
       hipLaunchKernelGGL(k_lt<T>, dim3(a.nb_lt), dim3(kLtNT), 0, st, a, n_iter);
-      hipLaunchKernelGGL(k_start<T>, dim3(a.nb_node), dim3(kNT), 0, st, a);
+      hipLaunchKernelGGL(k_start<T>, dim3(a.nb_node), dim3(kNodeNT), 0, st, a);
       for (int it = 0; it < n_iter; ++it) {
         T* ein = (it & 1) ? a.e1 : a.e0;
         T* eout = (it & 1) ? a.e0 : a.e1;
@@ -2035,7 +2036,7 @@ static int solve_impl(const sl_problem* pb, const double* lens, int ns, int n_it
                            it);
         hipLaunchKernelGGL((k_tile<T, TILE_BT>), dim3(ntiles), dim3(kTNT), lt, st, a, (const T*)ein, eout, it);
         hipLaunchKernelGGL(k_lt<T>, dim3(a.nb_lt), dim3(kLtNT), 0, st, a, it);
-        hipLaunchKernelGGL(k_update<T>, dim3(a.nb_node), dim3(kNT), 0, st, a, it);
+        hipLaunchKernelGGL(k_update<T>, dim3(a.nb_node), dim3(kNodeNT), 0, st, a, it);
       }
       if (int e = check_launch("large solve iterations (tiled blur)")) return e;
       hipLaunchKernelGGL(k_final<T>, dim3(1), dim3(kLtNT), 8 * kLcurveScratch, st, a, *out);
@@ -2047,13 +2048,13 @@ static int solve_impl(const sl_problem* pb, const double* lens, int ns, int n_it
   hipLaunchKernelGGL((k_rowfwd<T, ROW_D>), dim3(a.nb_row), dim3(kRowNT), lx, st, a, (const T*)nullptr);
   blur_tail<T, true, COL_E, OUT_W>(a, nullptr, 0, st);
   hipLaunchKernelGGL(k_lt<T>, dim3(a.nb_lt), dim3(kLtNT), 0, st, a, n_iter);
-  hipLaunchKernelGGL(k_start<T>, dim3(a.nb_node), dim3(kNT), 0, st, a);
+  hipLaunchKernelGGL(k_start<T>, dim3(a.nb_node), dim3(kNodeNT), 0, st, a);
   for (int it = 0; it < n_iter; ++it) {
     hipLaunchKernelGGL((k_rowfwd<T, ROW_LP>), dim3(a.nb_row), dim3(kRowNT), lx, st, a, (const T*)a.p);
     blur_tail<T, false, COL_S, OUT_Q>(a, nullptr, it, st);               // spectra of q = A p, |q|^2
     blur_tail<T, true, COL_E_UPD, OUT_W>(a, nullptr, it, st);            // e -= alpha q, |e|^2; w = B^T e
     hipLaunchKernelGGL(k_lt<T>, dim3(a.nb_lt), dim3(kLtNT), 0, st, a, it);
-    hipLaunchKernelGGL(k_update<T>, dim3(a.nb_node), dim3(kNT), 0, st, a, it);
+    hipLaunchKernelGGL(k_update<T>, dim3(a.nb_node), dim3(kNodeNT), 0, st, a, it);
   }
   if (int e = check_launch("large solve iterations")) return e;
   hipLaunchKernelGGL(k_final<T>, dim3(1), dim3(kLtNT), 8 * kLcurveScratch, st, a, *out);
