@@ -134,13 +134,14 @@ def test_large_solve_medium_vs_oracle(sl, prec, interp):
     assert out["s_off"].tolist() == [0, w.ns * w.ns]
 
 
-@pytest.mark.parametrize("nx,ny,K", [(70, 130, 1), (100, 60, 15), (96, 80, 81)])
+@pytest.mark.parametrize("nx,ny,K", [(70, 130, 1), (100, 60, 15), (24, 20, 9), (96, 80, 81)])
 def test_large_solve_psf_sizes_fp32(sl, nx, ny, K):
-    """FP32 solves with other PSF widths and ragged image sizes: K = 1 and
-    K = 15 take the overlap-save tiles (64 x 64 owned blocks, the image's
-    last row and column of tiles cut), K = 81 is wider than a tile's halo and
-    takes the padded frame; each against the oracle within its Monte Carlo
-    arithmetic envelope (24 draws), 16 iterations."""
+    """FP32 solves with other PSF widths and ragged image sizes: K = 1, 9 and
+    15 take the overlap-save tiles (32 x 64 owned blocks, the image's last
+    row and column of tiles cut; the 24 x 20 image is smaller than one owned
+    block), K = 81 is wider than a tile's halo and takes the padded frame;
+    each against the oracle within its Monte Carlo arithmetic envelope
+    (24 draws), 16 iterations."""
     n_iter = 16
     psf = np.ones((1, 1)) if K == 1 else synthgen.sinc_moffat_psf(K, 3.0 if K < 30 else 6.0)
     w = synthgen.Workload("psf-sizes", 13, nx, ny, 0.04, 2, 4, 40, 1.4, K, 3.0, 60.0, "identity", (), 0.0,
