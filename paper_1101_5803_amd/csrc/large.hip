@@ -5,7 +5,21 @@
 // the paper convolves with the PSF in Fourier space (Sec. 2.2).  One such
 // problem fills the GPU by itself, so it runs as a short sequence of
 // grid-wide kernels per CGLS iteration rather than as one persistent block
-// per lens:
+// per lens.  FP32 with a PSF of at most 65 x 65 (the large shape) blurs by
+// overlap-save tiles, each transformed whole in one block's LDS:
+//
+//   k_gather   y = L p                            one thread per pixel
+//   k_tile<B>  q = B y on each tile's owned 32 x 64 pixels, |q|^2
+//                                                 one block per 96 x 128 tile
+//   k_tile<BT> e -= alpha q (owned pixels, recomputed on the halo), |e|^2,
+//              w = B^T e                          one block per tile
+//   k_lt       L^T as a gather over a node-major table, with |g|^2
+//                                                 8 lanes per node; nodes with
+//                                                 many entries one wave each
+//   k_update   s += alpha p, p = g + beta p, |s|^2, the iterate kept
+//                                                 one thread per node
+//
+// FP64, or a wider PSF, blurs on a padded frame in three passes per blur:
 //
 //   k_rowfwd   row FFTs of L p (the gather fused)  one block per pair of rows
 //   k_col      column FFT, product with the PSF spectrum, inverse column FFT
@@ -15,12 +29,9 @@
 //   k_col      the residual update e -= alpha q on the row spectra, |e|^2 by
 //              Parseval, and the columns of B^T e
 //   k_rowinv   inverse row FFTs: w = B^T e
-//   k_lt       L^T as a gather over a node-major table, with |g|^2
-//                                                 16 lanes per node
-//   k_update   s += alpha p, p = g + beta p, |s|^2, the iterate kept
-//                                                 one thread per node
+//   k_lt, k_update as above (16 lanes per node)
 //
-// The residual e = d - A s lives only as row spectra: it starts as those of
+// On the frame the residual e = d - A s lives only as row spectra: it starts as those of
 // d, and q enters them cut to the image (the frame's columns from nx on are
 // zero), so e stays the spectrum of an image row padded with zeros.
 //
@@ -1010,12 +1021,8 @@ __device__ __forceinline__ void stage1_map(int wi, int& b, int& j) {
   }
 }
 
-// HM = 1 (2) multiplies each input by H (conj H), stored with row stride
-// kTN, at the same position first: the PSF product fused into the first
-// inverse stage.
-template <typename T, bool INV, int NB, int HM>
-__device__ __forceinline__ void tile_stage1(const cpx<T>* __restrict__ x, cpx<T>* __restrict__ y,
-                                            const cpx<T>* __restrict__ H) {
+template <typename T, bool INV, int NB>
+__device__ __forceinline__ void tile_stage1(const cpx<T>* __restrict__ x, cpx<T>* __restrict__ y) {
   constexpr int ITEMS = NB * 8, U = (ITEMS + kTNT - 1) / kTNT;
   cpx<T> v[U][16];
 #pragma unroll
@@ -1026,13 +1033,6 @@ __device__ __forceinline__ void tile_stage1(const cpx<T>* __restrict__ x, cpx<T>
       stage1_map<NB>(wi, b, j);
 #pragma unroll
       for (int r = 0; r < 16; ++r) v[u][r] = x[b * kTLD + j + 8 * r];
-      if (HM) {
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const cpx<T> h = H[b * kTN + j + 8 * r];
-          v[u][r] = HM == 1 ? cmul(v[u][r], h) : cmulc(v[u][r], h);
-        }
-      }
     }
   }
 #pragma unroll
@@ -1086,10 +1086,10 @@ __device__ __forceinline__ void tile_stage2(const cpx<T>* __restrict__ x, cpx<T>
 }
 
 // NB length-128 FFTs in place in x (row stride kTLD), y the stage scratch.
-template <typename T, bool INV, int NB, int HM = 0>
-__device__ __forceinline__ void fft_tile(cpx<T>* x, cpx<T>* y, const cpx<T>* tw8, const cpx<T>* __restrict__ H = nullptr) {
+template <typename T, bool INV, int NB>
+__device__ __forceinline__ void fft_tile(cpx<T>* x, cpx<T>* y, const cpx<T>* tw8) {
   static_assert(kTN == 128, "stage list is for length 128");
-  tile_stage1<T, INV, NB, HM>(x, y, H);
+  tile_stage1<T, INV, NB>(x, y);
   tile_stage2<T, INV, NB>(y, x, tw8);
 }
 
