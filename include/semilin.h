@@ -337,7 +337,10 @@ int sl_fft_blur(int dtype, int transpose, int nx, int ny, const double* psf, int
  * test (Sec. 4: a 640 x 640 image, a 512 x 512 source grid, a 65 x 65 PSF,
  * 40 CGLS iterations): one lens (device double[7]), images up to
  * 2048 x 2048, ns up to 1024, PSF side k odd up to 129 (pb->k may exceed
- * SL_MAX_PSF here), B and B^T applied in Fourier space as sl_fft_blur, L^T as
+ * SL_MAX_PSF here), B and B^T applied in Fourier space: with pb->dtype
+ * SL_F32 and k <= 65 by overlap-save on 96 x 128 tiles (32 x 64 owned
+ * pixels each, a 32-pixel halo), otherwise on the padded frame of
+ * sl_fft_blur; both the linear convolution of Eq. 4 up to rounding.  L^T is
  * a gather over a node-major table built and sorted on the device (each
  * node's terms summed in ascending pixel order: bitwise reproducible).  The
  * iteration, its outputs and statuses are those of sl_solve_implicit for
