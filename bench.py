@@ -35,36 +35,39 @@ PEAK_FP32_TFLOPS = 157.3
 PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 SOLVE_SRC = os.path.join(ROOT, "paper_1101_5803_amd", "csrc", "solve.hip")
+LARGE_SRC = os.path.join(ROOT, "paper_1101_5803_amd", "csrc", "large.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_solve_c3_hbm_traffic.txt")
+LARGE_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "large_shape_hbm_traffic.txt")
 
 
-def source_hash(text: str | None = None) -> str:
+def source_hash(text: str | None = None, path: str = SOLVE_SRC) -> str:
     """Hash of the kernel source with // comments and whitespace removed."""
     if text is None:
-        with open(SOLVE_SRC) as f:
+        with open(path) as f:
             text = f.read()
     code = re.sub(r"//[^\n]*", "", text)
     code = re.sub(r"\s+", "", code)
     return hashlib.sha256(code.encode()).hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per k_solve launch from the committed counter summary, or None.
+def measured_traffic(path=TRAFFIC_FILE, src=SOLVE_SRC, hash_key="solve_hip_sha256_16",
+                     value_key="hbm_bytes_per_launch"):
+    """HBM bytes from a committed counter summary (per k_solve launch by default), or None.
 
     The summary records the hash of the kernel source it was measured on; a
     different source (the kernel changed since) gives None.
     """
-    if not os.path.exists(TRAFFIC_FILE):
+    if not os.path.exists(path):
         return None
     kv = {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(path):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
-    if kv.get("solve_hip_sha256_16") != source_hash():
+    if kv.get(hash_key) != source_hash(path=src):
         return None
     try:
-        return float(kv["hbm_bytes_per_launch"])
+        return float(kv[value_key])
     except (KeyError, ValueError):
         return None
 
@@ -469,6 +472,13 @@ def large_main(args, torch, sl, synthgen):
     torch.cuda.set_device(dev)
     w, z, solver, lens = _large_setup(torch, sl, synthgen, dev)
     n_iter = synthgen.LARGE_ITERS
+    if args.copy_calibration:   # a device copy of known size, for the counter calibration of a profiled run
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     print(f"[bench] large: warmup {args.warmup}, timing {args.steps} solve(s)", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         solver.solve_large(lens, w.ns, n_iter)
@@ -540,6 +550,7 @@ def large_main(args, torch, sl, synthgen):
                    "chi2_rel_diff_at_gpu_corner": float(abs(res["chi2"][0][k] - ref["chi2"][k]) / ref["chi2"][k])}
     abytes = large_bytes_per_iteration(w, entries)
     gbs = abytes / (it_ms * 1e-3) / 1e9
+    traffic = measured_traffic(LARGE_TRAFFIC_FILE, LARGE_SRC, "large_hip_sha256_16", "hbm_bytes_per_iteration")
     rec = {"metric": "large-scale CGLS solves/s (640² image, 512² source, 65² PSF, 40 iterations)",
            "value": round(args.steps / dt, 3), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(1e3 * dt / args.steps, 3), "higher_is_better": True,
@@ -553,7 +564,8 @@ def large_main(args, torch, sl, synthgen):
            "corner_iterate": int(res["k_star"][0]) + 1,
            "fp64": fp64,
            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
-                        "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": None,
+                        "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": traffic,
+                        "measured_hbm_GBps": round(traffic / (it_ms * 1e-3) / 1e9, 1) if traffic else None,
                         "kernel": "one CGLS iteration: 5 kernels (L p; tile blur q = B y with |q|^2; tile blur "
                                   "with the residual update, |e|^2 and w = B^T e; L^T; update)",
                         "algorithmic_bytes": abytes, "table_entries": entries},

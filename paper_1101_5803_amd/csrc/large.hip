@@ -197,13 +197,26 @@ __device__ __forceinline__ double block_total(const double* p, int n) {
   return block_sum(v, red);
 }
 
-// Block FP64 sum written as this block's partial of reduction `which`, slot
-// `it` (all threads call it: barriers).
+// Block FP64 sum written as partial `idx` (by default this block's) of
+// reduction `which`, slot `it` (all threads call it: barriers).
 template <typename T>
-__device__ __forceinline__ void put_partial(const Args<T>& a, double v, int which, int it) {
+__device__ __forceinline__ void put_partial(const Args<T>& a, double v, int which, int it, int idx = -1) {
   __shared__ double red[kLtNT / kWave];
   v = block_sum(v, red);
-  if (threadIdx.x == 0) part_of(a, which, it)[blockIdx.x] = v;
+  if (threadIdx.x == 0) part_of(a, which, it)[idx < 0 ? (int)blockIdx.x : idx] = v;
+}
+
+// Work item of block b among n: blocks b = x, x + 8, ... run on XCD x (the
+// launch deals workgroups to the eight XCDs in turn), and each XCD takes a
+// contiguous range of items, so that neighbouring tiles or node ranges share
+// that XCD's L2 (a tile's halo is its neighbours' interior).  A bijection of
+// [0, n); partial sums stay indexed by item, so the reductions add in the
+// same order whatever block computes an item.
+__device__ __forceinline__ int xcd_item(int b, int n) {
+  constexpr int kXcd = 8;
+  const int per = n / kXcd, rem = n % kXcd;
+  const int x = b % kXcd, k = b / kXcd;
+  return x * per + (x < rem ? x : rem) + k;
 }
 
 // ---------------------------------------------------------------- FFT in LDS
@@ -1294,7 +1307,8 @@ __global__ void __launch_bounds__(kTNT) k_tile(Args<T> a, const T* __restrict__ 
   __shared__ cpx<T> tw6[5 * 16];
   cpx<T>* X = reinterpret_cast<cpx<T>*>(smem);
   cpx<T>* Y = X + kTBuf;
-  const int ty = blockIdx.x / a.tiles_x, tx = blockIdx.x - ty * a.tiles_x;
+  const int tile = xcd_item(blockIdx.x, gridDim.x);
+  const int ty = tile / a.tiles_x, tx = tile - ty * a.tiles_x;
   const int y0 = ty * kTVY - kTHalo, x0 = tx * kTV - kTHalo;   // image position of tile element (0, 0)
   if (threadIdx.x < 7 * 16) {
     const int r = threadIdx.x / 16 + 1, j = threadIdx.x & 15;
@@ -1344,7 +1358,7 @@ __global__ void __launch_bounds__(kTNT) k_tile(Args<T> a, const T* __restrict__ 
     }
     X[pr * kTLD + c] = {v[u][0], v[u][1]};
   }
-  if (MODE == TILE_BT) put_partial(a, part, P_EE, it);   // contains the barrier the FFT needs
+  if (MODE == TILE_BT) put_partial(a, part, P_EE, it, tile);   // contains the barrier the FFT needs
   else __syncthreads();
   fft_tile<T, false, kTNY / 2>(X, Y, tw8);                 // row spectra in X
   col_stage1_unpack<T>(X, Y);                               // half spectra, columns: stage 1 into Y
@@ -1380,7 +1394,7 @@ __global__ void __launch_bounds__(kTNT) k_tile(Args<T> a, const T* __restrict__ 
       }
     }
   }
-  if (MODE == TILE_B) put_partial(a, qq, P_QQ, it);
+  if (MODE == TILE_B) put_partial(a, qq, P_QQ, it, tile);
 }
 
 // y = L p (one thread per pixel).
@@ -1496,6 +1510,9 @@ __global__ void __launch_bounds__(kLtNT) k_lt(Args<T> a, int it) {
   }
   const int l = threadIdx.x & (kLtG - 1);
   constexpr int per_pass = kLtNT / kLtG;
+  // node ranges in block order, so consecutive ranges go to different XCDs:
+  // the long rows cluster near the critical curves, and contiguous runs of
+  // ranges per XCD (as the tiles take) load one XCD with most of them
   const int rb = (int)blockIdx.x - a.nb_heavy;
   for (int n0 = rb * per_pass * kLtU; n0 < a.I; n0 += nb_reg * per_pass * kLtU) {
     // kLtU node groups per thread: their row bounds, first entries and w values in flight together
