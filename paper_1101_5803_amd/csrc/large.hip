@@ -161,7 +161,7 @@ struct Args {
   T* q;                 // [J] B L p
   T* e0;                // [J] image residual, two buffers used in turn
   T* e1;
-  cpx<T>* Ht;           // [65][96] PSF spectrum on the tile / (128 96)
+  cpx<T>* Ht;           // [96][65] PSF spectrum on the tile / (128 96), [ky][kx]
   cpx<T>* twt;          // [128] exp(-2 pi i m / 128)
   cpx<T>* twc;          // [96] exp(-2 pi i m / 96)
   cpx<double>* T1t;     // [K][65] first stage of the tile's PSF transform
@@ -1151,7 +1151,7 @@ __device__ __forceinline__ void dft6(cpx<T> (&v)[6]) {
   for (int m = 0; m < 6; ++m) v[m] = o[m];
 }
 
-// HM = 1 (2): each input times H (conj H), stored [kx][96], first.
+// HM = 1 (2): each input times H (conj H), stored [ky][kx] (96 x 65), first.
 template <typename T, bool INV, int HM>
 __device__ __forceinline__ void col_stage1(const cpx<T>* __restrict__ x, cpx<T>* __restrict__ y,
                                            const cpx<T>* __restrict__ H) {
@@ -1159,20 +1159,22 @@ __device__ __forceinline__ void col_stage1(const cpx<T>* __restrict__ x, cpx<T>*
   static_assert(ITEMS <= kTNT, "one butterfly per thread");
   const int wi = threadIdx.x;
   cpx<T> v[16];
+  // consecutive lanes take consecutive columns (b = wi mod 65): the reads of a
+  // stage are then contiguous and its scratch writes 103 = 7 mod 32 apart
   if (wi < ITEMS) {
-    const int b = wi / 6, j = wi - b * 6;
+    const int j = wi / kTH, b = wi - j * kTH;
 #pragma unroll
     for (int r = 0; r < 16; ++r) v[r] = x[b * kTLDC + j + 6 * r];
     if (HM) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const cpx<T> hh = H[b * kTNY + j + 6 * r];
+        const cpx<T> hh = H[(j + 6 * r) * kTH + b];   // Ht is [ky][kx]: lanes along kx read consecutive values
         v[r] = HM == 1 ? cmul(v[r], hh) : cmulc(v[r], hh);
       }
     }
   }
   if (wi < ITEMS) {
-    const int b = wi / 6, j = wi - b * 6;
+    const int j = wi / kTH, b = wi - j * kTH;
     dft16<T, INV>(v);
     cpx<T>* o_ = y + p16c(b, 16 * j);
 #pragma unroll
@@ -1236,7 +1238,7 @@ __device__ __forceinline__ void col_stage1_unpack(const cpx<T>* __restrict__ x, 
   const int wi = threadIdx.x;
   cpx<T> v[16];
   if (wi < ITEMS) {
-    const int b = wi / 6, j = wi - b * 6;
+    const int j = wi / kTH, b = wi - j * kTH;   // consecutive lanes, consecutive columns (as col_stage1)
     const int km = (kTN - b) & (kTN - 1);
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
@@ -1247,7 +1249,7 @@ __device__ __forceinline__ void col_stage1_unpack(const cpx<T>* __restrict__ x, 
     }
   }
   if (wi < ITEMS) {
-    const int b = wi / 6, j = wi - b * 6;
+    const int j = wi / kTH, b = wi - j * kTH;
     dft16<T, false>(v);
     cpx<T>* o_ = y + p16c(b, 16 * j);
 #pragma unroll
@@ -1412,7 +1414,7 @@ __global__ void __launch_bounds__(kNT) k_copy_d(Args<T> a) {
 }
 
 // The tile's PSF spectrum
-//   Ht[kx][ky] = sum_{a,b} P[a][b] exp(-2 pi i (ky (a - ck) / 96 + kx (b - ck) / 128)) / (128 96)
+//   Ht[ky][kx] = sum_{a,b} P[a][b] exp(-2 pi i (ky (a - ck) / 96 + kx (b - ck) / 128)) / (128 96)
 // in FP64, separably: first T1t[a][kx] over b (and the tile twiddles), then over a.
 // exp(-2 pi i m / n)
 __device__ __forceinline__ cpx<double> root_of(long m, int n) {
@@ -1450,7 +1452,7 @@ template <typename T>
 __global__ void __launch_bounds__(kNT) k_tile_psf_cols(Args<T> a) {
   const int idx = blockIdx.x * kNT + threadIdx.x;
   if (idx >= kTH * kTNY) return;
-  const int kx = idx / kTNY, ky = idx - kx * kTNY;
+  const int ky = idx / kTH, kx = idx - ky * kTH;   // stored [ky][kx]
   double re = 0.0, im = 0.0;
   for (int r = 0; r < a.K; ++r) {
     const cpx<double> u = root_of((long)ky * (r - a.ck), kTNY);
