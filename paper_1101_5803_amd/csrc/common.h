@@ -308,4 +308,106 @@ __host__ __device__ inline int lcurve_corner_impl(const double* reg, const doubl
 
 constexpr int kLcurveScratch = 2 * SL_MAX_LAMBDA * SL_MAX_LAMBDA + 12 * SL_MAX_LAMBDA;
 
+// The L-curve corner of lcurve_corner_impl computed by a whole block (every
+// thread calls it; all receive the result): the logarithms, the segment
+// lengths, the rows of the two spline systems, the knot derivatives and the
+// curvatures one value per thread with the same operations as there; the
+// running arc length with its point drop, the two eliminations (on threads 0
+// and 64, in different waves, side by side) and the argmax in order.  Same
+// result bit for bit; the one-thread form is a chain of dependent FP64 steps.
+// sc: kLcurveScratch doubles of LDS; blocks of at least 128 + n threads.
+__device__ inline int lcurve_corner_block(const double* reg, const double* chi2, int n, double* sc) {
+  __shared__ int sh[4];   // validity, kept points m, the x system's solve then the result, the y system's solve
+  const int tid = threadIdx.x;
+  if (n < 4 || n > SL_MAX_LAMBDA) return -1;
+  double* X = sc;
+  double* Y = X + n;
+  double* seg = Y + n;
+  double* t = seg + n;
+  int* keep = (int*)(t + n);
+  double* xs = t + 2 * n;
+  double* ys = xs + n;
+  double* Mx = ys + n;
+  double* My = Mx + n;
+  double* dx1 = My + n;
+  double* dy1 = dx1 + n;
+  double* kap = dy1 + n;
+  double* Ax = kap + n;
+  double* Ay = Ax + n * n;   // 12 n + 2 n^2 doubles in all
+  if (tid == 0) sh[0] = 1;
+  __syncthreads();
+  if (tid < n) {
+    if (!(reg[tid] > 0.0) || !(chi2[tid] > 0.0) || !__builtin_isfinite(reg[tid]) || !__builtin_isfinite(chi2[tid]))
+      sh[0] = 0;
+    X[tid] = log10(reg[tid]);
+    Y[tid] = log10(chi2[tid]);
+  }
+  __syncthreads();
+  if (!sh[0]) return -1;
+  if (tid >= 1 && tid < n) seg[tid] = hypot(X[tid] - X[tid - 1], Y[tid] - Y[tid - 1]);
+  __syncthreads();
+  if (tid == 0) {
+    double total = 0.0;
+    for (int i = 1; i < n; ++i) total += seg[i];
+    int m = 0;
+    keep[m] = 0;
+    t[m] = 0.0;
+    xs[m] = X[0];
+    ys[m] = Y[0];
+    ++m;
+    double acc = 0.0;
+    for (int i = 1; i < n; ++i) {
+      acc += seg[i];
+      if (acc - t[m - 1] <= 1e-12 * total) continue;
+      keep[m] = i;
+      t[m] = acc;
+      xs[m] = X[i];
+      ys[m] = Y[i];
+      ++m;
+    }
+    sh[1] = m;
+  }
+  __syncthreads();
+  const int m = sh[1];
+  if (m < 4) return -1;
+  for (int i = tid; i < 2 * m * m; i += blockDim.x) Ax[i] = 0.0;   // Ax and Ay
+  if (tid < m) {
+    Mx[tid] = 0.0;
+    My[tid] = 0.0;
+  }
+  __syncthreads();
+  if (tid < m) spline_fill_row(t, xs, m, Ax, Mx, tid);
+  else if (tid >= 128 && tid < 128 + m) spline_fill_row(t, ys, m, Ay, My, tid - 128);
+  __syncthreads();
+  if (tid == 0) sh[2] = spline_solve(m, Ax, Mx) ? 1 : 0;
+  if (tid == 64) sh[3] = spline_solve(m, Ay, My) ? 1 : 0;
+  __syncthreads();
+  if (!sh[2] || !sh[3]) return -1;
+  __syncthreads();   // every thread has read sh[2] before thread 0 reuses it
+  if (tid < m) {
+    dx1[tid] = spline_d1_at(t, xs, m, Mx, tid);
+    dy1[tid] = spline_d1_at(t, ys, m, My, tid);
+  }
+  __syncthreads();
+  if (tid < m) {
+    const double num = fabs(dx1[tid] * My[tid] - dy1[tid] * Mx[tid]);
+    const double den = dx1[tid] * dx1[tid] + dy1[tid] * dy1[tid];
+    kap[tid] = num / (den * sqrt(den));
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int best = 0;
+    double bestk = -1.0;
+    for (int i = 0; i < m; ++i)
+      if (i == 0 || kap[i] > bestk * (1.0 + 1e-12)) {
+        best = i;
+        bestk = kap[i];
+      }
+    sh[2] = keep[best];
+  }
+  __syncthreads();
+  return sh[2];
+}
+
+
 }  // namespace sl

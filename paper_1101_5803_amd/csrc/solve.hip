@@ -2589,12 +2589,14 @@ __global__ void __launch_bounds__(256) k_corner(SolveArgs a) {
   const int m = blockIdx.x;
   const int nl = a.n_lambda;
   const MemberInfo mi = a.minfo[m];
+  // the corner by the whole block (the condition is the same for every thread)
+  const int kk = (mi.status == SL_ST_OK && nl >= 4)
+                     ? lcurve_corner_block(a.regv + (long)m * nl, a.chi2 + (long)m * nl, nl, scratch)
+                     : -1;
   if (threadIdx.x == 0) {
     int k = 0, cst = mi.status;
     if (mi.status == SL_ST_OK) {
       if (nl >= 4) {
-        const int kk = lcurve_corner_impl(a.regv + (long)m * nl, a.chi2 + (long)m * nl, nl, nullptr,
-                                          scratch);
         if (kk >= 0)
           k = kk;
         else
@@ -2914,7 +2916,8 @@ static int configure(SolveArgs& A, const Layout& L, const sl_tuning& v, LaunchCf
   const size_t tagged = 8 * (size_t)L.I_max + 768 + sizeof(int) * (size_t)L.I_max;
   A.prep_tags = tagged <= 159 * 1024;
   if (A.prep_tags) c->prep_lds = tagged;
-  c->corner_lds = sizeof(double) * (A.n_lambda * A.n_lambda + 12 * A.n_lambda + 16);
+  // lcurve_corner_block: 12 n + 2 n^2 doubles (both spline systems at once)
+  c->corner_lds = sizeof(double) * (2 * A.n_lambda * A.n_lambda + 12 * A.n_lambda + 16);
   static std::mutex mu;
   std::lock_guard<std::mutex> g(mu);
   for (SolveKernel k : {c->ks, c->ksd, c->kpc, c->kpcd, c->kmc, c->kmcd})
@@ -2923,6 +2926,9 @@ static int configure(SolveArgs& A, const Layout& L, const sl_tuning& v, LaunchCf
     SL_HIP(hipFuncSetAttribute((const void*)c->kim, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   SL_HIP(hipFuncSetAttribute((const void*)k_prep<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)c->prep_lds));
+  // up to 72 KB at SL_MAX_LAMBDA points
+  SL_HIP(hipFuncSetAttribute((const void*)k_corner<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)c->corner_lds));
   return SL_OK;
 }
 
