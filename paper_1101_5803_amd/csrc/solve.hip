@@ -211,11 +211,20 @@ struct LamList {
 
 template <typename T>
 __global__ void __launch_bounds__(1024) k_setup(SolveArgs a, LamList lams) {
+  // the tap table is built by thread 0 in LDS from the PSF staged there (in
+  // global memory every read of its loops waited on the stores before it) and
+  // copied out by all threads
+  extern __shared__ __align__(16) unsigned char smem_setup[];
+  double* tsh = reinterpret_cast<double*>(smem_setup);
   __shared__ double red[32];
   if (threadIdx.x < a.n_lambda) a.lamv[threadIdx.x] = lams.v[threadIdx.x];
   __shared__ int counts[4097];
   const int tid = threadIdx.x;
   const int M = a.n_members, K = a.K, ck = a.ck;
+  // the PSF staged in LDS beside the tap table, by all threads
+  double* psh = tsh + TapIdx(SL_MAX_PSF).total;
+  for (int i = tid; i < K * K; i += blockDim.x) psh[i] = a.psf[i];
+  __syncthreads();
   // offsets of packed solutions; invalid ns contribute nothing
   if (tid == 0) {
     long long off = 0;
@@ -238,8 +247,8 @@ __global__ void __launch_bounds__(1024) k_setup(SolveArgs a, LamList lams) {
       const int ns = a.ns[m];
       counts[(ns >= 2 && ns <= a.max_ns) ? ns : 0]++;
     }
-    int start = 0;   // exclusive prefix in descending ns order
-    for (int v = 4096; v >= 0; --v) {
+    int start = 0;   // exclusive prefix in descending ns order (keys are at most max_ns)
+    for (int v = a.max_ns < 4096 ? a.max_ns : 4096; v >= 0; --v) {
       const int c = counts[v];
       counts[v] = start;
       start += c;
@@ -273,23 +282,23 @@ __global__ void __launch_bounds__(1024) k_setup(SolveArgs a, LamList lams) {
     int am = 0, bm = 0;
     double pmax = 0.0;
     for (int i = 0; i < K * K; ++i)
-      if (fabs(a.psf[i]) > pmax) {
-        pmax = fabs(a.psf[i]);
+      if (fabs(psh[i]) > pmax) {
+        pmax = fabs(psh[i]);
         am = i / K;
         bm = i % K;
       }
-    double* tp = a.taps_d;
+    double* tp = tsh;
     for (int i = 0; i < ti.total; ++i) tp[i] = 0.0;
-    for (int i = 0; i < K * K; ++i) tp[ti.psf + i] = a.psf[i];
+    for (int i = 0; i < K * K; ++i) tp[ti.psf + i] = psh[i];
     int sep = pmax > 0.0;
     if (sep) {
       for (int x = 0; x < K; ++x) {
-        tp[ti.gy + x] = a.psf[x * K + bm];
-        tp[ti.gx + x] = a.psf[am * K + x] / a.psf[am * K + bm];
+        tp[ti.gy + x] = psh[x * K + bm];
+        tp[ti.gx + x] = psh[am * K + x] / psh[am * K + bm];
       }
       for (int x = 0; x < K && sep; ++x)
         for (int y = 0; y < K; ++y)
-          if (fabs(a.psf[x * K + y] - tp[ti.gy + x] * tp[ti.gx + y]) > 1e-12 * pmax) {
+          if (fabs(psh[x * K + y] - tp[ti.gy + x] * tp[ti.gx + y]) > 1e-12 * pmax) {
             sep = 0;
             break;
           }
@@ -336,8 +345,15 @@ __global__ void __launch_bounds__(1024) k_setup(SolveArgs a, LamList lams) {
           tp[ti.ery + p * ck + q] = ry;
         }
     }
+  }
+  __syncthreads();
+  {
+    const TapIdx ti(K);
     T* tt = reinterpret_cast<T*>(a.taps_t);
-    for (int i = 0; i < ti.total; ++i) tt[i] = (T)tp[i];
+    for (int i = tid; i < ti.total; i += blockDim.x) {
+      a.taps_d[i] = tsh[i];
+      tt[i] = (T)tsh[i];
+    }
   }
   // sums of d^2 and of the Monte Carlo draws squared, in FP64
   double acc = 0.0, accn = 0.0;
@@ -2627,6 +2643,21 @@ __global__ void __launch_bounds__(256) k_corner(SolveArgs a) {
 // ------------------------------------------------------------------ host side
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// k_setup's dynamic LDS: the tap table and the PSF of the largest PSF size
+// (65.5 + 31.8 KB at 63 x 63)
+static const size_t kSetupLds = sizeof(double) * ((size_t)TapIdx(SL_MAX_PSF).total + SL_MAX_PSF * SL_MAX_PSF);
+
+template <typename T>
+static int setup_lds_attr() {
+  static std::once_flag once;
+  static hipError_t err = hipSuccess;
+  std::call_once(once, [] {
+    err = hipFuncSetAttribute((const void*)k_setup<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSetupLds);
+  });
+  SL_HIP(err);
+  return SL_OK;
+}
+
 // Bytes after the solve's workspace that sl_chi2_sources uses: the device
 // copy of ns, then the member offsets k_setup writes.
 constexpr size_t kSrcTail = 512;
@@ -2959,7 +2990,8 @@ static int launch_pair(SolveKernel kb, SolveKernel kd, const Layout& L, const La
 template <typename T>
 static int enqueue(const SolveArgs& A, const LamList& lams, const Layout& L, const LaunchCfg& c, hipStream_t st,
                    bool profile, SideStream* priv = nullptr) {
-  hipLaunchKernelGGL(k_setup<T>, dim3(1), dim3(1024), 0, st, A, lams);
+  if (int e = setup_lds_attr<T>()) return e;
+  hipLaunchKernelGGL(k_setup<T>, dim3(1), dim3(1024), kSetupLds, st, A, lams);
   if (int e = check_launch("k_setup")) return e;
   hipLaunchKernelGGL(k_prep<T>, dim3(A.n_members), dim3(1024), c.prep_lds, st, A);
   if (int e = check_launch("k_prep")) return e;
@@ -3246,11 +3278,13 @@ int sl_chi2_sources(const sl_problem* pb, const double* lens, int ns, const doub
   hipLaunchKernelGGL(k_put_int, dim3(1), dim3(64), 0, st, ns_dev, ns);
   if (int e = check_launch("k_put_int")) return e;
   if (pb->dtype == SL_F32) {
-    hipLaunchKernelGGL(k_setup<float>, dim3(1), dim3(1024), 0, st, A, lams);
+    if (int e = setup_lds_attr<float>()) return e;
+    hipLaunchKernelGGL(k_setup<float>, dim3(1), dim3(1024), kSetupLds, st, A, lams);
     if (int e = check_launch("k_setup")) return e;
     hipLaunchKernelGGL(k_prep<float>, dim3(1), dim3(1024), c.prep_lds, st, A);
   } else {
-    hipLaunchKernelGGL(k_setup<double>, dim3(1), dim3(1024), 0, st, A, lams);
+    if (int e = setup_lds_attr<double>()) return e;
+    hipLaunchKernelGGL(k_setup<double>, dim3(1), dim3(1024), kSetupLds, st, A, lams);
     if (int e = check_launch("k_setup")) return e;
     hipLaunchKernelGGL(k_prep<double>, dim3(1), dim3(1024), c.prep_lds, st, A);
   }
