@@ -204,6 +204,20 @@ def test_large_solve_full_shape_fp32(sl):
     assert err <= 10 * g["ds"][k] + FLOOR["f32"] * np.linalg.norm(s_ref), (k, err / np.linalg.norm(s_ref))
 
 
+@pytest.mark.parametrize("interp", ["bilinear", "bicubic"])
+def test_large_solve_fp64_repeatable(sl, interp):
+    """The FP64 solve (frame form, fixed-order reductions and sorted L^T rows)
+    gives the same bits on a second call with the same inputs."""
+    w, lens, d, sigma, psf = _medium()
+    print(f"large solve fp64 repeat {interp}", flush=True)
+    s = _solver(sl, d, sigma, psf, w, torch.float64, interp)
+    first = _np(s.solve_large(lens, w.ns, 40))
+    again = _np(s.solve_large(lens, w.ns, 40))
+    for key in first:
+        if key != "dof":
+            assert np.array_equal(first[key], again[key]), key
+
+
 def test_large_solve_edge_cases(sl):
     """A genome outside the prior's domain is flagged, a lens that maps nothing
     gives empty iterates, fewer than four iterations skip the L-curve, and
